@@ -1,0 +1,168 @@
+"""CPU oracle for the K-Best graph edit distance search -- TEST INFRASTRUCTURE.
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The GPU library never calls it; see ged_oracle.c for the
+definitions it follows and the paper sections it cites.
+
+Functions take `Graph` objects from paper_2605_00830_amd.synth (or anything
+with n, vlabel, eu, ev, elabel) and a 6-tuple of costs
+(vsub, vdel, vins, esub, edel, eins).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ged_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OR_OK, OR_EINVAL, OR_ENOMEM, OR_ETOOBIG = 0, 1, 2, 3
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile ged_oracle.c with gcc -O2 into oracle/liboracle.so."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    graph_args = [ctypes.c_int, P, ctypes.c_int, P, P, P]
+    lib.oracle_kbest.argtypes = graph_args + graph_args + [P, i64, P, P]
+    lib.oracle_kbest.restype = ctypes.c_int
+    lib.oracle_exact.argtypes = graph_args + graph_args + [P, ctypes.c_double, P, P]
+    lib.oracle_exact.restype = ctypes.c_int
+    lib.oracle_induced_cost.argtypes = graph_args + graph_args + [P, P, P]
+    lib.oracle_induced_cost.restype = ctypes.c_int
+    lib.oracle_count_mappings.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.oracle_count_mappings.restype = ctypes.c_double
+    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, P, P, P, P]
+    lib.oracle_kbest_pairs.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _arr(a, dt=np.int32) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=dt))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _graph_args(g, keep: list):
+    vl = _arr(g.vlabel)
+    eu = _arr(g.eu)
+    ev = _arr(g.ev)
+    el = None if getattr(g, "elabel", None) is None else _arr(g.elabel)
+    keep += [vl, eu, ev, el]
+    return [int(g.n), _ptr(vl), int(eu.shape[0]), _ptr(eu), _ptr(ev), _ptr(el)]
+
+
+def _check(st: int, what: str):
+    if st != OR_OK:
+        raise OracleError(f"{what}: oracle status {st}")
+
+
+def kbest(g1, g2, costs: Sequence[int], K: int) -> Tuple[int, np.ndarray]:
+    """K-Best search g1 -> g2; returns (distance, mapping) with -1 = deleted."""
+    lib = _load()
+    keep: list = []
+    c = _arr(costs)
+    dist = ctypes.c_int64(0)
+    mp = np.zeros(max(int(g1.n), 1), dtype=np.int32)
+    st = lib.oracle_kbest(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
+                          ctypes.byref(dist), _ptr(mp))
+    _check(st, "kbest")
+    return int(dist.value), mp[: int(g1.n)].copy()
+
+
+def exact(g1, g2, costs: Sequence[int], max_mappings: float = 1e8) -> Tuple[int, np.ndarray]:
+    """Exact GED by enumerating every injective partial mapping."""
+    lib = _load()
+    keep: list = []
+    c = _arr(costs)
+    dist = ctypes.c_int64(0)
+    mp = np.zeros(max(int(g1.n), 1), dtype=np.int32)
+    st = lib.oracle_exact(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c),
+                          float(max_mappings), ctypes.byref(dist), _ptr(mp))
+    _check(st, "exact")
+    return int(dist.value), mp[: int(g1.n)].copy()
+
+
+def induced_cost(g1, g2, costs: Sequence[int], mapping) -> int:
+    """Edit cost of a complete mapping (mapping[v] = -1 deletes v)."""
+    lib = _load()
+    keep: list = []
+    c = _arr(costs)
+    mp = _arr(mapping)
+    if mp.shape[0] != int(g1.n):
+        raise OracleError("mapping length must equal g1.n")
+    out = ctypes.c_int64(0)
+    st = lib.oracle_induced_cost(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c),
+                                 _ptr(mp if mp.size else np.zeros(1, np.int32)), ctypes.byref(out))
+    _check(st, "induced_cost")
+    return int(out.value)
+
+
+def count_mappings(n1: int, n2: int) -> float:
+    """Number of complete mappings g1 -> g2 (sum over s of C(n1,s) n2!/(n2-s)!)."""
+    return float(_load().oracle_count_mappings(int(n1), int(n2)))
+
+
+def map_offsets(graphs, pairs: np.ndarray) -> np.ndarray:
+    """Exclusive prefix sum of the source orders: where each pair's mapping starts."""
+    n_src = np.asarray(graphs.n, dtype=np.int64)[np.asarray(pairs)[:, 0]]
+    off = np.zeros(len(n_src), dtype=np.int64)
+    if len(n_src) > 1:
+        np.cumsum(n_src[:-1], out=off[1:])
+    return off
+
+
+def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int):
+    """Run the oracle over many pairs of a GraphSet.
+
+    Returns (dist int64 [P], maps int32 [sum n_src], offsets int64 [P]).
+    """
+    lib = _load()
+    pairs = _arr(pairs, np.int64).reshape(-1, 2)
+    off = map_offsets(graphs, pairs)
+    total = int(np.asarray(graphs.n, np.int64)[pairs[:, 0]].sum()) if len(pairs) else 0
+    dist = np.zeros(len(pairs), dtype=np.int64)
+    maps = np.zeros(max(total, 1), dtype=np.int32)
+    n = _arr(graphs.n)
+    m = _arr(graphs.m)
+    voff = _arr(graphs.voff, np.int64)
+    eoff = _arr(graphs.eoff, np.int64)
+    vl = _arr(graphs.vlabel) if len(graphs.vlabel) else np.zeros(1, np.int32)
+    eu = _arr(graphs.eu) if len(graphs.eu) else np.zeros(1, np.int32)
+    ev = _arr(graphs.ev) if len(graphs.ev) else np.zeros(1, np.int32)
+    el = None if graphs.elabel is None else (_arr(graphs.elabel) if len(graphs.elabel) else np.zeros(1, np.int32))
+    c = _arr(costs)
+    failed = ctypes.c_int64(-1)
+    st = lib.oracle_kbest_pairs(_ptr(n), _ptr(m), _ptr(voff), _ptr(eoff), _ptr(vl), _ptr(eu),
+                                _ptr(ev), _ptr(el), _ptr(pairs), int(len(pairs)), _ptr(c), int(K),
+                                _ptr(dist), _ptr(maps), _ptr(off), ctypes.byref(failed))
+    _check(st, f"kbest_pairs (pair {failed.value})")
+    return dist, maps[:total], off

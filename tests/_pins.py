@@ -1,0 +1,174 @@
+"""Independent pure-Python computations that pin the oracle.
+
+None of this shares code with oracle/ged_oracle.c; each function reaches the
+same quantity by a different route:
+
+* qap_cost / qap_exact: the quadratic-assignment form of GED -- both graphs
+  padded with epsilon vertices to n1+n2, a permutation of the padded vertex
+  set, vertex and edge costs read off position by position (Sec. 2.2-2.4 of
+  the paper written as one formula over the padded adjacency).
+* scratch_beam: the K-Best search of Alg. 1 where every child's partial edit
+  distance is recomputed from scratch as the cost of all edit operations in
+  its path (Sec. 4.1, Evaluation), instead of the incremental implied-edge
+  scan, and ranking uses the child's mapping tuple itself (deleted = n2) for
+  the generation-order tie-break.
+"""
+from __future__ import annotations
+
+import itertools
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+VSUB, VDEL, VINS, ESUB, EDEL, EINS = range(6)
+
+
+def edge_dict(g) -> Dict[Tuple[int, int], int]:
+    el = g.elabel if getattr(g, "elabel", None) is not None else [0] * len(g.eu)
+    d = {}
+    for a, b, l in zip(g.eu, g.ev, el):
+        a, b, l = int(a), int(b), int(l)
+        d[(a, b)] = l
+        d[(b, a)] = l
+    return d
+
+
+def qap_cost(g1, g2, c: Sequence[int], perm: Sequence[int]) -> int:
+    """Cost of a permutation of the padded vertex set (size n1+n2).
+
+    Position i < n1 is g1 vertex i, position i >= n1 an epsilon; target
+    index t < n2 is g2 vertex t, t >= n2 an epsilon.
+    """
+    n1, n2 = int(g1.n), int(g2.n)
+    N = n1 + n2
+    E1, E2 = edge_dict(g1), edge_dict(g2)
+    cost = 0
+    for i in range(N):
+        t = perm[i]
+        if i < n1 and t < n2:
+            cost += c[VSUB] if int(g1.vlabel[i]) != int(g2.vlabel[t]) else 0
+        elif i < n1:
+            cost += c[VDEL]
+        elif t < n2:
+            cost += c[VINS]
+    for i in range(N):
+        for j in range(i + 1, N):
+            e1 = E1.get((i, j)) if (i < n1 and j < n1) else None
+            a, b = perm[i], perm[j]
+            e2 = E2.get((a, b)) if (a < n2 and b < n2) else None
+            if e1 is not None and e2 is not None:
+                cost += c[ESUB] if e1 != e2 else 0
+            elif e1 is not None:
+                cost += c[EDEL]
+            elif e2 is not None:
+                cost += c[EINS]
+    return cost
+
+
+def perm_from_map(mapping: Sequence[int], n1: int, n2: int) -> List[int]:
+    """Extend a mapping (-1 = deleted) to a padded permutation."""
+    perm = [0] * (n1 + n2)
+    used = set(int(x) for x in mapping if int(x) >= 0)
+    free_eps_targets = iter(range(n2, n2 + n1))
+    for i in range(n1):
+        perm[i] = int(mapping[i]) if int(mapping[i]) >= 0 else next(free_eps_targets)
+    rest_targets = [t for t in range(n2) if t not in used] + list(free_eps_targets)
+    for k, i in enumerate(range(n1, n1 + n2)):
+        perm[i] = rest_targets[k]
+    return perm
+
+
+def qap_exact(g1, g2, c: Sequence[int]) -> int:
+    n1, n2 = int(g1.n), int(g2.n)
+    return min(qap_cost(g1, g2, c, p) for p in itertools.permutations(range(n1 + n2)))
+
+
+def partial_cost(g1, g2, c, phi: Sequence[int]) -> int:
+    """Cost of all edit operations on the path phi (g1 vertices 0..len(phi)-1 edited)."""
+    E1, E2 = edge_dict(g1), edge_dict(g2)
+    k = len(phi)
+    cost = 0
+    img = {}
+    for v in range(k):
+        t = phi[v]
+        if t < 0:
+            cost += c[VDEL]
+        else:
+            img[t] = v
+            cost += c[VSUB] if int(g1.vlabel[v]) != int(g2.vlabel[t]) else 0
+    for a in range(k):
+        for b in range(a + 1, k):
+            e1 = E1.get((a, b))
+            if e1 is None:
+                continue
+            x, y = phi[a], phi[b]
+            e2 = E2.get((x, y)) if (x >= 0 and y >= 0) else None
+            if e2 is None:
+                cost += c[EDEL]
+            elif e2 != e1:
+                cost += c[ESUB]
+    targets = sorted(img)
+    for ia in range(len(targets)):
+        for ib in range(ia + 1, len(targets)):
+            x, y = targets[ia], targets[ib]
+            if (x, y) in E2 and (img[x], img[y]) not in E1:
+                cost += c[EINS]
+    return cost
+
+
+def scratch_beam(g1, g2, c, K: int) -> Tuple[int, List[int]]:
+    n1, n2 = int(g1.n), int(g2.n)
+    E2 = edge_dict(g2)
+
+    def key(phi):  # lexicographic key with deletion after every g2 vertex
+        return tuple(n2 if t < 0 else t for t in phi)
+
+    beam: List[Tuple[int, ...]] = [()]
+    for i in range(n1):
+        children = []
+        for phi in beam:
+            used = {t for t in phi if t >= 0}
+            for u in list(range(n2)) + [-1]:
+                if u >= 0 and u in used:
+                    continue
+                ch = phi + (u,)
+                children.append((partial_cost(g1, g2, c, ch), key(ch), ch))
+        children.sort(key=lambda x: (x[0], x[1]))
+        kept = children[:K]
+        kept.sort(key=lambda x: x[1])
+        beam = [x[2] for x in kept]
+    best: Optional[Tuple[int, Tuple[int, ...], Tuple[int, ...]]] = None
+    for phi in beam:
+        used = {t for t in phi if t >= 0}
+        total = partial_cost(g1, g2, c, phi) + c[VINS] * (n2 - len(used))
+        for x in range(n2):
+            for y in range(x + 1, n2):
+                if (x, y) in E2 and (x not in used or y not in used):
+                    total += c[EINS]
+        cand = (total, key(phi), phi)
+        if best is None or cand[:2] < best[:2]:
+            best = cand
+    return best[0], list(best[2])
+
+
+def to_networkx(g):
+    import networkx as nx
+    G = nx.Graph()
+    for v in range(int(g.n)):
+        G.add_node(v, label=int(g.vlabel[v]))
+    el = g.elabel if getattr(g, "elabel", None) is not None else [0] * len(g.eu)
+    for a, b, l in zip(g.eu, g.ev, el):
+        G.add_edge(int(a), int(b), label=int(l))
+    return G
+
+
+def networkx_ged(g1, g2, c) -> int:
+    import networkx as nx
+    return int(round(nx.graph_edit_distance(
+        to_networkx(g1), to_networkx(g2),
+        node_subst_cost=lambda a, b: 0 if a["label"] == b["label"] else c[VSUB],
+        node_del_cost=lambda a: c[VDEL],
+        node_ins_cost=lambda a: c[VINS],
+        edge_subst_cost=lambda a, b: 0 if a["label"] == b["label"] else c[ESUB],
+        edge_del_cost=lambda a: c[EDEL],
+        edge_ins_cost=lambda a: c[EINS])))

@@ -1,0 +1,251 @@
+"""Pins of the CPU oracle against things other than itself (CPU only).
+
+What fixes each value:
+* hand derivation from the GED definition (Sec. 2.2-2.4) and Alg. 1;
+* networkx's exact graph edit distance (an independent exact solver);
+* the quadratic-assignment form of GED, brute-forced over padded permutations;
+* a from-scratch K-Best beam (tests/_pins.py) that recomputes every partial
+  edit distance from the definition instead of the incremental scan;
+* closed forms: empty graphs, edgeless graphs, identical graphs;
+* the paper's limit statement: with K at least the number of complete
+  mappings the search is exhaustive and returns the exact GED (Sec. 4.5).
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_00830_amd.synth import Graph, er_graph, random_small_graph
+from tests import _pins
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+UNIT = (1, 1, 1, 1, 1, 1)
+PAPER = (2, 4, 4, 1, 2, 2)
+HIGH = (4, 12, 12, 1, 10, 10)          # the paper's second cost setting (Sec. 5)
+ODD = (3, 1, 2, 5, 1, 3)               # asymmetric, non-metric: catches swapped cost slots
+
+
+def g_from(d):
+    edges = d["edges"]
+    return Graph(d["n"], np.array(d["vlabel"], np.int32),
+                 np.array([e[0] for e in edges], np.int32),
+                 np.array([e[1] for e in edges], np.int32),
+                 np.array([e[2] for e in edges], np.int32))
+
+
+def load_fixtures():
+    with open(os.path.join(HERE, "golden", "fixtures.json")) as f:
+        return json.load(f)["fixtures"]
+
+
+def tiny_pairs(count, seed, n_max, p, nvl, nel=0, n_min=0):
+    out = []
+    for k in range(count):
+        g1 = random_small_graph(seed, 2 * k, n_max, p, nvl, nel, n_min)
+        g2 = random_small_graph(seed, 2 * k + 1, n_max, p, nvl, nel, n_min)
+        out.append((g1, g2))
+    return out
+
+
+# ---------------------------------------------------------------- fixtures
+
+@pytest.mark.parametrize("fx", load_fixtures(), ids=lambda f: f["name"])
+def test_golden_fixture(fx):
+    g1, g2, c = g_from(fx["g1"]), g_from(fx["g2"]), tuple(fx["costs"])
+    assert oracle.exact(g1, g2, c)[0] == fx["exact"]
+    assert oracle.exact(g2, g1, c)[0] == fx["reverse_exact"]
+    for K, d, m in fx["kbest"]:
+        dist, mp = oracle.kbest(g1, g2, c, K)
+        assert dist == d, K
+        if m is not None:
+            assert mp.tolist() == m, K
+    for K, d, m in fx["reverse_kbest"]:
+        dist, mp = oracle.kbest(g2, g1, c, K)
+        assert dist == d
+        if m is not None:
+            assert mp.tolist() == m
+
+
+def test_path_to_triangle_by_hand():
+    """g1 = path v0-v1-v2 labels (0,0,1); g2 = triangle labels (0,1,1); unit costs.
+
+    Lower bound: label multisets {0,0,1} vs {0,1,1} force one vertex edit, and
+    2 vs 3 edges force one edge edit, so GED >= 2; [0,1,2] costs exactly
+    1 (v1 relabel) + 1 (insert u0-u2) = 2.
+    K=1 trace: level 0 keeps v0->u0 (PED 0; u1, u2, delete cost 1).  Level 1:
+    v1->u1 and v1->u2 both cost 1 (relabel, edge v0-v1 kept), delete costs 2;
+    the tie goes to u1, generated first.  Level 2: v2->u2 costs 0 + 1 (edge
+    u0-u2 inserted, v0-v2 is no g1 edge) so PED 2; delete costs 1 + 1 -> 3.
+    No g2 vertex is left to insert: distance 2, mapping [0, 1, 2].
+    """
+    fx = load_fixtures()[0]
+    g1, g2 = g_from(fx["g1"]), g_from(fx["g2"])
+    assert oracle.exact(g1, g2, UNIT) == (2, pytest.approx(np.array([0, 1, 2])))
+    d, m = oracle.kbest(g1, g2, UNIT, 1)
+    assert d == 2 and m.tolist() == [0, 1, 2]
+    assert _pins.networkx_ged(g1, g2, UNIT) == 2
+
+
+def test_f3_exact_by_networkx():
+    fx = load_fixtures()[1]
+    g1, g2, c = g_from(fx["g1"]), g_from(fx["g2"]), tuple(fx["costs"])
+    assert _pins.networkx_ged(g1, g2, c) == fx["exact"]
+
+
+# ---------------------------------------------------------------- closed forms
+
+EMPTY = Graph(0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD])
+def test_empty_source_inserts_everything(c):
+    g2 = er_graph(11, 0, 7, 7, 0.5, 0.5, 3)
+    expect = c[2] * g2.n + c[5] * g2.m
+    assert oracle.kbest(EMPTY, g2, c, 3)[0] == expect
+    assert oracle.exact(EMPTY, g2, c)[0] == expect
+
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD])
+def test_empty_target_deletes_everything(c):
+    g1 = er_graph(11, 1, 6, 6, 0.5, 0.5, 3)
+    d, m = oracle.kbest(g1, EMPTY, c, 5)
+    assert d == c[1] * g1.n + c[4] * g1.m
+    assert m.tolist() == [-1] * g1.n
+    assert oracle.kbest(EMPTY, EMPTY, c, 1)[0] == 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_edgeless_exact_is_label_matching(seed):
+    """Without edges and with unit costs, GED = max(n1, n2) - sum_l min(count1_l, count2_l)."""
+    rng = np.random.default_rng(seed)
+    n1, n2 = int(rng.integers(0, 6)), int(rng.integers(0, 6))
+    z = np.zeros(0, np.int32)
+    g1 = Graph(n1, rng.integers(0, 3, n1).astype(np.int32), z, z)
+    g2 = Graph(n2, rng.integers(0, 3, n2).astype(np.int32), z, z)
+    match = sum(min(int((g1.vlabel == l).sum()), int((g2.vlabel == l).sum())) for l in range(3))
+    assert oracle.exact(g1, g2, UNIT)[0] == max(n1, n2) - match
+
+
+@pytest.mark.parametrize("K", [1, 2, 7, 64])
+def test_identity_is_zero(K):
+    for k in range(8):
+        g = random_small_graph(21, k, 9, 0.4, 3, 3)
+        d, m = oracle.kbest(g, g, PAPER, K)
+        assert d == 0 and m.tolist() == list(range(g.n))
+
+
+# ---------------------------------------------------------------- independent exact solvers
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, HIGH])
+def test_exact_matches_networkx(c):
+    """networkx is an exact reference only for metric costs (esub <= edel + eins,
+    vsub <= vdel + vins); the odd cost set is pinned by the QAP brute force."""
+    for g1, g2 in tiny_pairs(10, 31, 4, 0.5, 3, 2):
+        assert oracle.exact(g1, g2, c)[0] == _pins.networkx_ged(g1, g2, c)
+
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD])
+def test_exact_matches_qap_bruteforce(c):
+    for g1, g2 in tiny_pairs(12, 41, 3, 0.6, 2, 2):
+        assert oracle.exact(g1, g2, c)[0] == _pins.qap_exact(g1, g2, c)
+
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD])
+def test_induced_cost_matches_qap_form(c):
+    rng = np.random.default_rng(7)
+    for g1, g2 in tiny_pairs(15, 51, 6, 0.5, 3, 3):
+        for _ in range(5):
+            targets = list(rng.permutation(g2.n)) + [-1] * g1.n
+            mp = [int(x) for x in rng.permutation(targets)[: g1.n]]
+            perm = _pins.perm_from_map(mp, g1.n, g2.n)
+            assert oracle.induced_cost(g1, g2, c, mp) == _pins.qap_cost(g1, g2, c, perm)
+
+
+def test_induced_cost_rejects_bad_maps():
+    g1 = er_graph(3, 0, 4, 4, 0.5, 0.5, 2)
+    g2 = er_graph(3, 1, 4, 4, 0.5, 0.5, 2)
+    for bad in ([0, 0, 1, 2], [0, 1, 2, 4], [0, 1, 2, -2]):
+        with pytest.raises(oracle.OracleError):
+            oracle.induced_cost(g1, g2, UNIT, bad)
+
+
+def test_rejects_invalid_graphs():
+    loop = Graph(2, np.zeros(2, np.int32), np.array([0], np.int32), np.array([0], np.int32))
+    dup = Graph(2, np.zeros(2, np.int32), np.array([0, 1], np.int32), np.array([1, 0], np.int32))
+    ok = Graph(2, np.zeros(2, np.int32), np.array([0], np.int32), np.array([1], np.int32))
+    for bad in (loop, dup):
+        with pytest.raises(oracle.OracleError):
+            oracle.kbest(bad, ok, UNIT, 1)
+    with pytest.raises(oracle.OracleError):
+        oracle.kbest(ok, ok, (1, -1, 1, 1, 1, 1), 1)
+    with pytest.raises(oracle.OracleError):
+        oracle.kbest(ok, ok, UNIT, 0)
+
+
+# ---------------------------------------------------------------- the search itself
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD])
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 8, 1000])
+def test_kbest_matches_scratch_beam(c, K):
+    for g1, g2 in tiny_pairs(10, 61 + K, 5, 0.5, 3, 2):
+        d, m = oracle.kbest(g1, g2, c, K)
+        d2, m2 = _pins.scratch_beam(g1, g2, c, K)
+        assert (d, m.tolist()) == (d2, m2)
+
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD, HIGH])
+def test_kbest_properties(c):
+    """Upper bound of exact; distance equals the induced cost of the mapping;
+    equal to exact once K covers every complete mapping (Sec. 4.5)."""
+    for g1, g2 in tiny_pairs(20, 71, 5, 0.45, 3, 2, n_min=1):
+        ex = oracle.exact(g1, g2, c)[0]
+        full = int(oracle.count_mappings(g1.n, g2.n))
+        for K in (1, 3, 16, full):
+            d, m = oracle.kbest(g1, g2, c, K)
+            assert d >= ex
+            assert d == oracle.induced_cost(g1, g2, c, m)
+        assert oracle.kbest(g1, g2, c, full)[0] == ex
+
+
+def test_exact_symmetry_and_triangle():
+    gs = [random_small_graph(81, k, 4, 0.5, 2, 2) for k in range(6)]
+    for c in (UNIT, PAPER, HIGH):
+        D = [[oracle.exact(a, b, c)[0] for b in gs] for a in gs]
+        for i, j in itertools.product(range(len(gs)), repeat=2):
+            assert D[i][j] == D[j][i]
+            for k in range(len(gs)):
+                assert D[i][j] <= D[i][k] + D[k][j]
+
+
+def test_count_mappings_by_enumeration():
+    for n1, n2 in [(0, 0), (0, 3), (3, 0), (2, 2), (3, 4), (4, 3)]:
+        brute = sum(1 for _ in itertools.product(range(-1, n2), repeat=n1)
+                    if len([x for x in _ if x >= 0]) == len({x for x in _ if x >= 0}))
+        assert oracle.count_mappings(n1, n2) == brute
+    assert oracle.count_mappings(8, 9) == 4596553
+
+
+@pytest.mark.slow
+def test_full_k_equals_exact_on_8x9_pair():
+    """The 8 x 9 ER pair: with K = 4,596,553 (every complete mapping) the search is exact."""
+    from paper_2605_00830_amd.synth import pair_er_8x9
+    w = pair_er_8x9()
+    g1, g2 = w.graphs.graph(0), w.graphs.graph(1)
+    ex, exmap = oracle.exact(g1, g2, w.costs)
+    d, m = oracle.kbest(g1, g2, w.costs, int(oracle.count_mappings(8, 9)))
+    assert d == ex
+    assert oracle.induced_cost(g1, g2, w.costs, m) == ex
+    assert oracle.kbest(g1, g2, w.costs, 16)[0] >= ex
+
+
+def test_aggregate_mean_improves_with_k():
+    """Reported trend (Fig. 2c): the mean distance over a population does not
+    grow as K grows (single pairs may; the search is not monotone in K)."""
+    pairs = tiny_pairs(60, 91, 7, 0.4, 3, 2, n_min=3)
+    means = []
+    for K in (1, 4, 16, 64):
+        means.append(np.mean([oracle.kbest(a, b, PAPER, K)[0] for a, b in pairs]))
+    assert all(means[i + 1] <= means[i] for i in range(len(means) - 1))
