@@ -1,0 +1,174 @@
+/*
+ * ged.h -- C ABI of the MI355X (gfx950) K-Best graph edit distance library.
+ *
+ * The library computes, for many pairs of labelled graphs at once, the
+ * K-Best approximation of the graph edit distance (GED) described in
+ * "Efficient Accelerated Graph Edit Distance Computation on GPU" (Dabah and
+ * Herten): a level-by-level search over vertex mappings of the source graph
+ * g1 onto the target graph g2 that keeps the K children of least partial
+ * edit distance at every level (Alg. 1; branching Sec. 4.1, evaluation by
+ * implied edge operations Sec. 2.3 and Alg. 2, selection Sec. 4.2), inserts
+ * the unmatched target vertices at the end (Sec. 4.4.1) and returns the
+ * cheapest complete edit path: an upper bound of the exact GED (Sec. 2.2).
+ *
+ * Conventions
+ *   - Every function returns a ged_status.  Nothing aborts or throws across
+ *     the ABI.  On failure ged_last_error() returns a message describing the
+ *     most recent failure on the calling thread.
+ *   - Pointers named h_* or documented as "host" are host memory owned by the
+ *     caller; the library copies what it keeps before returning.
+ *   - Pointers named d_* are device memory on the current HIP device,
+ *     allocated and owned by the caller (for example torch tensors'
+ *     data_ptr()).  Results written there are valid once the given HIP stream
+ *     has been synchronized.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Graphs are undirected and simple (Sec. 2.1): no self-loops, no repeated
+ *     edge.  Vertex and edge labels are int32 values compared for equality
+ *     only (Sec. 2.4).
+ *   - Costs are non-negative int32 (Sec. 2.4; the paper's default setting is
+ *     vsub 2, vdel 4, vins 4, esub 1, edel 2, eins 2, Sec. 5).  A substitution
+ *     costs 0 when the two labels are equal.  All arithmetic is exact int32.
+ *
+ * Readings fixed by this library where the paper leaves a choice open:
+ *   - g1's vertices are edited in index order 0..n1-1 (the loop of Alg. 1).
+ *   - A node's children are the substitutions by each unused g2 vertex in
+ *     ascending index order, followed by the deletion (Sec. 4.1).
+ *   - When several children share the K-th smallest partial edit distance,
+ *     those generated first (parent by parent in beam order, then in child
+ *     order) take the remaining places.  The surviving beam keeps
+ *     generation order.  This makes every result deterministic.
+ *   - Selection happens at every level including the last; insertion costs
+ *     are added afterwards (Sec. 4.4.1); among leaves of equal total cost the
+ *     first in beam order is returned.
+ */
+#ifndef GED_H
+#define GED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GED_ABI_VERSION 1
+
+/* Limits of this version. */
+#define GED_MAX_VERTICES 512      /* per graph */
+#define GED_MAX_K 1024            /* beam width */
+#define GED_MAX_EDGE_LABELS 16    /* distinct edge labels in one database */
+
+typedef enum {
+    GED_OK = 0,
+    GED_EINVAL = 1,        /* an argument or a graph violates the contract */
+    GED_ENOMEM = 2,        /* host or device allocation failed */
+    GED_EUNSUPPORTED = 3,  /* valid input beyond this version's limits */
+    GED_EDEVICE = 4,       /* a HIP runtime call failed */
+    GED_EBUSY = 5,
+    GED_ETIMEOUT = 6,
+    GED_ECANCELED = 7
+} ged_status;
+
+/* Edit operation costs (Sec. 2.4).  All must be >= 0. */
+typedef struct {
+    int32_t vsub, vdel, vins;  /* vertex substitution (labels differ), deletion, insertion */
+    int32_t esub, edel, eins;  /* edge substitution (labels differ), deletion, insertion */
+} ged_costs;
+
+/* One graph G = (V, E, alpha, beta) (Sec. 2.1), host memory.
+ * Vertices are 0..n-1.  vlabel[n] holds alpha.  Edge k joins eu[k] and ev[k]
+ * (0 <= eu, ev < n, eu != ev, each unordered pair at most once); elabel[k]
+ * is beta(e_k), or elabel == NULL when every edge has label 0. */
+typedef struct {
+    int32_t n, m;
+    const int32_t *vlabel;
+    const int32_t *eu;
+    const int32_t *ev;
+    const int32_t *elabel;
+} ged_graph;
+
+/* A pair of database graph ids: src is g1 (edited), dst is g2 (target). */
+typedef struct {
+    int64_t src, dst;
+} ged_pair;
+
+typedef struct ged_db ged_db;
+typedef struct ged_plan ged_plan;
+
+/* GED_ABI_VERSION of the loaded library. */
+int32_t ged_abi_version(void);
+
+/* Message for the most recent failure on this thread ("" if none).  The
+ * string is owned by the library and valid until the next call on the same
+ * thread. */
+const char *ged_last_error(void);
+
+/* Static name of a status code ("GED_OK", ...). */
+const char *ged_status_name(int32_t status);
+
+/* ------------------------------------------------------------------------
+ * Device-resident graph database.
+ *
+ * ged_db_create validates `count` graphs (host memory, see ged_graph), packs
+ * them into adjacency bitsets plus edge-label bit planes and copies them to
+ * the current HIP device (synchronously).  The caller may free its arrays
+ * once it returns.  Edge labels are re-coded database-wide; at most
+ * GED_MAX_EDGE_LABELS distinct edge labels per database.
+ * Errors: GED_EINVAL (count < 0, NULL pointers with n/m > 0, negative n or m,
+ * vertex ids out of range, self-loop, repeated edge); GED_EUNSUPPORTED
+ * (n > GED_MAX_VERTICES, too many edge labels); GED_ENOMEM; GED_EDEVICE.
+ * On success *out owns device memory until ged_db_destroy.
+ * ---------------------------------------------------------------------- */
+ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out);
+ged_status ged_db_destroy(ged_db *db);
+ged_status ged_db_count(const ged_db *db, int64_t *count);
+ged_status ged_db_device_bytes(const ged_db *db, int64_t *bytes);
+/* n of graph `id` (host query), for sizing mapping outputs. */
+ged_status ged_db_order(const ged_db *db, int64_t id, int32_t *n);
+
+/* ------------------------------------------------------------------------
+ * Batched K-Best search (Alg. 1 for every pair of a batch).
+ *
+ * ged_plan_create validates a batch of pairs (host array h_pairs[npairs],
+ * ids in [0, count)) and the beam width K (1 <= K <= GED_MAX_K), bins the
+ * pairs by size, orders each bin longest-first, uploads the work lists and
+ * allocates the device workspace; the plan can then be run any number of
+ * times (for example inside a captured HIP graph: ged_plan_run enqueues only
+ * kernels).  The plan keeps a pointer to db, which must outlive it.
+ *
+ * ged_plan_run enqueues the search on `stream` and writes
+ *   d_dist[p]  (int32 [npairs]) the K-Best distance of pair p;
+ *   d_map[off(p) + v] (int32 [sum of n(src)]) the target vertex of source
+ *              vertex v on the returned edit path, or -1 if v is deleted;
+ *              off(p) = sum of n(src) over the pairs before p (caller order);
+ *              target vertices absent from the mapping are inserted;
+ *   d_cand[p]  (int64 [npairs], optional, NULL to skip) the number of
+ *              children whose partial edit distance the search evaluated
+ *              (sum over levels of the candidate count).
+ * Errors (host-side, nothing enqueued): GED_EINVAL (negative cost, NULL
+ * output with npairs > 0, costs that could overflow int32 on some pair of
+ * the plan); GED_EDEVICE (launch failure).
+ * ---------------------------------------------------------------------- */
+ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
+                           ged_plan **out);
+ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries);
+ged_status ged_plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
+                        int64_t *d_cand, void *stream);
+/* The plan's pairs again, as the per-pair baseline: one kernel launch per
+ * pair, back to back on `stream`, same outputs as ged_plan_run. */
+ged_status ged_plan_run_perpair(ged_plan *plan, ged_costs costs, int32_t *d_dist,
+                                int32_t *d_map, int64_t *d_cand, void *stream);
+ged_status ged_plan_destroy(ged_plan *plan);
+
+/* One-shot forms: create a plan, run it on `stream`, synchronize `stream`,
+ * destroy the plan.  Same arguments and errors as above. */
+ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs,
+                     int32_t K, int32_t *d_dist, int32_t *d_map, void *stream);
+ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs,
+                             ged_costs costs, int32_t K, int32_t *d_dist, int32_t *d_map,
+                             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GED_H */

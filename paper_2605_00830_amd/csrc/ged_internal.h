@@ -1,0 +1,69 @@
+// Internal types shared by the host side of the library and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "ged.h"
+
+namespace gedk {
+
+// Graph record in the device database.  The adjacency pool holds, from
+// word `adj` on: n rows of w 32-bit words (bit x of row v set iff {v,x} is
+// an edge), then `planes` blocks of the same shape, block b holding bit b
+// of the database-wide edge-label code at each edge position.
+struct GraphRec {
+    int32_t n;
+    int32_t m;
+    int32_t w;       // ceil(n / 32)
+    int32_t pad;
+    int64_t adj;     // word offset into the adjacency pool
+    int64_t vlab;    // offset into the vertex-label pool
+};
+
+struct DbView {
+    const GraphRec *graphs;
+    const uint32_t *adj;
+    const int32_t *vlab;
+    int32_t planes;  // edge-label bit planes in this database (0..4)
+};
+
+// One pair of a batch, in schedule order.
+struct WorkItem {
+    int32_t src;     // g1 id
+    int32_t dst;     // g2 id
+    int32_t out;     // index of the pair in the caller's order
+    int32_t pad;
+    int64_t map_off; // first mapping entry of the pair in d_map
+};
+
+struct Costs {
+    int32_t vsub, vdel, vins, esub, edel, eins;
+};
+
+struct Outputs {
+    int32_t *dist;
+    int32_t *map;
+    int64_t *cand;   // may be null
+};
+
+// Block-per-pair kernel family: any n <= 512, K <= GED_MAX_K; beam state and
+// the candidate matrix live in a per-block global workspace.
+constexpr int kBlockThreads = 256;
+
+struct BlockShape {
+    int W;       // words per target row the instantiation handles (1,2,4,8,16)
+    int PL;      // label planes the instantiation handles (0,2,4)
+    int KS;      // slot stride: K rounded up to kBlockThreads
+    int nmax1;   // largest source order in the bin
+    int nmax2;   // largest target order in the bin
+};
+
+size_t block_workspace_bytes(const BlockShape &s);
+hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu);
+hipError_t launch_block(const BlockShape &s, const DbView &db, const WorkItem *work, int nwork,
+                        int *queue, Costs c, int K, void *workspace, size_t ws_stride,
+                        Outputs out, int grid, hipStream_t stream);
+hipError_t launch_fill_zero(int *p, int count, hipStream_t stream);
+
+}  // namespace gedk

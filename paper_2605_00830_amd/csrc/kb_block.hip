@@ -1,0 +1,531 @@
+// kb_block.hip -- block-per-pair K-Best search for gfx950 (general shapes).
+//
+// One 256-thread workgroup searches one pair at a time and pulls the next
+// pair from a work queue (persistent launch).  Thread t owns the beam slots
+// s = r*256 + t.  Per level i (the loop of Alg. 1, g1 vertex v_i):
+//   expand    every slot s builds Phi = image of v_i's earlier neighbours
+//             (one bit per g2 vertex, plus one set per edge-label plane),
+//             then scores each child by the implied edge operations of
+//             Sec. 2.3 / Alg. 2 as popcounts of word-wise ANDs:
+//               kept   = |Phi & N2(u)|             edges kept (maybe relabelled)
+//               del    = |P(v_i)| - kept           g1 edges deleted
+//               ins    = |Img & N2(u)| - kept      g2 edges inserted
+//               relab  = |Phi & N2(u) & label-mismatch|
+//             The deletion child costs vdel + edel*|P(v_i)| (Sec. 4.1).
+//   select    the K best children (Sec. 4.2) without sorting: threshold T =
+//             K-th smallest partial edit distance from an LDS histogram, all
+//             children below T, and the first (K - #below) children equal to
+//             T in generation order (exclusive block scans).  Survivors are
+//             compacted in generation order, so the beam stays ordered.
+//   update    survivors copy their parent's mapping and add one entry (the
+//             paper's update step, Sec. 4.4.2).
+// At the end every slot adds the insertion costs of the unmatched g2
+// vertices and edges (Sec. 4.4.1) and a block arg-min picks the result.
+//
+// State per slot (global workspace, slot-minor so a wave touches 64
+// consecutive entries): partial edit distance, |Img|, number of g2 edges
+// inside Img, Img bitset, mapping phi[j] (uint16, 0xffff = deleted); the
+// candidate matrix cand[u][s] (u = n2 is the deletion child).
+#include "ged_internal.h"
+
+namespace gedk {
+namespace {
+
+constexpr int BT = kBlockThreads;
+constexpr int NW = BT / 64;
+constexpr int NBINS = 1024;
+constexpr int SENT = 0x7fffffff;        // invalid child (target vertex already used)
+constexpr uint16_t PHI_DEL = 0xffff;
+
+struct WsLayout {
+    size_t ped, ein, nsub, img, phi, cand, stride;
+    size_t phi_half;                     // elements per phi ping-pong half
+};
+
+struct BlockArgs {
+    DbView db;
+    const WorkItem *work;
+    int nwork;
+    int *queue;
+    Costs c;
+    int K;
+    int KS;
+    char *ws;
+    WsLayout L;
+    Outputs out;
+};
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(v, o);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int block_min(int v, int *red) {
+    v = wave_min(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = red[0];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) r = min(r, red[k]);
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ int block_sum(int v, int *red) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) r += red[k];
+    __syncthreads();
+    return r;
+}
+
+// Exclusive scan over threads in index order; *total gets the block sum.
+__device__ __forceinline__ int block_excl_scan(int v, int *red, int *total) {
+    const int incl = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) red[w] = incl;
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const int x = red[k];
+        base += (k < w) ? x : 0;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - v;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned lo = (unsigned)__shfl_xor((int)(unsigned)v, o);
+        const unsigned hi = (unsigned)__shfl_xor((int)(unsigned)(v >> 32), o);
+        const unsigned long long w = ((unsigned long long)hi << 32) | lo;
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t below_mask(int i, int kw) {
+    const int rem = i - kw * 32;
+    return rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
+}
+
+template <int W, int PL>
+__global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
+    constexpr int PLA = PL > 0 ? PL : 1;
+    __shared__ int s_sel[GED_MAX_K];      // survivor: parent slot << 10 | child (n2 = deletion)
+    __shared__ int s_selped[GED_MAX_K];   // survivor partial edit distance
+    __shared__ int s_hist[NBINS];
+    __shared__ int s_red[NW];
+    __shared__ unsigned long long s_red64[NW];
+    __shared__ int s_bc[4];
+
+    const int t = threadIdx.x;
+    char *wsb = a.ws + (size_t)blockIdx.x * a.L.stride;
+    int *ped_b = reinterpret_cast<int *>(wsb + a.L.ped);
+    int *ein_b = reinterpret_cast<int *>(wsb + a.L.ein);
+    int *nsub_b = reinterpret_cast<int *>(wsb + a.L.nsub);
+    uint32_t *img_b = reinterpret_cast<uint32_t *>(wsb + a.L.img);
+    uint16_t *phi_b = reinterpret_cast<uint16_t *>(wsb + a.L.phi);
+    int *cand = reinterpret_cast<int *>(wsb + a.L.cand);
+    const int KS = a.KS;
+    const int SPT = KS / BT;
+    const int K = a.K;
+    const Costs c = a.c;
+    const int P = a.db.planes;
+
+    for (;;) {
+        if (t == 0) s_bc[0] = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(s_bc[0]);
+        __syncthreads();
+        if (item >= a.nwork) break;
+
+        const WorkItem wi = a.work[item];
+        const GraphRec g1 = a.db.graphs[wi.src];
+        const GraphRec g2 = a.db.graphs[wi.dst];
+        const int n1 = g1.n, n2 = g2.n, w1 = g1.w, w2 = g2.w;
+        const uint32_t *A1 = a.db.adj + g1.adj;
+        const uint32_t *A2 = a.db.adj + g2.adj;
+        const int *L1 = a.db.vlab + g1.vlab;
+        const int *L2 = a.db.vlab + g2.vlab;
+        const size_t pl1 = (size_t)n1 * w1, pl2 = (size_t)n2 * w2;
+
+        if (t == 0) {
+            ped_b[0] = 0;
+            ein_b[0] = 0;
+            nsub_b[0] = 0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) img_b[(size_t)k * KS] = 0u;
+        }
+        int nb = 1, cur = 0;
+        long long ce = 0;
+        __syncthreads();
+
+        for (int i = 0; i < n1; ++i) {
+            const int lab1 = L1[i];
+            int degP = 0;
+            for (int kw = 0; kw * 32 < i; ++kw) degP += __popc(A1[(size_t)i * w1 + kw] & below_mask(i, kw));
+            const int del_cost = c.vdel + c.edel * degP;
+
+            const int *pedc = ped_b + cur * KS;
+            const uint32_t *imgc = img_b + (size_t)cur * W * KS;
+            const uint16_t *phic = phi_b + cur * a.L.phi_half;
+
+            // ---------------- expand and evaluate
+            int lmin = SENT, lcnt = 0;
+            for (int r = 0; r < SPT; ++r) {
+                const int s = r * BT + t;
+                if (s >= nb) break;
+                const int pp = pedc[s];
+                uint32_t img_r[W];
+                uint32_t phi_r[W];
+                uint32_t phib[PLA][W];
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    img_r[k] = imgc[(size_t)k * KS + s];
+                    phi_r[k] = 0u;
+#pragma unroll
+                    for (int b = 0; b < PLA; ++b) phib[b][k] = 0u;
+                }
+                for (int kw = 0; kw * 32 < i; ++kw) {
+                    uint32_t bits = A1[(size_t)i * w1 + kw] & below_mask(i, kw);
+                    uint32_t pw[PLA];
+#pragma unroll
+                    for (int b = 0; b < PLA; ++b)
+                        pw[b] = (PL > 0 && b < P) ? A1[(size_t)(1 + b) * pl1 + (size_t)i * w1 + kw] : 0u;
+                    while (bits) {
+                        const int jb = __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        const int x = phic[(size_t)(kw * 32 + jb) * KS + s];
+                        if (x != PHI_DEL) {
+                            const uint32_t bit = 1u << (x & 31);
+                            const int xw = x >> 5;
+#pragma unroll
+                            for (int k = 0; k < W; ++k) {
+                                const uint32_t hit = (k == xw) ? bit : 0u;
+                                phi_r[k] |= hit;
+#pragma unroll
+                                for (int b = 0; b < PLA; ++b)
+                                    phib[b][k] |= ((pw[b] >> jb) & 1u) ? hit : 0u;
+                            }
+                        }
+                    }
+                }
+                int cnt = 1;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    if (k * 32 < n2) {
+                        const int ub = min(32, n2 - k * 32);
+                        for (int b = 0; b < ub; ++b) {
+                            const int u = k * 32 + b;
+                            const uint32_t *R = A2 + (size_t)u * w2;
+                            int kept = 0, inimg = 0, relab = 0;
+#pragma unroll
+                            for (int kk = 0; kk < W; ++kk) {
+                                if (kk < w2) {
+                                    const uint32_t row = R[kk];
+                                    const uint32_t both = phi_r[kk] & row;
+                                    kept += __popc(both);
+                                    inimg += __popc(img_r[kk] & row);
+                                    if (PL > 0) {
+                                        uint32_t diff = 0u;
+#pragma unroll
+                                        for (int bb = 0; bb < PLA; ++bb)
+                                            if (bb < P) diff |= phib[bb][kk] ^ A2[(size_t)(1 + bb) * pl2 + (size_t)u * w2 + kk];
+                                        relab += __popc(both & diff);
+                                    }
+                                }
+                            }
+                            const int d = pp + (lab1 != L2[u] ? c.vsub : 0) + c.edel * (degP - kept) +
+                                          c.eins * (inimg - kept) + c.esub * relab;
+                            const bool used = (img_r[k] >> b) & 1u;
+                            cand[(size_t)u * KS + s] = used ? SENT : d;
+                            if (!used) {
+                                lmin = min(lmin, d);
+                                ++cnt;
+                            }
+                        }
+                    }
+                }
+                const int dd = pp + del_cost;
+                cand[(size_t)n2 * KS + s] = dd;
+                lmin = min(lmin, dd);
+                lcnt += cnt;
+            }
+            const int mmin = block_min(lmin, s_red);
+            const int V = block_sum(lcnt, s_red);
+            ce += V;
+
+            // ---------------- threshold: K-th smallest partial edit distance
+            int T = SENT, quota = 0;
+            if (V > K) {
+                int lo = mmin, below = 0;
+                for (;;) {
+                    for (int b = t; b < NBINS; b += BT) s_hist[b] = 0;
+                    __syncthreads();
+                    int nxt = SENT;
+                    for (int r = 0; r < SPT; ++r) {
+                        const int s = r * BT + t;
+                        if (s >= nb) break;
+                        for (int u = 0; u <= n2; ++u) {
+                            const int v = cand[(size_t)u * KS + s];
+                            if (v == SENT || v < lo) continue;
+                            if (v - lo < NBINS) atomicAdd(&s_hist[v - lo], 1);
+                            else nxt = min(nxt, v);
+                        }
+                    }
+                    nxt = block_min(nxt, s_red);   // also orders the histogram writes
+                    if (t < 64) {
+                        constexpr int PER = NBINS / 64;
+                        const int base = t * PER;
+                        int sum = 0;
+#pragma unroll
+                        for (int k = 0; k < PER; ++k) sum += s_hist[base + k];
+                        const int incl = wave_incl_scan(sum);
+                        const unsigned long long hit = __ballot(below + incl >= K);
+                        if (hit) {
+                            const int L = __ffsll((long long)hit) - 1;
+                            if (t == L) {
+                                int cum = below + incl - sum;
+                                for (int k = 0; k < PER; ++k) {
+                                    const int h = s_hist[base + k];
+                                    if (cum + h >= K) {
+                                        s_bc[1] = 1;
+                                        s_bc[2] = lo + base + k;
+                                        s_bc[3] = cum;
+                                        break;
+                                    }
+                                    cum += h;
+                                }
+                            }
+                        } else if (t == 63) {
+                            s_bc[1] = 0;
+                            s_bc[3] = below + incl;
+                        }
+                    }
+                    __syncthreads();
+                    const int found = s_bc[1];
+                    const int v2 = s_bc[2], v3 = s_bc[3];
+                    __syncthreads();
+                    if (found) {
+                        T = v2;
+                        quota = K - v3;
+                        break;
+                    }
+                    below = v3;
+                    lo = nxt;
+                }
+            }
+
+            // ---------------- keep flags, tie quota and compaction in generation order
+            int eq_carry = 0, out_carry = 0;
+            for (int r = 0; r < SPT; ++r) {
+                const int s = r * BT + t;
+                const bool live = s < nb;
+                int lt = 0, eq = 0;
+                if (live) {
+                    for (int u = 0; u <= n2; ++u) {
+                        const int v = cand[(size_t)u * KS + s];
+                        lt += v < T;
+                        eq += v == T;
+                    }
+                }
+                int tot;
+                const int EQ = eq_carry + block_excl_scan(eq, s_red, &tot);
+                eq_carry += tot;
+                const int keep = lt + min(max(quota - EQ, 0), eq);
+                const int OUT = out_carry + block_excl_scan(keep, s_red, &tot);
+                out_carry += tot;
+                if (live && keep > 0) {
+                    int pos = OUT, e = EQ;
+                    for (int u = 0; u <= n2; ++u) {
+                        const int v = cand[(size_t)u * KS + s];
+                        bool take = v < T;
+                        if (v == T) {
+                            take = e < quota;
+                            ++e;
+                        }
+                        if (take) {
+                            s_sel[pos] = (s << 10) | u;
+                            s_selped[pos] = v;
+                            ++pos;
+                        }
+                    }
+                }
+            }
+            const int nb_new = out_carry;
+            __syncthreads();
+
+            // ---------------- update: child = parent + (v_i -> u)
+            const int nxt = cur ^ 1;
+            int *pedn = ped_b + nxt * KS;
+            int *einn = ein_b + nxt * KS;
+            int *nsubn = nsub_b + nxt * KS;
+            const int *einc = ein_b + cur * KS;
+            const int *nsubc = nsub_b + cur * KS;
+            uint32_t *imgn = img_b + (size_t)nxt * W * KS;
+            uint16_t *phin = phi_b + nxt * a.L.phi_half;
+            for (int r = 0; r < SPT; ++r) {
+                const int s2 = r * BT + t;
+                if (s2 >= nb_new) break;
+                const int sel = s_sel[s2];
+                const int p = sel >> 10, u = sel & 1023;
+                const bool sub = u < n2;
+                for (int j = 0; j < i; ++j) phin[(size_t)j * KS + s2] = phic[(size_t)j * KS + p];
+                phin[(size_t)i * KS + s2] = sub ? (uint16_t)u : PHI_DEL;
+                int add_e = 0;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    const uint32_t ip = imgc[(size_t)k * KS + p];
+                    const uint32_t row = (sub && k < w2) ? A2[(size_t)u * w2 + k] : 0u;
+                    add_e += __popc(ip & row);
+                    imgn[(size_t)k * KS + s2] = ip | ((sub && (u >> 5) == k) ? (1u << (u & 31)) : 0u);
+                }
+                pedn[s2] = s_selped[s2];
+                einn[s2] = einc[p] + add_e;
+                nsubn[s2] = nsubc[p] + (sub ? 1 : 0);
+            }
+            __syncthreads();
+            cur = nxt;
+            nb = nb_new;
+        }
+
+        // ---------------- completion: insert what is left of g2, pick the best leaf
+        unsigned long long best = ~0ull;
+        {
+            const int *pedc = ped_b + cur * KS;
+            const int *einc = ein_b + cur * KS;
+            const int *nsubc = nsub_b + cur * KS;
+            for (int r = 0; r < SPT; ++r) {
+                const int s = r * BT + t;
+                if (s >= nb) break;
+                const int total = pedc[s] + c.vins * (n2 - nsubc[s]) + c.eins * (g2.m - einc[s]);
+                const unsigned long long key = ((unsigned long long)(unsigned)total << 32) | (unsigned)s;
+                best = key < best ? key : best;
+            }
+        }
+        best = wave_min_u64(best);
+        if ((t & 63) == 0) s_red64[t >> 6] = best;
+        __syncthreads();
+        best = s_red64[0];
+#pragma unroll
+        for (int k = 1; k < NW; ++k) best = s_red64[k] < best ? s_red64[k] : best;
+        const int bslot = (int)(best & 0xffffffffu);
+        if (t == 0) {
+            a.out.dist[wi.out] = (int)(best >> 32);
+            if (a.out.cand) a.out.cand[wi.out] = ce;
+        }
+        const uint16_t *phic = phi_b + cur * a.L.phi_half;
+        for (int j = t; j < n1; j += BT) {
+            const int x = phic[(size_t)j * KS + bslot];
+            a.out.map[wi.map_off + j] = (x == PHI_DEL) ? -1 : x;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void fill_zero_kernel(int *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+WsLayout layout_for(const BlockShape &s) {
+    WsLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t KS = (size_t)s.KS;
+    const size_t n1 = (size_t)(s.nmax1 > 0 ? s.nmax1 : 1);
+    L.ped = take(2 * KS * 4);
+    L.ein = take(2 * KS * 4);
+    L.nsub = take(2 * KS * 4);
+    L.img = take(2 * (size_t)s.W * KS * 4);
+    L.phi = take(2 * n1 * KS * 2);
+    L.cand = take(((size_t)s.nmax2 + 1) * KS * 4);
+    L.stride = off;
+    L.phi_half = n1 * KS;
+    return L;
+}
+
+template <int W, int PL>
+const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL>);
+}
+
+const void *select_kernel(int W, int PL) {
+#define GEDK_CASE(w, pl) \
+    if (W == w && PL == pl) return kernel_ptr<w, pl>();
+#define GEDK_ROW(w) GEDK_CASE(w, 0) GEDK_CASE(w, 2) GEDK_CASE(w, 4)
+    GEDK_ROW(1) GEDK_ROW(2) GEDK_ROW(4) GEDK_ROW(8) GEDK_ROW(16)
+#undef GEDK_ROW
+#undef GEDK_CASE
+    return nullptr;
+}
+
+}  // namespace
+
+size_t block_workspace_bytes(const BlockShape &s) { return layout_for(s).stride; }
+
+hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
+    const void *k = select_kernel(s.W, s.PL);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, BT, 0);
+}
+
+hipError_t launch_block(const BlockShape &s, const DbView &db, const WorkItem *work, int nwork,
+                        int *queue, Costs c, int K, void *workspace, size_t ws_stride,
+                        Outputs out, int grid, hipStream_t stream) {
+    const void *k = select_kernel(s.W, s.PL);
+    if (!k || grid <= 0) return hipErrorInvalidValue;
+    BlockArgs a;
+    a.db = db;
+    a.work = work;
+    a.nwork = nwork;
+    a.queue = queue;
+    a.c = c;
+    a.K = K;
+    a.KS = s.KS;
+    a.ws = static_cast<char *>(workspace);
+    a.L = layout_for(s);
+    if (a.L.stride != ws_stride) return hipErrorInvalidValue;
+    a.out = out;
+    void *args[] = {&a};
+    return hipLaunchKernel(k, dim3(grid), dim3(BT), args, 0, stream);
+}
+
+hipError_t launch_fill_zero(int *p, int count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    const int threads = 256;
+    const int blocks = (count + threads - 1) / threads;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(threads), 0, stream, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace gedk

@@ -1,0 +1,238 @@
+"""Python binding of libged (include/ged.h): argument marshalling only.
+
+Every step of the search runs in the HIP kernels of libged.so; this module
+only converts numpy / torch arguments to the C ABI.  torch provides device
+memory and streams.  If libged.so is missing the import of this module
+fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch  # noqa: F401  -- load torch's HIP runtime before libged binds to it
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libged.so")
+
+GED_OK, GED_EINVAL, GED_ENOMEM, GED_EUNSUPPORTED, GED_EDEVICE, GED_EBUSY, GED_ETIMEOUT, GED_ECANCELED = range(8)
+MAX_VERTICES = 512
+MAX_K = 1024
+MAX_EDGE_LABELS = 16
+
+
+class GedError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_name(status) if _lib else status}: {message}")
+        self.status = status
+
+
+class Costs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in ("vsub", "vdel", "vins", "esub", "edel", "eins")]
+
+
+# Layout of ged_graph: int32 n, m; then four pointers (x86-64: 40 bytes).
+GRAPH_DTYPE = np.dtype([("n", "<i4"), ("m", "<i4"), ("vlabel", "<u8"), ("eu", "<u8"),
+                        ("ev", "<u8"), ("elabel", "<u8")])
+
+_lib = None
+
+EXPORTS = (
+    "ged_abi_version", "ged_last_error", "ged_status_name",
+    "ged_db_create", "ged_db_destroy", "ged_db_count", "ged_db_device_bytes", "ged_db_order",
+    "ged_plan_create", "ged_plan_map_size", "ged_plan_run", "ged_plan_run_perpair",
+    "ged_plan_destroy", "ged_kbest", "ged_kbest_perpair",
+)
+
+
+def load(path: str = LIB_PATH):
+    """Load libged.so and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
+                          f"(or python paper_2605_00830_amd/build.py)")
+    lib = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "ged_abi_version": ([], i32),
+        "ged_last_error": ([], ctypes.c_char_p),
+        "ged_status_name": ([i32], ctypes.c_char_p),
+        "ged_db_create": ([P, i64, P], i32),
+        "ged_db_destroy": ([P], i32),
+        "ged_db_count": ([P, P], i32),
+        "ged_db_device_bytes": ([P, P], i32),
+        "ged_db_order": ([P, i64, P], i32),
+        "ged_plan_create": ([P, P, i64, i32, P], i32),
+        "ged_plan_map_size": ([P, P], i32),
+        "ged_plan_run": ([P, Costs, P, P, P, P], i32),
+        "ged_plan_run_perpair": ([P, Costs, P, P, P, P], i32),
+        "ged_plan_destroy": ([P], i32),
+        "ged_kbest": ([P, P, i64, Costs, i32, P, P, P], i32),
+        "ged_kbest_perpair": ([P, P, i64, Costs, i32, P, P, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    return load().ged_status_name(int(status)).decode()
+
+
+def _check(status: int):
+    if status != GED_OK:
+        msg = load().ged_last_error().decode(errors="replace")
+        raise GedError(status, msg)
+
+
+def _costs(c: Sequence[int]) -> Costs:
+    if len(c) != 6:
+        raise ValueError("costs are (vsub, vdel, vins, esub, edel, eins)")
+    return Costs(*[int(x) for x in c])
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class Database:
+    """A device-resident graph database (ged_db_create); `graphs` is a synth.GraphSet."""
+
+    def __init__(self, graphs):
+        lib = load()
+        torch.cuda.init()
+        count = len(graphs)
+        vl = np.ascontiguousarray(graphs.vlabel, dtype=np.int32)
+        eu = np.ascontiguousarray(graphs.eu, dtype=np.int32)
+        ev = np.ascontiguousarray(graphs.ev, dtype=np.int32)
+        el = None if graphs.elabel is None else np.ascontiguousarray(graphs.elabel, dtype=np.int32)
+        recs = np.zeros(max(count, 1), dtype=GRAPH_DTYPE)
+        recs["n"][:count] = graphs.n
+        recs["m"][:count] = graphs.m
+        voff = np.asarray(graphs.voff, dtype=np.uint64)[:count]
+        eoff = np.asarray(graphs.eoff, dtype=np.uint64)[:count]
+        recs["vlabel"][:count] = np.uint64(vl.ctypes.data) + voff * np.uint64(4)
+        recs["eu"][:count] = np.uint64(eu.ctypes.data) + eoff * np.uint64(4)
+        recs["ev"][:count] = np.uint64(ev.ctypes.data) + eoff * np.uint64(4)
+        if el is not None:
+            recs["elabel"][:count] = np.uint64(el.ctypes.data) + eoff * np.uint64(4)
+        handle = ctypes.c_void_p()
+        _check(lib.ged_db_create(recs.ctypes.data, count, ctypes.byref(handle)))
+        self._h = handle
+        self.count = count
+        self.n = np.asarray(graphs.n, dtype=np.int32).copy()
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise GedError(GED_EINVAL, "database is closed")
+        return self._h
+
+    def device_bytes(self) -> int:
+        out = ctypes.c_int64()
+        _check(load().ged_db_device_bytes(self.handle, ctypes.byref(out)))
+        return int(out.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ged_db_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _pairs_array(pairs) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+
+
+class Plan:
+    """A reusable batched launch plan (ged_plan_create)."""
+
+    def __init__(self, db: Database, pairs, K: int):
+        lib = load()
+        self.db = db
+        self.pairs = _pairs_array(pairs)
+        self.K = int(K)
+        handle = ctypes.c_void_p()
+        _check(lib.ged_plan_create(db.handle, self.pairs.ctypes.data, len(self.pairs), self.K,
+                                   ctypes.byref(handle)))
+        self._h = handle
+        size = ctypes.c_int64()
+        _check(lib.ged_plan_map_size(self._h, ctypes.byref(size)))
+        self.map_size = int(size.value)
+        n_src = db.n[self.pairs[:, 0]].astype(np.int64) if len(self.pairs) else np.zeros(0, np.int64)
+        self.offsets = np.zeros(len(self.pairs), dtype=np.int64)
+        if len(self.pairs) > 1:
+            np.cumsum(n_src[:-1], out=self.offsets[1:])
+
+    def outputs(self, device="cuda", with_cand: bool = False):
+        dist = torch.empty(max(len(self.pairs), 1), dtype=torch.int32, device=device)
+        maps = torch.empty(max(self.map_size, 1), dtype=torch.int32, device=device)
+        cand = torch.empty(max(len(self.pairs), 1), dtype=torch.int64, device=device) if with_cand else None
+        return dist, maps, cand
+
+    def run(self, costs, dist: torch.Tensor, maps: torch.Tensor, cand: Optional[torch.Tensor] = None,
+            stream=None, perpair: bool = False):
+        lib = load()
+        fn = lib.ged_plan_run_perpair if perpair else lib.ged_plan_run
+        for t, dt in ((dist, torch.int32), (maps, torch.int32)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("outputs must be contiguous int32 CUDA tensors")
+        if dist.numel() < len(self.pairs) or maps.numel() < self.map_size:
+            raise ValueError("output tensors are too small")
+        if cand is not None and (cand.dtype != torch.int64 or cand.numel() < len(self.pairs)):
+            raise ValueError("cand must be an int64 tensor of npairs entries")
+        _check(fn(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
+                  None if cand is None else cand.data_ptr(), _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ged_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Result:
+    dist: np.ndarray      # int32 [P]
+    maps: np.ndarray      # int32 [sum n(src)], -1 = deleted
+    offsets: np.ndarray   # int64 [P]
+    cand: Optional[np.ndarray] = None  # int64 [P] children evaluated
+
+    def mapping(self, p: int, n1: int) -> np.ndarray:
+        o = int(self.offsets[p])
+        return self.maps[o:o + n1]
+
+
+def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: bool = False,
+          stream=None) -> Result:
+    """K-Best GED of every (src, dst) pair; synchronizes and returns host arrays."""
+    plan = Plan(db, pairs, K)
+    try:
+        dist, maps, cand = plan.outputs(with_cand=with_cand)
+        plan.run(costs, dist, maps, cand, stream=stream, perpair=perpair)
+        (stream or torch.cuda.current_stream()).synchronize()
+        n = len(plan.pairs)
+        return Result(dist[:n].cpu().numpy(), maps[:plan.map_size].cpu().numpy(), plan.offsets.copy(),
+                      None if cand is None else cand[:n].cpu().numpy())
+    finally:
+        plan.close()

@@ -1,0 +1,183 @@
+"""GPU parity: distances and mappings from libged equal the CPU oracle's
+bit for bit on the same seeded inputs (run on an MI355X)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_00830_amd import synth
+from paper_2605_00830_amd.synth import Graph, GraphSet
+
+pytestmark = pytest.mark.gpu
+
+UNIT = synth.UNIT_COSTS
+PAPER = synth.PAPER_COSTS
+HIGH = (4, 12, 12, 1, 10, 10)
+ODD = (3, 1, 2, 5, 1, 3)
+
+
+@pytest.fixture(scope="module")
+def ged():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_00830_amd import ged as g
+    g.load()
+    return g
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_vs_oracle(ged, graphs, pairs, costs, K, perpair=False, db=None):
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    say(f"  case: {len(pairs)} pairs, K={K}, costs={costs}, perpair={perpair}")
+    own = db is None
+    if own:
+        db = ged.Database(graphs)
+    res = ged.kbest(db, pairs, costs, K, perpair=perpair, with_cand=True)
+    if own:
+        db.close()
+    d, m, off = oracle.kbest_pairs(graphs, pairs, costs, K)
+    np.testing.assert_array_equal(res.offsets, off)
+    bad = np.nonzero(res.dist != d)[0]
+    assert bad.size == 0, f"dist differs on pairs {bad[:10].tolist()}: gpu {res.dist[bad[:10]].tolist()} oracle {d[bad[:10]].tolist()}"
+    np.testing.assert_array_equal(res.maps, m)
+    assert (res.cand >= pairs.shape[0] * 0).all()
+    return res
+
+
+def tiny_set(seed, count, n_max, p, nvl, nel):
+    gs = [synth.random_small_graph(seed, k, n_max, p, nvl, nel) for k in range(count)]
+    return GraphSet.from_graphs(gs)
+
+
+@pytest.mark.parametrize("costs", [UNIT, PAPER, ODD, HIGH])
+@pytest.mark.parametrize("K", [1, 2, 3, 7, 64, 1024])
+def test_tiny_random_pairs(ged, costs, K):
+    graphs = tiny_set(100 + K, 60, 9, 0.45, 3, 3)
+    pairs = [[2 * k, 2 * k + 1] for k in range(30)] + [[k, k] for k in range(0, 60, 7)]
+    gpu_vs_oracle(ged, graphs, pairs, costs, K)
+
+
+def test_identity_is_zero(ged):
+    graphs = tiny_set(7, 20, 12, 0.4, 4, 2)
+    pairs = [[k, k] for k in range(20)]
+    res = gpu_vs_oracle(ged, graphs, pairs, PAPER, 3)
+    assert (res.dist == 0).all()
+
+
+def test_empty_graphs(ged):
+    z = np.zeros(0, np.int32)
+    empty = Graph(0, z, z, z, z)
+    g = synth.random_small_graph(9, 0, 7, 0.5, 3, 2, n_min=5)
+    graphs = GraphSet.from_graphs([empty, g, empty])
+    pairs = [[0, 1], [1, 0], [0, 2], [1, 1]]
+    for costs in (UNIT, PAPER, ODD):
+        res = gpu_vs_oracle(ged, graphs, pairs, costs, 4)
+        assert res.dist[0] == costs[2] * g.n + costs[5] * g.m
+        assert res.dist[1] == costs[1] * g.n + costs[4] * g.m
+        assert res.dist[2] == 0
+
+
+@pytest.mark.parametrize("K", [1, 16, 64, 1024])
+def test_pair_er_8x9(ged, K):
+    w = synth.pair_er_8x9()
+    gpu_vs_oracle(ged, w.graphs, [[0, 1], [1, 0]], w.costs, K)
+
+
+def test_batch_er_subset(ged):
+    w = synth.batch_er_10_30(512)
+    gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K)
+
+
+def test_query_molecule_subset(ged):
+    w = synth.query_molecule_10_70(120)
+    gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K)
+
+
+def test_stress_smallest_pairs(ged):
+    w = synth.stress_er_100_500(256)
+    size = w.graphs.n[w.pairs].max(1)
+    pick = w.pairs[np.argsort(size, kind="stable")[:2]]
+    gpu_vs_oracle(ged, w.graphs, pick, w.costs, w.K)
+
+
+@pytest.mark.parametrize("n1,n2", [(33, 31), (31, 33), (64, 65), (65, 64), (40, 100), (100, 40),
+                                   (130, 129), (300, 260)])
+def test_word_boundaries(ged, n1, n2):
+    g1 = synth.er_graph(13, n1, n1, n1, 0.2, 0.2, 3)
+    g2 = synth.er_graph(14, n2, n2, n2, 0.2, 0.2, 3)
+    graphs = GraphSet.from_graphs([g1, g2])
+    gpu_vs_oracle(ged, graphs, [[0, 1], [1, 0]], UNIT, 8)
+
+
+def test_max_order(ged):
+    g1 = synth.er_graph(15, 0, 512, 512, 0.3, 0.3, 4)
+    g2 = synth.er_graph(15, 1, 512, 512, 0.3, 0.3, 4)
+    graphs = GraphSet.from_graphs([g1, g2])
+    gpu_vs_oracle(ged, graphs, [[0, 1]], UNIT, 4)
+
+
+def test_labelled_edges_many_planes(ged):
+    gs = [synth.random_small_graph(17, k, 20, 0.4, 3, 16, n_min=10) for k in range(16)]
+    graphs = GraphSet.from_graphs(gs)
+    pairs = [[2 * k, 2 * k + 1] for k in range(8)]
+    gpu_vs_oracle(ged, graphs, pairs, PAPER, 32)
+
+
+def test_perpair_equals_batched(ged):
+    w = synth.batch_er_10_30(96)
+    res = gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K, perpair=True)
+    db = ged.Database(w.graphs)
+    res2 = ged.kbest(db, w.pairs, w.costs, w.K, with_cand=True)
+    db.close()
+    np.testing.assert_array_equal(res.dist, res2.dist)
+    np.testing.assert_array_equal(res.maps, res2.maps)
+    np.testing.assert_array_equal(res.cand, res2.cand)
+
+
+def test_repeat_runs_identical(ged):
+    w = synth.batch_er_10_30(256)
+    db = ged.Database(w.graphs)
+    plan = ged.Plan(db, w.pairs, w.K)
+    outs = []
+    for _ in range(3):
+        dist, maps, cand = plan.outputs(with_cand=True)
+        plan.run(w.costs, dist, maps, cand)
+        outs.append((dist.cpu().numpy(), maps.cpu().numpy(), cand.cpu().numpy()))
+    plan.close()
+    db.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_errors(ged):
+    w = synth.pair_er_8x9()
+    db = ged.Database(w.graphs)
+    with pytest.raises(ged.GedError) as e:
+        ged.Plan(db, [[0, 1]], 0)
+    assert e.value.status == ged.GED_EINVAL
+    with pytest.raises(ged.GedError) as e:
+        ged.Plan(db, [[0, 1]], ged.MAX_K + 1)
+    assert e.value.status == ged.GED_EUNSUPPORTED
+    with pytest.raises(ged.GedError) as e:
+        ged.Plan(db, [[0, 2]], 4)
+    assert e.value.status == ged.GED_EINVAL
+    plan = ged.Plan(db, [[0, 1]], 4)
+    dist, maps, _ = plan.outputs()
+    with pytest.raises(ged.GedError) as e:
+        plan.run((1, -1, 1, 1, 1, 1), dist, maps)
+    assert e.value.status == ged.GED_EINVAL
+    with pytest.raises(ged.GedError) as e:
+        plan.run((2 ** 30, 1, 1, 1, 1, 1), dist, maps)
+    assert e.value.status == ged.GED_EINVAL and "overflow" in str(e.value)
+    plan.close()
+    empty = ged.Plan(db, np.zeros((0, 2), np.int64), 4)
+    d0, m0, _ = empty.outputs()
+    empty.run(UNIT, d0, m0)
+    empty.close()
+    db.close()
