@@ -160,6 +160,17 @@ ged_status ged_plan_run_perpair(ged_plan *plan, ged_costs costs, int32_t *d_dist
                                 int32_t *d_map, int64_t *d_cand, void *stream);
 ged_status ged_plan_destroy(ged_plan *plan);
 
+/* Measurement hooks.  With timing enabled, ged_plan_run and
+ * ged_plan_run_perpair record a HIP event on `stream` right before the
+ * plan's first search-kernel launch and right after its last one; once that
+ * stream has been synchronized, ged_plan_kernel_ms returns the elapsed
+ * milliseconds between the two events of the most recent run (GED_EINVAL if
+ * timing is off or nothing has run).  ged_plan_kernel_launches returns how
+ * many search-kernel launches the most recent run made. */
+ged_status ged_plan_set_timing(ged_plan *plan, int32_t enable);
+ged_status ged_plan_kernel_ms(ged_plan *plan, float *ms);
+ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
+
 /* One-shot forms: create a plan, run it on `stream`, synchronize `stream`,
  * destroy the plan.  Same arguments and errors as above. */
 ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs,

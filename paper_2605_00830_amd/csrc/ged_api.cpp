@@ -88,6 +88,10 @@ struct ged_plan {
     std::vector<int64_t> pair_n;   // n1 + n2 per pair, for the overflow bound
     std::vector<int64_t> pair_m;   // m1 + m2 per pair
     std::vector<Bin> bins;
+    bool timing = false;
+    bool timed_run = false;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    int64_t launches = 0;
 };
 
 namespace {
@@ -99,6 +103,8 @@ void free_plan(ged_plan *p) {
         if (b.d_queue) (void)hipFree(b.d_queue);
         if (b.d_ws) (void)hipFree(b.d_ws);
     }
+    if (p->ev_start) (void)hipEventDestroy(p->ev_start);
+    if (p->ev_stop) (void)hipEventDestroy(p->ev_stop);
     delete p;
 }
 
@@ -428,9 +434,13 @@ static ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int
     const gedk::DbView view{plan->db->d_graphs, plan->db->d_adj, plan->db->d_vlab, plan->db->planes};
     const gedk::Costs c{costs.vsub, costs.vdel, costs.vins, costs.esub, costs.edel, costs.eins};
     const gedk::Outputs o{d_dist, d_map, d_cand};
+    for (Bin &b : plan->bins) GED_HIP(gedk::launch_fill_zero(b.d_queue, (int)b.h_work.size() + 1, s));
+    plan->timed_run = false;
+    plan->launches = 0;
+    if (plan->timing) GED_HIP(hipEventRecord(plan->ev_start, s));
     for (Bin &b : plan->bins) {
         const int nwork = (int)b.h_work.size();
-        GED_HIP(gedk::launch_fill_zero(b.d_queue, nwork + 1, s));
+        plan->launches += perpair ? nwork : 1;
         if (!perpair) {
             GED_HIP(gedk::launch_block(b.shape, view, b.d_work, nwork, b.d_queue, c, plan->K, b.d_ws,
                                        b.ws_stride, o, b.grid, s));
@@ -440,6 +450,34 @@ static ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int
                                            plan->K, b.d_ws, b.ws_stride, o, 1, s));
         }
     }
+    if (plan->timing) {
+        GED_HIP(hipEventRecord(plan->ev_stop, s));
+        plan->timed_run = true;
+    }
+    return ok();
+}
+
+ged_status ged_plan_set_timing(ged_plan *plan, int32_t enable) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    if (enable && !plan->ev_start) {
+        GED_HIP(hipEventCreate(&plan->ev_start));
+        GED_HIP(hipEventCreate(&plan->ev_stop));
+    }
+    plan->timing = enable != 0;
+    plan->timed_run = false;
+    return ok();
+}
+
+ged_status ged_plan_kernel_ms(ged_plan *plan, float *ms) {
+    if (!plan || !ms) return fail(GED_EINVAL, "NULL argument");
+    if (!plan->timing || !plan->timed_run) return fail(GED_EINVAL, "no timed run recorded");
+    GED_HIP(hipEventElapsedTime(ms, plan->ev_start, plan->ev_stop));
+    return ok();
+}
+
+ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches) {
+    if (!plan || !launches) return fail(GED_EINVAL, "NULL argument");
+    *launches = plan->launches;
     return ok();
 }
 

@@ -45,6 +45,7 @@ EXPORTS = (
     "ged_db_create", "ged_db_destroy", "ged_db_count", "ged_db_device_bytes", "ged_db_order",
     "ged_plan_create", "ged_plan_map_size", "ged_plan_run", "ged_plan_run_perpair",
     "ged_plan_destroy", "ged_kbest", "ged_kbest_perpair",
+    "ged_plan_set_timing", "ged_plan_kernel_ms", "ged_plan_kernel_launches",
 )
 
 
@@ -74,6 +75,9 @@ def load(path: str = LIB_PATH):
         "ged_plan_destroy": ([P], i32),
         "ged_kbest": ([P, P, i64, Costs, i32, P, P, P], i32),
         "ged_kbest_perpair": ([P, P, i64, Costs, i32, P, P, P], i32),
+        "ged_plan_set_timing": ([P, i32], i32),
+        "ged_plan_kernel_ms": ([P, P], i32),
+        "ged_plan_kernel_launches": ([P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -198,6 +202,21 @@ class Plan:
             raise ValueError("cand must be an int64 tensor of npairs entries")
         _check(fn(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
                   None if cand is None else cand.data_ptr(), _stream_handle(stream)))
+
+    def set_timing(self, enable: bool = True):
+        _check(load().ged_plan_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_ms(self) -> float:
+        """Elapsed ms between the events around the last run's search kernels
+        (the stream must have been synchronized)."""
+        out = ctypes.c_float()
+        _check(load().ged_plan_kernel_ms(self._h, ctypes.byref(out)))
+        return float(out.value)
+
+    def kernel_launches(self) -> int:
+        out = ctypes.c_int64()
+        _check(load().ged_plan_kernel_launches(self._h, ctypes.byref(out)))
+        return int(out.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None:
