@@ -6,8 +6,8 @@
  * "Efficient Accelerated Graph Edit Distance Computation on GPU" (Dabah and
  * Herten): a level-by-level search over vertex mappings of the source graph
  * g1 onto the target graph g2 that keeps the K children of least partial
- * edit distance at every level (Alg. 1; branching Sec. 4.1, evaluation by
- * implied edge operations Sec. 2.3 and Alg. 2, selection Sec. 4.2), inserts
+ * edit distance at every level (Alg. 1; branching Sec. 4.2.1, evaluation by
+ * implied edge operations Sec. 2.3 and Alg. 2, selection Sec. 4.3), inserts
  * the unmatched target vertices at the end (Sec. 4.4.1) and returns the
  * cheapest complete edit path: an upper bound of the exact GED (Sec. 2.2).
  *
@@ -32,7 +32,7 @@
  * Readings fixed by this library where the paper leaves a choice open:
  *   - g1's vertices are edited in index order 0..n1-1 (the loop of Alg. 1).
  *   - A node's children are the substitutions by each unused g2 vertex in
- *     ascending index order, followed by the deletion (Sec. 4.1).
+ *     ascending index order, followed by the deletion (Sec. 4.2.1).
  *   - When several children share the K-th smallest partial edit distance,
  *     those generated first (parent by parent in beam order, then in child
  *     order) take the remaining places.  The surviving beam keeps

@@ -21,9 +21,9 @@
  *                           (Sec. 4.5): the minimum of oracle_induced_cost over
  *                           every injective mapping V1 -> V2 u {deleted}.
  *   oracle_kbest         -- the K-Best search (Alg. 1), with branching
- *                           (Sec. 4.1), partial edit distance by implied edges
+ *                           (Sec. 4.2.1), partial edit distance by implied edges
  *                           (Sec. 2.3, Alg. 2), selection of the best K
- *                           (Sec. 4.2) and final insertion of the unmatched
+ *                           (Sec. 4.3) and final insertion of the unmatched
  *                           target vertices (Sec. 4.4.1).
  *
  * Readings taken where the paper is silent (each is listed in the design
@@ -310,7 +310,7 @@ int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const i
 
     for (int i = 0; i < n1; i++) {
         /* branching: every node yields one child per unused g2 vertex, then a
-         * deletion child (Sec. 4.1); children are listed node by node */
+         * deletion child (Sec. 4.2.1); children are listed node by node */
         int64_t cap = B * (int64_t)(n2 + 1);
         int32_t *c_par = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
         int32_t *c_u = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
@@ -340,7 +340,7 @@ int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const i
             keys[C].order = C;
             C++;
         }
-        /* selection: the K children of least partial edit distance (Sec. 4.2) */
+        /* selection: the K children of least partial edit distance (Sec. 4.3) */
         qsort(keys, (size_t)C, sizeof(rank_key), cmp_rank);
         int64_t keep = C < K ? C : K;
         /* the next beam keeps the survivors in generation order */

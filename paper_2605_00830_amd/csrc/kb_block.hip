@@ -11,8 +11,8 @@
 //               del    = |P(v_i)| - kept           g1 edges deleted
 //               ins    = |Img & N2(u)| - kept      g2 edges inserted
 //               relab  = |Phi & N2(u) & label-mismatch|
-//             The deletion child costs vdel + edel*|P(v_i)| (Sec. 4.1).
-//   select    the K best children (Sec. 4.2) without sorting: threshold T =
+//             The deletion child costs vdel + edel*|P(v_i)| (Sec. 4.2.1).
+//   select    the K best children (Sec. 4.3) without sorting: threshold T =
 //             K-th smallest partial edit distance from an LDS histogram, all
 //             children below T, and the first (K - #below) children equal to
 //             T in generation order (exclusive block scans).  Survivors are

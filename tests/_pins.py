@@ -9,7 +9,7 @@ same quantity by a different route:
   the paper written as one formula over the padded adjacency).
 * scratch_beam: the K-Best search of Alg. 1 where every child's partial edit
   distance is recomputed from scratch as the cost of all edit operations in
-  its path (Sec. 4.1, Evaluation), instead of the incremental implied-edge
+  its path (Sec. 4.2.2), instead of the incremental implied-edge
   scan, and ranking uses the child's mapping tuple itself (deleted = n2) for
   the generation-order tie-break.
 """
