@@ -151,6 +151,25 @@ ged_status ged_db_order(const ged_db *db, int64_t id, int32_t *n);
  * ---------------------------------------------------------------------- */
 ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                            ged_plan **out);
+
+/* Kernel schedules.  GED_SCHED_AUTO lets the library choose per size bin:
+ * a wavefront per pair (beam in registers) where n1, n2 <= 32 and K <= 64,
+ * else a 256-thread workgroup per pair.  GED_SCHED_BLOCK forces the
+ * workgroup-per-pair kernel for every pair.  Every schedule computes the
+ * same result bit for bit. */
+#define GED_SCHED_AUTO 0
+#define GED_SCHED_BLOCK 1
+
+typedef struct {
+    int32_t schedule;        /* GED_SCHED_* */
+    int32_t groups_per_cu;   /* resident workgroups per CU of a persistent launch;
+                                0 = the occupancy limit, larger values are clamped to it */
+} ged_plan_options;
+
+/* ged_plan_create with options (NULL = defaults).  GED_EINVAL for an
+ * unknown schedule or groups_per_cu < 0. */
+ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
+                              const ged_plan_options *options, ged_plan **out);
 ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries);
 ged_status ged_plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
                         int64_t *d_cand, void *stream);

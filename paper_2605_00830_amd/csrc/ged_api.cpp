@@ -69,6 +69,7 @@ struct ged_db {
 namespace {
 
 struct Bin {
+    bool wave = false;           // wavefront-per-pair kernel (else workgroup-per-pair)
     gedk::BlockShape shape{};
     std::vector<WorkItem> h_work;
     WorkItem *d_work = nullptr;
@@ -320,6 +321,16 @@ ged_status ged_db_order(const ged_db *db, int64_t id, int32_t *n) {
 
 ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                            ged_plan **out) {
+    return ged_plan_create_ex(db, h_pairs, npairs, K, nullptr, out);
+}
+
+ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
+                              const ged_plan_options *options, ged_plan **out) {
+    ged_plan_options opt{GED_SCHED_AUTO, 0};
+    if (options) opt = *options;
+    if (opt.schedule != GED_SCHED_AUTO && opt.schedule != GED_SCHED_BLOCK)
+        return fail(GED_EINVAL, "unknown schedule %d", opt.schedule);
+    if (opt.groups_per_cu < 0) return fail(GED_EINVAL, "groups_per_cu < 0");
     if (!out) return fail(GED_EINVAL, "out is NULL");
     *out = nullptr;
     if (!db) return fail(GED_EINVAL, "db is NULL");
@@ -354,8 +365,11 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
         const GraphRec &g2 = db->h_graphs[(size_t)d];
         p->pair_n[(size_t)i] = (int64_t)g1.n + g2.n;
         p->pair_m[(size_t)i] = (int64_t)g1.m + g2.m;
+        const bool wave = opt.schedule == GED_SCHED_AUTO && g1.n <= gedk::kWaveMaxN &&
+                          g2.n <= gedk::kWaveMaxN && K <= gedk::kWaveMaxK;
         const int W = pow2_at_least(std::max(1, g2.w));
-        Bin &b = bins[W];
+        Bin &b = bins[wave ? 0 : W];
+        b.wave = wave;
         b.shape.W = W;
         b.shape.PL = PL;
         b.shape.nmax1 = std::max(b.shape.nmax1, g1.n);
@@ -390,17 +404,18 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
         });
         b.shape.KS = (K + gedk::kBlockThreads - 1) / gedk::kBlockThreads * gedk::kBlockThreads;
         int per_cu = 0;
-        e = gedk::block_max_resident(b.shape, &per_cu);
+        e = b.wave ? gedk::wave_max_resident(b.shape.PL, &per_cu) : gedk::block_max_resident(b.shape, &per_cu);
         if (e != hipSuccess || per_cu <= 0) {
             free_plan(p);
             return fail(GED_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
         }
+        if (opt.groups_per_cu > 0) per_cu = std::min(per_cu, opt.groups_per_cu);
         const int64_t nwork = (int64_t)b.h_work.size();
         b.grid = (int)std::min<int64_t>(nwork, (int64_t)per_cu * cus);
-        b.ws_stride = gedk::block_workspace_bytes(b.shape);
+        b.ws_stride = b.wave ? 0 : gedk::block_workspace_bytes(b.shape);
         e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * (size_t)nwork);
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * (size_t)(nwork + 1));
-        if (e == hipSuccess) e = hipMalloc(&b.d_ws, b.ws_stride * (size_t)b.grid);
+        if (e == hipSuccess && !b.wave) e = hipMalloc(&b.d_ws, b.ws_stride * (size_t)b.grid);
         if (e == hipSuccess)
             e = hipMemcpy(b.d_work, b.h_work.data(), sizeof(WorkItem) * (size_t)nwork, hipMemcpyHostToDevice);
         p->bins.push_back(b);
@@ -441,7 +456,16 @@ static ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int
     for (Bin &b : plan->bins) {
         const int nwork = (int)b.h_work.size();
         plan->launches += perpair ? nwork : 1;
-        if (!perpair) {
+        if (b.wave) {
+            if (!perpair) {
+                GED_HIP(gedk::launch_wave(b.shape.PL, view, b.d_work, nwork, b.d_queue, c, plan->K, o,
+                                          b.grid, s));
+            } else {
+                for (int i = 0; i < nwork; ++i)
+                    GED_HIP(gedk::launch_wave(b.shape.PL, view, b.d_work + i, 1, b.d_queue + 1 + i, c,
+                                              plan->K, o, 1, s));
+            }
+        } else if (!perpair) {
             GED_HIP(gedk::launch_block(b.shape, view, b.d_work, nwork, b.d_queue, c, plan->K, b.d_ws,
                                        b.ws_stride, o, b.grid, s));
         } else {

@@ -66,4 +66,13 @@ hipError_t launch_block(const BlockShape &s, const DbView &db, const WorkItem *w
                         Outputs out, int grid, hipStream_t stream);
 hipError_t launch_fill_zero(int *p, int count, hipStream_t stream);
 
+// Wavefront-per-pair kernel family: n1, n2 <= 32 and K <= 64; the beam lives
+// in registers (one slot per lane) and LDS.
+constexpr int kWaveMaxN = 32;
+constexpr int kWaveMaxK = 64;
+
+hipError_t wave_max_resident(int PL, int *blocks_per_cu);
+hipError_t launch_wave(int PL, const DbView &db, const WorkItem *work, int nwork, int *queue, Costs c,
+                       int K, Outputs out, int grid, hipStream_t stream);
+
 }  // namespace gedk

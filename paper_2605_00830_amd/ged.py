@@ -30,6 +30,13 @@ class GedError(RuntimeError):
         self.status = status
 
 
+SCHED_AUTO, SCHED_BLOCK = 0, 1
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
+
+
 class Costs(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in ("vsub", "vdel", "vins", "esub", "edel", "eins")]
 
@@ -46,6 +53,7 @@ EXPORTS = (
     "ged_plan_create", "ged_plan_map_size", "ged_plan_run", "ged_plan_run_perpair",
     "ged_plan_destroy", "ged_kbest", "ged_kbest_perpair",
     "ged_plan_set_timing", "ged_plan_kernel_ms", "ged_plan_kernel_launches",
+    "ged_plan_create_ex",
 )
 
 
@@ -78,6 +86,7 @@ def load(path: str = LIB_PATH):
         "ged_plan_set_timing": ([P, i32], i32),
         "ged_plan_kernel_ms": ([P, P], i32),
         "ged_plan_kernel_launches": ([P, P], i32),
+        "ged_plan_create_ex": ([P, P, i64, i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -166,14 +175,15 @@ def _pairs_array(pairs) -> np.ndarray:
 class Plan:
     """A reusable batched launch plan (ged_plan_create)."""
 
-    def __init__(self, db: Database, pairs, K: int):
+    def __init__(self, db: Database, pairs, K: int, schedule: int = SCHED_AUTO, groups_per_cu: int = 0):
         lib = load()
         self.db = db
         self.pairs = _pairs_array(pairs)
         self.K = int(K)
         handle = ctypes.c_void_p()
-        _check(lib.ged_plan_create(db.handle, self.pairs.ctypes.data, len(self.pairs), self.K,
-                                   ctypes.byref(handle)))
+        opt = PlanOptions(int(schedule), int(groups_per_cu))
+        _check(lib.ged_plan_create_ex(db.handle, self.pairs.ctypes.data, len(self.pairs), self.K,
+                                      ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
         size = ctypes.c_int64()
         _check(lib.ged_plan_map_size(self._h, ctypes.byref(size)))
@@ -243,9 +253,9 @@ class Result:
 
 
 def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: bool = False,
-          stream=None) -> Result:
+          stream=None, schedule: int = SCHED_AUTO, groups_per_cu: int = 0) -> Result:
     """K-Best GED of every (src, dst) pair; synchronizes and returns host arrays."""
-    plan = Plan(db, pairs, K)
+    plan = Plan(db, pairs, K, schedule=schedule, groups_per_cu=groups_per_cu)
     try:
         dist, maps, cand = plan.outputs(with_cand=with_cand)
         plan.run(costs, dist, maps, cand, stream=stream, perpair=perpair)

@@ -31,13 +31,16 @@ def say(msg):
     sys.stdout.flush()
 
 
-def gpu_vs_oracle(ged, graphs, pairs, costs, K, perpair=False, db=None):
+SCHEDULES = [0, 1]   # library's choice (wavefront kernel where eligible), workgroup kernel only
+
+
+def gpu_vs_oracle(ged, graphs, pairs, costs, K, perpair=False, db=None, schedule=0):
     pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
-    say(f"  case: {len(pairs)} pairs, K={K}, costs={costs}, perpair={perpair}")
+    say(f"  case: {len(pairs)} pairs, K={K}, costs={costs}, perpair={perpair}, schedule={schedule}")
     own = db is None
     if own:
         db = ged.Database(graphs)
-    res = ged.kbest(db, pairs, costs, K, perpair=perpair, with_cand=True)
+    res = ged.kbest(db, pairs, costs, K, perpair=perpair, with_cand=True, schedule=schedule)
     if own:
         db.close()
     d, m, off = oracle.kbest_pairs(graphs, pairs, costs, K)
@@ -54,12 +57,13 @@ def tiny_set(seed, count, n_max, p, nvl, nel):
     return GraphSet.from_graphs(gs)
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("costs", [UNIT, PAPER, ODD, HIGH])
-@pytest.mark.parametrize("K", [1, 2, 3, 7, 64, 1024])
-def test_tiny_random_pairs(ged, costs, K):
+@pytest.mark.parametrize("K", [1, 2, 3, 7, 63, 64, 65, 1024])
+def test_tiny_random_pairs(ged, costs, K, schedule):
     graphs = tiny_set(100 + K, 60, 9, 0.45, 3, 3)
     pairs = [[2 * k, 2 * k + 1] for k in range(30)] + [[k, k] for k in range(0, 60, 7)]
-    gpu_vs_oracle(ged, graphs, pairs, costs, K)
+    gpu_vs_oracle(ged, graphs, pairs, costs, K, schedule=schedule)
 
 
 def test_identity_is_zero(ged):
@@ -82,15 +86,35 @@ def test_empty_graphs(ged):
         assert res.dist[2] == 0
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("K", [1, 16, 64, 1024])
-def test_pair_er_8x9(ged, K):
+def test_pair_er_8x9(ged, K, schedule):
     w = synth.pair_er_8x9()
-    gpu_vs_oracle(ged, w.graphs, [[0, 1], [1, 0]], w.costs, K)
+    gpu_vs_oracle(ged, w.graphs, [[0, 1], [1, 0]], w.costs, K, schedule=schedule)
 
 
-def test_batch_er_subset(ged):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_batch_er_subset(ged, schedule):
     w = synth.batch_er_10_30(512)
-    gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K)
+    gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K, schedule=schedule)
+
+
+@pytest.mark.parametrize("K", [5, 32, 64])
+def test_wave_size_limits(ged, K):
+    """Pairs at and around the wavefront kernel's limits (n = 31, 32, 33), labelled edges,
+    dense and empty graphs, run in one batch so both kernels share a launch plan."""
+    gs = []
+    for k, (n, p) in enumerate([(32, 0.5), (32, 0.0), (31, 0.9), (33, 0.3), (1, 0.0), (32, 1.0),
+                                (20, 0.3), (32, 0.25)]):
+        g = synth.er_graph(23, k, n, n, p, p, 4)
+        g.elabel = (np.arange(g.m) % 5).astype(np.int32)
+        gs.append(g)
+    graphs = GraphSet.from_graphs(gs)
+    pairs = [[a, b] for a in range(len(gs)) for b in range(len(gs))]
+    for costs in (UNIT, ODD):
+        res = gpu_vs_oracle(ged, graphs, pairs, costs, K, schedule=0)
+        res2 = gpu_vs_oracle(ged, graphs, pairs, costs, K, schedule=1)
+        np.testing.assert_array_equal(res.cand, res2.cand)
 
 
 def test_query_molecule_subset(ged):
@@ -128,9 +152,10 @@ def test_labelled_edges_many_planes(ged):
     gpu_vs_oracle(ged, graphs, pairs, PAPER, 32)
 
 
-def test_perpair_equals_batched(ged):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_perpair_equals_batched(ged, schedule):
     w = synth.batch_er_10_30(96)
-    res = gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K, perpair=True)
+    res = gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K, perpair=True, schedule=schedule)
     db = ged.Database(w.graphs)
     res2 = ged.kbest(db, w.pairs, w.costs, w.K, with_cand=True)
     db.close()
