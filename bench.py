@@ -101,6 +101,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-perpair", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -122,6 +124,18 @@ def main():
     dist, maps, cand = plan.outputs(with_cand=True)
     stream = torch.cuda.current_stream()
     plan.set_timing(True)
+
+    bins = plan.bins()
+    dominant = max(bins, key=lambda b: b[1])[0] if bins else "none"
+    log(f"bins: {bins}")
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes read and written once")
+        del src, dst
 
     for _ in range(args.warmup):
         plan.run(w.costs, dist, maps, cand, stream=stream)
@@ -156,7 +170,7 @@ def main():
     achieved = ops / (kms / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 2),
                 "unit": "Tops/s", "frac": round(achieved / PEAK_INT32_TOPS, 5), "traffic": None,
-                "kernel": "kb_block_kernel", "kernel_ms": round(kms, 4),
+                "kernel": dominant, "kernel_ms": round(kms, 4), "bins": bins,
                 "candidates_per_launch": int(ce.sum()), "ops_per_launch": ops}
 
     perpair = None

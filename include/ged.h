@@ -190,6 +190,17 @@ ged_status ged_plan_set_timing(ged_plan *plan, int32_t enable);
 ged_status ged_plan_kernel_ms(ged_plan *plan, float *ms);
 ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
 
+/* The plan's size bins, in launch order.  For bin `index`: *kernel is
+ * GED_KERNEL_WAVE (a wavefront per pair) or GED_KERNEL_BLOCK (a workgroup
+ * per pair), *npairs the pairs in the bin, *grid the persistent launch's
+ * workgroups, *words the target-row words the instantiation handles.
+ * Any output pointer may be NULL. */
+#define GED_KERNEL_WAVE 0
+#define GED_KERNEL_BLOCK 1
+ged_status ged_plan_bin_count(const ged_plan *plan, int32_t *count);
+ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kernel, int64_t *npairs,
+                             int32_t *grid, int32_t *words);
+
 /* One-shot forms: create a plan, run it on `stream`, synchronize `stream`,
  * destroy the plan.  Same arguments and errors as above. */
 ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs,

@@ -499,6 +499,24 @@ ged_status ged_plan_kernel_ms(ged_plan *plan, float *ms) {
     return ok();
 }
 
+ged_status ged_plan_bin_count(const ged_plan *plan, int32_t *count) {
+    if (!plan || !count) return fail(GED_EINVAL, "NULL argument");
+    *count = (int32_t)plan->bins.size();
+    return ok();
+}
+
+ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kernel, int64_t *npairs,
+                             int32_t *grid, int32_t *words) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    if (index < 0 || index >= (int32_t)plan->bins.size()) return fail(GED_EINVAL, "bin %d out of range", index);
+    const Bin &b = plan->bins[(size_t)index];
+    if (kernel) *kernel = b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK;
+    if (npairs) *npairs = (int64_t)b.h_work.size();
+    if (grid) *grid = b.grid;
+    if (words) *words = b.wave ? 1 : b.shape.W;
+    return ok();
+}
+
 ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches) {
     if (!plan || !launches) return fail(GED_EINVAL, "NULL argument");
     *launches = plan->launches;

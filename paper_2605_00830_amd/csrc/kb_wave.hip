@@ -15,7 +15,10 @@
 //              PED' = PED + [alpha1(v_i) != alpha2(u)] vsub + edel (|P| - kept)
 //                     + eins (|Img & N2(u)| - kept) + esub relabelled,
 //              kept = |Phi & N2(u)|  (implied edge operations, Sec. 2.3);
-//            the deletion child costs PED + vdel + edel |P|; used u -> SENT.
+//            the deletion child costs PED + vdel + edel |P|.  Children held
+//            as unsigned values; an invalid child (u used, u >= n2, or an
+//            empty slot) is 0xffffffff, obtained by OR-ing the sign-extended
+//            bit u of (Img | invalid-u mask).
 //   select   T = K-th smallest PED by counting probes: count(PED <= t) is a
 //            sum of popcounts of wave ballots, galloping then bisection from
 //            the wave minimum.  Every child below T survives and the first
@@ -29,12 +32,16 @@
 //            formula, so the value is identical to the candidate's).
 // Completion adds vins (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the
 // first lane of least total is the result.
+//
+// SMALL selects 24-bit multiply-adds, valid when every cost is below 2^22
+// (counts are at most 32, and the plan's overflow bound keeps every sum in
+// range); otherwise full 32-bit multiplies.
 #include "ged_internal.h"
 
 namespace gedk {
 namespace {
 
-constexpr int SENT = 0x7fffffff;
+constexpr uint32_t INVALID = 0xffffffffu;
 constexpr uint32_t DEL8 = 0xffu;
 
 struct WaveArgs {
@@ -50,26 +57,27 @@ struct WaveArgs {
 // DPP row rotations (row_ror:k) reduce inside each 16-lane row; the four
 // row results are combined with readlane.
 template <int CTRL>
-__device__ __forceinline__ int dpp_ror(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+__device__ __forceinline__ uint32_t dpp_ror(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
 }
 
-__device__ __forceinline__ int wave_sum(int v) {
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     v += dpp_ror<0x121>(v);
     v += dpp_ror<0x122>(v);
     v += dpp_ror<0x124>(v);
     v += dpp_ror<0x128>(v);
-    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
-           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+           (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
 }
 
-__device__ __forceinline__ int wave_min(int v) {
+__device__ __forceinline__ uint32_t wave_umin(uint32_t v) {
     v = min(v, dpp_ror<0x121>(v));
     v = min(v, dpp_ror<0x122>(v));
     v = min(v, dpp_ror<0x124>(v));
     v = min(v, dpp_ror<0x128>(v));
-    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+    const uint32_t a = min((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
+    const uint32_t b = min((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+    return min(a, b);
 }
 
 __device__ __forceinline__ int lanes_below(unsigned long long m) {
@@ -88,7 +96,17 @@ __device__ __forceinline__ uint32_t phi_byte(const uint32_t *plane, int j, int s
     return (plane[(j >> 2) * 64 + slot] >> ((j & 3) * 8)) & 0xffu;
 }
 
-template <int PL>
+// bit u of m, sign-extended: 0 or 0xffffffff
+__device__ __forceinline__ uint32_t bit_mask(uint32_t m, int u) {
+    return (uint32_t)__builtin_amdgcn_sbfe((int)m, u, 1);
+}
+
+template <bool SMALL>
+__device__ __forceinline__ uint32_t mul_cost(uint32_t count, uint32_t cost) {
+    return SMALL ? __umul24(count, cost) : count * cost;
+}
+
+template <int PL, bool SMALL>
 __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_phi[2][8 * 64];   // [half][word j/4][slot]: bytes of phi
@@ -96,7 +114,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     __shared__ int s_item;
 
     const int lane = threadIdx.x;
-    const Costs c = a.c;
+    const uint32_t vsub = (uint32_t)a.c.vsub, vdel = (uint32_t)a.c.vdel, vins = (uint32_t)a.c.vins;
+    const uint32_t esub = (uint32_t)a.c.esub, edel = (uint32_t)a.c.edel, eins = (uint32_t)a.c.eins;
+    const uint32_t kc = edel + eins;
     const int K = a.K;
     const int P = a.db.planes;
 
@@ -124,16 +144,16 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             p2[b] = (PL > 0 && b < P && lane < n2) ? A2[(size_t)(1 + b) * n2 + lane] : 0u;
         }
         const uint32_t umask = n2 >= 32 ? 0xffffffffu : ((1u << n2) - 1u);
+        const int ngroups = (n2 + 3) >> 2;     // u is processed in groups of four
 
-        int ped = 0, ein = 0;
-        uint32_t img = 0u;
+        uint32_t ped = 0u, img = 0u, ein = 0u;
         int nb = 1, cur = 0;
         long long ce = 0;
 
         for (int i = 0; i < n1; ++i) {
             const uint32_t nbm = (uint32_t)__builtin_amdgcn_readlane((int)r1, i) & ((1u << i) - 1u);
             const int lab1 = __builtin_amdgcn_readlane(l1, i);
-            const int degP = __popc(nbm);
+            const uint32_t degP = (uint32_t)__popc(nbm);
             uint32_t q[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) q[b] = (uint32_t)__builtin_amdgcn_readlane((int)p1[b], i) & nbm;
@@ -154,59 +174,69 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 for (int b = 0; b < PLA; ++b)
                     if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
             }
-            const int base = ped + c.edel * degP;
-            const int kc = c.edel + c.eins;
-            int cand[32];
-            int lmin = SENT;
+            const uint32_t base = ped + mul_cost<SMALL>(degP, edel);
+            const uint32_t blocked = live ? (img | ~umask) : 0xffffffffu;
+            uint32_t cand[32];
+            uint32_t lmin = INVALID;
 #pragma unroll
-            for (int u = 0; u < 32; ++u) {
-                cand[u] = SENT;
-                if (u < n2) {
-                    const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r2, u);
-                    const int vs = ((vsm >> u) & 1u) ? c.vsub : 0;
-                    const uint32_t kp = phi & R;
-                    int d = base + vs + c.eins * __popc(img & R) - kc * __popc(kp);
-                    if (PL > 0) {
-                        uint32_t diff = 0u;
+            for (int g = 0; g < 8; ++g) {
+                if (g < ngroups) {
 #pragma unroll
-                        for (int b = 0; b < PLA; ++b)
-                            diff |= phib[b] ^ (uint32_t)__builtin_amdgcn_readlane((int)p2[b], u);
-                        d += c.esub * __popc(kp & diff);
+                    for (int u = 4 * g; u < 4 * g + 4; ++u) {
+                        const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r2, u);
+                        const uint32_t vs = ((vsm >> u) & 1u) ? vsub : 0u;
+                        const uint32_t kp = phi & R;
+                        uint32_t d = base + vs + mul_cost<SMALL>((uint32_t)__popc(img & R), eins) -
+                                     mul_cost<SMALL>((uint32_t)__popc(kp), kc);
+                        if (PL > 0) {
+                            uint32_t diff = 0u;
+#pragma unroll
+                            for (int b = 0; b < PLA; ++b)
+                                diff |= phib[b] ^ (uint32_t)__builtin_amdgcn_readlane((int)p2[b], u);
+                            d += mul_cost<SMALL>((uint32_t)__popc(kp & diff), esub);
+                        }
+                        d |= bit_mask(blocked, u);
+                        cand[u] = d;
+                        lmin = min(lmin, d);
                     }
-                    d = (live && !((img >> u) & 1u)) ? d : SENT;
-                    cand[u] = d;
-                    lmin = min(lmin, d);
+                } else {
+#pragma unroll
+                    for (int u = 4 * g; u < 4 * g + 4; ++u) cand[u] = INVALID;
                 }
             }
-            const int cdel = live ? ped + c.vdel + c.edel * degP : SENT;
+            const uint32_t cdel = live ? base + vdel : INVALID;
             lmin = min(lmin, cdel);
-            const int V = wave_sum(live ? n2 - __popc(img) + 1 : 0);
+            const int V = (int)wave_sum(live ? (uint32_t)(n2 - __popc(img) + 1) : 0u);
             ce += V;
 
             // ---------------- threshold T: the K-th smallest PED
-            int T = SENT;
+            uint32_t T = INVALID;
             const bool trim = V > K;
             if (trim) {
-                auto count_le = [&](int t) {
+                auto count_le = [&](uint32_t t) {
                     int cnt = __popcll(__ballot(cdel <= t));
 #pragma unroll
-                    for (int u = 0; u < 32; ++u)
-                        if (u < n2) cnt += __popcll(__ballot(cand[u] <= t));
+                    for (int g = 0; g < 8; ++g) {
+                        if (g < ngroups) {
+#pragma unroll
+                            for (int u = 4 * g; u < 4 * g + 4; ++u) cnt += __popcll(__ballot(cand[u] <= t));
+                        }
+                    }
                     return cnt;
                 };
-                int lo = wave_min(lmin), t = lo, step = 1, hi;
+                uint32_t lo = wave_umin(lmin), t = lo, step = 1, hi;
                 for (;;) {
                     if (count_le(t) >= K) {
                         hi = t;
                         break;
                     }
                     lo = t + 1;
-                    // count_le(SENT - 1) = V > K, so the walk stops by then
-                    t = (t > SENT - 1 - step) ? SENT - 1 : t + step;
-                    step = step < (1 << 29) ? step << 1 : step;
+                    // count_le(INVALID - 1) = V > K, so the walk stops by then
+                    t = (t > INVALID - 1u - step) ? INVALID - 1u : t + step;
+                    step = step < (1u << 29) ? step << 1 : step;
                 }
                 while (lo < hi) {
-                    const int mid = lo + ((hi - lo) >> 1);
+                    const uint32_t mid = lo + ((hi - lo) >> 1);
                     if (count_le(mid) >= K) hi = mid;
                     else lo = mid + 1;
                 }
@@ -214,19 +244,24 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             }
 
             // ---------------- survivors in generation order
-            uint32_t ltm = 0u, eqm = 0u;
+            // bit u of ltm / lem: child u below / at most T (built high u first)
+            uint32_t ltm = 0u, lem = 0u;
 #pragma unroll
-            for (int u = 0; u < 32; ++u) {
-                if (u < n2) {
-                    ltm |= (cand[u] < T) ? (1u << u) : 0u;
-                    eqm |= (trim && cand[u] == T) ? (1u << u) : 0u;
+            for (int g = 7; g >= 0; --g) {
+                if (g < ngroups) {
+#pragma unroll
+                    for (int u = 4 * g + 3; u >= 4 * g; --u) {
+                        ltm = ltm + ltm + (cand[u] < T ? 1u : 0u);
+                        lem = lem + lem + (cand[u] <= T ? 1u : 0u);
+                    }
                 }
             }
+            const uint32_t eqm = trim ? (lem & ~ltm) : 0u;
             const bool ltd = cdel < T;
             const bool eqd = trim && cdel == T;
             const int lt_l = __popc(ltm) + (ltd ? 1 : 0);
             const int eq_l = __popc(eqm) + (eqd ? 1 : 0);
-            const int quota = trim ? K - wave_sum(lt_l) : 0;
+            const int quota = trim ? K - (int)wave_sum((uint32_t)lt_l) : 0;
             int r = min(max(quota - wave_excl_scan6(eq_l), 0), eq_l);
             uint32_t keepm = ltm;
             bool keepd = ltd;
@@ -247,9 +282,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const uint32_t u = sel & 0xffu;
             const bool sub = u != DEL8;
             const int us = sub ? (int)u : 0;
-            const int ped_p = __shfl(ped, p);
+            const uint32_t ped_p = (uint32_t)__shfl((int)ped, p);
             const uint32_t img_p = (uint32_t)__shfl((int)img, p);
-            const int ein_p = __shfl(ein, p);
+            const uint32_t ein_p = (uint32_t)__shfl((int)ein, p);
             const uint32_t R = (uint32_t)__shfl((int)r2, us);
             const int lab2u = __shfl(l2, us);
             uint32_t rp[PLA];
@@ -278,21 +313,23 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     for (int b = 0; b < PLA; ++b)
                         if (PL > 0 && ((q[b] >> j) & 1u)) phbp[b] |= bit;
                 }
+                const uint32_t pbase = ped_p + mul_cost<SMALL>(degP, edel);
                 if (sub) {
                     const uint32_t kp = php & R;
-                    const int inimg = __popc(img_p & R);
-                    int d = ped_p + c.edel * degP + (lab1 != lab2u ? c.vsub : 0) + c.eins * inimg - kc * __popc(kp);
+                    const uint32_t inimg = (uint32_t)__popc(img_p & R);
+                    uint32_t d = pbase + (lab1 != lab2u ? vsub : 0u) + mul_cost<SMALL>(inimg, eins) -
+                                 mul_cost<SMALL>((uint32_t)__popc(kp), kc);
                     if (PL > 0) {
                         uint32_t diff = 0u;
 #pragma unroll
                         for (int b = 0; b < PLA; ++b) diff |= phbp[b] ^ rp[b];
-                        d += c.esub * __popc(kp & diff);
+                        d += mul_cost<SMALL>((uint32_t)__popc(kp & diff), esub);
                     }
                     ped = d;
                     img = img_p | (1u << u);
                     ein = ein_p + inimg;
                 } else {
-                    ped = ped_p + c.vdel + c.edel * degP;
+                    ped = pbase + vdel;
                     img = img_p;
                     ein = ein_p;
                 }
@@ -303,11 +340,13 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
         }
 
         // ---------------- completion and best leaf
-        const int total = lane < nb ? ped + c.vins * (n2 - __popc(img)) + c.eins * (g2.m - ein) : SENT;
-        const int best_total = wave_min(total);
+        const uint32_t total = lane < nb ? ped + mul_cost<SMALL>((uint32_t)(n2 - __popc(img)), vins) +
+                                               mul_cost<SMALL>((uint32_t)g2.m - ein, eins)
+                                         : INVALID;
+        const uint32_t best_total = wave_umin(total);
         const int best = (int)__builtin_ctzll(__ballot(total == best_total));
         if (lane == 0) {
-            a.out.dist[wi.out] = best_total;
+            a.out.dist[wi.out] = (int)best_total;
             if (a.out.cand) a.out.cand[wi.out] = ce;
         }
         if (lane < n1) {
@@ -318,29 +357,39 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     }
 }
 
-template <int PL>
+template <int PL, bool SMALL>
 const void *wave_ptr() {
-    return reinterpret_cast<const void *>(&kb_wave_kernel<PL>);
+    return reinterpret_cast<const void *>(&kb_wave_kernel<PL, SMALL>);
 }
 
-const void *select_wave(int PL) {
-    if (PL == 0) return wave_ptr<0>();
-    if (PL == 2) return wave_ptr<2>();
-    if (PL == 4) return wave_ptr<4>();
+const void *select_wave(int PL, bool small) {
+    if (PL == 0) return small ? wave_ptr<0, true>() : wave_ptr<0, false>();
+    if (PL == 2) return small ? wave_ptr<2, true>() : wave_ptr<2, false>();
+    if (PL == 4) return small ? wave_ptr<4, true>() : wave_ptr<4, false>();
     return nullptr;
+}
+
+bool small_costs(const Costs &c) {
+    const int32_t lim = 1 << 22;
+    return c.vsub < lim && c.vdel < lim && c.vins < lim && c.esub < lim && c.edel < lim && c.eins < lim;
 }
 
 }  // namespace
 
 hipError_t wave_max_resident(int PL, int *blocks_per_cu) {
-    const void *k = select_wave(PL);
-    if (!k) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64, 0);
+    const void *k = select_wave(PL, true);
+    const void *k2 = select_wave(PL, false);
+    if (!k || !k2) return hipErrorInvalidValue;
+    int a = 0, b = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k, 64, 0);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k2, 64, 0);
+    *blocks_per_cu = a < b ? a : b;
+    return e;
 }
 
 hipError_t launch_wave(int PL, const DbView &db, const WorkItem *work, int nwork, int *queue, Costs c,
                        int K, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_wave(PL);
+    const void *k = select_wave(PL, small_costs(c));
     if (!k || grid <= 0 || K > kWaveMaxK) return hipErrorInvalidValue;
     WaveArgs a;
     a.db = db;

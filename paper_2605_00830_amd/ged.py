@@ -53,7 +53,7 @@ EXPORTS = (
     "ged_plan_create", "ged_plan_map_size", "ged_plan_run", "ged_plan_run_perpair",
     "ged_plan_destroy", "ged_kbest", "ged_kbest_perpair",
     "ged_plan_set_timing", "ged_plan_kernel_ms", "ged_plan_kernel_launches",
-    "ged_plan_create_ex",
+    "ged_plan_create_ex", "ged_plan_bin_count", "ged_plan_bin_info",
 )
 
 
@@ -87,6 +87,8 @@ def load(path: str = LIB_PATH):
         "ged_plan_kernel_ms": ([P, P], i32),
         "ged_plan_kernel_launches": ([P, P], i32),
         "ged_plan_create_ex": ([P, P, i64, i32, P, P], i32),
+        "ged_plan_bin_count": ([P, P], i32),
+        "ged_plan_bin_info": ([P, i32, P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -222,6 +224,20 @@ class Plan:
         out = ctypes.c_float()
         _check(load().ged_plan_kernel_ms(self._h, ctypes.byref(out)))
         return float(out.value)
+
+    def bins(self):
+        """[(kernel name, pairs, grid, words)] for each size bin, in launch order."""
+        lib = load()
+        cnt = ctypes.c_int32()
+        _check(lib.ged_plan_bin_count(self._h, ctypes.byref(cnt)))
+        out = []
+        for k in range(cnt.value):
+            kern, npairs, grid, words = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+            _check(lib.ged_plan_bin_info(self._h, k, ctypes.byref(kern), ctypes.byref(npairs),
+                                         ctypes.byref(grid), ctypes.byref(words)))
+            name = "kb_wave_kernel" if kern.value == 0 else "kb_block_kernel"
+            out.append((name, int(npairs.value), int(grid.value), int(words.value)))
+        return out
 
     def kernel_launches(self) -> int:
         out = ctypes.c_int64()
