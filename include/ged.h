@@ -195,6 +195,29 @@ ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
  * per pair), *npairs the pairs in the bin, *grid the persistent launch's
  * workgroups, *words the target-row words the instantiation handles.
  * Any output pointer may be NULL. */
+/* HIP graphs.  ged_plan_capture records one ged_plan_run with these costs
+ * and outputs into a HIP graph owned by the plan (replacing any previous
+ * one); ged_plan_replay launches it on `stream`.  The graph holds only
+ * kernel nodes (work-queue counters are cleared by a kernel, not a memset).
+ * The output buffers must stay allocated while the graph is replayed.
+ * `stream` must not be the null stream (HIP cannot capture it): GED_EINVAL.
+ * ged_plan_replay without a captured graph: GED_EINVAL. */
+ged_status ged_plan_capture(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
+                            int64_t *d_cand, void *stream);
+ged_status ged_plan_replay(ged_plan *plan, void *stream);
+
+/* Autotuner.  For every size bin, times the candidate schedules on the
+ * plan's own pairs -- the wavefront kernel where the bin is eligible and
+ * the workgroup kernel, each at several resident-workgroup counts -- and
+ * keeps the fastest; every candidate computes identical results, which are
+ * written to the outputs.  With cache_path (may be NULL) the choices are
+ * read from / appended to that text file, keyed by device, K and the bin's
+ * shape, and a cached choice is applied without timing.  Synchronizes
+ * `stream`.  *timed_bins (may be NULL) gets the number of bins that were
+ * timed rather than read from the cache.  A captured graph is discarded. */
+ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
+                         void *stream, const char *cache_path, int32_t *timed_bins);
+
 #define GED_KERNEL_WAVE 0
 #define GED_KERNEL_BLOCK 1
 ged_status ged_plan_bin_count(const ged_plan *plan, int32_t *count);

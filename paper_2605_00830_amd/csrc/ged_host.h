@@ -1,0 +1,54 @@
+// Host-side internals shared by the C ABI's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "ged.h"
+#include "ged_internal.h"
+
+namespace gedh {
+
+// Record `fmt` as the calling thread's last error and return `s`.
+ged_status fail(ged_status s, const char *fmt, ...);
+inline ged_status ok() { return GED_OK; }
+
+#define GED_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::gedh::fail(GED_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+ged_status check_costs(const ged_costs &c);
+
+// Shape checks of one host graph (index g for messages), host-only.
+ged_status check_graph_shape(const ged_graph &G, int64_t g);
+// Words of the packed adjacency (rows plus label planes) of an n-vertex graph.
+int64_t packed_words(int n, int planes);
+// Append graph G's packed rows, label planes and vertex labels to adj/vlab
+// and describe them in R (offsets into adj/vlab).  `labels` is the sorted
+// table of edge labels whose index is the label code; a label missing from
+// it, a vertex out of range, a self-loop or a repeated edge is GED_EINVAL.
+ged_status pack_graph(const ged_graph &G, int64_t g, const std::vector<int32_t> &labels, int planes,
+                      std::vector<uint32_t> &adj, std::vector<int32_t> &vlab, gedk::GraphRec &R);
+
+}  // namespace gedh
+
+struct ged_db {
+    int device = 0;
+    int64_t count = 0;
+    int32_t planes = 0;
+    std::vector<int32_t> elabels;   // sorted distinct edge labels; index = label code
+    std::vector<gedk::GraphRec> h_graphs;
+    gedk::GraphRec *d_graphs = nullptr;
+    uint32_t *d_adj = nullptr;
+    int32_t *d_vlab = nullptr;
+    int64_t bytes = 0;
+};
+
+namespace gedh {
+ged_status check_device(const ged_db *db);
+}  // namespace gedh

@@ -21,6 +21,9 @@ struct GraphRec {
     int64_t vlab;    // offset into the vertex-label pool
 };
 
+// A set of packed graphs: a database, or the staged queries of a serving
+// batch.  Work items index graphs of a source view (g1) and a target view
+// (g2); both use the same edge-label coding.
 struct DbView {
     const GraphRec *graphs;
     const uint32_t *adj;
@@ -61,7 +64,7 @@ struct BlockShape {
 
 size_t block_workspace_bytes(const BlockShape &s);
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu);
-hipError_t launch_block(const BlockShape &s, const DbView &db, const WorkItem *work, int nwork,
+hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
                         int *queue, Costs c, int K, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream);
 hipError_t launch_fill_zero(int *p, int count, hipStream_t stream);
@@ -72,7 +75,7 @@ constexpr int kWaveMaxN = 32;
 constexpr int kWaveMaxK = 64;
 
 hipError_t wave_max_resident(int PL, int *blocks_per_cu);
-hipError_t launch_wave(int PL, const DbView &db, const WorkItem *work, int nwork, int *queue, Costs c,
+hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue, Costs c,
                        int K, Outputs out, int grid, hipStream_t stream);
 
 }  // namespace gedk

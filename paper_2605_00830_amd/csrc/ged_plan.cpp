@@ -1,0 +1,562 @@
+// ged_plan.cpp -- launch plans of the C ABI (include/ged.h): size bins,
+// persistent work-queue launches, the per-pair baseline, HIP graph capture
+// and the autotuner.  No step of the search runs on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ged.h"
+#include "ged_host.h"
+#include "ged_internal.h"
+
+using gedh::fail;
+using gedh::ok;
+using gedk::GraphRec;
+using gedk::WorkItem;
+
+namespace {
+
+int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// One size bin: pairs sharing a kernel instantiation.
+struct Bin {
+    bool wave_ok = false;        // every pair fits the wavefront kernel
+    bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
+    gedk::BlockShape shape{};    // workgroup-kernel instantiation and workspace shape
+    std::vector<WorkItem> h_work;
+    WorkItem *d_work = nullptr;
+    int *d_queue = nullptr;      // [1 + nwork]: batched counter, then one per pair
+    void *d_ws = nullptr;        // workgroup-kernel workspace
+    size_t ws_stride = 0;
+    int ws_blocks = 0;           // workgroups the workspace holds
+    int grid = 0;                // current persistent grid
+    int groups_per_cu = 0;       // current resident workgroups per CU
+    int max_wave_per_cu = 0;     // occupancy limits
+    int max_block_per_cu = 0;
+};
+
+}  // namespace
+
+struct ged_plan {
+    ged_db *db = nullptr;
+    int64_t npairs = 0;
+    int32_t K = 0;
+    int64_t map_entries = 0;
+    int cus = 0;
+    std::vector<int64_t> pair_n;   // n1 + n2 per pair, for the overflow bound
+    std::vector<int64_t> pair_m;   // m1 + m2 per pair
+    std::vector<Bin> bins;
+    bool timing = false;
+    bool timed_run = false;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    int64_t launches = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(ged_plan *p) {
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+}
+
+void free_plan(ged_plan *p) {
+    if (!p) return;
+    drop_graph(p);
+    for (Bin &b : p->bins) {
+        if (b.d_work) (void)hipFree(b.d_work);
+        if (b.d_queue) (void)hipFree(b.d_queue);
+        if (b.d_ws) (void)hipFree(b.d_ws);
+    }
+    if (p->ev_start) (void)hipEventDestroy(p->ev_start);
+    if (p->ev_stop) (void)hipEventDestroy(p->ev_stop);
+    delete p;
+}
+
+// Every partial edit distance and every completed cost of a pair is at most
+// max_vertex_cost * (n1 + n2) + max_edge_cost * (m1 + m2); keep it below the
+// kernels' sentinel INT32_MAX.
+ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
+    const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
+    const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
+    const int64_t lim = (int64_t)std::numeric_limits<int32_t>::max() - 1;
+    for (int64_t i = 0; i < p->npairs; ++i) {
+        const int64_t bound = vmax * p->pair_n[i] + emax * p->pair_m[i];
+        if (bound > lim)
+            return fail(GED_EINVAL, "costs may overflow int32 on pair %lld (bound %lld)", (long long)i,
+                        (long long)bound);
+    }
+    return ok();
+}
+
+// Point bin `b` at one kernel family and resident-workgroup count
+// (groups_per_cu <= 0: the occupancy limit); grows the workspace as needed.
+ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu) {
+    if (wave && !b.wave_ok) return fail(GED_EINVAL, "bin does not fit the wavefront kernel");
+    const int limit = wave ? b.max_wave_per_cu : b.max_block_per_cu;
+    const int gpc = groups_per_cu > 0 ? std::min(groups_per_cu, limit) : limit;
+    const int64_t nwork = (int64_t)b.h_work.size();
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nwork, (int64_t)gpc * p->cus));
+    if (!wave && b.ws_blocks < grid) {
+        if (b.d_ws) GED_HIP(hipFree(b.d_ws));
+        b.d_ws = nullptr;
+        b.ws_blocks = 0;
+        b.ws_stride = gedk::block_workspace_bytes(b.shape);
+        hipError_t e = hipMalloc(&b.d_ws, b.ws_stride * (size_t)grid);
+        if (e != hipSuccess) return fail(GED_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
+        b.ws_blocks = grid;
+    }
+    b.wave = wave;
+    b.groups_per_cu = gpc;
+    b.grid = grid;
+    return ok();
+}
+
+struct RunCtx {
+    gedk::DbView view;
+    gedk::Costs c;
+    gedk::Outputs o;
+    hipStream_t s;
+};
+
+ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool perpair) {
+    const int nwork = (int)b.h_work.size();
+    if (nwork == 0) return ok();
+    if (b.wave) {
+        if (!perpair) {
+            GED_HIP(gedk::launch_wave(b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, r.o, b.grid, r.s));
+        } else {
+            for (int i = 0; i < nwork; ++i)
+                GED_HIP(gedk::launch_wave(b.shape.PL, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K, r.o,
+                                          1, r.s));
+        }
+    } else if (!perpair) {
+        GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, b.d_ws, b.ws_stride,
+                                   r.o, b.grid, r.s));
+    } else {
+        for (int i = 0; i < nwork; ++i)
+            GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K, b.d_ws,
+                                       b.ws_stride, r.o, 1, r.s));
+    }
+    return ok();
+}
+
+ged_status prepare_run(ged_plan *plan, const ged_costs &costs, int32_t *d_dist, int32_t *d_map,
+                       int64_t *d_cand, void *stream, RunCtx *r) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    ged_status st = gedh::check_costs(costs);
+    if (st != GED_OK) return st;
+    if (plan->npairs > 0 && !d_dist) return fail(GED_EINVAL, "d_dist is NULL");
+    if (plan->map_entries > 0 && !d_map) return fail(GED_EINVAL, "d_map is NULL");
+    st = check_overflow(plan, costs);
+    if (st != GED_OK) return st;
+    st = gedh::check_device(plan->db);
+    if (st != GED_OK) return st;
+    r->view = gedk::DbView{plan->db->d_graphs, plan->db->d_adj, plan->db->d_vlab, plan->db->planes};
+    r->c = gedk::Costs{costs.vsub, costs.vdel, costs.vins, costs.esub, costs.edel, costs.eins};
+    r->o = gedk::Outputs{d_dist, d_map, d_cand};
+    r->s = static_cast<hipStream_t>(stream);
+    return ok();
+}
+
+ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                    void *stream, bool perpair, bool allow_timing) {
+    RunCtx r;
+    ged_status st = prepare_run(plan, costs, d_dist, d_map, d_cand, stream, &r);
+    if (st != GED_OK) return st;
+    for (Bin &b : plan->bins) GED_HIP(gedk::launch_fill_zero(b.d_queue, (int)b.h_work.size() + 1, r.s));
+    const bool timing = plan->timing && allow_timing;
+    plan->timed_run = false;
+    plan->launches = 0;
+    if (timing) GED_HIP(hipEventRecord(plan->ev_start, r.s));
+    for (Bin &b : plan->bins) {
+        plan->launches += perpair ? (int64_t)b.h_work.size() : 1;
+        st = launch_bin(plan, b, r, perpair);
+        if (st != GED_OK) return st;
+    }
+    if (timing) {
+        GED_HIP(hipEventRecord(plan->ev_stop, r.s));
+        plan->timed_run = true;
+    }
+    return ok();
+}
+
+// ---------------------------------------------------------------- tuner cache
+
+std::string device_key() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s:%dcu", prop.gcnArchName, prop.multiProcessorCount);
+    for (char *c = buf; *c; ++c)
+        if (*c == ' ' || *c == '|') *c = '_';
+    return buf;
+}
+
+std::string bin_key(const std::string &dev, int K, const Bin &b) {
+    int lg = 0;
+    while ((1ll << (lg + 1)) <= (long long)b.h_work.size()) ++lg;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|K%d|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, b.wave_ok ? 1 : 0, b.shape.W,
+             b.shape.PL, b.shape.nmax1, b.shape.nmax2, lg);
+    return buf;
+}
+
+// cache lines: "<key> <wave 0|1> <groups_per_cu>"
+std::map<std::string, std::pair<int, int>> read_cache(const char *path) {
+    std::map<std::string, std::pair<int, int>> m;
+    if (!path) return m;
+    FILE *f = fopen(path, "r");
+    if (!f) return m;
+    char key[512];
+    int w = 0, g = 0;
+    while (fscanf(f, "%511s %d %d", key, &w, &g) == 3) m[key] = {w, g};
+    fclose(f);
+    return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K, ged_plan **out) {
+    return ged_plan_create_ex(db, h_pairs, npairs, K, nullptr, out);
+}
+
+ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
+                              const ged_plan_options *options, ged_plan **out) {
+    ged_plan_options opt{GED_SCHED_AUTO, 0};
+    if (options) opt = *options;
+    if (opt.schedule != GED_SCHED_AUTO && opt.schedule != GED_SCHED_BLOCK)
+        return fail(GED_EINVAL, "unknown schedule %d", opt.schedule);
+    if (opt.groups_per_cu < 0) return fail(GED_EINVAL, "groups_per_cu < 0");
+    if (!out) return fail(GED_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!db) return fail(GED_EINVAL, "db is NULL");
+    if (npairs < 0) return fail(GED_EINVAL, "npairs < 0");
+    if (npairs > 0 && !h_pairs) return fail(GED_EINVAL, "pairs is NULL");
+    if (npairs > (int64_t)std::numeric_limits<int32_t>::max()) return fail(GED_EUNSUPPORTED, "more than 2^31-1 pairs");
+    if (K < 1) return fail(GED_EINVAL, "K must be >= 1 (got %d)", K);
+    if (K > GED_MAX_K) return fail(GED_EUNSUPPORTED, "K = %d exceeds %d", K, GED_MAX_K);
+    ged_status st = gedh::check_device(db);
+    if (st != GED_OK) return st;
+
+    ged_plan *p = new (std::nothrow) ged_plan;
+    if (!p) return fail(GED_ENOMEM, "host allocation failed");
+    p->db = db;
+    p->npairs = npairs;
+    p->K = K;
+    p->pair_n.resize((size_t)npairs);
+    p->pair_m.resize((size_t)npairs);
+
+    // bins keyed by kernel: 0 = wavefront kernel, else target row words
+    // rounded up to a power of two (the workgroup kernel's instantiation)
+    const int PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
+    std::map<int, Bin> bins;
+    int64_t off = 0;
+    for (int64_t i = 0; i < npairs; ++i) {
+        const int64_t s = h_pairs[i].src, d = h_pairs[i].dst;
+        if (s < 0 || s >= db->count || d < 0 || d >= db->count) {
+            free_plan(p);
+            return fail(GED_EINVAL, "pair %lld: graph id out of range", (long long)i);
+        }
+        const GraphRec &g1 = db->h_graphs[(size_t)s];
+        const GraphRec &g2 = db->h_graphs[(size_t)d];
+        p->pair_n[(size_t)i] = (int64_t)g1.n + g2.n;
+        p->pair_m[(size_t)i] = (int64_t)g1.m + g2.m;
+        const bool wave_ok = g1.n <= gedk::kWaveMaxN && g2.n <= gedk::kWaveMaxN && K <= gedk::kWaveMaxK;
+        const bool wave = opt.schedule == GED_SCHED_AUTO && wave_ok;
+        const int W = pow2_at_least(std::max(1, g2.w));
+        Bin &b = bins[wave ? 0 : W];
+        b.wave_ok = wave;
+        b.wave = wave;
+        b.shape.W = W;
+        b.shape.PL = PL;
+        b.shape.nmax1 = std::max(b.shape.nmax1, g1.n);
+        b.shape.nmax2 = std::max(b.shape.nmax2, g2.n);
+        WorkItem wi;
+        wi.src = (int32_t)s;
+        wi.dst = (int32_t)d;
+        wi.out = (int32_t)i;
+        wi.pad = 0;
+        wi.map_off = off;
+        b.h_work.push_back(wi);
+        off += g1.n;
+    }
+    p->map_entries = off;
+
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(GED_EDEVICE, "device query failed: %s", hipGetErrorString(e));
+    }
+
+    for (auto &kv : bins) {
+        p->bins.push_back(Bin());
+        Bin &b = p->bins.back();
+        b.wave_ok = kv.second.wave_ok;
+        b.shape = kv.second.shape;
+        b.h_work.swap(kv.second.h_work);
+        // longest first: work grows with n1 * (n2 + 1)
+        std::stable_sort(b.h_work.begin(), b.h_work.end(), [&](const WorkItem &x, const WorkItem &y) {
+            const int64_t cx = (int64_t)db->h_graphs[x.src].n * (db->h_graphs[x.dst].n + 1);
+            const int64_t cy = (int64_t)db->h_graphs[y.src].n * (db->h_graphs[y.dst].n + 1);
+            return cx > cy;
+        });
+        b.shape.KS = (K + gedk::kBlockThreads - 1) / gedk::kBlockThreads * gedk::kBlockThreads;
+        e = gedk::block_max_resident(b.shape, &b.max_block_per_cu);
+        if (e == hipSuccess && b.wave_ok) e = gedk::wave_max_resident(b.shape.PL, &b.max_wave_per_cu);
+        if (e != hipSuccess || b.max_block_per_cu <= 0 || (b.wave_ok && b.max_wave_per_cu <= 0)) {
+            free_plan(p);
+            return fail(GED_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
+        }
+        const int64_t nwork = (int64_t)b.h_work.size();
+        e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * (size_t)nwork);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * (size_t)(nwork + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(b.d_work, b.h_work.data(), sizeof(WorkItem) * (size_t)nwork, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_plan(p);
+            return fail(GED_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
+        }
+        st = configure_bin(p, b, b.wave_ok, opt.groups_per_cu);
+        if (st != GED_OK) {
+            free_plan(p);
+            return st;
+        }
+    }
+    *out = p;
+    return ok();
+}
+
+ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries) {
+    if (!plan || !entries) return fail(GED_EINVAL, "NULL argument");
+    *entries = plan->map_entries;
+    return ok();
+}
+
+ged_status ged_plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                        void *stream) {
+    return plan_run(plan, costs, d_dist, d_map, d_cand, stream, false, true);
+}
+
+ged_status ged_plan_run_perpair(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
+                                int64_t *d_cand, void *stream) {
+    return plan_run(plan, costs, d_dist, d_map, d_cand, stream, true, true);
+}
+
+ged_status ged_plan_destroy(ged_plan *plan) {
+    free_plan(plan);
+    return ok();
+}
+
+ged_status ged_plan_set_timing(ged_plan *plan, int32_t enable) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    if (enable && !plan->ev_start) {
+        GED_HIP(hipEventCreate(&plan->ev_start));
+        GED_HIP(hipEventCreate(&plan->ev_stop));
+    }
+    plan->timing = enable != 0;
+    plan->timed_run = false;
+    return ok();
+}
+
+ged_status ged_plan_kernel_ms(ged_plan *plan, float *ms) {
+    if (!plan || !ms) return fail(GED_EINVAL, "NULL argument");
+    if (!plan->timing || !plan->timed_run) return fail(GED_EINVAL, "no timed run recorded");
+    GED_HIP(hipEventElapsedTime(ms, plan->ev_start, plan->ev_stop));
+    return ok();
+}
+
+ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches) {
+    if (!plan || !launches) return fail(GED_EINVAL, "NULL argument");
+    *launches = plan->launches;
+    return ok();
+}
+
+ged_status ged_plan_bin_count(const ged_plan *plan, int32_t *count) {
+    if (!plan || !count) return fail(GED_EINVAL, "NULL argument");
+    *count = (int32_t)plan->bins.size();
+    return ok();
+}
+
+ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kernel, int64_t *npairs, int32_t *grid,
+                             int32_t *words) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    if (index < 0 || index >= (int32_t)plan->bins.size()) return fail(GED_EINVAL, "bin %d out of range", index);
+    const Bin &b = plan->bins[(size_t)index];
+    if (kernel) *kernel = b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK;
+    if (npairs) *npairs = (int64_t)b.h_work.size();
+    if (grid) *grid = b.grid;
+    if (words) *words = b.wave ? 1 : b.shape.W;
+    return ok();
+}
+
+ged_status ged_plan_capture(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                            void *stream) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    if (!stream) return fail(GED_EINVAL, "the null stream cannot be captured; pass a created stream");
+    RunCtx r;
+    ged_status st = prepare_run(plan, costs, d_dist, d_map, d_cand, stream, &r);
+    if (st != GED_OK) return st;
+    drop_graph(plan);
+    GED_HIP(hipStreamBeginCapture(r.s, hipStreamCaptureModeThreadLocal));
+    st = plan_run(plan, costs, d_dist, d_map, d_cand, stream, false, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(r.s, &g);
+    if (st != GED_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(GED_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(GED_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    plan->graph = g;
+    plan->graph_exec = x;
+    return ok();
+}
+
+ged_status ged_plan_replay(ged_plan *plan, void *stream) {
+    if (!plan) return fail(GED_EINVAL, "plan is NULL");
+    if (!plan->graph_exec) return fail(GED_EINVAL, "no captured graph");
+    GED_HIP(hipGraphLaunch(plan->graph_exec, static_cast<hipStream_t>(stream)));
+    return ok();
+}
+
+ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, void *stream,
+                         const char *cache_path, int32_t *timed_bins) {
+    RunCtx r;
+    ged_status st = prepare_run(plan, costs, d_dist, d_map, nullptr, stream, &r);
+    if (st != GED_OK) return st;
+    drop_graph(plan);
+    const std::string dev = device_key();
+    std::map<std::string, std::pair<int, int>> cache = read_cache(cache_path);
+    FILE *append = nullptr;
+    int timed = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    GED_HIP(hipEventCreate(&e0));
+    GED_HIP(hipEventCreate(&e1));
+    for (Bin &b : plan->bins) {
+        const std::string key = bin_key(dev, plan->K, b);
+        auto hit = cache.find(key);
+        if (hit != cache.end() && (hit->second.first == 0 || b.wave_ok)) {
+            st = configure_bin(plan, b, hit->second.first != 0, hit->second.second);
+            if (st != GED_OK) break;
+            continue;
+        }
+        // candidates: each kernel family at the occupancy limit and fractions of it
+        std::vector<std::pair<bool, int>> cands;
+        for (int fam = 0; fam < 2; ++fam) {
+            const bool wave = fam == 0;
+            if (wave && !b.wave_ok) continue;
+            const int lim = wave ? b.max_wave_per_cu : b.max_block_per_cu;
+            for (int g = lim; g >= 1; g = g / 2) {
+                cands.push_back({wave, g});
+                if (g == 1) break;
+            }
+        }
+        float best_ms = 1e30f;
+        std::pair<bool, int> best = cands.front();
+        for (const auto &cd : cands) {
+            st = configure_bin(plan, b, cd.first, cd.second);
+            if (st != GED_OK) break;
+            float ms_sum[3] = {0, 0, 0};
+            for (int rep = 0; rep < 4 && st == GED_OK; ++rep) {
+                hipError_t he = gedk::launch_fill_zero(b.d_queue, (int)b.h_work.size() + 1, r.s);
+                if (he == hipSuccess) he = hipEventRecord(e0, r.s);
+                if (he != hipSuccess) {
+                    st = fail(GED_EDEVICE, "tuning launch failed: %s", hipGetErrorString(he));
+                    break;
+                }
+                st = launch_bin(plan, b, r, false);
+                if (st != GED_OK) break;
+                he = hipEventRecord(e1, r.s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he != hipSuccess) {
+                    st = fail(GED_EDEVICE, "tuning timing failed: %s", hipGetErrorString(he));
+                    break;
+                }
+                if (rep > 0) ms_sum[rep - 1] = ms;   // first run warms up
+            }
+            if (st != GED_OK) break;
+            std::sort(ms_sum, ms_sum + 3);
+            if (ms_sum[1] < best_ms) {
+                best_ms = ms_sum[1];
+                best = cd;
+            }
+        }
+        if (st != GED_OK) break;
+        st = configure_bin(plan, b, best.first, best.second);
+        if (st != GED_OK) break;
+        ++timed;
+        if (cache_path) {
+            if (!append) append = fopen(cache_path, "a");
+            if (append) fprintf(append, "%s %d %d\n", key.c_str(), best.first ? 1 : 0, best.second);
+        }
+    }
+    if (append) fclose(append);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != GED_OK) return st;
+    // leave the outputs holding a full result with the chosen configuration
+    st = plan_run(plan, costs, d_dist, d_map, nullptr, stream, false, false);
+    if (st != GED_OK) return st;
+    GED_HIP(hipStreamSynchronize(r.s));
+    if (timed_bins) *timed_bins = timed;
+    return ok();
+}
+
+ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs, int32_t K,
+                     int32_t *d_dist, int32_t *d_map, void *stream) {
+    ged_status st = gedh::check_costs(costs);
+    if (st != GED_OK) return st;
+    ged_plan *p = nullptr;
+    st = ged_plan_create(db, h_pairs, npairs, K, &p);
+    if (st != GED_OK) return st;
+    st = plan_run(p, costs, d_dist, d_map, nullptr, stream, false, false);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    free_plan(p);
+    if (st != GED_OK) return st;
+    if (e != hipSuccess) return fail(GED_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs, int32_t K,
+                             int32_t *d_dist, int32_t *d_map, void *stream) {
+    ged_status st = gedh::check_costs(costs);
+    if (st != GED_OK) return st;
+    ged_plan *p = nullptr;
+    st = ged_plan_create(db, h_pairs, npairs, K, &p);
+    if (st != GED_OK) return st;
+    st = plan_run(p, costs, d_dist, d_map, nullptr, stream, true, false);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    free_plan(p);
+    if (st != GED_OK) return st;
+    if (e != hipSuccess) return fail(GED_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+}  // extern "C"

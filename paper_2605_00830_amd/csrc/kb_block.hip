@@ -43,7 +43,8 @@ struct WsLayout {
 };
 
 struct BlockArgs {
-    DbView db;
+    DbView src;   // graphs edited (g1)
+    DbView dst;   // target graphs (g2); same edge-label coding as src
     const WorkItem *work;
     int nwork;
     int *queue;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     const int SPT = KS / BT;
     const int K = a.K;
     const Costs c = a.c;
-    const int P = a.db.planes;
+    const int P = a.dst.planes;
 
     for (;;) {
         if (t == 0) s_bc[0] = atomicAdd(a.queue, 1);
@@ -165,13 +166,13 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
         if (item >= a.nwork) break;
 
         const WorkItem wi = a.work[item];
-        const GraphRec g1 = a.db.graphs[wi.src];
-        const GraphRec g2 = a.db.graphs[wi.dst];
+        const GraphRec g1 = a.src.graphs[wi.src];
+        const GraphRec g2 = a.dst.graphs[wi.dst];
         const int n1 = g1.n, n2 = g2.n, w1 = g1.w, w2 = g2.w;
-        const uint32_t *A1 = a.db.adj + g1.adj;
-        const uint32_t *A2 = a.db.adj + g2.adj;
-        const int *L1 = a.db.vlab + g1.vlab;
-        const int *L2 = a.db.vlab + g2.vlab;
+        const uint32_t *A1 = a.src.adj + g1.adj;
+        const uint32_t *A2 = a.dst.adj + g2.adj;
+        const int *L1 = a.src.vlab + g1.vlab;
+        const int *L2 = a.dst.vlab + g2.vlab;
         const size_t pl1 = (size_t)n1 * w1, pl2 = (size_t)n2 * w2;
 
         if (t == 0) {
@@ -499,13 +500,14 @@ hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, BT, 0);
 }
 
-hipError_t launch_block(const BlockShape &s, const DbView &db, const WorkItem *work, int nwork,
+hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
                         int *queue, Costs c, int K, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream) {
     const void *k = select_kernel(s.W, s.PL);
     if (!k || grid <= 0) return hipErrorInvalidValue;
     BlockArgs a;
-    a.db = db;
+    a.src = src;
+    a.dst = dst;
     a.work = work;
     a.nwork = nwork;
     a.queue = queue;

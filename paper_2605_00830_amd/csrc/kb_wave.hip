@@ -45,7 +45,8 @@ constexpr uint32_t INVALID = 0xffffffffu;
 constexpr uint32_t DEL8 = 0xffu;
 
 struct WaveArgs {
-    DbView db;
+    DbView src;   // graphs edited (g1)
+    DbView dst;   // target graphs (g2); same edge-label coding as src
     const WorkItem *work;
     int nwork;
     int *queue;
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     const uint32_t esub = (uint32_t)a.c.esub, edel = (uint32_t)a.c.edel, eins = (uint32_t)a.c.eins;
     const uint32_t kc = edel + eins;
     const int K = a.K;
-    const int P = a.db.planes;
+    const int P = a.dst.planes;
 
     for (;;) {
         if (lane == 0) s_item = atomicAdd(a.queue, 1);
@@ -128,15 +129,15 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
         if (item >= a.nwork) break;
 
         const WorkItem wi = a.work[item];
-        const GraphRec g1 = a.db.graphs[wi.src];
-        const GraphRec g2 = a.db.graphs[wi.dst];
+        const GraphRec g1 = a.src.graphs[wi.src];
+        const GraphRec g2 = a.dst.graphs[wi.dst];
         const int n1 = g1.n, n2 = g2.n;
-        const uint32_t *A1 = a.db.adj + g1.adj;
-        const uint32_t *A2 = a.db.adj + g2.adj;
+        const uint32_t *A1 = a.src.adj + g1.adj;
+        const uint32_t *A2 = a.dst.adj + g2.adj;
         const uint32_t r1 = lane < n1 ? A1[lane] : 0u;
         const uint32_t r2 = lane < n2 ? A2[lane] : 0u;
-        const int l1 = lane < n1 ? a.db.vlab[g1.vlab + lane] : 0;
-        const int l2 = lane < n2 ? a.db.vlab[g2.vlab + lane] : 0;
+        const int l1 = lane < n1 ? a.src.vlab[g1.vlab + lane] : 0;
+        const int l2 = lane < n2 ? a.dst.vlab[g2.vlab + lane] : 0;
         uint32_t p1[PLA], p2[PLA];
 #pragma unroll
         for (int b = 0; b < PLA; ++b) {
@@ -387,12 +388,13 @@ hipError_t wave_max_resident(int PL, int *blocks_per_cu) {
     return e;
 }
 
-hipError_t launch_wave(int PL, const DbView &db, const WorkItem *work, int nwork, int *queue, Costs c,
+hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue, Costs c,
                        int K, Outputs out, int grid, hipStream_t stream) {
     const void *k = select_wave(PL, small_costs(c));
     if (!k || grid <= 0 || K > kWaveMaxK) return hipErrorInvalidValue;
     WaveArgs a;
-    a.db = db;
+    a.src = src;
+    a.dst = dst;
     a.work = work;
     a.nwork = nwork;
     a.queue = queue;

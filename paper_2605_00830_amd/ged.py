@@ -54,6 +54,7 @@ EXPORTS = (
     "ged_plan_destroy", "ged_kbest", "ged_kbest_perpair",
     "ged_plan_set_timing", "ged_plan_kernel_ms", "ged_plan_kernel_launches",
     "ged_plan_create_ex", "ged_plan_bin_count", "ged_plan_bin_info",
+    "ged_plan_capture", "ged_plan_replay", "ged_plan_tune",
 )
 
 
@@ -89,6 +90,9 @@ def load(path: str = LIB_PATH):
         "ged_plan_create_ex": ([P, P, i64, i32, P, P], i32),
         "ged_plan_bin_count": ([P, P], i32),
         "ged_plan_bin_info": ([P, i32, P, P, P, P], i32),
+        "ged_plan_capture": ([P, Costs, P, P, P, P], i32),
+        "ged_plan_replay": ([P, P], i32),
+        "ged_plan_tune": ([P, Costs, P, P, P, ctypes.c_char_p, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -201,17 +205,20 @@ class Plan:
         cand = torch.empty(max(len(self.pairs), 1), dtype=torch.int64, device=device) if with_cand else None
         return dist, maps, cand
 
-    def run(self, costs, dist: torch.Tensor, maps: torch.Tensor, cand: Optional[torch.Tensor] = None,
-            stream=None, perpair: bool = False):
-        lib = load()
-        fn = lib.ged_plan_run_perpair if perpair else lib.ged_plan_run
+    def _check_outputs(self, dist, maps, cand):
         for t, dt in ((dist, torch.int32), (maps, torch.int32)):
             if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
                 raise ValueError("outputs must be contiguous int32 CUDA tensors")
         if dist.numel() < len(self.pairs) or maps.numel() < self.map_size:
             raise ValueError("output tensors are too small")
-        if cand is not None and (cand.dtype != torch.int64 or cand.numel() < len(self.pairs)):
-            raise ValueError("cand must be an int64 tensor of npairs entries")
+        if cand is not None and (cand.dtype != torch.int64 or not cand.is_cuda or cand.numel() < len(self.pairs)):
+            raise ValueError("cand must be an int64 CUDA tensor of npairs entries")
+
+    def run(self, costs, dist: torch.Tensor, maps: torch.Tensor, cand: Optional[torch.Tensor] = None,
+            stream=None, perpair: bool = False):
+        lib = load()
+        fn = lib.ged_plan_run_perpair if perpair else lib.ged_plan_run
+        self._check_outputs(dist, maps, cand)
         _check(fn(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
                   None if cand is None else cand.data_ptr(), _stream_handle(stream)))
 
@@ -224,6 +231,27 @@ class Plan:
         out = ctypes.c_float()
         _check(load().ged_plan_kernel_ms(self._h, ctypes.byref(out)))
         return float(out.value)
+
+    def capture(self, costs, dist: torch.Tensor, maps: torch.Tensor, cand: Optional[torch.Tensor] = None,
+                stream=None):
+        """Record one run into a HIP graph owned by the plan (stream must not be the null stream)."""
+        self._check_outputs(dist, maps, cand)
+        _check(load().ged_plan_capture(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
+                                       None if cand is None else cand.data_ptr(), _stream_handle(stream)))
+
+    def replay(self, stream=None):
+        _check(load().ged_plan_replay(self._h, _stream_handle(stream)))
+
+    def tune(self, costs, dist: torch.Tensor, maps: torch.Tensor, stream=None,
+             cache_path: Optional[str] = None) -> int:
+        """Pick each bin's fastest schedule (see ged_plan_tune); returns the bins timed."""
+        self._check_outputs(dist, maps, None)
+        timed = ctypes.c_int32(0)
+        _check(load().ged_plan_tune(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
+                                    _stream_handle(stream),
+                                    None if cache_path is None else cache_path.encode(),
+                                    ctypes.byref(timed)))
+        return int(timed.value)
 
     def bins(self):
         """[(kernel name, pairs, grid, words)] for each size bin, in launch order."""

@@ -1,0 +1,100 @@
+"""Write tests/golden/digests.json: the CPU oracle's results on the full
+synthetic workloads, as SHA-256 digests of the int32 distances and mappings
+(plus the distances themselves where they are few).
+
+Calls only oracle/ (and the input generators); nothing here comes from the
+GPU library.  Run from the repository root:
+
+    python tests/golden/make_digests.py [--threads 8] [--only NAME ...]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2605_00830_amd import synth  # noqa: E402
+
+OUT = os.path.join(HERE, "digests.json")
+
+
+def digest(dist: np.ndarray, maps: np.ndarray) -> str:
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(dist, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(maps, dtype="<i4").tobytes())
+    return h.hexdigest()
+
+
+def run_oracle(w, pairs, threads):
+    """Oracle over `pairs`, sharded over threads; results in pair order."""
+    oracle._load()
+    order = np.argsort(-(w.graphs.n[pairs[:, 0]].astype(np.int64) * (w.graphs.n[pairs[:, 1]] + 1)), kind="stable")
+    shards = [order[t::threads] for t in range(threads)]
+    res = [None] * threads
+
+    def work(t):
+        res[t] = oracle.kbest_pairs(w.graphs, pairs[shards[t]], w.costs, w.K)
+
+    th = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    n_src = w.graphs.n[pairs[:, 0]].astype(np.int64)
+    off = np.concatenate([[0], np.cumsum(n_src)])
+    dist = np.zeros(len(pairs), np.int64)
+    maps = np.zeros(int(off[-1]), np.int32)
+    for t in range(threads):
+        d, m, o = res[t]
+        dist[shards[t]] = d
+        for k, p in enumerate(shards[t]):
+            maps[off[p]:off[p + 1]] = m[o[k]:o[k] + n_src[p]]
+    return dist, maps
+
+
+WORKLOADS = {
+    "pair_er_8x9_k16": lambda: (synth.pair_er_8x9(), None),
+    "batch_er_n10-30_p0.1-0.3_4096pairs_k64": lambda: (synth.batch_er_10_30(4096), None),
+    "query_molecule_n10-70_1x10000_k128": lambda: (synth.query_molecule_10_70(10000), None),
+    "stress_er_n100-500_p0.05-0.5_256pairs_k256": lambda: (synth.stress_er_100_500(256), None),
+    "serve_mix_db100000_q100000_k64:first2000": lambda: (synth.serve_mix(), 2000),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
+    ap.add_argument("--only", nargs="*")
+    args = ap.parse_args()
+    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    for name, make in WORKLOADS.items():
+        if args.only and name not in args.only:
+            continue
+        t0 = time.time()
+        w, limit = make()
+        pairs = w.pairs if limit is None else w.pairs[:limit]
+        dist, maps = run_oracle(w, pairs, args.threads)
+        entry = {"workload": w.name, "pairs": int(len(pairs)), "K": w.K, "costs": list(w.costs),
+                 "sha256": digest(dist.astype(np.int32), maps),
+                 "dist_sum": int(dist.sum()), "dist_head": [int(x) for x in dist[:16]],
+                 "oracle_seconds": round(time.time() - t0, 1), "threads": args.threads}
+        if len(pairs) <= 4096:
+            entry["dist"] = [int(x) for x in dist]
+        data[name] = entry
+        json.dump(data, open(OUT, "w"), indent=1)
+        print(name, entry["pairs"], entry["sha256"][:16], f"{entry['oracle_seconds']}s", flush=True)
+
+
+if __name__ == "__main__":
+    main()
