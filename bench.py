@@ -79,6 +79,120 @@ def cpu_oracle(graphs, pairs, costs, K, threads: int):
     return wall, dist, maps
 
 
+def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2000, seed: int = 7):
+    """Serving on the mix workload: saturated throughput (closed loop), then
+    Poisson arrivals at fractions of it; latency = completion - scheduled
+    arrival.  The same loop with one launch per query is the per-pair path."""
+    ndb = w.meta["ndb"]
+    nq = min(n_queries, len(w.pairs))
+    db = ged.Database(w.graphs.slice(0, ndb))
+    qgs = w.graphs.slice(ndb, ndb + nq)
+    recs, keep = ged.pack_queries(qgs)
+    targets = np.ascontiguousarray(w.pairs[:nq, 1])
+
+    def run(srv, idx, arrivals=None):
+        """Submit queries idx (at arrivals, monotonic ns, or as fast as possible)."""
+        n = len(idx)
+        t_sub = np.zeros(n, np.int64)
+        t_done = np.zeros(n, np.int64)
+        pos = {}
+        err = []
+
+        def producer():
+            try:
+                k = 0
+                while k < n:
+                    hi = n
+                    if arrivals is not None:
+                        now = time.monotonic_ns()
+                        hi = int(np.searchsorted(arrivals, now, side="right"))
+                        if hi <= k:
+                            time.sleep(max(0.0, min(2e-4, (arrivals[k] - now) * 1e-9)))
+                            continue
+                    hi = min(hi, k + 4096)
+                    tk = srv.submit_batch(recs[idx[k:hi]], targets[idx[k:hi]])
+                    for j, t in enumerate(tk):
+                        pos[int(t)] = k + j
+                    k += len(tk)
+                    if len(tk) == 0:
+                        time.sleep(1e-4)
+            except Exception as e:  # reported by the caller
+                err.append(e)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        got = 0
+        while got < n and not err:
+            r = srv.collect(max_count=8192, timeout_us=200_000)
+            if r is None:
+                continue
+            tk, d, times, _ = r
+            for j in range(len(tk)):
+                i = pos.get(int(tk[j]))
+                if i is None:          # collected before the producer recorded it
+                    while int(tk[j]) not in pos:
+                        time.sleep(1e-5)
+                    i = pos[int(tk[j])]
+                t_sub[i], t_done[i] = times[j]
+            got += len(tk)
+        th.join()
+        if err:
+            raise err[0]
+        return t_sub, t_done
+
+    def latency_stats(t_done, arrivals):
+        lat = (t_done - arrivals) / 1e6
+        lat = lat[len(lat) // 100:]          # first 1% is warm-up
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                "p999_ms": round(float(np.percentile(lat, 99.9)), 4), "mean_ms": round(float(lat.mean()), 4)}
+
+    out = {"config": {"workload": w.name, "database_graphs": ndb, "queries": nq, "K": w.K,
+                      "costs": list(w.costs)}}
+    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=3, max_batch=2048, max_inflight=8192)
+    warm = np.arange(min(2000, nq))
+    run(srv, warm)
+    idx = np.arange(nq)
+    ts, td = run(srv, idx)
+    qps_sat = nq / ((td.max() - ts.min()) / 1e9)
+    out["saturated_qps"] = round(qps_sat, 1)
+    log(f"serving: saturated {qps_sat:.0f} queries/s over {nq} queries")
+    rng = np.random.default_rng(seed)
+    out["open_loop"] = []
+    for f in fracs:
+        lam = f * qps_sat
+        gaps = rng.exponential(1.0 / lam, nq)
+        t0 = time.monotonic_ns() + 20_000_000
+        arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+        ts, td = run(srv, idx, arrivals)
+        achieved = nq / ((td.max() - arrivals[0]) / 1e9)
+        entry = {"load": f, "offered_qps": round(lam, 1), "achieved_qps": round(achieved, 1)}
+        entry.update(latency_stats(td, arrivals))
+        out["open_loop"].append(entry)
+        log(f"serving at {f:.2f} x saturated: {entry}")
+    out["server_stats"] = srv.stats()
+    srv.close()
+    # per-pair path: one launch per query, same loop
+    pp = ged.Server(db, w.K, w.costs, hbm_budget=4 << 30, streams=1, max_batch=1, max_inflight=1)
+    pidx = np.arange(min(perpair_queries, nq))
+    ts, td = run(pp, pidx)
+    qps_pp = len(pidx) / ((td.max() - ts.min()) / 1e9)
+    lam = fracs[0] * qps_sat
+    entry = {"saturated_qps": round(qps_pp, 1), "queries": int(len(pidx)), "offered_qps": round(lam, 1)}
+    if qps_pp < lam:
+        entry["saturated_at_offered_load"] = True
+    else:
+        gaps = rng.exponential(1.0 / lam, len(pidx))
+        t0 = time.monotonic_ns() + 20_000_000
+        arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
+        ts, td = run(pp, pidx, arrivals)
+        entry.update(latency_stats(td, arrivals))
+    out["perpair"] = entry
+    log(f"serving per-pair path: {entry}")
+    pp.close()
+    db.close()
+    return out
+
+
 def workload(name: str):
     from paper_2605_00830_amd import synth
     if name == "batch":
@@ -97,7 +211,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "pair", "query", "stress"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "pair", "query", "stress", "serve"])
+    ap.add_argument("--serve-queries", type=int, default=20000,
+                    help="queries of the serving measurement (the serving mix has 100,000)")
+    ap.add_argument("--serve-db", type=int, default=100000, help="database graphs of the serving measurement")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-perpair", action="store_true")
@@ -116,6 +234,19 @@ def main():
     from paper_2605_00830_amd import ged
 
     torch.cuda.set_device(0)
+    if args.workload == "serve":
+        from paper_2605_00830_amd import synth
+        t0 = time.perf_counter()
+        sw = synth.serve_mix(args.serve_db, args.serve_queries)
+        log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
+        res = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95))
+        head = res["open_loop"][1]
+        print(json.dumps({
+            "metric": METRIC, "value": res["saturated_qps"], "unit": "pairs/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": res["config"],
+            "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "serving": res}), flush=True)
+        return
     w, cpu_sample = workload(args.workload)
     P = len(w.pairs)
     log(f"workload {w.name}: {P} pairs, K={w.K}, costs={w.costs}")
@@ -206,6 +337,14 @@ def main():
         parity = {"pairs_checked": int(len(sample)), "bit_exact": ok}
         log(f"cpu oracle: {len(sample) / cw:.1f} pairs/s; GPU parity on sample: {ok}")
 
+    serving = None
+    if not args.no_serve and args.workload == "batch":
+        from paper_2605_00830_amd import synth
+        t0 = time.perf_counter()
+        sw = synth.serve_mix(args.serve_db, args.serve_queries)
+        log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
+        serving = serve_measure(ged, sw, args.serve_queries)
+
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -225,6 +364,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     plan.close()

@@ -232,6 +232,88 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
                              ged_costs costs, int32_t K, int32_t *d_dist, int32_t *d_map,
                              void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over a device-resident database.
+ *
+ * Clients submit queries -- a query graph (host memory, copied and packed
+ * with the database's edge-label coding) to be edited into database graph
+ * `target_id` -- and poll for results.  A worker thread owned by the server
+ * admits queued queries while device slots and the HBM budget allow, packs
+ * them into a batch (query graphs staged into a device arena) and launches
+ * the batch on one of `streams` HIP streams; a batch can start while earlier
+ * ones still run, so queries that arrive during a launch are admitted into
+ * the next one as slots and memory free up (continuous batching).  Each
+ * query's search state (its beam) lives on the device for the whole search;
+ * results are copied back once the batch's stream reaches its event.  The
+ * result of a query does not depend on the other queries of its batch.
+ * ---------------------------------------------------------------------- */
+typedef struct ged_server ged_server;
+
+typedef struct {
+    int32_t K;                /* beam width, 1..GED_MAX_K */
+    ged_costs costs;          /* edit costs of every query */
+    int64_t hbm_budget;       /* device bytes the server may hold (arenas, work
+                                 lists, outputs, workspaces); 0 = 2 GiB */
+    int32_t max_inflight;     /* queries admitted to the device at once; 0 = 4096 */
+    int32_t max_batch;        /* queries per launch; 0 = 1024 */
+    int32_t streams;          /* launches that may overlap, 1..8; 0 = 3 */
+    int32_t queue_capacity;   /* queued (not yet admitted) queries before
+                                 ged_server_submit returns GED_EBUSY; 0 = 1<<20 */
+} ged_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected_busy, launches;
+    int64_t queued, inflight, inflight_peak;
+    int64_t batch_peak;       /* largest batch launched */
+    int64_t device_bytes;     /* device memory held */
+} ged_server_stats;
+
+/* Errors: GED_EINVAL (bad config, costs, K); GED_ENOMEM when the budget
+ * cannot hold one batch of the configured size; GED_EDEVICE. */
+ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_server **out);
+
+/* Queue one query; *ticket identifies it.  GED_EINVAL for an invalid query
+ * graph (as for ged_db_create; also an edge label absent from the database)
+ * or target id, or costs that could overflow int32 on this pair;
+ * GED_EUNSUPPORTED for n > GED_MAX_VERTICES; GED_EBUSY when the queue is full
+ * (backpressure: retry later). */
+ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t target_id, uint64_t *ticket);
+
+/* Non-blocking: GED_OK writes the distance and the mapping (n1 entries,
+ * -1 = deleted; *n1 gets n1) and releases the ticket; GED_EBUSY if the query
+ * is not finished; GED_EINVAL for an unknown ticket or map_capacity < n1
+ * (the ticket is kept); a query whose launch failed reports GED_EDEVICE.
+ * times_ns (may be NULL) gets [submission, completion] on the monotonic
+ * clock (CLOCK_MONOTONIC, nanoseconds); completion is when the worker saw
+ * the batch's event. */
+ged_status ged_server_poll(ged_server *srv, uint64_t ticket, int32_t *dist, int32_t *map,
+                           int32_t map_capacity, int32_t *n1, int64_t *times_ns);
+/* Blocking form of ged_server_poll; GED_ETIMEOUT after timeout_us
+ * microseconds (< 0: wait without limit). */
+ged_status ged_server_wait(ged_server *srv, uint64_t ticket, int64_t timeout_us, int32_t *dist,
+                           int32_t *map, int32_t map_capacity, int32_t *n1, int64_t *times_ns);
+/* Submit queries[0..count) in order (query k against targets[k]) until one
+ * is refused; *accepted gets how many were queued (tickets[0..*accepted)).
+ * Returns GED_OK if all were queued, else the refusal's status (GED_EBUSY
+ * when the queue filled up). */
+ged_status ged_server_submit_batch(ged_server *srv, const ged_graph *queries, const int64_t *targets,
+                                   int64_t count, uint64_t *tickets, int64_t *accepted);
+/* Collect finished queries in completion order (each once), releasing
+ * their tickets: waits up to timeout_us microseconds (< 0: no limit) for
+ * at least one, then moves up to max_count of them out: tickets[k],
+ * dist[k] (-1 for a failed launch), times_ns[2k..2k+1] = submission and
+ * completion (monotonic clock, ns), and, if maps is not NULL, the mappings
+ * back to back in maps (stopping before one that would exceed
+ * maps_capacity).  *count gets the number collected; GED_ETIMEOUT when none
+ * finished in time.  A query taken with ged_server_poll/wait is not
+ * reported again here. */
+ged_status ged_server_collect(ged_server *srv, int64_t timeout_us, int64_t max_count, uint64_t *tickets,
+                              int32_t *dist, int64_t *times_ns, int32_t *maps, int64_t maps_capacity,
+                              int64_t *count);
+ged_status ged_server_stats_get(const ged_server *srv, ged_server_stats *out);
+/* Finishes every admitted query, cancels queued ones, frees everything. */
+ged_status ged_server_destroy(ged_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

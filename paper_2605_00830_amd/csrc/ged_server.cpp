@@ -1,0 +1,630 @@
+// ged_server.cpp -- the serving loop of the C ABI (include/ged.h).
+//
+// Client threads submit (query graph, target id) requests; submit packs the
+// query graph on the host with the database's edge-label coding.  One worker
+// thread per server runs the loop:
+//   1. completion: every stream whose batch event has fired hands its results
+//      (already copied to pinned host memory on that stream) to the waiting
+//      tickets and frees its slots and arena space;
+//   2. admission: while a stream is idle, queued requests move into a batch
+//      in arrival order as long as the in-flight slot limit and the stream's
+//      arena (its share of the HBM budget) have room;
+//   3. launch: the batch's query graphs and work lists are copied to the
+//      device, the work-queue counters cleared by a kernel, the size bins
+//      launched (wavefront kernel for small pairs, workgroup kernel for the
+//      rest), results copied back and an event recorded -- all on that
+//      stream, so batches on different streams overlap on the device.
+// A query's search runs entirely inside one kernel launch, so its result
+// does not depend on the other queries of its batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ged.h"
+#include "ged_host.h"
+#include "ged_internal.h"
+
+using gedh::fail;
+using gedh::ok;
+using gedk::GraphRec;
+using gedk::WorkItem;
+
+namespace {
+
+enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3, CANCELED = 4 };
+
+struct Request {
+    uint64_t ticket = 0;
+    int32_t n1 = 0;
+    int32_t target = 0;
+    GraphRec rec{};                 // adj / vlab offsets relative to this request's vectors
+    std::vector<uint32_t> adj;      // packed rows and label planes
+    std::vector<int32_t> vlab;
+    int state = QUEUED;
+    int32_t dist = -1;
+    std::vector<int32_t> map;
+    int64_t t_submit = 0, t_done = 0;   // monotonic clock, ns
+};
+
+int64_t now_ns() {
+    return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+using ReqPtr = std::shared_ptr<Request>;
+
+constexpr int kMaxBins = 6;         // wavefront bin + workgroup bins W = 1, 2, 4, 8, 16
+
+// Device and pinned-host buffers of one stream.
+struct Slab {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    // device
+    GraphRec *d_recs = nullptr;
+    uint32_t *d_adj = nullptr;
+    int32_t *d_vlab = nullptr;
+    WorkItem *d_work = nullptr;
+    int *d_queue = nullptr;
+    int32_t *d_dist = nullptr;
+    int32_t *d_map = nullptr;
+    void *d_ws = nullptr;
+    // pinned host staging
+    GraphRec *h_recs = nullptr;
+    uint32_t *h_adj = nullptr;
+    int32_t *h_vlab = nullptr;
+    WorkItem *h_work = nullptr;
+    int32_t *h_dist = nullptr;
+    int32_t *h_map = nullptr;
+    // the batch on the device
+    bool busy = false;
+    std::vector<ReqPtr> batch;
+    std::vector<int64_t> map_off;
+};
+
+int pow2_at_least(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+struct ged_server {
+    ged_db *db = nullptr;
+    ged_server_config cfg{};
+    gedk::Costs c{};
+    int PL = 0;
+    int cus = 0;
+    int64_t cap_words = 0, cap_vlab = 0, cap_map = 0;  // arena capacity per stream
+    size_t ws_bytes = 0;
+    int wave_per_cu = 0;
+    int block_per_cu[5] = {0, 0, 0, 0, 0};             // W = 1, 2, 4, 8, 16
+    int64_t device_bytes = 0;
+    std::vector<Slab> slabs;
+
+    std::mutex mu;
+    std::condition_variable cv_work;   // worker: new requests or stop
+    std::condition_variable cv_done;   // clients: results
+    std::deque<ReqPtr> queue;
+    std::unordered_map<uint64_t, ReqPtr> tickets;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::deque<uint64_t> done_order;   // finished tickets in completion order, for collect
+    std::thread worker;
+    int device = 0;
+
+    ged_server_stats stats{};
+};
+
+namespace {
+
+int w_index(int W) {
+    int k = 0;
+    while ((1 << k) < W) ++k;
+    return k;
+}
+
+gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2) {
+    gedk::BlockShape sh{};
+    sh.W = W;
+    sh.PL = s->PL;
+    sh.KS = (s->cfg.K + gedk::kBlockThreads - 1) / gedk::kBlockThreads * gedk::kBlockThreads;
+    sh.nmax1 = nmax1;
+    sh.nmax2 = nmax2;
+    return sh;
+}
+
+void free_slab(Slab &b) {
+    if (b.d_recs) (void)hipFree(b.d_recs);
+    if (b.d_adj) (void)hipFree(b.d_adj);
+    if (b.d_vlab) (void)hipFree(b.d_vlab);
+    if (b.d_work) (void)hipFree(b.d_work);
+    if (b.d_queue) (void)hipFree(b.d_queue);
+    if (b.d_dist) (void)hipFree(b.d_dist);
+    if (b.d_map) (void)hipFree(b.d_map);
+    if (b.d_ws) (void)hipFree(b.d_ws);
+    if (b.h_recs) (void)hipHostFree(b.h_recs);
+    if (b.h_adj) (void)hipHostFree(b.h_adj);
+    if (b.h_vlab) (void)hipHostFree(b.h_vlab);
+    if (b.h_work) (void)hipHostFree(b.h_work);
+    if (b.h_dist) (void)hipHostFree(b.h_dist);
+    if (b.h_map) (void)hipHostFree(b.h_map);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    b = Slab();
+}
+
+// Launch the slab's batch; on error the caller fails the batch.
+hipError_t launch_batch(ged_server *s, Slab &b) {
+    const int nq = (int)b.batch.size();
+    const int K = s->cfg.K;
+    const auto &dbg = s->db->h_graphs;
+    // stage query graphs and map offsets
+    int64_t aw = 0, vo = 0, mo = 0;
+    b.map_off.resize((size_t)nq);
+    for (int k = 0; k < nq; ++k) {
+        const Request &r = *b.batch[(size_t)k];
+        std::memcpy(b.h_adj + aw, r.adj.data(), sizeof(uint32_t) * r.adj.size());
+        std::memcpy(b.h_vlab + vo, r.vlab.data(), sizeof(int32_t) * r.vlab.size());
+        GraphRec rec = r.rec;
+        rec.adj = aw;
+        rec.vlab = vo;
+        b.h_recs[k] = rec;
+        b.map_off[(size_t)k] = mo;
+        aw += (int64_t)r.adj.size();
+        vo += (int64_t)r.vlab.size();
+        mo += r.n1;
+    }
+    // work items by bin: 0 = wavefront kernel, 1 + log2(W) = workgroup kernel
+    std::vector<WorkItem> bins[kMaxBins];
+    int nmax1[kMaxBins] = {0}, nmax2[kMaxBins] = {0};
+    for (int k = 0; k < nq; ++k) {
+        const Request &r = *b.batch[(size_t)k];
+        const GraphRec &g2 = dbg[(size_t)r.target];
+        const bool wave = r.n1 <= gedk::kWaveMaxN && g2.n <= gedk::kWaveMaxN && K <= gedk::kWaveMaxK;
+        const int bin = wave ? 0 : 1 + w_index(pow2_at_least(std::max(1, g2.w)));
+        WorkItem wi;
+        wi.src = k;
+        wi.dst = r.target;
+        wi.out = k;
+        wi.pad = 0;
+        wi.map_off = b.map_off[(size_t)k];
+        bins[bin].push_back(wi);
+        nmax1[bin] = std::max(nmax1[bin], r.n1);
+        nmax2[bin] = std::max(nmax2[bin], g2.n);
+    }
+    int64_t wo = 0;
+    int start[kMaxBins];
+    for (int bin = 0; bin < kMaxBins; ++bin) {
+        std::stable_sort(bins[bin].begin(), bins[bin].end(), [&](const WorkItem &x, const WorkItem &y) {
+            return (int64_t)b.h_recs[x.src].n * (dbg[(size_t)x.dst].n + 1) >
+                   (int64_t)b.h_recs[y.src].n * (dbg[(size_t)y.dst].n + 1);
+        });
+        start[bin] = (int)wo;
+        for (const WorkItem &wi : bins[bin]) b.h_work[wo++] = wi;
+    }
+    hipError_t e = hipMemcpyAsync(b.d_recs, b.h_recs, sizeof(GraphRec) * (size_t)nq, hipMemcpyHostToDevice, b.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.d_adj, b.h_adj, sizeof(uint32_t) * (size_t)std::max<int64_t>(aw, 1),
+                                            hipMemcpyHostToDevice, b.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.d_vlab, b.h_vlab, sizeof(int32_t) * (size_t)std::max<int64_t>(vo, 1),
+                                            hipMemcpyHostToDevice, b.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.d_work, b.h_work, sizeof(WorkItem) * (size_t)nq, hipMemcpyHostToDevice,
+                                            b.stream);
+    if (e == hipSuccess) e = gedk::launch_fill_zero(b.d_queue, kMaxBins, b.stream);
+    if (e != hipSuccess) return e;
+    const gedk::DbView src{b.d_recs, b.d_adj, b.d_vlab, s->db->planes};
+    const gedk::DbView dst{s->db->d_graphs, s->db->d_adj, s->db->d_vlab, s->db->planes};
+    const gedk::Outputs out{b.d_dist, b.d_map, nullptr};
+    for (int bin = 0; bin < kMaxBins && e == hipSuccess; ++bin) {
+        const int cnt = (int)bins[bin].size();
+        if (cnt == 0) continue;
+        if (bin == 0) {
+            const int grid = std::min(cnt, s->wave_per_cu * s->cus);
+            e = gedk::launch_wave(s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, out, grid,
+                                  b.stream);
+        } else {
+            const int W = 1 << (bin - 1);
+            const gedk::BlockShape sh = shape_for(s, W, nmax1[bin], nmax2[bin]);
+            const size_t stride = gedk::block_workspace_bytes(sh);
+            const int fit = (int)std::min<size_t>(s->ws_bytes / stride, (size_t)std::numeric_limits<int>::max());
+            const int grid = std::min({cnt, s->block_per_cu[bin - 1] * s->cus, fit});
+            if (grid <= 0) return hipErrorOutOfMemory;
+            e = gedk::launch_block(sh, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, b.d_ws,
+                                   stride, out, grid, b.stream);
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost,
+                                            b.stream);
+    if (e == hipSuccess && mo > 0)
+        e = hipMemcpyAsync(b.h_map, b.d_map, sizeof(int32_t) * (size_t)mo, hipMemcpyDeviceToHost, b.stream);
+    if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+    return e;
+}
+
+// Called with s->mu held: results of a finished (or failed) batch.
+void finish_batch(ged_server *s, Slab &b, bool failed) {
+    const int64_t t = now_ns();
+    for (size_t k = 0; k < b.batch.size(); ++k) {
+        Request &r = *b.batch[k];
+        r.t_done = t;
+        s->done_order.push_back(r.ticket);
+        if (failed) {
+            r.state = FAILED;
+        } else {
+            r.dist = b.h_dist[k];
+            r.map.assign(b.h_map + b.map_off[k], b.h_map + b.map_off[k] + r.n1);
+            r.state = DONE;
+            r.adj.clear();
+            r.adj.shrink_to_fit();
+            r.vlab.clear();
+            r.vlab.shrink_to_fit();
+        }
+    }
+    // tickets taken with poll/wait stay in done_order until collect skips
+    // them; keep the list within a constant factor of the live tickets
+    if (s->done_order.size() > 2 * s->tickets.size() + 4096) {
+        std::deque<uint64_t> live;
+        for (uint64_t id : s->done_order)
+            if (s->tickets.count(id)) live.push_back(id);
+        s->done_order.swap(live);
+    }
+    s->stats.completed += (int64_t)b.batch.size();
+    s->stats.inflight -= (int64_t)b.batch.size();
+    b.batch.clear();
+    b.busy = false;
+}
+
+void worker_loop(ged_server *s) {
+    (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // 1. completions
+        bool any_busy = false;
+        for (Slab &b : s->slabs) {
+            if (!b.busy) continue;
+            const hipError_t q = hipEventQuery(b.done);
+            if (q == hipSuccess) {
+                finish_batch(s, b, false);
+                s->cv_done.notify_all();
+            } else if (q != hipErrorNotReady) {
+                (void)hipStreamSynchronize(b.stream);
+                finish_batch(s, b, true);
+                s->cv_done.notify_all();
+            } else {
+                any_busy = true;
+            }
+        }
+        if (s->stop) {
+            for (ReqPtr &r : s->queue) r->state = CANCELED;
+            s->stats.queued = 0;
+            s->queue.clear();
+            s->cv_done.notify_all();
+            if (!any_busy) break;
+        }
+        // 2. admission and launch
+        bool launched = false;
+        if (!s->stop && !s->queue.empty()) {
+            for (Slab &b : s->slabs) {
+                if (b.busy || s->queue.empty()) continue;
+                if (s->stats.inflight >= s->cfg.max_inflight) break;
+                int64_t aw = 0, vo = 0;
+                while (!s->queue.empty() && (int)b.batch.size() < s->cfg.max_batch &&
+                       s->stats.inflight + (int64_t)b.batch.size() < s->cfg.max_inflight) {
+                    const Request &r = *s->queue.front();
+                    if (aw + (int64_t)r.adj.size() > s->cap_words || vo + r.n1 > s->cap_vlab) break;
+                    aw += (int64_t)r.adj.size();
+                    vo += r.n1;
+                    s->queue.front()->state = INFLIGHT;
+                    b.batch.push_back(s->queue.front());
+                    s->queue.pop_front();
+                }
+                if (b.batch.empty()) break;
+                b.busy = true;
+                s->stats.queued = (int64_t)s->queue.size();
+                s->stats.inflight += (int64_t)b.batch.size();
+                s->stats.inflight_peak = std::max(s->stats.inflight_peak, s->stats.inflight);
+                s->stats.batch_peak = std::max(s->stats.batch_peak, (int64_t)b.batch.size());
+                s->stats.launches += 1;
+                lk.unlock();
+                const hipError_t e = launch_batch(s, b);
+                lk.lock();
+                if (e != hipSuccess) {
+                    (void)hipStreamSynchronize(b.stream);
+                    finish_batch(s, b, true);
+                    s->cv_done.notify_all();
+                }
+                launched = true;
+                any_busy = true;
+            }
+        }
+        if (launched) continue;
+        // 3. wait for work or poll the device
+        if (any_busy) {
+            s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        } else {
+            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_server **out) {
+    if (!out) return fail(GED_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!db || !config) return fail(GED_EINVAL, "NULL argument");
+    ged_server_config cfg = *config;
+    if (cfg.K < 1) return fail(GED_EINVAL, "K must be >= 1 (got %d)", cfg.K);
+    if (cfg.K > GED_MAX_K) return fail(GED_EUNSUPPORTED, "K = %d exceeds %d", cfg.K, GED_MAX_K);
+    ged_status st = gedh::check_costs(cfg.costs);
+    if (st != GED_OK) return st;
+    if (cfg.hbm_budget < 0 || cfg.max_inflight < 0 || cfg.max_batch < 0 || cfg.streams < 0 || cfg.queue_capacity < 0)
+        return fail(GED_EINVAL, "negative server limit");
+    if (cfg.hbm_budget == 0) cfg.hbm_budget = (int64_t)2 << 30;
+    if (cfg.max_inflight == 0) cfg.max_inflight = 4096;
+    if (cfg.max_batch == 0) cfg.max_batch = 1024;
+    if (cfg.streams == 0) cfg.streams = 3;
+    if (cfg.queue_capacity == 0) cfg.queue_capacity = 1 << 20;
+    if (cfg.streams > 8) return fail(GED_EINVAL, "streams must be 1..8");
+    st = gedh::check_device(db);
+    if (st != GED_OK) return st;
+
+    ged_server *s = new (std::nothrow) ged_server;
+    if (!s) return fail(GED_ENOMEM, "host allocation failed");
+    s->db = db;
+    s->cfg = cfg;
+    s->c = gedk::Costs{cfg.costs.vsub, cfg.costs.vdel, cfg.costs.vins, cfg.costs.esub, cfg.costs.edel, cfg.costs.eins};
+    s->PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
+    s->device = db->device;
+    hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
+    if (e == hipSuccess && cfg.K <= gedk::kWaveMaxK) e = gedk::wave_max_resident(s->PL, &s->wave_per_cu);
+    // workgroup-kernel workspace: the largest over W of stride x resident grid,
+    // for targets of up to 32*W vertices
+    // per-stream budget: the workspace takes at most half (fewer resident
+    // workgroups when it is smaller), the arena gets what is left
+    const int64_t per_stream = cfg.hbm_budget / cfg.streams;
+    size_t ws = 0, one_block = 0;
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        const int W = 1 << k;
+        const gedk::BlockShape sh = shape_for(s, W, GED_MAX_VERTICES, std::min(32 * W, GED_MAX_VERTICES));
+        e = gedk::block_max_resident(sh, &s->block_per_cu[k]);
+        const int64_t grid = std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->block_per_cu[k] * s->cus);
+        one_block = std::max(one_block, gedk::block_workspace_bytes(sh));
+        ws = std::max(ws, gedk::block_workspace_bytes(sh) * (size_t)grid);
+    }
+    if (e != hipSuccess) {
+        delete s;
+        return fail(GED_EDEVICE, "device query failed: %s", hipGetErrorString(e));
+    }
+    ws = std::min<size_t>(ws, (size_t)std::max<int64_t>(per_stream / 2, 0));
+    if (ws < one_block) {
+        delete s;
+        return fail(GED_ENOMEM, "hbm_budget %lld is too small: a stream needs %zu bytes for one workgroup's "
+                                "workspace", (long long)cfg.hbm_budget, one_block);
+    }
+    s->ws_bytes = ws;
+    const int64_t fixed = (int64_t)ws + (int64_t)cfg.max_batch * (int64_t)(sizeof(GraphRec) + sizeof(WorkItem) + 4) +
+                          kMaxBins * 4;
+    const int64_t rest = per_stream - fixed;
+    // the largest query: 512 vertices, 16 words per row, rows plus planes
+    const int64_t big = gedh::packed_words(GED_MAX_VERTICES, db->planes);
+    s->cap_words = rest / 4 * 8 / 10;
+    s->cap_vlab = rest / 4 / 20;
+    s->cap_map = s->cap_vlab;
+    if (rest <= 0 || s->cap_words < big || s->cap_vlab < GED_MAX_VERTICES) {
+        delete s;
+        return fail(GED_ENOMEM, "hbm_budget %lld is too small: each of %d streams needs %lld bytes of workspace "
+                                "plus room for one 512-vertex query", (long long)cfg.hbm_budget, cfg.streams,
+                    (long long)fixed);
+    }
+    s->slabs.resize((size_t)cfg.streams);
+    for (Slab &b : s->slabs) {
+        e = hipStreamCreate(&b.stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
+        const size_t nb = (size_t)cfg.max_batch;
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_recs, sizeof(GraphRec) * nb);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_adj, sizeof(uint32_t) * (size_t)s->cap_words);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_vlab, sizeof(int32_t) * (size_t)s->cap_vlab);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * nb);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * kMaxBins);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_dist, sizeof(int32_t) * nb);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_map, sizeof(int32_t) * (size_t)s->cap_map);
+        if (e == hipSuccess && ws > 0) e = hipMalloc(&b.d_ws, ws);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_recs, sizeof(GraphRec) * nb, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_adj, sizeof(uint32_t) * (size_t)s->cap_words, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_vlab, sizeof(int32_t) * (size_t)s->cap_vlab, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_work, sizeof(WorkItem) * nb, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_dist, sizeof(int32_t) * nb, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_map, sizeof(int32_t) * (size_t)s->cap_map, hipHostMallocDefault);
+        if (e != hipSuccess) break;
+        s->device_bytes += (int64_t)(sizeof(GraphRec) * nb + sizeof(uint32_t) * (size_t)s->cap_words +
+                                     sizeof(int32_t) * (size_t)s->cap_vlab + sizeof(WorkItem) * nb + sizeof(int) * kMaxBins +
+                                     sizeof(int32_t) * nb + sizeof(int32_t) * (size_t)s->cap_map + ws);
+    }
+    if (e != hipSuccess) {
+        for (Slab &b : s->slabs) free_slab(b);
+        delete s;
+        return fail(GED_ENOMEM, "server allocation failed: %s", hipGetErrorString(e));
+    }
+    s->stats.device_bytes = s->device_bytes;
+    s->worker = std::thread(worker_loop, s);
+    *out = s;
+    return ok();
+}
+
+ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t target_id, uint64_t *ticket) {
+    if (!srv || !query || !ticket) return fail(GED_EINVAL, "NULL argument");
+    if (target_id < 0 || target_id >= srv->db->count) return fail(GED_EINVAL, "target id %lld out of range", (long long)target_id);
+    ged_status st = gedh::check_graph_shape(*query, 0);
+    if (st != GED_OK) return st;
+    auto r = std::make_shared<Request>();
+    r->n1 = query->n;
+    r->target = (int32_t)target_id;
+    st = gedh::pack_graph(*query, 0, srv->db->elabels, srv->db->planes, r->adj, r->vlab, r->rec);
+    if (st != GED_OK) return st;
+    const GraphRec &g2 = srv->db->h_graphs[(size_t)target_id];
+    const ged_costs &c = srv->cfg.costs;
+    const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
+    const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
+    if (vmax * ((int64_t)query->n + g2.n) + emax * ((int64_t)query->m + g2.m) > (int64_t)std::numeric_limits<int32_t>::max() - 1)
+        return fail(GED_EINVAL, "costs may overflow int32 on this pair");
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) return fail(GED_ECANCELED, "server is shutting down");
+        if ((int64_t)srv->queue.size() >= srv->cfg.queue_capacity) {
+            srv->stats.rejected_busy += 1;
+            return fail(GED_EBUSY, "queue full (%d queued)", srv->cfg.queue_capacity);
+        }
+        r->ticket = srv->next_ticket++;
+        r->t_submit = now_ns();
+        srv->tickets[r->ticket] = r;
+        srv->queue.push_back(r);
+        srv->stats.submitted += 1;
+        srv->stats.queued = (int64_t)srv->queue.size();
+        *ticket = r->ticket;
+    }
+    srv->cv_work.notify_one();
+    return ok();
+}
+
+static ged_status take_result(ged_server *srv, std::unordered_map<uint64_t, ReqPtr>::iterator it, int32_t *dist,
+                              int32_t *map, int32_t map_capacity, int32_t *n1, int64_t *times_ns) {
+    Request &r = *it->second;
+    if (times_ns) {
+        times_ns[0] = r.t_submit;
+        times_ns[1] = r.t_done;
+    }
+    if (r.state == FAILED) {
+        srv->tickets.erase(it);
+        return fail(GED_EDEVICE, "the query's launch failed");
+    }
+    if (r.state == CANCELED) {
+        srv->tickets.erase(it);
+        return fail(GED_ECANCELED, "the server was destroyed before the query ran");
+    }
+    if (r.state != DONE) return GED_EBUSY;
+    if (map_capacity < r.n1 || (r.n1 > 0 && !map)) return fail(GED_EINVAL, "map capacity %d < n1 = %d", map_capacity, r.n1);
+    if (dist) *dist = r.dist;
+    if (n1) *n1 = r.n1;
+    if (r.n1 > 0) std::memcpy(map, r.map.data(), sizeof(int32_t) * (size_t)r.n1);
+    srv->tickets.erase(it);
+    return ok();
+}
+
+ged_status ged_server_poll(ged_server *srv, uint64_t ticket, int32_t *dist, int32_t *map, int32_t map_capacity,
+                           int32_t *n1, int64_t *times_ns) {
+    if (!srv) return fail(GED_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end()) return fail(GED_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    return take_result(srv, it, dist, map, map_capacity, n1, times_ns);
+}
+
+ged_status ged_server_wait(ged_server *srv, uint64_t ticket, int64_t timeout_us, int32_t *dist, int32_t *map,
+                           int32_t map_capacity, int32_t *n1, int64_t *times_ns) {
+    if (!srv) return fail(GED_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end()) return fail(GED_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    ReqPtr r = it->second;
+    auto ready = [&] { return r->state != QUEUED && r->state != INFLIGHT; };
+    if (timeout_us < 0) {
+        srv->cv_done.wait(lk, ready);
+    } else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+        return fail(GED_ETIMEOUT, "query not finished after %lld us", (long long)timeout_us);
+    }
+    it = srv->tickets.find(ticket);
+    if (it == srv->tickets.end()) return fail(GED_EINVAL, "ticket %llu was taken by another caller", (unsigned long long)ticket);
+    return take_result(srv, it, dist, map, map_capacity, n1, times_ns);
+}
+
+ged_status ged_server_submit_batch(ged_server *srv, const ged_graph *queries, const int64_t *targets,
+                                   int64_t count, uint64_t *tickets, int64_t *accepted) {
+    if (!srv || !accepted || (count > 0 && (!queries || !targets || !tickets))) return fail(GED_EINVAL, "NULL argument");
+    *accepted = 0;
+    for (int64_t k = 0; k < count; ++k) {
+        const ged_status st = ged_server_submit(srv, &queries[k], targets[k], &tickets[k]);
+        if (st != GED_OK) return st;
+        *accepted = k + 1;
+    }
+    return ok();
+}
+
+ged_status ged_server_collect(ged_server *srv, int64_t timeout_us, int64_t max_count, uint64_t *tickets,
+                              int32_t *dist, int64_t *times_ns, int32_t *maps, int64_t maps_capacity,
+                              int64_t *count) {
+    if (!srv || !tickets || !dist || !times_ns || !count || max_count < 1) return fail(GED_EINVAL, "bad argument");
+    *count = 0;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto ready = [&] {
+        while (!srv->done_order.empty() && !srv->tickets.count(srv->done_order.front())) srv->done_order.pop_front();
+        return !srv->done_order.empty();
+    };
+    if (timeout_us < 0) {
+        srv->cv_done.wait(lk, ready);
+    } else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready)) {
+        return fail(GED_ETIMEOUT, "no query finished within %lld us", (long long)timeout_us);
+    }
+    int64_t n = 0, mo = 0;
+    while (n < max_count && !srv->done_order.empty()) {
+        const uint64_t t = srv->done_order.front();
+        auto it = srv->tickets.find(t);
+        if (it == srv->tickets.end()) {   // already taken with poll/wait
+            srv->done_order.pop_front();
+            continue;
+        }
+        Request &r = *it->second;
+        if (maps && mo + r.n1 > maps_capacity) break;
+        srv->done_order.pop_front();
+        tickets[n] = t;
+        dist[n] = r.state == DONE ? r.dist : -1;
+        times_ns[2 * n] = r.t_submit;
+        times_ns[2 * n + 1] = r.t_done;
+        if (maps && r.state == DONE && r.n1 > 0) std::memcpy(maps + mo, r.map.data(), sizeof(int32_t) * (size_t)r.n1);
+        if (maps) mo += r.n1;
+        srv->tickets.erase(it);
+        ++n;
+    }
+    *count = n;
+    return ok();
+}
+
+ged_status ged_server_stats_get(const ged_server *srv, ged_server_stats *out) {
+    if (!srv || !out) return fail(GED_EINVAL, "NULL argument");
+    ged_server *s = const_cast<ged_server *>(srv);
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return ok();
+}
+
+ged_status ged_server_destroy(ged_server *srv) {
+    if (!srv) return ok();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    for (Slab &b : srv->slabs) {
+        if (b.stream) (void)hipStreamSynchronize(b.stream);
+        free_slab(b);
+    }
+    delete srv;
+    return ok();
+}
+
+}  // extern "C"

@@ -41,6 +41,22 @@ class Costs(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int32) for f in ("vsub", "vdel", "vins", "esub", "edel", "eins")]
 
 
+class GraphStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("vlabel", ctypes.c_void_p),
+                ("eu", ctypes.c_void_p), ("ev", ctypes.c_void_p), ("elabel", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("costs", Costs), ("hbm_budget", ctypes.c_int64),
+                ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("submitted", "completed", "rejected_busy", "launches", "queued",
+                                              "inflight", "inflight_peak", "batch_peak", "device_bytes")]
+
+
 # Layout of ged_graph: int32 n, m; then four pointers (x86-64: 40 bytes).
 GRAPH_DTYPE = np.dtype([("n", "<i4"), ("m", "<i4"), ("vlabel", "<u8"), ("eu", "<u8"),
                         ("ev", "<u8"), ("elabel", "<u8")])
@@ -55,6 +71,8 @@ EXPORTS = (
     "ged_plan_set_timing", "ged_plan_kernel_ms", "ged_plan_kernel_launches",
     "ged_plan_create_ex", "ged_plan_bin_count", "ged_plan_bin_info",
     "ged_plan_capture", "ged_plan_replay", "ged_plan_tune",
+    "ged_server_create", "ged_server_submit", "ged_server_poll", "ged_server_wait",
+    "ged_server_stats_get", "ged_server_destroy", "ged_server_submit_batch", "ged_server_collect",
 )
 
 
@@ -93,6 +111,14 @@ def load(path: str = LIB_PATH):
         "ged_plan_capture": ([P, Costs, P, P, P, P], i32),
         "ged_plan_replay": ([P, P], i32),
         "ged_plan_tune": ([P, Costs, P, P, P, ctypes.c_char_p, P], i32),
+        "ged_server_create": ([P, P, P], i32),
+        "ged_server_submit": ([P, P, i64, P], i32),
+        "ged_server_poll": ([P, ctypes.c_uint64, P, P, i32, P, P], i32),
+        "ged_server_wait": ([P, ctypes.c_uint64, i64, P, P, i32, P, P], i32),
+        "ged_server_submit_batch": ([P, P, P, i64, P, P], i32),
+        "ged_server_collect": ([P, i64, i64, P, P, P, P, i64, P], i32),
+        "ged_server_stats_get": ([P, P], i32),
+        "ged_server_destroy": ([P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -309,3 +335,123 @@ def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: 
                       None if cand is None else cand[:n].cpu().numpy())
     finally:
         plan.close()
+
+
+def _graph_struct(g, keep: list) -> GraphStruct:
+    arrs = []
+    for a in (g.vlabel, g.eu, g.ev, getattr(g, "elabel", None)):
+        arrs.append(None if a is None else np.ascontiguousarray(a, dtype=np.int32))
+    keep.extend(arrs)
+    ptr = [None if a is None or a.size == 0 else a.ctypes.data for a in arrs]
+    return GraphStruct(int(g.n), int(arrs[1].shape[0]), ptr[0], ptr[1], ptr[2], ptr[3])
+
+
+class Server:
+    """The serving loop (ged_server_*): submit (query graph, target id), poll or wait."""
+
+    def __init__(self, db: Database, K: int, costs, hbm_budget: int = 0, max_inflight: int = 0,
+                 max_batch: int = 0, streams: int = 0, queue_capacity: int = 0):
+        lib = load()
+        self.db = db
+        cfg = ServerConfig(int(K), _costs(costs), int(hbm_budget), int(max_inflight), int(max_batch),
+                           int(streams), int(queue_capacity))
+        handle = ctypes.c_void_p()
+        _check(lib.ged_server_create(db.handle, ctypes.byref(cfg), ctypes.byref(handle)))
+        self._h = handle
+        self._map = np.zeros(MAX_VERTICES, dtype=np.int32)
+
+    def submit(self, query, target_id: int) -> int:
+        """Queue one query; raises GedError (status GED_EBUSY when the queue is full)."""
+        keep: list = []
+        gs = _graph_struct(query, keep)
+        t = ctypes.c_uint64()
+        _check(load().ged_server_submit(self._h, ctypes.byref(gs), int(target_id), ctypes.byref(t)))
+        return int(t.value)
+
+    def _result(self, fn, *args):
+        d, n1 = ctypes.c_int32(), ctypes.c_int32()
+        times = (ctypes.c_int64 * 2)()
+        st = fn(self._h, *args, ctypes.byref(d), self._map.ctypes.data, MAX_VERTICES, ctypes.byref(n1), times)
+        self.last_times_ns = (int(times[0]), int(times[1]))
+        return st, int(d.value), self._map[: n1.value].copy()
+
+    def poll(self, ticket: int):
+        """(dist, mapping) when finished, None while it runs; the submission and
+        completion times (monotonic ns) are left in self.last_times_ns."""
+        st, d, m = self._result(load().ged_server_poll, ctypes.c_uint64(ticket))
+        if st == GED_EBUSY:
+            return None
+        _check(st)
+        return d, m
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        st, d, m = self._result(load().ged_server_wait, ctypes.c_uint64(ticket), int(timeout_us))
+        _check(st)
+        return d, m
+
+    def submit_batch(self, recs: np.ndarray, targets: np.ndarray) -> np.ndarray:
+        """Submit ged_graph records (GRAPH_DTYPE array, see pack_queries) in order; returns
+        the tickets of those queued (fewer than given when the queue filled up)."""
+        recs = np.ascontiguousarray(recs)
+        targets = np.ascontiguousarray(targets, dtype=np.int64)
+        tickets = np.zeros(max(len(recs), 1), dtype=np.uint64)
+        acc = ctypes.c_int64()
+        st = load().ged_server_submit_batch(self._h, recs.ctypes.data, targets.ctypes.data, len(recs),
+                                            tickets.ctypes.data, ctypes.byref(acc))
+        if st not in (GED_OK, GED_EBUSY):
+            _check(st)
+        return tickets[: acc.value]
+
+    def collect(self, max_count: int = 4096, timeout_us: int = -1, with_maps: bool = False):
+        """(tickets, dist, times_ns [k,2], maps or None) of finished queries, or None on timeout."""
+        lib = load()
+        tickets = np.zeros(max_count, np.uint64)
+        dist = np.zeros(max_count, np.int32)
+        times = np.zeros((max_count, 2), np.int64)
+        maps = np.zeros(max_count * 64, np.int32) if with_maps else None
+        cnt = ctypes.c_int64()
+        st = lib.ged_server_collect(self._h, int(timeout_us), int(max_count), tickets.ctypes.data,
+                                    dist.ctypes.data, times.ctypes.data,
+                                    None if maps is None else maps.ctypes.data,
+                                    0 if maps is None else maps.shape[0], ctypes.byref(cnt))
+        if st == GED_ETIMEOUT:
+            return None
+        _check(st)
+        n = int(cnt.value)
+        return tickets[:n], dist[:n], times[:n], maps
+
+    def stats(self) -> dict:
+        out = ServerStats()
+        _check(load().ged_server_stats_get(self._h, ctypes.byref(out)))
+        return {f: int(getattr(out, f)) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ged_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_queries(graphs) -> Tuple[np.ndarray, list]:
+    """ged_graph records (GRAPH_DTYPE) for a GraphSet's graphs; returns (records, arrays to keep alive)."""
+    vl = np.ascontiguousarray(graphs.vlabel, dtype=np.int32)
+    eu = np.ascontiguousarray(graphs.eu, dtype=np.int32)
+    ev = np.ascontiguousarray(graphs.ev, dtype=np.int32)
+    el = None if graphs.elabel is None else np.ascontiguousarray(graphs.elabel, dtype=np.int32)
+    count = len(graphs)
+    recs = np.zeros(count, dtype=GRAPH_DTYPE)
+    recs["n"] = graphs.n
+    recs["m"] = graphs.m
+    voff = np.asarray(graphs.voff, dtype=np.uint64)[:count]
+    eoff = np.asarray(graphs.eoff, dtype=np.uint64)[:count]
+    recs["vlabel"] = np.uint64(vl.ctypes.data) + voff * np.uint64(4)
+    recs["eu"] = np.uint64(eu.ctypes.data) + eoff * np.uint64(4)
+    recs["ev"] = np.uint64(ev.ctypes.data) + eoff * np.uint64(4)
+    if el is not None:
+        recs["elabel"] = np.uint64(el.ctypes.data) + eoff * np.uint64(4)
+    return recs, [vl, eu, ev, el]

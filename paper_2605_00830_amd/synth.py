@@ -96,6 +96,15 @@ class GraphSet:
     def __len__(self) -> int:
         return int(self.n.shape[0])
 
+    def slice(self, lo: int, hi: int) -> "GraphSet":
+        """Graphs lo..hi-1 as a GraphSet of their own (arrays are copied)."""
+        a, b = int(self.voff[lo]), int(self.voff[hi])
+        c, d = int(self.eoff[lo]), int(self.eoff[hi])
+        el = None if self.elabel is None else self.elabel[c:d].copy()
+        return GraphSet(self.n[lo:hi].copy(), self.m[lo:hi].copy(), self.voff[lo:hi + 1] - a,
+                        self.eoff[lo:hi + 1] - c, self.vlabel[a:b].copy(), self.eu[c:d].copy(),
+                        self.ev[c:d].copy(), el)
+
     def graph(self, i: int) -> Graph:
         a, b = int(self.voff[i]), int(self.voff[i + 1])
         c, d = int(self.eoff[i]), int(self.eoff[i + 1])
@@ -186,20 +195,25 @@ def molecule_graph(seed: int, index: int, n_lo: int = 10, n_hi: int = 70,
     """
     n = n_lo + int(_uint_below(uniforms(seed, index, 0, 1), n_hi - n_lo + 1)[0])
     seq = _uint_below(uniforms(seed, index, 1, n - 2), n)
-    edges = set(_prufer_tree(seq, n))
+    tree = _prufer_tree(seq, n)
+    adj = np.zeros((n, n), dtype=bool)
+    for x, y in tree:
+        adj[x, y] = True
     k = int(np.floor(extra_frac * (n - 1) + 0.5))
     if k > 0:
         a, b = np.triu_indices(n, 1)
-        cand = [(int(x), int(y)) for x, y in zip(a, b) if (int(x), int(y)) not in edges]
+        free = ~adj[a, b]
+        ca, cb = a[free], b[free]          # the non-edges in row-major order
         draws = uniforms(seed, index, 3, k)
-        # partial Fisher-Yates over the non-edge list (in row-major order)
+        # partial Fisher-Yates over the non-edge list
         for t in range(k):
-            j = t + int(_uint_below(draws[t:t + 1], len(cand) - t)[0])
-            cand[t], cand[j] = cand[j], cand[t]
-            edges.add(cand[t])
-    el = sorted(edges)
-    eu = np.array([e[0] for e in el], dtype=np.int32)
-    ev = np.array([e[1] for e in el], dtype=np.int32)
+            j = t + int(_uint_below(draws[t:t + 1], len(ca) - t)[0])
+            ca[t], ca[j] = ca[j], ca[t]
+            cb[t], cb[j] = cb[j], cb[t]
+            adj[ca[t], cb[t]] = True
+    eu, ev = np.nonzero(np.triu(adj, 1))
+    eu = eu.astype(np.int32)
+    ev = ev.astype(np.int32)
     cum = np.cumsum(MOLECULE_VLABEL_P)
     cum[-1] = 1.0
     vl = np.searchsorted(cum, uniforms(seed, index, 4, n), side="right").astype(np.int32)

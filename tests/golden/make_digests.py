@@ -89,7 +89,7 @@ def main():
                  "sha256": digest(dist.astype(np.int32), maps),
                  "dist_sum": int(dist.sum()), "dist_head": [int(x) for x in dist[:16]],
                  "oracle_seconds": round(time.time() - t0, 1), "threads": args.threads}
-        if len(pairs) <= 4096:
+        if len(pairs) <= 10000:
             entry["dist"] = [int(x) for x in dist]
         data[name] = entry
         json.dump(data, open(OUT, "w"), indent=1)
