@@ -148,7 +148,7 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
 
     out = {"config": {"workload": w.name, "database_graphs": ndb, "queries": nq, "K": w.K,
                       "costs": list(w.costs)}}
-    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=3, max_batch=2048, max_inflight=8192)
+    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=1, max_batch=2048, max_inflight=8192)
     warm = np.arange(min(2000, nq))
     run(srv, warm)
     idx = np.arange(nq)

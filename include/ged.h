@@ -237,12 +237,16 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
  *
  * Clients submit queries -- a query graph (host memory, copied and packed
  * with the database's edge-label coding) to be edited into database graph
- * `target_id` -- and poll for results.  A worker thread owned by the server
- * admits queued queries while device slots and the HBM budget allow, packs
- * them into a batch (query graphs staged into a device arena) and launches
- * the batch on one of `streams` HIP streams; a batch can start while earlier
- * ones still run, so queries that arrive during a launch are admitted into
- * the next one as slots and memory free up (continuous batching).  Each
+ * `target_id` -- and poll for results.  Queries are sorted at submission
+ * into three size classes with queues and streams of their own: small
+ * (n1, n2 <= 32 and K <= 64: the wavefront kernel), medium (n1, n2 <= 128)
+ * and large, so a small query never waits for a large one's batch.  A
+ * worker thread owned by the server admits queued queries while device
+ * slots and the HBM budget allow, packs them into a batch (query graphs
+ * staged into a device arena) and launches the batch on a free stream of
+ * its class; a batch can start while earlier ones still run, so queries
+ * that arrive during a launch are admitted into the next one as slots and
+ * memory free up (continuous batching).  Each
  * query's search state (its beam) lives on the device for the whole search;
  * results are copied back once the batch's stream reaches its event.  The
  * result of a query does not depend on the other queries of its batch.
@@ -256,7 +260,10 @@ typedef struct {
                                  lists, outputs, workspaces); 0 = 2 GiB */
     int32_t max_inflight;     /* queries admitted to the device at once; 0 = 4096 */
     int32_t max_batch;        /* queries per launch; 0 = 1024 */
-    int32_t streams;          /* launches that may overlap, 1..8; 0 = 3 */
+    int32_t streams;          /* streams per size class (launches of a class that
+                                 may overlap), 1..4; 0 = 1.  Streams beyond the
+                                 device's hardware queues share queues, and a long
+                                 launch then delays the others on its queue. */
     int32_t queue_capacity;   /* queued (not yet admitted) queries before
                                  ged_server_submit returns GED_EBUSY; 0 = 1<<20 */
 } ged_server_config;

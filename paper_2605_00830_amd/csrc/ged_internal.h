@@ -57,11 +57,14 @@ constexpr int kBlockThreads = 256;
 struct BlockShape {
     int W;       // words per target row the instantiation handles (1,2,4,8,16)
     int PL;      // label planes the instantiation handles (0,2,4)
-    int KS;      // slot stride: K rounded up to kBlockThreads
+    int KS;      // slot stride: block_slot_stride(K)
     int nmax1;   // largest source order in the bin
     int nmax2;   // largest target order in the bin
 };
 
+// Slot stride of the workgroup kernel for beam width K (64, 128, or K
+// rounded up to 256): BlockShape::KS must equal it.
+int block_slot_stride(int K);
 size_t block_workspace_bytes(const BlockShape &s);
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu);
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,

@@ -320,7 +320,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             const int64_t cy = (int64_t)db->h_graphs[y.src].n * (db->h_graphs[y.dst].n + 1);
             return cx > cy;
         });
-        b.shape.KS = (K + gedk::kBlockThreads - 1) / gedk::kBlockThreads * gedk::kBlockThreads;
+        b.shape.KS = gedk::block_slot_stride(K);
         e = gedk::block_max_resident(b.shape, &b.max_block_per_cu);
         if (e == hipSuccess && b.wave_ok) e = gedk::wave_max_resident(b.shape.PL, &b.max_wave_per_cu);
         if (e != hipSuccess || b.max_block_per_cu <= 0 || (b.wave_ok && b.max_wave_per_cu <= 0)) {

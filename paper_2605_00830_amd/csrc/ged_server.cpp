@@ -45,8 +45,11 @@ namespace {
 
 enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3, CANCELED = 4 };
 
+constexpr int kClasses = 3;           // small (wavefront kernel), medium (n <= 128), large
+
 struct Request {
     uint64_t ticket = 0;
+    int cls = 0;
     int32_t n1 = 0;
     int32_t target = 0;
     GraphRec rec{};                 // adj / vlab offsets relative to this request's vectors
@@ -69,6 +72,9 @@ constexpr int kMaxBins = 6;         // wavefront bin + workgroup bins W = 1, 2, 
 
 // Device and pinned-host buffers of one stream.
 struct Slab {
+    int cls = 0;                    // size class this stream serves
+    size_t ws_bytes = 0;            // its workgroup-kernel workspace
+    int64_t cap_words = 0, cap_vlab = 0;   // arena capacity (mappings share cap_vlab)
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     // device
@@ -107,8 +113,6 @@ struct ged_server {
     gedk::Costs c{};
     int PL = 0;
     int cus = 0;
-    int64_t cap_words = 0, cap_vlab = 0, cap_map = 0;  // arena capacity per stream
-    size_t ws_bytes = 0;
     int wave_per_cu = 0;
     int block_per_cu[5] = {0, 0, 0, 0, 0};             // W = 1, 2, 4, 8, 16
     int64_t device_bytes = 0;
@@ -117,7 +121,8 @@ struct ged_server {
     std::mutex mu;
     std::condition_variable cv_work;   // worker: new requests or stop
     std::condition_variable cv_done;   // clients: results
-    std::deque<ReqPtr> queue;
+    std::deque<ReqPtr> queue[kClasses];
+    int64_t queued_total = 0;
     std::unordered_map<uint64_t, ReqPtr> tickets;
     uint64_t next_ticket = 1;
     bool stop = false;
@@ -136,11 +141,20 @@ int w_index(int W) {
     return k;
 }
 
+// Size class of a pair: 0 = small (wavefront kernel), 1 = medium, 2 = large.
+constexpr int kMediumMaxN = 128;
+
+int server_class(const ged_server *s, int n1, int n2) {
+    if (n1 <= gedk::kWaveMaxN && n2 <= gedk::kWaveMaxN && s->cfg.K <= gedk::kWaveMaxK) return 0;
+    if (n1 <= kMediumMaxN && n2 <= kMediumMaxN) return 1;
+    return 2;
+}
+
 gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2) {
     gedk::BlockShape sh{};
     sh.W = W;
     sh.PL = s->PL;
-    sh.KS = (s->cfg.K + gedk::kBlockThreads - 1) / gedk::kBlockThreads * gedk::kBlockThreads;
+    sh.KS = gedk::block_slot_stride(s->cfg.K);
     sh.nmax1 = nmax1;
     sh.nmax2 = nmax2;
     return sh;
@@ -238,7 +252,7 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
             const int W = 1 << (bin - 1);
             const gedk::BlockShape sh = shape_for(s, W, nmax1[bin], nmax2[bin]);
             const size_t stride = gedk::block_workspace_bytes(sh);
-            const int fit = (int)std::min<size_t>(s->ws_bytes / stride, (size_t)std::numeric_limits<int>::max());
+            const int fit = (int)std::min<size_t>(b.ws_bytes / stride, (size_t)std::numeric_limits<int>::max());
             const int grid = std::min({cnt, s->block_per_cu[bin - 1] * s->cus, fit});
             if (grid <= 0) return hipErrorOutOfMemory;
             e = gedk::launch_block(sh, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, b.d_ws,
@@ -307,32 +321,37 @@ void worker_loop(ged_server *s) {
             }
         }
         if (s->stop) {
-            for (ReqPtr &r : s->queue) r->state = CANCELED;
+            for (auto &q : s->queue) {
+                for (ReqPtr &r : q) r->state = CANCELED;
+                q.clear();
+            }
+            s->queued_total = 0;
             s->stats.queued = 0;
-            s->queue.clear();
             s->cv_done.notify_all();
             if (!any_busy) break;
         }
-        // 2. admission and launch
+        // 2. admission and launch: each idle stream takes from its class's queue
         bool launched = false;
-        if (!s->stop && !s->queue.empty()) {
+        if (!s->stop && s->queued_total > 0) {
             for (Slab &b : s->slabs) {
-                if (b.busy || s->queue.empty()) continue;
+                std::deque<ReqPtr> &queue = s->queue[b.cls];
+                if (b.busy || queue.empty()) continue;
                 if (s->stats.inflight >= s->cfg.max_inflight) break;
                 int64_t aw = 0, vo = 0;
-                while (!s->queue.empty() && (int)b.batch.size() < s->cfg.max_batch &&
+                while (!queue.empty() && (int)b.batch.size() < s->cfg.max_batch &&
                        s->stats.inflight + (int64_t)b.batch.size() < s->cfg.max_inflight) {
-                    const Request &r = *s->queue.front();
-                    if (aw + (int64_t)r.adj.size() > s->cap_words || vo + r.n1 > s->cap_vlab) break;
+                    const Request &r = *queue.front();
+                    if (aw + (int64_t)r.adj.size() > b.cap_words || vo + r.n1 > b.cap_vlab) break;
                     aw += (int64_t)r.adj.size();
                     vo += r.n1;
-                    s->queue.front()->state = INFLIGHT;
-                    b.batch.push_back(s->queue.front());
-                    s->queue.pop_front();
+                    queue.front()->state = INFLIGHT;
+                    b.batch.push_back(queue.front());
+                    queue.pop_front();
                 }
-                if (b.batch.empty()) break;
+                if (b.batch.empty()) continue;
                 b.busy = true;
-                s->stats.queued = (int64_t)s->queue.size();
+                s->queued_total -= (int64_t)b.batch.size();
+                s->stats.queued = s->queued_total;
                 s->stats.inflight += (int64_t)b.batch.size();
                 s->stats.inflight_peak = std::max(s->stats.inflight_peak, s->stats.inflight);
                 s->stats.batch_peak = std::max(s->stats.batch_peak, (int64_t)b.batch.size());
@@ -354,7 +373,7 @@ void worker_loop(ged_server *s) {
         if (any_busy) {
             s->cv_work.wait_for(lk, std::chrono::microseconds(20));
         } else {
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            s->cv_work.wait(lk, [&] { return s->stop || s->queued_total > 0; });
         }
     }
 }
@@ -377,9 +396,9 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     if (cfg.hbm_budget == 0) cfg.hbm_budget = (int64_t)2 << 30;
     if (cfg.max_inflight == 0) cfg.max_inflight = 4096;
     if (cfg.max_batch == 0) cfg.max_batch = 1024;
-    if (cfg.streams == 0) cfg.streams = 3;
+    if (cfg.streams == 0) cfg.streams = 1;
     if (cfg.queue_capacity == 0) cfg.queue_capacity = 1 << 20;
-    if (cfg.streams > 8) return fail(GED_EINVAL, "streams must be 1..8");
+    if (cfg.streams > 4) return fail(GED_EINVAL, "streams (per size class) must be 1..4");
     st = gedh::check_device(db);
     if (st != GED_OK) return st;
 
@@ -391,69 +410,84 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     s->PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     s->device = db->device;
     hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    if (e == hipSuccess && cfg.K <= gedk::kWaveMaxK) e = gedk::wave_max_resident(s->PL, &s->wave_per_cu);
-    // workgroup-kernel workspace: the largest over W of stride x resident grid,
-    // for targets of up to 32*W vertices
-    // per-stream budget: the workspace takes at most half (fewer resident
-    // workgroups when it is smaller), the arena gets what is left
-    const int64_t per_stream = cfg.hbm_budget / cfg.streams;
-    size_t ws = 0, one_block = 0;
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-        const int W = 1 << k;
-        const gedk::BlockShape sh = shape_for(s, W, GED_MAX_VERTICES, std::min(32 * W, GED_MAX_VERTICES));
-        e = gedk::block_max_resident(sh, &s->block_per_cu[k]);
-        const int64_t grid = std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->block_per_cu[k] * s->cus);
-        one_block = std::max(one_block, gedk::block_workspace_bytes(sh));
-        ws = std::max(ws, gedk::block_workspace_bytes(sh) * (size_t)grid);
+    const bool small_class = cfg.K <= gedk::kWaveMaxK;
+    if (e == hipSuccess && small_class) e = gedk::wave_max_resident(s->PL, &s->wave_per_cu);
+    const int first_class = small_class ? 0 : 1;
+    const int nslabs = (kClasses - first_class) * cfg.streams;
+    // every stream gets an equal share of the budget: its class's workspace
+    // (at most half of the share; fewer resident workgroups when smaller),
+    // then the arena
+    const int64_t per_stream = cfg.hbm_budget / nslabs;
+    size_t ws_class[kClasses] = {0, 0, 0};
+    const int max_n[kClasses] = {gedk::kWaveMaxN, kMediumMaxN, GED_MAX_VERTICES};
+    for (int cls = 1; cls < kClasses && e == hipSuccess; ++cls) {
+        size_t ws = 0, one_block = 0;
+        for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+            const int W = 1 << k;
+            if (W > 1 && 16 * W >= max_n[cls]) break;   // W / 2 words already cover the class
+            const gedk::BlockShape sh = shape_for(s, W, max_n[cls], std::min(32 * W, max_n[cls]));
+            e = gedk::block_max_resident(sh, &s->block_per_cu[k]);
+            const int64_t grid = std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->block_per_cu[k] * s->cus);
+            one_block = std::max(one_block, gedk::block_workspace_bytes(sh));
+            ws = std::max(ws, gedk::block_workspace_bytes(sh) * (size_t)grid);
+        }
+        ws = std::min<size_t>(ws, (size_t)std::max<int64_t>(per_stream / 2, 0));
+        if (e == hipSuccess && ws < one_block) {
+            delete s;
+            return fail(GED_ENOMEM, "hbm_budget %lld is too small: a stream needs %zu bytes for one workgroup's "
+                                    "workspace", (long long)cfg.hbm_budget, one_block);
+        }
+        ws_class[cls] = ws;
     }
     if (e != hipSuccess) {
         delete s;
         return fail(GED_EDEVICE, "device query failed: %s", hipGetErrorString(e));
     }
-    ws = std::min<size_t>(ws, (size_t)std::max<int64_t>(per_stream / 2, 0));
-    if (ws < one_block) {
-        delete s;
-        return fail(GED_ENOMEM, "hbm_budget %lld is too small: a stream needs %zu bytes for one workgroup's "
-                                "workspace", (long long)cfg.hbm_budget, one_block);
+    // arena of a stream: what its share leaves after the workspace, at most a
+    // full batch of the class's largest queries (and 64 MiB of graph words)
+    int64_t cap_words[kClasses], cap_vlab[kClasses];
+    for (int cls = first_class; cls < kClasses; ++cls) {
+        const int64_t fixed = (int64_t)ws_class[cls] +
+                              (int64_t)cfg.max_batch * (int64_t)(sizeof(GraphRec) + sizeof(WorkItem) + 4) + kMaxBins * 4;
+        const int64_t rest = per_stream - fixed;
+        const int64_t big = gedh::packed_words(max_n[cls], db->planes);
+        cap_words[cls] = std::min({rest / 4 * 8 / 10, (int64_t)cfg.max_batch * big, (int64_t)16 << 20});
+        cap_vlab[cls] = std::min(rest / 4 / 20, (int64_t)cfg.max_batch * max_n[cls]);
+        if (rest <= 0 || cap_words[cls] < big || cap_vlab[cls] < max_n[cls]) {
+            delete s;
+            return fail(GED_ENOMEM, "hbm_budget %lld is too small: each of %d streams needs %lld bytes of workspace "
+                                    "plus room for one %d-vertex query", (long long)cfg.hbm_budget, nslabs,
+                        (long long)fixed, max_n[cls]);
+        }
     }
-    s->ws_bytes = ws;
-    const int64_t fixed = (int64_t)ws + (int64_t)cfg.max_batch * (int64_t)(sizeof(GraphRec) + sizeof(WorkItem) + 4) +
-                          kMaxBins * 4;
-    const int64_t rest = per_stream - fixed;
-    // the largest query: 512 vertices, 16 words per row, rows plus planes
-    const int64_t big = gedh::packed_words(GED_MAX_VERTICES, db->planes);
-    s->cap_words = rest / 4 * 8 / 10;
-    s->cap_vlab = rest / 4 / 20;
-    s->cap_map = s->cap_vlab;
-    if (rest <= 0 || s->cap_words < big || s->cap_vlab < GED_MAX_VERTICES) {
-        delete s;
-        return fail(GED_ENOMEM, "hbm_budget %lld is too small: each of %d streams needs %lld bytes of workspace "
-                                "plus room for one 512-vertex query", (long long)cfg.hbm_budget, cfg.streams,
-                    (long long)fixed);
-    }
-    s->slabs.resize((size_t)cfg.streams);
-    for (Slab &b : s->slabs) {
+    s->slabs.resize((size_t)nslabs);
+    for (int k = 0; k < nslabs; ++k) {
+        Slab &b = s->slabs[(size_t)k];
+        b.cls = first_class + k / cfg.streams;
+        b.ws_bytes = ws_class[b.cls];
+        b.cap_words = cap_words[b.cls];
+        b.cap_vlab = cap_vlab[b.cls];
         e = hipStreamCreate(&b.stream);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
         const size_t nb = (size_t)cfg.max_batch;
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_recs, sizeof(GraphRec) * nb);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_adj, sizeof(uint32_t) * (size_t)s->cap_words);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_vlab, sizeof(int32_t) * (size_t)s->cap_vlab);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_adj, sizeof(uint32_t) * (size_t)b.cap_words);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_vlab, sizeof(int32_t) * (size_t)b.cap_vlab);
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * nb);
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * kMaxBins);
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_dist, sizeof(int32_t) * nb);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_map, sizeof(int32_t) * (size_t)s->cap_map);
-        if (e == hipSuccess && ws > 0) e = hipMalloc(&b.d_ws, ws);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_map, sizeof(int32_t) * (size_t)b.cap_vlab);
+        if (e == hipSuccess && b.ws_bytes > 0) e = hipMalloc(&b.d_ws, b.ws_bytes);
         if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_recs, sizeof(GraphRec) * nb, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_adj, sizeof(uint32_t) * (size_t)s->cap_words, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_vlab, sizeof(int32_t) * (size_t)s->cap_vlab, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_adj, sizeof(uint32_t) * (size_t)b.cap_words, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_vlab, sizeof(int32_t) * (size_t)b.cap_vlab, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_work, sizeof(WorkItem) * nb, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_dist, sizeof(int32_t) * nb, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_map, sizeof(int32_t) * (size_t)s->cap_map, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_map, sizeof(int32_t) * (size_t)b.cap_vlab, hipHostMallocDefault);
         if (e != hipSuccess) break;
-        s->device_bytes += (int64_t)(sizeof(GraphRec) * nb + sizeof(uint32_t) * (size_t)s->cap_words +
-                                     sizeof(int32_t) * (size_t)s->cap_vlab + sizeof(WorkItem) * nb + sizeof(int) * kMaxBins +
-                                     sizeof(int32_t) * nb + sizeof(int32_t) * (size_t)s->cap_map + ws);
+        s->device_bytes += (int64_t)(sizeof(GraphRec) * nb + sizeof(uint32_t) * (size_t)b.cap_words +
+                                     sizeof(int32_t) * (size_t)b.cap_vlab + sizeof(WorkItem) * nb + sizeof(int) * kMaxBins +
+                                     sizeof(int32_t) * nb + sizeof(int32_t) * (size_t)b.cap_vlab + b.ws_bytes);
     }
     if (e != hipSuccess) {
         for (Slab &b : s->slabs) free_slab(b);
@@ -477,6 +511,7 @@ ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t ta
     st = gedh::pack_graph(*query, 0, srv->db->elabels, srv->db->planes, r->adj, r->vlab, r->rec);
     if (st != GED_OK) return st;
     const GraphRec &g2 = srv->db->h_graphs[(size_t)target_id];
+    r->cls = server_class(srv, query->n, g2.n);
     const ged_costs &c = srv->cfg.costs;
     const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
     const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
@@ -485,16 +520,17 @@ ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t ta
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stop) return fail(GED_ECANCELED, "server is shutting down");
-        if ((int64_t)srv->queue.size() >= srv->cfg.queue_capacity) {
+        if (srv->queued_total >= srv->cfg.queue_capacity) {
             srv->stats.rejected_busy += 1;
             return fail(GED_EBUSY, "queue full (%d queued)", srv->cfg.queue_capacity);
         }
         r->ticket = srv->next_ticket++;
         r->t_submit = now_ns();
         srv->tickets[r->ticket] = r;
-        srv->queue.push_back(r);
+        srv->queue[r->cls].push_back(r);
+        srv->queued_total += 1;
         srv->stats.submitted += 1;
-        srv->stats.queued = (int64_t)srv->queue.size();
+        srv->stats.queued = srv->queued_total;
         *ticket = r->ticket;
     }
     srv->cv_work.notify_one();

@@ -1,31 +1,43 @@
-// kb_block.hip -- block-per-pair K-Best search for gfx950 (general shapes).
+// kb_block.hip -- workgroup-per-pair K-Best search for gfx950 (any shape up
+// to 512 vertices and K = 1024).
 //
 // One 256-thread workgroup searches one pair at a time and pulls the next
-// pair from a work queue (persistent launch).  Thread t owns the beam slots
-// s = r*256 + t.  Per level i (the loop of Alg. 1, g1 vertex v_i):
-//   expand    every slot s builds Phi = image of v_i's earlier neighbours
-//             (one bit per g2 vertex, plus one set per edge-label plane),
-//             then scores each child by the implied edge operations of
-//             Sec. 2.3 / Alg. 2 as popcounts of word-wise ANDs:
+// pair from a work queue (persistent launch).  Beam slots are spread over
+// the threads: G = min(KS, 256) slots per round, TPS = 256 / G threads per
+// slot (thread t = slot-in-round * TPS + part), each part owning a
+// contiguous range of the slot's children (substitutions by ascending g2
+// vertex, the deletion last), so thread order is generation order.
+// Per level i (the loop of Alg. 1, g1 vertex v_i):
+//   expand    every thread builds its slot's Phi = image of v_i's earlier
+//             neighbours (one bit per g2 vertex, one set per edge-label
+//             plane) and scores its children by the implied edge operations
+//             of Sec. 2.3 / Alg. 2 as popcounts of word-wise ANDs against
+//             g2's rows (staged in LDS):
 //               kept   = |Phi & N2(u)|             edges kept (maybe relabelled)
 //               del    = |P(v_i)| - kept           g1 edges deleted
 //               ins    = |Img & N2(u)| - kept      g2 edges inserted
 //               relab  = |Phi & N2(u) & label-mismatch|
 //             The deletion child costs vdel + edel*|P(v_i)| (Sec. 4.2.1).
-//   select    the K best children (Sec. 4.3) without sorting: threshold T =
-//             K-th smallest partial edit distance from an LDS histogram, all
-//             children below T, and the first (K - #below) children equal to
-//             T in generation order (exclusive block scans).  Survivors are
-//             compacted in generation order, so the beam stays ordered.
+//             Each child also lands in an LDS histogram of 1024 bins above
+//             the least parent PED (a lower bound of every child).
+//   select    the K best children (Sec. 4.3) without sorting: T = K-th
+//             smallest PED from the histogram (further windows from the
+//             least value above it when needed), every child below T, and
+//             the first (K - #below) children equal to T in generation order
+//             (exclusive block scans).  Survivors are compacted in generation
+//             order, so the beam stays ordered.
 //   update    survivors copy their parent's mapping and add one entry (the
 //             paper's update step, Sec. 4.4.2).
 // At the end every slot adds the insertion costs of the unmatched g2
 // vertices and edges (Sec. 4.4.1) and a block arg-min picks the result.
 //
-// State per slot (global workspace, slot-minor so a wave touches 64
-// consecutive entries): partial edit distance, |Img|, number of g2 edges
-// inside Img, Img bitset, mapping phi[j] (uint16, 0xffff = deleted); the
-// candidate matrix cand[u][s] (u = n2 is the deletion child).
+// LDS holds g2's rows padded to W words (read with vector loads, no bounds
+// tests), its label planes when they fit, and the candidate matrix as
+// cand[s][c] (odd row stride, so the parts of a wave hit different banks)
+// when everything fits 136 KB (CL); otherwise the candidate matrix lives in
+// the per-block global workspace as cand[c][s] (consecutive slots coalesce).
+// Beam state per slot in the workspace (slot-minor): PED, |Img|, g2 edges
+// inside Img, Img bitset, mapping phi[j] (uint16, 0xffff = deleted).
 #include "ged_internal.h"
 
 namespace gedk {
@@ -36,6 +48,8 @@ constexpr int NW = BT / 64;
 constexpr int NBINS = 1024;
 constexpr int SENT = 0x7fffffff;        // invalid child (target vertex already used)
 constexpr uint16_t PHI_DEL = 0xffff;
+constexpr size_t kDynLdsBytes = 136 * 1024;    // rows, staged planes, candidate matrix
+constexpr size_t kPlaneLdsBytes = 48 * 1024;   // rows plus planes staged when they fit this
 
 struct WsLayout {
     size_t ped, ein, nsub, img, phi, cand, stride;
@@ -43,14 +57,17 @@ struct WsLayout {
 };
 
 struct BlockArgs {
-    DbView src;   // graphs edited (g1)
-    DbView dst;   // target graphs (g2); same edge-label coding as src
+    DbView src;    // graphs edited (g1)
+    DbView dst;    // target graphs (g2); same edge-label coding as src
     const WorkItem *work;
     int nwork;
     int *queue;
     Costs c;
     int K;
-    int KS;
+    int KS;        // slot stride
+    int TPS;       // threads per slot
+    int rows_words;   // LDS words per staged block of g2 rows (nmax2 x W)
+    int planes_lds;   // label planes staged in LDS after the rows
     char *ws;
     WsLayout L;
     Outputs out;
@@ -134,12 +151,15 @@ __device__ __forceinline__ uint32_t below_mask(int i, int kw) {
     return rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
 }
 
-template <int W, int PL>
+template <int W, int PL, bool CL>
 __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
+    extern __shared__ uint32_t s_dyn[];   // g2 rows, then (CL) the candidate matrix
     __shared__ int s_sel[GED_MAX_K];      // survivor: parent slot << 10 | child (n2 = deletion)
     __shared__ int s_selped[GED_MAX_K];   // survivor partial edit distance
     __shared__ int s_hist[NBINS];
+    __shared__ uint16_t s_nbr[GED_MAX_VERTICES];   // earlier neighbours of v_i
+    __shared__ uint8_t s_nbl[GED_MAX_VERTICES];    // their edge-label codes
     __shared__ int s_red[NW];
     __shared__ unsigned long long s_red64[NW];
     __shared__ int s_bc[4];
@@ -151,9 +171,16 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     int *nsub_b = reinterpret_cast<int *>(wsb + a.L.nsub);
     uint32_t *img_b = reinterpret_cast<uint32_t *>(wsb + a.L.img);
     uint16_t *phi_b = reinterpret_cast<uint16_t *>(wsb + a.L.phi);
-    int *cand = reinterpret_cast<int *>(wsb + a.L.cand);
+    int *__restrict__ cand_g = reinterpret_cast<int *>(wsb + a.L.cand);
+    uint32_t *s_rows = s_dyn;             // row u at u * W, padded with zero words
+    uint32_t *s_planes = s_dyn + a.rows_words;
+    int *cand_l = reinterpret_cast<int *>(s_dyn + a.rows_words * (1 + (a.planes_lds ? PL : 0)));
     const int KS = a.KS;
-    const int SPT = KS / BT;
+    const int TPS = a.TPS;
+    const int G = BT / TPS;              // slots per round
+    const int SPT = KS / G;              // rounds
+    const int sg = t / TPS;              // slot within a round
+    const int part = t % TPS;
     const int K = a.K;
     const Costs c = a.c;
     const int P = a.dst.planes;
@@ -174,7 +201,22 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
         const int *L1 = a.src.vlab + g1.vlab;
         const int *L2 = a.dst.vlab + g2.vlab;
         const size_t pl1 = (size_t)n1 * w1, pl2 = (size_t)n2 * w2;
+        const int nc = n2 + 1;                       // children per slot (deletion = n2)
+        const int CST = nc | 1;                      // LDS row stride of the candidate matrix
+        const int chunk = (nc + TPS - 1) / TPS;      // children per part
+        const int c_lo = min(part * chunk, nc), c_hi = min(c_lo + chunk, nc);
 
+        for (int x = t; x < n2 * W; x += BT) {
+            const int u = x / W, kk = x % W;
+            s_rows[x] = kk < w2 ? A2[(size_t)u * w2 + kk] : 0u;
+        }
+        if (PL > 0 && a.planes_lds) {
+            for (int x = t; x < PL * n2 * W; x += BT) {
+                const int b = x / (n2 * W), r = x % (n2 * W), u = r / W, kk = r % W;
+                s_planes[(size_t)b * a.rows_words + r] =
+                    (b < P && kk < w2) ? A2[(size_t)(1 + b) * pl2 + (size_t)u * w2 + kk] : 0u;
+            }
+        }
         if (t == 0) {
             ped_b[0] = 0;
             ein_b[0] = 0;
@@ -191,15 +233,45 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             int degP = 0;
             for (int kw = 0; kw * 32 < i; ++kw) degP += __popc(A1[(size_t)i * w1 + kw] & below_mask(i, kw));
             const int del_cost = c.vdel + c.edel * degP;
+            // the earlier neighbours of v_i (the same for every slot), in index
+            // order, with their edge-label codes: listed once per level by wave 0
+            if (t < 64) {
+                int base = 0;
+                for (int kw = 0; kw * 32 < i; ++kw) {
+                    const uint32_t bits = A1[(size_t)i * w1 + kw] & below_mask(i, kw);
+                    const bool mine = t < 32 && ((bits >> t) & 1u);
+                    const unsigned long long m = __ballot(mine);
+                    if (mine) {
+                        const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                        int code = 0;
+#pragma unroll
+                        for (int b = 0; b < PLA; ++b)
+                            if (PL > 0 && b < P) code |= (int)((A1[(size_t)(1 + b) * pl1 + (size_t)i * w1 + kw] >> t) & 1u) << b;
+                        s_nbr[base + rank] = (uint16_t)(kw * 32 + t);
+                        s_nbl[base + rank] = (uint8_t)code;
+                    }
+                    base += __popcll(m);
+                }
+            }
 
-            const int *pedc = ped_b + cur * KS;
-            const uint32_t *imgc = img_b + (size_t)cur * W * KS;
-            const uint16_t *phic = phi_b + cur * a.L.phi_half;
+            const int *__restrict__ pedc = ped_b + cur * KS;
+            const uint32_t *__restrict__ imgc = img_b + (size_t)cur * W * KS;
+            const uint16_t *__restrict__ phic = phi_b + cur * a.L.phi_half;
 
-            // ---------------- expand and evaluate
-            int lmin = SENT, lcnt = 0;
+            // lower bound of every child: the least parent PED
+            int lpmin = SENT;
             for (int r = 0; r < SPT; ++r) {
-                const int s = r * BT + t;
+                const int s = r * G + sg;
+                if (s < nb && part == 0) lpmin = min(lpmin, pedc[s]);
+            }
+            for (int b = t; b < NBINS; b += BT) s_hist[b] = 0;
+            const int m0 = block_min(lpmin, s_red);   // also orders the histogram reset and the list
+
+            // ---------------- expand, evaluate, histogram
+            int lcnt = 0, ovmin = SENT;
+            for (int r = 0; r < SPT; ++r) {
+                const int s = r * G + sg;
                 if (s >= nb) break;
                 const int pp = pedc[s];
                 uint32_t img_r[W];
@@ -212,94 +284,94 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
 #pragma unroll
                     for (int b = 0; b < PLA; ++b) phib[b][k] = 0u;
                 }
-                for (int kw = 0; kw * 32 < i; ++kw) {
-                    uint32_t bits = A1[(size_t)i * w1 + kw] & below_mask(i, kw);
-                    uint32_t pw[PLA];
+#pragma unroll 8
+                for (int q = 0; q < degP; ++q) {
+                    const int x = phic[(size_t)s_nbr[q] * KS + s];
+                    if (x != PHI_DEL) {
+                        const uint32_t bit = 1u << (x & 31);
+                        const int xw = x >> 5;
+                        const int code = PL > 0 ? s_nbl[q] : 0;
 #pragma unroll
-                    for (int b = 0; b < PLA; ++b)
-                        pw[b] = (PL > 0 && b < P) ? A1[(size_t)(1 + b) * pl1 + (size_t)i * w1 + kw] : 0u;
-                    while (bits) {
-                        const int jb = __builtin_ctz(bits);
-                        bits &= bits - 1u;
-                        const int x = phic[(size_t)(kw * 32 + jb) * KS + s];
-                        if (x != PHI_DEL) {
-                            const uint32_t bit = 1u << (x & 31);
-                            const int xw = x >> 5;
+                        for (int k = 0; k < W; ++k) {
+                            const uint32_t hit = (k == xw) ? bit : 0u;
+                            phi_r[k] |= hit;
 #pragma unroll
-                            for (int k = 0; k < W; ++k) {
-                                const uint32_t hit = (k == xw) ? bit : 0u;
-                                phi_r[k] |= hit;
-#pragma unroll
-                                for (int b = 0; b < PLA; ++b)
-                                    phib[b][k] |= ((pw[b] >> jb) & 1u) ? hit : 0u;
-                            }
+                            for (int b = 0; b < PLA; ++b)
+                                phib[b][k] |= ((code >> b) & 1) ? hit : 0u;
                         }
                     }
                 }
-                int cnt = 1;
+                // children u = c_lo .. min(c_hi, n2)-1 in order; the image word of
+                // u is refreshed once per 32 children (no dynamic register index)
+                uint32_t cur_img = 0u;
+                int cur_w = -1;
+                const int u_end = min(c_hi, n2);
+#pragma unroll 2
+                for (int u = c_lo; u < u_end; ++u) {
+                    const int uw = u >> 5;
+                    if (uw != cur_w) {
+                        cur_w = uw;
+                        cur_img = 0u;
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    if (k * 32 < n2) {
-                        const int ub = min(32, n2 - k * 32);
-                        for (int b = 0; b < ub; ++b) {
-                            const int u = k * 32 + b;
-                            const uint32_t *R = A2 + (size_t)u * w2;
-                            int kept = 0, inimg = 0, relab = 0;
+                        for (int k = 0; k < W; ++k) cur_img = (k == uw) ? img_r[k] : cur_img;
+                    }
+                    const uint32_t *R = s_rows + u * W;
+                    uint32_t row[W];
 #pragma unroll
-                            for (int kk = 0; kk < W; ++kk) {
-                                if (kk < w2) {
-                                    const uint32_t row = R[kk];
-                                    const uint32_t both = phi_r[kk] & row;
-                                    kept += __popc(both);
-                                    inimg += __popc(img_r[kk] & row);
-                                    if (PL > 0) {
-                                        uint32_t diff = 0u;
+                    for (int kk = 0; kk < W; ++kk) row[kk] = R[kk];
+                    int kept = 0, inimg = 0, relab = 0;
 #pragma unroll
-                                        for (int bb = 0; bb < PLA; ++bb)
-                                            if (bb < P) diff |= phib[bb][kk] ^ A2[(size_t)(1 + bb) * pl2 + (size_t)u * w2 + kk];
-                                        relab += __popc(both & diff);
-                                    }
-                                }
+                    for (int kk = 0; kk < W; ++kk) {
+                        const uint32_t both = phi_r[kk] & row[kk];
+                        kept += __popc(both);
+                        inimg += __popc(img_r[kk] & row[kk]);
+                        if (PL > 0) {
+                            uint32_t diff = 0u;
+                            if (a.planes_lds) {
+#pragma unroll
+                                for (int bb = 0; bb < PLA; ++bb)
+                                    diff |= phib[bb][kk] ^ s_planes[(size_t)bb * a.rows_words + u * W + kk];
+                            } else if (kk < w2) {
+#pragma unroll
+                                for (int bb = 0; bb < PLA; ++bb)
+                                    if (bb < P) diff |= phib[bb][kk] ^ A2[(size_t)(1 + bb) * pl2 + (size_t)u * w2 + kk];
                             }
-                            const int d = pp + (lab1 != L2[u] ? c.vsub : 0) + c.edel * (degP - kept) +
-                                          c.eins * (inimg - kept) + c.esub * relab;
-                            const bool used = (img_r[k] >> b) & 1u;
-                            cand[(size_t)u * KS + s] = used ? SENT : d;
-                            if (!used) {
-                                lmin = min(lmin, d);
-                                ++cnt;
-                            }
+                            relab += __popc(both & diff);
                         }
                     }
+                    const int d = pp + (lab1 != L2[u] ? c.vsub : 0) + c.edel * (degP - kept) +
+                                  c.eins * (inimg - kept) + c.esub * relab;
+                    const bool used = (cur_img >> (u & 31)) & 1u;
+                    const int v = used ? SENT : d;
+                    if (CL) cand_l[s * CST + u] = v;
+                    else cand_g[(size_t)u * KS + s] = v;
+                    if (!used) {
+                        ++lcnt;
+                        if (d - m0 < NBINS) atomicAdd(&s_hist[d - m0], 1);
+                        else ovmin = min(ovmin, d);
+                    }
                 }
-                const int dd = pp + del_cost;
-                cand[(size_t)n2 * KS + s] = dd;
-                lmin = min(lmin, dd);
-                lcnt += cnt;
+                if (c_lo <= n2 && c_hi == nc) {   // this part owns the deletion child
+                    const int dd = pp + del_cost;
+                    if (CL) cand_l[s * CST + n2] = dd;
+                    else cand_g[(size_t)n2 * KS + s] = dd;
+                    ++lcnt;
+                    if (dd - m0 < NBINS) atomicAdd(&s_hist[dd - m0], 1);
+                    else ovmin = min(ovmin, dd);
+                }
             }
-            const int mmin = block_min(lmin, s_red);
-            const int V = block_sum(lcnt, s_red);
+            const int V = block_sum(lcnt, s_red);   // also orders the histogram updates
             ce += V;
+            auto cand_at = [&](int s, int u) -> int {
+                return CL ? cand_l[s * CST + u] : cand_g[(size_t)u * KS + s];
+            };
 
             // ---------------- threshold: K-th smallest partial edit distance
             int T = SENT, quota = 0;
             if (V > K) {
-                int lo = mmin, below = 0;
+                int lo = m0, below = 0;
+                int nxt = block_min(ovmin, s_red);
                 for (;;) {
-                    for (int b = t; b < NBINS; b += BT) s_hist[b] = 0;
-                    __syncthreads();
-                    int nxt = SENT;
-                    for (int r = 0; r < SPT; ++r) {
-                        const int s = r * BT + t;
-                        if (s >= nb) break;
-                        for (int u = 0; u <= n2; ++u) {
-                            const int v = cand[(size_t)u * KS + s];
-                            if (v == SENT || v < lo) continue;
-                            if (v - lo < NBINS) atomicAdd(&s_hist[v - lo], 1);
-                            else nxt = min(nxt, v);
-                        }
-                    }
-                    nxt = block_min(nxt, s_red);   // also orders the histogram writes
                     if (t < 64) {
                         constexpr int PER = NBINS / 64;
                         const int base = t * PER;
@@ -309,8 +381,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                         const int incl = wave_incl_scan(sum);
                         const unsigned long long hit = __ballot(below + incl >= K);
                         if (hit) {
-                            const int L = __ffsll((long long)hit) - 1;
-                            if (t == L) {
+                            const int Lh = __ffsll((long long)hit) - 1;
+                            if (t == Lh) {
                                 int cum = below + incl - sum;
                                 for (int k = 0; k < PER; ++k) {
                                     const int h = s_hist[base + k];
@@ -337,20 +409,38 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                         quota = K - v3;
                         break;
                     }
+                    // the K-th value lies above this window: the next window starts
+                    // at the least value above it (one exists, since V > K)
                     below = v3;
                     lo = nxt;
+                    for (int b = t; b < NBINS; b += BT) s_hist[b] = 0;
+                    __syncthreads();
+                    int nn = SENT;
+                    for (int r = 0; r < SPT; ++r) {
+                        const int s = r * G + sg;
+                        if (s >= nb) break;
+#pragma unroll 8
+                        for (int u = c_lo; u < c_hi; ++u) {
+                            const int v = cand_at(s, u);
+                            if (v == SENT || v < lo) continue;
+                            if (v - lo < NBINS) atomicAdd(&s_hist[v - lo], 1);
+                            else nn = min(nn, v);
+                        }
+                    }
+                    nxt = block_min(nn, s_red);   // also orders the histogram writes
                 }
             }
 
             // ---------------- keep flags, tie quota and compaction in generation order
             int eq_carry = 0, out_carry = 0;
             for (int r = 0; r < SPT; ++r) {
-                const int s = r * BT + t;
+                const int s = r * G + sg;
                 const bool live = s < nb;
                 int lt = 0, eq = 0;
                 if (live) {
-                    for (int u = 0; u <= n2; ++u) {
-                        const int v = cand[(size_t)u * KS + s];
+#pragma unroll 8
+                    for (int u = c_lo; u < c_hi; ++u) {
+                        const int v = cand_at(s, u);
                         lt += v < T;
                         eq += v == T;
                     }
@@ -363,8 +453,9 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 out_carry += tot;
                 if (live && keep > 0) {
                     int pos = OUT, e = EQ;
-                    for (int u = 0; u <= n2; ++u) {
-                        const int v = cand[(size_t)u * KS + s];
+#pragma unroll 8
+                    for (int u = c_lo; u < c_hi; ++u) {
+                        const int v = cand_at(s, u);
                         bool take = v < T;
                         if (v == T) {
                             take = e < quota;
@@ -388,27 +479,30 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             int *nsubn = nsub_b + nxt * KS;
             const int *einc = ein_b + cur * KS;
             const int *nsubc = nsub_b + cur * KS;
-            uint32_t *imgn = img_b + (size_t)nxt * W * KS;
-            uint16_t *phin = phi_b + nxt * a.L.phi_half;
+            uint32_t *__restrict__ imgn = img_b + (size_t)nxt * W * KS;
+            uint16_t *__restrict__ phin = phi_b + nxt * a.L.phi_half;
             for (int r = 0; r < SPT; ++r) {
-                const int s2 = r * BT + t;
+                const int s2 = r * G + sg;
                 if (s2 >= nb_new) break;
                 const int sel = s_sel[s2];
                 const int p = sel >> 10, u = sel & 1023;
                 const bool sub = u < n2;
-                for (int j = 0; j < i; ++j) phin[(size_t)j * KS + s2] = phic[(size_t)j * KS + p];
-                phin[(size_t)i * KS + s2] = sub ? (uint16_t)u : PHI_DEL;
-                int add_e = 0;
+#pragma unroll 8
+                for (int j = part; j < i; j += TPS) phin[(size_t)j * KS + s2] = phic[(size_t)j * KS + p];
+                if (part == 0) {
+                    phin[(size_t)i * KS + s2] = sub ? (uint16_t)u : PHI_DEL;
+                    int add_e = 0;
 #pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    const uint32_t ip = imgc[(size_t)k * KS + p];
-                    const uint32_t row = (sub && k < w2) ? A2[(size_t)u * w2 + k] : 0u;
-                    add_e += __popc(ip & row);
-                    imgn[(size_t)k * KS + s2] = ip | ((sub && (u >> 5) == k) ? (1u << (u & 31)) : 0u);
+                    for (int k = 0; k < W; ++k) {
+                        const uint32_t ip = imgc[(size_t)k * KS + p];
+                        const uint32_t row = sub ? s_rows[u * W + k] : 0u;
+                        add_e += __popc(ip & row);
+                        imgn[(size_t)k * KS + s2] = ip | ((sub && (u >> 5) == k) ? (1u << (u & 31)) : 0u);
+                    }
+                    pedn[s2] = s_selped[s2];
+                    einn[s2] = einc[p] + add_e;
+                    nsubn[s2] = nsubc[p] + (sub ? 1 : 0);
                 }
-                pedn[s2] = s_selped[s2];
-                einn[s2] = einc[p] + add_e;
-                nsubn[s2] = nsubc[p] + (sub ? 1 : 0);
             }
             __syncthreads();
             cur = nxt;
@@ -422,8 +516,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             const int *einc = ein_b + cur * KS;
             const int *nsubc = nsub_b + cur * KS;
             for (int r = 0; r < SPT; ++r) {
-                const int s = r * BT + t;
-                if (s >= nb) break;
+                const int s = r * G + sg;
+                if (s >= nb || part != 0) continue;
                 const int total = pedc[s] + c.vins * (n2 - nsubc[s]) + c.eins * (g2.m - einc[s]);
                 const unsigned long long key = ((unsigned long long)(unsigned)total << 32) | (unsigned)s;
                 best = key < best ? key : best;
@@ -454,6 +548,22 @@ __global__ void fill_zero_kernel(int *p, int count) {
     if (i < count) p[i] = 0;
 }
 
+int cand_stride_max(const BlockShape &s) { return (s.nmax2 + 1) | 1; }
+
+int rows_words(const BlockShape &s) { return s.nmax2 * s.W; }
+
+bool planes_in_lds(const BlockShape &s) {
+    return s.PL > 0 && (size_t)(1 + s.PL) * (size_t)rows_words(s) * 4 <= kPlaneLdsBytes;
+}
+
+size_t staged_bytes(const BlockShape &s) {
+    return (size_t)rows_words(s) * 4 * (1 + (planes_in_lds(s) ? s.PL : 0));
+}
+
+bool cand_in_lds(const BlockShape &s) {
+    return staged_bytes(s) + (size_t)s.KS * (size_t)cand_stride_max(s) * 4 <= kDynLdsBytes;
+}
+
 WsLayout layout_for(const BlockShape &s) {
     WsLayout L{};
     size_t off = 0;
@@ -469,22 +579,29 @@ WsLayout layout_for(const BlockShape &s) {
     L.nsub = take(2 * KS * 4);
     L.img = take(2 * (size_t)s.W * KS * 4);
     L.phi = take(2 * n1 * KS * 2);
-    L.cand = take(((size_t)s.nmax2 + 1) * KS * 4);
+    L.cand = take(cand_in_lds(s) ? 0 : ((size_t)s.nmax2 + 1) * KS * 4);
     L.stride = off;
     L.phi_half = n1 * KS;
     return L;
 }
 
-template <int W, int PL>
-const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL>);
+size_t dyn_lds_bytes(const BlockShape &s) {
+    size_t b = staged_bytes(s);
+    if (cand_in_lds(s)) b += (size_t)s.KS * (size_t)cand_stride_max(s) * 4;
+    return b;
 }
 
-const void *select_kernel(int W, int PL) {
-#define GEDK_CASE(w, pl) \
-    if (W == w && PL == pl) return kernel_ptr<w, pl>();
-#define GEDK_ROW(w) GEDK_CASE(w, 0) GEDK_CASE(w, 2) GEDK_CASE(w, 4)
-    GEDK_ROW(1) GEDK_ROW(2) GEDK_ROW(4) GEDK_ROW(8) GEDK_ROW(16)
+template <int W, int PL, bool CL>
+const void *kernel_ptr() {
+    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL, CL>);
+}
+
+const void *select_kernel(int W, int PL, bool CL) {
+#define GEDK_CASE(w, pl, cl) \
+    if (W == w && PL == pl && CL == cl) return kernel_ptr<w, pl, cl>();
+#define GEDK_ROW(w, cl) GEDK_CASE(w, 0, cl) GEDK_CASE(w, 2, cl) GEDK_CASE(w, 4, cl)
+    GEDK_ROW(1, true) GEDK_ROW(2, true) GEDK_ROW(4, true) GEDK_ROW(8, true) GEDK_ROW(16, true)
+    GEDK_ROW(1, false) GEDK_ROW(2, false) GEDK_ROW(4, false) GEDK_ROW(8, false) GEDK_ROW(16, false)
 #undef GEDK_ROW
 #undef GEDK_CASE
     return nullptr;
@@ -492,19 +609,25 @@ const void *select_kernel(int W, int PL) {
 
 }  // namespace
 
+int block_slot_stride(int K) {
+    if (K <= 64) return 64;
+    if (K <= 128) return 128;
+    return (K + kBlockThreads - 1) / kBlockThreads * kBlockThreads;
+}
+
 size_t block_workspace_bytes(const BlockShape &s) { return layout_for(s).stride; }
 
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
-    const void *k = select_kernel(s.W, s.PL);
+    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s));
     if (!k) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, BT, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, BT, dyn_lds_bytes(s));
 }
 
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
                         int *queue, Costs c, int K, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_kernel(s.W, s.PL);
-    if (!k || grid <= 0) return hipErrorInvalidValue;
+    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s));
+    if (!k || grid <= 0 || s.KS != block_slot_stride(K)) return hipErrorInvalidValue;
     BlockArgs a;
     a.src = src;
     a.dst = dst;
@@ -514,12 +637,15 @@ hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &ds
     a.c = c;
     a.K = K;
     a.KS = s.KS;
+    a.TPS = s.KS >= BT ? 1 : BT / s.KS;
+    a.rows_words = rows_words(s);
+    a.planes_lds = planes_in_lds(s) ? 1 : 0;
     a.ws = static_cast<char *>(workspace);
     a.L = layout_for(s);
     if (a.L.stride != ws_stride) return hipErrorInvalidValue;
     a.out = out;
     void *args[] = {&a};
-    return hipLaunchKernel(k, dim3(grid), dim3(BT), args, 0, stream);
+    return hipLaunchKernel(k, dim3(grid), dim3(BT), args, dyn_lds_bytes(s), stream);
 }
 
 hipError_t launch_fill_zero(int *p, int count, hipStream_t stream) {
