@@ -2,40 +2,50 @@
 //
 // Handles pairs with n1 <= 32, n2 <= 32 and K <= 64: one 64-lane wavefront
 // owns one pair for all its levels and pulls the next pair from a work queue
-// (persistent launch, one wave per workgroup so a barrier is one s_barrier).
-// Lane s holds beam slot s in registers: partial edit distance, the image
-// Img (one 32-bit word: bit u set iff g2 vertex u is used) and e_in (g2
-// edges inside Img).  Lane u also holds g2's adjacency row N2(u), its label
-// and its label-plane rows, and lane v holds g1's row N1(v).  The mapping
-// phi of each slot lives in LDS, one byte per g1 vertex (0xff = deleted).
+// (persistent launch, one wave per workgroup).  Lane s holds beam slot s in
+// registers: partial edit distance, the image Img (one 32-bit word: bit u
+// set iff g2 vertex u is used), e_in (g2 edges inside Img) and the mapping
+// phi as eight words of bytes (byte j = image of g1 vertex j, 0xff =
+// deleted).  Lane u also holds g2's adjacency row N2(u), its label, its
+// label-plane rows and edel * deg(u); lane v holds g1's row N1(v).
 //
 // Per level i (Alg. 1), with P = earlier neighbours of v_i:
-//   expand   Phi = {phi(j) : j in P, not deleted}; for every g2 vertex u
-//            (a compile-time unrolled loop; N2(u) broadcast from lane u):
-//              PED' = PED + [alpha1(v_i) != alpha2(u)] vsub + edel (|P| - kept)
-//                     + eins (|Img & N2(u)| - kept) + esub relabelled,
-//              kept = |Phi & N2(u)|  (implied edge operations, Sec. 2.3);
-//            the deletion child costs PED + vdel + edel |P|.  Children held
-//            as unsigned values; an invalid child (u used, u >= n2, or an
-//            empty slot) is 0xffffffff, obtained by OR-ing the sign-extended
-//            bit u of (Img | invalid-u mask).
-//   select   T = K-th smallest PED by counting probes: count(PED <= t) is a
-//            sum of popcounts of wave ballots, galloping then bisection from
-//            the wave minimum.  Every child below T survives and the first
-//            (K - #below) children equal to T in generation order (lane
-//            order, then u, then the deletion), via per-lane bit masks and
-//            ballot/mbcnt exclusive scans; survivor (parent, u) pairs are
+//   expand   Phi = {phi(j) : j in P, not deleted} and A = Img \ Phi.  Since
+//            Phi is a subset of Img, the implied edge operations of Sec. 2.3
+//            for the child (v_i -> u) are
+//              deleted  = |P| - |Phi & N2(u)| = |P| - deg(u) + |~Phi & N2(u)|
+//              inserted = |Img & N2(u)| - |Phi & N2(u)| = |A & N2(u)|
+//            so PED' = (PED + edel |P|) + S(u) + edel |~Phi & N2(u)|
+//                      + eins |A & N2(u)| [+ esub |Phi & N2(u) & relabelled|]
+//            with S(u) = vsub [alpha1(v_i) != alpha2(u)] - edel deg(u)
+//            computed once per level by lane u.  The deletion child costs
+//            PED + vdel + edel |P|.  An invalid child (u used, u >= n2, or
+//            an empty slot) is 0xffffffff.
+//   select   T = K-th smallest PED.  Children are packed four to a word as
+//            bytes e = min(PED - m0, 127) (m0 = least child), and
+//            count(PED <= m0 + t) for t < 127 is the sum over lanes of
+//            popcount(((t * 0x01010101) | 0x80808080) - packed) & 0x80808080
+//            (each byte's top bit is set iff e <= t; no borrow crosses a
+//            byte).  The smallest t with count >= K is found by galloping
+//            from the previous level's t, then bisection.  When T lies 127
+//            or more above m0 the exact count (wave ballots of full-width
+//            compares) takes over.  Every child below T survives and the
+//            first (K - #below) children equal to T in generation order
+//            (lane order, then u, then the deletion), via per-lane bit masks
+//            and ballot/mbcnt exclusive scans; survivor (parent, u) pairs are
 //            written to LDS in generation order.
-//   update   new slot s reads its (parent, u), copies the parent's phi
-//            words, fetches the parent's registers with ds_bpermute and
-//            recomputes the child's PED from the parent (the same integer
-//            formula, so the value is identical to the candidate's).
+//   update   new slot s reads its (parent, u) and fetches the parent's
+//            registers (PED + edel |P|, ~Phi, A, Img, e_in, the phi words up
+//            to byte i) and lane u's row and S(u) with ds_bpermute, then
+//            recomputes the child's PED with the same integer formula, so the
+//            value is identical to the candidate's.
 // Completion adds vins (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the
 // first lane of least total is the result.
 //
-// SMALL selects 24-bit multiply-adds, valid when every cost is below 2^22
+// SMALL selects 24-bit multiplies, valid when every cost is below 2^22
 // (counts are at most 32, and the plan's overflow bound keeps every sum in
-// range); otherwise full 32-bit multiplies.
+// range); otherwise full 32-bit multiplies.  All sums are taken modulo 2^32;
+// the true values are below 2^31, so they come out exact.
 #include "ged_internal.h"
 
 namespace gedk {
@@ -43,6 +53,7 @@ namespace {
 
 constexpr uint32_t INVALID = 0xffffffffu;
 constexpr uint32_t DEL8 = 0xffu;
+constexpr int TBYTE = 127;        // byte-domain cap: e = min(PED - m0, 127)
 
 struct WaveArgs {
     DbView src;   // graphs edited (g1)
@@ -93,13 +104,24 @@ __device__ __forceinline__ int wave_excl_scan6(int v) {
     return r;
 }
 
-__device__ __forceinline__ uint32_t phi_byte(const uint32_t *plane, int j, int slot) {
-    return (plane[(j >> 2) * 64 + slot] >> ((j & 3) * 8)) & 0xffu;
-}
-
 // bit u of m, sign-extended: 0 or 0xffffffff
 __device__ __forceinline__ uint32_t bit_mask(uint32_t m, int u) {
     return (uint32_t)__builtin_amdgcn_sbfe((int)m, u, 1);
+}
+
+// m1 = 2 m1 + [c1], m2 = 2 m2 + [c2]: each condition's wave mask (one
+// compare into a scalar pair) is the carry-in of one add; both compares are
+// issued before the adds
+__device__ __forceinline__ void shift_in2(uint32_t &m1, bool c1, uint32_t &m2, bool c2) {
+    const unsigned long long b1 = __ballot(c1);
+    const unsigned long long b2 = __ballot(c2);
+    uint32_t r1, r2;
+    unsigned long long co1, co2;
+    asm("v_addc_co_u32 %0, %2, %4, %4, %6\n\tv_addc_co_u32 %1, %3, %5, %5, %7"
+        : "=&v"(r1), "=&v"(r2), "=&s"(co1), "=&s"(co2)
+        : "v"(m1), "v"(m2), "s"(b1), "s"(b2));
+    m1 = r1;
+    m2 = r2;
 }
 
 template <bool SMALL>
@@ -107,17 +129,30 @@ __device__ __forceinline__ uint32_t mul_cost(uint32_t count, uint32_t cost) {
     return SMALL ? __umul24(count, cost) : count * cost;
 }
 
+// count * cost + acc (one v_mad_u32_u24 under SMALL)
+template <bool SMALL>
+__device__ __forceinline__ uint32_t mad_cost(uint32_t count, uint32_t cost, uint32_t acc) {
+    if (SMALL) {
+        uint32_t r;
+        asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(count), "s"(cost), "v"(acc));
+        return r;
+    }
+    return count * cost + acc;
+}
+
+__device__ __forceinline__ uint32_t pack4(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
+    return e0 | (e1 << 8) | (e2 << 16) | (e3 << 24);
+}
+
 template <int PL, bool SMALL>
 __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
-    __shared__ uint32_t s_phi[2][8 * 64];   // [half][word j/4][slot]: bytes of phi
     __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | u (0xff = deletion)
     __shared__ int s_item;
 
     const int lane = threadIdx.x;
     const uint32_t vsub = (uint32_t)a.c.vsub, vdel = (uint32_t)a.c.vdel, vins = (uint32_t)a.c.vins;
     const uint32_t esub = (uint32_t)a.c.esub, edel = (uint32_t)a.c.edel, eins = (uint32_t)a.c.eins;
-    const uint32_t kc = edel + eins;
     const int K = a.K;
     const int P = a.dst.planes;
 
@@ -144,11 +179,15 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             p1[b] = (PL > 0 && b < P && lane < n1) ? A1[(size_t)(1 + b) * n1 + lane] : 0u;
             p2[b] = (PL > 0 && b < P && lane < n2) ? A2[(size_t)(1 + b) * n2 + lane] : 0u;
         }
+        const uint32_t dg2 = mul_cost<SMALL>((uint32_t)__popc(r2), edel);   // lane u: edel deg(u)
         const uint32_t umask = n2 >= 32 ? 0xffffffffu : ((1u << n2) - 1u);
         const int ngroups = (n2 + 3) >> 2;     // u is processed in groups of four
 
         uint32_t ped = 0u, img = 0u, ein = 0u;
-        int nb = 1, cur = 0;
+        uint32_t ph[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) ph[w] = 0u;
+        int nb = 1, hint = 0;
         long long ce = 0;
 
         for (int i = 0; i < n1; ++i) {
@@ -158,9 +197,8 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             uint32_t q[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) q[b] = (uint32_t)__builtin_amdgcn_readlane((int)p1[b], i) & nbm;
-            const uint32_t vsm = (uint32_t)__ballot(l2 != lab1) & umask;
+            const uint32_t su = (l2 != lab1 ? vsub : 0u) - dg2;
             const bool live = lane < nb;
-            const uint32_t *phic = s_phi[cur];
 
             // ---------------- expand and evaluate
             uint32_t phi = 0u, phib[PLA];
@@ -168,14 +206,15 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             for (int b = 0; b < PLA; ++b) phib[b] = 0u;
             for (uint32_t bits = nbm; bits; bits &= bits - 1u) {
                 const int j = __builtin_ctz(bits);
-                const uint32_t x = phi_byte(phic, j, lane);
-                const uint32_t bit = (x != DEL8) ? (1u << (x & 31u)) : 0u;
+                const uint32_t x = __builtin_amdgcn_ubfe(ph[j >> 2], (uint32_t)(j & 3) * 8u, 8u);
+                const uint32_t bit = x < 32u ? (1u << x) : 0u;
                 phi |= bit;
 #pragma unroll
                 for (int b = 0; b < PLA; ++b)
                     if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
             }
-            const uint32_t base = ped + mul_cost<SMALL>(degP, edel);
+            const uint32_t np = ~phi, ai = img & np;
+            const uint32_t basel = ped + mul_cost<SMALL>(degP, edel);
             const uint32_t blocked = live ? (img | ~umask) : 0xffffffffu;
             uint32_t cand[32];
             uint32_t lmin = INVALID;
@@ -185,16 +224,15 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
 #pragma unroll
                     for (int u = 4 * g; u < 4 * g + 4; ++u) {
                         const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r2, u);
-                        const uint32_t vs = ((vsm >> u) & 1u) ? vsub : 0u;
-                        const uint32_t kp = phi & R;
-                        uint32_t d = base + vs + mul_cost<SMALL>((uint32_t)__popc(img & R), eins) -
-                                     mul_cost<SMALL>((uint32_t)__popc(kp), kc);
+                        const uint32_t S = (uint32_t)__builtin_amdgcn_readlane((int)su, u);
+                        uint32_t d = mad_cost<SMALL>((uint32_t)__popc(ai & R), eins,
+                                                     mad_cost<SMALL>((uint32_t)__popc(np & R), edel, basel + S));
                         if (PL > 0) {
                             uint32_t diff = 0u;
 #pragma unroll
                             for (int b = 0; b < PLA; ++b)
                                 diff |= phib[b] ^ (uint32_t)__builtin_amdgcn_readlane((int)p2[b], u);
-                            d += mul_cost<SMALL>((uint32_t)__popc(kp & diff), esub);
+                            d += mul_cost<SMALL>((uint32_t)__popc(phi & R & diff), esub);
                         }
                         d |= bit_mask(blocked, u);
                         cand[u] = d;
@@ -205,7 +243,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     for (int u = 4 * g; u < 4 * g + 4; ++u) cand[u] = INVALID;
                 }
             }
-            const uint32_t cdel = live ? base + vdel : INVALID;
+            const uint32_t cdel = live ? basel + vdel : INVALID;
             lmin = min(lmin, cdel);
             const int V = (int)wave_sum(live ? (uint32_t)(n2 - __popc(img) + 1) : 0u);
             ce += V;
@@ -214,34 +252,105 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             uint32_t T = INVALID;
             const bool trim = V > K;
             if (trim) {
-                auto count_le = [&](uint32_t t) {
-                    int cnt = __popcll(__ballot(cdel <= t));
+                const uint32_t m0 = wave_umin(lmin);
+                uint32_t pk[8];
 #pragma unroll
-                    for (int g = 0; g < 8; ++g) {
-                        if (g < ngroups) {
+                for (int g = 0; g < 8; ++g) {
+                    if (g < ngroups) {
+                        uint32_t e[4];
 #pragma unroll
-                            for (int u = 4 * g; u < 4 * g + 4; ++u) cnt += __popcll(__ballot(cand[u] <= t));
+                        for (int b = 0; b < 4; ++b) e[b] = min(cand[4 * g + b] - m0, (uint32_t)TBYTE);
+                        pk[g] = pack4(e[0], e[1], e[2], e[3]);
+                    } else {
+                        pk[g] = 0x7f7f7f7fu;
+                    }
+                }
+                const uint32_t pkd = 0x7f7f7f00u | min(cdel - m0, (uint32_t)TBYTE);
+                // count(PED <= m0 + t) >= K, for t in [0, 126]
+                auto enough = [&](int t) {
+                    const uint32_t C = ((uint32_t)t * 0x01010101u) | 0x80808080u;
+                    uint32_t cnt = (uint32_t)__popc((C - pkd) & 0x80808080u);
+                    // words past the last group hold 127s and count nothing
+                    switch (ngroups) {
+                    case 8: cnt += (uint32_t)__popc((C - pk[7]) & 0x80808080u); [[fallthrough]];
+                    case 7: cnt += (uint32_t)__popc((C - pk[6]) & 0x80808080u); [[fallthrough]];
+                    case 6: cnt += (uint32_t)__popc((C - pk[5]) & 0x80808080u); [[fallthrough]];
+                    case 5: cnt += (uint32_t)__popc((C - pk[4]) & 0x80808080u); [[fallthrough]];
+                    case 4: cnt += (uint32_t)__popc((C - pk[3]) & 0x80808080u); [[fallthrough]];
+                    case 3: cnt += (uint32_t)__popc((C - pk[2]) & 0x80808080u); [[fallthrough]];
+                    case 2: cnt += (uint32_t)__popc((C - pk[1]) & 0x80808080u); [[fallthrough]];
+                    case 1: cnt += (uint32_t)__popc((C - pk[0]) & 0x80808080u); [[fallthrough]];
+                    default: break;
+                    }
+                    return (int)wave_sum(cnt) >= K;
+                };
+                // smallest t in [lo, hi] with enough(t); hi = 127 stands for
+                // "none below 127"
+                int lo = 0, hi = TBYTE;
+                int t = min(hint, TBYTE - 1);
+                if (enough(t)) {
+                    hi = t;
+                    for (int s = 1; hi > lo; s <<= 1) {
+                        const int x = hi - s;
+                        if (x < lo) break;
+                        if (enough(x)) {
+                            hi = x;
+                        } else {
+                            lo = x + 1;
+                            break;
                         }
                     }
-                    return cnt;
-                };
-                uint32_t lo = wave_umin(lmin), t = lo, step = 1, hi;
-                for (;;) {
-                    if (count_le(t) >= K) {
-                        hi = t;
-                        break;
-                    }
+                } else {
                     lo = t + 1;
-                    // count_le(INVALID - 1) = V > K, so the walk stops by then
-                    t = (t > INVALID - 1u - step) ? INVALID - 1u : t + step;
-                    step = step < (1u << 29) ? step << 1 : step;
+                    for (int s = 1; lo < hi; s <<= 1) {
+                        const int x = min(lo - 1 + s, TBYTE - 1);
+                        if (enough(x)) {
+                            hi = x;
+                            break;
+                        }
+                        lo = x + 1;
+                    }
                 }
                 while (lo < hi) {
-                    const uint32_t mid = lo + ((hi - lo) >> 1);
-                    if (count_le(mid) >= K) hi = mid;
+                    const int mid = (lo + hi) >> 1;
+                    if (enough(mid)) hi = mid;
                     else lo = mid + 1;
                 }
-                T = lo;
+                if (lo < TBYTE) {
+                    T = m0 + (uint32_t)lo;
+                    hint = lo;
+                } else {
+                    // T >= m0 + 127: exact counts on the full values
+                    auto count_le = [&](uint32_t t) {
+                        int cnt = __popcll(__ballot(cdel <= t));
+#pragma unroll
+                        for (int g = 0; g < 8; ++g) {
+                            if (g < ngroups) {
+#pragma unroll
+                                for (int u = 4 * g; u < 4 * g + 4; ++u) cnt += __popcll(__ballot(cand[u] <= t));
+                            }
+                        }
+                        return cnt;
+                    };
+                    uint32_t l2o = m0 + (uint32_t)TBYTE, tt = l2o, step = 1, h2;
+                    for (;;) {
+                        if (count_le(tt) >= K) {
+                            h2 = tt;
+                            break;
+                        }
+                        l2o = tt + 1;
+                        // count_le(INVALID - 1) = V > K, so the walk stops by then
+                        tt = (tt > INVALID - 1u - step) ? INVALID - 1u : tt + step;
+                        step = step < (1u << 29) ? step << 1 : step;
+                    }
+                    while (l2o < h2) {
+                        const uint32_t mid = l2o + ((h2 - l2o) >> 1);
+                        if (count_le(mid) >= K) h2 = mid;
+                        else l2o = mid + 1;
+                    }
+                    T = l2o;
+                    hint = TBYTE - 1;
+                }
             }
 
             // ---------------- survivors in generation order
@@ -252,8 +361,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 if (g < ngroups) {
 #pragma unroll
                     for (int u = 4 * g + 3; u >= 4 * g; --u) {
-                        ltm = ltm + ltm + (cand[u] < T ? 1u : 0u);
-                        lem = lem + lem + (cand[u] <= T ? 1u : 0u);
+                        shift_in2(ltm, cand[u] < T, lem, cand[u] <= T);
                     }
                 }
             }
@@ -275,68 +383,53 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             __syncthreads();
 
             // ---------------- update: child = parent + (v_i -> u)
-            const int nxt = cur ^ 1;
-            uint32_t *phin = s_phi[nxt];
             const bool live2 = lane < nb_new;
             const uint32_t sel = live2 ? s_sel[lane] : 0u;
             const int p = (int)(sel >> 8);
             const uint32_t u = sel & 0xffu;
             const bool sub = u != DEL8;
             const int us = sub ? (int)u : 0;
-            const uint32_t ped_p = (uint32_t)__shfl((int)ped, p);
+            const uint32_t basel_p = (uint32_t)__shfl((int)basel, p);
+            const uint32_t np_p = (uint32_t)__shfl((int)np, p);
+            const uint32_t ai_p = (uint32_t)__shfl((int)ai, p);
             const uint32_t img_p = (uint32_t)__shfl((int)img, p);
             const uint32_t ein_p = (uint32_t)__shfl((int)ein, p);
             const uint32_t R = (uint32_t)__shfl((int)r2, us);
-            const int lab2u = __shfl(l2, us);
-            uint32_t rp[PLA];
+            const uint32_t S = (uint32_t)__shfl((int)su, us);
+            uint32_t rp[PLA], phbp[PLA];
 #pragma unroll
-            for (int b = 0; b < PLA; ++b) rp[b] = PL > 0 ? (uint32_t)__shfl((int)p2[b], us) : 0u;
+            for (int b = 0; b < PLA; ++b) {
+                rp[b] = PL > 0 ? (uint32_t)__shfl((int)p2[b], us) : 0u;
+                phbp[b] = PL > 0 ? (uint32_t)__shfl((int)phib[b], p) : 0u;
+            }
+            const int wl = i >> 2;
+#pragma unroll
+            for (int w = 0; w < 8; ++w)
+                if (w <= wl) ph[w] = (uint32_t)__shfl((int)ph[w], p);
             if (live2) {
-                // copy the parent's phi bytes 0..i-1 and append byte i
-                const int wi_last = i >> 2;
-                for (int jw = 0; jw <= wi_last; ++jw) {
-                    uint32_t wv = phic[jw * 64 + p];
-                    if (jw == wi_last) {
-                        const int sh = (i & 3) * 8;
-                        wv = (wv & ((1u << sh) - 1u)) | (u << sh);
-                    }
-                    phin[jw * 64 + lane] = wv;
-                }
-                uint32_t php = 0u, phbp[PLA];
-#pragma unroll
-                for (int b = 0; b < PLA; ++b) phbp[b] = 0u;
-                for (uint32_t bits = nbm; bits; bits &= bits - 1u) {
-                    const int j = __builtin_ctz(bits);
-                    const uint32_t x = phi_byte(phic, j, p);
-                    const uint32_t bit = (x != DEL8) ? (1u << (x & 31u)) : 0u;
-                    php |= bit;
-#pragma unroll
-                    for (int b = 0; b < PLA; ++b)
-                        if (PL > 0 && ((q[b] >> j) & 1u)) phbp[b] |= bit;
-                }
-                const uint32_t pbase = ped_p + mul_cost<SMALL>(degP, edel);
                 if (sub) {
-                    const uint32_t kp = php & R;
-                    const uint32_t inimg = (uint32_t)__popc(img_p & R);
-                    uint32_t d = pbase + (lab1 != lab2u ? vsub : 0u) + mul_cost<SMALL>(inimg, eins) -
-                                 mul_cost<SMALL>((uint32_t)__popc(kp), kc);
+                    uint32_t d = mad_cost<SMALL>((uint32_t)__popc(ai_p & R), eins,
+                                                 mad_cost<SMALL>((uint32_t)__popc(np_p & R), edel, basel_p + S));
                     if (PL > 0) {
                         uint32_t diff = 0u;
 #pragma unroll
                         for (int b = 0; b < PLA; ++b) diff |= phbp[b] ^ rp[b];
-                        d += mul_cost<SMALL>((uint32_t)__popc(kp & diff), esub);
+                        d += mul_cost<SMALL>((uint32_t)__popc(~np_p & R & diff), esub);
                     }
                     ped = d;
                     img = img_p | (1u << u);
-                    ein = ein_p + inimg;
+                    ein = ein_p + (uint32_t)__popc(img_p & R);
                 } else {
-                    ped = pbase + vdel;
+                    ped = basel_p + vdel;
                     img = img_p;
                     ein = ein_p;
                 }
             }
-            __syncthreads();
-            cur = nxt;
+            // byte i of the mapping
+            const uint32_t sh = (uint32_t)(i & 3) * 8u;
+#pragma unroll
+            for (int w = 0; w < 8; ++w)
+                if (w == wl) ph[w] = (ph[w] & ~(0xffu << sh)) | (u << sh);
             nb = nb_new;
         }
 
@@ -350,8 +443,14 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             a.out.dist[wi.out] = (int)best_total;
             if (a.out.cand) a.out.cand[wi.out] = ce;
         }
+        uint32_t word = 0u;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+            const uint32_t bw = (uint32_t)__builtin_amdgcn_readlane((int)ph[w], best);
+            word = (lane >> 2) == w ? bw : word;
+        }
         if (lane < n1) {
-            const uint32_t x = phi_byte(s_phi[cur], lane, best);
+            const uint32_t x = __builtin_amdgcn_ubfe(word, (uint32_t)(lane & 3) * 8u, 8u);
             a.out.map[wi.map_off + lane] = (x == DEL8) ? -1 : (int)x;
         }
         __syncthreads();
