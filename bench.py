@@ -248,6 +248,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-perpair", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule (no autotuning)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file: reuse its choices, append new ones (default: tune afresh)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -284,6 +287,10 @@ def main():
     dist, maps, cand = plan.outputs(with_cand=True)
     stream = torch.cuda.current_stream()
     plan.set_timing(True)
+    if not args.no_tune:
+        timed = plan.tune(w.costs, dist, maps, stream=stream, cache_path=args.tune_cache)
+        stream.synchronize()
+        log(f"autotuner timed {timed} bin(s)")
 
     bins = plan.bins()
     dominant = max(bins, key=lambda b: b[1])[0] if bins else "none"

@@ -1,12 +1,13 @@
 // kb_block.hip -- workgroup-per-pair K-Best search for gfx950 (any shape up
 // to 512 vertices and K = 1024).
 //
-// One 256-thread workgroup searches one pair at a time and pulls the next
-// pair from a work queue (persistent launch).  Beam slots are spread over
-// the threads: G = min(KS, 256) slots per round, TPS = 256 / G threads per
-// slot (thread t = slot-in-round * TPS + part), each part owning a
-// contiguous range of the slot's children (substitutions by ascending g2
-// vertex, the deletion last), so thread order is generation order.
+// One 256-thread workgroup searches one pair at a time: first the pair at
+// its own index, then further pairs from a work queue (persistent launch).
+// Beam slots are spread over the threads: G = min(KS, 256) slots per round,
+// TPS = 256 / G threads per slot (thread t = slot-in-round * TPS + part),
+// each part owning a contiguous range of the slot's children (substitutions
+// by ascending g2 vertex, the deletion last), so thread order is generation
+// order.
 // Per level i (the loop of Alg. 1, g1 vertex v_i):
 //   expand    every thread builds its slot's Phi = image of v_i's earlier
 //             neighbours (one bit per g2 vertex, one set per edge-label
@@ -185,11 +186,17 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     const Costs c = a.c;
     const int P = a.dst.planes;
 
-    for (;;) {
-        if (t == 0) s_bc[0] = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_bc[0]);
-        __syncthreads();
+    for (bool first = true;; first = false) {
+        // the first pair is the workgroup's own index; later ones come from
+        // the queue (taking every first pair from one shared counter would
+        // serialise the grid's start on one atomic)
+        int item = (int)blockIdx.x;
+        if (!first) {
+            if (t == 0) s_bc[0] = (int)gridDim.x + atomicAdd(a.queue, 1);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_bc[0]);
+            __syncthreads();
+        }
         if (item >= a.nwork) break;
 
         const WorkItem wi = a.work[item];

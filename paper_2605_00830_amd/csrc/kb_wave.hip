@@ -2,32 +2,37 @@
 //
 // Handles pairs with n1 <= 32, n2 <= 32 and K <= 64: one 64-lane wavefront
 // owns one pair for all its levels and pulls the next pair from a work queue
-// (persistent launch, one wave per workgroup).  Lane s holds beam slot s in
+// (persistent launch, one wave per workgroup; the first pair is the
+// workgroup's index).  Lane s holds beam slot s in
 // registers: partial edit distance, the image Img (one 32-bit word: bit u
 // set iff g2 vertex u is used), e_in (g2 edges inside Img) and the mapping
 // phi as eight words of bytes (byte j = image of g1 vertex j, 0xff =
-// deleted).  Lane u also holds g2's adjacency row N2(u), its label, its
-// label-plane rows and edel * deg(u); lane v holds g1's row N1(v).
+// deleted).  Lane u also holds g2's adjacency row N2(u), its label and its
+// label-plane rows; lane v holds g1's row N1(v).
 //
 // Per level i (Alg. 1), with P = earlier neighbours of v_i:
 //   expand   Phi = {phi(j) : j in P, not deleted} and A = Img \ Phi.  Since
 //            Phi is a subset of Img, the implied edge operations of Sec. 2.3
 //            for the child (v_i -> u) are
-//              deleted  = |P| - |Phi & N2(u)| = |P| - deg(u) + |~Phi & N2(u)|
-//              inserted = |Img & N2(u)| - |Phi & N2(u)| = |A & N2(u)|
-//            so PED' = (PED + edel |P|) + S(u) + edel |~Phi & N2(u)|
-//                      + eins |A & N2(u)| [+ esub |Phi & N2(u) & relabelled|]
-//            with S(u) = vsub [alpha1(v_i) != alpha2(u)] - edel deg(u)
-//            computed once per level by lane u.  The deletion child costs
-//            PED + vdel + edel |P|.  An invalid child (u used, u >= n2, or
-//            an empty slot) is 0xffffffff.
+//              kept     = |Phi & N2(u)|
+//              deleted  = |P| - kept
+//              inserted = |Img & N2(u)| - kept = |A & N2(u)|
+//            so PED' = (PED + edel |P|) + vsub [alpha1(v_i) != alpha2(u)]
+//                      + eins |A & N2(u)| - edel |Phi & N2(u)|
+//                      [+ esub |Phi & N2(u) & relabelled|]:
+//            per child one readlane of N2(u), two AND + popcount and two
+//            24-bit multiply-adds (the second with -edel); the label test is
+//            a bit of a wave-uniform mask, handled by the scalar unit.  The
+//            deletion child costs PED + vdel + edel |P|.  An invalid child
+//            (u used, u >= n2, or an empty slot) is 0xffffffff.
 //   select   T = K-th smallest PED.  Children are packed four to a word as
 //            bytes e = min(PED - m0, 127) (m0 = least child), and
 //            count(PED <= m0 + t) for t < 127 is the sum over lanes of
 //            popcount(((t * 0x01010101) | 0x80808080) - packed) & 0x80808080
 //            (each byte's top bit is set iff e <= t; no borrow crosses a
-//            byte).  The smallest t with count >= K is found by galloping
-//            from the previous level's t, then bisection.  When T lies 127
+//            byte).  The smallest t with count >= K is searched two
+//            thresholds per reduction, starting at the previous level's t
+//            (galloping, then thirds).  When T lies 127
 //            or more above m0 the exact count (wave ballots of full-width
 //            compares) takes over.  Every child below T survives and the
 //            first (K - #below) children equal to T in generation order
@@ -35,8 +40,8 @@
 //            and ballot/mbcnt exclusive scans; survivor (parent, u) pairs are
 //            written to LDS in generation order.
 //   update   new slot s reads its (parent, u) and fetches the parent's
-//            registers (PED + edel |P|, ~Phi, A, Img, e_in, the phi words up
-//            to byte i) and lane u's row and S(u) with ds_bpermute, then
+//            registers (PED + edel |P|, Phi, A, Img, e_in, the phi words up
+//            to byte i) and lane u's row with ds_bpermute, then
 //            recomputes the child's PED with the same integer formula, so the
 //            value is identical to the candidate's.
 // Completion adds vins (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the
@@ -140,6 +145,18 @@ __device__ __forceinline__ uint32_t mad_cost(uint32_t count, uint32_t cost, uint
     return count * cost + acc;
 }
 
+// acc - count * cost (one v_mad_i32_i24 with the negated cost under SMALL;
+// modulo 2^32)
+template <bool SMALL>
+__device__ __forceinline__ uint32_t msub_cost(uint32_t count, uint32_t neg_cost, uint32_t acc) {
+    if (SMALL) {
+        uint32_t r;
+        asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(count), "s"(neg_cost), "v"(acc));
+        return r;
+    }
+    return count * neg_cost + acc;
+}
+
 __device__ __forceinline__ uint32_t pack4(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
     return e0 | (e1 << 8) | (e2 << 16) | (e3 << 24);
 }
@@ -153,14 +170,21 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     const int lane = threadIdx.x;
     const uint32_t vsub = (uint32_t)a.c.vsub, vdel = (uint32_t)a.c.vdel, vins = (uint32_t)a.c.vins;
     const uint32_t esub = (uint32_t)a.c.esub, edel = (uint32_t)a.c.edel, eins = (uint32_t)a.c.eins;
+    const uint32_t nedel = 0u - edel;
     const int K = a.K;
     const int P = a.dst.planes;
 
-    for (;;) {
-        if (lane == 0) s_item = atomicAdd(a.queue, 1);
-        __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
+    for (bool first = true;; first = false) {
+        // the first pair is the workgroup's own index; later ones come from
+        // the queue (one shared counter: taking every first pair from it would
+        // serialise the whole grid's start on one atomic)
+        int item = (int)blockIdx.x;
+        if (!first) {
+            if (lane == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
+            __syncthreads();
+            item = __builtin_amdgcn_readfirstlane(s_item);
+            __syncthreads();
+        }
         if (item >= a.nwork) break;
 
         const WorkItem wi = a.work[item];
@@ -179,7 +203,6 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             p1[b] = (PL > 0 && b < P && lane < n1) ? A1[(size_t)(1 + b) * n1 + lane] : 0u;
             p2[b] = (PL > 0 && b < P && lane < n2) ? A2[(size_t)(1 + b) * n2 + lane] : 0u;
         }
-        const uint32_t dg2 = mul_cost<SMALL>((uint32_t)__popc(r2), edel);   // lane u: edel deg(u)
         const uint32_t umask = n2 >= 32 ? 0xffffffffu : ((1u << n2) - 1u);
         const int ngroups = (n2 + 3) >> 2;     // u is processed in groups of four
 
@@ -197,7 +220,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             uint32_t q[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) q[b] = (uint32_t)__builtin_amdgcn_readlane((int)p1[b], i) & nbm;
-            const uint32_t su = (l2 != lab1 ? vsub : 0u) - dg2;
+            const uint32_t vsm = (uint32_t)__ballot(l2 != lab1);   // bit u: labels differ (u < 32)
             const bool live = lane < nb;
 
             // ---------------- expand and evaluate
@@ -213,7 +236,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 for (int b = 0; b < PLA; ++b)
                     if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
             }
-            const uint32_t np = ~phi, ai = img & np;
+            const uint32_t ai = img & ~phi;
             const uint32_t basel = ped + mul_cost<SMALL>(degP, edel);
             const uint32_t blocked = live ? (img | ~umask) : 0xffffffffu;
             uint32_t cand[32];
@@ -224,9 +247,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
 #pragma unroll
                     for (int u = 4 * g; u < 4 * g + 4; ++u) {
                         const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r2, u);
-                        const uint32_t S = (uint32_t)__builtin_amdgcn_readlane((int)su, u);
-                        uint32_t d = mad_cost<SMALL>((uint32_t)__popc(ai & R), eins,
-                                                     mad_cost<SMALL>((uint32_t)__popc(np & R), edel, basel + S));
+                        const uint32_t vs = ((vsm >> u) & 1u) ? vsub : 0u;
+                        uint32_t d = msub_cost<SMALL>((uint32_t)__popc(phi & R), nedel,
+                                                      mad_cost<SMALL>((uint32_t)__popc(ai & R), eins, basel + vs));
                         if (PL > 0) {
                             uint32_t diff = 0u;
 #pragma unroll
@@ -266,55 +289,57 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     }
                 }
                 const uint32_t pkd = 0x7f7f7f00u | min(cdel - m0, (uint32_t)TBYTE);
-                // count(PED <= m0 + t) >= K, for t in [0, 126]
-                auto enough = [&](int t) {
-                    const uint32_t C = ((uint32_t)t * 0x01010101u) | 0x80808080u;
-                    uint32_t cnt = (uint32_t)__popc((C - pkd) & 0x80808080u);
+                // count(PED <= m0 + ta) and count(PED <= m0 + tb), ta, tb in
+                // [0, 126], summed in one reduction (low and high halves)
+                auto counts2 = [&](int ta, int tb) {
+                    const uint32_t Ca = ((uint32_t)ta * 0x01010101u) | 0x80808080u;
+                    const uint32_t Cb = ((uint32_t)tb * 0x01010101u) | 0x80808080u;
+                    uint32_t ca = (uint32_t)__popc((Ca - pkd) & 0x80808080u);
+                    uint32_t cb = (uint32_t)__popc((Cb - pkd) & 0x80808080u);
                     // words past the last group hold 127s and count nothing
+#define GED_PROBE_WORD(g)                                            \
+    ca += (uint32_t)__popc((Ca - pk[g]) & 0x80808080u);              \
+    cb += (uint32_t)__popc((Cb - pk[g]) & 0x80808080u);
                     switch (ngroups) {
-                    case 8: cnt += (uint32_t)__popc((C - pk[7]) & 0x80808080u); [[fallthrough]];
-                    case 7: cnt += (uint32_t)__popc((C - pk[6]) & 0x80808080u); [[fallthrough]];
-                    case 6: cnt += (uint32_t)__popc((C - pk[5]) & 0x80808080u); [[fallthrough]];
-                    case 5: cnt += (uint32_t)__popc((C - pk[4]) & 0x80808080u); [[fallthrough]];
-                    case 4: cnt += (uint32_t)__popc((C - pk[3]) & 0x80808080u); [[fallthrough]];
-                    case 3: cnt += (uint32_t)__popc((C - pk[2]) & 0x80808080u); [[fallthrough]];
-                    case 2: cnt += (uint32_t)__popc((C - pk[1]) & 0x80808080u); [[fallthrough]];
-                    case 1: cnt += (uint32_t)__popc((C - pk[0]) & 0x80808080u); [[fallthrough]];
+                    case 8: GED_PROBE_WORD(7) [[fallthrough]];
+                    case 7: GED_PROBE_WORD(6) [[fallthrough]];
+                    case 6: GED_PROBE_WORD(5) [[fallthrough]];
+                    case 5: GED_PROBE_WORD(4) [[fallthrough]];
+                    case 4: GED_PROBE_WORD(3) [[fallthrough]];
+                    case 3: GED_PROBE_WORD(2) [[fallthrough]];
+                    case 2: GED_PROBE_WORD(1) [[fallthrough]];
+                    case 1: GED_PROBE_WORD(0) [[fallthrough]];
                     default: break;
                     }
-                    return (int)wave_sum(cnt) >= K;
+#undef GED_PROBE_WORD
+                    return wave_sum(ca | (cb << 16));
                 };
-                // smallest t in [lo, hi] with enough(t); hi = 127 stands for
-                // "none below 127"
+                // smallest t in [lo, hi] with count(t) >= K; hi = 127 stands
+                // for "none below 127".  Two thresholds per round: first the
+                // previous level's t and the one below it, then galloping
+                // up (no upper bound yet) or down (no lower bound yet), then
+                // thirds of [lo, hi).
                 int lo = 0, hi = TBYTE;
-                int t = min(hint, TBYTE - 1);
-                if (enough(t)) {
-                    hi = t;
-                    for (int s = 1; hi > lo; s <<= 1) {
-                        const int x = hi - s;
-                        if (x < lo) break;
-                        if (enough(x)) {
-                            hi = x;
-                        } else {
-                            lo = x + 1;
-                            break;
-                        }
+                int ta = max(min(hint, TBYTE - 1) - 1, 0);
+                int tb = min(ta + 1, TBYTE - 1);
+                for (int s = 1;; s <<= 1) {
+                    const uint32_t c2 = counts2(ta, tb);
+                    if ((int)(c2 >> 16) >= K) hi = min(hi, tb);
+                    else lo = max(lo, tb + 1);
+                    if ((int)(c2 & 0xffffu) >= K) hi = min(hi, ta);
+                    else lo = max(lo, ta + 1);
+                    if (lo >= hi) break;
+                    if (hi == TBYTE) {
+                        ta = min(lo + s - 1, TBYTE - 1);
+                        tb = min(lo + 2 * s, TBYTE - 1);
+                    } else if (lo == 0) {
+                        tb = hi - 1;
+                        ta = max(hi - 1 - s, 0);
+                    } else {
+                        const int span = hi - lo;     // probe points lie in [lo, hi - 1]
+                        ta = lo + (span - 1) / 3;
+                        tb = lo + (2 * span - 1) / 3;
                     }
-                } else {
-                    lo = t + 1;
-                    for (int s = 1; lo < hi; s <<= 1) {
-                        const int x = min(lo - 1 + s, TBYTE - 1);
-                        if (enough(x)) {
-                            hi = x;
-                            break;
-                        }
-                        lo = x + 1;
-                    }
-                }
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (enough(mid)) hi = mid;
-                    else lo = mid + 1;
                 }
                 if (lo < TBYTE) {
                     T = m0 + (uint32_t)lo;
@@ -390,12 +415,12 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const bool sub = u != DEL8;
             const int us = sub ? (int)u : 0;
             const uint32_t basel_p = (uint32_t)__shfl((int)basel, p);
-            const uint32_t np_p = (uint32_t)__shfl((int)np, p);
+            const uint32_t phi_p = (uint32_t)__shfl((int)phi, p);
             const uint32_t ai_p = (uint32_t)__shfl((int)ai, p);
             const uint32_t img_p = (uint32_t)__shfl((int)img, p);
             const uint32_t ein_p = (uint32_t)__shfl((int)ein, p);
             const uint32_t R = (uint32_t)__shfl((int)r2, us);
-            const uint32_t S = (uint32_t)__shfl((int)su, us);
+            const uint32_t vs_u = ((vsm >> us) & 1u) ? vsub : 0u;
             uint32_t rp[PLA], phbp[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) {
@@ -408,13 +433,13 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 if (w <= wl) ph[w] = (uint32_t)__shfl((int)ph[w], p);
             if (live2) {
                 if (sub) {
-                    uint32_t d = mad_cost<SMALL>((uint32_t)__popc(ai_p & R), eins,
-                                                 mad_cost<SMALL>((uint32_t)__popc(np_p & R), edel, basel_p + S));
+                    uint32_t d = msub_cost<SMALL>((uint32_t)__popc(phi_p & R), nedel,
+                                                  mad_cost<SMALL>((uint32_t)__popc(ai_p & R), eins, basel_p + vs_u));
                     if (PL > 0) {
                         uint32_t diff = 0u;
 #pragma unroll
                         for (int b = 0; b < PLA; ++b) diff |= phbp[b] ^ rp[b];
-                        d += mul_cost<SMALL>((uint32_t)__popc(~np_p & R & diff), esub);
+                        d += mul_cost<SMALL>((uint32_t)__popc(phi_p & R & diff), esub);
                     }
                     ped = d;
                     img = img_p | (1u << u);

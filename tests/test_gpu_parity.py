@@ -66,6 +66,27 @@ def test_tiny_random_pairs(ged, costs, K, schedule):
     gpu_vs_oracle(ged, graphs, pairs, costs, K, schedule=schedule)
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("costs", [
+    (40, 90, 70, 25, 60, 45),        # thresholds near 127 above the least child: both counting paths
+    (1000, 3000, 2500, 700, 1300, 900),  # thresholds far above it: full-width counts every level
+    (4_194_304, 5_000_011, 4_500_007, 4_300_003, 4_200_001, 4_250_017),  # a cost >= 2^22: 32-bit products
+])
+@pytest.mark.parametrize("K", [16, 64])
+def test_cost_scales(ged, costs, K, schedule):
+    """Small pairs (the wavefront kernel's range) under cost scales that move the K-th
+    smallest PED in and out of the byte-packed window, and past 24-bit products."""
+    gs = []
+    for k in range(36):
+        g = synth.er_graph(61, k, 10, 24, 0.1, 0.3, 4)
+        if k % 3 == 0:
+            g.elabel = (np.arange(g.m) % 3).astype(np.int32)
+        gs.append(g)
+    graphs = GraphSet.from_graphs(gs)
+    pairs = [[2 * k, 2 * k + 1] for k in range(18)] + [[k, (k * 7 + 3) % 36] for k in range(18)]
+    gpu_vs_oracle(ged, graphs, pairs, costs, K, schedule=schedule)
+
+
 def test_identity_is_zero(ged):
     graphs = tiny_set(7, 20, 12, 0.4, 4, 2)
     pairs = [[k, k] for k in range(20)]
