@@ -212,9 +212,11 @@ ged_status ged_plan_replay(ged_plan *plan, void *stream);
  * keeps the fastest; every candidate computes identical results, which are
  * written to the outputs.  With cache_path (may be NULL) the choices are
  * read from / appended to that text file, keyed by device, K and the bin's
- * shape, and a cached choice is applied without timing.  Synchronizes
- * `stream`.  *timed_bins (may be NULL) gets the number of bins that were
- * timed rather than read from the cache.  A captured graph is discarded. */
+ * shape, and a cached choice is applied without timing.  Waits for all
+ * work on the device first (the plan's work lists are rewritten), and
+ * synchronizes `stream`.  *timed_bins (may be NULL) gets the number of bins
+ * that were timed rather than read from the cache.  A captured graph is
+ * discarded. */
 ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
                          void *stream, const char *cache_path, int32_t *timed_bins);
 

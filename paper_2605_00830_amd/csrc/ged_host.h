@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,25 @@ int64_t packed_words(int n, int planes);
 // it, a vertex out of range, a self-loop or a repeated edge is GED_EINVAL.
 ged_status pack_graph(const ged_graph &G, int64_t g, const std::vector<int32_t> &labels, int planes,
                       std::vector<uint32_t> &adj, std::vector<int32_t> &vlab, gedk::GraphRec &R);
+
+// Order the first `grid` items of a longest-first work list (the pairs the
+// workgroups of a persistent launch take statically, workgroup b taking item
+// b) so that the execution units share the work evenly.  A grid that fills
+// the device evenly lands workgroup b on unit b mod `slots` (SIMDs for
+// one-wave workgroups, CUs for workgroups of four waves), so unit u gets
+// items u, u + slots, u + 2 slots, ...; dealing rounds of `slots` items in
+// alternating directions gives each unit long and short pairs alike instead
+// of the longest of every round.  Items past `grid` keep the longest-first
+// order of the dynamic queue.
+template <class T>
+void deal_alternating(std::vector<T> &items, int64_t grid, int64_t slots) {
+    const int64_t n = std::min<int64_t>((int64_t)items.size(), grid);
+    if (slots <= 0) return;
+    for (int64_t r = 1; r * slots < n; r += 2) {
+        const int64_t lo = r * slots, hi = std::min(n, lo + slots);
+        std::reverse(items.begin() + lo, items.begin() + hi);
+    }
+}
 
 }  // namespace gedh
 

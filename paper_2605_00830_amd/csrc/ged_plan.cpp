@@ -34,7 +34,8 @@ struct Bin {
     bool wave_ok = false;        // every pair fits the wavefront kernel
     bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
     gedk::BlockShape shape{};    // workgroup-kernel instantiation and workspace shape
-    std::vector<WorkItem> h_work;
+    std::vector<WorkItem> h_sorted;   // longest first
+    std::vector<WorkItem> h_work;     // launch order for the current grid (deal_alternating)
     WorkItem *d_work = nullptr;
     int *d_queue = nullptr;      // [1 + nwork]: batched counter, then one per pair
     void *d_ws = nullptr;        // workgroup-kernel workspace
@@ -104,7 +105,9 @@ ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
 }
 
 // Point bin `b` at one kernel family and resident-workgroup count
-// (groups_per_cu <= 0: the occupancy limit); grows the workspace as needed.
+// (groups_per_cu <= 0: the occupancy limit); grows the workspace as needed
+// and uploads the work list in the launch order for that grid (blocking
+// copy: no run of the plan may be in flight).
 ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu) {
     if (wave && !b.wave_ok) return fail(GED_EINVAL, "bin does not fit the wavefront kernel");
     const int limit = wave ? b.max_wave_per_cu : b.max_block_per_cu;
@@ -120,6 +123,9 @@ ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu) {
         if (e != hipSuccess) return fail(GED_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
         b.ws_blocks = grid;
     }
+    b.h_work = b.h_sorted;
+    gedh::deal_alternating(b.h_work, grid, wave ? 4 * (int64_t)p->cus : (int64_t)p->cus);
+    GED_HIP(hipMemcpy(b.d_work, b.h_work.data(), sizeof(WorkItem) * (size_t)nwork, hipMemcpyHostToDevice));
     b.wave = wave;
     b.groups_per_cu = gpc;
     b.grid = grid;
@@ -320,6 +326,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             const int64_t cy = (int64_t)db->h_graphs[y.src].n * (db->h_graphs[y.dst].n + 1);
             return cx > cy;
         });
+        b.h_sorted = b.h_work;
         b.shape.KS = gedk::block_slot_stride(K);
         e = gedk::block_max_resident(b.shape, &b.max_block_per_cu);
         if (e == hipSuccess && b.wave_ok) e = gedk::wave_max_resident(b.shape.PL, &b.max_wave_per_cu);
@@ -330,8 +337,6 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const int64_t nwork = (int64_t)b.h_work.size();
         e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * (size_t)nwork);
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * (size_t)(nwork + 1));
-        if (e == hipSuccess)
-            e = hipMemcpy(b.d_work, b.h_work.data(), sizeof(WorkItem) * (size_t)nwork, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             free_plan(p);
             return fail(GED_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
@@ -449,6 +454,8 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     RunCtx r;
     ged_status st = prepare_run(plan, costs, d_dist, d_map, nullptr, stream, &r);
     if (st != GED_OK) return st;
+    // reconfiguring rewrites the plan's work lists: let earlier runs finish
+    GED_HIP(hipDeviceSynchronize());
     drop_graph(plan);
     const std::string dev = device_key();
     std::map<std::string, std::pair<int, int>> cache = read_cache(cache_path);

@@ -220,13 +220,28 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         nmax2[bin] = std::max(nmax2[bin], g2.n);
     }
     int64_t wo = 0;
-    int start[kMaxBins];
+    int start[kMaxBins], grid[kMaxBins];
+    gedk::BlockShape shape[kMaxBins];
+    size_t stride[kMaxBins];
     for (int bin = 0; bin < kMaxBins; ++bin) {
+        const int cnt = (int)bins[bin].size();
+        start[bin] = (int)wo;
+        grid[bin] = 0;
+        if (cnt == 0) continue;
         std::stable_sort(bins[bin].begin(), bins[bin].end(), [&](const WorkItem &x, const WorkItem &y) {
             return (int64_t)b.h_recs[x.src].n * (dbg[(size_t)x.dst].n + 1) >
                    (int64_t)b.h_recs[y.src].n * (dbg[(size_t)y.dst].n + 1);
         });
-        start[bin] = (int)wo;
+        if (bin == 0) {
+            grid[bin] = std::min(cnt, s->wave_per_cu * s->cus);
+        } else {
+            shape[bin] = shape_for(s, 1 << (bin - 1), nmax1[bin], nmax2[bin]);
+            stride[bin] = gedk::block_workspace_bytes(shape[bin]);
+            const int fit = (int)std::min<size_t>(b.ws_bytes / stride[bin], (size_t)std::numeric_limits<int>::max());
+            grid[bin] = std::min({cnt, s->block_per_cu[bin - 1] * s->cus, fit});
+            if (grid[bin] <= 0) return hipErrorOutOfMemory;
+        }
+        gedh::deal_alternating(bins[bin], grid[bin], bin == 0 ? 4 * (int64_t)s->cus : (int64_t)s->cus);
         for (const WorkItem &wi : bins[bin]) b.h_work[wo++] = wi;
     }
     hipError_t e = hipMemcpyAsync(b.d_recs, b.h_recs, sizeof(GraphRec) * (size_t)nq, hipMemcpyHostToDevice, b.stream);
@@ -245,18 +260,11 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         const int cnt = (int)bins[bin].size();
         if (cnt == 0) continue;
         if (bin == 0) {
-            const int grid = std::min(cnt, s->wave_per_cu * s->cus);
-            e = gedk::launch_wave(s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, out, grid,
-                                  b.stream);
+            e = gedk::launch_wave(s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, out,
+                                  grid[bin], b.stream);
         } else {
-            const int W = 1 << (bin - 1);
-            const gedk::BlockShape sh = shape_for(s, W, nmax1[bin], nmax2[bin]);
-            const size_t stride = gedk::block_workspace_bytes(sh);
-            const int fit = (int)std::min<size_t>(b.ws_bytes / stride, (size_t)std::numeric_limits<int>::max());
-            const int grid = std::min({cnt, s->block_per_cu[bin - 1] * s->cus, fit});
-            if (grid <= 0) return hipErrorOutOfMemory;
-            e = gedk::launch_block(sh, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, b.d_ws,
-                                   stride, out, grid, b.stream);
+            e = gedk::launch_block(shape[bin], src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, b.d_ws,
+                                   stride[bin], out, grid[bin], b.stream);
         }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost,
