@@ -6,7 +6,7 @@
 // workgroup's index).  Lane s holds beam slot s in
 // registers: partial edit distance, the image Img (one 32-bit word: bit u
 // set iff g2 vertex u is used), e_in (g2 edges inside Img) and the mapping
-// phi as eight words of bytes (byte j = image of g1 vertex j, 0xff =
+// phi as eight words of bytes (byte v = image of g1 vertex v, 0xff =
 // deleted).  Lane u also holds g2's adjacency row N2(u), its label and its
 // label-plane rows; lane v holds g1's row N1(v).
 //
@@ -19,12 +19,18 @@
 //              inserted = |Img & N2(u)| - kept = |A & N2(u)|
 //            so PED' = (PED + edel |P|) + vsub [alpha1(v_i) != alpha2(u)]
 //                      + eins |A & N2(u)| - edel |Phi & N2(u)|
-//                      [+ esub |Phi & N2(u) & relabelled|]:
-//            per child one readlane of N2(u), two AND + popcount and two
-//            24-bit multiply-adds (the second with -edel); the label test is
-//            a bit of a wave-uniform mask, handled by the scalar unit.  The
-//            deletion child costs PED + vdel + edel |P|.  An invalid child
-//            (u used, u >= n2, or an empty slot) is 0xffffffff.
+//                      [+ esub |Phi & N2(u) & relabelled|].
+//            Child j of a slot substitutes the slot's j-th free g2 vertex
+//            (ascending, so j order is generation order): only free
+//            vertices are visited, found with find-lowest-bit on the free
+//            set, and (N2(u), vsub [labels differ]) comes from a per-level
+//            LDS table.  Once a slot's free set is exhausted the lookup hits
+//            a sentinel entry (empty row, label cost 0xffffffff, added with
+//            unsigned saturation) whose child is 0xffffffff, the invalid
+//            value, so no per-child validity test is needed.
+//            Per child: two AND + popcount and two 24-bit multiply-adds (the
+//            second with -edel).  The deletion child costs PED + vdel +
+//            edel |P|.
 //   select   T = K-th smallest PED.  Children are packed four to a word as
 //            bytes e = min(PED - m0, 127) (m0 = least child), and
 //            count(PED <= m0 + t) for t < 127 is the sum over lanes of
@@ -36,14 +42,15 @@
 //            or more above m0 the exact count (wave ballots of full-width
 //            compares) takes over.  Every child below T survives and the
 //            first (K - #below) children equal to T in generation order
-//            (lane order, then u, then the deletion), via per-lane bit masks
-//            and ballot/mbcnt exclusive scans; survivor (parent, u) pairs are
+//            (lane order, then j, then the deletion), via per-lane bit masks
+//            and ballot/mbcnt exclusive scans; survivor (parent, j) pairs are
 //            written to LDS in generation order.
-//   update   new slot s reads its (parent, u) and fetches the parent's
-//            registers (PED + edel |P|, Phi, A, Img, e_in, the phi words up
-//            to byte i) and lane u's row with ds_bpermute, then
-//            recomputes the child's PED with the same integer formula, so the
-//            value is identical to the candidate's.
+//   update   new slot s reads its (parent, j), fetches the parent's
+//            registers (PED + edel |P|, Phi, A, Img, e_in, the free set, the
+//            phi words up to byte i) with ds_bpermute, finds u as the j-th set
+//            bit of the parent's free set, and recomputes the child's PED
+//            with the same integer formula, so the value is identical to the
+//            candidate's.
 // Completion adds vins (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the
 // first lane of least total is the result.
 //
@@ -101,17 +108,36 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
+    v = max(v, dpp_ror<0x121>(v));
+    v = max(v, dpp_ror<0x122>(v));
+    v = max(v, dpp_ror<0x124>(v));
+    v = max(v, dpp_ror<0x128>(v));
+    const uint32_t a = max((uint32_t)__builtin_amdgcn_readlane((int)v, 0), (uint32_t)__builtin_amdgcn_readlane((int)v, 16));
+    const uint32_t b = max((uint32_t)__builtin_amdgcn_readlane((int)v, 32), (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
+    return max(a, b);
+}
+
+// Position of the k-th (0-based) set bit of x; k < popcount(x).
+__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k) {
+    uint32_t pos = 0u;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const uint32_t c = (uint32_t)__popc(x & ((1u << w) - 1u));
+        const bool up = k >= c;
+        k = up ? k - c : k;
+        x = up ? x >> w : x;
+        pos = up ? pos + (uint32_t)w : pos;
+    }
+    return pos;
+}
+
 // Exclusive prefix sum over lanes of v in [0, 63], bit-sliced with ballots.
 __device__ __forceinline__ int wave_excl_scan6(int v) {
     int r = 0;
 #pragma unroll
     for (int b = 0; b < 6; ++b) r += lanes_below(__ballot((v >> b) & 1)) << b;
     return r;
-}
-
-// bit u of m, sign-extended: 0 or 0xffffffff
-__device__ __forceinline__ uint32_t bit_mask(uint32_t m, int u) {
-    return (uint32_t)__builtin_amdgcn_sbfe((int)m, u, 1);
 }
 
 // m1 = 2 m1 + [c1], m2 = 2 m2 + [c2]: each condition's wave mask (one
@@ -164,7 +190,9 @@ __device__ __forceinline__ uint32_t pack4(uint32_t e0, uint32_t e1, uint32_t e2,
 template <int PL, bool SMALL>
 __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
-    __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | u (0xff = deletion)
+    __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
+    __shared__ uint2 s_tab[33];             // per level: (N2(u), vsub [labels differ]); [32] = sentinel
+    __shared__ uint32_t s_pl[PLA][33];      // label-plane rows of g2; [32] = 0
     __shared__ int s_item;
 
     const int lane = threadIdx.x;
@@ -204,7 +232,10 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             p2[b] = (PL > 0 && b < P && lane < n2) ? A2[(size_t)(1 + b) * n2 + lane] : 0u;
         }
         const uint32_t umask = n2 >= 32 ? 0xffffffffu : ((1u << n2) - 1u);
-        const int ngroups = (n2 + 3) >> 2;     // u is processed in groups of four
+        if (PL > 0 && lane <= 32) {
+#pragma unroll
+            for (int b = 0; b < PLA; ++b) s_pl[b][lane] = p2[b];
+        }
 
         uint32_t ped = 0u, img = 0u, ein = 0u;
         uint32_t ph[8];
@@ -220,8 +251,12 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             uint32_t q[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) q[b] = (uint32_t)__builtin_amdgcn_readlane((int)p1[b], i) & nbm;
-            const uint32_t vsm = (uint32_t)__ballot(l2 != lab1);   // bit u: labels differ (u < 32)
             const bool live = lane < nb;
+            // lane u: (N2(u), label cost); entry 32 is the sentinel of an
+            // exhausted free set: an empty row and a label cost of
+            // 0xffffffff, which the saturating add below turns into an
+            // invalid child
+            if (lane <= 32) s_tab[lane] = lane < 32 ? make_uint2(r2, l2 != lab1 ? vsub : 0u) : make_uint2(0u, INVALID);
 
             // ---------------- expand and evaluate
             uint32_t phi = 0u, phib[PLA];
@@ -237,38 +272,47 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
             }
             const uint32_t ai = img & ~phi;
-            const uint32_t basel = ped + mul_cost<SMALL>(degP, edel);
-            const uint32_t blocked = live ? (img | ~umask) : 0xffffffffu;
+            const uint32_t basel = live ? ped + mul_cost<SMALL>(degP, edel) : 0u;
+            // child j of a slot substitutes its j-th free g2 vertex (free
+            // vertices in ascending order: generation order)
+            const uint32_t free = live ? (~img & umask) : 0u;
+            const uint32_t nfree = (uint32_t)__popc(free);
+            const int ngroups = (int)(wave_umax(nfree) + 3u) >> 2;   // children in groups of four
+            __syncthreads();
             uint32_t cand[32];
             uint32_t lmin = INVALID;
+            uint32_t fr = free;
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
                 if (g < ngroups) {
 #pragma unroll
-                    for (int u = 4 * g; u < 4 * g + 4; ++u) {
-                        const uint32_t R = (uint32_t)__builtin_amdgcn_readlane((int)r2, u);
-                        const uint32_t vs = ((vsm >> u) & 1u) ? vsub : 0u;
+                    for (int j = 4 * g; j < 4 * g + 4; ++j) {
+                        const uint32_t u = (uint32_t)__builtin_ctzg(fr, 32);   // 32 once exhausted
+                        fr &= fr - 1u;
+                        const uint2 t = s_tab[u];
+                        const uint32_t R = t.x;
+                        // PED + label cost saturates only for the sentinel; its
+                        // empty row keeps the edge terms at zero
                         uint32_t d = msub_cost<SMALL>((uint32_t)__popc(phi & R), nedel,
-                                                      mad_cost<SMALL>((uint32_t)__popc(ai & R), eins, basel + vs));
+                                                      mad_cost<SMALL>((uint32_t)__popc(ai & R), eins,
+                                                                      __builtin_elementwise_add_sat(basel, t.y)));
                         if (PL > 0) {
                             uint32_t diff = 0u;
 #pragma unroll
-                            for (int b = 0; b < PLA; ++b)
-                                diff |= phib[b] ^ (uint32_t)__builtin_amdgcn_readlane((int)p2[b], u);
+                            for (int b = 0; b < PLA; ++b) diff |= phib[b] ^ s_pl[b][u];
                             d += mul_cost<SMALL>((uint32_t)__popc(phi & R & diff), esub);
                         }
-                        d |= bit_mask(blocked, u);
-                        cand[u] = d;
+                        cand[j] = d;
                         lmin = min(lmin, d);
                     }
                 } else {
 #pragma unroll
-                    for (int u = 4 * g; u < 4 * g + 4; ++u) cand[u] = INVALID;
+                    for (int j = 4 * g; j < 4 * g + 4; ++j) cand[j] = INVALID;
                 }
             }
             const uint32_t cdel = live ? basel + vdel : INVALID;
             lmin = min(lmin, cdel);
-            const int V = (int)wave_sum(live ? (uint32_t)(n2 - __popc(img) + 1) : 0u);
+            const int V = (int)wave_sum(live ? nfree + 1u : 0u);
             ce += V;
 
             // ---------------- threshold T: the K-th smallest PED
@@ -411,20 +455,23 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const bool live2 = lane < nb_new;
             const uint32_t sel = live2 ? s_sel[lane] : 0u;
             const int p = (int)(sel >> 8);
-            const uint32_t u = sel & 0xffu;
-            const bool sub = u != DEL8;
-            const int us = sub ? (int)u : 0;
+            const uint32_t jc = sel & 0xffu;
+            const bool sub = jc != DEL8;
+            const uint32_t free_p = (uint32_t)__shfl((int)free, p);
+            const uint32_t u = sub ? select_bit(free_p, jc) : DEL8;
+            const uint32_t us = sub ? u : 0u;
             const uint32_t basel_p = (uint32_t)__shfl((int)basel, p);
             const uint32_t phi_p = (uint32_t)__shfl((int)phi, p);
             const uint32_t ai_p = (uint32_t)__shfl((int)ai, p);
             const uint32_t img_p = (uint32_t)__shfl((int)img, p);
             const uint32_t ein_p = (uint32_t)__shfl((int)ein, p);
-            const uint32_t R = (uint32_t)__shfl((int)r2, us);
-            const uint32_t vs_u = ((vsm >> us) & 1u) ? vsub : 0u;
+            const uint2 tu = s_tab[us];
+            const uint32_t R = tu.x;
+            const uint32_t vs_u = tu.y;
             uint32_t rp[PLA], phbp[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) {
-                rp[b] = PL > 0 ? (uint32_t)__shfl((int)p2[b], us) : 0u;
+                rp[b] = PL > 0 ? s_pl[b][us] : 0u;
                 phbp[b] = PL > 0 ? (uint32_t)__shfl((int)phib[b], p) : 0u;
             }
             const int wl = i >> 2;
