@@ -262,14 +262,23 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             uint32_t phi = 0u, phib[PLA];
 #pragma unroll
             for (int b = 0; b < PLA; ++b) phib[b] = 0u;
-            for (uint32_t bits = nbm; bits; bits &= bits - 1u) {
-                const int j = __builtin_ctz(bits);
-                const uint32_t x = __builtin_amdgcn_ubfe(ph[j >> 2], (uint32_t)(j & 3) * 8u, 8u);
-                const uint32_t bit = x < 32u ? (1u << x) : 0u;
-                phi |= bit;
+            // word w of phi holds the images of g1 vertices 4w .. 4w+3: the
+            // earlier neighbours are visited word by word (uniform branches,
+            // static register indices)
 #pragma unroll
-                for (int b = 0; b < PLA; ++b)
-                    if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
+            for (int w = 0; w < 8; ++w) {
+                if (((nbm >> (4 * w)) & 0xfu) == 0u) continue;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int j = 4 * w + k;
+                    if (!((nbm >> j) & 1u)) continue;
+                    const uint32_t x = __builtin_amdgcn_ubfe(ph[w], (uint32_t)k * 8u, 8u);
+                    const uint32_t bit = x < 32u ? (1u << x) : 0u;
+                    phi |= bit;
+#pragma unroll
+                    for (int b = 0; b < PLA; ++b)
+                        if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
+                }
             }
             const uint32_t ai = img & ~phi;
             const uint32_t basel = live ? ped + mul_cost<SMALL>(degP, edel) : 0u;
@@ -443,7 +452,13 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             int r = min(max(quota - wave_excl_scan6(eq_l), 0), eq_l);
             uint32_t keepm = ltm;
             bool keepd = ltd;
-            for (uint32_t e = eqm; r > 0 && e; e &= e - 1u, --r) keepm |= e & (0u - e);
+            const int ne = __popc(eqm);
+            if (r >= ne) {             // every tie of the slot is within the quota
+                keepm |= eqm;
+                r -= ne;
+            } else {                   // the slot where the quota ends: its first r ties
+                for (uint32_t e = eqm; r > 0; e &= e - 1u, --r) keepm |= e & (0u - e);
+            }
             if (r > 0 && eqd) keepd = true;
             int pos = wave_excl_scan6(__popc(keepm) + (keepd ? 1 : 0));
             for (uint32_t mk = keepm; mk; mk &= mk - 1u) s_sel[pos++] = ((uint32_t)lane << 8) | (uint32_t)__builtin_ctz(mk);
