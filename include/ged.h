@@ -208,7 +208,8 @@ ged_status ged_plan_replay(ged_plan *plan, void *stream);
 
 /* Autotuner.  For every size bin, times the candidate schedules on the
  * plan's own pairs -- the wavefront kernel where the bin is eligible and
- * the workgroup kernel, each at several resident-workgroup counts -- and
+ * the workgroup kernel with 256- and 512-thread workgroups, each at several
+ * resident-workgroup counts -- and
  * keeps the fastest; every candidate computes identical results, which are
  * written to the outputs.  With cache_path (may be NULL) the choices are
  * read from / appended to that text file, keyed by device, K and the bin's

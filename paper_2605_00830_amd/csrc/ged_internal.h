@@ -51,20 +51,25 @@ struct Outputs {
 };
 
 // Block-per-pair kernel family: any n <= 512, K <= GED_MAX_K; beam state and
-// the candidate matrix live in a per-block global workspace.
+// the candidate matrix live in a per-block global workspace.  Workgroups of
+// 256 threads, or 512 for bins too small to fill the device (two waves per
+// SIMD on one pair instead of one).
 constexpr int kBlockThreads = 256;
+constexpr int kBlockThreadsWide = 512;
 
 struct BlockShape {
     int W;       // words per target row the instantiation handles (1,2,4,8,16)
     int PL;      // label planes the instantiation handles (0,2,4)
-    int KS;      // slot stride: block_slot_stride(K)
+    int KS;      // slot stride: block_slot_stride(K, BT)
     int nmax1;   // largest source order in the bin
     int nmax2;   // largest target order in the bin
+    int BT;      // threads per workgroup: kBlockThreads or kBlockThreadsWide
 };
 
-// Slot stride of the workgroup kernel for beam width K (64, 128, or K
-// rounded up to 256): BlockShape::KS must equal it.
-int block_slot_stride(int K);
+// Slot stride of the workgroup kernel for beam width K and `threads` per
+// workgroup (64, 128, 256, or K rounded up to a multiple of `threads`):
+// BlockShape::KS must equal it.
+int block_slot_stride(int K, int threads);
 size_t block_workspace_bytes(const BlockShape &s);
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu);
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,

@@ -40,12 +40,15 @@ struct Bin {
     int *d_queue = nullptr;      // [1 + nwork]: batched counter, then one per pair
     void *d_ws = nullptr;        // workgroup-kernel workspace
     size_t ws_stride = 0;
-    int ws_blocks = 0;           // workgroups the workspace holds
+    size_t ws_bytes = 0;         // workspace allocation
     int grid = 0;                // current persistent grid
     int groups_per_cu = 0;       // current resident workgroups per CU
     int max_wave_per_cu = 0;     // occupancy limits
-    int max_block_per_cu = 0;
+    int max_block_per_cu[2] = {0, 0};   // workgroups of 256, 512 threads
 };
+
+int bt_index(int threads) { return threads == gedk::kBlockThreadsWide ? 1 : 0; }
+int bt_of(int index) { return index == 1 ? gedk::kBlockThreadsWide : gedk::kBlockThreads; }
 
 }  // namespace
 
@@ -104,24 +107,38 @@ ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
     return ok();
 }
 
-// Point bin `b` at one kernel family and resident-workgroup count
-// (groups_per_cu <= 0: the occupancy limit); grows the workspace as needed
-// and uploads the work list in the launch order for that grid (blocking
-// copy: no run of the plan may be in flight).
-ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu) {
+// Default workgroup size of a workgroup-kernel bin: 512 threads when the
+// bin cannot put two 256-thread workgroups on every CU, so each pair gets
+// two waves per SIMD; otherwise 256.
+int default_threads(const ged_plan *p, const Bin &b) {
+    return (int64_t)b.h_sorted.size() < 2 * (int64_t)p->cus ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
+}
+
+// Point bin `b` at one kernel family, workgroup size (workgroup kernel) and
+// resident-workgroup count (groups_per_cu <= 0: the occupancy limit); grows
+// the workspace as needed and uploads the work list in the launch order for
+// that grid (blocking copy: no run of the plan may be in flight).
+ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu, int threads) {
     if (wave && !b.wave_ok) return fail(GED_EINVAL, "bin does not fit the wavefront kernel");
-    const int limit = wave ? b.max_wave_per_cu : b.max_block_per_cu;
+    if (!wave) {
+        b.shape.BT = threads;
+        b.shape.KS = gedk::block_slot_stride(p->K, threads);
+    }
+    const int limit = wave ? b.max_wave_per_cu : b.max_block_per_cu[bt_index(threads)];
     const int gpc = groups_per_cu > 0 ? std::min(groups_per_cu, limit) : limit;
     const int64_t nwork = (int64_t)b.h_work.size();
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nwork, (int64_t)gpc * p->cus));
-    if (!wave && b.ws_blocks < grid) {
-        if (b.d_ws) GED_HIP(hipFree(b.d_ws));
-        b.d_ws = nullptr;
-        b.ws_blocks = 0;
+    if (!wave) {
         b.ws_stride = gedk::block_workspace_bytes(b.shape);
-        hipError_t e = hipMalloc(&b.d_ws, b.ws_stride * (size_t)grid);
-        if (e != hipSuccess) return fail(GED_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
-        b.ws_blocks = grid;
+        const size_t need = b.ws_stride * (size_t)grid;
+        if (b.ws_bytes < need) {
+            if (b.d_ws) GED_HIP(hipFree(b.d_ws));
+            b.d_ws = nullptr;
+            b.ws_bytes = 0;
+            hipError_t e = hipMalloc(&b.d_ws, need);
+            if (e != hipSuccess) return fail(GED_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
+            b.ws_bytes = need;
+        }
     }
     b.h_work = b.h_sorted;
     gedh::deal_alternating(b.h_work, grid, wave ? 4 * (int64_t)p->cus : (int64_t)p->cus);
@@ -223,15 +240,25 @@ std::string bin_key(const std::string &dev, int K, const Bin &b) {
     return buf;
 }
 
-// cache lines: "<key> <wave 0|1> <groups_per_cu>"
-std::map<std::string, std::pair<int, int>> read_cache(const char *path) {
-    std::map<std::string, std::pair<int, int>> m;
+struct Choice {
+    bool wave;
+    int groups_per_cu;
+    int threads;
+};
+
+// cache lines: "<key> <wave 0|1> <groups_per_cu> <threads>"
+std::map<std::string, Choice> read_cache(const char *path) {
+    std::map<std::string, Choice> m;
     if (!path) return m;
     FILE *f = fopen(path, "r");
     if (!f) return m;
-    char key[512];
-    int w = 0, g = 0;
-    while (fscanf(f, "%511s %d %d", key, &w, &g) == 3) m[key] = {w, g};
+    char line[768], key[512];
+    while (fgets(line, sizeof line, f)) {
+        int w = 0, g = 0, t = 0;
+        if (sscanf(line, "%511s %d %d %d", key, &w, &g, &t) == 4 &&
+            (t == gedk::kBlockThreads || t == gedk::kBlockThreadsWide))
+            m[key] = Choice{w != 0, g, t};
+    }
     fclose(f);
     return m;
 }
@@ -327,10 +354,15 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             return cx > cy;
         });
         b.h_sorted = b.h_work;
-        b.shape.KS = gedk::block_slot_stride(K);
-        e = gedk::block_max_resident(b.shape, &b.max_block_per_cu);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            gedk::BlockShape sh = b.shape;
+            sh.BT = bt_of(k);
+            sh.KS = gedk::block_slot_stride(K, sh.BT);
+            e = gedk::block_max_resident(sh, &b.max_block_per_cu[k]);
+        }
         if (e == hipSuccess && b.wave_ok) e = gedk::wave_max_resident(b.shape.PL, &b.max_wave_per_cu);
-        if (e != hipSuccess || b.max_block_per_cu <= 0 || (b.wave_ok && b.max_wave_per_cu <= 0)) {
+        if (e != hipSuccess || b.max_block_per_cu[0] <= 0 || b.max_block_per_cu[1] <= 0 ||
+            (b.wave_ok && b.max_wave_per_cu <= 0)) {
             free_plan(p);
             return fail(GED_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
         }
@@ -341,7 +373,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             free_plan(p);
             return fail(GED_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
         }
-        st = configure_bin(p, b, b.wave_ok, opt.groups_per_cu);
+        st = configure_bin(p, b, b.wave_ok, opt.groups_per_cu, default_threads(p, b));
         if (st != GED_OK) {
             free_plan(p);
             return st;
@@ -458,7 +490,7 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     GED_HIP(hipDeviceSynchronize());
     drop_graph(plan);
     const std::string dev = device_key();
-    std::map<std::string, std::pair<int, int>> cache = read_cache(cache_path);
+    std::map<std::string, Choice> cache = read_cache(cache_path);
     FILE *append = nullptr;
     int timed = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -467,26 +499,33 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     for (Bin &b : plan->bins) {
         const std::string key = bin_key(dev, plan->K, b);
         auto hit = cache.find(key);
-        if (hit != cache.end() && (hit->second.first == 0 || b.wave_ok)) {
-            st = configure_bin(plan, b, hit->second.first != 0, hit->second.second);
+        if (hit != cache.end() && (!hit->second.wave || b.wave_ok)) {
+            st = configure_bin(plan, b, hit->second.wave, hit->second.groups_per_cu, hit->second.threads);
             if (st != GED_OK) break;
             continue;
         }
-        // candidates: each kernel family at the occupancy limit and fractions of it
-        std::vector<std::pair<bool, int>> cands;
-        for (int fam = 0; fam < 2; ++fam) {
+        // candidates: the wavefront kernel and the workgroup kernel (256 and
+        // 512 threads), each at the occupancy limit and fractions of it; one
+        // candidate per distinct grid
+        std::vector<Choice> cands;
+        const int64_t nwork = (int64_t)b.h_sorted.size();
+        for (int fam = 0; fam < 3; ++fam) {
             const bool wave = fam == 0;
             if (wave && !b.wave_ok) continue;
-            const int lim = wave ? b.max_wave_per_cu : b.max_block_per_cu;
+            const int threads = fam == 2 ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
+            const int lim = wave ? b.max_wave_per_cu : b.max_block_per_cu[bt_index(threads)];
+            int64_t last_grid = -1;
             for (int g = lim; g >= 1; g = g / 2) {
-                cands.push_back({wave, g});
+                const int64_t grid = std::min<int64_t>(nwork, (int64_t)g * plan->cus);
+                if (grid != last_grid) cands.push_back(Choice{wave, g, threads});
+                last_grid = grid;
                 if (g == 1) break;
             }
         }
         float best_ms = 1e30f;
-        std::pair<bool, int> best = cands.front();
-        for (const auto &cd : cands) {
-            st = configure_bin(plan, b, cd.first, cd.second);
+        Choice best = cands.front();
+        for (const Choice &cd : cands) {
+            st = configure_bin(plan, b, cd.wave, cd.groups_per_cu, cd.threads);
             if (st != GED_OK) break;
             float ms_sum[3] = {0, 0, 0};
             for (int rep = 0; rep < 4 && st == GED_OK; ++rep) {
@@ -516,12 +555,13 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
             }
         }
         if (st != GED_OK) break;
-        st = configure_bin(plan, b, best.first, best.second);
+        st = configure_bin(plan, b, best.wave, best.groups_per_cu, best.threads);
         if (st != GED_OK) break;
         ++timed;
         if (cache_path) {
             if (!append) append = fopen(cache_path, "a");
-            if (append) fprintf(append, "%s %d %d\n", key.c_str(), best.first ? 1 : 0, best.second);
+            if (append)
+                fprintf(append, "%s %d %d %d\n", key.c_str(), best.wave ? 1 : 0, best.groups_per_cu, best.threads);
         }
     }
     if (append) fclose(append);

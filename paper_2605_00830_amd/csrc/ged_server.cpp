@@ -114,7 +114,7 @@ struct ged_server {
     int PL = 0;
     int cus = 0;
     int wave_per_cu = 0;
-    int block_per_cu[5] = {0, 0, 0, 0, 0};             // W = 1, 2, 4, 8, 16
+    int block_per_cu[2][5] = {};   // [256 | 512 threads][W = 1, 2, 4, 8, 16]
     int64_t device_bytes = 0;
     std::vector<Slab> slabs;
 
@@ -150,11 +150,12 @@ int server_class(const ged_server *s, int n1, int n2) {
     return 2;
 }
 
-gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2) {
+gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2, int threads) {
     gedk::BlockShape sh{};
     sh.W = W;
     sh.PL = s->PL;
-    sh.KS = gedk::block_slot_stride(s->cfg.K);
+    sh.BT = threads;
+    sh.KS = gedk::block_slot_stride(s->cfg.K, threads);
     sh.nmax1 = nmax1;
     sh.nmax2 = nmax2;
     return sh;
@@ -235,10 +236,14 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         if (bin == 0) {
             grid[bin] = std::min(cnt, s->wave_per_cu * s->cus);
         } else {
-            shape[bin] = shape_for(s, 1 << (bin - 1), nmax1[bin], nmax2[bin]);
+            // 512-thread workgroups when the bin cannot put two workgroups on
+            // every CU: two waves per SIMD on each pair instead of one
+            const int wide = cnt < 2 * s->cus ? 1 : 0;
+            shape[bin] = shape_for(s, 1 << (bin - 1), nmax1[bin], nmax2[bin],
+                                   wide ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
             stride[bin] = gedk::block_workspace_bytes(shape[bin]);
             const int fit = (int)std::min<size_t>(b.ws_bytes / stride[bin], (size_t)std::numeric_limits<int>::max());
-            grid[bin] = std::min({cnt, s->block_per_cu[bin - 1] * s->cus, fit});
+            grid[bin] = std::min({cnt, s->block_per_cu[wide][bin - 1] * s->cus, fit});
             if (grid[bin] <= 0) return hipErrorOutOfMemory;
         }
         gedh::deal_alternating(bins[bin], grid[bin], bin == 0 ? 4 * (int64_t)s->cus : (int64_t)s->cus);
@@ -433,11 +438,15 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
         for (int k = 0; k < 5 && e == hipSuccess; ++k) {
             const int W = 1 << k;
             if (W > 1 && 16 * W >= max_n[cls]) break;   // W / 2 words already cover the class
-            const gedk::BlockShape sh = shape_for(s, W, max_n[cls], std::min(32 * W, max_n[cls]));
-            e = gedk::block_max_resident(sh, &s->block_per_cu[k]);
-            const int64_t grid = std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->block_per_cu[k] * s->cus);
-            one_block = std::max(one_block, gedk::block_workspace_bytes(sh));
-            ws = std::max(ws, gedk::block_workspace_bytes(sh) * (size_t)grid);
+            for (int wide = 0; wide < 2 && e == hipSuccess; ++wide) {
+                const gedk::BlockShape sh = shape_for(s, W, max_n[cls], std::min(32 * W, max_n[cls]),
+                                                      wide ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
+                e = gedk::block_max_resident(sh, &s->block_per_cu[wide][k]);
+                const int64_t grid =
+                    std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->block_per_cu[wide][k] * s->cus);
+                one_block = std::max(one_block, gedk::block_workspace_bytes(sh));
+                ws = std::max(ws, gedk::block_workspace_bytes(sh) * (size_t)grid);
+            }
         }
         ws = std::min<size_t>(ws, (size_t)std::max<int64_t>(per_stream / 2, 0));
         if (e == hipSuccess && ws < one_block) {

@@ -44,8 +44,6 @@
 namespace gedk {
 namespace {
 
-constexpr int BT = kBlockThreads;
-constexpr int NW = BT / 64;
 constexpr int NBINS = 1024;
 constexpr int SENT = 0x7fffffff;        // invalid child (target vertex already used)
 constexpr uint16_t PHI_DEL = 0xffff;
@@ -96,6 +94,7 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+template <int NW>
 __device__ __forceinline__ int block_min(int v, int *red) {
     v = wave_min(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -107,6 +106,7 @@ __device__ __forceinline__ int block_min(int v, int *red) {
     return r;
 }
 
+template <int NW>
 __device__ __forceinline__ int block_sum(int v, int *red) {
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
@@ -119,6 +119,7 @@ __device__ __forceinline__ int block_sum(int v, int *red) {
 }
 
 // Exclusive scan over threads in index order; *total gets the block sum.
+template <int NW>
 __device__ __forceinline__ int block_excl_scan(int v, int *red, int *total) {
     const int incl = wave_incl_scan(v);
     const int w = threadIdx.x >> 6;
@@ -152,9 +153,10 @@ __device__ __forceinline__ uint32_t below_mask(int i, int kw) {
     return rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
 }
 
-template <int W, int PL, bool CL>
+template <int W, int PL, bool CL, int BT>
 __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
+    constexpr int NW = BT / 64;
     extern __shared__ uint32_t s_dyn[];   // g2 rows, then (CL) the candidate matrix
     __shared__ int s_sel[GED_MAX_K];      // survivor: parent slot << 10 | child (n2 = deletion)
     __shared__ int s_selped[GED_MAX_K];   // survivor partial edit distance
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 if (s < nb && part == 0) lpmin = min(lpmin, pedc[s]);
             }
             for (int b = t; b < NBINS; b += BT) s_hist[b] = 0;
-            const int m0 = block_min(lpmin, s_red);   // also orders the histogram reset and the list
+            const int m0 = block_min<NW>(lpmin, s_red);   // also orders the histogram reset and the list
 
             // ---------------- expand, evaluate, histogram
             int lcnt = 0, ovmin = SENT;
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     else ovmin = min(ovmin, dd);
                 }
             }
-            const int V = block_sum(lcnt, s_red);   // also orders the histogram updates
+            const int V = block_sum<NW>(lcnt, s_red);   // also orders the histogram updates
             ce += V;
             auto cand_at = [&](int s, int u) -> int {
                 return CL ? cand_l[s * CST + u] : cand_g[(size_t)u * KS + s];
@@ -377,7 +379,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             int T = SENT, quota = 0;
             if (V > K) {
                 int lo = m0, below = 0;
-                int nxt = block_min(ovmin, s_red);
+                int nxt = block_min<NW>(ovmin, s_red);
                 for (;;) {
                     if (t < 64) {
                         constexpr int PER = NBINS / 64;
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                             else nn = min(nn, v);
                         }
                     }
-                    nxt = block_min(nn, s_red);   // also orders the histogram writes
+                    nxt = block_min<NW>(nn, s_red);   // also orders the histogram writes
                 }
             }
 
@@ -453,10 +455,10 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     }
                 }
                 int tot;
-                const int EQ = eq_carry + block_excl_scan(eq, s_red, &tot);
+                const int EQ = eq_carry + block_excl_scan<NW>(eq, s_red, &tot);
                 eq_carry += tot;
                 const int keep = lt + min(max(quota - EQ, 0), eq);
-                const int OUT = out_carry + block_excl_scan(keep, s_red, &tot);
+                const int OUT = out_carry + block_excl_scan<NW>(keep, s_red, &tot);
                 out_carry += tot;
                 if (live && keep > 0) {
                     int pos = OUT, e = EQ;
@@ -598,17 +600,22 @@ size_t dyn_lds_bytes(const BlockShape &s) {
     return b;
 }
 
-template <int W, int PL, bool CL>
+template <int W, int PL, bool CL, int BT>
 const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL, CL>);
+    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL, CL, BT>);
 }
 
-const void *select_kernel(int W, int PL, bool CL) {
-#define GEDK_CASE(w, pl, cl) \
-    if (W == w && PL == pl && CL == cl) return kernel_ptr<w, pl, cl>();
-#define GEDK_ROW(w, cl) GEDK_CASE(w, 0, cl) GEDK_CASE(w, 2, cl) GEDK_CASE(w, 4, cl)
-    GEDK_ROW(1, true) GEDK_ROW(2, true) GEDK_ROW(4, true) GEDK_ROW(8, true) GEDK_ROW(16, true)
-    GEDK_ROW(1, false) GEDK_ROW(2, false) GEDK_ROW(4, false) GEDK_ROW(8, false) GEDK_ROW(16, false)
+const void *select_kernel(int W, int PL, bool CL, int BT) {
+#define GEDK_CASE(w, pl, cl, bt) \
+    if (W == w && PL == pl && CL == cl && BT == bt) return kernel_ptr<w, pl, cl, bt>();
+#define GEDK_ROW(w, cl, bt) GEDK_CASE(w, 0, cl, bt) GEDK_CASE(w, 2, cl, bt) GEDK_CASE(w, 4, cl, bt)
+#define GEDK_ALL(bt)                                                                              \
+    GEDK_ROW(1, true, bt) GEDK_ROW(2, true, bt) GEDK_ROW(4, true, bt) GEDK_ROW(8, true, bt)     \
+    GEDK_ROW(16, true, bt) GEDK_ROW(1, false, bt) GEDK_ROW(2, false, bt) GEDK_ROW(4, false, bt) \
+    GEDK_ROW(8, false, bt) GEDK_ROW(16, false, bt)
+    GEDK_ALL(256)
+    GEDK_ALL(512)
+#undef GEDK_ALL
 #undef GEDK_ROW
 #undef GEDK_CASE
     return nullptr;
@@ -616,25 +623,26 @@ const void *select_kernel(int W, int PL, bool CL) {
 
 }  // namespace
 
-int block_slot_stride(int K) {
+int block_slot_stride(int K, int threads) {
     if (K <= 64) return 64;
     if (K <= 128) return 128;
-    return (K + kBlockThreads - 1) / kBlockThreads * kBlockThreads;
+    if (K <= 256) return 256;
+    return (K + threads - 1) / threads * threads;
 }
 
 size_t block_workspace_bytes(const BlockShape &s) { return layout_for(s).stride; }
 
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
-    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s));
+    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT);
     if (!k) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, BT, dyn_lds_bytes(s));
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, s.BT, dyn_lds_bytes(s));
 }
 
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
                         int *queue, Costs c, int K, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s));
-    if (!k || grid <= 0 || s.KS != block_slot_stride(K)) return hipErrorInvalidValue;
+    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT);
+    if (!k || grid <= 0 || s.KS != block_slot_stride(K, s.BT)) return hipErrorInvalidValue;
     BlockArgs a;
     a.src = src;
     a.dst = dst;
@@ -644,7 +652,7 @@ hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &ds
     a.c = c;
     a.K = K;
     a.KS = s.KS;
-    a.TPS = s.KS >= BT ? 1 : BT / s.KS;
+    a.TPS = s.KS >= s.BT ? 1 : s.BT / s.KS;
     a.rows_words = rows_words(s);
     a.planes_lds = planes_in_lds(s) ? 1 : 0;
     a.ws = static_cast<char *>(workspace);
@@ -652,7 +660,7 @@ hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &ds
     if (a.L.stride != ws_stride) return hipErrorInvalidValue;
     a.out = out;
     void *args[] = {&a};
-    return hipLaunchKernel(k, dim3(grid), dim3(BT), args, dyn_lds_bytes(s), stream);
+    return hipLaunchKernel(k, dim3(grid), dim3(s.BT), args, dyn_lds_bytes(s), stream);
 }
 
 hipError_t launch_fill_zero(int *p, int count, hipStream_t stream) {

@@ -103,3 +103,39 @@ def test_tune_keeps_results_and_caches(ged, tmp_path):
     plan.close()
     plan2.close()
     db.close()
+
+
+@pytest.mark.parametrize("K", [64, 600])
+def test_forced_workgroup_sizes_agree(ged, tmp_path, K):
+    """The workgroup kernel at 256 and at 512 threads (and a one-workgroup-per-CU grid),
+    forced through tuning-cache lines, gives the oracle's results; K = 600 makes the slot
+    stride differ between the two sizes (768 and 1024)."""
+    gs = [synth.random_small_graph(77, k, 12, 0.4, 3, 2) for k in range(40)]
+    graphs = GraphSet.from_graphs(gs)
+    pairs = np.array([[2 * k, 2 * k + 1] for k in range(20)], np.int64)
+    costs = (2, 3, 3, 1, 2, 2)
+    d_ref, m_ref, _ = oracle.kbest_pairs(graphs, pairs, costs, K)
+    db = ged.Database(graphs)
+    probe = str(tmp_path / "probe.txt")
+    plan = ged.Plan(db, pairs, K, schedule=ged.SCHED_BLOCK)
+    dist, maps, _ = plan.outputs()
+    plan.tune(costs, dist, maps, cache_path=probe)
+    keys = [line.split()[0] for line in open(probe).read().strip().splitlines()]
+    assert keys
+    plan.close()
+    for threads in (256, 512):
+        for gpc in (1, 2):
+            forced = str(tmp_path / f"forced_{threads}_{gpc}.txt")
+            with open(forced, "w") as f:
+                for k in keys:
+                    f.write(f"{k} 0 {gpc} {threads}\n")
+            print(f"  case: K={K}, threads={threads}, groups_per_cu={gpc}", flush=True)
+            p2 = ged.Plan(db, pairs, K, schedule=ged.SCHED_BLOCK)
+            d2, m2, _ = p2.outputs()
+            assert p2.tune(costs, d2, m2, cache_path=forced) == 0
+            d2.fill_(-7)
+            p2.run(costs, d2, m2)
+            np.testing.assert_array_equal(d2[:len(pairs)].cpu().numpy(), d_ref)
+            np.testing.assert_array_equal(m2[:p2.map_size].cpu().numpy(), m_ref)
+            p2.close()
+    db.close()
