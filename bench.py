@@ -28,6 +28,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "GED pairs/sec at K=64 batched vs per-pair on 1 GPU; serving p50/p99 latency"
+
+# The serving measurement runs SERVE_STREAMS streams per size class.  Streams
+# that share one of the process's hardware queues run one after another (a
+# long large-query launch then blocks the small queries behind it), and HIP's
+# default is 4 queues per process, so the bench asks for enough queues before
+# the runtime starts.
+SERVE_STREAMS = 4
+HW_QUEUES = 16
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < HW_QUEUES:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 # int32 VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, one op per lane per clock
 PEAK_INT32_TOPS = 256 * 64 * 2.4e9 / 1e12
 
@@ -108,7 +118,8 @@ def cpu_oracle(graphs, pairs, costs, K, threads: int):
     return wall, dist, maps
 
 
-def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2000, seed: int = 7):
+def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2000, seed: int = 7,
+                  streams: int = 1):
     """Serving on the mix workload: saturated throughput (closed loop), then
     Poisson arrivals at fractions of it; latency = completion - scheduled
     arrival.  The same loop with one launch per query is the per-pair path."""
@@ -169,15 +180,32 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
             raise err[0]
         return t_sub, t_done
 
-    def latency_stats(t_done, arrivals):
+    # the server's size classes: small (both orders <= 32, K <= 64), medium (<= 128), large
+    n_q = np.asarray(qgs.n, np.int64)
+    n_t = np.asarray(w.graphs.n, np.int64)[targets]
+    n_max = np.maximum(n_q, n_t)
+    cls = np.where((n_max <= 32) & (w.K <= 64), 0, np.where(n_max <= 128, 1, 2))
+
+    def latency_stats(t_done, arrivals, idx=None):
         lat = (t_done - arrivals) / 1e6
-        lat = lat[len(lat) // 100:]          # first 1% is warm-up
-        return {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
-                "p999_ms": round(float(np.percentile(lat, 99.9)), 4), "mean_ms": round(float(lat.mean()), 4)}
+        c = cls[idx] if idx is not None else cls[:len(lat)]
+        skip = len(lat) // 100               # first 1% is warm-up
+        lat, c = lat[skip:], c[skip:]
+        out = {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
+               "p999_ms": round(float(np.percentile(lat, 99.9)), 4), "mean_ms": round(float(lat.mean()), 4)}
+        per = {}
+        for k, name in enumerate(("small", "medium", "large")):
+            x = lat[c == k]
+            if len(x):
+                per[name] = {"queries": int(len(x)), "p50_ms": round(float(np.percentile(x, 50)), 4),
+                             "p99_ms": round(float(np.percentile(x, 99)), 4)}
+        out["by_class"] = per
+        return out
 
     out = {"config": {"workload": w.name, "database_graphs": ndb, "queries": nq, "K": w.K,
-                      "costs": list(w.costs)}}
-    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=1, max_batch=2048, max_inflight=8192)
+                      "costs": list(w.costs), "streams_per_class": streams,
+                      "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}}
+    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=streams, max_batch=2048, max_inflight=8192)
     warm = np.arange(min(2000, nq))
     run(srv, warm)
     idx = np.arange(nq)
@@ -245,6 +273,7 @@ def main():
                     help="queries of the serving measurement (the serving mix has 100,000)")
     ap.add_argument("--serve-db", type=int, default=100000, help="database graphs of the serving measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS, help="server streams per size class")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-perpair", action="store_true")
@@ -271,7 +300,7 @@ def main():
         t0 = time.perf_counter()
         sw = synth.serve_mix(args.serve_db, args.serve_queries)
         log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
-        res = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95))
+        res = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95), streams=args.serve_streams)
         head = res["open_loop"][1]
         print(json.dumps({
             "metric": METRIC, "value": res["saturated_qps"], "unit": "pairs/s", "n_gpus": 1,
@@ -384,7 +413,7 @@ def main():
         t0 = time.perf_counter()
         sw = synth.serve_mix(args.serve_db, args.serve_queries)
         log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
-        serving = serve_measure(ged, sw, args.serve_queries)
+        serving = serve_measure(ged, sw, args.serve_queries, streams=args.serve_streams)
 
     out = {
         "metric": METRIC,

@@ -264,9 +264,13 @@ typedef struct {
     int32_t max_inflight;     /* queries admitted to the device at once; 0 = 4096 */
     int32_t max_batch;        /* queries per launch; 0 = 1024 */
     int32_t streams;          /* streams per size class (launches of a class that
-                                 may overlap), 1..4; 0 = 1.  Streams beyond the
-                                 device's hardware queues share queues, and a long
-                                 launch then delays the others on its queue. */
+                                 may overlap), 1..4; 0 = 1.  With more than one,
+                                 a class's next batch starts while a slow one
+                                 runs.  Streams beyond the process's hardware
+                                 queues (HIP: GPU_MAX_HW_QUEUES, 4 by default)
+                                 share queues, and a long launch then delays the
+                                 others on its queue: 3 * streams + 1 queues
+                                 keep every stream on its own. */
     int32_t queue_capacity;   /* queued (not yet admitted) queries before
                                  ged_server_submit returns GED_EBUSY; 0 = 1<<20 */
 } ged_server_config;
