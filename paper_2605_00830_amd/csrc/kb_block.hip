@@ -242,6 +242,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             int degP = 0;
             for (int kw = 0; kw * 32 < i; ++kw) degP += __popc(A1[(size_t)i * w1 + kw] & below_mask(i, kw));
             const int del_cost = c.vdel + c.edel * degP;
+            const bool coop = TPS > 1 && degP >= 2 * TPS;   // split the Phi lookups over a slot's parts
             // the earlier neighbours of v_i (the same for every slot), in index
             // order, with their edge-label codes: listed once per level by wave 0
             if (t < 64) {
@@ -293,8 +294,11 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
 #pragma unroll
                     for (int b = 0; b < PLA; ++b) phib[b][k] = 0u;
                 }
+                // with many earlier neighbours the slot's parts split them (each
+                // part looks up every TPS-th one) and OR their sets together:
+                // the parts of a slot are adjacent lanes of one wave
 #pragma unroll 8
-                for (int q = 0; q < degP; ++q) {
+                for (int q = coop ? part : 0; q < degP; q += coop ? TPS : 1) {
                     const int x = phic[(size_t)s_nbr[q] * KS + s];
                     if (x != PHI_DEL) {
                         const uint32_t bit = 1u << (x & 31);
@@ -307,6 +311,17 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
 #pragma unroll
                             for (int b = 0; b < PLA; ++b)
                                 phib[b][k] |= ((code >> b) & 1) ? hit : 0u;
+                        }
+                    }
+                }
+                if (coop) {
+                    for (int o = 1; o < TPS; o <<= 1) {
+#pragma unroll
+                        for (int k = 0; k < W; ++k) {
+                            phi_r[k] |= (uint32_t)__shfl_xor((int)phi_r[k], o);
+#pragma unroll
+                            for (int b = 0; b < PLA; ++b)
+                                if (PL > 0) phib[b][k] |= (uint32_t)__shfl_xor((int)phib[b][k], o);
                         }
                     }
                 }
