@@ -45,12 +45,12 @@
 //            (lane order, then j, then the deletion), via per-lane bit masks
 //            and ballot/mbcnt exclusive scans; survivor (parent, j) pairs are
 //            written to LDS in generation order.
-//   update   new slot s reads its (parent, j), fetches the parent's
-//            registers (PED + edel |P|, Phi, A, Img, e_in, the free set, the
-//            phi words up to byte i) with ds_bpermute, finds u as the j-th set
-//            bit of the parent's free set, and recomputes the child's PED
-//            with the same integer formula, so the value is identical to the
-//            candidate's.
+//   update   new slot s reads its (parent, j) and the parent's child-j
+//            vertex u (recorded in LDS during the expand), fetches the
+//            parent's registers (PED + edel |P|, Phi, A, Img, e_in, the phi
+//            words up to byte i) with ds_bpermute, and recomputes the child's
+//            PED with the same integer formula, so the value is identical to
+//            the candidate's.
 // Completion adds vins (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the
 // first lane of least total is the result.
 //
@@ -104,10 +104,6 @@ __device__ __forceinline__ uint32_t wave_umin(uint32_t v) {
     return min(a, b);
 }
 
-__device__ __forceinline__ int lanes_below(unsigned long long m) {
-    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
-
 __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
     v = max(v, dpp_ror<0x121>(v));
     v = max(v, dpp_ror<0x122>(v));
@@ -118,26 +114,24 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v) {
     return max(a, b);
 }
 
-// Position of the k-th (0-based) set bit of x; k < popcount(x).
-__device__ __forceinline__ uint32_t select_bit(uint32_t x, uint32_t k) {
-    uint32_t pos = 0u;
-#pragma unroll
-    for (int w = 16; w >= 1; w >>= 1) {
-        const uint32_t c = (uint32_t)__popc(x & ((1u << w) - 1u));
-        const bool up = k >= c;
-        k = up ? k - c : k;
-        x = up ? x >> w : x;
-        pos = up ? pos + (uint32_t)w : pos;
-    }
-    return pos;
+// DPP move with out-of-row sources and rows outside ROWS reading 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true);
 }
 
-// Exclusive prefix sum over lanes of v in [0, 63], bit-sliced with ballots.
-__device__ __forceinline__ int wave_excl_scan6(int v) {
-    int r = 0;
-#pragma unroll
-    for (int b = 0; b < 6; ++b) r += lanes_below(__ballot((v >> b) & 1)) << b;
-    return r;
+// Exclusive prefix sum over lanes: shifted adds inside each 16-lane row,
+// then the last lane of row 0 (row 2) is broadcast into row 1 (row 3), and
+// the last lane of row 1 into rows 2 and 3.
+__device__ __forceinline__ int wave_excl_scan(int v) {
+    uint32_t x = (uint32_t)v;
+    x += dpp_zero<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_zero<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_zero<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_zero<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_zero<0x142, 0xa>(x);   // row_bcast:15
+    x += dpp_zero<0x143, 0xc>(x);   // row_bcast:31
+    return (int)x - v;
 }
 
 // m1 = 2 m1 + [c1], m2 = 2 m2 + [c2]: each condition's wave mask (one
@@ -192,6 +186,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
     __shared__ uint2 s_tab[33];             // per level: (N2(u), vsub [labels differ]); [32] = sentinel
+    __shared__ uint32_t s_uv[8][64];        // per level: [j / 4][slot] = g2 vertices of children j, bytes
     __shared__ uint32_t s_pl[PLA][33];      // label-plane rows of g2; [32] = 0
     __shared__ int s_item;
 
@@ -294,10 +289,12 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
                 if (g < ngroups) {
+                    uint32_t uw = 0u;
 #pragma unroll
                     for (int j = 4 * g; j < 4 * g + 4; ++j) {
                         const uint32_t u = (uint32_t)__builtin_ctzg(fr, 32);   // 32 once exhausted
                         fr &= fr - 1u;
+                        uw |= u << (8 * (j & 3));
                         const uint2 t = s_tab[u];
                         const uint32_t R = t.x;
                         // PED + label cost saturates only for the sentinel; its
@@ -314,6 +311,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         cand[j] = d;
                         lmin = min(lmin, d);
                     }
+                    s_uv[g][lane] = uw;
                 } else {
 #pragma unroll
                     for (int j = 4 * g; j < 4 * g + 4; ++j) cand[j] = INVALID;
@@ -449,7 +447,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const int lt_l = __popc(ltm) + (ltd ? 1 : 0);
             const int eq_l = __popc(eqm) + (eqd ? 1 : 0);
             const int quota = trim ? K - (int)wave_sum((uint32_t)lt_l) : 0;
-            int r = min(max(quota - wave_excl_scan6(eq_l), 0), eq_l);
+            int r = min(max(quota - wave_excl_scan(eq_l), 0), eq_l);
             uint32_t keepm = ltm;
             bool keepd = ltd;
             const int ne = __popc(eqm);
@@ -460,7 +458,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 for (uint32_t e = eqm; r > 0; e &= e - 1u, --r) keepm |= e & (0u - e);
             }
             if (r > 0 && eqd) keepd = true;
-            int pos = wave_excl_scan6(__popc(keepm) + (keepd ? 1 : 0));
+            int pos = wave_excl_scan(__popc(keepm) + (keepd ? 1 : 0));
             for (uint32_t mk = keepm; mk; mk &= mk - 1u) s_sel[pos++] = ((uint32_t)lane << 8) | (uint32_t)__builtin_ctz(mk);
             if (keepd) s_sel[pos] = ((uint32_t)lane << 8) | DEL8;
             const int nb_new = min(V, K);
@@ -472,8 +470,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const int p = (int)(sel >> 8);
             const uint32_t jc = sel & 0xffu;
             const bool sub = jc != DEL8;
-            const uint32_t free_p = (uint32_t)__shfl((int)free, p);
-            const uint32_t u = sub ? select_bit(free_p, jc) : DEL8;
+            const uint32_t u = sub ? __builtin_amdgcn_ubfe(s_uv[(jc >> 2) & 7u][p], (jc & 3u) * 8u, 8u) : DEL8;
             const uint32_t us = sub ? u : 0u;
             const uint32_t basel_p = (uint32_t)__shfl((int)basel, p);
             const uint32_t phi_p = (uint32_t)__shfl((int)phi, p);
