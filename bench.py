@@ -83,6 +83,17 @@ def measured_traffic(kernel: str, workload: str):
     return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
@@ -131,11 +142,14 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
     targets = np.ascontiguousarray(w.pairs[:nq, 1])
 
     def run(srv, idx, arrivals=None):
-        """Submit queries idx (at arrivals, monotonic ns, or as fast as possible)."""
+        """Submit queries idx (at arrivals, monotonic ns, or as fast as possible).
+
+        One producer thread submits; the server numbers accepted queries
+        consecutively, so query k of this run has ticket base + k."""
         n = len(idx)
         t_sub = np.zeros(n, np.int64)
         t_done = np.zeros(n, np.int64)
-        pos = {}
+        base = []
         err = []
 
         def producer():
@@ -151,8 +165,8 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
                             continue
                     hi = min(hi, k + 4096)
                     tk = srv.submit_batch(recs[idx[k:hi]], targets[idx[k:hi]])
-                    for j, t in enumerate(tk):
-                        pos[int(t)] = k + j
+                    if len(tk) and not base:
+                        base.append(int(tk[0]) - k)
                     k += len(tk)
                     if len(tk) == 0:
                         time.sleep(1e-4)
@@ -167,13 +181,11 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
             if r is None:
                 continue
             tk, d, times, _ = r
-            for j in range(len(tk)):
-                i = pos.get(int(tk[j]))
-                if i is None:          # collected before the producer recorded it
-                    while int(tk[j]) not in pos:
-                        time.sleep(1e-5)
-                    i = pos[int(tk[j])]
-                t_sub[i], t_done[i] = times[j]
+            while not base:            # collected before the producer recorded the first ticket
+                time.sleep(1e-5)
+            i = tk.astype(np.int64) - base[0]
+            t_sub[i] = times[:, 0]
+            t_done[i] = times[:, 1]
             got += len(tk)
         th.join()
         if err:
@@ -269,7 +281,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch", choices=["batch", "pair", "query", "stress", "serve"])
-    ap.add_argument("--serve-queries", type=int, default=20000,
+    ap.add_argument("--serve-queries", type=int, default=100000,
                     help="queries of the serving measurement (the serving mix has 100,000)")
     ap.add_argument("--serve-db", type=int, default=100000, help="database graphs of the serving measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -368,9 +380,27 @@ def main():
     ops = float(sum(ops_per_candidate(int(x), planes) * int(c) for x, c in zip(words, ce)))
     achieved = ops / (kms / 1e3) / 1e12
     tr = measured_traffic(dominant, w.name) if len(bins) == 1 else None
+    # algorithmic HBM bytes of a launch: both graphs' rows (and label planes)
+    # and vertex labels, two records and a work item per pair in; distance,
+    # mapping and candidate count per pair out
+    gn = np.asarray(w.graphs.n, np.int64)
+    gw = np.maximum((gn + 31) // 32, 1)
+    gbytes = gn * gw * 4 * (1 + planes) + gn * 4 + 32
+    n1 = gn[w.pairs[:, 0]]
+    alg_bytes = float(gbytes[w.pairs[:, 0]].sum() + gbytes[w.pairs[:, 1]].sum() + 24 * P +
+                      (4 + 4 * n1 + 8).sum())
+    hbm_peak = 8.0e12
+    hbm = {"algorithmic_bytes": alg_bytes,
+           "algorithmic_gbps": round(alg_bytes / (kms / 1e3) / 1e9, 2),
+           "algorithmic_frac": round(alg_bytes / (kms / 1e3) / hbm_peak, 6),
+           "peak_gbps": hbm_peak / 1e9}
+    if tr is not None:
+        hbm["measured_gbps"] = round(tr["bytes_per_launch"] / (kms / 1e3) / 1e9, 2)
+        hbm["measured_frac"] = round(tr["bytes_per_launch"] / (kms / 1e3) / hbm_peak, 6)
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 2),
                 "unit": "Tops/s", "frac": round(achieved / PEAK_INT32_TOPS, 5),
                 "traffic": None if tr is None else tr["bytes_per_launch"],
+                "ce_per_s": round(float(ce.sum()) / (kms / 1e3), 1), "hbm": hbm,
                 "kernel": dominant, "kernel_ms": round(kms, 4), "bins": bins,
                 "candidates_per_launch": int(ce.sum()), "ops_per_launch": ops}
 
@@ -397,9 +427,14 @@ def main():
         sample = np.arange(P) if cpu_sample is None else np.arange(min(cpu_sample, P))
         log(f"cpu oracle on {len(sample)} pairs with {threads} threads ...")
         cw, cd, cm = cpu_oracle(w.graphs, w.pairs[sample], w.costs, w.K, threads)
+        # one core on a tenth of the sample (the oracle is single-threaded per pair)
+        one = sample[:max(1, len(sample) // 10)]
+        c1, _, _ = cpu_oracle(w.graphs, w.pairs[one], w.costs, w.K, 1)
         cpu = {"value": round(len(sample) / cw, 2), "unit": "pairs/s", "cores": threads, "kind": "oracle",
                "sample": f"{len(sample)} of {P} pairs of the same workload, {threads} threads, "
-                         f"{cw:.2f} s wall"}
+                         f"{cw:.2f} s wall",
+               "single_core": {"value": round(len(one) / c1, 2), "unit": "pairs/s", "pairs": int(len(one))},
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
         n_src = np.asarray(w.graphs.n, np.int64)[w.pairs[:, 0]]
         moff = np.concatenate([[0], np.cumsum(n_src)])
         g_maps = np.concatenate([gpu_maps[moff[p]:moff[p + 1]] for p in sample]) if len(sample) else gpu_maps[:0]
@@ -413,7 +448,7 @@ def main():
         t0 = time.perf_counter()
         sw = synth.serve_mix(args.serve_db, args.serve_queries)
         log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
-        serving = serve_measure(ged, sw, args.serve_queries, streams=args.serve_streams)
+        serving = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8), streams=args.serve_streams)
 
     out = {
         "metric": METRIC,
