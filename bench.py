@@ -54,7 +54,7 @@ def ops_per_candidate(w: int, planes: int) -> int:
     return 4 * w + lab + 16
 
 
-KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "ged_internal.h"),
+KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "wave_common.h", "ged_internal.h"),
                   "kb_block_kernel": ("kb_block.hip", "ged_internal.h")}
 
 
