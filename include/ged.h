@@ -153,8 +153,9 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
                            ged_plan **out);
 
 /* Kernel schedules.  GED_SCHED_AUTO lets the library choose per size bin:
- * a wavefront per pair (beam in registers) where n1, n2 <= 32 and K <= 64,
- * else a 256-thread workgroup per pair.  GED_SCHED_BLOCK forces the
+ * a wavefront per pair (beam in registers) where n1, n2 <= 64 and K <= 64
+ * (one instantiation for n <= 32, one for n <= 64), else a workgroup per
+ * pair.  GED_SCHED_BLOCK forces the
  * workgroup-per-pair kernel for every pair.  Every schedule computes the
  * same result bit for bit. */
 #define GED_SCHED_AUTO 0
@@ -193,7 +194,8 @@ ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
 /* The plan's size bins, in launch order.  For bin `index`: *kernel is
  * GED_KERNEL_WAVE (a wavefront per pair) or GED_KERNEL_BLOCK (a workgroup
  * per pair), *npairs the pairs in the bin, *grid the persistent launch's
- * workgroups, *words the target-row words the instantiation handles.
+ * workgroups, *words the target-row words the instantiation handles (1
+ * or 2 for the wavefront kernels: n <= 32 or n <= 64).
  * Any output pointer may be NULL. */
 /* HIP graphs.  ged_plan_capture records one ged_plan_run with these costs
  * and outputs into a HIP graph owned by the plan (replacing any previous

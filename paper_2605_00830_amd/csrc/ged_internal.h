@@ -86,4 +86,29 @@ hipError_t wave_max_resident(int PL, int *blocks_per_cu);
 hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue, Costs c,
                        int K, Outputs out, int grid, hipStream_t stream);
 
+// The same scheme for n1, n2 <= 64 (two-word vertex sets, children scored
+// into bytes), K <= 64.
+constexpr int kWave2MaxN = 64;
+
+hipError_t wave2_max_resident(int PL, int *blocks_per_cu);
+hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
+                        Costs c, int K, Outputs out, int grid, hipStream_t stream);
+
+// Wavefront family that fits a pair: 1 (n1, n2 <= 32), 2 (n1, n2 <= 64), 0
+// none (K > 64 or a larger graph).
+inline int wave_words_for(int n1, int n2, int K) {
+    if (K > kWaveMaxK) return 0;
+    const int n = n1 > n2 ? n1 : n2;
+    return n <= kWaveMaxN ? 1 : (n <= kWave2MaxN ? 2 : 0);
+}
+inline hipError_t wave_family_max_resident(int words, int PL, int *blocks_per_cu) {
+    return words == 1 ? wave_max_resident(PL, blocks_per_cu) : wave2_max_resident(PL, blocks_per_cu);
+}
+inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const DbView &dst, const WorkItem *work,
+                                     int nwork, int *queue, Costs c, int K, Outputs out, int grid,
+                                     hipStream_t stream) {
+    return words == 1 ? launch_wave(PL, src, dst, work, nwork, queue, c, K, out, grid, stream)
+                      : launch_wave2(PL, src, dst, work, nwork, queue, c, K, out, grid, stream);
+}
+
 }  // namespace gedk

@@ -32,6 +32,7 @@ int pow2_at_least(int x) {
 // One size bin: pairs sharing a kernel instantiation.
 struct Bin {
     bool wave_ok = false;        // every pair fits the wavefront kernel
+    int wave_words = 0;          // its family: 1 (n <= 32), 2 (n <= 64)
     bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
     gedk::BlockShape shape{};    // workgroup-kernel instantiation and workspace shape
     std::vector<WorkItem> h_sorted;   // longest first
@@ -161,11 +162,12 @@ ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool per
     if (nwork == 0) return ok();
     if (b.wave) {
         if (!perpair) {
-            GED_HIP(gedk::launch_wave(b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, r.o, b.grid, r.s));
+            GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c,
+                                             p->K, r.o, b.grid, r.s));
         } else {
             for (int i = 0; i < nwork; ++i)
-                GED_HIP(gedk::launch_wave(b.shape.PL, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K, r.o,
-                                          1, r.s));
+                GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work + i, 1,
+                                                 b.d_queue + 1 + i, r.c, p->K, r.o, 1, r.s));
         }
     } else if (!perpair) {
         GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, b.d_ws, b.ws_stride,
@@ -235,7 +237,7 @@ std::string bin_key(const std::string &dev, int K, const Bin &b) {
     int lg = 0;
     while ((1ll << (lg + 1)) <= (long long)b.h_work.size()) ++lg;
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|K%d|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, b.wave_ok ? 1 : 0, b.shape.W,
+    snprintf(buf, sizeof buf, "%s|K%d|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, b.wave_ok ? b.wave_words : 0, b.shape.W,
              b.shape.PL, b.shape.nmax1, b.shape.nmax2, lg);
     return buf;
 }
@@ -297,8 +299,9 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     p->pair_n.resize((size_t)npairs);
     p->pair_m.resize((size_t)npairs);
 
-    // bins keyed by kernel: 0 = wavefront kernel, else target row words
-    // rounded up to a power of two (the workgroup kernel's instantiation)
+    // bins keyed by kernel: -1 / -2 = wavefront kernel for n <= 32 / 64,
+    // else target row words rounded up to a power of two (the workgroup
+    // kernel's instantiation)
     const int PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     std::map<int, Bin> bins;
     int64_t off = 0;
@@ -312,12 +315,13 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const GraphRec &g2 = db->h_graphs[(size_t)d];
         p->pair_n[(size_t)i] = (int64_t)g1.n + g2.n;
         p->pair_m[(size_t)i] = (int64_t)g1.m + g2.m;
-        const bool wave_ok = g1.n <= gedk::kWaveMaxN && g2.n <= gedk::kWaveMaxN && K <= gedk::kWaveMaxK;
-        const bool wave = opt.schedule == GED_SCHED_AUTO && wave_ok;
+        const int ww = opt.schedule == GED_SCHED_AUTO ? gedk::wave_words_for(g1.n, g2.n, K) : 0;
+        const bool wave = ww > 0;
         const int W = pow2_at_least(std::max(1, g2.w));
-        Bin &b = bins[wave ? 0 : W];
+        Bin &b = bins[wave ? -ww : W];
         b.wave_ok = wave;
         b.wave = wave;
+        b.wave_words = ww;
         b.shape.W = W;
         b.shape.PL = PL;
         b.shape.nmax1 = std::max(b.shape.nmax1, g1.n);
@@ -345,6 +349,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         p->bins.push_back(Bin());
         Bin &b = p->bins.back();
         b.wave_ok = kv.second.wave_ok;
+        b.wave_words = kv.second.wave_words;
         b.shape = kv.second.shape;
         b.h_work.swap(kv.second.h_work);
         // longest first: work grows with n1 * (n2 + 1)
@@ -360,7 +365,8 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             sh.KS = gedk::block_slot_stride(K, sh.BT);
             e = gedk::block_max_resident(sh, &b.max_block_per_cu[k]);
         }
-        if (e == hipSuccess && b.wave_ok) e = gedk::wave_max_resident(b.shape.PL, &b.max_wave_per_cu);
+        if (e == hipSuccess && b.wave_ok)
+            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, &b.max_wave_per_cu);
         if (e != hipSuccess || b.max_block_per_cu[0] <= 0 || b.max_block_per_cu[1] <= 0 ||
             (b.wave_ok && b.max_wave_per_cu <= 0)) {
             free_plan(p);
@@ -442,7 +448,7 @@ ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kerne
     if (kernel) *kernel = b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK;
     if (npairs) *npairs = (int64_t)b.h_work.size();
     if (grid) *grid = b.grid;
-    if (words) *words = b.wave ? 1 : b.shape.W;
+    if (words) *words = b.wave ? b.wave_words : b.shape.W;
     return ok();
 }
 

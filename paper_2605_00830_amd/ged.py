@@ -289,7 +289,10 @@ class Plan:
             kern, npairs, grid, words = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
             _check(lib.ged_plan_bin_info(self._h, k, ctypes.byref(kern), ctypes.byref(npairs),
                                          ctypes.byref(grid), ctypes.byref(words)))
-            name = "kb_wave_kernel" if kern.value == 0 else "kb_block_kernel"
+            if kern.value == 0:
+                name = "kb_wave_kernel" if words.value == 1 else "kb_wave2_kernel"
+            else:
+                name = "kb_block_kernel"
             out.append((name, int(npairs.value), int(grid.value), int(words.value)))
         return out
 

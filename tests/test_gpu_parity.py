@@ -138,6 +138,50 @@ def test_wave_size_limits(ged, K):
         np.testing.assert_array_equal(res.cand, res2.cand)
 
 
+# the last: vertex costs >= 2^22 (32-bit products); edge costs stay small enough that
+# the complete 64-vertex graph cannot overflow int32
+WAVE64_COSTS = [UNIT, ODD, (40, 90, 70, 25, 60, 45), (1000, 3000, 2500, 700, 1300, 900),
+                (4_194_304, 5_000_011, 4_500_007, 30_011, 20_021, 35_003)]
+
+
+@pytest.mark.parametrize("costs", WAVE64_COSTS)
+@pytest.mark.parametrize("K", [1, 3, 16, 63, 64])
+def test_wave64_range(ged, costs, K):
+    """Pairs of 33..64 vertices (the two-word wavefront kernel): both word boundaries,
+    empty and complete graphs, labelled edges, cost scales that put the K-th smallest
+    child inside the first byte window, past it (bucket passes) and past 24-bit
+    products.  The workgroup kernel must agree on the candidate counts as well."""
+    gs = []
+    for k, (n, p) in enumerate([(64, 0.1), (64, 0.0), (63, 0.3), (33, 0.2), (48, 0.05), (64, 1.0),
+                                (40, 0.15), (57, 0.08), (20, 0.3), (35, 0.5), (1, 0.0)]):
+        g = synth.er_graph(29, k, n, n, p, p, 4)
+        if k % 2 == 0:
+            g.elabel = (np.arange(g.m) % 5).astype(np.int32)
+        gs.append(g)
+    graphs = GraphSet.from_graphs(gs)
+    n = graphs.n
+    pairs = [[a, b] for a in range(len(gs)) for b in range(len(gs)) if max(n[a], n[b]) > 32]
+    db = ged.Database(graphs)
+    plan = ged.Plan(db, pairs, K)
+    kinds = {name for name, *_ in plan.bins()}
+    plan.close()
+    assert kinds == {"kb_wave2_kernel"}, kinds
+    res = gpu_vs_oracle(ged, graphs, pairs, costs, K, db=db, schedule=0)
+    res2 = ged.kbest(db, pairs, costs, K, with_cand=True, schedule=1)
+    db.close()
+    np.testing.assert_array_equal(res.dist, res2.dist)
+    np.testing.assert_array_equal(res.maps, res2.maps)
+    np.testing.assert_array_equal(res.cand, res2.cand)
+
+
+@pytest.mark.parametrize("K", [8, 64])
+def test_query_molecule_wave64(ged, K):
+    """Molecule-like pairs (n 10..70) at K <= 64: the n <= 32, n <= 64 wavefront bins and
+    the workgroup bin for n > 64 in one plan."""
+    w = synth.query_molecule_10_70(200)
+    gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, K)
+
+
 def test_query_molecule_subset(ged):
     w = synth.query_molecule_10_70(120)
     gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K)
