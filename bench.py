@@ -35,7 +35,7 @@ METRIC = "GED pairs/sec at K=64 batched vs per-pair on 1 GPU; serving p50/p99 la
 # default is 4 queues per process, so the bench asks for enough queues before
 # the runtime starts.
 SERVE_STREAMS = 4
-HW_QUEUES = 16
+HW_QUEUES = 4 * SERVE_STREAMS + 1   # four size classes, plus the stream the bench itself uses
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < HW_QUEUES:
     os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 # int32 VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, one op per lane per clock
@@ -55,6 +55,7 @@ def ops_per_candidate(w: int, planes: int) -> int:
 
 
 KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "wave_common.h", "ged_internal.h"),
+                  "kb_wave2_kernel": ("kb_wave2.hip", "wave_common.h", "ged_internal.h"),
                   "kb_block_kernel": ("kb_block.hip", "ged_internal.h")}
 
 
@@ -192,11 +193,13 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
             raise err[0]
         return t_sub, t_done
 
-    # the server's size classes: small (both orders <= 32, K <= 64), medium (<= 128), large
+    # the server's size classes: small (both orders <= 32) and mid (<= 64) for K <= 64,
+    # medium (<= 128), large
     n_q = np.asarray(qgs.n, np.int64)
     n_t = np.asarray(w.graphs.n, np.int64)[targets]
     n_max = np.maximum(n_q, n_t)
-    cls = np.where((n_max <= 32) & (w.K <= 64), 0, np.where(n_max <= 128, 1, 2))
+    wave = w.K <= 64
+    cls = np.where(wave & (n_max <= 32), 0, np.where(wave & (n_max <= 64), 1, np.where(n_max <= 128, 2, 3)))
 
     def latency_stats(t_done, arrivals, idx=None):
         lat = (t_done - arrivals) / 1e6
@@ -206,7 +209,7 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         out = {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
                "p999_ms": round(float(np.percentile(lat, 99.9)), 4), "mean_ms": round(float(lat.mean()), 4)}
         per = {}
-        for k, name in enumerate(("small", "medium", "large")):
+        for k, name in enumerate(("small", "mid", "medium", "large")):
             x = lat[c == k]
             if len(x):
                 per[name] = {"queries": int(len(x)), "p50_ms": round(float(np.percentile(x, 50)), 4),

@@ -243,9 +243,10 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
  * Clients submit queries -- a query graph (host memory, copied and packed
  * with the database's edge-label coding) to be edited into database graph
  * `target_id` -- and poll for results.  Queries are sorted at submission
- * into three size classes with queues and streams of their own: small
- * (n1, n2 <= 32 and K <= 64: the wavefront kernel), medium (n1, n2 <= 128)
- * and large, so a small query never waits for a large one's batch.  A
+ * into four size classes with queues and streams of their own: small
+ * (n1, n2 <= 32) and mid (n1, n2 <= 64), both for K <= 64 (the wavefront
+ * kernels), medium (n1, n2 <= 128) and large, so a small query never waits
+ * for a larger one's batch.  A
  * worker thread owned by the server admits queued queries while device
  * slots and the HBM budget allow, packs them into a batch (query graphs
  * staged into a device arena) and launches the batch on a free stream of
@@ -271,7 +272,7 @@ typedef struct {
                                  runs.  Streams beyond the process's hardware
                                  queues (HIP: GPU_MAX_HW_QUEUES, 4 by default)
                                  share queues, and a long launch then delays the
-                                 others on its queue: 3 * streams + 1 queues
+                                 others on its queue: 4 * streams + 1 queues
                                  keep every stream on its own. */
     int32_t queue_capacity;   /* queued (not yet admitted) queries before
                                  ged_server_submit returns GED_EBUSY; 0 = 1<<20 */

@@ -11,8 +11,8 @@
 //      arena (its share of the HBM budget) have room;
 //   3. launch: the batch's query graphs and work lists are copied to the
 //      device, the work-queue counters cleared by a kernel, the size bins
-//      launched (wavefront kernel for small pairs, workgroup kernel for the
-//      rest), results copied back and an event recorded -- all on that
+//      launched (wavefront kernels for pairs of up to 64 vertices, workgroup
+//      kernel for the rest), results copied back and an event recorded -- all on that
 //      stream, so batches on different streams overlap on the device.
 // A query's search runs entirely inside one kernel launch, so its result
 // does not depend on the other queries of its batch.
@@ -45,7 +45,10 @@ namespace {
 
 enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3, CANCELED = 4 };
 
-constexpr int kClasses = 3;           // small (wavefront kernel), medium (n <= 128), large
+// size classes: small (n <= 32) and mid (n <= 64) for the two wavefront
+// kernels (K <= 64), medium (n <= 128) and large for the workgroup kernel
+constexpr int kClasses = 4;
+constexpr int kFirstBlockClass = 2;
 
 struct Request {
     uint64_t ticket = 0;
@@ -68,7 +71,8 @@ int64_t now_ns() {
 
 using ReqPtr = std::shared_ptr<Request>;
 
-constexpr int kMaxBins = 6;         // wavefront bin + workgroup bins W = 1, 2, 4, 8, 16
+constexpr int kWaveBins = 2;        // wavefront bins: n <= 32, n <= 64
+constexpr int kMaxBins = 7;         // wavefront bins + workgroup bins W = 1, 2, 4, 8, 16
 
 // Device and pinned-host buffers of one stream.
 struct Slab {
@@ -113,7 +117,7 @@ struct ged_server {
     gedk::Costs c{};
     int PL = 0;
     int cus = 0;
-    int wave_per_cu = 0;
+    int wave_per_cu[kWaveBins] = {0, 0};   // n <= 32, n <= 64 kernels
     int block_per_cu[2][5] = {};   // [256 | 512 threads][W = 1, 2, 4, 8, 16]
     int64_t device_bytes = 0;
     std::vector<Slab> slabs;
@@ -141,13 +145,15 @@ int w_index(int W) {
     return k;
 }
 
-// Size class of a pair: 0 = small (wavefront kernel), 1 = medium, 2 = large.
+// Size class of a pair: 0 = small, 1 = mid (the wavefront kernels for
+// n <= 32 and n <= 64), 2 = medium, 3 = large.
 constexpr int kMediumMaxN = 128;
 
 int server_class(const ged_server *s, int n1, int n2) {
-    if (n1 <= gedk::kWaveMaxN && n2 <= gedk::kWaveMaxN && s->cfg.K <= gedk::kWaveMaxK) return 0;
-    if (n1 <= kMediumMaxN && n2 <= kMediumMaxN) return 1;
-    return 2;
+    const int ww = gedk::wave_words_for(n1, n2, s->cfg.K);
+    if (ww > 0) return ww - 1;
+    if (n1 <= kMediumMaxN && n2 <= kMediumMaxN) return 2;
+    return 3;
 }
 
 gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2, int threads) {
@@ -202,14 +208,15 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         vo += (int64_t)r.vlab.size();
         mo += r.n1;
     }
-    // work items by bin: 0 = wavefront kernel, 1 + log2(W) = workgroup kernel
+    // work items by bin: 0, 1 = wavefront kernels (n <= 32, n <= 64),
+    // kWaveBins + log2(W) = workgroup kernel
     std::vector<WorkItem> bins[kMaxBins];
     int nmax1[kMaxBins] = {0}, nmax2[kMaxBins] = {0};
     for (int k = 0; k < nq; ++k) {
         const Request &r = *b.batch[(size_t)k];
         const GraphRec &g2 = dbg[(size_t)r.target];
-        const bool wave = r.n1 <= gedk::kWaveMaxN && g2.n <= gedk::kWaveMaxN && K <= gedk::kWaveMaxK;
-        const int bin = wave ? 0 : 1 + w_index(pow2_at_least(std::max(1, g2.w)));
+        const int ww = gedk::wave_words_for(r.n1, g2.n, K);
+        const int bin = ww > 0 ? ww - 1 : kWaveBins + w_index(pow2_at_least(std::max(1, g2.w)));
         WorkItem wi;
         wi.src = k;
         wi.dst = r.target;
@@ -233,20 +240,20 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
             return (int64_t)b.h_recs[x.src].n * (dbg[(size_t)x.dst].n + 1) >
                    (int64_t)b.h_recs[y.src].n * (dbg[(size_t)y.dst].n + 1);
         });
-        if (bin == 0) {
-            grid[bin] = std::min(cnt, s->wave_per_cu * s->cus);
+        if (bin < kWaveBins) {
+            grid[bin] = std::min(cnt, s->wave_per_cu[bin] * s->cus);
         } else {
             // 512-thread workgroups when the bin cannot put two workgroups on
             // every CU: two waves per SIMD on each pair instead of one
             const int wide = cnt < 2 * s->cus ? 1 : 0;
-            shape[bin] = shape_for(s, 1 << (bin - 1), nmax1[bin], nmax2[bin],
+            shape[bin] = shape_for(s, 1 << (bin - kWaveBins), nmax1[bin], nmax2[bin],
                                    wide ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
             stride[bin] = gedk::block_workspace_bytes(shape[bin]);
             const int fit = (int)std::min<size_t>(b.ws_bytes / stride[bin], (size_t)std::numeric_limits<int>::max());
-            grid[bin] = std::min({cnt, s->block_per_cu[wide][bin - 1] * s->cus, fit});
+            grid[bin] = std::min({cnt, s->block_per_cu[wide][bin - kWaveBins] * s->cus, fit});
             if (grid[bin] <= 0) return hipErrorOutOfMemory;
         }
-        gedh::deal_alternating(bins[bin], grid[bin], bin == 0 ? 4 * (int64_t)s->cus : (int64_t)s->cus);
+        gedh::deal_alternating(bins[bin], grid[bin], bin < kWaveBins ? 4 * (int64_t)s->cus : (int64_t)s->cus);
         for (const WorkItem &wi : bins[bin]) b.h_work[wo++] = wi;
     }
     hipError_t e = hipMemcpyAsync(b.d_recs, b.h_recs, sizeof(GraphRec) * (size_t)nq, hipMemcpyHostToDevice, b.stream);
@@ -264,9 +271,9 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
     for (int bin = 0; bin < kMaxBins && e == hipSuccess; ++bin) {
         const int cnt = (int)bins[bin].size();
         if (cnt == 0) continue;
-        if (bin == 0) {
-            e = gedk::launch_wave(s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, out,
-                                  grid[bin], b.stream);
+        if (bin < kWaveBins) {
+            e = gedk::launch_wave_family(bin + 1, s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K,
+                                         out, grid[bin], b.stream);
         } else {
             e = gedk::launch_block(shape[bin], src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, b.d_ws,
                                    stride[bin], out, grid[bin], b.stream);
@@ -423,17 +430,18 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     s->PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     s->device = db->device;
     hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    const bool small_class = cfg.K <= gedk::kWaveMaxK;
-    if (e == hipSuccess && small_class) e = gedk::wave_max_resident(s->PL, &s->wave_per_cu);
-    const int first_class = small_class ? 0 : 1;
+    const bool wave_classes = cfg.K <= gedk::kWaveMaxK;
+    for (int k = 0; k < kWaveBins && e == hipSuccess && wave_classes; ++k)
+        e = gedk::wave_family_max_resident(k + 1, s->PL, &s->wave_per_cu[k]);
+    const int first_class = wave_classes ? 0 : kFirstBlockClass;
     const int nslabs = (kClasses - first_class) * cfg.streams;
     // every stream gets an equal share of the budget: its class's workspace
     // (at most half of the share; fewer resident workgroups when smaller),
     // then the arena
     const int64_t per_stream = cfg.hbm_budget / nslabs;
-    size_t ws_class[kClasses] = {0, 0, 0};
-    const int max_n[kClasses] = {gedk::kWaveMaxN, kMediumMaxN, GED_MAX_VERTICES};
-    for (int cls = 1; cls < kClasses && e == hipSuccess; ++cls) {
+    size_t ws_class[kClasses] = {0, 0, 0, 0};
+    const int max_n[kClasses] = {gedk::kWaveMaxN, gedk::kWave2MaxN, kMediumMaxN, GED_MAX_VERTICES};
+    for (int cls = kFirstBlockClass; cls < kClasses && e == hipSuccess; ++cls) {
         size_t ws = 0, one_block = 0;
         for (int k = 0; k < 5 && e == hipSuccess; ++k) {
             const int W = 1 << k;
