@@ -55,7 +55,8 @@ extern "C" {
 
 /* Limits of this version. */
 #define GED_MAX_VERTICES 512      /* per graph */
-#define GED_MAX_K 1024            /* beam width */
+#define GED_MAX_K 1024            /* beam width (batched plans, serving) */
+#define GED_MAX_K_WIDE (1 << 21)  /* beam width of the single-pair large-K search */
 #define GED_MAX_EDGE_LABELS 16    /* distinct edge labels in one database */
 
 typedef enum {
@@ -236,6 +237,38 @@ ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_co
 ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs,
                              ged_costs costs, int32_t K, int32_t *d_dist, int32_t *d_map,
                              void *stream);
+
+/* ------------------------------------------------------------------------
+ * Single-pair search at large K (the paper's own regime, Sec. 5: K from
+ * thousands to 1.2 million).  The whole device works on one pair: the beam
+ * lives in device memory, and every level of Alg. 1 is a sequence of
+ * grid-wide kernels -- every child's PED (Sec. 2.3) into a candidate matrix
+ * with a histogram of the PEDs, the K-th smallest child by histogram select
+ * (refined where the PED range needs it), stable compaction of the survivors
+ * in generation order, and the beam update.  The result is the same as the
+ * batched search's (ged_plan_run) at the same K, bit for bit.
+ *
+ * ged_wide_create sizes and allocates the workspace for pair (src, dst) of
+ * `db` at beam width K (1 <= K <= GED_MAX_K_WIDE): about
+ * K * (4 (n2 + 1) + 4 n1 + 24 + 4 w2 (3 + planes)) bytes (w2 = target words
+ * of 32 vertices).  ged_wide_bytes returns what it holds.  ged_wide_run
+ * enqueues the search on `stream` (NULL = the null stream); outputs are
+ * device pointers: d_dist[0] the distance, d_map[0..n1) the target vertex
+ * of each source vertex (-1 = deleted), d_cand[0] (may be NULL) the children
+ * evaluated.  The workspace belongs to the handle, so runs of one handle must
+ * not overlap; different handles are independent.
+ *
+ * Errors: GED_EINVAL (NULL arguments, graph id out of range, K out of range,
+ * negative costs, costs that could overflow int32 on the pair, a device other
+ * than the database's); GED_ENOMEM (workspace); GED_EDEVICE (launch failure).
+ * ---------------------------------------------------------------------- */
+typedef struct ged_wide ged_wide;
+
+ged_status ged_wide_create(ged_db *db, int64_t src, int64_t dst, int32_t K, ged_wide **out);
+ged_status ged_wide_bytes(const ged_wide *w, int64_t *bytes);
+ged_status ged_wide_run(ged_wide *w, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                        void *stream);
+ged_status ged_wide_destroy(ged_wide *w);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop over a device-resident database.

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libged.so")
 
-SOURCES = ["ged_api.cpp", "ged_plan.cpp", "ged_server.cpp", "kb_block.hip", "kb_wave.hip", "kb_wave2.hip"]
+SOURCES = ["ged_api.cpp", "ged_plan.cpp", "ged_server.cpp", "ged_wide.cpp", "kb_block.hip", "kb_wave.hip",
+           "kb_wave2.hip", "kb_wide.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

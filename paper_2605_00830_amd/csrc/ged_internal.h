@@ -94,6 +94,17 @@ hipError_t wave2_max_resident(int PL, int *blocks_per_cu);
 hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                         Costs c, int K, Outputs out, int grid, hipStream_t stream);
 
+// Whole-device search of one pair at large K (kb_wide.hip).
+constexpr int kWideMaxK = GED_MAX_K_WIDE;
+
+size_t wide_workspace_bytes(int n1, int n2, int w2, int planes, int K);
+// Enqueue the search of pair (g1 of src, g2 of dst); `ws` holds at least
+// wide_workspace_bytes bytes; dist[0], map[0..n1), cand[0] (may be null) are
+// device outputs; `cus` sizes the grids.
+hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1, const GraphRec &g2, Costs c, int K,
+                       void *ws, size_t ws_bytes, int32_t *dist, int32_t *map, int64_t *cand, int cus,
+                       hipStream_t stream);
+
 // Wavefront family that fits a pair: 1 (n1, n2 <= 32), 2 (n1, n2 <= 64), 0
 // none (K > 64 or a larger graph).
 inline int wave_words_for(int n1, int n2, int K) {

@@ -1,0 +1,729 @@
+// kb_wide.hip -- the K-Best search (Alg. 1) on ONE pair with the whole
+// device: beam widths from thousands to millions, the regime of the paper's
+// own experiments (Sec. 5: K up to 1.2 million).
+//
+// The beam lives in HBM, structure of arrays with the slot index fastest so
+// that every per-slot access of a workgroup is coalesced:
+//   ped[s], ein[s]        partial edit distance, g2 edges inside Img
+//   img[k][s]             word k of Img (the g2 vertices in use)
+//   phi[j][s]             image of g1 vertex j (uint16, 0xffff = deleted)
+//   sets[b][k][s]         Phi for the current level (b = 0) and its edge-label
+//                         planes Phi_b (b = 1..planes), built by the update
+// ped/ein/img/phi are double-buffered by level parity.  Per level i (g1
+// vertex v_i, in index order):
+//   expand   one thread per parent and one workgroup per (256 parents, range
+//            of target words): every child's PED (Sec. 2.3, implied edge
+//            operations), written to the candidate matrix cand[u][p] (u = n2
+//            is the deletion, 0xffffffff marks a used u), and an LDS
+//            histogram of (PED - m0) >> shift, m0 the least parent PED and
+//            shift chosen so that every child PED of the level fits 4096
+//            bins; the workgroup histograms are summed in HBM.
+//   select   one workgroup: the bin holding the K-th smallest child.  With
+//            shift 0 that bin IS the threshold T; otherwise up to two refine
+//            passes histogram the candidates inside the bin at finer shifts
+//            (12 bits at a time) until the threshold is exact.
+//   count    per parent: children below T and equal to T.
+//   scan     one workgroup: exclusive prefix sums of the per-workgroup counts.
+//   compact  per parent: its survivors in generation order (parent slot, then
+//            target vertex ascending, then the deletion): every child below T,
+//            and ties at T while the quota K - #below lasts, counted from the
+//            first parent on.  Survivors are written as records parent << 10 |
+//            column at their beam position, so the new beam is again in
+//            generation order and never needs sorting.
+//   update   one thread per new slot: PED, Img, e_in and the mapping from its
+//            parent, and the Phi sets of the next level.
+// After the last level, one workgroup completes every leaf (Sec. 4.4.1) and
+// returns the first leaf of least total in beam order.
+#include <algorithm>
+
+#include "ged_internal.h"
+#include "wave_common.h"
+
+namespace gedk {
+namespace {
+
+using namespace wv;
+
+constexpr uint32_t INVALID = 0xffffffffu;
+constexpr uint32_t DEL16 = 0xffffu;
+constexpr int WT = 256;          // threads of the per-parent kernels
+constexpr int NWV = WT / 64;
+constexpr int ST = 1024;         // threads of the single-workgroup kernels
+constexpr int HBITS = 12;
+constexpr int HB = 1 << HBITS;   // histogram bins
+constexpr int CBITS = 10;        // survivor record: parent << CBITS | column
+
+struct LevelState {
+    uint32_t B;       // parents (beam slots) at this level
+    uint32_t m0;      // least parent PED
+    uint32_t mmax;    // largest parent PED
+    uint32_t V;       // valid children of the level
+    uint32_t shift;   // histogram shift of the expansion pass
+    uint32_t T;       // threshold
+    uint32_t quota;   // children equal to T that survive
+    uint32_t refine;  // a refinement pass is pending
+    uint32_t lo;      // refinement range [lo, lo + 2^rwidth)
+    uint32_t rwidth;
+    uint32_t rbin;    // refinement bin shift
+    uint32_t need;    // rank of the threshold inside the refinement range
+    uint32_t pad[4];
+};
+
+struct WideCtx {
+    const uint32_t *a1;   // g1 rows, then its label planes
+    const int32_t *l1;
+    const uint32_t *a2;   // g2 rows, then its label planes
+    const int32_t *l2;
+    int n1, w1, n2, w2, m2, planes;
+    Costs c;
+    uint64_t pedmax;      // vmax n1 + emax (m1 + m2): no PED of the search exceeds it
+    uint32_t K;
+    uint32_t Kp;          // slot stride: K rounded up to WT
+    uint32_t *ped[2];
+    uint32_t *ein[2];
+    uint32_t *img[2];
+    uint16_t *phi[2];
+    uint32_t *sets;
+    uint32_t *cand;
+    uint32_t *cnt;
+    uint32_t *blk;        // [2][Kp / WT]: per-workgroup counts, then their prefix sums
+    uint32_t *rec;
+    uint32_t *hist;
+    LevelState *st;
+    unsigned long long *ce;
+    int32_t *out_dist;
+    int32_t *out_map;
+    int64_t *out_cand;
+};
+
+__device__ __forceinline__ uint32_t sgpr(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// Exclusive prefix sum over a workgroup of NW waves; *total gets the sum.
+template <int NW>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_tmp, uint32_t *total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const uint32_t x = (uint32_t)wave_excl_scan((int)v);
+    if (lane == 63) s_tmp[wid] = x + v;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const uint32_t t = s_tmp[k];
+        pre += k < wid ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x;
+}
+
+// Earlier neighbours of g1 vertex v (bits below `lim`) in word k of its row.
+__device__ __forceinline__ uint32_t earlier_word(const WideCtx &c, int v, int k, int lim) {
+    const uint32_t r = c.a1[(size_t)v * c.w1 + k];
+    const int lo = 32 * k;
+    if (lim >= lo + 32) return r;
+    if (lim <= lo) return 0u;
+    return r & ((1u << (lim - lo)) - 1u);
+}
+
+// ------------------------------------------------------------------ init
+__global__ __launch_bounds__(WT) void wide_init(WideCtx c) {
+    const int t = threadIdx.x;
+    for (int l = t; l <= c.n1; l += WT) {
+        LevelState s = {};
+        s.m0 = l == 0 ? 0u : INVALID;
+        s.B = l == 0 ? 1u : 0u;
+        c.st[l] = s;
+    }
+    for (int b = t; b < HB; b += WT) c.hist[b] = 0u;
+    for (int k = t; k < c.w2; k += WT) c.img[0][(size_t)k * c.Kp] = 0u;
+    for (int k = t; k < (1 + c.planes) * c.w2; k += WT) c.sets[(size_t)k * c.Kp] = 0u;
+    if (t == 0) {
+        c.ped[0][0] = 0u;
+        c.ein[0][0] = 0u;
+        *c.ce = 0ull;
+    }
+}
+
+// ------------------------------------------------------------------ expand
+// Workgroup = 256 parents x target words [k0, k1) of chunk (blockIdx % S);
+// the last chunk also evaluates the deletion child.
+template <int W, int PL, bool SMALL>
+__global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S) {
+    constexpr int PLA = PL > 0 ? PL : 1;
+    __shared__ uint32_t s_rows[32 * W * W];   // N2(u) rows of the chunk, W words each
+    __shared__ uint32_t s_lc[32 * W];         // label cost of substituting v_i by u
+    __shared__ uint32_t s_hist[HB];
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x / S, chunk = blockIdx.x % S;
+    const uint32_t B = sgpr(c.st[i].B);
+    if ((uint32_t)tile * WT >= B) return;
+    const uint32_t m0 = sgpr(c.st[i].m0), mmax = sgpr(c.st[i].mmax);
+    const int n2 = c.n2, w2 = c.w2, P = c.planes;
+    const uint32_t vsub = (uint32_t)c.c.vsub, vdel = (uint32_t)c.c.vdel, esub = (uint32_t)c.c.esub;
+    const uint32_t edel = (uint32_t)c.c.edel, eins = (uint32_t)c.c.eins, nedel = 0u - edel;
+    const int k0 = chunk * w2 / S, k1 = (chunk + 1) * w2 / S;
+    const int u0 = 32 * k0, u1 = min(32 * k1, n2);
+    const bool has_del = chunk == S - 1;
+
+    uint32_t deg = 0;
+    for (int k = 0; k < c.w1; ++k) deg += (uint32_t)__popc(earlier_word(c, i, k, i));
+    deg = sgpr(deg);
+    const int lab1 = c.l1[i];
+    // every child PED of the level lies in [m0, m0 + R]
+    // (no child exceeds pedmax either: every PED counts at most one operation
+    // per vertex of g1 and per edge of g1 and g2)
+    const uint64_t inc_sub = (uint64_t)vsub + (uint64_t)max(edel, esub) * deg + (uint64_t)eins * (uint64_t)min(i, n2);
+    const uint64_t inc_del = (uint64_t)vdel + (uint64_t)edel * deg;
+    uint64_t R = (uint64_t)(mmax - m0) + (inc_sub > inc_del ? inc_sub : inc_del);
+    R = R < c.pedmax ? R : c.pedmax;
+    uint32_t shift = 0;
+    while ((R >> shift) >= (uint64_t)HB) ++shift;
+    if (blockIdx.x == 0 && tid == 0) c.st[i].shift = shift;
+
+    for (int idx = tid; idx < (u1 - u0) * W; idx += WT) {
+        const int uu = idx / W, k = idx % W;
+        s_rows[idx] = k < w2 ? c.a2[(size_t)(u0 + uu) * w2 + k] : 0u;
+    }
+    for (int uu = tid; uu < u1 - u0; uu += WT) s_lc[uu] = c.l2[u0 + uu] != lab1 ? vsub : 0u;
+    for (int b = tid; b < HB; b += WT) s_hist[b] = 0u;
+    __syncthreads();
+
+    const uint32_t Kp = c.Kp;
+    const uint32_t p = (uint32_t)tile * WT + tid;
+    const bool live = p < B;
+    const int cur = i & 1;
+    uint32_t ph[W], am[W], pb[PLA][W];
+    uint32_t ped = 0u;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        ph[k] = 0u;
+        am[k] = 0u;
+#pragma unroll
+        for (int b = 0; b < PLA; ++b) pb[b][k] = 0u;
+    }
+    if (live) {
+        ped = c.ped[cur][p];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k < w2) {
+                ph[k] = c.sets[(size_t)k * Kp + p];
+                am[k] = c.img[cur][(size_t)k * Kp + p] & ~ph[k];
+#pragma unroll
+                for (int b = 0; b < PLA; ++b)
+                    if (PL > 0 && b < P) pb[b][k] = c.sets[(size_t)((1 + b) * w2 + k) * Kp + p];
+            }
+        }
+    }
+    const uint32_t basel = ped + mul_cost<SMALL>(deg, edel);
+    const uint32_t *planes2 = c.a2 + (size_t)n2 * w2;
+    uint32_t nvalid = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        if (k < k0 || k >= k1) continue;
+        const uint32_t used = ph[k] | am[k];
+        const int ub = 32 * k;
+        const int nb = min(32, n2 - ub);
+        for (int bit = 0; bit < nb; ++bit) {
+            const int u = ub + bit;
+            const uint32_t *Rw = s_rows + (u - u0) * W;
+            uint32_t mt = 0u, at = 0u, rl = 0u;
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const uint32_t r = Rw[q];
+                mt += (uint32_t)__popc(ph[q] & r);
+                at += (uint32_t)__popc(am[q] & r);
+                if (PL > 0) {
+                    uint32_t diff = 0u;
+#pragma unroll
+                    for (int b = 0; b < PLA; ++b)
+                        if (b < P && q < w2) diff |= pb[b][q] ^ planes2[((size_t)b * n2 + u) * w2 + q];
+                    rl += (uint32_t)__popc(ph[q] & r & diff);
+                }
+            }
+            uint32_t d = msub_cost<SMALL>(mt, nedel, mad_cost<SMALL>(at, eins, basel + s_lc[u - u0]));
+            if (PL > 0) d += mul_cost<SMALL>(rl, esub);
+            const bool ok = live && !((used >> bit) & 1u);
+            if (live) c.cand[(size_t)u * Kp + p] = ok ? d : INVALID;
+            if (ok) {
+                atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
+                ++nvalid;
+            }
+        }
+    }
+    if (has_del && live) {
+        const uint32_t d = basel + vdel;
+        c.cand[(size_t)n2 * Kp + p] = d;
+        atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
+        ++nvalid;
+    }
+    __syncthreads();
+    for (int b = tid; b < HB; b += WT) {
+        const uint32_t h = s_hist[b];
+        if (h) atomicAdd(&c.hist[b], h);
+    }
+    const uint32_t tot = wave_sum(nvalid);
+    if ((tid & 63) == 0 && tot) atomicAdd(&c.st[i].V, tot);
+}
+
+// ------------------------------------------------------------------ select
+// round 0 reads the expansion histogram; rounds 1 and 2 read refinement
+// histograms while a refinement is pending.  Clears the histogram it read.
+__global__ __launch_bounds__(ST) void wide_select(WideCtx c, int i, int round) {
+    __shared__ uint32_t s_tmp[ST / 64];
+    __shared__ uint32_t s_res[2];
+    LevelState *L = c.st + i;
+    const int t = threadIdx.x;
+    if (round > 0 && L->refine == 0u) return;
+    const uint32_t K = c.K;
+    const uint32_t V = L->V;
+    uint32_t h[HB / ST];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < HB / ST; ++q) {
+        h[q] = c.hist[t * (HB / ST) + q];
+        sum += h[q];
+    }
+    if (round == 0 && V <= K) {
+        // every child survives
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < HB / ST; ++q) c.hist[t * (HB / ST) + q] = 0u;
+        if (t == 0) {
+            L->T = INVALID;
+            L->quota = 0u;
+            L->refine = 0u;
+            c.st[i + 1].B = V;
+            *c.ce += V;
+        }
+        return;
+    }
+    const uint32_t target = round == 0 ? K : L->need;
+    uint32_t tot;
+    const uint32_t pre = block_excl_scan<ST / 64>(sum, s_tmp, &tot);
+    if (pre < target && target <= pre + sum) {
+        uint32_t below = pre, bin = 0u;
+        bool found = false;
+#pragma unroll
+        for (int q = 0; q < HB / ST; ++q) {
+            if (!found && below + h[q] >= target) {
+                found = true;
+                bin = (uint32_t)q;
+            }
+            if (!found) below += h[q];
+        }
+        s_res[0] = (uint32_t)(t * (HB / ST)) + bin;
+        s_res[1] = below;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < HB / ST; ++q) c.hist[t * (HB / ST) + q] = 0u;
+    if (t != 0) return;
+    const uint32_t bin = s_res[0], below = s_res[1];
+    if (round == 0) {
+        c.st[i + 1].B = K;
+        *c.ce += V;
+        const uint32_t shift = L->shift;
+        if (shift == 0u) {
+            L->T = L->m0 + bin;
+            L->quota = K - below;
+            L->refine = 0u;
+        } else {
+            L->lo = L->m0 + (bin << shift);
+            L->rwidth = shift;
+            L->rbin = shift > (uint32_t)HBITS ? shift - HBITS : 0u;
+            L->need = K - below;
+            L->refine = 1u;
+        }
+    } else {
+        const uint32_t rbin = L->rbin;
+        if (rbin == 0u) {
+            L->T = L->lo + bin;
+            L->quota = L->need - below;
+            L->refine = 0u;
+        } else {
+            L->lo += bin << rbin;
+            L->rwidth = rbin;
+            L->rbin = rbin > (uint32_t)HBITS ? rbin - HBITS : 0u;
+            L->need -= below;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ refine
+__global__ __launch_bounds__(WT) void wide_refine(WideCtx c, int i) {
+    __shared__ uint32_t s_hist[HB];
+    const LevelState *L = c.st + i;
+    if (sgpr(L->refine) == 0u) return;
+    const uint32_t B = sgpr(L->B);
+    if ((uint32_t)blockIdx.x * WT >= B) return;
+    const uint32_t lo = sgpr(L->lo), rwidth = sgpr(L->rwidth), rbin = sgpr(L->rbin);
+    const int tid = threadIdx.x;
+    for (int b = tid; b < HB; b += WT) s_hist[b] = 0u;
+    __syncthreads();
+    const uint32_t p = blockIdx.x * WT + tid;
+    if (p < B) {
+        for (int u = 0; u <= c.n2; ++u) {
+            const uint32_t d = c.cand[(size_t)u * c.Kp + p];
+            if (d != INVALID && d >= lo && ((d - lo) >> rwidth) == 0u)
+                atomicAdd(&s_hist[min((d - lo) >> rbin, (uint32_t)HB - 1u)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < HB; b += WT) {
+        const uint32_t h = s_hist[b];
+        if (h) atomicAdd(&c.hist[b], h);
+    }
+}
+
+// ------------------------------------------------------------------ count
+__global__ __launch_bounds__(WT) void wide_count(WideCtx c, int i, int nblk) {
+    __shared__ uint32_t s_tmp[2][NWV];
+    const LevelState *L = c.st + i;
+    const uint32_t B = sgpr(L->B), T = sgpr(L->T);
+    const uint32_t p = blockIdx.x * WT + threadIdx.x;
+    uint32_t lt = 0u, eq = 0u;
+    if (p < B) {
+        for (int u = 0; u <= c.n2; ++u) {
+            const uint32_t d = c.cand[(size_t)u * c.Kp + p];
+            lt += d < T ? 1u : 0u;
+            eq += d == T ? 1u : 0u;
+        }
+        c.cnt[p] = lt | (eq << 16);
+    }
+    const uint32_t a = wave_sum(lt), b = wave_sum(eq);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_tmp[0][wid] = a;
+        s_tmp[1][wid] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sa = 0u, sb = 0u;
+#pragma unroll
+        for (int k = 0; k < NWV; ++k) {
+            sa += s_tmp[0][k];
+            sb += s_tmp[1][k];
+        }
+        c.blk[blockIdx.x] = sa;
+        c.blk[(size_t)nblk + blockIdx.x] = sb;
+    }
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sums of both per-workgroup count arrays, in place.
+__global__ __launch_bounds__(ST) void wide_scan(WideCtx c, int nblk) {
+    __shared__ uint32_t s_tmp[ST / 64];
+    const int t = threadIdx.x;
+    const int per = (nblk + ST - 1) / ST;
+    for (int a = 0; a < 2; ++a) {
+        uint32_t *x = c.blk + (size_t)a * nblk;
+        uint32_t sum = 0u;
+        for (int q = 0; q < per; ++q) {
+            const int j = t * per + q;
+            sum += j < nblk ? x[j] : 0u;
+        }
+        uint32_t tot;
+        uint32_t run = block_excl_scan<ST / 64>(sum, s_tmp, &tot);
+        for (int q = 0; q < per; ++q) {
+            const int j = t * per + q;
+            if (j < nblk) {
+                const uint32_t v = x[j];
+                x[j] = run;
+                run += v;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ compact
+__global__ __launch_bounds__(WT) void wide_compact(WideCtx c, int i, int nblk) {
+    __shared__ uint32_t s_tmp[NWV];
+    const LevelState *L = c.st + i;
+    const uint32_t B = sgpr(L->B), T = sgpr(L->T), quota = sgpr(L->quota);
+    const uint32_t p = blockIdx.x * WT + threadIdx.x;
+    const uint32_t cv = p < B ? c.cnt[p] : 0u;
+    uint32_t lt = cv & 0xffffu;
+    const uint32_t eq = cv >> 16;
+    uint32_t tot;
+    const uint32_t LT = c.blk[blockIdx.x] + block_excl_scan<NWV>(lt, s_tmp, &tot);
+    const uint32_t EQ = c.blk[(size_t)nblk + blockIdx.x] + block_excl_scan<NWV>(eq, s_tmp, &tot);
+    uint32_t keq = EQ >= quota ? 0u : min(quota - EQ, eq);
+    uint32_t pos = LT + min(EQ, quota);
+    if (p >= B) return;
+    for (int u = 0; u <= c.n2 && (lt | keq) != 0u; ++u) {
+        const uint32_t d = c.cand[(size_t)u * c.Kp + p];
+        bool keep = false;
+        if (d < T) {
+            keep = true;
+            --lt;
+        } else if (d == T && keq > 0u) {
+            keep = true;
+            --keq;
+        }
+        if (keep && pos < c.K) c.rec[pos] = (p << CBITS) | (uint32_t)u;
+        pos += keep ? 1u : 0u;
+    }
+}
+
+// ------------------------------------------------------------------ update
+template <int W, int PL>
+__global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i) {
+    constexpr int NS = (1 + PL) * W;
+    __shared__ uint32_t s_set[NS * WT];   // column tid: this thread's Phi sets
+    const uint32_t Bn = sgpr(c.st[i + 1].B);
+    if ((uint32_t)blockIdx.x * WT >= Bn) return;
+    const int tid = threadIdx.x;
+    const uint32_t s = blockIdx.x * WT + tid;
+    const bool live = s < Bn;
+    const uint32_t Kp = c.Kp;
+    const int cur = i & 1, nxt = cur ^ 1;
+    const int n2 = c.n2, w2 = c.w2, P = c.planes;
+    const uint32_t Bp = sgpr(c.st[i].B);
+    const uint32_t r = live ? c.rec[s] : 0u;
+    // (records always name a parent of this level and a column <= n2; the
+    // clamps only keep the accesses inside the beam)
+    const uint32_t p = min(r >> CBITS, Bp - 1u), u = min(r & ((1u << CBITS) - 1u), (uint32_t)c.n2);
+    const bool sub = (int)u < n2;
+    uint32_t d = 0u;
+    if (live) {
+        d = c.cand[(size_t)u * Kp + p];
+        c.ped[nxt][s] = d;
+        uint32_t e = c.ein[cur][p];
+        for (int k = 0; k < w2; ++k) {
+            uint32_t im = c.img[cur][(size_t)k * Kp + p];
+            if (sub) {
+                e += (uint32_t)__popc(im & c.a2[(size_t)u * w2 + k]);
+                if (k == (int)(u >> 5)) im |= 1u << (u & 31u);
+            }
+            c.img[nxt][(size_t)k * Kp + s] = im;
+        }
+        c.ein[nxt][s] = e;
+    }
+    // mapping: copy the parent's, append u; collect Phi of the next level
+    const int v = i + 1;
+    const bool next = v < c.n1;
+    if (next) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) s_set[q * WT + tid] = 0u;
+    }
+    const uint32_t *planes1 = c.a1 + (size_t)c.n1 * c.w1;
+    auto collect = [&](int j, uint32_t x, uint32_t rowbits) {
+        if (!((rowbits >> (j & 31)) & 1u) || x == DEL16) return;
+        atomicOr(&s_set[(x >> 5) * WT + tid], 1u << (x & 31u));
+#pragma unroll
+        for (int b = 0; b < PL; ++b) {
+            if (b < P && ((planes1[((size_t)b * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u))
+                atomicOr(&s_set[((1 + b) * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
+        }
+    };
+    uint32_t rowbits = 0u;
+    for (int j = 0; j < i; ++j) {
+        if ((j & 31) == 0 && next) rowbits = sgpr(earlier_word(c, v, j >> 5, v));
+        if (live) {
+            const uint32_t x = c.phi[cur][(size_t)j * Kp + p];
+            c.phi[nxt][(size_t)j * Kp + s] = (uint16_t)x;
+            if (next) collect(j, x, rowbits);
+        }
+    }
+    if (live) {
+        const uint32_t x = sub ? u : DEL16;
+        c.phi[nxt][(size_t)i * Kp + s] = (uint16_t)x;
+        if (next) {
+            if ((i & 31) == 0) rowbits = sgpr(earlier_word(c, v, i >> 5, v));
+            collect(i, x, rowbits);
+        }
+    }
+    if (next && live) {
+        for (int b = 0; b < 1 + P && b < 1 + PL; ++b)
+            for (int k = 0; k < w2; ++k) c.sets[(size_t)(b * w2 + k) * Kp + s] = s_set[(b * W + k) * WT + tid];
+    }
+    const uint32_t mn = wave_umin(live ? d : INVALID), mx = wave_umax(live ? d : 0u);
+    if ((tid & 63) == 0) {
+        atomicMin(&c.st[v].m0, mn);
+        atomicMax(&c.st[v].mmax, mx);
+    }
+}
+
+// ------------------------------------------------------------------ final
+__global__ __launch_bounds__(ST) void wide_final(WideCtx c) {
+    __shared__ unsigned long long s_key[ST / 64];
+    const int t = threadIdx.x;
+    const int n1 = c.n1, cur = n1 & 1;
+    const uint32_t B = c.st[n1].B;
+    unsigned long long best = ~0ull;
+    for (uint32_t s = t; s < B; s += ST) {
+        uint32_t used = 0u;
+        for (int k = 0; k < c.w2; ++k) used += (uint32_t)__popc(c.img[cur][(size_t)k * c.Kp + s]);
+        const uint64_t total = (uint64_t)c.ped[cur][s] + (uint64_t)c.c.vins * (uint64_t)(c.n2 - (int)used) +
+                               (uint64_t)c.c.eins * (uint64_t)(c.m2 - (int)c.ein[cur][s]);
+        const unsigned long long key = (total << 32) | s;
+        best = key < best ? key : best;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long other = (unsigned long long)__shfl_xor((long long)best, o);
+        best = other < best ? other : best;
+    }
+    if ((t & 63) == 0) s_key[t >> 6] = best;
+    __syncthreads();
+    best = s_key[0];
+#pragma unroll
+    for (int k = 1; k < ST / 64; ++k) best = s_key[k] < best ? s_key[k] : best;
+    const uint32_t slot = (uint32_t)(best & 0xffffffffull);
+    if (t == 0) {
+        *c.out_dist = (int32_t)(best >> 32);
+        if (c.out_cand) *c.out_cand = (int64_t)*c.ce;
+    }
+    for (int j = t; j < n1; j += ST) {
+        const uint32_t x = c.phi[cur][(size_t)j * c.Kp + slot];
+        c.out_map[j] = x == DEL16 ? -1 : (int32_t)x;
+    }
+}
+
+// ------------------------------------------------------------------ host side
+
+struct Layout {
+    size_t ped[2], ein[2], img[2], phi[2], sets, cand, cnt, blk, rec, hist, st, ce, total;
+};
+
+Layout layout(int n1, int n2, int w2, int planes, uint32_t Kp) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    for (int k = 0; k < 2; ++k) {
+        L.ped[k] = take((size_t)Kp * 4);
+        L.ein[k] = take((size_t)Kp * 4);
+        L.img[k] = take((size_t)w2 * Kp * 4);
+        L.phi[k] = take((size_t)n1 * Kp * 2);
+    }
+    L.sets = take((size_t)(1 + planes) * w2 * Kp * 4);
+    L.cand = take((size_t)(n2 + 1) * Kp * 4);
+    L.cnt = take((size_t)Kp * 4);
+    L.blk = take((size_t)2 * (Kp / WT) * 4);
+    L.rec = take((size_t)Kp * 4);
+    L.hist = take((size_t)HB * 4);
+    L.st = take((size_t)(n1 + 1) * sizeof(LevelState));
+    L.ce = take(8);
+    L.total = off;
+    return L;
+}
+
+uint32_t slot_stride(int K) { return (uint32_t)((K + WT - 1) / WT) * WT; }
+
+template <int W, int PL>
+hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStream_t stream) {
+    const bool small = c.c.vsub < (1 << 22) && c.c.vdel < (1 << 22) && c.c.vins < (1 << 22) &&
+                       c.c.esub < (1 << 22) && c.c.edel < (1 << 22) && c.c.eins < (1 << 22);
+    hipLaunchKernelGGL(wide_init, dim3(1), dim3(WT), 0, stream, c);
+    uint64_t bound = 1;   // parents at level i are at most min(K, (n2 + 1)^i)
+    for (int i = 0; i < c.n1; ++i) {
+        const int tiles = (int)((bound + WT - 1) / WT);
+        int S = 1;
+        if (c.w2 > 1) {
+            const int want = (8 * cus + tiles - 1) / tiles;
+            S = want < c.w2 ? want : c.w2;
+            if (S < 1) S = 1;
+        }
+        if (small)
+            hipLaunchKernelGGL((wide_expand<W, PL, true>), dim3(tiles * S), dim3(WT), 0, stream, c, i, S);
+        else
+            hipLaunchKernelGGL((wide_expand<W, PL, false>), dim3(tiles * S), dim3(WT), 0, stream, c, i, S);
+        hipLaunchKernelGGL(wide_select, dim3(1), dim3(ST), 0, stream, c, i, 0);
+        if (refine_possible) {
+            for (int r = 1; r <= 2; ++r) {
+                hipLaunchKernelGGL(wide_refine, dim3(tiles), dim3(WT), 0, stream, c, i);
+                hipLaunchKernelGGL(wide_select, dim3(1), dim3(ST), 0, stream, c, i, r);
+            }
+        }
+        hipLaunchKernelGGL(wide_count, dim3(tiles), dim3(WT), 0, stream, c, i, tiles);
+        hipLaunchKernelGGL(wide_scan, dim3(1), dim3(ST), 0, stream, c, tiles);
+        hipLaunchKernelGGL(wide_compact, dim3(tiles), dim3(WT), 0, stream, c, i, tiles);
+        const uint64_t grown = bound * (uint64_t)(c.n2 + 1);
+        bound = grown < c.K ? grown : c.K;
+        const int utiles = (int)((bound + WT - 1) / WT);
+        hipLaunchKernelGGL((wide_update<W, PL>), dim3(utiles), dim3(WT), 0, stream, c, i);
+    }
+    hipLaunchKernelGGL(wide_final, dim3(1), dim3(ST), 0, stream, c);
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_pl(int PL, const WideCtx &c, bool refine_possible, int cus, hipStream_t stream) {
+    if (PL == 0) return launch_levels<W, 0>(c, refine_possible, cus, stream);
+    if (PL == 2) return launch_levels<W, 2>(c, refine_possible, cus, stream);
+    if (PL == 4) return launch_levels<W, 4>(c, refine_possible, cus, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t wide_workspace_bytes(int n1, int n2, int w2, int planes, int K) {
+    return layout(n1, n2, w2, planes, slot_stride(K)).total;
+}
+
+hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1, const GraphRec &g2, Costs costs,
+                       int K, void *ws, size_t ws_bytes, int32_t *dist, int32_t *map, int64_t *cand, int cus,
+                       hipStream_t stream) {
+    const int planes = dst.planes;
+    const int PL = planes == 0 ? 0 : (planes <= 2 ? 2 : 4);
+    int W = 1;
+    while (W < g2.w) W <<= 1;
+    const uint32_t Kp = slot_stride(K);
+    const Layout L = layout(g1.n, g2.n, g2.w, planes, Kp);
+    if (K < 1 || K > kWideMaxK || L.total > ws_bytes || W > 16 || g1.n > GED_MAX_VERTICES ||
+        g2.n > GED_MAX_VERTICES)
+        return hipErrorInvalidValue;
+    char *base = static_cast<char *>(ws);
+    WideCtx c{};
+    c.a1 = src.adj + g1.adj;
+    c.l1 = src.vlab + g1.vlab;
+    c.a2 = dst.adj + g2.adj;
+    c.l2 = dst.vlab + g2.vlab;
+    c.n1 = g1.n;
+    c.w1 = g1.w;
+    c.n2 = g2.n;
+    c.w2 = g2.w;
+    c.m2 = g2.m;
+    c.planes = planes;
+    c.c = costs;
+    c.K = (uint32_t)K;
+    c.Kp = Kp;
+    for (int k = 0; k < 2; ++k) {
+        c.ped[k] = reinterpret_cast<uint32_t *>(base + L.ped[k]);
+        c.ein[k] = reinterpret_cast<uint32_t *>(base + L.ein[k]);
+        c.img[k] = reinterpret_cast<uint32_t *>(base + L.img[k]);
+        c.phi[k] = reinterpret_cast<uint16_t *>(base + L.phi[k]);
+    }
+    c.sets = reinterpret_cast<uint32_t *>(base + L.sets);
+    c.cand = reinterpret_cast<uint32_t *>(base + L.cand);
+    c.cnt = reinterpret_cast<uint32_t *>(base + L.cnt);
+    c.blk = reinterpret_cast<uint32_t *>(base + L.blk);
+    c.rec = reinterpret_cast<uint32_t *>(base + L.rec);
+    c.hist = reinterpret_cast<uint32_t *>(base + L.hist);
+    c.st = reinterpret_cast<LevelState *>(base + L.st);
+    c.ce = reinterpret_cast<unsigned long long *>(base + L.ce);
+    c.out_dist = dist;
+    c.out_map = map;
+    c.out_cand = cand;
+    // no PED of the search exceeds pedmax, so the expansion histogram needs a
+    // shift (and refinement) only if pedmax does not fit its bins
+    const int64_t vmax = std::max({(int64_t)costs.vsub, (int64_t)costs.vdel, (int64_t)costs.vins});
+    const int64_t emax = std::max({(int64_t)costs.esub, (int64_t)costs.edel, (int64_t)costs.eins});
+    c.pedmax = (uint64_t)(vmax * (int64_t)g1.n + emax * ((int64_t)g1.m + g2.m));
+    const bool refine_possible = c.pedmax >= (uint64_t)HB;
+    switch (W) {
+        case 1: return launch_pl<1>(PL, c, refine_possible, cus, stream);
+        case 2: return launch_pl<2>(PL, c, refine_possible, cus, stream);
+        case 4: return launch_pl<4>(PL, c, refine_possible, cus, stream);
+        case 8: return launch_pl<8>(PL, c, refine_possible, cus, stream);
+        case 16: return launch_pl<16>(PL, c, refine_possible, cus, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gedk

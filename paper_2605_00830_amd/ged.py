@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libged.so")
 GED_OK, GED_EINVAL, GED_ENOMEM, GED_EUNSUPPORTED, GED_EDEVICE, GED_EBUSY, GED_ETIMEOUT, GED_ECANCELED = range(8)
 MAX_VERTICES = 512
 MAX_K = 1024
+MAX_K_WIDE = 1 << 21
 MAX_EDGE_LABELS = 16
 
 
@@ -73,6 +74,7 @@ EXPORTS = (
     "ged_plan_capture", "ged_plan_replay", "ged_plan_tune",
     "ged_server_create", "ged_server_submit", "ged_server_poll", "ged_server_wait",
     "ged_server_stats_get", "ged_server_destroy", "ged_server_submit_batch", "ged_server_collect",
+    "ged_wide_create", "ged_wide_bytes", "ged_wide_run", "ged_wide_destroy",
 )
 
 
@@ -119,6 +121,10 @@ def load(path: str = LIB_PATH):
         "ged_server_collect": ([P, i64, i64, P, P, P, P, i64, P], i32),
         "ged_server_stats_get": ([P, P], i32),
         "ged_server_destroy": ([P], i32),
+        "ged_wide_create": ([P, i64, i64, i32, P], i32),
+        "ged_wide_bytes": ([P, P], i32),
+        "ged_wide_run": ([P, Costs, P, P, P, P], i32),
+        "ged_wide_destroy": ([P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -338,6 +344,60 @@ def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: 
                       None if cand is None else cand[:n].cpu().numpy())
     finally:
         plan.close()
+
+
+class Wide:
+    """Single-pair search at large K with the whole device (ged_wide_*)."""
+
+    def __init__(self, db: Database, src: int, dst: int, K: int):
+        lib = load()
+        self.db = db
+        self.src, self.dst, self.K = int(src), int(dst), int(K)
+        handle = ctypes.c_void_p()
+        _check(lib.ged_wide_create(db.handle, self.src, self.dst, self.K, ctypes.byref(handle)))
+        self._h = handle
+        self.n1 = int(db.n[self.src])
+        size = ctypes.c_int64()
+        _check(lib.ged_wide_bytes(self._h, ctypes.byref(size)))
+        self.bytes = int(size.value)
+
+    def outputs(self, device="cuda"):
+        dist = torch.empty(1, dtype=torch.int32, device=device)
+        maps = torch.empty(max(self.n1, 1), dtype=torch.int32, device=device)
+        cand = torch.empty(1, dtype=torch.int64, device=device)
+        return dist, maps, cand
+
+    def run(self, costs, dist: torch.Tensor, maps: torch.Tensor, cand: Optional[torch.Tensor] = None, stream=None):
+        for t, dt, n in ((dist, torch.int32, 1), (maps, torch.int32, self.n1)):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() < n:
+                raise ValueError("outputs must be contiguous int32 CUDA tensors of 1 and n1 entries")
+        if cand is not None and (cand.dtype != torch.int64 or not cand.is_cuda):
+            raise ValueError("cand must be an int64 CUDA tensor")
+        _check(load().ged_wide_run(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
+                                   None if cand is None else cand.data_ptr(), _stream_handle(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().ged_wide_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kbest_wide(db: Database, src: int, dst: int, costs, K: int, stream=None):
+    """(dist, mapping, children evaluated) of one pair by the large-K search; synchronizes."""
+    w = Wide(db, src, dst, K)
+    try:
+        dist, maps, cand = w.outputs()
+        w.run(costs, dist, maps, cand, stream=stream)
+        (stream or torch.cuda.current_stream()).synchronize()
+        return int(dist.item()), maps[:w.n1].cpu().numpy(), int(cand.item())
+    finally:
+        w.close()
 
 
 def _graph_struct(g, keep: list) -> GraphStruct:

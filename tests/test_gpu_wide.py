@@ -1,0 +1,144 @@
+"""The single-pair large-K search (ged_wide_*): equal to the oracle bit for bit at
+sizes the oracle finishes in seconds, equal to the batched search at K <= 1024 on
+larger pairs, and at K in the hundreds of thousands the returned mapping's
+induced cost is the returned distance (GPU)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_00830_amd import synth
+from paper_2605_00830_amd.synth import Graph, GraphSet
+
+pytestmark = pytest.mark.gpu
+
+UNIT = synth.UNIT_COSTS
+PAPER = synth.PAPER_COSTS
+ODD = (3, 1, 2, 5, 1, 3)
+WIDE_RANGE = (1000, 3000, 2500, 700, 1300, 900)           # PED ranges past 4096: refinement passes
+BIG_VERTEX = (4_194_304, 5_000_011, 4_500_007, 30_011, 20_021, 35_003)   # products past 24 bits
+
+
+@pytest.fixture(scope="module")
+def ged():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_00830_amd import ged as g
+    g.load()
+    return g
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def labelled_set(seed, specs, nlab):
+    gs = []
+    for k, (n, p) in enumerate(specs):
+        g = synth.er_graph(seed, k, n, n, p, p, 4)
+        if nlab > 0:
+            g.elabel = (np.arange(g.m) % nlab).astype(np.int32)
+        gs.append(g)
+    return GraphSet.from_graphs(gs)
+
+
+def wide_vs_oracle(ged, db, graphs, pairs, costs, K):
+    d, m, off = oracle.kbest_pairs(graphs, np.asarray(pairs, np.int64), costs, K)
+    n = graphs.n
+    for q, (a, b) in enumerate(pairs):
+        say(f"  pair ({a},{b}) n1={n[a]} n2={n[b]} K={K} costs={costs}")
+        dist, mp, cand = ged.kbest_wide(db, a, b, costs, K)
+        assert dist == d[q], f"pair {q}: gpu {dist} oracle {d[q]}"
+        np.testing.assert_array_equal(mp, m[off[q]:off[q] + n[a]])
+        assert (cand > 0) == (n[a] > 0)   # no level, no child, when g1 is empty
+
+
+SMALL_SPECS = [(0, 0.0), (1, 0.0), (7, 0.5), (12, 0.3), (20, 0.2), (30, 0.15), (33, 0.1), (26, 0.6)]
+
+
+@pytest.mark.parametrize("nlab", [0, 3, 9])
+@pytest.mark.parametrize("costs", [UNIT, PAPER, ODD, WIDE_RANGE, BIG_VERTEX])
+@pytest.mark.parametrize("K", [1, 3, 64])
+def test_wide_small_k_matches_oracle(ged, costs, K, nlab):
+    """Empty and one-vertex graphs, both word boundaries of 32, no / 2 / 4 label planes."""
+    graphs = labelled_set(71 + nlab, SMALL_SPECS, nlab)
+    db = ged.Database(graphs)
+    pairs = [(2, 3), (3, 2), (4, 5), (5, 6), (6, 7), (7, 4), (0, 3), (3, 0), (0, 1), (1, 1)]
+    wide_vs_oracle(ged, db, graphs, pairs, costs, K)
+    db.close()
+
+
+@pytest.mark.parametrize("costs", [UNIT, WIDE_RANGE, BIG_VERTEX])
+@pytest.mark.parametrize("K", [777, 5000, 20000])
+def test_wide_large_k_matches_oracle(ged, costs, K):
+    graphs = labelled_set(83, [(24, 0.2), (28, 0.15), (36, 0.1), (18, 0.3)], 3)
+    db = ged.Database(graphs)
+    wide_vs_oracle(ged, db, graphs, [(0, 1), (2, 1), (3, 2)], costs, K)
+    db.close()
+
+
+def test_wide_max_k_tiny_pair(ged):
+    """K = GED_MAX_K_WIDE on a pair whose whole search tree is smaller: no trimming."""
+    graphs = labelled_set(89, [(6, 0.4), (7, 0.4)], 2)
+    db = ged.Database(graphs)
+    wide_vs_oracle(ged, db, graphs, [(0, 1)], PAPER, ged.MAX_K_WIDE)
+    db.close()
+
+
+@pytest.mark.parametrize("K", [64, 1024])
+def test_wide_equals_batched(ged, K):
+    """Larger pairs (2, 3, 4 and 10 target words; labelled edges): the same distance,
+    mapping and candidate count as the batched workgroup kernel, itself pinned to the
+    oracle."""
+    graphs = labelled_set(97, [(60, 0.1), (70, 0.08), (100, 0.05), (120, 0.04), (300, 0.02)], 3)
+    db = ged.Database(graphs)
+    pairs = [(0, 1), (1, 0), (2, 3), (3, 2), (1, 4)]
+    for costs in (UNIT, PAPER):
+        ref = ged.kbest(db, pairs, costs, K, with_cand=True, schedule=ged.SCHED_BLOCK)
+        for q, (a, b) in enumerate(pairs):
+            say(f"  pair ({a},{b}) K={K} costs={costs}")
+            dist, mp, cand = ged.kbest_wide(db, a, b, costs, K)
+            assert dist == ref.dist[q]
+            np.testing.assert_array_equal(mp, ref.mapping(q, graphs.n[a]))
+            assert cand == ref.cand[q]
+    db.close()
+
+
+def test_wide_big_k_properties(ged):
+    """K = 200,000 on a 100-vertex pair: the mapping is injective and its induced cost
+    (oracle) is the returned distance; a second run returns the same."""
+    graphs = labelled_set(101, [(100, 0.06), (100, 0.06)], 3)
+    db = ged.Database(graphs)
+    K = 200_000
+    say(f"  pair (0,1) n=100 K={K}")
+    d1, m1, c1 = ged.kbest_wide(db, 0, 1, PAPER, K)
+    d2, m2, c2 = ged.kbest_wide(db, 0, 1, PAPER, K)
+    db.close()
+    assert (d1, c1) == (d2, c2)
+    np.testing.assert_array_equal(m1, m2)
+    used = m1[m1 >= 0]
+    assert len(np.unique(used)) == len(used) and (used < 100).all()
+    g1, g2 = graphs.graph(0), graphs.graph(1)
+    assert oracle.induced_cost(g1, g2, PAPER, m1) == d1
+    assert c1 > K
+
+
+def test_wide_errors(ged):
+    graphs = labelled_set(103, [(5, 0.5), (6, 0.5)], 0)
+    db = ged.Database(graphs)
+    for bad in [(0, 1, 0), (0, 1, ged.MAX_K_WIDE + 1), (0, 2, 4), (-1, 1, 4)]:
+        with pytest.raises(ged.GedError) as e:
+            ged.Wide(db, *bad)
+        assert e.value.status == ged.GED_EINVAL
+    w = ged.Wide(db, 0, 1, 8)
+    dist, maps, cand = w.outputs()
+    with pytest.raises(ged.GedError) as e:
+        w.run((1, -1, 1, 1, 1, 1), dist, maps, cand)
+    assert e.value.status == ged.GED_EINVAL
+    with pytest.raises(ged.GedError) as e:
+        w.run((2**30, 2**30, 2**30, 1, 1, 1), dist, maps, cand)
+    assert e.value.status == ged.GED_EINVAL
+    w.close()
+    db.close()
