@@ -8,32 +8,37 @@
 //   img[k][s]             word k of Img (the g2 vertices in use)
 //   phi[j][s]             image of g1 vertex j (uint16, 0xffff = deleted)
 //   sets[b][k][s]         Phi for the current level (b = 0) and its edge-label
-//                         planes Phi_b (b = 1..planes), built by the update
-// ped/ein/img/phi are double-buffered by level parity.  Per level i (g1
-// vertex v_i, in index order):
-//   expand   one thread per parent and one workgroup per (256 parents, range
-//            of target words): every child's PED (Sec. 2.3, implied edge
-//            operations), written to the candidate matrix cand[u][p] (u = n2
-//            is the deletion, 0xffffffff marks a used u), and an LDS
-//            histogram of (PED - m0) >> shift, m0 the least parent PED and
+//                         planes Phi_b (b = 1..planes)
+// ped/ein/img/phi are double-buffered by level parity.  The candidate
+// columns u = 0..n2 (u = n2 is the deletion) are split into S chunks of
+// whole 32-vertex words, so that a level with few parents (large graphs,
+// small K) still spreads over the device: the per-parent kernels run one
+// workgroup per (256 parents, chunk).  Per level i (g1 vertex v_i, in index
+// order):
+//   expand   every child's PED (Sec. 2.3, implied edge operations) into the
+//            candidate matrix cand[u][p] (0xffffffff marks a used u), and an
+//            LDS histogram of (PED - m0) >> shift, m0 the least parent PED and
 //            shift chosen so that every child PED of the level fits 4096
 //            bins; the workgroup histograms are summed in HBM.
 //   select   one workgroup: the bin holding the K-th smallest child.  With
 //            shift 0 that bin IS the threshold T; otherwise up to two refine
 //            passes histogram the candidates inside the bin at finer shifts
 //            (12 bits at a time) until the threshold is exact.
-//   count    per parent: children below T and equal to T.
-//   scan     one workgroup: exclusive prefix sums of the per-workgroup counts.
-//   compact  per parent: its survivors in generation order (parent slot, then
-//            target vertex ascending, then the deletion): every child below T,
-//            and ties at T while the quota K - #below lasts, counted from the
-//            first parent on.  Survivors are written as records parent << 10 |
-//            column at their beam position, so the new beam is again in
-//            generation order and never needs sorting.
-//   update   one thread per new slot: PED, Img, e_in and the mapping from its
-//            parent, and the Phi sets of the next level.
-// After the last level, one workgroup completes every leaf (Sec. 4.4.1) and
-// returns the first leaf of least total in beam order.
+//   count    per (parent, chunk): children below T and equal to T.
+//   scan     one workgroup: exclusive prefix sums over the workgroups.
+//   compact  per (parent, chunk): its survivors in generation order (parent
+//            slot, then target vertex ascending, then the deletion): every
+//            child below T, and ties at T while the quota K - #below lasts,
+//            counted from the first parent on, written as records
+//            parent << 10 | column at their beam position -- the new beam is
+//            again in generation order and never needs sorting.
+//   update   per (new slot, range of 64 mapping entries): the mapping copied
+//            from the parent with u appended; the first range also sets PED,
+//            Img and e_in and clears the Phi sets.
+//   sets     per (new slot, range of 64 mapping entries): the images of the
+//            next vertex's earlier neighbours in the range, OR-ed into Phi.
+// After the last level every leaf is completed (Sec. 4.4.1) and the first
+// leaf of least total in beam order is returned.
 #include <algorithm>
 
 #include "ged_internal.h"
@@ -52,6 +57,8 @@ constexpr int ST = 1024;         // threads of the single-workgroup kernels
 constexpr int HBITS = 12;
 constexpr int HB = 1 << HBITS;   // histogram bins
 constexpr int CBITS = 10;        // survivor record: parent << CBITS | column
+constexpr int MAXS = 16;         // column chunks (one per target word at most)
+constexpr int JR = 64;           // mapping entries per update workgroup
 
 struct LevelState {
     uint32_t B;       // parents (beam slots) at this level
@@ -85,12 +92,14 @@ struct WideCtx {
     uint16_t *phi[2];
     uint32_t *sets;
     uint32_t *cand;
-    uint32_t *cnt;
-    uint32_t *blk;        // [2][Kp / WT]: per-workgroup counts, then their prefix sums
+    uint32_t *cnt;        // [MAXS][Kp]: below | equal << 16 per (chunk, parent)
+    uint32_t *blk;        // [2][MAXS][Kp / WT]: per-workgroup sums of the counts
+    uint32_t *pre;        // [2][Kp / WT]: their exclusive prefix over parent tiles
     uint32_t *rec;
     uint32_t *hist;
     LevelState *st;
     unsigned long long *ce;
+    unsigned long long *best;   // least (total << 32 | slot) of the leaves
     int32_t *out_dist;
     int32_t *out_map;
     int64_t *out_cand;
@@ -126,6 +135,17 @@ __device__ __forceinline__ uint32_t earlier_word(const WideCtx &c, int v, int k,
     return r & ((1u << (lim - lo)) - 1u);
 }
 
+// Candidate columns of chunk `chunk` of S: target words [k0, k1), i.e.
+// vertices [u0, u1), plus the deletion column in the last chunk.
+struct Cols {
+    int u0, u1;
+    bool del;
+};
+__device__ __forceinline__ Cols chunk_cols(const WideCtx &c, int chunk, int S) {
+    const int k0 = chunk * c.w2 / S, k1 = (chunk + 1) * c.w2 / S;
+    return Cols{32 * k0, min(32 * k1, c.n2), chunk == S - 1};
+}
+
 // ------------------------------------------------------------------ init
 __global__ __launch_bounds__(WT) void wide_init(WideCtx c) {
     const int t = threadIdx.x;
@@ -142,123 +162,130 @@ __global__ __launch_bounds__(WT) void wide_init(WideCtx c) {
         c.ped[0][0] = 0u;
         c.ein[0][0] = 0u;
         *c.ce = 0ull;
+        *c.best = ~0ull;
     }
 }
 
 // ------------------------------------------------------------------ expand
-// Workgroup = 256 parents x target words [k0, k1) of chunk (blockIdx % S);
-// the last chunk also evaluates the deletion child.
+// Persistent over the items (chunk, tile) of the level, chunk-major so that
+// a workgroup restages its target rows only when its chunk changes.
 template <int W, int PL, bool SMALL>
-__global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S) {
+__global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S, int tiles) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_rows[32 * W * W];   // N2(u) rows of the chunk, W words each
     __shared__ uint32_t s_lc[32 * W];         // label cost of substituting v_i by u
     __shared__ uint32_t s_hist[HB];
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x / S, chunk = blockIdx.x % S;
     const uint32_t B = sgpr(c.st[i].B);
-    if ((uint32_t)tile * WT >= B) return;
     const uint32_t m0 = sgpr(c.st[i].m0), mmax = sgpr(c.st[i].mmax);
     const int n2 = c.n2, w2 = c.w2, P = c.planes;
     const uint32_t vsub = (uint32_t)c.c.vsub, vdel = (uint32_t)c.c.vdel, esub = (uint32_t)c.c.esub;
     const uint32_t edel = (uint32_t)c.c.edel, eins = (uint32_t)c.c.eins, nedel = 0u - edel;
-    const int k0 = chunk * w2 / S, k1 = (chunk + 1) * w2 / S;
-    const int u0 = 32 * k0, u1 = min(32 * k1, n2);
-    const bool has_del = chunk == S - 1;
+    const uint32_t Kp = c.Kp;
+    const int cur = i & 1;
 
     uint32_t deg = 0;
     for (int k = 0; k < c.w1; ++k) deg += (uint32_t)__popc(earlier_word(c, i, k, i));
     deg = sgpr(deg);
     const int lab1 = c.l1[i];
-    // every child PED of the level lies in [m0, m0 + R]
-    // (no child exceeds pedmax either: every PED counts at most one operation
-    // per vertex of g1 and per edge of g1 and g2)
+    // every child PED of the level lies in [m0, m0 + R] (and below pedmax:
+    // a PED counts at most one operation per vertex of g1 and per edge of g1
+    // and g2)
     const uint64_t inc_sub = (uint64_t)vsub + (uint64_t)max(edel, esub) * deg + (uint64_t)eins * (uint64_t)min(i, n2);
     const uint64_t inc_del = (uint64_t)vdel + (uint64_t)edel * deg;
     uint64_t R = (uint64_t)(mmax - m0) + (inc_sub > inc_del ? inc_sub : inc_del);
     R = R < c.pedmax ? R : c.pedmax;
     uint32_t shift = 0;
     while ((R >> shift) >= (uint64_t)HB) ++shift;
+    const int nbins = (int)(R >> shift) + 1;   // bins that can be hit
     if (blockIdx.x == 0 && tid == 0) c.st[i].shift = shift;
 
-    for (int idx = tid; idx < (u1 - u0) * W; idx += WT) {
-        const int uu = idx / W, k = idx % W;
-        s_rows[idx] = k < w2 ? c.a2[(size_t)(u0 + uu) * w2 + k] : 0u;
-    }
-    for (int uu = tid; uu < u1 - u0; uu += WT) s_lc[uu] = c.l2[u0 + uu] != lab1 ? vsub : 0u;
-    for (int b = tid; b < HB; b += WT) s_hist[b] = 0u;
-    __syncthreads();
-
-    const uint32_t Kp = c.Kp;
-    const uint32_t p = (uint32_t)tile * WT + tid;
-    const bool live = p < B;
-    const int cur = i & 1;
-    uint32_t ph[W], am[W], pb[PLA][W];
-    uint32_t ped = 0u;
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        ph[k] = 0u;
-        am[k] = 0u;
-#pragma unroll
-        for (int b = 0; b < PLA; ++b) pb[b][k] = 0u;
-    }
-    if (live) {
-        ped = c.ped[cur][p];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            if (k < w2) {
-                ph[k] = c.sets[(size_t)k * Kp + p];
-                am[k] = c.img[cur][(size_t)k * Kp + p] & ~ph[k];
-#pragma unroll
-                for (int b = 0; b < PLA; ++b)
-                    if (PL > 0 && b < P) pb[b][k] = c.sets[(size_t)((1 + b) * w2 + k) * Kp + p];
-            }
-        }
-    }
-    const uint32_t basel = ped + mul_cost<SMALL>(deg, edel);
+    for (int b = tid; b < nbins; b += WT) s_hist[b] = 0u;
     const uint32_t *planes2 = c.a2 + (size_t)n2 * w2;
     uint32_t nvalid = 0;
+    int staged = -1;
+    for (int w = blockIdx.x; w < tiles * S; w += gridDim.x) {
+        const int chunk = w / tiles, tile = w % tiles;
+        if ((uint32_t)tile * WT >= B) continue;
+        const Cols cc = chunk_cols(c, chunk, S);
+        const int k0 = cc.u0 >> 5, k1 = (cc.u1 + 31) >> 5;
+        if (chunk != staged) {
+            __syncthreads();
+            for (int idx = tid; idx < (cc.u1 - cc.u0) * W; idx += WT) {
+                const int uu = idx / W, k = idx % W;
+                s_rows[idx] = k < w2 ? c.a2[(size_t)(cc.u0 + uu) * w2 + k] : 0u;
+            }
+            for (int uu = tid; uu < cc.u1 - cc.u0; uu += WT) s_lc[uu] = c.l2[cc.u0 + uu] != lab1 ? vsub : 0u;
+            __syncthreads();
+            staged = chunk;
+        }
+        const uint32_t p = (uint32_t)tile * WT + tid;
+        const bool live = p < B;
+        uint32_t ph[W], am[W], pb[PLA][W];
+        uint32_t ped = 0u;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
-        if (k < k0 || k >= k1) continue;
-        const uint32_t used = ph[k] | am[k];
-        const int ub = 32 * k;
-        const int nb = min(32, n2 - ub);
-        for (int bit = 0; bit < nb; ++bit) {
-            const int u = ub + bit;
-            const uint32_t *Rw = s_rows + (u - u0) * W;
-            uint32_t mt = 0u, at = 0u, rl = 0u;
+        for (int k = 0; k < W; ++k) {
+            ph[k] = 0u;
+            am[k] = 0u;
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const uint32_t r = Rw[q];
-                mt += (uint32_t)__popc(ph[q] & r);
-                at += (uint32_t)__popc(am[q] & r);
-                if (PL > 0) {
-                    uint32_t diff = 0u;
+            for (int b = 0; b < PLA; ++b) pb[b][k] = 0u;
+        }
+        if (live) {
+            ped = c.ped[cur][p];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                if (k < w2) {
+                    ph[k] = c.sets[(size_t)k * Kp + p];
+                    am[k] = c.img[cur][(size_t)k * Kp + p] & ~ph[k];
 #pragma unroll
                     for (int b = 0; b < PLA; ++b)
-                        if (b < P && q < w2) diff |= pb[b][q] ^ planes2[((size_t)b * n2 + u) * w2 + q];
-                    rl += (uint32_t)__popc(ph[q] & r & diff);
+                        if (PL > 0 && b < P) pb[b][k] = c.sets[(size_t)((1 + b) * w2 + k) * Kp + p];
                 }
             }
-            uint32_t d = msub_cost<SMALL>(mt, nedel, mad_cost<SMALL>(at, eins, basel + s_lc[u - u0]));
-            if (PL > 0) d += mul_cost<SMALL>(rl, esub);
-            const bool ok = live && !((used >> bit) & 1u);
-            if (live) c.cand[(size_t)u * Kp + p] = ok ? d : INVALID;
-            if (ok) {
-                atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
-                ++nvalid;
+        }
+        const uint32_t basel = ped + mul_cost<SMALL>(deg, edel);
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k < k0 || k >= k1) continue;
+            const uint32_t used = ph[k] | am[k];
+            const int ub = 32 * k;
+            const int nb = min(32, n2 - ub);
+            for (int bit = 0; bit < nb; ++bit) {
+                const int u = ub + bit;
+                const uint32_t *Rw = s_rows + (u - cc.u0) * W;
+                uint32_t mt = 0u, at = 0u, rl = 0u;
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const uint32_t r = Rw[q];
+                    mt += (uint32_t)__popc(ph[q] & r);
+                    at += (uint32_t)__popc(am[q] & r);
+                    if (PL > 0) {
+                        uint32_t diff = 0u;
+#pragma unroll
+                        for (int b = 0; b < PLA; ++b)
+                            if (b < P && q < w2) diff |= pb[b][q] ^ planes2[((size_t)b * n2 + u) * w2 + q];
+                        rl += (uint32_t)__popc(ph[q] & r & diff);
+                    }
+                }
+                uint32_t d = msub_cost<SMALL>(mt, nedel, mad_cost<SMALL>(at, eins, basel + s_lc[u - cc.u0]));
+                if (PL > 0) d += mul_cost<SMALL>(rl, esub);
+                const bool ok = live && !((used >> bit) & 1u);
+                if (live) c.cand[(size_t)u * Kp + p] = ok ? d : INVALID;
+                if (ok) {
+                    atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
+                    ++nvalid;
+                }
             }
         }
-    }
-    if (has_del && live) {
-        const uint32_t d = basel + vdel;
-        c.cand[(size_t)n2 * Kp + p] = d;
-        atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
-        ++nvalid;
+        if (cc.del && live) {
+            const uint32_t d = basel + vdel;
+            c.cand[(size_t)n2 * Kp + p] = d;
+            atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
+            ++nvalid;
+        }
     }
     __syncthreads();
-    for (int b = tid; b < HB; b += WT) {
+    for (int b = tid; b < nbins; b += WT) {
         const uint32_t h = s_hist[b];
         if (h) atomicAdd(&c.hist[b], h);
     }
@@ -351,20 +378,24 @@ __global__ __launch_bounds__(ST) void wide_select(WideCtx c, int i, int round) {
 }
 
 // ------------------------------------------------------------------ refine
-__global__ __launch_bounds__(WT) void wide_refine(WideCtx c, int i) {
+// One workgroup per (chunk, tile), chunk-major like every per-parent kernel.
+__global__ __launch_bounds__(WT) void wide_refine(WideCtx c, int i, int S, int tiles) {
     __shared__ uint32_t s_hist[HB];
     const LevelState *L = c.st + i;
     if (sgpr(L->refine) == 0u) return;
+    const int chunk = blockIdx.x / tiles, tile = blockIdx.x % tiles;
     const uint32_t B = sgpr(L->B);
-    if ((uint32_t)blockIdx.x * WT >= B) return;
+    if ((uint32_t)tile * WT >= B) return;
     const uint32_t lo = sgpr(L->lo), rwidth = sgpr(L->rwidth), rbin = sgpr(L->rbin);
     const int tid = threadIdx.x;
     for (int b = tid; b < HB; b += WT) s_hist[b] = 0u;
     __syncthreads();
-    const uint32_t p = blockIdx.x * WT + tid;
+    const Cols cc = chunk_cols(c, chunk, S);
+    const uint32_t p = (uint32_t)tile * WT + tid;
     if (p < B) {
-        for (int u = 0; u <= c.n2; ++u) {
-            const uint32_t d = c.cand[(size_t)u * c.Kp + p];
+        for (int u = cc.u0; u < cc.u1 + (cc.del ? 1 : 0); ++u) {
+            const int col = u < cc.u1 ? u : c.n2;
+            const uint32_t d = c.cand[(size_t)col * c.Kp + p];
             if (d != INVALID && d >= lo && ((d - lo) >> rwidth) == 0u)
                 atomicAdd(&s_hist[min((d - lo) >> rbin, (uint32_t)HB - 1u)], 1u);
         }
@@ -377,19 +408,22 @@ __global__ __launch_bounds__(WT) void wide_refine(WideCtx c, int i) {
 }
 
 // ------------------------------------------------------------------ count
-__global__ __launch_bounds__(WT) void wide_count(WideCtx c, int i, int nblk) {
+__global__ __launch_bounds__(WT) void wide_count(WideCtx c, int i, int S, int tiles) {
     __shared__ uint32_t s_tmp[2][NWV];
     const LevelState *L = c.st + i;
     const uint32_t B = sgpr(L->B), T = sgpr(L->T);
-    const uint32_t p = blockIdx.x * WT + threadIdx.x;
+    const int chunk = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const Cols cc = chunk_cols(c, chunk, S);
+    const uint32_t p = (uint32_t)tile * WT + threadIdx.x;
     uint32_t lt = 0u, eq = 0u;
     if (p < B) {
-        for (int u = 0; u <= c.n2; ++u) {
-            const uint32_t d = c.cand[(size_t)u * c.Kp + p];
+        for (int u = cc.u0; u < cc.u1 + (cc.del ? 1 : 0); ++u) {
+            const int col = u < cc.u1 ? u : c.n2;
+            const uint32_t d = c.cand[(size_t)col * c.Kp + p];
             lt += d < T ? 1u : 0u;
             eq += d == T ? 1u : 0u;
         }
-        c.cnt[p] = lt | (eq << 16);
+        c.cnt[(size_t)chunk * c.Kp + p] = lt | (eq << 16);
     }
     const uint32_t a = wave_sum(lt), b = wave_sum(eq);
     const int wid = threadIdx.x >> 6;
@@ -405,31 +439,34 @@ __global__ __launch_bounds__(WT) void wide_count(WideCtx c, int i, int nblk) {
             sa += s_tmp[0][k];
             sb += s_tmp[1][k];
         }
-        c.blk[blockIdx.x] = sa;
-        c.blk[(size_t)nblk + blockIdx.x] = sb;
+        c.blk[(size_t)chunk * tiles + tile] = sa;
+        c.blk[(size_t)(S + chunk) * tiles + tile] = sb;
     }
 }
 
 // ------------------------------------------------------------------ scan
-// Exclusive prefix sums of both per-workgroup count arrays, in place.
-__global__ __launch_bounds__(ST) void wide_scan(WideCtx c, int nblk) {
+// pre[a][t] = sum over tiles before t and all chunks of blk[a][chunk][tile].
+__global__ __launch_bounds__(ST) void wide_scan(WideCtx c, int S, int tiles) {
     __shared__ uint32_t s_tmp[ST / 64];
     const int t = threadIdx.x;
-    const int per = (nblk + ST - 1) / ST;
+    const int per = (tiles + ST - 1) / ST;
     for (int a = 0; a < 2; ++a) {
-        uint32_t *x = c.blk + (size_t)a * nblk;
+        const uint32_t *x = c.blk + (size_t)a * S * tiles;
+        uint32_t *y = c.pre + (size_t)a * tiles;
         uint32_t sum = 0u;
         for (int q = 0; q < per; ++q) {
             const int j = t * per + q;
-            sum += j < nblk ? x[j] : 0u;
+            if (j < tiles)
+                for (int ch = 0; ch < S; ++ch) sum += x[(size_t)ch * tiles + j];
         }
         uint32_t tot;
         uint32_t run = block_excl_scan<ST / 64>(sum, s_tmp, &tot);
         for (int q = 0; q < per; ++q) {
             const int j = t * per + q;
-            if (j < nblk) {
-                const uint32_t v = x[j];
-                x[j] = run;
+            if (j < tiles) {
+                uint32_t v = 0u;
+                for (int ch = 0; ch < S; ++ch) v += x[(size_t)ch * tiles + j];
+                y[j] = run;
                 run += v;
             }
         }
@@ -437,54 +474,98 @@ __global__ __launch_bounds__(ST) void wide_scan(WideCtx c, int nblk) {
 }
 
 // ------------------------------------------------------------------ compact
-__global__ __launch_bounds__(WT) void wide_compact(WideCtx c, int i, int nblk) {
+__global__ __launch_bounds__(WT) void wide_compact(WideCtx c, int i, int S, int tiles) {
     __shared__ uint32_t s_tmp[NWV];
     const LevelState *L = c.st + i;
     const uint32_t B = sgpr(L->B), T = sgpr(L->T), quota = sgpr(L->quota);
-    const uint32_t p = blockIdx.x * WT + threadIdx.x;
-    const uint32_t cv = p < B ? c.cnt[p] : 0u;
-    uint32_t lt = cv & 0xffffu;
-    const uint32_t eq = cv >> 16;
+    const int chunk = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const uint32_t p = (uint32_t)tile * WT + threadIdx.x;
+    const bool live = p < B;
+    // the parent's counts: all chunks, chunks before this one, this chunk
+    uint32_t lt = 0u, eq = 0u, ltb = 0u, eqb = 0u, ltc = 0u, eqc = 0u;
+    if (live) {
+        for (int ch = 0; ch < S; ++ch) {
+            const uint32_t v = c.cnt[(size_t)ch * c.Kp + p];
+            const uint32_t a = v & 0xffffu, b = v >> 16;
+            lt += a;
+            eq += b;
+            if (ch < chunk) {
+                ltb += a;
+                eqb += b;
+            }
+            if (ch == chunk) {
+                ltc = a;
+                eqc = b;
+            }
+        }
+    }
     uint32_t tot;
-    const uint32_t LT = c.blk[blockIdx.x] + block_excl_scan<NWV>(lt, s_tmp, &tot);
-    const uint32_t EQ = c.blk[(size_t)nblk + blockIdx.x] + block_excl_scan<NWV>(eq, s_tmp, &tot);
-    uint32_t keq = EQ >= quota ? 0u : min(quota - EQ, eq);
-    uint32_t pos = LT + min(EQ, quota);
-    if (p >= B) return;
-    for (int u = 0; u <= c.n2 && (lt | keq) != 0u; ++u) {
-        const uint32_t d = c.cand[(size_t)u * c.Kp + p];
+    const uint32_t LT = c.pre[tile] + block_excl_scan<NWV>(lt, s_tmp, &tot);
+    const uint32_t EQ = c.pre[tiles + tile] + block_excl_scan<NWV>(eq, s_tmp, &tot);
+    if (!live) return;
+    // (every difference below is of a value and its own minimum with
+    // something else, so none can wrap)
+    const uint32_t eqk = min(EQ, quota);                 // ties kept before this parent
+    const uint32_t keq = min(quota - eqk, eq);           // ties the parent keeps
+    const uint32_t eqbk = min(eqb, keq);                 // ... in its earlier chunks
+    uint32_t keqc = min(keq - eqbk, eqc);                // ... in this chunk
+    uint32_t pos = LT + eqk + ltb + eqbk;
+    const Cols cc = chunk_cols(c, chunk, S);
+    for (int u = cc.u0; u < cc.u1 + (cc.del ? 1 : 0) && (ltc | keqc) != 0u; ++u) {
+        const int col = u < cc.u1 ? u : c.n2;
+        const uint32_t d = c.cand[(size_t)col * c.Kp + p];
         bool keep = false;
         if (d < T) {
             keep = true;
-            --lt;
-        } else if (d == T && keq > 0u) {
+            --ltc;
+        } else if (d == T && keqc > 0u) {
             keep = true;
-            --keq;
+            --keqc;
         }
-        if (keep && pos < c.K) c.rec[pos] = (p << CBITS) | (uint32_t)u;
+        if (keep && pos < c.K) c.rec[pos] = (p << CBITS) | (uint32_t)col;
         pos += keep ? 1u : 0u;
     }
 }
 
+// Parent slot and column of new slot s (records always name a parent of this
+// level and a column <= n2; the clamps only keep accesses inside the beam).
+__device__ __forceinline__ void read_record(const WideCtx &c, uint32_t s, uint32_t Bp, uint32_t *p, uint32_t *u) {
+    const uint32_t r = c.rec[s];
+    *p = min(r >> CBITS, Bp - 1u);
+    *u = min(r & ((1u << CBITS) - 1u), (uint32_t)c.n2);
+}
+
 // ------------------------------------------------------------------ update
-template <int W, int PL>
-__global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i) {
-    constexpr int NS = (1 + PL) * W;
-    __shared__ uint32_t s_set[NS * WT];   // column tid: this thread's Phi sets
+// One workgroup per (mapping range jr, slot tile), range-major.
+__global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles) {
+    const int jr = blockIdx.x / utiles, tile = blockIdx.x % utiles;
     const uint32_t Bn = sgpr(c.st[i + 1].B);
-    if ((uint32_t)blockIdx.x * WT >= Bn) return;
+    if ((uint32_t)tile * WT >= Bn) return;
     const int tid = threadIdx.x;
-    const uint32_t s = blockIdx.x * WT + tid;
+    const uint32_t s = (uint32_t)tile * WT + tid;
     const bool live = s < Bn;
     const uint32_t Kp = c.Kp;
     const int cur = i & 1, nxt = cur ^ 1;
-    const int n2 = c.n2, w2 = c.w2, P = c.planes;
-    const uint32_t Bp = sgpr(c.st[i].B);
-    const uint32_t r = live ? c.rec[s] : 0u;
-    // (records always name a parent of this level and a column <= n2; the
-    // clamps only keep the accesses inside the beam)
-    const uint32_t p = min(r >> CBITS, Bp - 1u), u = min(r & ((1u << CBITS) - 1u), (uint32_t)c.n2);
+    const int n2 = c.n2, w2 = c.w2;
+    uint32_t p = 0u, u = 0u;
+    if (live) read_record(c, s, sgpr(c.st[i].B), &p, &u);
     const bool sub = (int)u < n2;
+    const uint16_t *__restrict__ src = c.phi[cur];
+    uint16_t *__restrict__ dst = c.phi[nxt];
+    const int j0 = jr * JR, j1 = min(j0 + JR, i);
+    if (live) {
+        int j = j0;
+        for (; j + 8 <= j1; j += 8) {
+            uint16_t x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = src[(size_t)(j + q) * Kp + p];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) dst[(size_t)(j + q) * Kp + s] = x[q];
+        }
+        for (; j < j1; ++j) dst[(size_t)j * Kp + s] = src[(size_t)j * Kp + p];
+        if (i >= j0 && i < j0 + JR) dst[(size_t)i * Kp + s] = (uint16_t)(sub ? u : DEL16);
+    }
+    if (jr != 0) return;
     uint32_t d = 0u;
     if (live) {
         d = c.cand[(size_t)u * Kp + p];
@@ -499,83 +580,104 @@ __global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i) {
             c.img[nxt][(size_t)k * Kp + s] = im;
         }
         c.ein[nxt][s] = e;
-    }
-    // mapping: copy the parent's, append u; collect Phi of the next level
-    const int v = i + 1;
-    const bool next = v < c.n1;
-    if (next) {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) s_set[q * WT + tid] = 0u;
-    }
-    const uint32_t *planes1 = c.a1 + (size_t)c.n1 * c.w1;
-    auto collect = [&](int j, uint32_t x, uint32_t rowbits) {
-        if (!((rowbits >> (j & 31)) & 1u) || x == DEL16) return;
-        atomicOr(&s_set[(x >> 5) * WT + tid], 1u << (x & 31u));
-#pragma unroll
-        for (int b = 0; b < PL; ++b) {
-            if (b < P && ((planes1[((size_t)b * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u))
-                atomicOr(&s_set[((1 + b) * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
-        }
-    };
-    uint32_t rowbits = 0u;
-    for (int j = 0; j < i; ++j) {
-        if ((j & 31) == 0 && next) rowbits = sgpr(earlier_word(c, v, j >> 5, v));
-        if (live) {
-            const uint32_t x = c.phi[cur][(size_t)j * Kp + p];
-            c.phi[nxt][(size_t)j * Kp + s] = (uint16_t)x;
-            if (next) collect(j, x, rowbits);
-        }
-    }
-    if (live) {
-        const uint32_t x = sub ? u : DEL16;
-        c.phi[nxt][(size_t)i * Kp + s] = (uint16_t)x;
-        if (next) {
-            if ((i & 31) == 0) rowbits = sgpr(earlier_word(c, v, i >> 5, v));
-            collect(i, x, rowbits);
-        }
-    }
-    if (next && live) {
-        for (int b = 0; b < 1 + P && b < 1 + PL; ++b)
-            for (int k = 0; k < w2; ++k) c.sets[(size_t)(b * w2 + k) * Kp + s] = s_set[(b * W + k) * WT + tid];
+        if (i + 1 < c.n1)
+            for (int k = 0; k < (1 + c.planes) * w2; ++k) c.sets[(size_t)k * Kp + s] = 0u;
     }
     const uint32_t mn = wave_umin(live ? d : INVALID), mx = wave_umax(live ? d : 0u);
     if ((tid & 63) == 0) {
-        atomicMin(&c.st[v].m0, mn);
-        atomicMax(&c.st[v].mmax, mx);
+        atomicMin(&c.st[i + 1].m0, mn);
+        atomicMax(&c.st[i + 1].mmax, mx);
+    }
+}
+
+// ------------------------------------------------------------------ sets
+// Phi of level v = i + 1 for the new slots: the images of v's earlier
+// neighbours j in range jr, OR-ed into sets (cleared by the update).
+template <int W, int PL>
+__global__ __launch_bounds__(WT) void wide_sets(WideCtx c, int i, int utiles, int nranges) {
+    constexpr int NS = (1 + PL) * W;
+    __shared__ uint32_t s_set[NS * WT];   // column tid: this thread's partial sets
+    const int jr = blockIdx.x / utiles, tile = blockIdx.x % utiles;
+    const uint32_t Bn = sgpr(c.st[i + 1].B);
+    if ((uint32_t)tile * WT >= Bn) return;
+    const int tid = threadIdx.x;
+    const uint32_t s = (uint32_t)tile * WT + tid;
+    const bool live = s < Bn;
+    const uint32_t Kp = c.Kp;
+    const int nxt = (i + 1) & 1, v = i + 1, P = c.planes, w2 = c.w2;
+    const uint16_t *phin = c.phi[nxt];
+    const uint32_t *planes1 = c.a1 + (size_t)c.n1 * c.w1;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) s_set[q * WT + tid] = 0u;
+    const int j0 = jr * JR, j1 = min(j0 + JR, v);
+    for (int k = j0 >> 5; k < (j1 + 31) >> 5; ++k) {
+        uint32_t nb = sgpr(earlier_word(c, v, k, j1));
+        if (32 * k < j0) nb &= ~((1u << (j0 - 32 * k)) - 1u);
+        while (nb) {
+            const int j = 32 * k + __builtin_ctz(nb);
+            nb &= nb - 1u;
+            if (!live) continue;
+            const uint32_t x = phin[(size_t)j * Kp + s];
+            if (x == DEL16) continue;
+            atomicOr(&s_set[(x >> 5) * WT + tid], 1u << (x & 31u));
+#pragma unroll
+            for (int b = 0; b < PL; ++b) {
+                if (b < P && ((planes1[((size_t)b * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u))
+                    atomicOr(&s_set[((1 + b) * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
+            }
+        }
+    }
+    if (!live) return;
+    for (int b = 0; b < 1 + P && b < 1 + PL; ++b) {
+        for (int k = 0; k < w2; ++k) {
+            const uint32_t word = s_set[(b * W + k) * WT + tid];
+            uint32_t *dstw = &c.sets[(size_t)(b * w2 + k) * Kp + s];
+            if (nranges == 1) *dstw = word;
+            else if (word) atomicOr(dstw, word);
+        }
     }
 }
 
 // ------------------------------------------------------------------ final
-__global__ __launch_bounds__(ST) void wide_final(WideCtx c) {
-    __shared__ unsigned long long s_key[ST / 64];
-    const int t = threadIdx.x;
+// Every leaf's total (Sec. 4.4.1); the least (total, slot) wins.
+__global__ __launch_bounds__(WT) void wide_final_keys(WideCtx c) {
+    __shared__ unsigned long long s_key[NWV];
     const int n1 = c.n1, cur = n1 & 1;
-    const uint32_t B = c.st[n1].B;
-    unsigned long long best = ~0ull;
-    for (uint32_t s = t; s < B; s += ST) {
+    const uint32_t B = sgpr(c.st[n1].B);
+    if ((uint32_t)blockIdx.x * WT >= B) return;
+    const uint32_t s = blockIdx.x * WT + threadIdx.x;
+    unsigned long long key = ~0ull;
+    if (s < B) {
         uint32_t used = 0u;
         for (int k = 0; k < c.w2; ++k) used += (uint32_t)__popc(c.img[cur][(size_t)k * c.Kp + s]);
         const uint64_t total = (uint64_t)c.ped[cur][s] + (uint64_t)c.c.vins * (uint64_t)(c.n2 - (int)used) +
                                (uint64_t)c.c.eins * (uint64_t)(c.m2 - (int)c.ein[cur][s]);
-        const unsigned long long key = (total << 32) | s;
-        best = key < best ? key : best;
+        key = (total << 32) | s;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
-        const unsigned long long other = (unsigned long long)__shfl_xor((long long)best, o);
-        best = other < best ? other : best;
+        const unsigned long long other = (unsigned long long)__shfl_xor((long long)key, o);
+        key = other < key ? other : key;
     }
-    if ((t & 63) == 0) s_key[t >> 6] = best;
+    if ((threadIdx.x & 63) == 0) s_key[threadIdx.x >> 6] = key;
     __syncthreads();
-    best = s_key[0];
+    if (threadIdx.x == 0) {
+        unsigned long long m = s_key[0];
 #pragma unroll
-    for (int k = 1; k < ST / 64; ++k) best = s_key[k] < best ? s_key[k] : best;
+        for (int k = 1; k < NWV; ++k) m = s_key[k] < m ? s_key[k] : m;
+        atomicMin(c.best, m);
+    }
+}
+
+__global__ __launch_bounds__(WT) void wide_final_map(WideCtx c) {
+    const int n1 = c.n1, cur = n1 & 1;
+    const unsigned long long best = *c.best;
     const uint32_t slot = (uint32_t)(best & 0xffffffffull);
-    if (t == 0) {
+    if (threadIdx.x == 0) {
         *c.out_dist = (int32_t)(best >> 32);
         if (c.out_cand) *c.out_cand = (int64_t)*c.ce;
     }
-    for (int j = t; j < n1; j += ST) {
+    for (int j = threadIdx.x; j < n1; j += WT) {
         const uint32_t x = c.phi[cur][(size_t)j * c.Kp + slot];
         c.out_map[j] = x == DEL16 ? -1 : (int32_t)x;
     }
@@ -584,7 +686,7 @@ __global__ __launch_bounds__(ST) void wide_final(WideCtx c) {
 // ------------------------------------------------------------------ host side
 
 struct Layout {
-    size_t ped[2], ein[2], img[2], phi[2], sets, cand, cnt, blk, rec, hist, st, ce, total;
+    size_t ped[2], ein[2], img[2], phi[2], sets, cand, cnt, blk, pre, rec, hist, st, ce, best, total;
 };
 
 Layout layout(int n1, int n2, int w2, int planes, uint32_t Kp) {
@@ -595,6 +697,7 @@ Layout layout(int n1, int n2, int w2, int planes, uint32_t Kp) {
         off += (bytes + 255) & ~(size_t)255;
         return o;
     };
+    const int S = w2 > 1 ? std::min(w2, MAXS) : 1;
     for (int k = 0; k < 2; ++k) {
         L.ped[k] = take((size_t)Kp * 4);
         L.ein[k] = take((size_t)Kp * 4);
@@ -603,17 +706,27 @@ Layout layout(int n1, int n2, int w2, int planes, uint32_t Kp) {
     }
     L.sets = take((size_t)(1 + planes) * w2 * Kp * 4);
     L.cand = take((size_t)(n2 + 1) * Kp * 4);
-    L.cnt = take((size_t)Kp * 4);
-    L.blk = take((size_t)2 * (Kp / WT) * 4);
+    L.cnt = take((size_t)S * Kp * 4);
+    L.blk = take((size_t)2 * S * (Kp / WT) * 4);
+    L.pre = take((size_t)2 * (Kp / WT) * 4);
     L.rec = take((size_t)Kp * 4);
     L.hist = take((size_t)HB * 4);
     L.st = take((size_t)(n1 + 1) * sizeof(LevelState));
     L.ce = take(8);
+    L.best = take(8);
     L.total = off;
     return L;
 }
 
 uint32_t slot_stride(int K) { return (uint32_t)((K + WT - 1) / WT) * WT; }
+
+// Column chunks for a level of `tiles` parent tiles: enough workgroups to
+// cover the device twice over, at most one chunk per target word.
+int column_chunks(int tiles, int w2, int cus) {
+    if (w2 <= 1) return 1;
+    const int want = (2 * cus + tiles - 1) / tiles;
+    return std::max(1, std::min({want, w2, MAXS}));
+}
 
 template <int W, int PL>
 hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStream_t stream) {
@@ -623,32 +736,37 @@ hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStr
     uint64_t bound = 1;   // parents at level i are at most min(K, (n2 + 1)^i)
     for (int i = 0; i < c.n1; ++i) {
         const int tiles = (int)((bound + WT - 1) / WT);
-        int S = 1;
-        if (c.w2 > 1) {
-            const int want = (8 * cus + tiles - 1) / tiles;
-            S = want < c.w2 ? want : c.w2;
-            if (S < 1) S = 1;
-        }
+        const int S = column_chunks(tiles, c.w2, cus);
+        const int items = tiles * S;
+        const int egrid = std::min(items, 8 * cus);
         if (small)
-            hipLaunchKernelGGL((wide_expand<W, PL, true>), dim3(tiles * S), dim3(WT), 0, stream, c, i, S);
+            hipLaunchKernelGGL((wide_expand<W, PL, true>), dim3(egrid), dim3(WT), 0, stream, c, i, S, tiles);
         else
-            hipLaunchKernelGGL((wide_expand<W, PL, false>), dim3(tiles * S), dim3(WT), 0, stream, c, i, S);
+            hipLaunchKernelGGL((wide_expand<W, PL, false>), dim3(egrid), dim3(WT), 0, stream, c, i, S, tiles);
         hipLaunchKernelGGL(wide_select, dim3(1), dim3(ST), 0, stream, c, i, 0);
         if (refine_possible) {
             for (int r = 1; r <= 2; ++r) {
-                hipLaunchKernelGGL(wide_refine, dim3(tiles), dim3(WT), 0, stream, c, i);
+                hipLaunchKernelGGL(wide_refine, dim3(items), dim3(WT), 0, stream, c, i, S, tiles);
                 hipLaunchKernelGGL(wide_select, dim3(1), dim3(ST), 0, stream, c, i, r);
             }
         }
-        hipLaunchKernelGGL(wide_count, dim3(tiles), dim3(WT), 0, stream, c, i, tiles);
-        hipLaunchKernelGGL(wide_scan, dim3(1), dim3(ST), 0, stream, c, tiles);
-        hipLaunchKernelGGL(wide_compact, dim3(tiles), dim3(WT), 0, stream, c, i, tiles);
+        hipLaunchKernelGGL(wide_count, dim3(items), dim3(WT), 0, stream, c, i, S, tiles);
+        hipLaunchKernelGGL(wide_scan, dim3(1), dim3(ST), 0, stream, c, S, tiles);
+        hipLaunchKernelGGL(wide_compact, dim3(items), dim3(WT), 0, stream, c, i, S, tiles);
         const uint64_t grown = bound * (uint64_t)(c.n2 + 1);
         bound = grown < c.K ? grown : c.K;
         const int utiles = (int)((bound + WT - 1) / WT);
-        hipLaunchKernelGGL((wide_update<W, PL>), dim3(utiles), dim3(WT), 0, stream, c, i);
+        const int ranges = i / JR + 1;   // entries 0..i
+        hipLaunchKernelGGL(wide_update, dim3(utiles * ranges), dim3(WT), 0, stream, c, i, utiles);
+        if (i + 1 < c.n1) {
+            const int sranges = (i + 1 + JR - 1) / JR;   // earlier neighbours 0..i of v = i + 1
+            hipLaunchKernelGGL((wide_sets<W, PL>), dim3(utiles * sranges), dim3(WT), 0, stream, c, i, utiles,
+                               sranges);
+        }
     }
-    hipLaunchKernelGGL(wide_final, dim3(1), dim3(ST), 0, stream, c);
+    const int ftiles = (int)((bound + WT - 1) / WT);
+    hipLaunchKernelGGL(wide_final_keys, dim3(ftiles), dim3(WT), 0, stream, c);
+    hipLaunchKernelGGL(wide_final_map, dim3(1), dim3(WT), 0, stream, c);
     return hipGetLastError();
 }
 
@@ -676,7 +794,7 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
     const uint32_t Kp = slot_stride(K);
     const Layout L = layout(g1.n, g2.n, g2.w, planes, Kp);
     if (K < 1 || K > kWideMaxK || L.total > ws_bytes || W > 16 || g1.n > GED_MAX_VERTICES ||
-        g2.n > GED_MAX_VERTICES)
+        g2.n > GED_MAX_VERTICES || cus < 1)
         return hipErrorInvalidValue;
     char *base = static_cast<char *>(ws);
     WideCtx c{};
@@ -703,10 +821,12 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
     c.cand = reinterpret_cast<uint32_t *>(base + L.cand);
     c.cnt = reinterpret_cast<uint32_t *>(base + L.cnt);
     c.blk = reinterpret_cast<uint32_t *>(base + L.blk);
+    c.pre = reinterpret_cast<uint32_t *>(base + L.pre);
     c.rec = reinterpret_cast<uint32_t *>(base + L.rec);
     c.hist = reinterpret_cast<uint32_t *>(base + L.hist);
     c.st = reinterpret_cast<LevelState *>(base + L.st);
     c.ce = reinterpret_cast<unsigned long long *>(base + L.ce);
+    c.best = reinterpret_cast<unsigned long long *>(base + L.best);
     c.out_dist = dist;
     c.out_map = map;
     c.out_cand = cand;
