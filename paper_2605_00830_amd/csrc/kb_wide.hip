@@ -30,13 +30,15 @@
 //            slot, then target vertex ascending, then the deletion): every
 //            child below T, and ties at T while the quota K - #below lasts,
 //            counted from the first parent on, written as records
-//            parent << 10 | column at their beam position -- the new beam is
-//            again in generation order and never needs sorting.
+//            parent << 10 | column (and the child's PED) at their beam
+//            position -- the new beam is again in generation order and never
+//            needs sorting.
 //   update   per (new slot, range of 64 mapping entries): the mapping copied
-//            from the parent with u appended; the first range also sets PED,
-//            Img and e_in and clears the Phi sets.
-//   sets     per (new slot, range of 64 mapping entries): the images of the
-//            next vertex's earlier neighbours in the range, OR-ed into Phi.
+//            from the parent with u appended; the first range also sets Img
+//            and e_in (compaction wrote the PED) and, when one range covers
+//            the mapping, the next level's Phi sets.
+//   sets     (mappings past 64 entries) per (new slot, range): the images of
+//            the next vertex's earlier neighbours in the range, OR-ed into Phi.
 // After the last level every leaf is completed (Sec. 4.4.1) and the first
 // leaf of least total in beam order is returned.
 #include <algorithm>
@@ -202,7 +204,6 @@ __global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S, int t
 
     for (int b = tid; b < nbins; b += WT) s_hist[b] = 0u;
     const uint32_t *planes2 = c.a2 + (size_t)n2 * w2;
-    uint32_t nvalid = 0;
     int staged = -1;
     for (int w = blockIdx.x; w < tiles * S; w += gridDim.x) {
         const int chunk = w / tiles, tile = w % tiles;
@@ -271,17 +272,13 @@ __global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S, int t
                 if (PL > 0) d += mul_cost<SMALL>(rl, esub);
                 const bool ok = live && !((used >> bit) & 1u);
                 if (live) c.cand[(size_t)u * Kp + p] = ok ? d : INVALID;
-                if (ok) {
-                    atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
-                    ++nvalid;
-                }
+                if (ok) atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
             }
         }
         if (cc.del && live) {
             const uint32_t d = basel + vdel;
             c.cand[(size_t)n2 * Kp + p] = d;
             atomicAdd(&s_hist[min((d - m0) >> shift, (uint32_t)HB - 1u)], 1u);
-            ++nvalid;
         }
     }
     __syncthreads();
@@ -289,51 +286,52 @@ __global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S, int t
         const uint32_t h = s_hist[b];
         if (h) atomicAdd(&c.hist[b], h);
     }
-    const uint32_t tot = wave_sum(nvalid);
-    if ((tid & 63) == 0 && tot) atomicAdd(&c.st[i].V, tot);
 }
 
 // ------------------------------------------------------------------ select
 // round 0 reads the expansion histogram; rounds 1 and 2 read refinement
 // histograms while a refinement is pending.  Clears the histogram it read.
+// Round 0 also sets the next level's beam size and PED bounds: m0 from the
+// least non-empty bin (the least child survives), mmax from the top of the
+// threshold's bin (or of the last non-empty bin when every child survives).
 __global__ __launch_bounds__(ST) void wide_select(WideCtx c, int i, int round) {
     __shared__ uint32_t s_tmp[ST / 64];
     __shared__ uint32_t s_res[2];
+    __shared__ uint32_t s_first, s_last;
     LevelState *L = c.st + i;
     const int t = threadIdx.x;
     if (round > 0 && L->refine == 0u) return;
     const uint32_t K = c.K;
-    const uint32_t V = L->V;
+    if (t == 0) {
+        s_first = HB;
+        s_last = 0u;
+    }
     uint32_t h[HB / ST];
-    uint32_t sum = 0;
+    uint32_t sum = 0, first = HB, last = 0;
 #pragma unroll
     for (int q = 0; q < HB / ST; ++q) {
-        h[q] = c.hist[t * (HB / ST) + q];
+        const uint32_t b = (uint32_t)(t * (HB / ST) + q);
+        h[q] = c.hist[b];
         sum += h[q];
-    }
-    if (round == 0 && V <= K) {
-        // every child survives
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < HB / ST; ++q) c.hist[t * (HB / ST) + q] = 0u;
-        if (t == 0) {
-            L->T = INVALID;
-            L->quota = 0u;
-            L->refine = 0u;
-            c.st[i + 1].B = V;
-            *c.ce += V;
+        if (h[q]) {
+            first = min(first, b);
+            last = max(last, b);
         }
-        return;
     }
-    const uint32_t target = round == 0 ? K : L->need;
-    uint32_t tot;
-    const uint32_t pre = block_excl_scan<ST / 64>(sum, s_tmp, &tot);
-    if (pre < target && target <= pre + sum) {
+    const uint32_t target0 = round == 0 ? K : L->need;
+    uint32_t V;   // children in the histogram
+    const uint32_t pre = block_excl_scan<ST / 64>(sum, s_tmp, &V);
+    if (round == 0) {
+        if (first < (uint32_t)HB) atomicMin(&s_first, first);
+        if (sum) atomicMax(&s_last, last);
+    }
+    const bool all = round == 0 && V <= K;   // every child survives
+    if (!all && pre < target0 && target0 <= pre + sum) {
         uint32_t below = pre, bin = 0u;
         bool found = false;
 #pragma unroll
         for (int q = 0; q < HB / ST; ++q) {
-            if (!found && below + h[q] >= target) {
+            if (!found && below + h[q] >= target0) {
                 found = true;
                 bin = (uint32_t)q;
             }
@@ -346,28 +344,42 @@ __global__ __launch_bounds__(ST) void wide_select(WideCtx c, int i, int round) {
 #pragma unroll
     for (int q = 0; q < HB / ST; ++q) c.hist[t * (HB / ST) + q] = 0u;
     if (t != 0) return;
-    const uint32_t bin = s_res[0], below = s_res[1];
     if (round == 0) {
-        c.st[i + 1].B = K;
+        const uint32_t m0 = L->m0, shift = L->shift, top = (1u << shift) - 1u;
+        LevelState *N = c.st + i + 1;
+        L->V = V;
         *c.ce += V;
-        const uint32_t shift = L->shift;
+        N->m0 = m0 + (s_first << shift);
+        if (all) {
+            L->T = INVALID;
+            L->quota = 0u;
+            L->refine = 0u;
+            N->B = V;
+            N->mmax = m0 + (s_last << shift) + top;
+            return;
+        }
+        const uint32_t bin = s_res[0], below = s_res[1];
+        N->B = K;
+        N->mmax = m0 + (bin << shift) + top;
         if (shift == 0u) {
-            L->T = L->m0 + bin;
+            L->T = m0 + bin;
             L->quota = K - below;
             L->refine = 0u;
         } else {
-            L->lo = L->m0 + (bin << shift);
+            L->lo = m0 + (bin << shift);
             L->rwidth = shift;
             L->rbin = shift > (uint32_t)HBITS ? shift - HBITS : 0u;
             L->need = K - below;
             L->refine = 1u;
         }
     } else {
+        const uint32_t bin = s_res[0], below = s_res[1];
         const uint32_t rbin = L->rbin;
         if (rbin == 0u) {
             L->T = L->lo + bin;
             L->quota = L->need - below;
             L->refine = 0u;
+            c.st[i + 1].mmax = L->T;
         } else {
             L->lo += bin << rbin;
             L->rwidth = rbin;
@@ -522,7 +534,10 @@ __global__ __launch_bounds__(WT) void wide_compact(WideCtx c, int i, int S, int 
             keep = true;
             --keqc;
         }
-        if (keep && pos < c.K) c.rec[pos] = (p << CBITS) | (uint32_t)col;
+        if (keep && pos < c.K) {
+            c.rec[pos] = (p << CBITS) | (uint32_t)col;
+            c.ped[(i + 1) & 1][pos] = d;
+        }
         pos += keep ? 1u : 0u;
     }
 }
@@ -536,8 +551,58 @@ __device__ __forceinline__ void read_record(const WideCtx &c, uint32_t s, uint32
 }
 
 // ------------------------------------------------------------------ update
-// One workgroup per (mapping range jr, slot tile), range-major.
-__global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles) {
+// Phi of level v for slot s from the images x(j) of v's earlier neighbours j
+// in [j0, j1): bits OR-ed into this thread's LDS column of s_set.
+template <int W, int PL, class GetX>
+__device__ __forceinline__ void collect_phi(const WideCtx &c, int v, int j0, int j1, bool live, uint32_t *s_set,
+                                            GetX getx) {
+    constexpr int NS = (1 + PL) * W;
+    const int tid = threadIdx.x;
+    const uint32_t *planes1 = c.a1 + (size_t)c.n1 * c.w1;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) s_set[q * WT + tid] = 0u;
+    for (int k = j0 >> 5; k < (j1 + 31) >> 5; ++k) {
+        uint32_t nb = sgpr(earlier_word(c, v, k, j1));
+        if (32 * k < j0) nb &= ~((1u << (j0 - 32 * k)) - 1u);
+        while (nb) {
+            const int j = 32 * k + __builtin_ctz(nb);
+            nb &= nb - 1u;
+            if (!live) continue;
+            const uint32_t x = getx(j);
+            if (x == DEL16) continue;
+            atomicOr(&s_set[(x >> 5) * WT + tid], 1u << (x & 31u));
+#pragma unroll
+            for (int b = 0; b < PL; ++b) {
+                if (b < c.planes && ((planes1[((size_t)b * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u))
+                    atomicOr(&s_set[((1 + b) * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
+            }
+        }
+    }
+}
+
+// Store (whole) or OR in (partial) this thread's Phi words for slot s.
+template <int W, int PL>
+__device__ __forceinline__ void store_phi(const WideCtx &c, uint32_t s, const uint32_t *s_set, bool whole) {
+    const int tid = threadIdx.x;
+    for (int b = 0; b < 1 + c.planes && b < 1 + PL; ++b) {
+        for (int k = 0; k < c.w2; ++k) {
+            const uint32_t word = s_set[(b * W + k) * WT + tid];
+            uint32_t *dstw = &c.sets[(size_t)(b * c.w2 + k) * c.Kp + s];
+            if (whole) *dstw = word;
+            else if (word) atomicOr(dstw, word);
+        }
+    }
+}
+
+// One workgroup per (mapping range jr, slot tile), range-major: the
+// mapping copied from the parent with u appended.  The first range also
+// sets Img and e_in (the PED came with the record); when one range holds
+// the whole mapping it also builds the next level's Phi, else it clears
+// Phi for the sets kernel.
+template <int W, int PL>
+__global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles, int nranges) {
+    constexpr int NS = (1 + PL) * W;
+    __shared__ uint32_t s_set[NS * WT];
     const int jr = blockIdx.x / utiles, tile = blockIdx.x % utiles;
     const uint32_t Bn = sgpr(c.st[i + 1].B);
     if ((uint32_t)tile * WT >= Bn) return;
@@ -566,10 +631,7 @@ __global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles) 
         if (i >= j0 && i < j0 + JR) dst[(size_t)i * Kp + s] = (uint16_t)(sub ? u : DEL16);
     }
     if (jr != 0) return;
-    uint32_t d = 0u;
     if (live) {
-        d = c.cand[(size_t)u * Kp + p];
-        c.ped[nxt][s] = d;
         uint32_t e = c.ein[cur][p];
         for (int k = 0; k < w2; ++k) {
             uint32_t im = c.img[cur][(size_t)k * Kp + p];
@@ -580,62 +642,38 @@ __global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles) 
             c.img[nxt][(size_t)k * Kp + s] = im;
         }
         c.ein[nxt][s] = e;
-        if (i + 1 < c.n1)
-            for (int k = 0; k < (1 + c.planes) * w2; ++k) c.sets[(size_t)k * Kp + s] = 0u;
     }
-    const uint32_t mn = wave_umin(live ? d : INVALID), mx = wave_umax(live ? d : 0u);
-    if ((tid & 63) == 0) {
-        atomicMin(&c.st[i + 1].m0, mn);
-        atomicMax(&c.st[i + 1].mmax, mx);
+    const int v = i + 1;
+    if (v >= c.n1) return;
+    if (nranges == 1) {
+        collect_phi<W, PL>(c, v, 0, v, live, s_set, [&](int j) -> uint32_t {
+            return j < i ? (uint32_t)src[(size_t)j * Kp + p] : (sub ? u : DEL16);
+        });
+        if (live) store_phi<W, PL>(c, s, s_set, true);
+    } else if (live) {
+        for (int k = 0; k < (1 + c.planes) * w2; ++k) c.sets[(size_t)k * Kp + s] = 0u;
     }
 }
 
 // ------------------------------------------------------------------ sets
-// Phi of level v = i + 1 for the new slots: the images of v's earlier
-// neighbours j in range jr, OR-ed into sets (cleared by the update).
+// Phi of level v = i + 1 for the new slots when the mapping spans several
+// ranges: the images of v's earlier neighbours in range jr, OR-ed into the
+// sets the update cleared.
 template <int W, int PL>
-__global__ __launch_bounds__(WT) void wide_sets(WideCtx c, int i, int utiles, int nranges) {
+__global__ __launch_bounds__(WT) void wide_sets(WideCtx c, int i, int utiles) {
     constexpr int NS = (1 + PL) * W;
-    __shared__ uint32_t s_set[NS * WT];   // column tid: this thread's partial sets
+    __shared__ uint32_t s_set[NS * WT];
     const int jr = blockIdx.x / utiles, tile = blockIdx.x % utiles;
     const uint32_t Bn = sgpr(c.st[i + 1].B);
     if ((uint32_t)tile * WT >= Bn) return;
-    const int tid = threadIdx.x;
-    const uint32_t s = (uint32_t)tile * WT + tid;
+    const uint32_t s = (uint32_t)tile * WT + threadIdx.x;
     const bool live = s < Bn;
-    const uint32_t Kp = c.Kp;
-    const int nxt = (i + 1) & 1, v = i + 1, P = c.planes, w2 = c.w2;
-    const uint16_t *phin = c.phi[nxt];
-    const uint32_t *planes1 = c.a1 + (size_t)c.n1 * c.w1;
-#pragma unroll
-    for (int q = 0; q < NS; ++q) s_set[q * WT + tid] = 0u;
+    const int v = i + 1;
+    const uint16_t *phin = c.phi[v & 1];
     const int j0 = jr * JR, j1 = min(j0 + JR, v);
-    for (int k = j0 >> 5; k < (j1 + 31) >> 5; ++k) {
-        uint32_t nb = sgpr(earlier_word(c, v, k, j1));
-        if (32 * k < j0) nb &= ~((1u << (j0 - 32 * k)) - 1u);
-        while (nb) {
-            const int j = 32 * k + __builtin_ctz(nb);
-            nb &= nb - 1u;
-            if (!live) continue;
-            const uint32_t x = phin[(size_t)j * Kp + s];
-            if (x == DEL16) continue;
-            atomicOr(&s_set[(x >> 5) * WT + tid], 1u << (x & 31u));
-#pragma unroll
-            for (int b = 0; b < PL; ++b) {
-                if (b < P && ((planes1[((size_t)b * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u))
-                    atomicOr(&s_set[((1 + b) * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
-            }
-        }
-    }
-    if (!live) return;
-    for (int b = 0; b < 1 + P && b < 1 + PL; ++b) {
-        for (int k = 0; k < w2; ++k) {
-            const uint32_t word = s_set[(b * W + k) * WT + tid];
-            uint32_t *dstw = &c.sets[(size_t)(b * w2 + k) * Kp + s];
-            if (nranges == 1) *dstw = word;
-            else if (word) atomicOr(dstw, word);
-        }
-    }
+    collect_phi<W, PL>(c, v, j0, j1, live, s_set,
+                       [&](int j) -> uint32_t { return (uint32_t)phin[(size_t)j * c.Kp + s]; });
+    if (live) store_phi<W, PL>(c, s, s_set, false);
 }
 
 // ------------------------------------------------------------------ final
@@ -756,13 +794,11 @@ hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStr
         const uint64_t grown = bound * (uint64_t)(c.n2 + 1);
         bound = grown < c.K ? grown : c.K;
         const int utiles = (int)((bound + WT - 1) / WT);
-        const int ranges = i / JR + 1;   // entries 0..i
-        hipLaunchKernelGGL(wide_update, dim3(utiles * ranges), dim3(WT), 0, stream, c, i, utiles);
-        if (i + 1 < c.n1) {
-            const int sranges = (i + 1 + JR - 1) / JR;   // earlier neighbours 0..i of v = i + 1
-            hipLaunchKernelGGL((wide_sets<W, PL>), dim3(utiles * sranges), dim3(WT), 0, stream, c, i, utiles,
-                               sranges);
-        }
+        // ranges of mapping entries 0..i (also of the next vertex's earlier neighbours)
+        const int ranges = i / JR + 1;
+        hipLaunchKernelGGL((wide_update<W, PL>), dim3(utiles * ranges), dim3(WT), 0, stream, c, i, utiles, ranges);
+        if (i + 1 < c.n1 && ranges > 1)
+            hipLaunchKernelGGL((wide_sets<W, PL>), dim3(utiles * ranges), dim3(WT), 0, stream, c, i, utiles);
     }
     const int ftiles = (int)((bound + WT - 1) / WT);
     hipLaunchKernelGGL(wide_final_keys, dim3(ftiles), dim3(WT), 0, stream, c);
