@@ -265,6 +265,46 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
     return out
 
 
+# The paper's single-pair runtimes on an A100 (other hardware: context only):
+# runtime versus K for two 20-vertex graphs, and K = 5000 at 500 vertices.
+LARGE_K_RUNS = [(20, 6, 1000, 35.0), (20, 6, 100_000, 120.0), (20, 6, 700_000, 473.0),
+                (20, 6, 1_200_000, 780.0), (500, 7, 5000, 428.0)]
+
+
+def large_k_measure(ged, reps: int = 5):
+    """Single-pair large-K search (ged_wide_*) on the paper's runtime shapes: median of
+    `reps` timed runs (HIP events on the launch stream) after one warm-up run."""
+    import torch
+    from paper_2605_00830_amd import synth
+    out = []
+    for n, seed, K, paper_ms in LARGE_K_RUNS:
+        w = synth.pair_er_large_k(n, seed)
+        db = ged.Database(w.graphs)
+        wide = ged.Wide(db, 0, 1, K)
+        dist, maps, cand = wide.outputs()
+        s = torch.cuda.current_stream()
+        wide.run(w.costs, dist, maps, cand, stream=s)
+        s.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            wide.run(w.costs, dist, maps, cand, stream=s)
+            e1.record(s)
+            s.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        ce = int(cand.item())
+        out.append({"workload": w.name, "n": n, "K": K, "costs": list(w.costs), "ms": round(ms, 3),
+                    "dist": int(dist.item()), "children_evaluated": ce, "ce_per_s": round(ce / (ms / 1e3), 1),
+                    "workspace_bytes": wide.bytes, "paper_a100_ms": paper_ms,
+                    "ratio_to_paper_a100": round(paper_ms / ms, 1)})
+        log(f"large K: n={n} K={K}: {ms:.3f} ms, {ce / (ms / 1e3):.3e} children/s")
+        wide.close()
+        db.close()
+    return out
+
+
 def workload(name: str):
     from paper_2605_00830_amd import synth
     if name == "batch":
@@ -275,6 +315,8 @@ def workload(name: str):
         return synth.query_molecule_10_70(10000), 500
     if name == "stress":
         return synth.stress_er_100_500(256), 4
+    if name == "molecule":
+        return synth.batch_molecule_k64(10000), 1000
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -283,11 +325,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batch", choices=["batch", "pair", "query", "stress", "serve"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "pair", "query", "stress", "molecule", "serve"])
     ap.add_argument("--serve-queries", type=int, default=100000,
                     help="queries of the serving measurement (the serving mix has 100,000)")
     ap.add_argument("--serve-db", type=int, default=100000, help="database graphs of the serving measurement")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-large-k", action="store_true", help="skip the single-pair large-K measurement")
+    ap.add_argument("--large-k-only", action="store_true",
+                    help="run only the single-pair large-K measurement and print its JSON")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS, help="server streams per size class")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -310,6 +355,9 @@ def main():
     from paper_2605_00830_amd import ged
 
     torch.cuda.set_device(0)
+    if args.large_k_only:
+        print(json.dumps({"large_k": large_k_measure(ged)}), flush=True)
+        return
     if args.workload == "serve":
         from paper_2605_00830_amd import synth
         t0 = time.perf_counter()
@@ -445,6 +493,10 @@ def main():
         parity = {"pairs_checked": int(len(sample)), "bit_exact": ok}
         log(f"cpu oracle: {len(sample) / cw:.1f} pairs/s; GPU parity on sample: {ok}")
 
+    large_k = None
+    if not args.no_large_k and args.workload == "batch":
+        large_k = large_k_measure(ged)
+
     serving = None
     if not args.no_serve and args.workload == "batch":
         from paper_2605_00830_amd import synth
@@ -472,6 +524,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "large_k": large_k,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

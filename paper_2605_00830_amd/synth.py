@@ -271,12 +271,34 @@ def query_molecule_10_70(ndb: int = 10000) -> Workload:
     return Workload(f"query_molecule_n10-70_1x{ndb}_k128", gs, pairs, PAPER_COSTS, 128)
 
 
+def batch_molecule_k64(npairs: int = 10000) -> Workload:
+    """npairs disjoint pairs of molecule-shaped graphs (n 10..70; the molecule graphs of
+    query_molecule_10_70, seed 3), unit costs, K=64: the molecule half of the serving mix."""
+    gs = GraphSet.from_graphs([molecule_graph(3, i) for i in range(1, 2 * npairs + 1)])
+    pairs = np.stack([np.arange(0, 2 * npairs, 2), np.arange(1, 2 * npairs, 2)], 1)
+    return Workload(f"batch_molecule_n10-70_{npairs}pairs_k64", gs, pairs.astype(np.int64), UNIT_COSTS, 64)
+
+
 def stress_er_100_500(npairs: int = 256) -> Workload:
     """npairs ER pairs, n ~ U{100..500}, p ~ U[0.05,0.5], 8 labels, unit costs, K=256 (seed 4)."""
     gs = _er_pairs(4, npairs, 100, 500, 0.05, 0.5, 8)
     pairs = np.stack([np.arange(0, 2 * npairs, 2), np.arange(1, 2 * npairs, 2)], 1)
     return Workload(f"stress_er_n100-500_p0.05-0.5_{npairs}pairs_k256", gs,
                     pairs.astype(np.int64), UNIT_COSTS, 256)
+
+
+def pair_er_large_k(n: int, seed: int) -> Workload:
+    """One ER pair for the single-pair large-K search: n vertices each, p = 0.4, 4 vertex
+    labels, no edge labels, the paper's cost setting 1 (seed 6 for n = 20, 7 for n = 500).
+
+    The shapes of the paper's runtime-versus-K experiment (two 20-vertex graphs) and of its
+    runtime-versus-size experiment (density 0.4, K = 5000); the paper states neither labels
+    nor seeds, so the labels are a reading.
+    """
+    g1 = er_graph(seed, 0, n, n, 0.4, 0.4, 4)
+    g2 = er_graph(seed, 1, n, n, 0.4, 0.4, 4)
+    return Workload(f"pair_er_n{n}_p0.4", GraphSet.from_graphs([g1, g2]),
+                    np.array([[0, 1]], dtype=np.int64), PAPER_COSTS, 0)
 
 
 def mix_graph(seed: int, index: int) -> Graph:
