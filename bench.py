@@ -35,7 +35,11 @@ METRIC = "GED pairs/sec at K=64 batched vs per-pair on 1 GPU; serving p50/p99 la
 # default is 4 queues per process, so the bench asks for enough queues before
 # the runtime starts.
 SERVE_STREAMS = 4
-HW_QUEUES = 4 * SERVE_STREAMS + 1   # four size classes, plus the stream the bench itself uses
+# four size classes x 4 streams need 16 queues of their own, but the process holds
+# other streams as well (torch's, the runtime's): with exactly 17 queues a mid-size
+# stream still shared a queue with a large-query stream (mid p99 55-58 ms at half
+# load); 24 or 32 queues brought it to 1.3 ms in most runs
+HW_QUEUES = 32
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < HW_QUEUES:
     os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
 # int32 VALU peak of MI355X: 256 CUs x 64 lanes x 2.4 GHz, one op per lane per clock

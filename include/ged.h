@@ -305,8 +305,9 @@ typedef struct {
                                  runs.  Streams beyond the process's hardware
                                  queues (HIP: GPU_MAX_HW_QUEUES, 4 by default)
                                  share queues, and a long launch then delays the
-                                 others on its queue: 4 * streams + 1 queues
-                                 keep every stream on its own. */
+                                 others on its queue; give the process well
+                                 over 4 * streams queues (other streams of the
+                                 process take queues too). */
     int32_t queue_capacity;   /* queued (not yet admitted) queries before
                                  ged_server_submit returns GED_EBUSY; 0 = 1<<20 */
 } ged_server_config;
