@@ -51,13 +51,15 @@ def _load():
     graph_args = [ctypes.c_int, P, ctypes.c_int, P, P, P]
     lib.oracle_kbest.argtypes = graph_args + graph_args + [P, i64, P, P]
     lib.oracle_kbest.restype = ctypes.c_int
+    lib.oracle_kbest_ex.argtypes = graph_args + graph_args + [P, i64, ctypes.c_int, P, P]
+    lib.oracle_kbest_ex.restype = ctypes.c_int
     lib.oracle_exact.argtypes = graph_args + graph_args + [P, ctypes.c_double, P, P]
     lib.oracle_exact.restype = ctypes.c_int
     lib.oracle_induced_cost.argtypes = graph_args + graph_args + [P, P, P]
     lib.oracle_induced_cost.restype = ctypes.c_int
     lib.oracle_count_mappings.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.oracle_count_mappings.restype = ctypes.c_double
-    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, P, P, P, P]
+    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, P, P, P, P]
     lib.oracle_kbest_pairs.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -85,15 +87,18 @@ def _check(st: int, what: str):
         raise OracleError(f"{what}: oracle status {st}")
 
 
-def kbest(g1, g2, costs: Sequence[int], K: int) -> Tuple[int, np.ndarray]:
-    """K-Best search g1 -> g2; returns (distance, mapping) with -1 = deleted."""
+def kbest(g1, g2, costs: Sequence[int], K: int, last_complete: bool = False) -> Tuple[int, np.ndarray]:
+    """K-Best search g1 -> g2; returns (distance, mapping) with -1 = deleted.
+
+    last_complete: complete every child of the last level and keep the least total
+    (instead of keeping the K of least partial distance, then completing)."""
     lib = _load()
     keep: list = []
     c = _arr(costs)
     dist = ctypes.c_int64(0)
     mp = np.zeros(max(int(g1.n), 1), dtype=np.int32)
-    st = lib.oracle_kbest(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
-                          ctypes.byref(dist), _ptr(mp))
+    st = lib.oracle_kbest_ex(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
+                             1 if last_complete else 0, ctypes.byref(dist), _ptr(mp))
     _check(st, "kbest")
     return int(dist.value), mp[: int(g1.n)].copy()
 
@@ -140,7 +145,7 @@ def map_offsets(graphs, pairs: np.ndarray) -> np.ndarray:
     return off
 
 
-def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int):
+def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_complete: bool = False):
     """Run the oracle over many pairs of a GraphSet.
 
     Returns (dist int64 [P], maps int32 [sum n_src], offsets int64 [P]).
@@ -163,6 +168,7 @@ def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int):
     failed = ctypes.c_int64(-1)
     st = lib.oracle_kbest_pairs(_ptr(n), _ptr(m), _ptr(voff), _ptr(eoff), _ptr(vl), _ptr(eu),
                                 _ptr(ev), _ptr(el), _ptr(pairs), int(len(pairs)), _ptr(c), int(K),
-                                _ptr(dist), _ptr(maps), _ptr(off), ctypes.byref(failed))
+                                1 if last_complete else 0, _ptr(dist), _ptr(maps), _ptr(off),
+                                ctypes.byref(failed))
     _check(st, f"kbest_pairs (pair {failed.value})")
     return dist, maps[:total], off

@@ -25,6 +25,12 @@
  *                           (Sec. 2.3, Alg. 2), selection of the best K
  *                           (Sec. 4.3) and final insertion of the unmatched
  *                           target vertices (Sec. 4.4.1).
+ *   oracle_kbest_ex      -- the same with a choice of last level: the literal
+ *                           reading above, or "complete then take the minimum":
+ *                           every child of the last level is completed by the
+ *                           insertions of Sec. 4.4.1 and the least total wins
+ *                           (Alg. 1's final minimum taken over all of them
+ *                           instead of over the K kept by partial distance).
  *
  * Readings taken where the paper is silent (each is listed in the design
  * notes): g1 vertices are processed in index order; the children of a node
@@ -289,10 +295,36 @@ static int64_t del_step(const dgraph *g1, const int32_t *c, int i) {
     return d;
 }
 
+/* Insertions that complete a mapping whose used g2 vertices are marked in
+ * `used` (Sec. 4.4.1): every unused g2 vertex and every g2 edge with an
+ * unused end. */
+static int64_t completion(const dgraph *g2, const int32_t *c, const int *used) {
+    int64_t t = 0;
+    for (int u = 0; u < g2->n; u++)
+        if (!used[u]) t += c[2];
+    for (int x = 0; x < g2->n; x++)
+        for (int y = x + 1; y < g2->n; y++)
+            if (edge(g2, x, y) && (!used[x] || !used[y])) t += c[5];
+    return t;
+}
+
+int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
+                    const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
+                    const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
+                    int last_complete, int64_t *dist, int32_t *map_out);
+
 int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                  const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
                  const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
                  int64_t *dist, int32_t *map_out) {
+    return oracle_kbest_ex(n1, vl1, m1, eu1, ev1, el1, n2, vl2, m2, eu2, ev2, el2, costs, K, 0, dist,
+                           map_out);
+}
+
+int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
+                    const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
+                    const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
+                    int last_complete, int64_t *dist, int32_t *map_out) {
     if (!costs_ok(costs) || K < 1) return OR_EINVAL;
     dgraph g1, g2;
     int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1);
@@ -340,9 +372,31 @@ int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const i
             keys[C].order = C;
             C++;
         }
-        /* selection: the K children of least partial edit distance (Sec. 4.3) */
-        qsort(keys, (size_t)C, sizeof(rank_key), cmp_rank);
-        int64_t keep = C < K ? C : K;
+        int64_t keep;
+        if (last_complete && i == n1 - 1) {
+            /* last level, complete-then-minimum: each child's partial edit
+             * distance plus its completion; the least total, the first in
+             * generation order on ties, is the only child kept */
+            int64_t best = INT64_MAX, best_t = 0;
+            for (int64_t t = 0; t < C; t++) {
+                const int32_t *ph = phi + (int64_t)c_par[t] * width;
+                for (int u = 0; u < n2; u++) used[u] = 0;
+                for (int j = 0; j < i; j++)
+                    if (ph[j] != DELETED) used[ph[j]] = 1;
+                if (c_u[t] != DELETED) used[c_u[t]] = 1;
+                const int64_t total = keys[t].ped + completion(&g2, costs, used);
+                if (total < best) {
+                    best = total;
+                    best_t = t;
+                }
+            }
+            keys[0] = keys[best_t];
+            keep = 1;
+        } else {
+            /* selection: the K children of least partial edit distance (Sec. 4.3) */
+            qsort(keys, (size_t)C, sizeof(rank_key), cmp_rank);
+            keep = C < K ? C : K;
+        }
         /* the next beam keeps the survivors in generation order */
         qsort(keys, (size_t)keep, sizeof(rank_key), cmp_order);
         int32_t *nphi = (int32_t *)malloc(sizeof(int32_t) * width * (size_t)keep);
@@ -407,15 +461,15 @@ done:
 int oracle_kbest_pairs(const int32_t *n, const int32_t *m, const int64_t *voff,
                        const int64_t *eoff, const int32_t *vlabel, const int32_t *eu,
                        const int32_t *ev, const int32_t *elabel, const int64_t *pairs,
-                       int64_t npairs, const int32_t *costs, int64_t K, int64_t *dist,
-                       int32_t *map_out, const int64_t *map_off, int64_t *failed_pair) {
+                       int64_t npairs, const int32_t *costs, int64_t K, int last_complete,
+                       int64_t *dist, int32_t *map_out, const int64_t *map_off, int64_t *failed_pair) {
     for (int64_t p = 0; p < npairs; p++) {
         int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
         const int32_t *el_a = elabel ? elabel + eoff[a] : NULL;
         const int32_t *el_b = elabel ? elabel + eoff[b] : NULL;
-        int st = oracle_kbest(n[a], vlabel + voff[a], m[a], eu + eoff[a], ev + eoff[a], el_a,
-                              n[b], vlabel + voff[b], m[b], eu + eoff[b], ev + eoff[b], el_b,
-                              costs, K, dist + p, map_out + map_off[p]);
+        int st = oracle_kbest_ex(n[a], vlabel + voff[a], m[a], eu + eoff[a], ev + eoff[a], el_a,
+                                 n[b], vlabel + voff[b], m[b], eu + eoff[b], ev + eoff[b], el_b,
+                                 costs, K, last_complete, dist + p, map_out + map_off[p]);
         if (st) {
             *failed_pair = p;
             return st;

@@ -11,7 +11,8 @@ same quantity by a different route:
   distance is recomputed from scratch as the cost of all edit operations in
   its path (Sec. 4.2.2), instead of the incremental implied-edge
   scan, and ranking uses the child's mapping tuple itself (deleted = n2) for
-  the generation-order tie-break.
+  the generation-order tie-break; optionally with the complete-then-minimum
+  last level, scored by the padded-permutation cost of each complete path.
 """
 from __future__ import annotations
 
@@ -116,7 +117,10 @@ def partial_cost(g1, g2, c, phi: Sequence[int]) -> int:
     return cost
 
 
-def scratch_beam(g1, g2, c, K: int) -> Tuple[int, List[int]]:
+def scratch_beam(g1, g2, c, K: int, last_complete: bool = False) -> Tuple[int, List[int]]:
+    """last_complete: at the last level every child is scored by the cost of its
+    complete edit path (the padded-permutation form, qap_cost) and the least
+    (cost, mapping tuple) is returned."""
     n1, n2 = int(g1.n), int(g2.n)
     E2 = edge_dict(g2)
 
@@ -133,6 +137,9 @@ def scratch_beam(g1, g2, c, K: int) -> Tuple[int, List[int]]:
                     continue
                 ch = phi + (u,)
                 children.append((partial_cost(g1, g2, c, ch), key(ch), ch))
+        if last_complete and i == n1 - 1:
+            best_c = min((qap_cost(g1, g2, c, perm_from_map(ch, n1, n2)), key(ch), ch) for _, _, ch in children)
+            return best_c[0], list(best_c[2])
         children.sort(key=lambda x: (x[0], x[1]))
         kept = children[:K]
         kept.sort(key=lambda x: x[1])

@@ -210,6 +210,36 @@ def test_kbest_properties(c):
         assert oracle.kbest(g1, g2, c, full)[0] == ex
 
 
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD])
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 8, 1000])
+def test_complete_then_min_matches_scratch_beam(c, K):
+    """Last level completed before the minimum: the oracle against the from-scratch
+    beam, whose last level scores complete edit paths by the padded-permutation form."""
+    for g1, g2 in tiny_pairs(10, 161 + K, 5, 0.5, 3, 2):
+        d, m = oracle.kbest(g1, g2, c, K, last_complete=True)
+        d2, m2 = _pins.scratch_beam(g1, g2, c, K, last_complete=True)
+        assert (d, m.tolist()) == (d2, m2)
+
+
+@pytest.mark.parametrize("c", [UNIT, PAPER, ODD, HIGH])
+def test_complete_then_min_properties(c):
+    """Never worse than the literal last level (its K kept children are a subset of
+    every child), an upper bound of exact GED, equal to the induced cost of its
+    mapping, and exact once K covers every complete mapping."""
+    strict = 0
+    for g1, g2 in tiny_pairs(24, 171, 6, 0.45, 3, 2, n_min=1):
+        ex = oracle.exact(g1, g2, c)[0]
+        full = int(oracle.count_mappings(g1.n, g2.n))
+        for K in (1, 2, 4, 16, full):
+            d, m = oracle.kbest(g1, g2, c, K, last_complete=True)
+            lit = oracle.kbest(g1, g2, c, K)[0]
+            assert ex <= d <= lit
+            strict += d < lit
+            assert d == oracle.induced_cost(g1, g2, c, m)
+        assert oracle.kbest(g1, g2, c, full, last_complete=True)[0] == ex
+    assert strict > 0   # the option changes results somewhere in this sample
+
+
 def test_exact_symmetry_and_triangle():
     gs = [random_small_graph(81, k, 4, 0.5, 2, 2) for k in range(6)]
     for c in (UNIT, PAPER, HIGH):
