@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define GED_ABI_VERSION 1
+#define GED_ABI_VERSION 2
 
 /* Limits of this version. */
 #define GED_MAX_VERTICES 512      /* per graph */
@@ -162,14 +162,24 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
 #define GED_SCHED_AUTO 0
 #define GED_SCHED_BLOCK 1
 
+/* Last level of the search.  GED_LAST_SELECT (the default) keeps the K
+ * children of least partial edit distance at every level, the last one
+ * included, then completes them (Alg. 1 read literally).  GED_LAST_COMPLETE
+ * completes every child of the last level with the insertions of Sec. 4.4.1
+ * and keeps the least total (first in generation order on ties): never a
+ * larger distance than GED_LAST_SELECT, and it skips the last selection. */
+#define GED_LAST_SELECT 0
+#define GED_LAST_COMPLETE 1
+
 typedef struct {
     int32_t schedule;        /* GED_SCHED_* */
     int32_t groups_per_cu;   /* resident workgroups per CU of a persistent launch;
                                 0 = the occupancy limit, larger values are clamped to it */
+    int32_t last_level;      /* GED_LAST_* */
 } ged_plan_options;
 
 /* ged_plan_create with options (NULL = defaults).  GED_EINVAL for an
- * unknown schedule or groups_per_cu < 0. */
+ * unknown schedule or last level, or groups_per_cu < 0. */
 ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                               const ged_plan_options *options, ged_plan **out);
 ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries);
@@ -265,6 +275,10 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
 typedef struct ged_wide ged_wide;
 
 ged_status ged_wide_create(ged_db *db, int64_t src, int64_t dst, int32_t K, ged_wide **out);
+/* With options: only last_level is used (GED_LAST_*; schedule and
+ * groups_per_cu are ignored).  GED_EINVAL for an unknown last level. */
+ged_status ged_wide_create_ex(ged_db *db, int64_t src, int64_t dst, int32_t K, const ged_plan_options *options,
+                              ged_wide **out);
 ged_status ged_wide_bytes(const ged_wide *w, int64_t *bytes);
 ged_status ged_wide_run(ged_wide *w, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
                         void *stream);
@@ -319,7 +333,8 @@ typedef struct {
     int64_t device_bytes;     /* device memory held */
 } ged_server_stats;
 
-/* Errors: GED_EINVAL (bad config, costs, K); GED_ENOMEM when the budget
+/* The server's searches use the default last level (GED_LAST_SELECT).
+ * Errors: GED_EINVAL (bad config, costs, K); GED_ENOMEM when the budget
  * cannot hold one batch of the configured size; GED_EDEVICE. */
 ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_server **out);
 

@@ -72,8 +72,11 @@ struct BlockShape {
 int block_slot_stride(int K, int threads);
 size_t block_workspace_bytes(const BlockShape &s);
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu);
+// last_complete: at the last level every child is completed (Sec. 4.4.1) and
+// only the least total is kept, instead of the K of least partial distance
+// (the same argument of every launch below).
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
-                        int *queue, Costs c, int K, void *workspace, size_t ws_stride,
+                        int *queue, Costs c, int K, int last_complete, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream);
 hipError_t launch_fill_zero(int *p, int count, hipStream_t stream);
 
@@ -82,17 +85,17 @@ hipError_t launch_fill_zero(int *p, int count, hipStream_t stream);
 constexpr int kWaveMaxN = 32;
 constexpr int kWaveMaxK = 64;
 
-hipError_t wave_max_resident(int PL, int *blocks_per_cu);
+hipError_t wave_max_resident(int PL, int last_complete, int *blocks_per_cu);
 hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue, Costs c,
-                       int K, Outputs out, int grid, hipStream_t stream);
+                       int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 
 // The same scheme for n1, n2 <= 64 (two-word vertex sets, children scored
 // into bytes), K <= 64.
 constexpr int kWave2MaxN = 64;
 
-hipError_t wave2_max_resident(int PL, int *blocks_per_cu);
+hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu);
 hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
-                        Costs c, int K, Outputs out, int grid, hipStream_t stream);
+                        Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 
 // Whole-device search of one pair at large K (kb_wide.hip).
 constexpr int kWideMaxK = GED_MAX_K_WIDE;
@@ -102,8 +105,8 @@ size_t wide_workspace_bytes(int n1, int n2, int w2, int planes, int K);
 // wide_workspace_bytes bytes; dist[0], map[0..n1), cand[0] (may be null) are
 // device outputs; `cus` sizes the grids.
 hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1, const GraphRec &g2, Costs c, int K,
-                       void *ws, size_t ws_bytes, int32_t *dist, int32_t *map, int64_t *cand, int cus,
-                       hipStream_t stream);
+                       int last_complete, void *ws, size_t ws_bytes, int32_t *dist, int32_t *map, int64_t *cand,
+                       int cus, hipStream_t stream);
 
 // Wavefront family that fits a pair: 1 (n1, n2 <= 32), 2 (n1, n2 <= 64), 0
 // none (K > 64 or a larger graph).
@@ -112,14 +115,15 @@ inline int wave_words_for(int n1, int n2, int K) {
     const int n = n1 > n2 ? n1 : n2;
     return n <= kWaveMaxN ? 1 : (n <= kWave2MaxN ? 2 : 0);
 }
-inline hipError_t wave_family_max_resident(int words, int PL, int *blocks_per_cu) {
-    return words == 1 ? wave_max_resident(PL, blocks_per_cu) : wave2_max_resident(PL, blocks_per_cu);
+inline hipError_t wave_family_max_resident(int words, int PL, int last_complete, int *blocks_per_cu) {
+    return words == 1 ? wave_max_resident(PL, last_complete, blocks_per_cu)
+                      : wave2_max_resident(PL, last_complete, blocks_per_cu);
 }
 inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const DbView &dst, const WorkItem *work,
-                                     int nwork, int *queue, Costs c, int K, Outputs out, int grid,
+                                     int nwork, int *queue, Costs c, int K, int last_complete, Outputs out, int grid,
                                      hipStream_t stream) {
-    return words == 1 ? launch_wave(PL, src, dst, work, nwork, queue, c, K, out, grid, stream)
-                      : launch_wave2(PL, src, dst, work, nwork, queue, c, K, out, grid, stream);
+    return words == 1 ? launch_wave(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream)
+                      : launch_wave2(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream);
 }
 
 }  // namespace gedk

@@ -57,6 +57,7 @@ struct ged_plan {
     ged_db *db = nullptr;
     int64_t npairs = 0;
     int32_t K = 0;
+    int last_complete = 0;   // GED_LAST_COMPLETE
     int64_t map_entries = 0;
     int cus = 0;
     std::vector<int64_t> pair_n;   // n1 + n2 per pair, for the overflow bound
@@ -163,19 +164,19 @@ ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool per
     if (b.wave) {
         if (!perpair) {
             GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c,
-                                             p->K, r.o, b.grid, r.s));
+                                             p->K, p->last_complete, r.o, b.grid, r.s));
         } else {
             for (int i = 0; i < nwork; ++i)
                 GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work + i, 1,
-                                                 b.d_queue + 1 + i, r.c, p->K, r.o, 1, r.s));
+                                                 b.d_queue + 1 + i, r.c, p->K, p->last_complete, r.o, 1, r.s));
         }
     } else if (!perpair) {
-        GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, b.d_ws, b.ws_stride,
-                                   r.o, b.grid, r.s));
+        GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, p->last_complete,
+                                   b.d_ws, b.ws_stride, r.o, b.grid, r.s));
     } else {
         for (int i = 0; i < nwork; ++i)
-            GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K, b.d_ws,
-                                       b.ws_stride, r.o, 1, r.s));
+            GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K,
+                                       p->last_complete, b.d_ws, b.ws_stride, r.o, 1, r.s));
     }
     return ok();
 }
@@ -233,12 +234,12 @@ std::string device_key() {
     return buf;
 }
 
-std::string bin_key(const std::string &dev, int K, const Bin &b) {
+std::string bin_key(const std::string &dev, int K, int last_complete, const Bin &b) {
     int lg = 0;
     while ((1ll << (lg + 1)) <= (long long)b.h_work.size()) ++lg;
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|K%d|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, b.wave_ok ? b.wave_words : 0, b.shape.W,
-             b.shape.PL, b.shape.nmax1, b.shape.nmax2, lg);
+    snprintf(buf, sizeof buf, "%s|K%d%s|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, last_complete ? "c" : "",
+             b.wave_ok ? b.wave_words : 0, b.shape.W, b.shape.PL, b.shape.nmax1, b.shape.nmax2, lg);
     return buf;
 }
 
@@ -275,10 +276,12 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
 
 ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                               const ged_plan_options *options, ged_plan **out) {
-    ged_plan_options opt{GED_SCHED_AUTO, 0};
+    ged_plan_options opt{GED_SCHED_AUTO, 0, GED_LAST_SELECT};
     if (options) opt = *options;
     if (opt.schedule != GED_SCHED_AUTO && opt.schedule != GED_SCHED_BLOCK)
         return fail(GED_EINVAL, "unknown schedule %d", opt.schedule);
+    if (opt.last_level != GED_LAST_SELECT && opt.last_level != GED_LAST_COMPLETE)
+        return fail(GED_EINVAL, "unknown last level %d", opt.last_level);
     if (opt.groups_per_cu < 0) return fail(GED_EINVAL, "groups_per_cu < 0");
     if (!out) return fail(GED_EINVAL, "out is NULL");
     *out = nullptr;
@@ -296,6 +299,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     p->db = db;
     p->npairs = npairs;
     p->K = K;
+    p->last_complete = opt.last_level == GED_LAST_COMPLETE ? 1 : 0;
     p->pair_n.resize((size_t)npairs);
     p->pair_m.resize((size_t)npairs);
 
@@ -366,7 +370,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             e = gedk::block_max_resident(sh, &b.max_block_per_cu[k]);
         }
         if (e == hipSuccess && b.wave_ok)
-            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, &b.max_wave_per_cu);
+            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, p->last_complete, &b.max_wave_per_cu);
         if (e != hipSuccess || b.max_block_per_cu[0] <= 0 || b.max_block_per_cu[1] <= 0 ||
             (b.wave_ok && b.max_wave_per_cu <= 0)) {
             free_plan(p);
@@ -503,7 +507,7 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     GED_HIP(hipEventCreate(&e0));
     GED_HIP(hipEventCreate(&e1));
     for (Bin &b : plan->bins) {
-        const std::string key = bin_key(dev, plan->K, b);
+        const std::string key = bin_key(dev, plan->K, plan->last_complete, b);
         auto hit = cache.find(key);
         if (hit != cache.end() && (!hit->second.wave || b.wave_ok)) {
             st = configure_bin(plan, b, hit->second.wave, hit->second.groups_per_cu, hit->second.threads);

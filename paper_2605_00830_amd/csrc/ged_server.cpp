@@ -273,10 +273,10 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         if (cnt == 0) continue;
         if (bin < kWaveBins) {
             e = gedk::launch_wave_family(bin + 1, s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K,
-                                         out, grid[bin], b.stream);
+                                         0, out, grid[bin], b.stream);
         } else {
-            e = gedk::launch_block(shape[bin], src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, b.d_ws,
-                                   stride[bin], out, grid[bin], b.stream);
+            e = gedk::launch_block(shape[bin], src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, 0,
+                                   b.d_ws, stride[bin], out, grid[bin], b.stream);
         }
     }
     if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost,
@@ -432,7 +432,7 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
     const bool wave_classes = cfg.K <= gedk::kWaveMaxK;
     for (int k = 0; k < kWaveBins && e == hipSuccess && wave_classes; ++k)
-        e = gedk::wave_family_max_resident(k + 1, s->PL, &s->wave_per_cu[k]);
+        e = gedk::wave_family_max_resident(k + 1, s->PL, 0, &s->wave_per_cu[k]);
     const int first_class = wave_classes ? 0 : kFirstBlockClass;
     const int nslabs = (kClasses - first_class) * cfg.streams;
     // every stream gets an equal share of the budget: its class's workspace

@@ -18,6 +18,7 @@ struct ged_wide {
     ged_db *db = nullptr;
     int64_t src = 0, dst = 0;
     int32_t K = 0;
+    int last_complete = 0;
     int cus = 0;
     void *d_ws = nullptr;
     size_t ws_bytes = 0;
@@ -26,7 +27,14 @@ struct ged_wide {
 extern "C" {
 
 ged_status ged_wide_create(ged_db *db, int64_t src, int64_t dst, int32_t K, ged_wide **out) {
+    return ged_wide_create_ex(db, src, dst, K, nullptr, out);
+}
+
+ged_status ged_wide_create_ex(ged_db *db, int64_t src, int64_t dst, int32_t K, const ged_plan_options *options,
+                              ged_wide **out) {
     if (!out) return fail(GED_EINVAL, "out is NULL");
+    const int last = options ? options->last_level : GED_LAST_SELECT;
+    if (last != GED_LAST_SELECT && last != GED_LAST_COMPLETE) return fail(GED_EINVAL, "unknown last level %d", last);
     *out = nullptr;
     if (!db) return fail(GED_EINVAL, "db is NULL");
     if (src < 0 || src >= db->count || dst < 0 || dst >= db->count)
@@ -42,6 +50,7 @@ ged_status ged_wide_create(ged_db *db, int64_t src, int64_t dst, int32_t K, ged_
     w->src = src;
     w->dst = dst;
     w->K = K;
+    w->last_complete = last == GED_LAST_COMPLETE ? 1 : 0;
     w->ws_bytes = gedk::wide_workspace_bytes(g1.n, g2.n, g2.w, db->planes, K);
     hipError_t e = hipDeviceGetAttribute(&w->cus, hipDeviceAttributeMultiprocessorCount, db->device);
     if (e != hipSuccess) {
@@ -82,8 +91,8 @@ ged_status ged_wide_run(ged_wide *w, ged_costs costs, int32_t *d_dist, int32_t *
     const ged_db *db = w->db;
     const gedk::DbView view{db->d_graphs, db->d_adj, db->d_vlab, db->planes};
     const gedk::Costs c{costs.vsub, costs.vdel, costs.vins, costs.esub, costs.edel, costs.eins};
-    GED_HIP(gedk::launch_wide(view, view, g1, g2, c, w->K, w->d_ws, w->ws_bytes, d_dist, d_map, d_cand, w->cus,
-                              static_cast<hipStream_t>(stream)));
+    GED_HIP(gedk::launch_wide(view, view, g1, g2, c, w->K, w->last_complete, w->d_ws, w->ws_bytes, d_dist, d_map,
+                              d_cand, w->cus, static_cast<hipStream_t>(stream)));
     return ok();
 }
 

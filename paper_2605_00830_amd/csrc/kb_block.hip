@@ -63,6 +63,7 @@ struct BlockArgs {
     int *queue;
     Costs c;
     int K;
+    int last_complete;   // last level: complete every child, keep the least total
     int KS;        // slot stride
     int TPS;       // threads per slot
     int rows_words;   // LDS words per staged block of g2 rows (nmax2 x W)
@@ -390,6 +391,49 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 return CL ? cand_l[s * CST + u] : cand_g[(size_t)u * KS + s];
             };
 
+            int nb_new;
+            if (a.last_complete && i == n1 - 1) {
+                // ---------------- complete-then-minimum last level: each
+                // child's total (Sec. 4.4.1); the least, first in generation
+                // order (slot, then column), is the one survivor
+                const int *einc = ein_b + cur * KS;
+                const int *nsubc = nsub_b + cur * KS;
+                unsigned long long bk = ~0ull;
+                for (int r = 0; r < SPT; ++r) {
+                    const int s = r * G + sg;
+                    if (s >= nb) break;
+                    uint32_t img_r[W];
+#pragma unroll
+                    for (int k = 0; k < W; ++k) img_r[k] = imgc[(size_t)k * KS + s];
+                    const int e0 = einc[s], used0 = nsubc[s];
+                    for (int u = c_lo; u < c_hi; ++u) {
+                        const int v = cand_at(s, u);
+                        if (v == SENT) continue;
+                        int add_e = 0, used = used0;
+                        if (u < n2) {
+#pragma unroll
+                            for (int k = 0; k < W; ++k) add_e += __popc(img_r[k] & s_rows[u * W + k]);
+                            ++used;
+                        }
+                        const int total = v + c.vins * (n2 - used) + c.eins * (g2.m - e0 - add_e);
+                        const unsigned long long key =
+                            ((unsigned long long)(unsigned)total << 32) | (unsigned)((s << 10) | u);
+                        bk = key < bk ? key : bk;
+                    }
+                }
+                bk = wave_min_u64(bk);
+                if ((t & 63) == 0) s_red64[t >> 6] = bk;
+                __syncthreads();
+                if (t == 0) {
+                    unsigned long long m = s_red64[0];
+#pragma unroll
+                    for (int k = 1; k < NW; ++k) m = s_red64[k] < m ? s_red64[k] : m;
+                    const int sel = (int)(m & 0xffffffffu);
+                    s_sel[0] = sel;
+                    s_selped[0] = cand_at(sel >> 10, sel & 1023);
+                }
+                nb_new = 1;
+            } else {
             // ---------------- threshold: K-th smallest partial edit distance
             int T = SENT, quota = 0;
             if (V > K) {
@@ -493,7 +537,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     }
                 }
             }
-            const int nb_new = out_carry;
+            nb_new = out_carry;
+            }
             __syncthreads();
 
             // ---------------- update: child = parent + (v_i -> u)
@@ -654,7 +699,7 @@ hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
 }
 
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
-                        int *queue, Costs c, int K, void *workspace, size_t ws_stride,
+                        int *queue, Costs c, int K, int last_complete, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream) {
     const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT);
     if (!k || grid <= 0 || s.KS != block_slot_stride(K, s.BT)) return hipErrorInvalidValue;
@@ -666,6 +711,7 @@ hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &ds
     a.queue = queue;
     a.c = c;
     a.K = K;
+    a.last_complete = last_complete;
     a.KS = s.KS;
     a.TPS = s.KS >= s.BT ? 1 : s.BT / s.KS;
     a.rows_words = rows_words(s);

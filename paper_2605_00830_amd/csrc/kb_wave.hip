@@ -52,7 +52,9 @@
 //            PED with the same integer formula, so the value is identical to
 //            the candidate's.
 // Completion adds vins (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the
-// first lane of least total is the result.
+// first lane of least total is the result.  The COMPLETE instantiation's last
+// level instead completes every child and keeps only the least total (first
+// in generation order), which then is the result.
 //
 // SMALL selects 24-bit multiplies, valid when every cost is below 2^22
 // (counts are at most 32, and the plan's overflow bound keeps every sum in
@@ -81,7 +83,7 @@ struct WaveArgs {
     Outputs out;
 };
 
-template <int PL, bool SMALL>
+template <int PL, bool SMALL, bool COMPLETE>
 __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
@@ -222,6 +224,45 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const int V = (int)wave_sum(live ? nfree + 1u : 0u);
             ce += V;
 
+            int nb_new;
+            if (COMPLETE && i == n1 - 1) {
+                // ---------------- complete-then-minimum last level: each
+                // child's total (Sec. 4.4.1: the unused g2 vertices and the g2
+                // edges with an unused end inserted); the least, first in
+                // generation order, is the one survivor
+                const uint32_t nu = (uint32_t)(n2 - __popc(img));
+                const uint32_t mo = (uint32_t)g2.m - ein;   // g2 edges not inside Img
+                uint32_t bt = INVALID, bj = DEL8;
+#pragma unroll
+                for (int g = 0; g < 8; ++g) {
+                    if (g < ngroups) {
+                        const uint32_t uw = s_uv[g][lane];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const uint32_t d = cand[4 * g + k];
+                            if (d == INVALID) continue;
+                            const uint32_t R = s_tab[__builtin_amdgcn_ubfe(uw, (uint32_t)k * 8u, 8u)].x;
+                            const uint32_t t = d + mul_cost<SMALL>(nu - 1u, vins) +
+                                               mul_cost<SMALL>(mo - (uint32_t)__popc(img & R), eins);
+                            if (t < bt) {
+                                bt = t;
+                                bj = (uint32_t)(4 * g + k);
+                            }
+                        }
+                    }
+                }
+                if (live) {
+                    const uint32_t t = cdel + mul_cost<SMALL>(nu, vins) + mul_cost<SMALL>(mo, eins);
+                    if (t < bt) {
+                        bt = t;
+                        bj = DEL8;
+                    }
+                }
+                const uint32_t wmin = wave_umin(bt);
+                const int bl = (int)__builtin_ctzll(__ballot(bt == wmin));
+                if (lane == bl) s_sel[0] = ((uint32_t)lane << 8) | bj;
+                nb_new = 1;
+            } else {
             // ---------------- threshold T: the K-th smallest PED
             uint32_t T = INVALID;
             const bool trim = V > K;
@@ -361,7 +402,8 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             int pos = wave_excl_scan(__popc(keepm) + (keepd ? 1 : 0));
             for (uint32_t mk = keepm; mk; mk &= mk - 1u) s_sel[pos++] = ((uint32_t)lane << 8) | (uint32_t)__builtin_ctz(mk);
             if (keepd) s_sel[pos] = ((uint32_t)lane << 8) | DEL8;
-            const int nb_new = min(V, K);
+            nb_new = min(V, K);
+            }
             __syncthreads();
 
             // ---------------- update: child = parent + (v_i -> u)
@@ -441,16 +483,23 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     }
 }
 
-template <int PL, bool SMALL>
+template <int PL, bool SMALL, bool COMPLETE>
 const void *wave_ptr() {
-    return reinterpret_cast<const void *>(&kb_wave_kernel<PL, SMALL>);
+    return reinterpret_cast<const void *>(&kb_wave_kernel<PL, SMALL, COMPLETE>);
 }
 
-const void *select_wave(int PL, bool small) {
-    if (PL == 0) return small ? wave_ptr<0, true>() : wave_ptr<0, false>();
-    if (PL == 2) return small ? wave_ptr<2, true>() : wave_ptr<2, false>();
-    if (PL == 4) return small ? wave_ptr<4, true>() : wave_ptr<4, false>();
+// the complete-then-minimum last level is a kernel of its own, so that the
+// default search keeps its register budget
+template <bool COMPLETE>
+const void *select_wave_c(int PL, bool small) {
+    if (PL == 0) return small ? wave_ptr<0, true, COMPLETE>() : wave_ptr<0, false, COMPLETE>();
+    if (PL == 2) return small ? wave_ptr<2, true, COMPLETE>() : wave_ptr<2, false, COMPLETE>();
+    if (PL == 4) return small ? wave_ptr<4, true, COMPLETE>() : wave_ptr<4, false, COMPLETE>();
     return nullptr;
+}
+
+const void *select_wave(int PL, bool small, bool complete) {
+    return complete ? select_wave_c<true>(PL, small) : select_wave_c<false>(PL, small);
 }
 
 bool small_costs(const Costs &c) {
@@ -460,9 +509,9 @@ bool small_costs(const Costs &c) {
 
 }  // namespace
 
-hipError_t wave_max_resident(int PL, int *blocks_per_cu) {
-    const void *k = select_wave(PL, true);
-    const void *k2 = select_wave(PL, false);
+hipError_t wave_max_resident(int PL, int last_complete, int *blocks_per_cu) {
+    const void *k = select_wave(PL, true, last_complete != 0);
+    const void *k2 = select_wave(PL, false, last_complete != 0);
     if (!k || !k2) return hipErrorInvalidValue;
     int a = 0, b = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k, 64, 0);
@@ -472,8 +521,8 @@ hipError_t wave_max_resident(int PL, int *blocks_per_cu) {
 }
 
 hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue, Costs c,
-                       int K, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_wave(PL, small_costs(c));
+                       int K, int last_complete, Outputs out, int grid, hipStream_t stream) {
+    const void *k = select_wave(PL, small_costs(c), last_complete != 0);
     if (!k || grid <= 0 || K > kWaveMaxK) return hipErrorInvalidValue;
     WaveArgs a;
     a.src = src;

@@ -41,7 +41,8 @@
 // (parent, j); a new slot reads its vertex from the parent's record and
 // recomputes its PED with the same formula.  Completion adds vins
 // (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the first lane of least total
-// is the result.
+// is the result.  The COMPLETE instantiation's last level instead completes every
+// child and keeps only the least total (first in generation order).
 #include "ged_internal.h"
 #include "wave_common.h"
 
@@ -83,7 +84,7 @@ __device__ __forceinline__ uint32_t to_byte(uint32_t d, uint32_t b, int sh) {
     return d < b ? 0u : min((d - b) >> sh, 126u) + 1u;
 }
 
-template <int PL, bool SMALL>
+template <int PL, bool SMALL, bool COMPLETE>
 __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
@@ -193,6 +194,25 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             const uint32_t cdel = live ? basel + vdel : INVALID;
             __syncthreads();
 
+            // PED of the child substituting v_i by u (u = 64: the exhausted-set
+            // sentinel, whose label cost saturates the sum to 0xffffffff)
+            auto score = [&](uint32_t u) -> uint32_t {
+                const uint4 t = s_tab[u];
+                const uint64_t R = u64(t.x, t.y);
+                uint32_t d = msub_cost<SMALL>(popc64(phi & R), nedel,
+                                              mad_cost<SMALL>(popc64(ai & R), eins,
+                                                              __builtin_elementwise_add_sat(basel, t.z)));
+                if (PL > 0) {
+                    uint64_t diff = 0ull;
+#pragma unroll
+                    for (int b = 0; b < PLA; ++b) {
+                        const uint2 pl = s_pl[b][u];
+                        diff |= phib[b] ^ u64(pl.x, pl.y);
+                    }
+                    d += mul_cost<SMALL>(popc64(phi & R & diff), esub);
+                }
+                return d;
+            };
             // one pass: every child's byte against (base, sh) into pk; the
             // first pass also records each child's vertex
             uint32_t pk[16];
@@ -207,21 +227,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                             const uint32_t u = (uint32_t)__builtin_ctzg(fr, 64);   // 64 once exhausted
                             fr &= fr - 1ull;
                             uw |= u << (8 * k);
-                            const uint4 t = s_tab[u];
-                            const uint64_t R = u64(t.x, t.y);
-                            uint32_t d = msub_cost<SMALL>(popc64(phi & R), nedel,
-                                                          mad_cost<SMALL>(popc64(ai & R), eins,
-                                                                          __builtin_elementwise_add_sat(basel, t.z)));
-                            if (PL > 0) {
-                                uint64_t diff = 0ull;
-#pragma unroll
-                                for (int b = 0; b < PLA; ++b) {
-                                    const uint2 pl = s_pl[b][u];
-                                    diff |= phib[b] ^ u64(pl.x, pl.y);
-                                }
-                                d += mul_cost<SMALL>(popc64(phi & R & diff), esub);
-                            }
-                            w |= to_byte(d, base, sh) << (8 * k);
+                            w |= to_byte(score(u), base, sh) << (8 * k);
                         }
                         pk[g] = w;
                         if (record) s_uv[g][lane] = uw;
@@ -277,6 +283,37 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             // ---------------- threshold T (byte t_T in the final pass)
             const uint32_t m0 = wave_umin(live ? ped : INVALID);   // no child lies below
             pass(m0, 0, true);
+            int nb_new;
+            if (COMPLETE && i == n1 - 1) {
+                // ---------------- complete-then-minimum last level: each
+                // child's total (Sec. 4.4.1); the least, first in generation
+                // order, is the one survivor
+                const uint32_t nu = (uint32_t)n2 - popc64(img);
+                const uint32_t mo = (uint32_t)g2.m - ein;   // g2 edges not inside Img
+                uint32_t bt = INVALID, bj = DEL8;
+                uint64_t fr = free;
+                for (uint32_t j = 0; fr; ++j, fr &= fr - 1ull) {
+                    const uint32_t u = (uint32_t)__builtin_ctzll(fr);
+                    const uint4 tu = s_tab[u];
+                    const uint32_t t = score(u) + mul_cost<SMALL>(nu - 1u, vins) +
+                                       mul_cost<SMALL>(mo - popc64(img & u64(tu.x, tu.y)), eins);
+                    if (t < bt) {
+                        bt = t;
+                        bj = j;
+                    }
+                }
+                if (live) {
+                    const uint32_t t = cdel + mul_cost<SMALL>(nu, vins) + mul_cost<SMALL>(mo, eins);
+                    if (t < bt) {
+                        bt = t;
+                        bj = DEL8;
+                    }
+                }
+                const uint32_t wmin = wave_umin(bt);
+                const int bl = (int)__builtin_ctzll(__ballot(bt == wmin));
+                if (lane == bl) s_sel[0] = ((uint32_t)lane << 8) | bj;
+                nb_new = 1;
+            } else {
             uint32_t T = INVALID;
             int tT = TOP;   // no trimming: every child with a byte below 127 survives
             if (trim) {
@@ -369,7 +406,8 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             for (uint64_t mk = keepm; mk; mk &= mk - 1ull)
                 s_sel[pos++] = ((uint32_t)lane << 8) | (uint32_t)__builtin_ctzll(mk);
             if (keepd) s_sel[pos] = ((uint32_t)lane << 8) | DEL8;
-            const int nb_new = min(V, K);
+            nb_new = min(V, K);
+            }
             __syncthreads();
 
             // ---------------- update: child = parent + (v_i -> u)
@@ -449,16 +487,23 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
     }
 }
 
-template <int PL, bool SMALL>
+template <int PL, bool SMALL, bool COMPLETE>
 const void *wave2_ptr() {
-    return reinterpret_cast<const void *>(&kb_wave2_kernel<PL, SMALL>);
+    return reinterpret_cast<const void *>(&kb_wave2_kernel<PL, SMALL, COMPLETE>);
 }
 
-const void *select_wave2(int PL, bool small) {
-    if (PL == 0) return small ? wave2_ptr<0, true>() : wave2_ptr<0, false>();
-    if (PL == 2) return small ? wave2_ptr<2, true>() : wave2_ptr<2, false>();
-    if (PL == 4) return small ? wave2_ptr<4, true>() : wave2_ptr<4, false>();
+// the complete-then-minimum last level is a kernel of its own, so that the
+// default search keeps its register budget
+template <bool COMPLETE>
+const void *select_wave2_c(int PL, bool small) {
+    if (PL == 0) return small ? wave2_ptr<0, true, COMPLETE>() : wave2_ptr<0, false, COMPLETE>();
+    if (PL == 2) return small ? wave2_ptr<2, true, COMPLETE>() : wave2_ptr<2, false, COMPLETE>();
+    if (PL == 4) return small ? wave2_ptr<4, true, COMPLETE>() : wave2_ptr<4, false, COMPLETE>();
     return nullptr;
+}
+
+const void *select_wave2(int PL, bool small, bool complete) {
+    return complete ? select_wave2_c<true>(PL, small) : select_wave2_c<false>(PL, small);
 }
 
 bool small_costs2(const Costs &c) {
@@ -468,9 +513,9 @@ bool small_costs2(const Costs &c) {
 
 }  // namespace
 
-hipError_t wave2_max_resident(int PL, int *blocks_per_cu) {
-    const void *k = select_wave2(PL, true);
-    const void *k2 = select_wave2(PL, false);
+hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu) {
+    const void *k = select_wave2(PL, true, last_complete != 0);
+    const void *k2 = select_wave2(PL, false, last_complete != 0);
     if (!k || !k2) return hipErrorInvalidValue;
     int x = 0, y = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&x, k, 64, 0);
@@ -480,8 +525,8 @@ hipError_t wave2_max_resident(int PL, int *blocks_per_cu) {
 }
 
 hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
-                        Costs c, int K, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_wave2(PL, small_costs2(c));
+                        Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream) {
+    const void *k = select_wave2(PL, small_costs2(c), last_complete != 0);
     if (!k || grid <= 0 || K > kWaveMaxK) return hipErrorInvalidValue;
     Wave2Args a;
     a.src = src;

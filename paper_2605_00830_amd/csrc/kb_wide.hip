@@ -40,7 +40,9 @@
 //   sets     (mappings past 64 entries) per (new slot, range): the images of
 //            the next vertex's earlier neighbours in the range, OR-ed into Phi.
 // After the last level every leaf is completed (Sec. 4.4.1) and the first
-// leaf of least total in beam order is returned.
+// leaf of least total in beam order is returned.  With the complete-then-
+// minimum option the last level skips selection: every child is completed
+// and the least total (first in generation order) is the only survivor.
 #include <algorithm>
 
 #include "ged_internal.h"
@@ -676,6 +678,77 @@ __global__ __launch_bounds__(WT) void wide_sets(WideCtx c, int i, int utiles) {
     if (live) store_phi<W, PL>(c, s, s_set, false);
 }
 
+// ------------------------------------------------------------------ complete-then-minimum
+// Last level with the complete-then-minimum option: every child's total
+// (Sec. 4.4.1: the unused g2 vertices and the g2 edges with an unused end
+// inserted); the least (total, generation order) of the grid lands in *best.
+__global__ __launch_bounds__(WT) void wide_complete(WideCtx c, int i, int S, int tiles) {
+    __shared__ unsigned long long s_key[NWV];
+    const uint32_t B = sgpr(c.st[i].B);
+    const int chunk = blockIdx.x / tiles, tile = blockIdx.x % tiles;
+    const Cols cc = chunk_cols(c, chunk, S);
+    const uint32_t p = (uint32_t)tile * WT + threadIdx.x;
+    const int cur = i & 1, w2 = c.w2;
+    unsigned long long key = ~0ull;
+    if (p < B) {
+        uint32_t used = 0u;
+        for (int k = 0; k < w2; ++k) used += (uint32_t)__popc(c.img[cur][(size_t)k * c.Kp + p]);
+        const uint32_t e0 = c.ein[cur][p];
+        for (int u = cc.u0; u < cc.u1 + (cc.del ? 1 : 0); ++u) {
+            const int col = u < cc.u1 ? u : c.n2;
+            const uint32_t d = c.cand[(size_t)col * c.Kp + p];
+            if (d == INVALID) continue;
+            uint32_t add = 0u, nu = (uint32_t)c.n2 - used;
+            if (col < c.n2) {
+                for (int k = 0; k < w2; ++k)
+                    add += (uint32_t)__popc(c.img[cur][(size_t)k * c.Kp + p] & c.a2[(size_t)col * w2 + k]);
+                --nu;
+            }
+            const uint64_t total = (uint64_t)d + (uint64_t)c.c.vins * nu + (uint64_t)c.c.eins * ((uint32_t)c.m2 - e0 - add);
+            const unsigned long long k2 = (total << 32) | ((p << CBITS) | (uint32_t)col);
+            key = k2 < key ? k2 : key;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long other = (unsigned long long)__shfl_xor((long long)key, o);
+        key = other < key ? other : key;
+    }
+    if ((threadIdx.x & 63) == 0) s_key[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = s_key[0];
+#pragma unroll
+        for (int k = 1; k < NWV; ++k) m = s_key[k] < m ? s_key[k] : m;
+        if (m != ~0ull) atomicMin(c.best, m);
+    }
+}
+
+// The winner of wide_complete becomes the level's only survivor; the level's
+// children (for the candidate count) come from the expansion histogram, which
+// is cleared for the next use, as is *best.
+__global__ __launch_bounds__(WT) void wide_pick(WideCtx c, int i) {
+    __shared__ uint32_t s_tmp[NWV];
+    const int t = threadIdx.x;
+    uint32_t sum = 0u;
+    for (int b = t; b < HB; b += WT) {
+        sum += c.hist[b];
+        c.hist[b] = 0u;
+    }
+    uint32_t V;
+    (void)block_excl_scan<NWV>(sum, s_tmp, &V);
+    if (t != 0) return;
+    const unsigned long long best = *c.best;
+    const uint32_t r = (uint32_t)(best & 0xffffffffull);
+    const uint32_t p = r >> CBITS, col = r & ((1u << CBITS) - 1u);
+    c.rec[0] = r;
+    c.ped[(i + 1) & 1][0] = c.cand[(size_t)col * c.Kp + p];
+    c.st[i].V = V;
+    c.st[i + 1].B = 1u;
+    *c.ce += V;
+    *c.best = ~0ull;
+}
+
 // ------------------------------------------------------------------ final
 // Every leaf's total (Sec. 4.4.1); the least (total, slot) wins.
 __global__ __launch_bounds__(WT) void wide_final_keys(WideCtx c) {
@@ -767,7 +840,7 @@ int column_chunks(int tiles, int w2, int cus) {
 }
 
 template <int W, int PL>
-hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStream_t stream) {
+hipError_t launch_levels(const WideCtx &c, bool refine_possible, bool last_complete, int cus, hipStream_t stream) {
     const bool small = c.c.vsub < (1 << 22) && c.c.vdel < (1 << 22) && c.c.vins < (1 << 22) &&
                        c.c.esub < (1 << 22) && c.c.edel < (1 << 22) && c.c.eins < (1 << 22);
     hipLaunchKernelGGL(wide_init, dim3(1), dim3(WT), 0, stream, c);
@@ -781,6 +854,14 @@ hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStr
             hipLaunchKernelGGL((wide_expand<W, PL, true>), dim3(egrid), dim3(WT), 0, stream, c, i, S, tiles);
         else
             hipLaunchKernelGGL((wide_expand<W, PL, false>), dim3(egrid), dim3(WT), 0, stream, c, i, S, tiles);
+        if (last_complete && i == c.n1 - 1) {
+            // the last level keeps only its least completed child
+            hipLaunchKernelGGL(wide_complete, dim3(items), dim3(WT), 0, stream, c, i, S, tiles);
+            hipLaunchKernelGGL(wide_pick, dim3(1), dim3(WT), 0, stream, c, i);
+            bound = 1;
+            hipLaunchKernelGGL((wide_update<W, PL>), dim3(i / JR + 1), dim3(WT), 0, stream, c, i, 1, i / JR + 1);
+            break;
+        }
         hipLaunchKernelGGL(wide_select, dim3(1), dim3(ST), 0, stream, c, i, 0);
         if (refine_possible) {
             for (int r = 1; r <= 2; ++r) {
@@ -807,10 +888,11 @@ hipError_t launch_levels(const WideCtx &c, bool refine_possible, int cus, hipStr
 }
 
 template <int W>
-hipError_t launch_pl(int PL, const WideCtx &c, bool refine_possible, int cus, hipStream_t stream) {
-    if (PL == 0) return launch_levels<W, 0>(c, refine_possible, cus, stream);
-    if (PL == 2) return launch_levels<W, 2>(c, refine_possible, cus, stream);
-    if (PL == 4) return launch_levels<W, 4>(c, refine_possible, cus, stream);
+hipError_t launch_pl(int PL, const WideCtx &c, bool refine_possible, bool last_complete, int cus,
+                     hipStream_t stream) {
+    if (PL == 0) return launch_levels<W, 0>(c, refine_possible, last_complete, cus, stream);
+    if (PL == 2) return launch_levels<W, 2>(c, refine_possible, last_complete, cus, stream);
+    if (PL == 4) return launch_levels<W, 4>(c, refine_possible, last_complete, cus, stream);
     return hipErrorInvalidValue;
 }
 
@@ -821,8 +903,8 @@ size_t wide_workspace_bytes(int n1, int n2, int w2, int planes, int K) {
 }
 
 hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1, const GraphRec &g2, Costs costs,
-                       int K, void *ws, size_t ws_bytes, int32_t *dist, int32_t *map, int64_t *cand, int cus,
-                       hipStream_t stream) {
+                       int K, int last_complete, void *ws, size_t ws_bytes, int32_t *dist, int32_t *map,
+                       int64_t *cand, int cus, hipStream_t stream) {
     const int planes = dst.planes;
     const int PL = planes == 0 ? 0 : (planes <= 2 ? 2 : 4);
     int W = 1;
@@ -872,12 +954,13 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
     const int64_t emax = std::max({(int64_t)costs.esub, (int64_t)costs.edel, (int64_t)costs.eins});
     c.pedmax = (uint64_t)(vmax * (int64_t)g1.n + emax * ((int64_t)g1.m + g2.m));
     const bool refine_possible = c.pedmax >= (uint64_t)HB;
+    const bool lc = last_complete != 0;
     switch (W) {
-        case 1: return launch_pl<1>(PL, c, refine_possible, cus, stream);
-        case 2: return launch_pl<2>(PL, c, refine_possible, cus, stream);
-        case 4: return launch_pl<4>(PL, c, refine_possible, cus, stream);
-        case 8: return launch_pl<8>(PL, c, refine_possible, cus, stream);
-        case 16: return launch_pl<16>(PL, c, refine_possible, cus, stream);
+        case 1: return launch_pl<1>(PL, c, refine_possible, lc, cus, stream);
+        case 2: return launch_pl<2>(PL, c, refine_possible, lc, cus, stream);
+        case 4: return launch_pl<4>(PL, c, refine_possible, lc, cus, stream);
+        case 8: return launch_pl<8>(PL, c, refine_possible, lc, cus, stream);
+        case 16: return launch_pl<16>(PL, c, refine_possible, lc, cus, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -32,10 +32,11 @@ class GedError(RuntimeError):
 
 
 SCHED_AUTO, SCHED_BLOCK = 0, 1
+LAST_SELECT, LAST_COMPLETE = 0, 1
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("schedule", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32)]
+    _fields_ = [("schedule", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("last_level", ctypes.c_int32)]
 
 
 class Costs(ctypes.Structure):
@@ -74,7 +75,7 @@ EXPORTS = (
     "ged_plan_capture", "ged_plan_replay", "ged_plan_tune",
     "ged_server_create", "ged_server_submit", "ged_server_poll", "ged_server_wait",
     "ged_server_stats_get", "ged_server_destroy", "ged_server_submit_batch", "ged_server_collect",
-    "ged_wide_create", "ged_wide_bytes", "ged_wide_run", "ged_wide_destroy",
+    "ged_wide_create", "ged_wide_create_ex", "ged_wide_bytes", "ged_wide_run", "ged_wide_destroy",
 )
 
 
@@ -122,6 +123,7 @@ def load(path: str = LIB_PATH):
         "ged_server_stats_get": ([P, P], i32),
         "ged_server_destroy": ([P], i32),
         "ged_wide_create": ([P, i64, i64, i32, P], i32),
+        "ged_wide_create_ex": ([P, i64, i64, i32, P, P], i32),
         "ged_wide_bytes": ([P, P], i32),
         "ged_wide_run": ([P, Costs, P, P, P, P], i32),
         "ged_wide_destroy": ([P], i32),
@@ -213,13 +215,14 @@ def _pairs_array(pairs) -> np.ndarray:
 class Plan:
     """A reusable batched launch plan (ged_plan_create)."""
 
-    def __init__(self, db: Database, pairs, K: int, schedule: int = SCHED_AUTO, groups_per_cu: int = 0):
+    def __init__(self, db: Database, pairs, K: int, schedule: int = SCHED_AUTO, groups_per_cu: int = 0,
+                 last_level: int = LAST_SELECT):
         lib = load()
         self.db = db
         self.pairs = _pairs_array(pairs)
         self.K = int(K)
         handle = ctypes.c_void_p()
-        opt = PlanOptions(int(schedule), int(groups_per_cu))
+        opt = PlanOptions(int(schedule), int(groups_per_cu), int(last_level))
         _check(lib.ged_plan_create_ex(db.handle, self.pairs.ctypes.data, len(self.pairs), self.K,
                                       ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
@@ -332,9 +335,9 @@ class Result:
 
 
 def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: bool = False,
-          stream=None, schedule: int = SCHED_AUTO, groups_per_cu: int = 0) -> Result:
+          stream=None, schedule: int = SCHED_AUTO, groups_per_cu: int = 0, last_level: int = LAST_SELECT) -> Result:
     """K-Best GED of every (src, dst) pair; synchronizes and returns host arrays."""
-    plan = Plan(db, pairs, K, schedule=schedule, groups_per_cu=groups_per_cu)
+    plan = Plan(db, pairs, K, schedule=schedule, groups_per_cu=groups_per_cu, last_level=last_level)
     try:
         dist, maps, cand = plan.outputs(with_cand=with_cand)
         plan.run(costs, dist, maps, cand, stream=stream, perpair=perpair)
@@ -349,12 +352,13 @@ def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: 
 class Wide:
     """Single-pair search at large K with the whole device (ged_wide_*)."""
 
-    def __init__(self, db: Database, src: int, dst: int, K: int):
+    def __init__(self, db: Database, src: int, dst: int, K: int, last_level: int = LAST_SELECT):
         lib = load()
         self.db = db
         self.src, self.dst, self.K = int(src), int(dst), int(K)
         handle = ctypes.c_void_p()
-        _check(lib.ged_wide_create(db.handle, self.src, self.dst, self.K, ctypes.byref(handle)))
+        opt = PlanOptions(SCHED_AUTO, 0, int(last_level))
+        _check(lib.ged_wide_create_ex(db.handle, self.src, self.dst, self.K, ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
         self.n1 = int(db.n[self.src])
         size = ctypes.c_int64()
@@ -388,9 +392,9 @@ class Wide:
             pass
 
 
-def kbest_wide(db: Database, src: int, dst: int, costs, K: int, stream=None):
+def kbest_wide(db: Database, src: int, dst: int, costs, K: int, stream=None, last_level: int = LAST_SELECT):
     """(dist, mapping, children evaluated) of one pair by the large-K search; synchronizes."""
-    w = Wide(db, src, dst, K)
+    w = Wide(db, src, dst, K, last_level=last_level)
     try:
         dist, maps, cand = w.outputs()
         w.run(costs, dist, maps, cand, stream=stream)
