@@ -1,8 +1,9 @@
 """CPU oracle for the K-Best graph edit distance search -- TEST INFRASTRUCTURE.
 
 Only tests, the smoke check and the benchmark's CPU-baseline leg may import
-this package.  The GPU library never calls it; see ged_oracle.c for the
-definitions it follows and the paper sections it cites.
+this package.  The GPU library never calls it; see ged_oracle.c (the paper's
+K-Best tree search) and bipartite_oracle.c (the bipartite K-best-assignment
+variant) for the definitions they follow and what they cite.
 
 Functions take `Graph` objects from paper_2605_00830_amd.synth (or anything
 with n, vlabel, eu, ev, elabel) and a 6-tuple of costs
@@ -18,7 +19,7 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "ged_oracle.c")
+_SRCS = [os.path.join(_HERE, "ged_oracle.c"), os.path.join(_HERE, "bipartite_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -29,12 +30,16 @@ class OracleError(RuntimeError):
     pass
 
 
+def _stale() -> bool:
+    return not os.path.exists(_LIB_PATH) or any(os.path.getmtime(_LIB_PATH) < os.path.getmtime(f) for f in _SRCS)
+
+
 def build(force: bool = True) -> str:
-    """Compile ged_oracle.c with gcc -O2 into oracle/liboracle.so."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    """Compile the oracle's C sources with gcc -O2 into oracle/liboracle.so."""
+    if force or _stale():
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
+                               "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -43,7 +48,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if _stale():
         build(force=True)
     lib = ctypes.CDLL(_LIB_PATH)
     P = ctypes.c_void_p
@@ -61,6 +66,10 @@ def _load():
     lib.oracle_count_mappings.restype = ctypes.c_double
     lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, P, P, P, P]
     lib.oracle_kbest_pairs.restype = ctypes.c_int
+    lib.oracle_bipartite.argtypes = graph_args + graph_args + [P, i64, P, P, P, P, P, P]
+    lib.oracle_bipartite.restype = ctypes.c_int
+    lib.oracle_bipartite_pairs.argtypes = [P] * 9 + [i64, P, i64, P, P, P, P, P]
+    lib.oracle_bipartite_pairs.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -172,3 +181,57 @@ def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_co
                                 ctypes.byref(failed))
     _check(st, f"kbest_pairs (pair {failed.value})")
     return dist, maps[:total], off
+
+
+def bipartite(g1, g2, costs: Sequence[int], K: int, trace: bool = False):
+    """Bipartite K-best bound g1 -> g2: (distance, mapping, solves), and with
+    trace=True also (assignment costs [npop], mappings [npop, n1]) of the popped
+    assignments in pop order."""
+    lib = _load()
+    keep: list = []
+    c = _arr(costs)
+    dist = ctypes.c_int64(0)
+    solves = ctypes.c_int64(0)
+    n1 = int(g1.n)
+    mp = np.zeros(max(n1, 1), dtype=np.int32)
+    pc = pm = None
+    npop = ctypes.c_int64(0)
+    if trace:
+        pc = np.zeros(max(int(K), 1), dtype=np.int64)
+        pm = np.zeros(max(int(K) * n1, 1), dtype=np.int32)
+    st = lib.oracle_bipartite(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
+                              ctypes.byref(dist), _ptr(mp), ctypes.byref(solves), _ptr(pc), _ptr(pm),
+                              ctypes.byref(npop))
+    _check(st, "bipartite")
+    out = (int(dist.value), mp[:n1].copy(), int(solves.value))
+    if trace:
+        k = int(npop.value)
+        return out + (pc[:k].copy(), pm[:k * n1].reshape(k, n1).copy())
+    return out
+
+
+def bipartite_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int):
+    """bipartite() over many pairs of a GraphSet: (dist int64 [P], maps int32
+    [sum n_src], offsets int64 [P], solves int64 [P])."""
+    lib = _load()
+    pairs = _arr(pairs, np.int64).reshape(-1, 2)
+    off = map_offsets(graphs, pairs)
+    total = int(np.asarray(graphs.n, np.int64)[pairs[:, 0]].sum()) if len(pairs) else 0
+    dist = np.zeros(len(pairs), dtype=np.int64)
+    solves = np.zeros(len(pairs), dtype=np.int64)
+    maps = np.zeros(max(total, 1), dtype=np.int32)
+    n = _arr(graphs.n)
+    m = _arr(graphs.m)
+    voff = _arr(graphs.voff, np.int64)
+    eoff = _arr(graphs.eoff, np.int64)
+    vl = _arr(graphs.vlabel) if len(graphs.vlabel) else np.zeros(1, np.int32)
+    eu = _arr(graphs.eu) if len(graphs.eu) else np.zeros(1, np.int32)
+    ev = _arr(graphs.ev) if len(graphs.ev) else np.zeros(1, np.int32)
+    el = None if graphs.elabel is None else (_arr(graphs.elabel) if len(graphs.elabel) else np.zeros(1, np.int32))
+    c = _arr(costs)
+    failed = ctypes.c_int64(-1)
+    st = lib.oracle_bipartite_pairs(_ptr(n), _ptr(m), _ptr(voff), _ptr(eoff), _ptr(vl), _ptr(eu),
+                                    _ptr(ev), _ptr(el), _ptr(pairs), int(len(pairs)), _ptr(c), int(K),
+                                    _ptr(dist), _ptr(maps), _ptr(off), _ptr(solves), ctypes.byref(failed))
+    _check(st, f"bipartite_pairs (pair {failed.value})")
+    return dist, maps[:total], off, solves

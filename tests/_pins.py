@@ -179,3 +179,74 @@ def networkx_ged(g1, g2, c) -> int:
         edge_subst_cost=lambda a, b: 0 if a["label"] == b["label"] else c[ESUB],
         edge_del_cost=lambda a: c[EDEL],
         edge_ins_cost=lambda a: c[EINS])))
+
+
+# ---------------------------------------------------------------------------
+# Bipartite K-best assignments: every vertex mapping with its bipartite
+# (Riesen-Bunke) assignment cost, the local edge term found by brute force
+# over the incident edges instead of a closed form.
+
+def incident_labels(g) -> List[List[int]]:
+    el = g.elabel if getattr(g, "elabel", None) is not None else [0] * len(g.eu)
+    out: List[List[int]] = [[] for _ in range(int(g.n))]
+    for a, b, l in zip(g.eu, g.ev, el):
+        out[int(a)].append(int(l))
+        out[int(b)].append(int(l))
+    return out
+
+
+def edge_assignment_cost(A: Sequence[int], B: Sequence[int], c: Sequence[int]) -> int:
+    """Least cost of editing the edge-label list A into B: every injective
+    partial matching of A into B tried (matched pairs cost esub when the labels
+    differ, unmatched A edges edel, unmatched B edges eins)."""
+    best = None
+    nA, nB = len(A), len(B)
+    for k in range(min(nA, nB) + 1):
+        for sa in itertools.combinations(range(nA), k):
+            for sb in itertools.permutations(range(nB), k):
+                cost = sum(c[ESUB] if A[x] != B[y] else 0 for x, y in zip(sa, sb))
+                cost += c[EDEL] * (nA - k) + c[EINS] * (nB - k)
+                if best is None or cost < best:
+                    best = cost
+    return 0 if best is None else best
+
+
+def all_mappings(n1: int, n2: int):
+    """Every vertex mapping g1 -> g2 (-1 = deleted), injective on g2."""
+    def rec(i, used, cur):
+        if i == n1:
+            yield list(cur)
+            return
+        for t in range(n2):
+            if t not in used:
+                used.add(t)
+                cur.append(t)
+                yield from rec(i + 1, used, cur)
+                cur.pop()
+                used.discard(t)
+        cur.append(-1)
+        yield from rec(i + 1, used, cur)
+        cur.pop()
+    yield from rec(0, set(), [])
+
+
+def bipartite_cost(g1, g2, c: Sequence[int], mapping: Sequence[int], inc1=None, inc2=None) -> int:
+    """Assignment cost of a mapping in the square bipartite matrix: substituted
+    pairs (label cost + least incident-edge assignment), deleted g1 vertices
+    with their edges, inserted g2 vertices with their edges."""
+    inc1 = incident_labels(g1) if inc1 is None else inc1
+    inc2 = incident_labels(g2) if inc2 is None else inc2
+    used = set()
+    cost = 0
+    for i, t in enumerate(mapping):
+        t = int(t)
+        if t >= 0:
+            used.add(t)
+            cost += c[VSUB] if int(g1.vlabel[i]) != int(g2.vlabel[t]) else 0
+            cost += edge_assignment_cost(inc1[i], inc2[t], c)
+        else:
+            cost += c[VDEL] + c[EDEL] * len(inc1[i])
+    for t in range(int(g2.n)):
+        if t not in used:
+            cost += c[VINS] + c[EINS] * len(inc2[t])
+    return cost
