@@ -51,13 +51,15 @@
 extern "C" {
 #endif
 
-#define GED_ABI_VERSION 2
+#define GED_ABI_VERSION 3
 
 /* Limits of this version. */
 #define GED_MAX_VERTICES 512      /* per graph */
 #define GED_MAX_K 1024            /* beam width (batched plans, serving) */
 #define GED_MAX_K_WIDE (1 << 21)  /* beam width of the single-pair large-K search */
 #define GED_MAX_EDGE_LABELS 16    /* distinct edge labels in one database */
+#define GED_BIP_MAX_ORDER 64      /* n1 + n2 of a pair, bipartite method */
+#define GED_BIP_MAX_K 64          /* K of the bipartite method */
 
 typedef enum {
     GED_OK = 0,
@@ -171,15 +173,31 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
 #define GED_LAST_SELECT 0
 #define GED_LAST_COMPLETE 1
 
+/* Method.  GED_METHOD_TREE (the default) is the paper's K-Best tree search
+ * (Alg. 1).  GED_METHOD_BIPARTITE is the assignment-based variant, which the
+ * paper does not contain: a node-assignment cost matrix (vertex operation
+ * plus the least-cost assignment of the incident edges, Riesen and Bunke),
+ * the K assignments of least cost enumerated by Murty's partitioning
+ * (Hungarian solver, lowest index on ties, children re-solved from their
+ * parent's potentials, subproblems popped by (cost, creation order)), and
+ * the exact edit cost (Sec. 2.2-2.4) of each; the least, first popped among
+ * equals, is the bound.  It needs n1 + n2 <= GED_BIP_MAX_ORDER for every
+ * pair and K <= GED_BIP_MAX_K (else GED_EUNSUPPORTED), takes last_level =
+ * GED_LAST_SELECT only, and d_cand then counts the assignment problems
+ * solved (the first assignment included). */
+#define GED_METHOD_TREE 0
+#define GED_METHOD_BIPARTITE 1
+
 typedef struct {
     int32_t schedule;        /* GED_SCHED_* */
     int32_t groups_per_cu;   /* resident workgroups per CU of a persistent launch;
                                 0 = the occupancy limit, larger values are clamped to it */
     int32_t last_level;      /* GED_LAST_* */
+    int32_t method;          /* GED_METHOD_* */
 } ged_plan_options;
 
 /* ged_plan_create with options (NULL = defaults).  GED_EINVAL for an
- * unknown schedule or last level, or groups_per_cu < 0. */
+ * unknown schedule, last level or method, or groups_per_cu < 0. */
 ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                               const ged_plan_options *options, ged_plan **out);
 ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries);
@@ -203,8 +221,8 @@ ged_status ged_plan_kernel_ms(ged_plan *plan, float *ms);
 ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
 
 /* The plan's size bins, in launch order.  For bin `index`: *kernel is
- * GED_KERNEL_WAVE (a wavefront per pair) or GED_KERNEL_BLOCK (a workgroup
- * per pair), *npairs the pairs in the bin, *grid the persistent launch's
+ * GED_KERNEL_WAVE (a wavefront per pair), GED_KERNEL_BLOCK (a workgroup
+ * per pair) or GED_KERNEL_BIPARTITE (bipartite method), *npairs the pairs in the bin, *grid the persistent launch's
  * workgroups, *words the target-row words the instantiation handles (1
  * or 2 for the wavefront kernels: n <= 32 or n <= 64).
  * Any output pointer may be NULL. */
@@ -236,6 +254,7 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
 
 #define GED_KERNEL_WAVE 0
 #define GED_KERNEL_BLOCK 1
+#define GED_KERNEL_BIPARTITE 2   /* the bipartite method's wavefront kernel */
 ged_status ged_plan_bin_count(const ged_plan *plan, int32_t *count);
 ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kernel, int64_t *npairs,
                              int32_t *grid, int32_t *words);
@@ -276,7 +295,8 @@ typedef struct ged_wide ged_wide;
 
 ged_status ged_wide_create(ged_db *db, int64_t src, int64_t dst, int32_t K, ged_wide **out);
 /* With options: only last_level is used (GED_LAST_*; schedule and
- * groups_per_cu are ignored).  GED_EINVAL for an unknown last level. */
+ * groups_per_cu are ignored; method must be GED_METHOD_TREE).  GED_EINVAL
+ * for an unknown last level or another method. */
 ged_status ged_wide_create_ex(ged_db *db, int64_t src, int64_t dst, int32_t K, const ged_plan_options *options,
                               ged_wide **out);
 ged_status ged_wide_bytes(const ged_wide *w, int64_t *bytes);

@@ -97,6 +97,15 @@ hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu);
 hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                         Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 
+// Bipartite K-best-assignment bound, one wavefront per pair (kb_bip.hip):
+// n1 + n2 <= 64, K <= 64; `ws` holds grid x K x kBipNodeBytes (queue nodes).
+constexpr int kBipMaxM = 64;
+constexpr int kBipMaxK = 64;
+constexpr int kBipNodeBytes = 768;
+hipError_t bip_max_resident(int PL, int *blocks_per_cu);
+hipError_t launch_bip(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
+                      Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
+
 // Whole-device search of one pair at large K (kb_wide.hip).
 constexpr int kWideMaxK = GED_MAX_K_WIDE;
 

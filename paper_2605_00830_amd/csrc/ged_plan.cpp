@@ -31,6 +31,7 @@ int pow2_at_least(int x) {
 
 // One size bin: pairs sharing a kernel instantiation.
 struct Bin {
+    bool bip = false;            // bipartite method (its own wavefront kernel, queue workspace)
     bool wave_ok = false;        // every pair fits the wavefront kernel
     int wave_words = 0;          // its family: 1 (n <= 32), 2 (n <= 64)
     bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
@@ -58,6 +59,7 @@ struct ged_plan {
     int64_t npairs = 0;
     int32_t K = 0;
     int last_complete = 0;   // GED_LAST_COMPLETE
+    int method = GED_METHOD_TREE;
     int64_t map_entries = 0;
     int cus = 0;
     std::vector<int64_t> pair_n;   // n1 + n2 per pair, for the overflow bound
@@ -96,6 +98,11 @@ void free_plan(ged_plan *p) {
 // Every partial edit distance and every completed cost of a pair is at most
 // max_vertex_cost * (n1 + n2) + max_edge_cost * (m1 + m2); keep it below the
 // kernels' sentinel INT32_MAX.
+//
+// The bipartite method also keeps its matrix entries, assignment costs and
+// solver potentials in int32: an entry is at most 2 vmax + 3 emax (n1 + n2),
+// the potentials stay within a few times (n1 + n2) entries; the bound asks
+// for (n1 + n2 + 1) entries to stay below 2^26.
 ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
     const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
     const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
@@ -105,6 +112,11 @@ ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
         if (bound > lim)
             return fail(GED_EINVAL, "costs may overflow int32 on pair %lld (bound %lld)", (long long)i,
                         (long long)bound);
+        if (p->method == GED_METHOD_BIPARTITE) {
+            const int64_t entry = 2 * vmax + 3 * emax * p->pair_n[i];
+            if ((p->pair_n[i] + 1) * entry >= ((int64_t)1 << 26))
+                return fail(GED_EINVAL, "costs may overflow the bipartite solver on pair %lld", (long long)i);
+        }
     }
     return ok();
 }
@@ -121,6 +133,28 @@ int default_threads(const ged_plan *p, const Bin &b) {
 // the workspace as needed and uploads the work list in the launch order for
 // that grid (blocking copy: no run of the plan may be in flight).
 ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu, int threads) {
+    if (b.bip) {
+        const int gpc = groups_per_cu > 0 ? std::min(groups_per_cu, b.max_wave_per_cu) : b.max_wave_per_cu;
+        const int64_t nwork = (int64_t)b.h_work.size();
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nwork, (int64_t)gpc * p->cus));
+        b.ws_stride = (size_t)p->K * gedk::kBipNodeBytes;
+        const size_t need = b.ws_stride * (size_t)grid;
+        if (b.ws_bytes < need) {
+            if (b.d_ws) GED_HIP(hipFree(b.d_ws));
+            b.d_ws = nullptr;
+            b.ws_bytes = 0;
+            hipError_t e = hipMalloc(&b.d_ws, need);
+            if (e != hipSuccess) return fail(GED_ENOMEM, "workspace allocation failed: %s", hipGetErrorString(e));
+            b.ws_bytes = need;
+        }
+        b.h_work = b.h_sorted;
+        gedh::deal_alternating(b.h_work, grid, 4 * (int64_t)p->cus);
+        GED_HIP(hipMemcpy(b.d_work, b.h_work.data(), sizeof(WorkItem) * (size_t)nwork, hipMemcpyHostToDevice));
+        b.wave = false;
+        b.groups_per_cu = gpc;
+        b.grid = grid;
+        return ok();
+    }
     if (wave && !b.wave_ok) return fail(GED_EINVAL, "bin does not fit the wavefront kernel");
     if (!wave) {
         b.shape.BT = threads;
@@ -161,7 +195,16 @@ struct RunCtx {
 ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool perpair) {
     const int nwork = (int)b.h_work.size();
     if (nwork == 0) return ok();
-    if (b.wave) {
+    if (b.bip) {
+        if (!perpair) {
+            GED_HIP(gedk::launch_bip(b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, b.d_ws, r.o,
+                                     b.grid, r.s));
+        } else {
+            for (int i = 0; i < nwork; ++i)
+                GED_HIP(gedk::launch_bip(b.shape.PL, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K,
+                                         b.d_ws, r.o, 1, r.s));
+        }
+    } else if (b.wave) {
         if (!perpair) {
             GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c,
                                              p->K, p->last_complete, r.o, b.grid, r.s));
@@ -238,8 +281,9 @@ std::string bin_key(const std::string &dev, int K, int last_complete, const Bin 
     int lg = 0;
     while ((1ll << (lg + 1)) <= (long long)b.h_work.size()) ++lg;
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|K%d%s|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, last_complete ? "c" : "",
-             b.wave_ok ? b.wave_words : 0, b.shape.W, b.shape.PL, b.shape.nmax1, b.shape.nmax2, lg);
+    snprintf(buf, sizeof buf, "%s|K%d%s%s|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, last_complete ? "c" : "",
+             b.bip ? "bip" : "", b.wave_ok ? b.wave_words : 0, b.shape.W, b.shape.PL, b.shape.nmax1, b.shape.nmax2,
+             lg);
     return buf;
 }
 
@@ -276,8 +320,13 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
 
 ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                               const ged_plan_options *options, ged_plan **out) {
-    ged_plan_options opt{GED_SCHED_AUTO, 0, GED_LAST_SELECT};
+    ged_plan_options opt{GED_SCHED_AUTO, 0, GED_LAST_SELECT, GED_METHOD_TREE};
     if (options) opt = *options;
+    if (opt.method != GED_METHOD_TREE && opt.method != GED_METHOD_BIPARTITE)
+        return fail(GED_EINVAL, "unknown method %d", opt.method);
+    const bool bip = opt.method == GED_METHOD_BIPARTITE;
+    if (bip && opt.last_level != GED_LAST_SELECT)
+        return fail(GED_EINVAL, "the bipartite method has no last-level option");
     if (opt.schedule != GED_SCHED_AUTO && opt.schedule != GED_SCHED_BLOCK)
         return fail(GED_EINVAL, "unknown schedule %d", opt.schedule);
     if (opt.last_level != GED_LAST_SELECT && opt.last_level != GED_LAST_COMPLETE)
@@ -291,6 +340,8 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     if (npairs > (int64_t)std::numeric_limits<int32_t>::max()) return fail(GED_EUNSUPPORTED, "more than 2^31-1 pairs");
     if (K < 1) return fail(GED_EINVAL, "K must be >= 1 (got %d)", K);
     if (K > GED_MAX_K) return fail(GED_EUNSUPPORTED, "K = %d exceeds %d", K, GED_MAX_K);
+    if (bip && K > GED_BIP_MAX_K)
+        return fail(GED_EUNSUPPORTED, "K = %d exceeds the bipartite method's %d", K, GED_BIP_MAX_K);
     ged_status st = gedh::check_device(db);
     if (st != GED_OK) return st;
 
@@ -300,6 +351,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     p->npairs = npairs;
     p->K = K;
     p->last_complete = opt.last_level == GED_LAST_COMPLETE ? 1 : 0;
+    p->method = opt.method;
     p->pair_n.resize((size_t)npairs);
     p->pair_m.resize((size_t)npairs);
 
@@ -319,10 +371,16 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const GraphRec &g2 = db->h_graphs[(size_t)d];
         p->pair_n[(size_t)i] = (int64_t)g1.n + g2.n;
         p->pair_m[(size_t)i] = (int64_t)g1.m + g2.m;
-        const int ww = opt.schedule == GED_SCHED_AUTO ? gedk::wave_words_for(g1.n, g2.n, K) : 0;
+        if (bip && g1.n + g2.n > GED_BIP_MAX_ORDER) {
+            free_plan(p);
+            return fail(GED_EUNSUPPORTED, "pair %lld: n1 + n2 = %d exceeds the bipartite method's %d", (long long)i,
+                        g1.n + g2.n, GED_BIP_MAX_ORDER);
+        }
+        const int ww = (!bip && opt.schedule == GED_SCHED_AUTO) ? gedk::wave_words_for(g1.n, g2.n, K) : 0;
         const bool wave = ww > 0;
         const int W = pow2_at_least(std::max(1, g2.w));
-        Bin &b = bins[wave ? -ww : W];
+        Bin &b = bins[bip ? -3 : (wave ? -ww : W)];
+        b.bip = bip;
         b.wave_ok = wave;
         b.wave = wave;
         b.wave_words = ww;
@@ -352,6 +410,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     for (auto &kv : bins) {
         p->bins.push_back(Bin());
         Bin &b = p->bins.back();
+        b.bip = kv.second.bip;
         b.wave_ok = kv.second.wave_ok;
         b.wave_words = kv.second.wave_words;
         b.shape = kv.second.shape;
@@ -363,7 +422,11 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             return cx > cy;
         });
         b.h_sorted = b.h_work;
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        if (b.bip) {
+            e = gedk::bip_max_resident(b.shape.PL, &b.max_wave_per_cu);
+            b.max_block_per_cu[0] = b.max_block_per_cu[1] = 1;   // not used
+        }
+        for (int k = 0; k < 2 && e == hipSuccess && !b.bip; ++k) {
             gedk::BlockShape sh = b.shape;
             sh.BT = bt_of(k);
             sh.KS = gedk::block_slot_stride(K, sh.BT);
@@ -372,7 +435,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         if (e == hipSuccess && b.wave_ok)
             e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, p->last_complete, &b.max_wave_per_cu);
         if (e != hipSuccess || b.max_block_per_cu[0] <= 0 || b.max_block_per_cu[1] <= 0 ||
-            (b.wave_ok && b.max_wave_per_cu <= 0)) {
+            ((b.wave_ok || b.bip) && b.max_wave_per_cu <= 0)) {
             free_plan(p);
             return fail(GED_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
         }
@@ -449,7 +512,7 @@ ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kerne
     if (!plan) return fail(GED_EINVAL, "plan is NULL");
     if (index < 0 || index >= (int32_t)plan->bins.size()) return fail(GED_EINVAL, "bin %d out of range", index);
     const Bin &b = plan->bins[(size_t)index];
-    if (kernel) *kernel = b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK;
+    if (kernel) *kernel = b.bip ? GED_KERNEL_BIPARTITE : (b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK);
     if (npairs) *npairs = (int64_t)b.h_work.size();
     if (grid) *grid = b.grid;
     if (words) *words = b.wave ? b.wave_words : b.shape.W;
@@ -509,7 +572,7 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     for (Bin &b : plan->bins) {
         const std::string key = bin_key(dev, plan->K, plan->last_complete, b);
         auto hit = cache.find(key);
-        if (hit != cache.end() && (!hit->second.wave || b.wave_ok)) {
+        if (hit != cache.end() && (!hit->second.wave || b.wave_ok || b.bip)) {
             st = configure_bin(plan, b, hit->second.wave, hit->second.groups_per_cu, hit->second.threads);
             if (st != GED_OK) break;
             continue;
@@ -521,7 +584,8 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
         const int64_t nwork = (int64_t)b.h_sorted.size();
         for (int fam = 0; fam < 3; ++fam) {
             const bool wave = fam == 0;
-            if (wave && !b.wave_ok) continue;
+            if (wave && !b.wave_ok && !b.bip) continue;
+            if (!wave && b.bip) continue;   // the bipartite bin has one kernel: only its grid is tuned
             const int threads = fam == 2 ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
             const int lim = wave ? b.max_wave_per_cu : b.max_block_per_cu[bt_index(threads)];
             int64_t last_grid = -1;

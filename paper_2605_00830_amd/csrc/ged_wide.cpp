@@ -35,6 +35,8 @@ ged_status ged_wide_create_ex(ged_db *db, int64_t src, int64_t dst, int32_t K, c
     if (!out) return fail(GED_EINVAL, "out is NULL");
     const int last = options ? options->last_level : GED_LAST_SELECT;
     if (last != GED_LAST_SELECT && last != GED_LAST_COMPLETE) return fail(GED_EINVAL, "unknown last level %d", last);
+    if (options && options->method != GED_METHOD_TREE)
+        return fail(GED_EINVAL, "the single-pair search runs the tree method only");
     *out = nullptr;
     if (!db) return fail(GED_EINVAL, "db is NULL");
     if (src < 0 || src >= db->count || dst < 0 || dst >= db->count)

@@ -33,10 +33,13 @@ class GedError(RuntimeError):
 
 SCHED_AUTO, SCHED_BLOCK = 0, 1
 LAST_SELECT, LAST_COMPLETE = 0, 1
+METHOD_TREE, METHOD_BIPARTITE = 0, 1
+BIP_MAX_ORDER, BIP_MAX_K = 64, 64
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("schedule", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("last_level", ctypes.c_int32)]
+    _fields_ = [("schedule", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("last_level", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 class Costs(ctypes.Structure):
@@ -216,13 +219,13 @@ class Plan:
     """A reusable batched launch plan (ged_plan_create)."""
 
     def __init__(self, db: Database, pairs, K: int, schedule: int = SCHED_AUTO, groups_per_cu: int = 0,
-                 last_level: int = LAST_SELECT):
+                 last_level: int = LAST_SELECT, method: int = METHOD_TREE):
         lib = load()
         self.db = db
         self.pairs = _pairs_array(pairs)
         self.K = int(K)
         handle = ctypes.c_void_p()
-        opt = PlanOptions(int(schedule), int(groups_per_cu), int(last_level))
+        opt = PlanOptions(int(schedule), int(groups_per_cu), int(last_level), int(method))
         _check(lib.ged_plan_create_ex(db.handle, self.pairs.ctypes.data, len(self.pairs), self.K,
                                       ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
@@ -300,6 +303,8 @@ class Plan:
                                          ctypes.byref(grid), ctypes.byref(words)))
             if kern.value == 0:
                 name = "kb_wave_kernel" if words.value == 1 else "kb_wave2_kernel"
+            elif kern.value == 2:
+                name = "kb_bip_kernel"
             else:
                 name = "kb_block_kernel"
             out.append((name, int(npairs.value), int(grid.value), int(words.value)))
@@ -327,7 +332,7 @@ class Result:
     dist: np.ndarray      # int32 [P]
     maps: np.ndarray      # int32 [sum n(src)], -1 = deleted
     offsets: np.ndarray   # int64 [P]
-    cand: Optional[np.ndarray] = None  # int64 [P] children evaluated
+    cand: Optional[np.ndarray] = None  # int64 [P] children evaluated (bipartite: assignment problems solved)
 
     def mapping(self, p: int, n1: int) -> np.ndarray:
         o = int(self.offsets[p])
@@ -335,9 +340,10 @@ class Result:
 
 
 def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: bool = False,
-          stream=None, schedule: int = SCHED_AUTO, groups_per_cu: int = 0, last_level: int = LAST_SELECT) -> Result:
+          stream=None, schedule: int = SCHED_AUTO, groups_per_cu: int = 0, last_level: int = LAST_SELECT,
+          method: int = METHOD_TREE) -> Result:
     """K-Best GED of every (src, dst) pair; synchronizes and returns host arrays."""
-    plan = Plan(db, pairs, K, schedule=schedule, groups_per_cu=groups_per_cu, last_level=last_level)
+    plan = Plan(db, pairs, K, schedule=schedule, groups_per_cu=groups_per_cu, last_level=last_level, method=method)
     try:
         dist, maps, cand = plan.outputs(with_cand=with_cand)
         plan.run(costs, dist, maps, cand, stream=stream, perpair=perpair)
@@ -357,7 +363,7 @@ class Wide:
         self.db = db
         self.src, self.dst, self.K = int(src), int(dst), int(K)
         handle = ctypes.c_void_p()
-        opt = PlanOptions(SCHED_AUTO, 0, int(last_level))
+        opt = PlanOptions(SCHED_AUTO, 0, int(last_level), METHOD_TREE)
         _check(lib.ged_wide_create_ex(db.handle, self.src, self.dst, self.K, ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
         self.n1 = int(db.n[self.src])
