@@ -309,6 +309,81 @@ def large_k_measure(ged, reps: int = 5):
     return out
 
 
+# int32 operations per column relaxation of the bipartite method's solver
+# step: the reduced cost (two subtractions), the tentative-distance compare and
+# two selects (distance, predecessor), the open-column term of the minimum,
+# and the potential or distance update (two)
+BIP_OPS_PER_RELAX = 8
+
+
+def cpu_oracle_bip(graphs, pairs, costs, K, threads: int):
+    """The bipartite oracle over `pairs` with `threads` threads: (wall, dist, maps, solves, steps)."""
+    import oracle
+    oracle._load()
+    shards = [np.arange(t, len(pairs), threads) for t in range(threads)]
+    results = [None] * threads
+
+    def work(t):
+        results[t] = oracle.bipartite_pairs(graphs, pairs[shards[t]], costs, K, with_steps=True)
+
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    wall = time.perf_counter() - t0
+    n_src = np.asarray(graphs.n, np.int64)[pairs[:, 0]]
+    off = np.zeros(len(pairs), np.int64)
+    if len(pairs) > 1:
+        np.cumsum(n_src[:-1], out=off[1:])
+    dist = np.zeros(len(pairs), np.int64)
+    solves = np.zeros(len(pairs), np.int64)
+    steps = np.zeros(len(pairs), np.int64)
+    maps = np.zeros(int(n_src.sum()), np.int32)
+    for t in range(threads):
+        d, m, o, sv, st = results[t]
+        dist[shards[t]] = d
+        solves[shards[t]] = sv
+        steps[shards[t]] = st
+        for k, p in enumerate(shards[t]):
+            maps[off[p]:off[p] + n_src[p]] = m[o[k]:o[k] + n_src[p]]
+    return wall, dist, maps, solves, steps
+
+
+def bipartite_measure(ged, db, w, steps: int, warmup: int, tune: bool, tune_cache):
+    """The same batch by the bipartite K-best-assignment method: pairs/s and
+    kernel time of its plan; parity and the roofline come from the oracle leg."""
+    import torch
+    P = len(w.pairs)
+    plan = ged.Plan(db, w.pairs, w.K, method=ged.METHOD_BIPARTITE)
+    dist, maps, cand = plan.outputs(with_cand=True)
+    s = torch.cuda.current_stream()
+    plan.set_timing(True)
+    if tune:
+        plan.tune(w.costs, dist, maps, stream=s, cache_path=tune_cache)
+        s.synchronize()
+    for _ in range(warmup):
+        plan.run(w.costs, dist, maps, cand, stream=s)
+        s.synchronize()
+    ks = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(w.costs, dist, maps, cand, stream=s)
+        s.synchronize()
+        ks.append(plan.kernel_ms())
+    wall = time.perf_counter() - t0
+    out = {"value": round(P * steps / wall, 2), "unit": "pairs/s", "ms_per_step": round(wall * 1e3 / steps, 4),
+           "kernel_ms": round(float(np.mean(ks)), 4), "bins": plan.bins(), "K": w.K,
+           "assignment_solves": int(cand[:P].sum().item())}
+    log(f"bipartite: kernel {out['kernel_ms']} ms, {out['value']:.0f} pairs/s")
+    d = dist[:P].cpu().numpy().astype(np.int64)
+    m = maps[:plan.map_size].cpu().numpy()
+    c = cand[:P].cpu().numpy()
+    plan.close()
+    return out, d, m, c
+
+
 def complete_measure(ged, db, w, steps: int, warmup: int, literal_dist, tune: bool, tune_cache):
     """The batch with the complete-then-minimum last level (Sec. 4.4.1 applied to
     every child of the last level): kernel time of the same plan shape, and how
@@ -380,6 +455,8 @@ def main():
     ap.add_argument("--no-perpair", action="store_true")
     ap.add_argument("--no-complete", action="store_true",
                     help="skip the complete-then-minimum last-level measurement")
+    ap.add_argument("--no-bipartite", action="store_true",
+                    help="skip the bipartite K-best-assignment measurement")
     ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: reuse its choices, append new ones (default: tune afresh)")
@@ -524,6 +601,11 @@ def main():
         complete["roofline"] = {"bound": "alu", "achieved": round(ach_c, 4), "peak": round(PEAK_INT32_TOPS, 2),
                                 "unit": "Tops/s", "frac": round(ach_c / PEAK_INT32_TOPS, 5)}
 
+    bip = None
+    if not args.no_bipartite and args.workload == "batch":
+        bip, b_dist, b_maps, b_cand = bipartite_measure(ged, db, w, args.steps, args.warmup, not args.no_tune,
+                                                        args.tune_cache)
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -551,6 +633,27 @@ def main():
             c_sel = np.concatenate([c_maps[moff[p]:moff[p + 1]] for p in sample]) if len(sample) else c_maps[:0]
             complete["parity"] = {"pairs_checked": int(len(sample)),
                                   "bit_exact": bool(np.array_equal(c_dist[sample], kd) and np.array_equal(c_sel, km))}
+        if bip is not None:
+            # the bipartite oracle on the same sample: parity, its own CPU
+            # baseline, and the solver steps that price the kernel's work
+            bw, bd, bm, bsv, bst = cpu_oracle_bip(w.graphs, w.pairs[sample], w.costs, w.K, threads)
+            b_sel = np.concatenate([b_maps[moff[p]:moff[p + 1]] for p in sample]) if len(sample) else b_maps[:0]
+            bip["parity"] = {"pairs_checked": int(len(sample)),
+                             "bit_exact": bool(np.array_equal(b_dist[sample], bd) and np.array_equal(b_sel, bm) and
+                                               np.array_equal(b_cand[sample], bsv))}
+            bip["cpu_baseline"] = {"value": round(len(sample) / bw, 2), "unit": "pairs/s", "cores": threads,
+                                   "kind": "oracle", "sample": f"{len(sample)} of {P} pairs, {threads} threads, "
+                                                               f"{bw:.2f} s wall"}
+            if len(sample) == P:
+                order = np.asarray(w.graphs.n, np.int64)[w.pairs].sum(1)
+                relax = int((bst * order).sum())
+                ops = float(relax) * BIP_OPS_PER_RELAX
+                ach = ops / (bip["kernel_ms"] / 1e3) / 1e12
+                bip["roofline"] = {"bound": "alu", "achieved": round(ach, 4), "peak": round(PEAK_INT32_TOPS, 2),
+                                   "unit": "Tops/s", "frac": round(ach / PEAK_INT32_TOPS, 5),
+                                   "solver_steps": int(bst.sum()), "column_relaxations": relax,
+                                   "ops_per_relaxation": BIP_OPS_PER_RELAX, "ops_per_launch": ops}
+            log(f"bipartite oracle: {len(sample) / bw:.1f} pairs/s; parity {bip['parity']['bit_exact']}")
 
     large_k = None
     if not args.no_large_k and args.workload == "batch":
@@ -584,6 +687,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "complete_then_min": complete,
+        "bipartite": bip,
         "large_k": large_k,
         "serving": serving,
     }

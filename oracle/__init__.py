@@ -66,9 +66,9 @@ def _load():
     lib.oracle_count_mappings.restype = ctypes.c_double
     lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, P, P, P, P]
     lib.oracle_kbest_pairs.restype = ctypes.c_int
-    lib.oracle_bipartite.argtypes = graph_args + graph_args + [P, i64, P, P, P, P, P, P]
+    lib.oracle_bipartite.argtypes = graph_args + graph_args + [P, i64, P, P, P, P, P, P, P]
     lib.oracle_bipartite.restype = ctypes.c_int
-    lib.oracle_bipartite_pairs.argtypes = [P] * 9 + [i64, P, i64, P, P, P, P, P]
+    lib.oracle_bipartite_pairs.argtypes = [P] * 9 + [i64, P, i64, P, P, P, P, P, P]
     lib.oracle_bipartite_pairs.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -201,7 +201,7 @@ def bipartite(g1, g2, costs: Sequence[int], K: int, trace: bool = False):
         pm = np.zeros(max(int(K) * n1, 1), dtype=np.int32)
     st = lib.oracle_bipartite(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
                               ctypes.byref(dist), _ptr(mp), ctypes.byref(solves), _ptr(pc), _ptr(pm),
-                              ctypes.byref(npop))
+                              ctypes.byref(npop), None)
     _check(st, "bipartite")
     out = (int(dist.value), mp[:n1].copy(), int(solves.value))
     if trace:
@@ -210,15 +210,17 @@ def bipartite(g1, g2, costs: Sequence[int], K: int, trace: bool = False):
     return out
 
 
-def bipartite_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int):
+def bipartite_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, with_steps: bool = False):
     """bipartite() over many pairs of a GraphSet: (dist int64 [P], maps int32
-    [sum n_src], offsets int64 [P], solves int64 [P])."""
+    [sum n_src], offsets int64 [P], solves int64 [P]), and with with_steps the
+    solver's search steps per pair (each relaxes every column from one row)."""
     lib = _load()
     pairs = _arr(pairs, np.int64).reshape(-1, 2)
     off = map_offsets(graphs, pairs)
     total = int(np.asarray(graphs.n, np.int64)[pairs[:, 0]].sum()) if len(pairs) else 0
     dist = np.zeros(len(pairs), dtype=np.int64)
     solves = np.zeros(len(pairs), dtype=np.int64)
+    steps = np.zeros(len(pairs), dtype=np.int64)
     maps = np.zeros(max(total, 1), dtype=np.int32)
     n = _arr(graphs.n)
     m = _arr(graphs.m)
@@ -232,6 +234,9 @@ def bipartite_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int):
     failed = ctypes.c_int64(-1)
     st = lib.oracle_bipartite_pairs(_ptr(n), _ptr(m), _ptr(voff), _ptr(eoff), _ptr(vl), _ptr(eu),
                                     _ptr(ev), _ptr(el), _ptr(pairs), int(len(pairs)), _ptr(c), int(K),
-                                    _ptr(dist), _ptr(maps), _ptr(off), _ptr(solves), ctypes.byref(failed))
+                                    _ptr(dist), _ptr(maps), _ptr(off), _ptr(solves), _ptr(steps),
+                                    ctypes.byref(failed))
     _check(st, f"bipartite_pairs (pair {failed.value})")
+    if with_steps:
+        return dist, maps[:total], off, solves, steps
     return dist, maps[:total], off, solves

@@ -197,7 +197,8 @@ static int allowed(const bmatrix *B, const bnode *x, const int *colfix, int i, i
 
 /* insert unassigned row r into the assignment x->p with a shortest
  * augmenting path over reduced costs; 0 when no column can take it */
-static int augment(const bmatrix *B, bnode *x, int r, int64_t *minv, int *way, uint8_t *used, int *colfix) {
+static int augment(const bmatrix *B, bnode *x, int r, int64_t *minv, int *way, uint8_t *used, int *colfix,
+                   int64_t *steps) {
     const int M = B->M;
     for (int j = 0; j < M; j++) colfix[j] = -1;
     for (int i = 0; i < B->n1; i++)
@@ -209,6 +210,7 @@ static int augment(const bmatrix *B, bnode *x, int r, int64_t *minv, int *way, u
     }
     int i0 = r, j0 = -1;
     for (;;) {
+        ++*steps;
         /* relax the columns from row i0 */
         for (int j = 0; j < M; j++) {
             if (used[j] || !allowed(B, x, colfix, i0, j)) continue;
@@ -303,11 +305,13 @@ static int64_t induced(const bgraph *g1, const bgraph *g2, const int32_t *c, con
  * Optional traces of the popped subproblems in pop order: pop_cost[K]
  * (assignment cost in the square form: sum of the chosen substitution and
  * deletion entries plus the insertions of the unused g2 vertices), pop_map
- * [K * n1] and *npop. */
+ * [K * n1] and *npop, and *dijkstra_steps: the solver's search steps (each
+ * relaxes the n1 + n2 columns from one row), a count of the work done. */
 int oracle_bipartite(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                      const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
                      const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K, int64_t *dist,
-                     int32_t *map, int64_t *solves, int64_t *pop_cost, int32_t *pop_map, int64_t *npop) {
+                     int32_t *map, int64_t *solves, int64_t *pop_cost, int32_t *pop_map, int64_t *npop,
+                     int64_t *dijkstra_steps) {
     if (K < 1 || n1 < 0 || n2 < 0) return BO_EINVAL;
     for (int k = 0; k < 6; k++)
         if (costs[k] < 0) return BO_EINVAL;
@@ -335,7 +339,7 @@ int oracle_bipartite(int n1, const int32_t *vl1, int m1, const int32_t *eu1, con
         q = (bnode *)calloc((size_t)capq, sizeof(bnode));
         if (!minv || !way || !colfix || !used || !pre || !rows || !cur || !q) st = BO_ENOMEM;
     }
-    int64_t nsolve = 0, popped = 0, seq = 0, best = BINF;
+    int64_t nsolve = 0, popped = 0, seq = 0, best = BINF, nsteps = 0;
     if (st == BO_OK) {
         /* first solution: rows 0 .. n1-1 from zero potentials (each row's
          * deletion column keeps it feasible) */
@@ -349,7 +353,7 @@ int oracle_bipartite(int n1, const int32_t *vl1, int m1, const int32_t *eu1, con
                 r->p[j] = -1;
             }
             for (int i = 0; i < M && st == BO_OK; i++)
-                if (!augment(&B, r, i, minv, way, used, colfix)) st = BO_EINVAL;   /* cannot happen */
+                if (!augment(&B, r, i, minv, way, used, colfix, &nsteps)) st = BO_EINVAL;   /* cannot happen */
             r->cost = assignment_cost(&B, r);
             r->seq = seq++;
             nq = 1;
@@ -415,7 +419,7 @@ int oracle_bipartite(int n1, const int32_t *vl1, int m1, const int32_t *eu1, con
             memcpy(ch->p, par->p, sizeof(int) * M);
             ch->p[cr] = -1;
             nsolve++;
-            if (augment(&B, ch, r, minv, way, used, colfix)) {
+            if (augment(&B, ch, r, minv, way, used, colfix, &nsteps)) {
                 ch->cost = assignment_cost(&B, ch);
                 ch->seq = seq++;
                 ch->popped = 0;
@@ -430,6 +434,7 @@ int oracle_bipartite(int n1, const int32_t *vl1, int m1, const int32_t *eu1, con
         *dist = best;
         *solves = nsolve;
         if (npop) *npop = popped;
+        if (dijkstra_steps) *dijkstra_steps = nsteps;
     }
     for (int64_t k = 0; k < nq; k++) node_free(&q[k]);
     free(q);
@@ -450,14 +455,15 @@ int oracle_bipartite(int n1, const int32_t *vl1, int m1, const int32_t *eu1, con
 int oracle_bipartite_pairs(const int32_t *n, const int32_t *m, const int64_t *voff, const int64_t *eoff,
                            const int32_t *vlabel, const int32_t *eu, const int32_t *ev, const int32_t *elabel,
                            const int64_t *pairs, int64_t npairs, const int32_t *costs, int64_t K, int64_t *dist,
-                           int32_t *map_out, const int64_t *map_off, int64_t *solves, int64_t *failed_pair) {
+                           int32_t *map_out, const int64_t *map_off, int64_t *solves, int64_t *steps,
+                           int64_t *failed_pair) {
     for (int64_t p = 0; p < npairs; p++) {
         int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
         const int32_t *el_a = elabel ? elabel + eoff[a] : NULL;
         const int32_t *el_b = elabel ? elabel + eoff[b] : NULL;
         int st = oracle_bipartite(n[a], vlabel + voff[a], m[a], eu + eoff[a], ev + eoff[a], el_a, n[b],
                                   vlabel + voff[b], m[b], eu + eoff[b], ev + eoff[b], el_b, costs, K, dist + p,
-                                  map_out + map_off[p], solves + p, NULL, NULL, NULL);
+                                  map_out + map_off[p], solves + p, NULL, NULL, NULL, steps ? steps + p : NULL);
         if (st) {
             *failed_pair = p;
             return st;

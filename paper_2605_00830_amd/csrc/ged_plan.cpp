@@ -100,9 +100,9 @@ void free_plan(ged_plan *p) {
 // kernels' sentinel INT32_MAX.
 //
 // The bipartite method also keeps its matrix entries, assignment costs and
-// solver potentials in int32: an entry is at most 2 vmax + 3 emax (n1 + n2),
-// the potentials stay within a few times (n1 + n2) entries; the bound asks
-// for (n1 + n2 + 1) entries to stay below 2^26.
+// solver potentials in int32, and packs a reduced cost with a 6-bit column
+// index: an entry is at most 2 vmax + 4 emax (n1 + n2), a reduced cost at
+// most (n1 + n2 + 1) entries; the bound keeps that below 2^26.
 ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
     const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
     const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
@@ -113,7 +113,7 @@ ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
             return fail(GED_EINVAL, "costs may overflow int32 on pair %lld (bound %lld)", (long long)i,
                         (long long)bound);
         if (p->method == GED_METHOD_BIPARTITE) {
-            const int64_t entry = 2 * vmax + 3 * emax * p->pair_n[i];
+            const int64_t entry = 2 * vmax + 4 * emax * p->pair_n[i];
             if ((p->pair_n[i] + 1) * entry >= ((int64_t)1 << 26))
                 return fail(GED_EINVAL, "costs may overflow the bipartite solver on pair %lld", (long long)i);
         }
@@ -415,12 +415,15 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         b.wave_words = kv.second.wave_words;
         b.shape = kv.second.shape;
         b.h_work.swap(kv.second.h_work);
-        // longest first: work grows with n1 * (n2 + 1)
-        std::stable_sort(b.h_work.begin(), b.h_work.end(), [&](const WorkItem &x, const WorkItem &y) {
-            const int64_t cx = (int64_t)db->h_graphs[x.src].n * (db->h_graphs[x.dst].n + 1);
-            const int64_t cy = (int64_t)db->h_graphs[y.src].n * (db->h_graphs[y.dst].n + 1);
-            return cx > cy;
-        });
+        // longest first: the tree search's work grows with n1 * (n2 + 1); the
+        // bipartite method's with n1^2 (n1 + n2) (children per pop times
+        // solver steps, measured by rank correlation with its step counts)
+        auto work_of = [&](const WorkItem &x) -> int64_t {
+            const int64_t a = db->h_graphs[x.src].n, c = db->h_graphs[x.dst].n;
+            return b.bip ? a * a * (a + c) : a * (c + 1);
+        };
+        std::stable_sort(b.h_work.begin(), b.h_work.end(),
+                         [&](const WorkItem &x, const WorkItem &y) { return work_of(x) > work_of(y); });
         b.h_sorted = b.h_work;
         if (b.bip) {
             e = gedk::bip_max_resident(b.shape.PL, &b.max_wave_per_cu);

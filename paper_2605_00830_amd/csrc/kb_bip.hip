@@ -15,15 +15,20 @@
 // mm = min(d1, d2), common = equal-label incident edge pairs, ins(j) = vins +
 // eins d2(j), D = max_j ins(j); column n2 + i holds vdel + edel d1 + D; other
 // deletion columns are closed.  Rows n1 .. M-1 are zero filler rows, so every
-// column is always assigned.  The matrix of g1's rows lives in LDS.
+// column is always assigned.  Without edge labels a substitution entry
+// simplifies to edel d1 - vins + D + vsub [labels differ] - (edel + eins) mm
+// (the eins d2 terms cancel), so each lane computes its entry of the scanned
+// row on the fly from the row's degree and label; with edge labels the
+// matrix of g1's rows is built once in LDS, in 16-bit entries when the costs
+// keep every entry below 2^16 (else 32-bit).
 //
-// Lane layout: lane j holds column j's potential v and its row p (-1 when
-// free); lane i holds row i's potential u and its forbidden-column mask; lane
-// q holds queue slot q's key (assignment cost, creation number).  A row is
-// inserted by a Dijkstra search over reduced costs: per step one LDS read of
-// the scanned row per lane, a DPP minimum and a ballot for the first column
-// of least distance, and the potential updates of the tree's rows and
-// columns, all lane-parallel.
+// Lane layout: lane j holds column j's potential v, its row p (-1 when free)
+// and its forbidden-row mask; lane i holds row i's potential u; lane q holds
+// queue slot q's key (assignment cost, creation number).  A row is inserted
+// by a Dijkstra search over reduced costs: per step each lane forms its
+// column's entry of the scanned row, then a DPP minimum and a ballot give the
+// first column of least distance, and the potentials of the tree's rows and
+// columns are updated, all lane-parallel.
 //
 // Murty's partitioning runs over g1's rows: a popped subproblem's free rows
 // r_0 < r_1 < ... each give one child with r_0 .. r_{t-1} fixed to their
@@ -34,6 +39,9 @@
 // suffice (a full queue evicts its largest key).  Each popped mapping is
 // scored by its induced cost with bitset rows: the images of each vertex's
 // earlier neighbours against the image's g2 row.
+#include <algorithm>
+#include <type_traits>
+
 #include "ged_internal.h"
 #include "wave_common.h"
 
@@ -43,6 +51,7 @@ namespace {
 using namespace wv;
 
 constexpr uint32_t BINF = 0x7fffffffu;   // closed entry / unreached column
+constexpr uint32_t C16_CLOSED = 0xffffu;  // closed entry of the 16-bit matrix
 
 // node layout inside a queue slot of kBipNodeBytes
 constexpr int kNodeU = 0;       // int32 [64] row potentials
@@ -71,12 +80,6 @@ __device__ __forceinline__ uint64_t load_row(const uint32_t *A, int w, int v) {
     return lo | (hi << 32);
 }
 
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
-    return (uint64_t)lo | ((uint64_t)hi << 32);
-}
-
 __device__ __forceinline__ uint64_t shfl64(uint64_t x, int l) {
     const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, l);
     const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), l);
@@ -85,10 +88,12 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t x, int l) {
 
 __device__ __forceinline__ uint64_t low_bits(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
 
-template <int PL>
+template <int PL, bool C16>
 __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
-    __shared__ int32_t s_C[64][64];   // rows of g1's vertices
+    using Entry = typename std::conditional<C16, uint16_t, int32_t>::type;
+    // rows of g1's vertices (edge labels only; one row otherwise, unused)
+    __shared__ Entry s_C[PL > 0 ? 64 : 1][64];
     __shared__ int s_col[64];         // column of each row of the popped assignment
     __shared__ int s_item;
 
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
         }
         const int32_t ins = vins + eins * d2;
         const int32_t D = (int32_t)wave_umax(lane < n2 ? (uint32_t)ins : 0u);
-        for (int i = 0; i < n1; ++i) {
+        for (int i = 0; i < (PL > 0 ? n1 : 0); ++i) {
             const int d1i = __builtin_amdgcn_readlane(d1, i);
             const int l1i = __builtin_amdgcn_readlane(l1, i);
             const int mm = min(d1i, d2);
@@ -164,50 +169,69 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                         common += (int)min(__builtin_amdgcn_ubfe(c1, 8u * s, 8u), __builtin_amdgcn_ubfe(cnt2[k], 8u * s, 8u));
                 }
             }
-            int32_t val = (int32_t)BINF;
+            int32_t val = (int32_t)(C16 ? C16_CLOSED : BINF);
             if (lane < n2)
                 val = (l1i != l2 ? vsub : 0) + edel * (d1i - mm) + eins * (d2 - mm) + cross * (mm - common) - ins + D;
             else if (lane == n2 + i)
                 val = vdel + edel * d1i + D;
-            s_C[i][lane] = val;
+            s_C[i][lane] = (Entry)val;
         }
         __syncthreads();
+        // entry (i, lane) of a g1 row; BINF where closed
+        const int32_t rowbase_c = -vins + D;   // + edel d1(i): substitution entries without edge labels
+        const int32_t ed_ei = edel + eins;
+        auto entry = [&](int i) -> uint32_t {
+            if (PL > 0) {
+                const uint32_t e = (uint32_t)s_C[i][lane];
+                return (C16 && e == C16_CLOSED) ? BINF : e;
+            }
+            const int d1i = __builtin_amdgcn_readlane(d1, i);
+            const int l1i = __builtin_amdgcn_readlane(l1, i);
+            const uint32_t sub = (uint32_t)(rowbase_c + edel * d1i + (l1i != l2 ? vsub : 0) - ed_ei * min(d1i, d2));
+            const uint32_t del = lane == n2 + i ? (uint32_t)(vdel + edel * d1i + D) : BINF;
+            return lane < n2 ? sub : del;
+        };
 
         // ---------------- Hungarian row insertion (shortest augmenting path)
-        // u: row potential of lane i; v, p: column lane j.  rowfm: forbidden
-        // columns of row lane i; blocked: column lane j belongs to a fixed row.
-        auto augment = [&](int r, int32_t &u, int32_t &v, int &p, uint64_t rowfm, bool blocked) -> bool {
+        // u: row potential of lane i; v, p: column lane j.  colfm: rows
+        // forbidden on column lane j; blocked: column lane j belongs to a fixed
+        // row.
+        //
+        // Reduced costs stay below (n1 + n2 + 1) times the largest entry
+        // (potentials: u >= 0 grows, v <= 0 falls, |v| at most the assignment
+        // cost), which the host keeps below 2^26; so (distance << 6 | column)
+        // is one 32-bit key whose wave minimum gives both the least distance
+        // and the lowest column holding it.  Per lane the step is branch-free.
+        auto augment = [&](int r, int32_t &u, int32_t &v, int &p, uint64_t colfm, bool blocked) -> bool {
             uint32_t minv = BINF;
             int way = -1;
             bool used = false;
+            bool live = lane < M && !blocked;   // may still be reached (not used, not closed)
             bool intree = lane == r;
             int i0 = r, j0 = -1;
             for (;;) {
                 const int32_t ui0 = __builtin_amdgcn_readlane(u, i0);
-                const uint64_t fm = readlane64(rowfm, i0);
-                const bool real = i0 < n1;
-                const int32_t cst = real ? s_C[i0][lane] : 0;
-                const bool allow = lane < M && !used && !blocked && !((fm >> lane) & 1ull) && (!real || (uint32_t)cst != BINF);
-                if (allow) {
-                    const uint32_t cur = (uint32_t)(cst - ui0 - v);
-                    if (cur < minv) {
-                        minv = cur;
-                        way = j0;
-                    }
-                }
-                const bool open = lane < M && !used;
-                const uint32_t delta = wave_umin(open ? minv : BINF);
-                if (delta == BINF) return false;
-                const int j1 = (int)__builtin_ctzll(__ballot(open && minv == delta));
-                if (intree) u += (int32_t)delta;
-                if (used) v -= (int32_t)delta;
-                else if (lane < M && minv != BINF) minv -= delta;
-                if (lane == j1) used = true;
+                const uint32_t cst = i0 < n1 ? entry(i0) : 0u;
+                const bool allow = live && !((colfm >> i0) & 1ull) && cst != BINF;
+                const uint32_t cur = (uint32_t)((int32_t)cst - ui0 - v);
+                const bool better = allow && cur < minv;
+                minv = better ? cur : minv;
+                way = better ? j0 : way;
+                const bool reach = live && minv != BINF;
+                const uint32_t key = wave_umin(reach ? ((minv << 6) | (uint32_t)lane) : 0xffffffffu);
+                if (key == 0xffffffffu) return false;
+                const uint32_t delta = key >> 6;
+                const int j1 = (int)(key & 63u);
+                u += intree ? (int32_t)delta : 0;
+                v -= used ? (int32_t)delta : 0;
+                minv -= reach ? delta : 0u;
+                used = used || lane == j1;
+                live = live && lane != j1;
                 j0 = j1;
                 const int pj = __builtin_amdgcn_readlane(p, j1);
                 if (pj < 0) break;
                 i0 = pj;
-                if (lane == i0) intree = true;
+                intree = intree || lane == i0;
             }
             // flip the path back to r
             while (j0 >= 0) {
@@ -219,7 +243,18 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
             return true;
         };
         auto assignment_cost = [&](int p) -> uint32_t {
-            const uint32_t e = (lane < M && p >= 0 && p < n1) ? (uint32_t)s_C[p][lane] : 0u;
+            const bool real = lane < M && p >= 0 && p < n1;
+            uint32_t e = 0u;
+            if (PL > 0) {
+                e = real ? (uint32_t)s_C[p][lane] : 0u;
+            } else {
+                // every lane shuffles (sources outside the branch's lanes)
+                const int pp = real ? p : 0;
+                const int d1p = __shfl(d1, pp), l1p = __shfl(l1, pp);
+                if (real)
+                    e = lane < n2 ? (uint32_t)(rowbase_c + edel * d1p + (l1p != l2 ? vsub : 0) - ed_ei * min(d1p, d2))
+                                  : (uint32_t)(vdel + edel * d1p + D);
+            }
             return wave_sum(e);
         };
 
@@ -267,10 +302,10 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
             const uint64_t fixm = *reinterpret_cast<const uint64_t *>(nq + kNodeFix);
             const int nf = *reinterpret_cast<const int32_t *>(nq + kNodeNf);
             const uint32_t fent = lane < nf ? reinterpret_cast<const uint16_t *>(nq + kNodeForb)[lane] : 0u;
-            uint64_t rowfm = 0ull;
+            uint64_t colfm = 0ull;
             for (int k = 0; k < nf; ++k) {
                 const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)fent, k);
-                if (lane == (int)(e & 0xffu)) rowfm |= 1ull << (e >> 8);
+                if (lane == (int)(e >> 8)) colfm |= 1ull << (e & 0xffu);
             }
             if (p_par >= 0) s_col[p_par] = lane;
             __syncthreads();
@@ -327,7 +362,7 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                 const int c = __builtin_amdgcn_readlane(colr, r);
                 int32_t cu = u_par, cv = v_par;
                 int cp = lane == c ? -1 : p_par;
-                const uint64_t cfm = rowfm | (lane == r ? (1ull << c) : 0ull);
+                const uint64_t cfm = colfm | (lane == c ? (1ull << r) : 0ull);
                 ++solves;
                 if (augment(r, cu, cv, cp, cfm, blocked)) {
                     const uint32_t cost = assignment_cost(cp);
@@ -377,29 +412,40 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
     }
 }
 
-template <int PL>
+template <int PL, bool C16>
 const void *bip_ptr() {
-    return reinterpret_cast<const void *>(&kb_bip_kernel<PL>);
+    return reinterpret_cast<const void *>(&kb_bip_kernel<PL, C16>);
 }
 
-const void *select_bip(int PL) {
-    if (PL == 0) return bip_ptr<0>();
-    if (PL == 2) return bip_ptr<2>();
-    if (PL == 4) return bip_ptr<4>();
+const void *select_bip(int PL, bool c16) {
+    if (PL == 0) return bip_ptr<0, true>();   // no matrix: one instantiation
+    if (PL == 2) return c16 ? bip_ptr<2, true>() : bip_ptr<2, false>();
+    if (PL == 4) return c16 ? bip_ptr<4, true>() : bip_ptr<4, false>();
     return nullptr;
+}
+
+// every matrix entry below the 16-bit closed marker: an entry is at most
+// max(vsub, vdel) + (edel + eins + cross) * 63 + (vins + eins * 63)
+bool entries_fit_16(const Costs &c) {
+    const int64_t cross = std::min<int64_t>(c.esub, (int64_t)c.edel + c.eins);
+    const int64_t top = std::max<int64_t>(c.vsub, c.vdel) + ((int64_t)c.edel + c.eins + cross) * 63 + c.vins +
+                        (int64_t)c.eins * 63;
+    return top < (int64_t)C16_CLOSED;
 }
 
 }  // namespace
 
+// grids are sized for the 16-bit matrix; with larger costs the 32-bit
+// instantiation holds fewer waves and the rest start as others finish
 hipError_t bip_max_resident(int PL, int *blocks_per_cu) {
-    const void *k = select_bip(PL);
+    const void *k = select_bip(PL, true);
     if (!k) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64, 0);
 }
 
 hipError_t launch_bip(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                       Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_bip(PL);
+    const void *k = select_bip(PL, entries_fit_16(c));
     if (!k || grid <= 0 || K < 1 || K > kBipMaxK || !ws) return hipErrorInvalidValue;
     BipArgs a;
     a.src = src;
