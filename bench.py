@@ -602,7 +602,7 @@ def main():
                                 "unit": "Tops/s", "frac": round(ach_c / PEAK_INT32_TOPS, 5)}
 
     bip = None
-    if not args.no_bipartite and args.workload == "batch":
+    if not args.no_bipartite and args.workload in ("batch", "query"):
         bip, b_dist, b_maps, b_cand = bipartite_measure(ged, db, w, args.steps, args.warmup, not args.no_tune,
                                                         args.tune_cache)
 

@@ -58,8 +58,8 @@ extern "C" {
 #define GED_MAX_K 1024            /* beam width (batched plans, serving) */
 #define GED_MAX_K_WIDE (1 << 21)  /* beam width of the single-pair large-K search */
 #define GED_MAX_EDGE_LABELS 16    /* distinct edge labels in one database */
-#define GED_BIP_MAX_ORDER 64      /* n1 + n2 of a pair, bipartite method */
-#define GED_BIP_MAX_K 64          /* K of the bipartite method */
+#define GED_BIP_MAX_ORDER 256     /* n1 + n2 of a pair, bipartite method */
+#define GED_BIP_MAX_K 256         /* K of the bipartite method */
 
 typedef enum {
     GED_OK = 0,
@@ -222,7 +222,8 @@ ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
 
 /* The plan's size bins, in launch order.  For bin `index`: *kernel is
  * GED_KERNEL_WAVE (a wavefront per pair), GED_KERNEL_BLOCK (a workgroup
- * per pair) or GED_KERNEL_BIPARTITE (bipartite method), *npairs the pairs in the bin, *grid the persistent launch's
+ * per pair) or GED_KERNEL_BIPARTITE (bipartite method; *words is then
+ * its columns per lane, ceil((n1 + n2) / 64)), *npairs the pairs in the bin, *grid the persistent launch's
  * workgroups, *words the target-row words the instantiation handles (1
  * or 2 for the wavefront kernels: n <= 32 or n <= 64).
  * Any output pointer may be NULL. */

@@ -98,13 +98,21 @@ hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const Work
                         Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 
 // Bipartite K-best-assignment bound, one wavefront per pair (kb_bip.hip):
-// n1 + n2 <= 64, K <= 64; `ws` holds grid x K x kBipNodeBytes (queue nodes).
-constexpr int kBipMaxM = 64;
-constexpr int kBipMaxK = 64;
-constexpr int kBipNodeBytes = 768;
-hipError_t bip_max_resident(int PL, int *blocks_per_cu);
-hipError_t launch_bip(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
-                      Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
+// n1 + n2 <= 256, K <= 256.  A launch's columns per lane (cpl = ceil((n1 +
+// n2) / 64), 1..4) and queue slots per lane (ceil(K / 64): 1, 2 or 4) pick
+// the instantiation; `ws` holds grid x K x bip_node_bytes(cpl, K) (queue
+// nodes: potentials, assignment, fixed rows, forbidden pairs).
+constexpr int kBipMaxM = 256;
+constexpr int kBipMaxK = 256;
+inline int bip_cols_per_lane(int m) { return m <= 64 ? 1 : (m + 63) / 64; }
+inline int bip_queue_words(int K) { return K <= 64 ? 1 : (K <= 128 ? 2 : 4); }
+inline size_t bip_node_bytes(int cpl, int K) {
+    const size_t raw = 10 * 64 * (size_t)cpl + 8 * (size_t)cpl + 16 + 4 * (size_t)K;
+    return (raw + 255) / 256 * 256;
+}
+hipError_t bip_max_resident(int PL, int cpl, int K, int *blocks_per_cu);
+hipError_t launch_bip(int PL, int cpl, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
+                      int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
 
 // Whole-device search of one pair at large K (kb_wide.hip).
 constexpr int kWideMaxK = GED_MAX_K_WIDE;

@@ -32,6 +32,7 @@ int pow2_at_least(int x) {
 // One size bin: pairs sharing a kernel instantiation.
 struct Bin {
     bool bip = false;            // bipartite method (its own wavefront kernel, queue workspace)
+    int bip_cpl = 0;             // its columns per lane
     bool wave_ok = false;        // every pair fits the wavefront kernel
     int wave_words = 0;          // its family: 1 (n <= 32), 2 (n <= 64)
     bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
@@ -100,9 +101,9 @@ void free_plan(ged_plan *p) {
 // kernels' sentinel INT32_MAX.
 //
 // The bipartite method also keeps its matrix entries, assignment costs and
-// solver potentials in int32, and packs a reduced cost with a 6-bit column
+// solver potentials in int32, and packs a reduced cost with an 8-bit column
 // index: an entry is at most 2 vmax + 4 emax (n1 + n2), a reduced cost at
-// most (n1 + n2 + 1) entries; the bound keeps that below 2^26.
+// most (n1 + n2 + 1) entries; the bound keeps that below 2^24.
 ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
     const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
     const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
@@ -114,7 +115,7 @@ ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
                         (long long)bound);
         if (p->method == GED_METHOD_BIPARTITE) {
             const int64_t entry = 2 * vmax + 4 * emax * p->pair_n[i];
-            if ((p->pair_n[i] + 1) * entry >= ((int64_t)1 << 26))
+            if ((p->pair_n[i] + 1) * entry >= ((int64_t)1 << 24))
                 return fail(GED_EINVAL, "costs may overflow the bipartite solver on pair %lld", (long long)i);
         }
     }
@@ -137,7 +138,7 @@ ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu, int 
         const int gpc = groups_per_cu > 0 ? std::min(groups_per_cu, b.max_wave_per_cu) : b.max_wave_per_cu;
         const int64_t nwork = (int64_t)b.h_work.size();
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nwork, (int64_t)gpc * p->cus));
-        b.ws_stride = (size_t)p->K * gedk::kBipNodeBytes;
+        b.ws_stride = (size_t)p->K * gedk::bip_node_bytes(b.bip_cpl, p->K);
         const size_t need = b.ws_stride * (size_t)grid;
         if (b.ws_bytes < need) {
             if (b.d_ws) GED_HIP(hipFree(b.d_ws));
@@ -197,12 +198,12 @@ ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool per
     if (nwork == 0) return ok();
     if (b.bip) {
         if (!perpair) {
-            GED_HIP(gedk::launch_bip(b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, b.d_ws, r.o,
-                                     b.grid, r.s));
+            GED_HIP(gedk::launch_bip(b.shape.PL, b.bip_cpl, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K,
+                                     b.d_ws, r.o, b.grid, r.s));
         } else {
             for (int i = 0; i < nwork; ++i)
-                GED_HIP(gedk::launch_bip(b.shape.PL, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i, r.c, p->K,
-                                         b.d_ws, r.o, 1, r.s));
+                GED_HIP(gedk::launch_bip(b.shape.PL, b.bip_cpl, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i,
+                                         r.c, p->K, b.d_ws, r.o, 1, r.s));
         }
     } else if (b.wave) {
         if (!perpair) {
@@ -282,8 +283,8 @@ std::string bin_key(const std::string &dev, int K, int last_complete, const Bin 
     while ((1ll << (lg + 1)) <= (long long)b.h_work.size()) ++lg;
     char buf[256];
     snprintf(buf, sizeof buf, "%s|K%d%s%s|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, last_complete ? "c" : "",
-             b.bip ? "bip" : "", b.wave_ok ? b.wave_words : 0, b.shape.W, b.shape.PL, b.shape.nmax1, b.shape.nmax2,
-             lg);
+             b.bip ? "bip" : "", b.bip ? b.bip_cpl : (b.wave_ok ? b.wave_words : 0), b.shape.W, b.shape.PL,
+             b.shape.nmax1, b.shape.nmax2, lg);
     return buf;
 }
 
@@ -356,8 +357,9 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     p->pair_m.resize((size_t)npairs);
 
     // bins keyed by kernel: -1 / -2 = wavefront kernel for n <= 32 / 64,
-    // else target row words rounded up to a power of two (the workgroup
-    // kernel's instantiation)
+    // -3 .. -6 = bipartite kernel with 1 .. 4 columns per lane, else target
+    // row words rounded up to a power of two (the workgroup kernel's
+    // instantiation)
     const int PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     std::map<int, Bin> bins;
     int64_t off = 0;
@@ -379,8 +381,10 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const int ww = (!bip && opt.schedule == GED_SCHED_AUTO) ? gedk::wave_words_for(g1.n, g2.n, K) : 0;
         const bool wave = ww > 0;
         const int W = pow2_at_least(std::max(1, g2.w));
-        Bin &b = bins[bip ? -3 : (wave ? -ww : W)];
+        const int cpl = bip ? gedk::bip_cols_per_lane(g1.n + g2.n) : 0;
+        Bin &b = bins[bip ? -2 - cpl : (wave ? -ww : W)];
         b.bip = bip;
+        b.bip_cpl = cpl;
         b.wave_ok = wave;
         b.wave = wave;
         b.wave_words = ww;
@@ -411,6 +415,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         p->bins.push_back(Bin());
         Bin &b = p->bins.back();
         b.bip = kv.second.bip;
+        b.bip_cpl = kv.second.bip_cpl;
         b.wave_ok = kv.second.wave_ok;
         b.wave_words = kv.second.wave_words;
         b.shape = kv.second.shape;
@@ -426,7 +431,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
                          [&](const WorkItem &x, const WorkItem &y) { return work_of(x) > work_of(y); });
         b.h_sorted = b.h_work;
         if (b.bip) {
-            e = gedk::bip_max_resident(b.shape.PL, &b.max_wave_per_cu);
+            e = gedk::bip_max_resident(b.shape.PL, b.bip_cpl, K, &b.max_wave_per_cu);
             b.max_block_per_cu[0] = b.max_block_per_cu[1] = 1;   // not used
         }
         for (int k = 0; k < 2 && e == hipSuccess && !b.bip; ++k) {
@@ -518,7 +523,7 @@ ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kerne
     if (kernel) *kernel = b.bip ? GED_KERNEL_BIPARTITE : (b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK);
     if (npairs) *npairs = (int64_t)b.h_work.size();
     if (grid) *grid = b.grid;
-    if (words) *words = b.wave ? b.wave_words : b.shape.W;
+    if (words) *words = b.bip ? b.bip_cpl : (b.wave ? b.wave_words : b.shape.W);
     return ok();
 }
 

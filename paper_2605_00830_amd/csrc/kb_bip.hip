@@ -1,5 +1,5 @@
 // kb_bip.hip -- the bipartite K-best-assignment bound of graph edit distance,
-// one wavefront per pair (n1 + n2 <= 64, K <= 64).
+// one wavefront per pair (n1 + n2 <= 256, K <= 256).
 //
 // The variant: a node-assignment cost matrix (Riesen and Bunke's bipartite
 // edit cost: vertex operation plus the least-cost assignment of the incident
@@ -15,20 +15,21 @@
 // mm = min(d1, d2), common = equal-label incident edge pairs, ins(j) = vins +
 // eins d2(j), D = max_j ins(j); column n2 + i holds vdel + edel d1 + D; other
 // deletion columns are closed.  Rows n1 .. M-1 are zero filler rows, so every
-// column is always assigned.  Without edge labels a substitution entry
-// simplifies to edel d1 - vins + D + vsub [labels differ] - (edel + eins) mm
-// (the eins d2 terms cancel), so each lane computes its entry of the scanned
-// row on the fly from the row's degree and label; with edge labels the
-// matrix of g1's rows is built once in LDS, in 16-bit entries when the costs
-// keep every entry below 2^16 (else 32-bit).
+// column is always assigned.  No matrix is stored: a lane forms its columns'
+// entries of the scanned row from the row's degree, label and incident-label
+// counts (read once per step) and its columns' own.
 //
-// Lane layout: lane j holds column j's potential v, its row p (-1 when free)
-// and its forbidden-row mask; lane i holds row i's potential u; lane q holds
-// queue slot q's key (assignment cost, creation number).  A row is inserted
-// by a Dijkstra search over reduced costs: per step each lane forms its
-// column's entry of the scanned row, then a DPP minimum and a ballot give the
-// first column of least distance, and the potentials of the tree's rows and
-// columns are updated, all lane-parallel.
+// Lane layout, CPL = ceil(M / 64) slots per lane: lane l holds columns l,
+// l + 64, ... (potential v, row p, search distance and predecessor) and rows
+// l, l + 64, ... (potential u); QPL = ceil(K / 64) queue slots per lane hold
+// the keys (assignment cost, creation number).  A row is inserted by a
+// Dijkstra search over reduced costs: per step each lane relaxes its columns
+// from the scanned row, one DPP minimum over (distance << 8 | column) gives
+// the first column of least distance (reduced costs stay below (M + 1)
+// entries, which the host keeps below 2^24), and the potentials of the
+// tree's rows and columns are updated, branch-free per lane.  The matrix is
+// square and every assigned pair tight, so an assignment's cost is the sum
+// of all potentials.
 //
 // Murty's partitioning runs over g1's rows: a popped subproblem's free rows
 // r_0 < r_1 < ... each give one child with r_0 .. r_{t-1} fixed to their
@@ -36,10 +37,13 @@
 // potentials with that one row re-inserted.  Queue nodes (potentials,
 // assignment, fixed rows, forbidden pairs) live in a per-wave slice of the
 // workspace; only the K - popped least keys can still be popped, so K slots
-// suffice (a full queue evicts its largest key).  Each popped mapping is
-// scored by its induced cost with bitset rows: the images of each vertex's
-// earlier neighbours against the image's g2 row.
-#include <algorithm>
+// suffice (a full queue evicts its largest key).  A popped node's forbidden
+// pairs go into an LDS bitmap (row x column) with a per-row summary bit, read
+// by a step only when its row has any.  Each popped mapping is scored by its
+// induced cost: per g1 vertex, its earlier neighbours' images tested against
+// the image's g2 row.
+#include <hip/hip_runtime.h>
+
 #include <type_traits>
 
 #include "ged_internal.h"
@@ -51,16 +55,6 @@ namespace {
 using namespace wv;
 
 constexpr uint32_t BINF = 0x7fffffffu;   // closed entry / unreached column
-constexpr uint32_t C16_CLOSED = 0xffffu;  // closed entry of the 16-bit matrix
-
-// node layout inside a queue slot of kBipNodeBytes
-constexpr int kNodeU = 0;       // int32 [64] row potentials
-constexpr int kNodeV = 256;     // int32 [64] column potentials
-constexpr int kNodeP = 512;     // int8 [64] row on each column
-constexpr int kNodeFix = 576;   // uint64 fixed rows
-constexpr int kNodeNf = 584;    // int32 forbidden pairs
-constexpr int kNodeForb = 640;  // uint16 [64] forbidden (row | column << 8)
-static_assert(kNodeForb + 128 <= kBipNodeBytes, "queue node layout");
 
 struct BipArgs {
     DbView src;
@@ -70,31 +64,44 @@ struct BipArgs {
     int *queue;
     Costs c;
     int K;
-    unsigned char *ws;   // grid x K x kBipNodeBytes
+    int pad;
+    size_t node_bytes;
+    unsigned char *ws;   // grid x K x node_bytes
     Outputs out;
 };
 
-__device__ __forceinline__ uint64_t load_row(const uint32_t *A, int w, int v) {
-    const uint64_t lo = A[(size_t)v * w];
-    const uint64_t hi = w > 1 ? A[(size_t)v * w + 1] : 0u;
-    return lo | (hi << 32);
+// one of N per-lane slots, chosen by an index: an OR of masked values (a
+// select chain over the array would be turned back into an indexed load of
+// a stack copy)
+template <int N, typename T>
+__device__ __forceinline__ T pick(const T (&x)[N], int s) {
+    using U = typename std::conditional<sizeof(T) == 8, uint64_t, uint32_t>::type;
+    U r = 0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        U bits;
+        __builtin_memcpy(&bits, &x[k], sizeof(T));
+        r |= bits & (U)(0 - (U)(s == k));
+    }
+    T out;
+    __builtin_memcpy(&out, &r, sizeof(T));
+    return out;
 }
 
-__device__ __forceinline__ uint64_t shfl64(uint64_t x, int l) {
-    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, l);
-    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), l);
-    return (uint64_t)lo | ((uint64_t)hi << 32);
+__device__ __forceinline__ bool adj_bit(const uint32_t *A, int w, int x, int y) {
+    return (A[(size_t)x * w + (y >> 5)] >> (y & 31)) & 1u;
 }
 
-__device__ __forceinline__ uint64_t low_bits(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
-
-template <int PL, bool C16>
+template <int PL, int CPL, int QPL>
 __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
-    using Entry = typename std::conditional<C16, uint16_t, int32_t>::type;
-    // rows of g1's vertices (edge labels only; one row otherwise, unused)
-    __shared__ Entry s_C[PL > 0 ? 64 : 1][64];
-    __shared__ int s_col[64];         // column of each row of the popped assignment
+    constexpr int NL = PL > 0 ? (1 << PL) : 1;   // edge-label codes
+    constexpr int NW = (NL + 3) / 4;             // words of byte counts
+    constexpr int MAXM = 64 * CPL;
+    __shared__ int s_col[MAXM];                  // column of each row of the popped assignment
+    __shared__ int s_phi[MAXM];                  // its mapping of g1's vertices
+    __shared__ unsigned long long s_forb[MAXM][CPL];   // forbidden (row, column) bits
+    __shared__ unsigned long long s_rowf[CPL];   // rows with any forbidden column
     __shared__ int s_item;
 
     const int lane = threadIdx.x;
@@ -103,7 +110,11 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
     const int32_t cross = min(esub, edel + eins);
     const int K = a.K;
     const int P = a.dst.planes;
-    unsigned char *ws = a.ws + (size_t)blockIdx.x * (size_t)K * kBipNodeBytes;
+    const size_t NB = a.node_bytes;
+    // node layout (offsets inside a slot of NB bytes)
+    const size_t oV = 4 * (size_t)MAXM, oP = 8 * (size_t)MAXM, oFix = 10 * (size_t)MAXM;
+    const size_t oNf = oFix + 8 * CPL, oForb = oNf + 16;
+    unsigned char *ws = a.ws + (size_t)blockIdx.x * (size_t)K * NB;
 
     for (bool first = true;; first = false) {
         int item = (int)blockIdx.x;
@@ -119,287 +130,439 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
         const GraphRec g1 = a.src.graphs[wi.src];
         const GraphRec g2 = a.dst.graphs[wi.dst];
         const int n1 = g1.n, n2 = g2.n, M = n1 + n2;
+        const int w1 = g1.w, w2 = g2.w;
         const uint32_t *A1 = a.src.adj + g1.adj;
         const uint32_t *A2 = a.dst.adj + g2.adj;
-        const uint64_t r1 = lane < n1 ? load_row(A1, g1.w, lane) : 0ull;
-        const uint64_t r2 = lane < n2 ? load_row(A2, g2.w, lane) : 0ull;
-        const int l1 = lane < n1 ? a.src.vlab[g1.vlab + lane] : 0;
-        const int l2 = lane < n2 ? a.dst.vlab[g2.vlab + lane] : 0;
-        uint64_t p1[PLA], p2[PLA];
-#pragma unroll
-        for (int b = 0; b < PLA; ++b) {
-            p1[b] = (PL > 0 && b < P && lane < n1) ? load_row(A1 + (size_t)(1 + b) * n1 * g1.w, g1.w, lane) : 0ull;
-            p2[b] = (PL > 0 && b < P && lane < n2) ? load_row(A2 + (size_t)(1 + b) * n2 * g2.w, g2.w, lane) : 0ull;
-        }
-        const int d1 = __popcll(r1), d2 = __popcll(r2);
 
-        // ---------------- cost matrix
-        // incident-edge label counts, one byte per label code
-        constexpr int NL = PL > 0 ? (1 << PL) : 1;
-        uint32_t cnt1[(NL + 3) / 4], cnt2[(NL + 3) / 4];
+        // ---------------- per-vertex degree, label, incident-label counts
+        int d1[CPL], l1[CPL], d2[CPL], l2[CPL];
+        uint32_t c1[CPL][NW], c2[CPL][NW];
 #pragma unroll
-        for (int k = 0; k < (NL + 3) / 4; ++k) cnt1[k] = cnt2[k] = 0u;
-        if (PL > 0) {
+        for (int k = 0; k < CPL; ++k) {
+            const int x = lane + 64 * k;
+            d1[k] = d2[k] = 0;
+            l1[k] = x < n1 ? a.src.vlab[g1.vlab + x] : 0;
+            l2[k] = x < n2 ? a.dst.vlab[g2.vlab + x] : 0;
 #pragma unroll
-            for (int L = 0; L < NL; ++L) {
-                uint64_t m1 = r1, m2 = r2;
+            for (int q = 0; q < NW; ++q) c1[k][q] = c2[k][q] = 0u;
+            for (int wd = 0; wd < max(w1, w2); ++wd) {
+                const uint32_t r1 = (x < n1 && wd < w1) ? A1[(size_t)x * w1 + wd] : 0u;
+                const uint32_t r2 = (x < n2 && wd < w2) ? A2[(size_t)x * w2 + wd] : 0u;
+                d1[k] += __popc(r1);
+                d2[k] += __popc(r2);
+                if (PL > 0) {
+                    uint32_t q1[PLA], q2[PLA];
 #pragma unroll
-                for (int b = 0; b < PLA; ++b) {
-                    m1 &= ((L >> b) & 1) ? p1[b] : ~p1[b];
-                    m2 &= ((L >> b) & 1) ? p2[b] : ~p2[b];
+                    for (int b = 0; b < PLA; ++b) {
+                        q1[b] = (b < P && x < n1 && wd < w1) ? A1[(size_t)(1 + b) * n1 * w1 + (size_t)x * w1 + wd] : 0u;
+                        q2[b] = (b < P && x < n2 && wd < w2) ? A2[(size_t)(1 + b) * n2 * w2 + (size_t)x * w2 + wd] : 0u;
+                    }
+#pragma unroll
+                    for (int L = 0; L < NL; ++L) {
+                        uint32_t m1 = r1, m2 = r2;
+#pragma unroll
+                        for (int b = 0; b < PLA; ++b) {
+                            m1 &= ((L >> b) & 1) ? q1[b] : ~q1[b];
+                            m2 &= ((L >> b) & 1) ? q2[b] : ~q2[b];
+                        }
+                        c1[k][L >> 2] += (uint32_t)__popc(m1) << (8 * (L & 3));
+                        c2[k][L >> 2] += (uint32_t)__popc(m2) << (8 * (L & 3));
+                    }
                 }
-                cnt1[L >> 2] |= (uint32_t)__popcll(m1) << (8 * (L & 3));
-                cnt2[L >> 2] |= (uint32_t)__popcll(m2) << (8 * (L & 3));
             }
         }
-        const int32_t ins = vins + eins * d2;
-        const int32_t D = (int32_t)wave_umax(lane < n2 ? (uint32_t)ins : 0u);
-        for (int i = 0; i < (PL > 0 ? n1 : 0); ++i) {
-            const int d1i = __builtin_amdgcn_readlane(d1, i);
-            const int l1i = __builtin_amdgcn_readlane(l1, i);
-            const int mm = min(d1i, d2);
-            int common = mm;
-            if (PL > 0) {
-                common = 0;
+        int32_t ins[CPL];
+        uint32_t dmax = 0u;
 #pragma unroll
-                for (int k = 0; k < (NL + 3) / 4; ++k) {
-                    const uint32_t c1 = (uint32_t)__builtin_amdgcn_readlane((int)cnt1[k], i);
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        common += (int)min(__builtin_amdgcn_ubfe(c1, 8u * s, 8u), __builtin_amdgcn_ubfe(cnt2[k], 8u * s, 8u));
-                }
-            }
-            int32_t val = (int32_t)(C16 ? C16_CLOSED : BINF);
-            if (lane < n2)
-                val = (l1i != l2 ? vsub : 0) + edel * (d1i - mm) + eins * (d2 - mm) + cross * (mm - common) - ins + D;
-            else if (lane == n2 + i)
-                val = vdel + edel * d1i + D;
-            s_C[i][lane] = (Entry)val;
+        for (int k = 0; k < CPL; ++k) {
+            ins[k] = vins + eins * d2[k];
+            dmax = max(dmax, lane + 64 * k < n2 ? (uint32_t)ins[k] : 0u);
         }
-        __syncthreads();
-        // entry (i, lane) of a g1 row; BINF where closed
-        const int32_t rowbase_c = -vins + D;   // + edel d1(i): substitution entries without edge labels
-        const int32_t ed_ei = edel + eins;
-        auto entry = [&](int i) -> uint32_t {
-            if (PL > 0) {
-                const uint32_t e = (uint32_t)s_C[i][lane];
-                return (C16 && e == C16_CLOSED) ? BINF : e;
+        const int32_t D = (int32_t)wave_umax(dmax);
+
+        // entries of g1 row i for this lane's columns; BINF where closed
+        auto row_entries = [&](int i, uint32_t (&e)[CPL]) __attribute__((always_inline)) {
+            const int s = i >> 6, l = i & 63;
+            const int d1i = __builtin_amdgcn_readlane(pick(d1, s), l);
+            const int l1i = __builtin_amdgcn_readlane(pick(l1, s), l);
+            uint32_t c1i[NW];
+#pragma unroll
+            for (int q = 0; q < NW; ++q) {
+                uint32_t col[CPL];
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) col[k] = c1[k][q];
+                c1i[q] = (uint32_t)__builtin_amdgcn_readlane((int)pick(col, s), l);
             }
-            const int d1i = __builtin_amdgcn_readlane(d1, i);
-            const int l1i = __builtin_amdgcn_readlane(l1, i);
-            const uint32_t sub = (uint32_t)(rowbase_c + edel * d1i + (l1i != l2 ? vsub : 0) - ed_ei * min(d1i, d2));
-            const uint32_t del = lane == n2 + i ? (uint32_t)(vdel + edel * d1i + D) : BINF;
-            return lane < n2 ? sub : del;
+            const uint32_t del = (uint32_t)(vdel + edel * d1i + D);
+            if (PL == 0) {
+                // no edge labels (common = mm): the eins d2 terms cancel
+                const int32_t base = edel * d1i - vins + D;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const int j = lane + 64 * k;
+                    const uint32_t sub = (uint32_t)(base + (l1i != l2[k] ? vsub : 0) - (edel + eins) * min(d1i, d2[k]));
+                    e[k] = j < n2 ? sub : (j == n2 + i ? del : BINF);
+                }
+                return;
+            }
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                const int j = lane + 64 * k;
+                const int mm = min(d1i, d2[k]);
+                int common = mm;
+                if (PL > 0) {
+                    common = 0;
+#pragma unroll
+                    for (int q = 0; q < NW; ++q)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            common += (int)min(__builtin_amdgcn_ubfe(c1i[q], 8u * b, 8u),
+                                               __builtin_amdgcn_ubfe(c2[k][q], 8u * b, 8u));
+                }
+                const uint32_t sub = (uint32_t)((l1i != l2[k] ? vsub : 0) + edel * (d1i - mm) + eins * (d2[k] - mm) +
+                                                cross * (mm - common) - ins[k] + D);
+                e[k] = j < n2 ? sub : (j == n2 + i ? del : BINF);
+            }
         };
 
+        // rows of the popped node with any forbidden column (wave-uniform copy)
+        unsigned long long rowf[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) rowf[k] = 0ull;
+
         // ---------------- Hungarian row insertion (shortest augmenting path)
-        // u: row potential of lane i; v, p: column lane j.  colfm: rows
-        // forbidden on column lane j; blocked: column lane j belongs to a fixed
-        // row.
-        //
-        // Reduced costs stay below (n1 + n2 + 1) times the largest entry
-        // (potentials: u >= 0 grows, v <= 0 falls, |v| at most the assignment
-        // cost), which the host keeps below 2^26; so (distance << 6 | column)
-        // is one 32-bit key whose wave minimum gives both the least distance
-        // and the lowest column holding it.  Per lane the step is branch-free.
-        auto augment = [&](int r, int32_t &u, int32_t &v, int &p, uint64_t colfm, bool blocked) -> bool {
-            uint32_t minv = BINF;
-            int way = -1;
-            bool used = false;
-            bool live = lane < M && !blocked;   // may still be reached (not used, not closed)
-            bool intree = lane == r;
+        // u: rows, v / p: columns (per-lane slots); open: column inside M and
+        // not fixed to another row; (fr, fc): the child's own forbidden pair.
+        auto augment = [&](int r, int32_t (&u)[CPL], int32_t (&v)[CPL], int (&p)[CPL], const bool (&open)[CPL], int fr,
+                           int fc) __attribute__((always_inline)) -> bool {
+            uint32_t minv[CPL];
+            int way[CPL];
+            bool used[CPL], live[CPL], intree[CPL];
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                minv[k] = BINF;
+                way[k] = -1;
+                used[k] = false;
+                live[k] = open[k];
+                intree[k] = lane + 64 * k == r;
+            }
             int i0 = r, j0 = -1;
             for (;;) {
-                const int32_t ui0 = __builtin_amdgcn_readlane(u, i0);
-                const uint32_t cst = i0 < n1 ? entry(i0) : 0u;
-                const bool allow = live && !((colfm >> i0) & 1ull) && cst != BINF;
-                const uint32_t cur = (uint32_t)((int32_t)cst - ui0 - v);
-                const bool better = allow && cur < minv;
-                minv = better ? cur : minv;
-                way = better ? j0 : way;
-                const bool reach = live && minv != BINF;
-                const uint32_t key = wave_umin(reach ? ((minv << 6) | (uint32_t)lane) : 0xffffffffu);
+                const int32_t ui0 = __builtin_amdgcn_readlane(pick(u, i0 >> 6), i0 & 63);
+                uint32_t e[CPL];
+                if (i0 < n1) {
+                    row_entries(i0, e);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) e[k] = 0u;
+                }
+                const bool rf = (pick(rowf, i0 >> 6) >> (i0 & 63)) & 1ull;
+                uint32_t key = 0xffffffffu;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const int j = lane + 64 * k;
+                    const bool forb = (rf && ((s_forb[i0][k] >> lane) & 1ull)) || (i0 == fr && j == fc);
+                    const bool allow = live[k] && !forb && e[k] != BINF;
+                    const uint32_t cur = (uint32_t)((int32_t)e[k] - ui0 - v[k]);
+                    const bool better = allow && cur < minv[k];
+                    minv[k] = better ? cur : minv[k];
+                    way[k] = better ? j0 : way[k];
+                    key = min(key, (live[k] && minv[k] != BINF) ? ((minv[k] << 8) | (uint32_t)j) : 0xffffffffu);
+                }
+                key = wave_umin(key);
                 if (key == 0xffffffffu) return false;
-                const uint32_t delta = key >> 6;
-                const int j1 = (int)(key & 63u);
-                u += intree ? (int32_t)delta : 0;
-                v -= used ? (int32_t)delta : 0;
-                minv -= reach ? delta : 0u;
-                used = used || lane == j1;
-                live = live && lane != j1;
+                const uint32_t delta = key >> 8;
+                const int j1 = (int)(key & 255u);
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const bool reach = live[k] && minv[k] != BINF;
+                    u[k] += intree[k] ? (int32_t)delta : 0;
+                    v[k] -= used[k] ? (int32_t)delta : 0;
+                    minv[k] -= reach ? delta : 0u;
+                    const bool hit = lane + 64 * k == j1;
+                    used[k] = used[k] || hit;
+                    live[k] = live[k] && !hit;
+                }
                 j0 = j1;
-                const int pj = __builtin_amdgcn_readlane(p, j1);
+                const int pj = __builtin_amdgcn_readlane(pick(p, j1 >> 6), j1 & 63);
                 if (pj < 0) break;
                 i0 = pj;
-                intree = intree || lane == i0;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) intree[k] = intree[k] || lane + 64 * k == i0;
             }
             // flip the path back to r
             while (j0 >= 0) {
-                const int jp = __builtin_amdgcn_readlane(way, j0);
-                const int np = jp < 0 ? r : __builtin_amdgcn_readlane(p, jp);
-                if (lane == j0) p = np;
+                const int jp = __builtin_amdgcn_readlane(pick(way, j0 >> 6), j0 & 63);
+                const int np = jp < 0 ? r : __builtin_amdgcn_readlane(pick(p, jp >> 6), jp & 63);
+#pragma unroll
+                for (int k = 0; k < CPL; ++k)
+                    if (lane + 64 * k == j0) p[k] = np;
                 j0 = jp;
             }
             return true;
         };
-        auto assignment_cost = [&](int p) -> uint32_t {
-            const bool real = lane < M && p >= 0 && p < n1;
-            uint32_t e = 0u;
-            if (PL > 0) {
-                e = real ? (uint32_t)s_C[p][lane] : 0u;
-            } else {
-                // every lane shuffles (sources outside the branch's lanes)
-                const int pp = real ? p : 0;
-                const int d1p = __shfl(d1, pp), l1p = __shfl(l1, pp);
-                if (real)
-                    e = lane < n2 ? (uint32_t)(rowbase_c + edel * d1p + (l1p != l2 ? vsub : 0) - ed_ei * min(d1p, d2))
-                                  : (uint32_t)(vdel + edel * d1p + D);
-            }
-            return wave_sum(e);
+        // cost of a complete assignment: every row and column assigned and
+        // every assigned pair tight, so it is the sum of all potentials
+        // (lanes past M keep zero potentials)
+        auto assignment_cost = [&](const int32_t (&u)[CPL], const int32_t (&v)[CPL]) __attribute__((always_inline)) -> uint32_t {
+            uint32_t s = 0u;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) s += (uint32_t)u[k] + (uint32_t)v[k];
+            return wave_sum(s);
         };
 
         // ---------------- first assignment: every row from zero potentials
-        int32_t u = 0, v = 0;
-        int p = -1;
-        for (int r = 0; r < M; ++r) (void)augment(r, u, v, p, 0ull, false);   // a deletion column is always open
-        uint32_t qcost = 0u, qseq = 0u;
-        bool qocc = false;
+        int32_t u[CPL], v[CPL];
+        int p[CPL];
+        bool open0[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            u[k] = v[k] = 0;
+            p[k] = -1;
+            open0[k] = lane + 64 * k < M;
+        }
+        for (int r = 0; r < M; ++r) (void)augment(r, u, v, p, open0, -1, -1);   // a deletion column is always open
+        uint32_t qcost[QPL], qseq[QPL];
+        bool qocc[QPL];
+#pragma unroll
+        for (int s = 0; s < QPL; ++s) {
+            qcost[s] = qseq[s] = 0u;
+            qocc[s] = false;
+        }
         {
+            const uint32_t c0 = assignment_cost(u, v);
             unsigned char *nb = ws;
-            if (lane < 64) {
-                reinterpret_cast<int32_t *>(nb + kNodeU)[lane] = u;
-                reinterpret_cast<int32_t *>(nb + kNodeV)[lane] = v;
-                reinterpret_cast<int8_t *>(nb + kNodeP)[lane] = (int8_t)p;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                reinterpret_cast<int32_t *>(nb)[lane + 64 * k] = u[k];
+                reinterpret_cast<int32_t *>(nb + oV)[lane + 64 * k] = v[k];
+                reinterpret_cast<int16_t *>(nb + oP)[lane + 64 * k] = (int16_t)p[k];
             }
-            if (lane == 0) {
-                *reinterpret_cast<uint64_t *>(nb + kNodeFix) = 0ull;
-                *reinterpret_cast<int32_t *>(nb + kNodeNf) = 0;
-            }
-            const uint32_t c0 = assignment_cost(p);
-            if (lane == 0) {
-                qocc = true;
-                qcost = c0;
-                qseq = 0u;
-            }
+            if (lane < CPL) reinterpret_cast<unsigned long long *>(nb + oFix)[lane] = 0ull;
+            if (lane == 0) *reinterpret_cast<int32_t *>(nb + oNf) = 0;
+            qocc[0] = lane == 0;
+            qcost[0] = lane == 0 ? c0 : 0u;
         }
         uint32_t seq = 1u;
         int popped = 0;
         int64_t solves = 1;
         uint32_t best = BINF;
-        int bestphi = -1;
+        int bestphi[CPL];
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) bestphi[k] = -1;
 
         while (popped < K) {
-            if (__ballot(qocc) == 0ull) break;
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < QPL; ++s) any = any || __ballot(qocc[s]) != 0ull;
+            if (!any) break;
             // ---------------- pop the least (cost, creation number)
-            const uint32_t mc = wave_umin(qocc ? qcost : 0xffffffffu);
-            const uint32_t ms = wave_umin(qocc && qcost == mc ? qseq : 0xffffffffu);
-            const int q = (int)__builtin_ctzll(__ballot(qocc && qcost == mc && qseq == ms));
-            if (lane == q) qocc = false;
-            const unsigned char *nq = ws + (size_t)q * kBipNodeBytes;
-            const int32_t u_par = reinterpret_cast<const int32_t *>(nq + kNodeU)[lane];
-            const int32_t v_par = reinterpret_cast<const int32_t *>(nq + kNodeV)[lane];
-            const int p_par = lane < M ? (int)reinterpret_cast<const int8_t *>(nq + kNodeP)[lane] : -1;
-            const uint64_t fixm = *reinterpret_cast<const uint64_t *>(nq + kNodeFix);
-            const int nf = *reinterpret_cast<const int32_t *>(nq + kNodeNf);
-            const uint32_t fent = lane < nf ? reinterpret_cast<const uint16_t *>(nq + kNodeForb)[lane] : 0u;
-            uint64_t colfm = 0ull;
-            for (int k = 0; k < nf; ++k) {
-                const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)fent, k);
-                if (lane == (int)(e >> 8)) colfm |= 1ull << (e & 0xffu);
+            uint32_t lc = 0xffffffffu;
+#pragma unroll
+            for (int s = 0; s < QPL; ++s) lc = min(lc, qocc[s] ? qcost[s] : 0xffffffffu);
+            const uint32_t mc = wave_umin(lc);
+            uint32_t ls = 0xffffffffu;
+#pragma unroll
+            for (int s = 0; s < QPL; ++s) ls = min(ls, (qocc[s] && qcost[s] == mc) ? qseq[s] : 0xffffffffu);
+            const uint32_t ms = wave_umin(ls);
+            int q = 0;
+#pragma unroll
+            for (int s = QPL - 1; s >= 0; --s) {
+                const unsigned long long bl = __ballot(qocc[s] && qcost[s] == mc && qseq[s] == ms);
+                q = bl ? 64 * s + (int)__builtin_ctzll(bl) : q;
             }
-            if (p_par >= 0) s_col[p_par] = lane;
+#pragma unroll
+            for (int s = 0; s < QPL; ++s) qocc[s] = qocc[s] && lane + 64 * s != q;
+            const unsigned char *nq = ws + (size_t)q * NB;
+            int32_t u_par[CPL], v_par[CPL];
+            int p_par[CPL];
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                u_par[k] = reinterpret_cast<const int32_t *>(nq)[lane + 64 * k];
+                v_par[k] = reinterpret_cast<const int32_t *>(nq + oV)[lane + 64 * k];
+                p_par[k] = lane + 64 * k < M ? (int)reinterpret_cast<const int16_t *>(nq + oP)[lane + 64 * k] : -1;
+            }
+            unsigned long long fixm[CPL];
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) fixm[k] = reinterpret_cast<const unsigned long long *>(nq + oFix)[k];
+            const int nf = *reinterpret_cast<const int32_t *>(nq + oNf);
+            uint32_t fent[QPL];
+#pragma unroll
+            for (int s = 0; s < QPL; ++s)
+                fent[s] = lane + 64 * s < nf ? reinterpret_cast<const uint32_t *>(nq + oForb)[lane + 64 * s] : 0u;
+            // forbidden bitmap of this node
+            for (int x = lane; x < MAXM * CPL; x += 64) (&s_forb[0][0])[x] = 0ull;
+            if (lane < CPL) s_rowf[lane] = 0ull;
             __syncthreads();
-            const int colr = lane < n1 ? s_col[lane] : -1;
+#pragma unroll
+            for (int s = 0; s < QPL; ++s) {
+                if (lane + 64 * s < nf) {
+                    const int fr = (int)(fent[s] & 0xffffu), fcol = (int)(fent[s] >> 16);
+                    atomicOr(&s_forb[fr][fcol >> 6], 1ull << (fcol & 63));
+                    atomicOr(&s_rowf[fr >> 6], 1ull << (fr & 63));
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) rowf[k] = s_rowf[k];
+            // row -> column of the popped assignment, and its mapping
+#pragma unroll
+            for (int k = 0; k < CPL; ++k)
+                if (p_par[k] >= 0) s_col[p_par[k]] = lane + 64 * k;
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                const int x = lane + 64 * k;
+                if (x < n1) {
+                    const int cx = s_col[x];
+                    s_phi[x] = cx < n2 ? cx : -1;
+                }
+            }
             __syncthreads();
 
-            // ---------------- its mapping and induced edit cost
-            const int phi = (lane < n1 && colr < n2) ? colr : -1;
-            const int ph = phi >= 0 ? phi : 0;
-            const int l2p = __shfl(l2, ph);
-            const uint64_t R = shfl64(r2, ph);
-            uint64_t Phi = 0ull, PhiB[PLA];
+            // ---------------- its induced edit cost
+            uint32_t vc = 0u, matched = 0u, nsub = 0u;
 #pragma unroll
-            for (int b = 0; b < PLA; ++b) PhiB[b] = 0ull;
-            for (int b = 0; b < n1; ++b) {
-                const int pb = __builtin_amdgcn_readlane(phi, b);
-                if (pb < 0 || b >= lane || !((r1 >> b) & 1ull)) continue;
-                Phi |= 1ull << pb;
-#pragma unroll
-                for (int pl = 0; pl < PLA; ++pl)
-                    if (PL > 0 && ((p1[pl] >> b) & 1ull)) PhiB[pl] |= 1ull << pb;
+            for (int k = 0; k < CPL; ++k) {
+                const int x = lane + 64 * k;
+                if (x >= n1) continue;
+                const int fx = s_phi[x];
+                if (fx < 0) {
+                    vc += (uint32_t)vdel;
+                } else {
+                    ++nsub;
+                    vc += a.dst.vlab[g2.vlab + fx] != l1[k] ? (uint32_t)vsub : 0u;
+                }
+                // earlier neighbours b < x: kept (both mapped onto a g2 edge,
+                // relabelled when a label plane differs) or deleted
+                for (int wd = 0; wd <= (x >> 5); ++wd) {
+                    uint32_t row = A1[(size_t)x * w1 + wd];
+                    if (wd == (x >> 5)) row &= (1u << (x & 31)) - 1u;
+                    while (row) {
+                        const int b = 32 * wd + __builtin_ctz(row);
+                        row &= row - 1u;
+                        const int fb = s_phi[b];
+                        if (fx >= 0 && fb >= 0 && adj_bit(A2, w2, fx, fb)) {
+                            ++matched;
+                            if (PL > 0) {
+                                bool diff = false;
+                                for (int pl = 0; pl < P; ++pl)
+                                    diff = diff || (adj_bit(A1 + (size_t)(1 + pl) * n1 * w1, w1, x, b) !=
+                                                    adj_bit(A2 + (size_t)(1 + pl) * n2 * w2, w2, fx, fb));
+                                vc += diff ? (uint32_t)esub : 0u;
+                            }
+                        } else {
+                            vc += (uint32_t)edel;
+                        }
+                    }
+                }
             }
-            const bool sub = phi >= 0;
-            const uint32_t matched = sub ? (uint32_t)__popcll(Phi & R) : 0u;
-            uint32_t mism = 0u;
-            if (PL > 0) {
-                uint64_t diff = 0ull;
-#pragma unroll
-                for (int pl = 0; pl < PLA; ++pl) diff |= PhiB[pl] ^ shfl64(p2[pl], ph);   // every lane shuffles
-                mism = sub ? (uint32_t)__popcll(Phi & R & diff) : 0u;
-            }
-            const uint32_t early = lane < n1 ? (uint32_t)__popcll(r1 & low_bits(lane)) : 0u;
-            uint32_t lc = 0u;
-            if (lane < n1)
-                lc = (sub ? (l1 != l2p ? (uint32_t)vsub : 0u) : (uint32_t)vdel) + (uint32_t)edel * (early - matched) +
-                     (uint32_t)esub * mism;
-            const uint32_t nsub = (uint32_t)__popcll(__ballot(lane < n1 && sub));
-            const uint32_t d = wave_sum(lc) + (uint32_t)vins * ((uint32_t)n2 - nsub) +
+            const uint32_t nsub_all = wave_sum(nsub);
+            const uint32_t d = wave_sum(vc) + (uint32_t)vins * ((uint32_t)n2 - nsub_all) +
                                (uint32_t)eins * ((uint32_t)g2.m - wave_sum(matched));
             ++popped;
             if (d < best) {
                 best = d;
-                bestphi = phi;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) bestphi[k] = lane + 64 * k < n1 ? s_phi[lane + 64 * k] : -1;
             }
             if (popped == K) break;
 
             // ---------------- partition: one child per free row, ascending
-            uint64_t freem = low_bits(n1) & ~fixm;
-            uint64_t cfix = fixm;
-            bool blocked = p_par >= 0 && p_par < n1 && ((fixm >> p_par) & 1ull);
-            while (freem) {
-                const int r = (int)__builtin_ctzll(freem);
-                freem &= freem - 1ull;
-                const int c = __builtin_amdgcn_readlane(colr, r);
-                int32_t cu = u_par, cv = v_par;
-                int cp = lane == c ? -1 : p_par;
-                const uint64_t cfm = colfm | (lane == c ? (1ull << r) : 0ull);
-                ++solves;
-                if (augment(r, cu, cv, cp, cfm, blocked)) {
-                    const uint32_t cost = assignment_cost(cp);
-                    const uint32_t cseq = seq++;
-                    const int cap = K - popped;
-                    const int occn = __popcll(__ballot(qocc));
-                    int slot = -1;
-                    if (occn < cap) {
-                        slot = (int)__builtin_ctzll(__ballot(!qocc && lane < K));
-                    } else {
-                        // the child's creation number exceeds every queued one,
-                        // so it displaces the largest key only when cheaper
-                        const uint32_t xc = wave_umax(qocc ? qcost : 0u);
-                        const uint32_t xs = wave_umax(qocc && qcost == xc ? qseq : 0u);
-                        if (cost < xc) slot = (int)__builtin_ctzll(__ballot(qocc && qcost == xc && qseq == xs));
+            unsigned long long cfix[CPL];
+            bool blocked[CPL];
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                cfix[k] = fixm[k];
+                const int pk = p_par[k];
+                blocked[k] = pk >= 0 && pk < n1 && ((pick(fixm, pk >> 6) >> (pk & 63)) & 1ull);
+            }
+            for (int wsl = 0; wsl < CPL; ++wsl) {
+                const int base = 64 * wsl;
+                unsigned long long freem = ~pick(fixm, wsl);
+                freem &= n1 - base >= 64 ? ~0ull : (n1 > base ? ((1ull << (n1 - base)) - 1ull) : 0ull);
+                while (freem) {
+                    const int r = base + (int)__builtin_ctzll(freem);
+                    freem &= freem - 1ull;
+                    const int c = s_col[r];   // uniform
+                    int32_t cu[CPL], cv[CPL];
+                    int cp[CPL];
+                    bool open[CPL];
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) {
+                        cu[k] = u_par[k];
+                        cv[k] = v_par[k];
+                        cp[k] = lane + 64 * k == c ? -1 : p_par[k];
+                        open[k] = lane + 64 * k < M && !blocked[k];
                     }
-                    if (slot >= 0) {
-                        unsigned char *nb = ws + (size_t)slot * kBipNodeBytes;
-                        reinterpret_cast<int32_t *>(nb + kNodeU)[lane] = cu;
-                        reinterpret_cast<int32_t *>(nb + kNodeV)[lane] = cv;
-                        reinterpret_cast<int8_t *>(nb + kNodeP)[lane] = (int8_t)cp;
-                        if (lane == 0) {
-                            *reinterpret_cast<uint64_t *>(nb + kNodeFix) = cfix;
-                            *reinterpret_cast<int32_t *>(nb + kNodeNf) = nf + 1;
+                    ++solves;
+                    if (augment(r, cu, cv, cp, open, r, c)) {
+                        const uint32_t cost = assignment_cost(cu, cv);
+                        const uint32_t cseq = seq++;
+                        const int cap = K - popped;
+                        int occn = 0;
+#pragma unroll
+                        for (int s = 0; s < QPL; ++s) occn += __popcll(__ballot(qocc[s]));
+                        int slot = -1;
+                        if (occn < cap) {
+#pragma unroll
+                            for (int s = QPL - 1; s >= 0; --s) {
+                                const unsigned long long bl = __ballot(!qocc[s] && lane + 64 * s < K);
+                                slot = bl ? 64 * s + (int)__builtin_ctzll(bl) : slot;
+                            }
+                        } else {
+                            // the child's creation number exceeds every queued
+                            // one, so it displaces the largest key only when
+                            // cheaper
+                            uint32_t xl = 0u;
+#pragma unroll
+                            for (int s = 0; s < QPL; ++s) xl = max(xl, qocc[s] ? qcost[s] : 0u);
+                            const uint32_t xc = wave_umax(xl);
+                            uint32_t sl = 0u;
+#pragma unroll
+                            for (int s = 0; s < QPL; ++s) sl = max(sl, (qocc[s] && qcost[s] == xc) ? qseq[s] : 0u);
+                            const uint32_t xs = wave_umax(sl);
+                            if (cost < xc) {
+#pragma unroll
+                                for (int s = QPL - 1; s >= 0; --s) {
+                                    const unsigned long long bl = __ballot(qocc[s] && qcost[s] == xc && qseq[s] == xs);
+                                    slot = bl ? 64 * s + (int)__builtin_ctzll(bl) : slot;
+                                }
+                            }
                         }
-                        if (lane <= nf)
-                            reinterpret_cast<uint16_t *>(nb + kNodeForb)[lane] =
-                                (uint16_t)(lane < nf ? fent : ((uint32_t)r | ((uint32_t)c << 8)));
-                        if (lane == slot) {
-                            qocc = true;
-                            qcost = cost;
-                            qseq = cseq;
+                        if (slot >= 0) {
+                            unsigned char *nb = ws + (size_t)slot * NB;
+#pragma unroll
+                            for (int k = 0; k < CPL; ++k) {
+                                reinterpret_cast<int32_t *>(nb)[lane + 64 * k] = cu[k];
+                                reinterpret_cast<int32_t *>(nb + oV)[lane + 64 * k] = cv[k];
+                                reinterpret_cast<int16_t *>(nb + oP)[lane + 64 * k] = (int16_t)cp[k];
+                            }
+                            if (lane < CPL) reinterpret_cast<unsigned long long *>(nb + oFix)[lane] = pick(cfix, lane);
+                            if (lane == 0) *reinterpret_cast<int32_t *>(nb + oNf) = nf + 1;
+#pragma unroll
+                            for (int s = 0; s < QPL; ++s) {
+                                const int x = lane + 64 * s;
+                                if (x <= nf)
+                                    reinterpret_cast<uint32_t *>(nb + oForb)[x] =
+                                        x < nf ? fent[s] : ((uint32_t)r | ((uint32_t)c << 16));
+                            }
+#pragma unroll
+                            for (int s = 0; s < QPL; ++s) {
+                                const bool mine = lane + 64 * s == slot;
+                                qocc[s] = qocc[s] || mine;
+                                qcost[s] = mine ? cost : qcost[s];
+                                qseq[s] = mine ? cseq : qseq[s];
+                            }
                         }
+                    }
+                    // r is fixed for the later children
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) {
+                        cfix[k] |= (r >> 6) == k ? (1ull << (r & 63)) : 0ull;
+                        blocked[k] = blocked[k] || lane + 64 * k == c;
                     }
                 }
-                cfix |= 1ull << r;
-                if (lane == c) blocked = true;
             }
         }
 
@@ -407,45 +570,48 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
             a.out.dist[wi.out] = (int32_t)best;
             if (a.out.cand) a.out.cand[wi.out] = solves;
         }
-        if (lane < n1) a.out.map[wi.map_off + lane] = bestphi;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            if (lane + 64 * k < n1) a.out.map[wi.map_off + lane + 64 * k] = bestphi[k];
         __syncthreads();
     }
 }
 
-template <int PL, bool C16>
-const void *bip_ptr() {
-    return reinterpret_cast<const void *>(&kb_bip_kernel<PL, C16>);
-}
-
-const void *select_bip(int PL, bool c16) {
-    if (PL == 0) return bip_ptr<0, true>();   // no matrix: one instantiation
-    if (PL == 2) return c16 ? bip_ptr<2, true>() : bip_ptr<2, false>();
-    if (PL == 4) return c16 ? bip_ptr<4, true>() : bip_ptr<4, false>();
+template <int PL, int CPL>
+const void *bip_ptr_q(int qpl) {
+    if (qpl == 1) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, 1>);
+    if (qpl == 2) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, 2>);
+    if (qpl == 4) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, 4>);
     return nullptr;
 }
 
-// every matrix entry below the 16-bit closed marker: an entry is at most
-// max(vsub, vdel) + (edel + eins + cross) * 63 + (vins + eins * 63)
-bool entries_fit_16(const Costs &c) {
-    const int64_t cross = std::min<int64_t>(c.esub, (int64_t)c.edel + c.eins);
-    const int64_t top = std::max<int64_t>(c.vsub, c.vdel) + ((int64_t)c.edel + c.eins + cross) * 63 + c.vins +
-                        (int64_t)c.eins * 63;
-    return top < (int64_t)C16_CLOSED;
+template <int PL>
+const void *bip_ptr_c(int cpl, int qpl) {
+    if (cpl == 1) return bip_ptr_q<PL, 1>(qpl);
+    if (cpl == 2) return bip_ptr_q<PL, 2>(qpl);
+    if (cpl == 3) return bip_ptr_q<PL, 3>(qpl);
+    if (cpl == 4) return bip_ptr_q<PL, 4>(qpl);
+    return nullptr;
+}
+
+const void *select_bip(int PL, int cpl, int qpl) {
+    if (PL == 0) return bip_ptr_c<0>(cpl, qpl);
+    if (PL == 2) return bip_ptr_c<2>(cpl, qpl);
+    if (PL == 4) return bip_ptr_c<4>(cpl, qpl);
+    return nullptr;
 }
 
 }  // namespace
 
-// grids are sized for the 16-bit matrix; with larger costs the 32-bit
-// instantiation holds fewer waves and the rest start as others finish
-hipError_t bip_max_resident(int PL, int *blocks_per_cu) {
-    const void *k = select_bip(PL, true);
+hipError_t bip_max_resident(int PL, int cpl, int K, int *blocks_per_cu) {
+    const void *k = select_bip(PL, cpl, bip_queue_words(K));
     if (!k) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64, 0);
 }
 
-hipError_t launch_bip(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
-                      Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_bip(PL, entries_fit_16(c));
+hipError_t launch_bip(int PL, int cpl, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
+                      int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream) {
+    const void *k = select_bip(PL, cpl, bip_queue_words(K));
     if (!k || grid <= 0 || K < 1 || K > kBipMaxK || !ws) return hipErrorInvalidValue;
     BipArgs a;
     a.src = src;
@@ -455,6 +621,8 @@ hipError_t launch_bip(int PL, const DbView &src, const DbView &dst, const WorkIt
     a.queue = queue;
     a.c = c;
     a.K = K;
+    a.pad = 0;
+    a.node_bytes = bip_node_bytes(cpl, K);
     a.ws = static_cast<unsigned char *>(ws);
     a.out = out;
     void *args[] = {&a};

@@ -34,7 +34,7 @@ class GedError(RuntimeError):
 SCHED_AUTO, SCHED_BLOCK = 0, 1
 LAST_SELECT, LAST_COMPLETE = 0, 1
 METHOD_TREE, METHOD_BIPARTITE = 0, 1
-BIP_MAX_ORDER, BIP_MAX_K = 64, 64
+BIP_MAX_ORDER, BIP_MAX_K = 256, 256
 
 
 class PlanOptions(ctypes.Structure):

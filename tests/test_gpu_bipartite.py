@@ -1,7 +1,8 @@
 """The bipartite method (GED_METHOD_BIPARTITE, kb_bip_kernel) against the
 bipartite oracle bit for bit: distance, mapping and the number of assignment
-problems solved, on seeded pairs from one-vertex graphs to n1 + n2 = 64, with and
-without edge labels, at cost scales up to the solver's int32 bound (GPU)."""
+problems solved, on seeded pairs from one-vertex graphs to n1 + n2 = 256 (one to
+four columns per lane) and K up to 256 (one, two and four queue slots per lane),
+with and without edge labels, at cost scales up to the solver's int32 bound (GPU)."""
 import sys
 
 import numpy as np
@@ -93,6 +94,44 @@ def test_order_limits(ged, K):
     bip_vs_oracle(ged, graphs, pairs, PAPER, K)
 
 
+LARGE_SPECS = [(100, 0.05), (90, 0.08), (40, 0.2), (150, 0.03), (120, 0.04), (33, 0.3), (66, 0.1), (128, 0.02)]
+
+
+def large_set():
+    gs = []
+    for k, (n, p) in enumerate(LARGE_SPECS):
+        g = synth.er_graph(89, k, n, n, p, p, 4)
+        if k % 2 == 0:
+            g.elabel = (np.arange(g.m) % 3).astype(np.int32)
+        gs.append(g)
+    return GraphSet.from_graphs(gs)
+
+
+@pytest.mark.parametrize("K", [8, 100])
+def test_orders_past_64(ged, K):
+    """n1 + n2 from 66 to 256: two, three and four columns per lane, labelled and
+    unlabelled graphs, one and two queue slots per lane."""
+    graphs = large_set()
+    n = graphs.n
+    pairs = [[a, b] for a in range(len(n)) for b in range(len(n)) if 64 < n[a] + n[b] <= 256]
+    pick = pairs[1::4] if K == 100 else pairs[::2]
+    m = np.asarray(n)[np.asarray(pick)].sum(1)
+    assert len(set(((m + 63) // 64).tolist())) >= 3   # three column counts per lane
+    bip_vs_oracle(ged, graphs, pick, PAPER, K)
+
+
+def test_k256(ged):
+    """Four queue slots per lane, across column counts."""
+    graphs = large_set()
+    bip_vs_oracle(ged, graphs, [[2, 5], [6, 2], [0, 2], [4, 6], [1, 5], [7, 6]], UNIT, 256)
+
+
+def test_query_molecule_k128(ged):
+    """The molecule query workload's shape at its K = 128 (n 10..70, three edge labels)."""
+    w = synth.query_molecule_10_70(40)
+    bip_vs_oracle(ged, w.graphs, w.pairs, w.costs, 128)
+
+
 def test_pair_er_8x9(ged):
     w = synth.pair_er_8x9()
     bip_vs_oracle(ged, w.graphs, w.pairs, w.costs, w.K)
@@ -132,13 +171,13 @@ def test_perpair_and_tuned_equal(ged):
 
 
 def test_errors(ged):
-    graphs = GraphSet.from_graphs([synth.er_graph(83, k, n, n, 0.2, 0.2, 3) for k, n in enumerate([40, 30, 5])])
+    graphs = GraphSet.from_graphs([synth.er_graph(83, k, n, n, 0.02, 0.02, 3) for k, n in enumerate([140, 120, 5])])
     db = ged.Database(graphs)
     with pytest.raises(ged.GedError) as e:
-        ged.Plan(db, [[0, 1]], 8, method=ged.METHOD_BIPARTITE)          # n1 + n2 = 70
+        ged.Plan(db, [[0, 1]], 8, method=ged.METHOD_BIPARTITE)          # n1 + n2 = 260
     assert e.value.status == ged.GED_EUNSUPPORTED
     with pytest.raises(ged.GedError) as e:
-        ged.Plan(db, [[2, 2]], 65, method=ged.METHOD_BIPARTITE)
+        ged.Plan(db, [[2, 2]], 257, method=ged.METHOD_BIPARTITE)
     assert e.value.status == ged.GED_EUNSUPPORTED
     with pytest.raises(ged.GedError) as e:
         ged.Plan(db, [[2, 2]], 4, method=ged.METHOD_BIPARTITE, last_level=ged.LAST_COMPLETE)
@@ -149,7 +188,7 @@ def test_errors(ged):
     plan = ged.Plan(db, [[2, 1]], 4, method=ged.METHOD_BIPARTITE)
     dist, maps, cand = plan.outputs(with_cand=True)
     with pytest.raises(ged.GedError) as e:
-        plan.run((1 << 20, 1, 1, 1, 1, 1), dist, maps, cand)            # past the solver's int32 bound
+        plan.run((1 << 18, 1, 1, 1, 1, 1), dist, maps, cand)            # past the solver's int32 bound
     assert e.value.status == ged.GED_EINVAL
     plan.close()
     db.close()
