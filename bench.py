@@ -103,6 +103,11 @@ def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
 
 
+def oracle_mod():
+    import oracle
+    return oracle
+
+
 def cpu_oracle(graphs, pairs, costs, K, threads: int, last_complete: bool = False):
     """Run the CPU oracle over `pairs` with `threads` threads (ctypes releases the GIL)."""
     import oracle
@@ -591,6 +596,21 @@ def main():
                    "same_results_as_batched": same}
         log(f"per-pair: {pw * 1e3:.1f} ms for {P} launches, {P / pw:.0f} pairs/s")
 
+    # edit-path output of the batch's mappings (one synchronous library call:
+    # work-list staging, the kernel, the per-pair counts read back)
+    epath = None
+    if args.workload == "batch":
+        e_ops, e_off, e_cnt = ged.edit_path(db, w.pairs, w.costs, maps)
+        eps = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            e_ops, e_off, e_cnt = ged.edit_path(db, w.pairs, w.costs, maps)
+            eps.append(time.perf_counter() - t1)
+        e_sum = np.add.reduceat(e_ops[:, 5].astype(np.int64), e_off[:-1]) if len(e_ops) else np.zeros(0)
+        epath = {"ms_per_call": round(float(np.median(eps)) * 1e3, 3), "operations": int(e_cnt.sum()),
+                 "costs_sum_to_distance": bool(np.array_equal(e_sum, gpu_dist.astype(np.int64)))}
+        log(f"edit paths: {epath}")
+
     complete = None
     if not args.no_complete and args.workload == "batch":
         complete, c_dist, c_maps = complete_measure(ged, db, w, args.steps, args.warmup, gpu_dist,
@@ -633,6 +653,15 @@ def main():
             c_sel = np.concatenate([c_maps[moff[p]:moff[p + 1]] for p in sample]) if len(sample) else c_maps[:0]
             complete["parity"] = {"pairs_checked": int(len(sample)),
                                   "bit_exact": bool(np.array_equal(c_dist[sample], kd) and np.array_equal(c_sel, km))}
+        if epath is not None:
+            # the oracle's expansion of the same mappings, first 256 pairs
+            ok_ep = True
+            for q in range(min(256, P)):
+                a_, b_ = int(w.pairs[q, 0]), int(w.pairs[q, 1])
+                ref = oracle_mod().edit_path(w.graphs.graph(a_), w.graphs.graph(b_), w.costs, gpu_maps[moff[q]:moff[q + 1]])
+                got = e_ops[e_off[q]:e_off[q] + e_cnt[q]]
+                ok_ep = ok_ep and e_cnt[q] == len(ref) and np.array_equal(got, np.asarray(ref, np.int32).reshape(-1, 6))
+            epath["parity"] = {"pairs_checked": min(256, P), "equal_to_oracle": bool(ok_ep)}
         if bip is not None:
             # the bipartite oracle on the same sample: parity, its own CPU
             # baseline, and the solver steps that price the kernel's work
@@ -686,6 +715,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "edit_path": epath,
         "complete_then_min": complete,
         "bipartite": bip,
         "large_k": large_k,

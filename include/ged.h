@@ -269,6 +269,53 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
                              void *stream);
 
 /* ------------------------------------------------------------------------
+ * Edit paths.  A vertex mapping (as the searches return it) induces one edit
+ * path (Sec. 2.2-2.4); ged_edit_path writes its operations explicitly.
+ *
+ * For each pair p the operations are, in this order:
+ *   1. per g1 vertex v ascending: GED_OP_VSUB (a = v, b = map(v)) or
+ *      GED_OP_VDEL (a = v, b = -1);
+ *   2. per g2 vertex u ascending outside the mapping's image: GED_OP_VINS
+ *      (a = -1, b = u);
+ *   3. per g1 edge {a, b}, a < b, in lexicographic order: GED_OP_ESUB (c, d =
+ *      the g2 edge {map(a), map(b)}, c < d) when both ends are mapped onto a
+ *      g2 edge, else GED_OP_EDEL (c = d = -1);
+ *   4. per g2 edge {c, d}, c < d, in lexicographic order that is no g1 edge's
+ *      image: GED_OP_EINS (a = b = -1).
+ * cost is the operation's cost (0 for a substitution that keeps the label);
+ * the costs of a pair sum to the edit cost of its mapping, i.e. to the
+ * distance the search returned with it.
+ *
+ * ged_edit_path_capacity: h_offsets[0..npairs] (host, int64) receives the
+ * exclusive prefix sum of n1 + n2 + m1 + m2 over the pairs, the most
+ * operations each can take; pair p's operations start at h_offsets[p].
+ * ged_edit_path: d_map is the mappings in the searches' layout (pair p at
+ * the sum of n(src) of the pairs before it); d_ops holds h_offsets[npairs]
+ * records; d_count[p] (int32, device) receives pair p's number of
+ * operations.  Enqueued on `stream`, then synchronized.  Errors: GED_EINVAL
+ * (ids out of range, NULL buffers, negative costs, or a mapping that is not
+ * injective or has an entry outside [-1, n2): its d_count is -1 and the
+ * message names the first such pair); GED_ENOMEM; GED_EDEVICE.
+ * ---------------------------------------------------------------------- */
+#define GED_OP_VSUB 0
+#define GED_OP_VDEL 1
+#define GED_OP_VINS 2
+#define GED_OP_ESUB 3
+#define GED_OP_EDEL 4
+#define GED_OP_EINS 5
+
+typedef struct {
+    int32_t kind;   /* GED_OP_* */
+    int32_t a, b;   /* vertex ops: g1 vertex, g2 vertex; edge ops: g1 edge ends */
+    int32_t c, d;   /* edge ops: g2 edge ends */
+    int32_t cost;
+} ged_edit_op;
+
+ged_status ged_edit_path_capacity(const ged_db *db, const ged_pair *h_pairs, int64_t npairs, int64_t *h_offsets);
+ged_status ged_edit_path(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs, const int32_t *d_map,
+                         ged_edit_op *d_ops, int32_t *d_count, void *stream);
+
+/* ------------------------------------------------------------------------
  * Single-pair search at large K (the paper's own regime, Sec. 5: K from
  * thousands to 1.2 million).  The whole device works on one pair: the beam
  * lives in device memory, and every level of Alg. 1 is a sequence of

@@ -114,6 +114,11 @@ hipError_t bip_max_resident(int PL, int cpl, int K, int *blocks_per_cu);
 hipError_t launch_bip(int PL, int cpl, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
                       int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
 
+// Edit-path output (kb_path.hip): one workgroup per pair; cap_off[out] is
+// the pair's first operation slot.
+hipError_t launch_path(const DbView &view, const WorkItem *work, const int64_t *cap_off, int nwork, Costs c,
+                       const int32_t *map, ged_edit_op *ops, int32_t *count, int grid, hipStream_t stream);
+
 // Whole-device search of one pair at large K (kb_wide.hip).
 constexpr int kWideMaxK = GED_MAX_K_WIDE;
 

@@ -79,6 +79,7 @@ EXPORTS = (
     "ged_server_create", "ged_server_submit", "ged_server_poll", "ged_server_wait",
     "ged_server_stats_get", "ged_server_destroy", "ged_server_submit_batch", "ged_server_collect",
     "ged_wide_create", "ged_wide_create_ex", "ged_wide_bytes", "ged_wide_run", "ged_wide_destroy",
+    "ged_edit_path_capacity", "ged_edit_path",
 )
 
 
@@ -130,6 +131,8 @@ def load(path: str = LIB_PATH):
         "ged_wide_bytes": ([P, P], i32),
         "ged_wide_run": ([P, Costs, P, P, P, P], i32),
         "ged_wide_destroy": ([P], i32),
+        "ged_edit_path_capacity": ([P, P, i64, P], i32),
+        "ged_edit_path": ([P, P, i64, Costs, P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -528,3 +531,30 @@ def pack_queries(graphs) -> Tuple[np.ndarray, list]:
     if el is not None:
         recs["elabel"] = np.uint64(el.ctypes.data) + eoff * np.uint64(4)
     return recs, [vl, eu, ev, el]
+
+
+# ------------------------------------------------------------------ edit paths
+
+OP_VSUB, OP_VDEL, OP_VINS, OP_ESUB, OP_EDEL, OP_EINS = range(6)
+OP_NAMES = ("vsub", "vdel", "vins", "esub", "edel", "eins")
+
+
+def edit_path(db: Database, pairs, costs, maps: torch.Tensor, stream=None):
+    """Explicit edit operations of each pair's mapping (ged_edit_path).
+
+    maps: the device mappings in the searches' layout (Plan.outputs / Result order).
+    Returns (ops int32 [total, 6] as (kind, a, b, c, d, cost), offsets int64 [P + 1],
+    counts int32 [P]); pair p's operations are ops[offsets[p] : offsets[p] + counts[p]].
+    """
+    lib = load()
+    pairs = _pairs_array(pairs)
+    P = len(pairs)
+    off = np.zeros(P + 1, dtype=np.int64)
+    _check(lib.ged_edit_path_capacity(db.handle, pairs.ctypes.data, P, off.ctypes.data))
+    if maps.dtype != torch.int32 or not maps.is_cuda or not maps.is_contiguous():
+        raise ValueError("maps must be a contiguous int32 CUDA tensor")
+    ops = torch.empty(max(int(off[-1]), 1) * 6, dtype=torch.int32, device=maps.device)
+    count = torch.empty(max(P, 1), dtype=torch.int32, device=maps.device)
+    _check(lib.ged_edit_path(db.handle, pairs.ctypes.data, P, _costs(costs), maps.data_ptr(), ops.data_ptr(),
+                             count.data_ptr(), _stream_handle(stream)))
+    return ops.view(-1, 6)[: int(off[-1])].cpu().numpy(), off, count[:P].cpu().numpy()
