@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define GED_ABI_VERSION 3
+#define GED_ABI_VERSION 4
 
 /* Limits of this version. */
 #define GED_MAX_VERTICES 512      /* per graph */
@@ -392,6 +392,11 @@ typedef struct {
                                  process take queues too). */
     int32_t queue_capacity;   /* queued (not yet admitted) queries before
                                  ged_server_submit returns GED_EBUSY; 0 = 1<<20 */
+    int32_t method;           /* GED_METHOD_TREE (0) or GED_METHOD_BIPARTITE: the
+                                 latter serves pairs with n1 + n2 <= GED_BIP_MAX_ORDER
+                                 at K <= GED_BIP_MAX_K, in four size classes by
+                                 ceil((n1 + n2) / 64) (submit: GED_EUNSUPPORTED
+                                 for a larger pair) */
 } ged_server_config;
 
 typedef struct {
@@ -401,7 +406,7 @@ typedef struct {
     int64_t device_bytes;     /* device memory held */
 } ged_server_stats;
 
-/* The server's searches use the default last level (GED_LAST_SELECT).
+/* The server's tree searches use the default last level (GED_LAST_SELECT).
  * Errors: GED_EINVAL (bad config, costs, K); GED_ENOMEM when the budget
  * cannot hold one batch of the configured size; GED_EDEVICE. */
 ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_server **out);

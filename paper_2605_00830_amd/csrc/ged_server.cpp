@@ -46,7 +46,9 @@ namespace {
 enum ReqState { QUEUED = 0, INFLIGHT = 1, DONE = 2, FAILED = 3, CANCELED = 4 };
 
 // size classes: small (n <= 32) and mid (n <= 64) for the two wavefront
-// kernels (K <= 64), medium (n <= 128) and large for the workgroup kernel
+// kernels (K <= 64), medium (n <= 128) and large for the workgroup kernel;
+// with the bipartite method, n1 + n2 <= 64, 128, 192, 256 (its kernel's
+// columns per lane)
 constexpr int kClasses = 4;
 constexpr int kFirstBlockClass = 2;
 
@@ -119,6 +121,8 @@ struct ged_server {
     int cus = 0;
     int wave_per_cu[kWaveBins] = {0, 0};   // n <= 32, n <= 64 kernels
     int block_per_cu[2][5] = {};   // [256 | 512 threads][W = 1, 2, 4, 8, 16]
+    bool bip = false;              // bipartite method
+    int bip_per_cu[kClasses] = {0, 0, 0, 0};   // its kernel, 1..4 columns per lane
     int64_t device_bytes = 0;
     std::vector<Slab> slabs;
 
@@ -150,6 +154,7 @@ int w_index(int W) {
 constexpr int kMediumMaxN = 128;
 
 int server_class(const ged_server *s, int n1, int n2) {
+    if (s->bip) return gedk::bip_cols_per_lane(n1 + n2) - 1;
     const int ww = gedk::wave_words_for(n1, n2, s->cfg.K);
     if (ww > 0) return ww - 1;
     if (n1 <= kMediumMaxN && n2 <= kMediumMaxN) return 2;
@@ -207,6 +212,43 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         aw += (int64_t)r.adj.size();
         vo += (int64_t)r.vlab.size();
         mo += r.n1;
+    }
+    // the bipartite method: one launch of the class's instantiation
+    if (s->bip) {
+        for (int k = 0; k < nq; ++k) {
+            WorkItem wi;
+            wi.src = k;
+            wi.dst = b.batch[(size_t)k]->target;
+            wi.out = k;
+            wi.pad = 0;
+            wi.map_off = b.map_off[(size_t)k];
+            b.h_work[k] = wi;
+        }
+        const int cpl = b.cls + 1;
+        const size_t per_wave = (size_t)K * gedk::bip_node_bytes(cpl, K);
+        const int fit = (int)std::min<size_t>(b.ws_bytes / per_wave, (size_t)std::numeric_limits<int>::max());
+        const int grid = std::min({nq, s->bip_per_cu[b.cls] * s->cus, fit});
+        if (grid <= 0) return hipErrorOutOfMemory;
+        hipError_t e = hipMemcpyAsync(b.d_recs, b.h_recs, sizeof(GraphRec) * (size_t)nq, hipMemcpyHostToDevice,
+                                      b.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.d_adj, b.h_adj, sizeof(uint32_t) * (size_t)std::max<int64_t>(aw, 1),
+                                                hipMemcpyHostToDevice, b.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.d_vlab, b.h_vlab, sizeof(int32_t) * (size_t)std::max<int64_t>(vo, 1),
+                                                hipMemcpyHostToDevice, b.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.d_work, b.h_work, sizeof(WorkItem) * (size_t)nq,
+                                                hipMemcpyHostToDevice, b.stream);
+        if (e == hipSuccess) e = gedk::launch_fill_zero(b.d_queue, kMaxBins, b.stream);
+        const gedk::DbView src{b.d_recs, b.d_adj, b.d_vlab, s->db->planes};
+        const gedk::DbView dst{s->db->d_graphs, s->db->d_adj, s->db->d_vlab, s->db->planes};
+        const gedk::Outputs out{b.d_dist, b.d_map, nullptr};
+        if (e == hipSuccess)
+            e = gedk::launch_bip(s->PL, cpl, src, dst, b.d_work, nq, b.d_queue, s->c, K, b.d_ws, out, grid, b.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq,
+                                                hipMemcpyDeviceToHost, b.stream);
+        if (e == hipSuccess && mo > 0)
+            e = hipMemcpyAsync(b.h_map, b.d_map, sizeof(int32_t) * (size_t)mo, hipMemcpyDeviceToHost, b.stream);
+        if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+        return e;
     }
     // work items by bin: 0, 1 = wavefront kernels (n <= 32, n <= 64),
     // kWaveBins + log2(W) = workgroup kernel
@@ -419,6 +461,10 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     if (cfg.streams == 0) cfg.streams = 1;
     if (cfg.queue_capacity == 0) cfg.queue_capacity = 1 << 20;
     if (cfg.streams > 4) return fail(GED_EINVAL, "streams (per size class) must be 1..4");
+    if (cfg.method != GED_METHOD_TREE && cfg.method != GED_METHOD_BIPARTITE)
+        return fail(GED_EINVAL, "unknown method %d", cfg.method);
+    if (cfg.method == GED_METHOD_BIPARTITE && cfg.K > GED_BIP_MAX_K)
+        return fail(GED_EUNSUPPORTED, "K = %d exceeds the bipartite method's %d", cfg.K, GED_BIP_MAX_K);
     st = gedh::check_device(db);
     if (st != GED_OK) return st;
 
@@ -429,19 +475,34 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     s->c = gedk::Costs{cfg.costs.vsub, cfg.costs.vdel, cfg.costs.vins, cfg.costs.esub, cfg.costs.edel, cfg.costs.eins};
     s->PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     s->device = db->device;
+    s->bip = cfg.method == GED_METHOD_BIPARTITE;
     hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    const bool wave_classes = cfg.K <= gedk::kWaveMaxK;
+    const bool wave_classes = !s->bip && cfg.K <= gedk::kWaveMaxK;
     for (int k = 0; k < kWaveBins && e == hipSuccess && wave_classes; ++k)
         e = gedk::wave_family_max_resident(k + 1, s->PL, 0, &s->wave_per_cu[k]);
-    const int first_class = wave_classes ? 0 : kFirstBlockClass;
+    const int first_class = (wave_classes || s->bip) ? 0 : kFirstBlockClass;
     const int nslabs = (kClasses - first_class) * cfg.streams;
     // every stream gets an equal share of the budget: its class's workspace
     // (at most half of the share; fewer resident workgroups when smaller),
     // then the arena
     const int64_t per_stream = cfg.hbm_budget / nslabs;
     size_t ws_class[kClasses] = {0, 0, 0, 0};
-    const int max_n[kClasses] = {gedk::kWaveMaxN, gedk::kWave2MaxN, kMediumMaxN, GED_MAX_VERTICES};
-    for (int cls = kFirstBlockClass; cls < kClasses && e == hipSuccess; ++cls) {
+    const int max_n[kClasses] = {s->bip ? 64 : gedk::kWaveMaxN, s->bip ? 128 : gedk::kWave2MaxN,
+                                 s->bip ? 192 : kMediumMaxN, s->bip ? 256 : GED_MAX_VERTICES};
+    // bipartite classes: one queue slice per resident wave, at most half the share
+    for (int cls = 0; cls < kClasses && e == hipSuccess && s->bip; ++cls) {
+        e = gedk::bip_max_resident(s->PL, cls + 1, cfg.K, &s->bip_per_cu[cls]);
+        const size_t per_wave = (size_t)cfg.K * gedk::bip_node_bytes(cls + 1, cfg.K);
+        const int64_t grid = std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->bip_per_cu[cls] * s->cus);
+        size_t ws = std::min<size_t>(per_wave * (size_t)grid, (size_t)std::max<int64_t>(per_stream / 2, 0));
+        if (e == hipSuccess && ws < per_wave) {
+            delete s;
+            return fail(GED_ENOMEM, "hbm_budget %lld is too small: a stream needs %zu bytes for one wave's queue",
+                        (long long)cfg.hbm_budget, per_wave);
+        }
+        ws_class[cls] = ws;
+    }
+    for (int cls = kFirstBlockClass; cls < kClasses && e == hipSuccess && !s->bip; ++cls) {
         size_t ws = 0, one_block = 0;
         for (int k = 0; k < 5 && e == hipSuccess; ++k) {
             const int W = 1 << k;
@@ -536,12 +597,19 @@ ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t ta
     st = gedh::pack_graph(*query, 0, srv->db->elabels, srv->db->planes, r->adj, r->vlab, r->rec);
     if (st != GED_OK) return st;
     const GraphRec &g2 = srv->db->h_graphs[(size_t)target_id];
+    if (srv->bip && query->n + g2.n > GED_BIP_MAX_ORDER)
+        return fail(GED_EUNSUPPORTED, "n1 + n2 = %d exceeds the bipartite method's %d", query->n + g2.n,
+                    GED_BIP_MAX_ORDER);
     r->cls = server_class(srv, query->n, g2.n);
     const ged_costs &c = srv->cfg.costs;
     const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
     const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
     if (vmax * ((int64_t)query->n + g2.n) + emax * ((int64_t)query->m + g2.m) > (int64_t)std::numeric_limits<int32_t>::max() - 1)
         return fail(GED_EINVAL, "costs may overflow int32 on this pair");
+    // the bipartite solver's bound (as for plans): (n1 + n2 + 1) entries below 2^24
+    const int64_t order = (int64_t)query->n + g2.n;
+    if (srv->bip && (order + 1) * (2 * vmax + 4 * emax * order) >= ((int64_t)1 << 24))
+        return fail(GED_EINVAL, "costs may overflow the bipartite solver on this pair");
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stop) return fail(GED_ECANCELED, "server is shutting down");

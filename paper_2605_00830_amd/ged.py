@@ -54,7 +54,7 @@ class GraphStruct(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("costs", Costs), ("hbm_budget", ctypes.c_int64),
                 ("max_inflight", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32)]
+                ("streams", ctypes.c_int32), ("queue_capacity", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -426,11 +426,11 @@ class Server:
     """The serving loop (ged_server_*): submit (query graph, target id), poll or wait."""
 
     def __init__(self, db: Database, K: int, costs, hbm_budget: int = 0, max_inflight: int = 0,
-                 max_batch: int = 0, streams: int = 0, queue_capacity: int = 0):
+                 max_batch: int = 0, streams: int = 0, queue_capacity: int = 0, method: int = METHOD_TREE):
         lib = load()
         self.db = db
         cfg = ServerConfig(int(K), _costs(costs), int(hbm_budget), int(max_inflight), int(max_batch),
-                           int(streams), int(queue_capacity))
+                           int(streams), int(queue_capacity), int(method))
         handle = ctypes.c_void_p()
         _check(lib.ged_server_create(db.handle, ctypes.byref(cfg), ctypes.byref(handle)))
         self._h = handle

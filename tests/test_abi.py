@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_status_names():
     lib = ged.load()
-    assert lib.ged_abi_version() == 3
+    assert lib.ged_abi_version() == 4
     assert ged.status_name(ged.GED_OK) == "GED_OK"
     assert ged.status_name(ged.GED_EUNSUPPORTED) == "GED_EUNSUPPORTED"
     assert ged.status_name(99) == "GED_UNKNOWN"
