@@ -139,3 +139,39 @@ def test_forced_workgroup_sizes_agree(ged, tmp_path, K):
             np.testing.assert_array_equal(m2[:p2.map_size].cpu().numpy(), m_ref)
             p2.close()
     db.close()
+
+
+def test_bipartite_graph_replay_matches_eager(ged):
+    """A bipartite plan with two bins (one and two columns per lane) captured once
+    and replayed four times, with another plan's eager run between replays."""
+    import torch
+    gs = [synth.er_graph(33, k, 10, 30, 0.1, 0.3, 5) for k in range(40)]
+    gs += [synth.er_graph(34, k, 40, 60, 0.05, 0.1, 5) for k in range(20)]
+    graphs = GraphSet.from_graphs(gs)
+    rng = np.random.default_rng(9)
+    pairs = np.stack([rng.integers(0, len(gs), 120), rng.integers(0, len(gs), 120)], 1).astype(np.int64)
+    costs, K = synth.PAPER_COSTS, 40
+    d_ref, m_ref, _, s_ref = oracle.bipartite_pairs(graphs, pairs, costs, K)
+    db = ged.Database(graphs)
+    plan = ged.Plan(db, pairs, K, method=ged.METHOD_BIPARTITE)
+    assert len(plan.bins()) == 2
+    other = ged.Plan(db, pairs[::-1].copy(), 9, method=ged.METHOD_BIPARTITE)
+    od, om, _ = other.outputs()
+    s = torch.cuda.Stream()
+    dist, maps, cand = plan.outputs(with_cand=True)
+    plan.capture(costs, dist, maps, cand, stream=s)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            dist.fill_(-7)
+            maps.fill_(-7)
+            cand.fill_(-7)
+        plan.replay(stream=s)
+        s.synchronize()
+        np.testing.assert_array_equal(dist[:len(pairs)].cpu().numpy(), d_ref)
+        np.testing.assert_array_equal(maps[:plan.map_size].cpu().numpy(), m_ref)
+        np.testing.assert_array_equal(cand[:len(pairs)].cpu().numpy(), s_ref)
+        other.run(costs, od, om)
+        torch.cuda.synchronize()
+    plan.close()
+    other.close()
+    db.close()
