@@ -97,11 +97,12 @@ hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu);
 hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                         Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 
-// Bipartite K-best-assignment bound, one wavefront per pair (kb_bip.hip):
-// n1 + n2 <= 256, K <= 256.  A launch's columns per lane (cpl = ceil((n1 +
-// n2) / 64), 1..4) and queue slots per lane (ceil(K / 64): 1, 2 or 4) pick
-// the instantiation; `ws` holds grid x K x bip_node_bytes(cpl, K) (queue
-// nodes: potentials, assignment, fixed rows, forbidden pairs).
+// Bipartite K-best-assignment bound, a workgroup of nwav (1 or 4) waves per
+// pair (kb_bip.hip): n1 + n2 <= 256, K <= 256.  A launch's columns per lane
+// (cpl = ceil((n1 + n2) / 64), 1..4), queue slots per lane (ceil(K / 64): 1,
+// 2 or 4) and nwav pick the instantiation; `ws` holds grid x
+// bip_workgroup_bytes(cpl, K) (a pool of K + 64 cpl queue nodes: potentials,
+// assignment, fixed rows, forbidden pairs).
 constexpr int kBipMaxM = 256;
 constexpr int kBipMaxK = 256;
 inline int bip_cols_per_lane(int m) { return m <= 64 ? 1 : (m + 63) / 64; }
@@ -110,9 +111,10 @@ inline size_t bip_node_bytes(int cpl, int K) {
     const size_t raw = 10 * 64 * (size_t)cpl + 8 * (size_t)cpl + 16 + 4 * (size_t)K;
     return (raw + 255) / 256 * 256;
 }
-hipError_t bip_max_resident(int PL, int cpl, int K, int *blocks_per_cu);
-hipError_t launch_bip(int PL, int cpl, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
-                      int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
+inline size_t bip_workgroup_bytes(int cpl, int K) { return ((size_t)K + 64 * (size_t)cpl) * bip_node_bytes(cpl, K); }
+hipError_t bip_max_resident(int PL, int cpl, int K, int nwav, int *blocks_per_cu);
+hipError_t launch_bip(int PL, int cpl, int nwav, const DbView &src, const DbView &dst, const WorkItem *work,
+                      int nwork, int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
 
 // Edit-path output (kb_path.hip): one workgroup per pair; cap_off[out] is
 // the pair's first operation slot.

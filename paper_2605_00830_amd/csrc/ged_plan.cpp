@@ -31,8 +31,10 @@ int pow2_at_least(int x) {
 
 // One size bin: pairs sharing a kernel instantiation.
 struct Bin {
-    bool bip = false;            // bipartite method (its own wavefront kernel, queue workspace)
+    bool bip = false;            // bipartite method (its own kernel, queue-node workspace)
     int bip_cpl = 0;             // its columns per lane
+    int bip_nwav = 1;            // its waves per pair (1 or 4)
+    int bip_max_per_cu[2] = {0, 0};   // occupancy: 1 and 4 waves per workgroup
     bool wave_ok = false;        // every pair fits the wavefront kernel
     int wave_words = 0;          // its family: 1 (n <= 32), 2 (n <= 64)
     bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
@@ -126,6 +128,10 @@ ged_status check_overflow(const ged_plan *p, const ged_costs &c) {
 // bin cannot put two 256-thread workgroups on every CU, so each pair gets
 // two waves per SIMD; otherwise 256.
 int default_threads(const ged_plan *p, const Bin &b) {
+    // the bipartite kernel: four waves per pair when every pair of the bin is
+    // resident at once with one (the launch then lasts as long as its
+    // slowest pair, which four waves shorten), else one
+    if (b.bip) return (int64_t)b.h_sorted.size() <= (int64_t)b.bip_max_per_cu[0] * p->cus ? 256 : 64;
     return (int64_t)b.h_sorted.size() < 2 * (int64_t)p->cus ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
 }
 
@@ -135,10 +141,14 @@ int default_threads(const ged_plan *p, const Bin &b) {
 // that grid (blocking copy: no run of the plan may be in flight).
 ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu, int threads) {
     if (b.bip) {
-        const int gpc = groups_per_cu > 0 ? std::min(groups_per_cu, b.max_wave_per_cu) : b.max_wave_per_cu;
+        // threads: 64 = one wave per pair, 256 = four
+        const int nwav = threads >= 256 ? 4 : 1;
+        const int limit = b.bip_max_per_cu[nwav == 4 ? 1 : 0];
+        const int gpc = groups_per_cu > 0 ? std::min(groups_per_cu, limit) : limit;
         const int64_t nwork = (int64_t)b.h_work.size();
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(nwork, (int64_t)gpc * p->cus));
-        b.ws_stride = (size_t)p->K * gedk::bip_node_bytes(b.bip_cpl, p->K);
+        b.bip_nwav = nwav;
+        b.ws_stride = gedk::bip_workgroup_bytes(b.bip_cpl, p->K);
         const size_t need = b.ws_stride * (size_t)grid;
         if (b.ws_bytes < need) {
             if (b.d_ws) GED_HIP(hipFree(b.d_ws));
@@ -149,7 +159,7 @@ ged_status configure_bin(ged_plan *p, Bin &b, bool wave, int groups_per_cu, int 
             b.ws_bytes = need;
         }
         b.h_work = b.h_sorted;
-        gedh::deal_alternating(b.h_work, grid, 4 * (int64_t)p->cus);
+        gedh::deal_alternating(b.h_work, grid, (nwav == 1 ? 4 : 1) * (int64_t)p->cus);
         GED_HIP(hipMemcpy(b.d_work, b.h_work.data(), sizeof(WorkItem) * (size_t)nwork, hipMemcpyHostToDevice));
         b.wave = false;
         b.groups_per_cu = gpc;
@@ -198,12 +208,12 @@ ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool per
     if (nwork == 0) return ok();
     if (b.bip) {
         if (!perpair) {
-            GED_HIP(gedk::launch_bip(b.shape.PL, b.bip_cpl, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K,
-                                     b.d_ws, r.o, b.grid, r.s));
+            GED_HIP(gedk::launch_bip(b.shape.PL, b.bip_cpl, b.bip_nwav, r.view, r.view, b.d_work, nwork, b.d_queue,
+                                     r.c, p->K, b.d_ws, r.o, b.grid, r.s));
         } else {
             for (int i = 0; i < nwork; ++i)
-                GED_HIP(gedk::launch_bip(b.shape.PL, b.bip_cpl, r.view, r.view, b.d_work + i, 1, b.d_queue + 1 + i,
-                                         r.c, p->K, b.d_ws, r.o, 1, r.s));
+                GED_HIP(gedk::launch_bip(b.shape.PL, b.bip_cpl, b.bip_nwav, r.view, r.view, b.d_work + i, 1,
+                                         b.d_queue + 1 + i, r.c, p->K, b.d_ws, r.o, 1, r.s));
         }
     } else if (b.wave) {
         if (!perpair) {
@@ -304,7 +314,7 @@ std::map<std::string, Choice> read_cache(const char *path) {
     while (fgets(line, sizeof line, f)) {
         int w = 0, g = 0, t = 0;
         if (sscanf(line, "%511s %d %d %d", key, &w, &g, &t) == 4 &&
-            (t == gedk::kBlockThreads || t == gedk::kBlockThreadsWide))
+            (t == gedk::kBlockThreads || t == gedk::kBlockThreadsWide || t == 64))
             m[key] = Choice{w != 0, g, t};
     }
     fclose(f);
@@ -431,7 +441,9 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
                          [&](const WorkItem &x, const WorkItem &y) { return work_of(x) > work_of(y); });
         b.h_sorted = b.h_work;
         if (b.bip) {
-            e = gedk::bip_max_resident(b.shape.PL, b.bip_cpl, K, &b.max_wave_per_cu);
+            e = gedk::bip_max_resident(b.shape.PL, b.bip_cpl, K, 1, &b.bip_max_per_cu[0]);
+            if (e == hipSuccess) e = gedk::bip_max_resident(b.shape.PL, b.bip_cpl, K, 4, &b.bip_max_per_cu[1]);
+            b.max_wave_per_cu = std::min(b.bip_max_per_cu[0], b.bip_max_per_cu[1]);
             b.max_block_per_cu[0] = b.max_block_per_cu[1] = 1;   // not used
         }
         for (int k = 0; k < 2 && e == hipSuccess && !b.bip; ++k) {
@@ -592,10 +604,10 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
         const int64_t nwork = (int64_t)b.h_sorted.size();
         for (int fam = 0; fam < 3; ++fam) {
             const bool wave = fam == 0;
+            if (b.bip && fam == 2) continue;   // the bipartite kernel: one or four waves per pair
             if (wave && !b.wave_ok && !b.bip) continue;
-            if (!wave && b.bip) continue;   // the bipartite bin has one kernel: only its grid is tuned
-            const int threads = fam == 2 ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
-            const int lim = wave ? b.max_wave_per_cu : b.max_block_per_cu[bt_index(threads)];
+            const int threads = b.bip ? (fam == 0 ? 64 : 256) : (fam == 2 ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
+            const int lim = b.bip ? b.bip_max_per_cu[fam] : (wave ? b.max_wave_per_cu : b.max_block_per_cu[bt_index(threads)]);
             int64_t last_grid = -1;
             for (int g = lim; g >= 1; g = g / 2) {
                 const int64_t grid = std::min<int64_t>(nwork, (int64_t)g * plan->cus);

@@ -225,7 +225,7 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
             b.h_work[k] = wi;
         }
         const int cpl = b.cls + 1;
-        const size_t per_wave = (size_t)K * gedk::bip_node_bytes(cpl, K);
+        const size_t per_wave = gedk::bip_workgroup_bytes(cpl, K);
         const int fit = (int)std::min<size_t>(b.ws_bytes / per_wave, (size_t)std::numeric_limits<int>::max());
         const int grid = std::min({nq, s->bip_per_cu[b.cls] * s->cus, fit});
         if (grid <= 0) return hipErrorOutOfMemory;
@@ -242,7 +242,8 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         const gedk::DbView dst{s->db->d_graphs, s->db->d_adj, s->db->d_vlab, s->db->planes};
         const gedk::Outputs out{b.d_dist, b.d_map, nullptr};
         if (e == hipSuccess)
-            e = gedk::launch_bip(s->PL, cpl, src, dst, b.d_work, nq, b.d_queue, s->c, K, b.d_ws, out, grid, b.stream);
+            e = gedk::launch_bip(s->PL, cpl, 1, src, dst, b.d_work, nq, b.d_queue, s->c, K, b.d_ws, out, grid,
+                                 b.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq,
                                                 hipMemcpyDeviceToHost, b.stream);
         if (e == hipSuccess && mo > 0)
@@ -491,8 +492,8 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
                                  s->bip ? 192 : kMediumMaxN, s->bip ? 256 : GED_MAX_VERTICES};
     // bipartite classes: one queue slice per resident wave, at most half the share
     for (int cls = 0; cls < kClasses && e == hipSuccess && s->bip; ++cls) {
-        e = gedk::bip_max_resident(s->PL, cls + 1, cfg.K, &s->bip_per_cu[cls]);
-        const size_t per_wave = (size_t)cfg.K * gedk::bip_node_bytes(cls + 1, cfg.K);
+        e = gedk::bip_max_resident(s->PL, cls + 1, cfg.K, 1, &s->bip_per_cu[cls]);
+        const size_t per_wave = gedk::bip_workgroup_bytes(cls + 1, cfg.K);
         const int64_t grid = std::min<int64_t>((int64_t)cfg.max_batch, (int64_t)s->bip_per_cu[cls] * s->cus);
         size_t ws = std::min<size_t>(per_wave * (size_t)grid, (size_t)std::max<int64_t>(per_stream / 2, 0));
         if (e == hipSuccess && ws < per_wave) {

@@ -92,19 +92,23 @@ __device__ __forceinline__ bool adj_bit(const uint32_t *A, int w, int x, int y) 
     return (A[(size_t)x * w + (y >> 5)] >> (y & 31)) & 1u;
 }
 
-template <int PL, int CPL, int QPL>
-__global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
+template <int PL, int CPL, int QPL, int NWAV>
+__global__ __launch_bounds__(64 * NWAV) void kb_bip_kernel(BipArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     constexpr int NL = PL > 0 ? (1 << PL) : 1;   // edge-label codes
     constexpr int NW = (NL + 3) / 4;             // words of byte counts
     constexpr int MAXM = 64 * CPL;
+    constexpr int PWMAX = QPL + CPL;             // words of the node pool's free flags
     __shared__ int s_col[MAXM];                  // column of each row of the popped assignment
     __shared__ int s_phi[MAXM];                  // its mapping of g1's vertices
     __shared__ unsigned long long s_forb[MAXM][CPL];   // forbidden (row, column) bits
     __shared__ unsigned long long s_rowf[CPL];   // rows with any forbidden column
+    __shared__ int s_res[MAXM];                  // per child: assignment cost, or ~0 (none)
+    __shared__ int s_alloc[MAXM];                // per child: pool slot of its node
     __shared__ int s_item;
 
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const int32_t vsub = a.c.vsub, vdel = a.c.vdel, vins = a.c.vins;
     const int32_t esub = a.c.esub, edel = a.c.edel, eins = a.c.eins;
     const int32_t cross = min(esub, edel + eins);
@@ -114,12 +118,12 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
     // node layout (offsets inside a slot of NB bytes)
     const size_t oV = 4 * (size_t)MAXM, oP = 8 * (size_t)MAXM, oFix = 10 * (size_t)MAXM;
     const size_t oNf = oFix + 8 * CPL, oForb = oNf + 16;
-    unsigned char *ws = a.ws + (size_t)blockIdx.x * (size_t)K * NB;
+    unsigned char *ws = a.ws + (size_t)blockIdx.x * (size_t)(K + MAXM) * NB;
 
     for (bool first = true;; first = false) {
         int item = (int)blockIdx.x;
         if (!first) {
-            if (lane == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
+            if (threadIdx.x == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(s_item);
             __syncthreads();
@@ -311,27 +315,20 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
             return wave_sum(s);
         };
 
-        // ---------------- first assignment: every row from zero potentials
-        int32_t u[CPL], v[CPL];
-        int p[CPL];
-        bool open0[CPL];
+        // ---------------- first assignment (wave 0): every row from zero potentials
+        if (wv == 0) {
+            int32_t u[CPL], v[CPL];
+            int p[CPL];
+            bool open0[CPL];
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            u[k] = v[k] = 0;
-            p[k] = -1;
-            open0[k] = lane + 64 * k < M;
-        }
-        for (int r = 0; r < M; ++r) (void)augment(r, u, v, p, open0, -1, -1);   // a deletion column is always open
-        uint32_t qcost[QPL], qseq[QPL];
-        bool qocc[QPL];
-#pragma unroll
-        for (int s = 0; s < QPL; ++s) {
-            qcost[s] = qseq[s] = 0u;
-            qocc[s] = false;
-        }
-        {
+            for (int k = 0; k < CPL; ++k) {
+                u[k] = v[k] = 0;
+                p[k] = -1;
+                open0[k] = lane + 64 * k < M;
+            }
+            for (int r = 0; r < M; ++r) (void)augment(r, u, v, p, open0, -1, -1);   // a deletion column is always open
             const uint32_t c0 = assignment_cost(u, v);
-            unsigned char *nb = ws;
+            unsigned char *nb = ws;   // pool slot 0
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
                 reinterpret_cast<int32_t *>(nb)[lane + 64 * k] = u[k];
@@ -339,10 +336,31 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                 reinterpret_cast<int16_t *>(nb + oP)[lane + 64 * k] = (int16_t)p[k];
             }
             if (lane < CPL) reinterpret_cast<unsigned long long *>(nb + oFix)[lane] = 0ull;
-            if (lane == 0) *reinterpret_cast<int32_t *>(nb + oNf) = 0;
-            qocc[0] = lane == 0;
-            qcost[0] = lane == 0 ? c0 : 0u;
+            if (lane == 0) {
+                *reinterpret_cast<int32_t *>(nb + oNf) = 0;
+                s_res[0] = c0;
+            }
         }
+        __syncthreads();
+        // the queue, identical in every wave: slot q = lane + 64 s holds
+        // (assignment cost, creation number, pool slot of its node)
+        uint32_t qcost[QPL], qseq[QPL];
+        int qidx[QPL];
+        bool qocc[QPL];
+#pragma unroll
+        for (int s = 0; s < QPL; ++s) {
+            qcost[s] = qseq[s] = 0u;
+            qidx[s] = 0;
+            qocc[s] = false;
+        }
+        qocc[0] = lane == 0;
+        qcost[0] = lane == 0 ? (uint32_t)s_res[0] : 0u;
+        // node pool: K + MAXM slots (a full queue plus one pop's children);
+        // slot x free <=> pfree[x >> 6] at lane x & 63
+        const int PN = K + MAXM;
+        bool pfree[PWMAX];
+#pragma unroll
+        for (int w = 0; w < PWMAX; ++w) pfree[w] = lane + 64 * w < PN && lane + 64 * w != 0;
         uint32_t seq = 1u;
         int popped = 0;
         int64_t solves = 1;
@@ -350,6 +368,10 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
         int bestphi[CPL];
 #pragma unroll
         for (int k = 0; k < CPL; ++k) bestphi[k] = -1;
+        auto set_free = [&](int x, bool f) __attribute__((always_inline)) {
+#pragma unroll
+            for (int w = 0; w < PWMAX; ++w) pfree[w] = (lane + 64 * w == x) ? f : pfree[w];
+        };
 
         while (popped < K) {
             bool any = false;
@@ -371,9 +393,10 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                 const unsigned long long bl = __ballot(qocc[s] && qcost[s] == mc && qseq[s] == ms);
                 q = bl ? 64 * s + (int)__builtin_ctzll(bl) : q;
             }
+            const int pi = __builtin_amdgcn_readlane(pick(qidx, q >> 6), q & 63);
 #pragma unroll
             for (int s = 0; s < QPL; ++s) qocc[s] = qocc[s] && lane + 64 * s != q;
-            const unsigned char *nq = ws + (size_t)q * NB;
+            const unsigned char *nq = ws + (size_t)pi * NB;
             int32_t u_par[CPL], v_par[CPL];
             int p_par[CPL];
 #pragma unroll
@@ -390,85 +413,114 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
 #pragma unroll
             for (int s = 0; s < QPL; ++s)
                 fent[s] = lane + 64 * s < nf ? reinterpret_cast<const uint32_t *>(nq + oForb)[lane + 64 * s] : 0u;
-            // forbidden bitmap of this node
-            for (int x = lane; x < MAXM * CPL; x += 64) (&s_forb[0][0])[x] = 0ull;
-            if (lane < CPL) s_rowf[lane] = 0ull;
+            set_free(pi, true);   // its children may reuse the slot once every wave has read it
+            // forbidden bitmap, row -> column map and mapping of this node (every
+            // wave stores the same values)
+            for (int x = (int)threadIdx.x; x < MAXM * CPL; x += 64 * NWAV) (&s_forb[0][0])[x] = 0ull;
+            if ((int)threadIdx.x < CPL) s_rowf[threadIdx.x] = 0ull;
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < QPL; ++s) {
-                if (lane + 64 * s < nf) {
+                if (wv == 0 && lane + 64 * s < nf) {
                     const int fr = (int)(fent[s] & 0xffffu), fcol = (int)(fent[s] >> 16);
                     atomicOr(&s_forb[fr][fcol >> 6], 1ull << (fcol & 63));
                     atomicOr(&s_rowf[fr >> 6], 1ull << (fr & 63));
                 }
             }
-            __syncthreads();
+            if (wv == 0) {
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) rowf[k] = s_rowf[k];
-            // row -> column of the popped assignment, and its mapping
-#pragma unroll
-            for (int k = 0; k < CPL; ++k)
-                if (p_par[k] >= 0) s_col[p_par[k]] = lane + 64 * k;
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                const int x = lane + 64 * k;
-                if (x < n1) {
-                    const int cx = s_col[x];
-                    s_phi[x] = cx < n2 ? cx : -1;
-                }
+                for (int k = 0; k < CPL; ++k)
+                    if (p_par[k] >= 0) s_col[p_par[k]] = lane + 64 * k;
             }
-            __syncthreads();
-
-            // ---------------- its induced edit cost
-            uint32_t vc = 0u, matched = 0u, nsub = 0u;
+            // the free rows (children, in ascending row order) and the pool
+            // slot each child's node goes to: the lowest free slots, in order
+            int m = 0;
+            for (int w = 0; w < CPL; ++w) {
+                const int base = 64 * w;
+                unsigned long long fr = ~pick(fixm, w);
+                fr &= n1 - base >= 64 ? ~0ull : (n1 > base ? ((1ull << (n1 - base)) - 1ull) : 0ull);
+                m += __popcll(fr);
+            }
+            if (wv == 0) {
+                int t = 0;
 #pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                const int x = lane + 64 * k;
-                if (x >= n1) continue;
-                const int fx = s_phi[x];
-                if (fx < 0) {
-                    vc += (uint32_t)vdel;
-                } else {
-                    ++nsub;
-                    vc += a.dst.vlab[g2.vlab + fx] != l1[k] ? (uint32_t)vsub : 0u;
-                }
-                // earlier neighbours b < x: kept (both mapped onto a g2 edge,
-                // relabelled when a label plane differs) or deleted
-                for (int wd = 0; wd <= (x >> 5); ++wd) {
-                    uint32_t row = A1[(size_t)x * w1 + wd];
-                    if (wd == (x >> 5)) row &= (1u << (x & 31)) - 1u;
-                    while (row) {
-                        const int b = 32 * wd + __builtin_ctz(row);
-                        row &= row - 1u;
-                        const int fb = s_phi[b];
-                        if (fx >= 0 && fb >= 0 && adj_bit(A2, w2, fx, fb)) {
-                            ++matched;
-                            if (PL > 0) {
-                                bool diff = false;
-                                for (int pl = 0; pl < P; ++pl)
-                                    diff = diff || (adj_bit(A1 + (size_t)(1 + pl) * n1 * w1, w1, x, b) !=
-                                                    adj_bit(A2 + (size_t)(1 + pl) * n2 * w2, w2, fx, fb));
-                                vc += diff ? (uint32_t)esub : 0u;
-                            }
-                        } else {
-                            vc += (uint32_t)edel;
-                        }
+                for (int w = 0; w < PWMAX; ++w) {
+                    unsigned long long bl = __ballot(pfree[w]);
+                    while (bl && t < m) {
+                        if (lane == 0) s_alloc[t] = 64 * w + (int)__builtin_ctzll(bl);
+                        bl &= bl - 1ull;
+                        ++t;
                     }
                 }
             }
-            const uint32_t nsub_all = wave_sum(nsub);
-            const uint32_t d = wave_sum(vc) + (uint32_t)vins * ((uint32_t)n2 - nsub_all) +
-                               (uint32_t)eins * ((uint32_t)g2.m - wave_sum(matched));
-            ++popped;
-            if (d < best) {
-                best = d;
+            __syncthreads();
 #pragma unroll
-                for (int k = 0; k < CPL; ++k) bestphi[k] = lane + 64 * k < n1 ? s_phi[lane + 64 * k] : -1;
+            for (int k = 0; k < CPL; ++k) rowf[k] = s_rowf[k];
+            if (wv == 0) {
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const int x = lane + 64 * k;
+                    if (x < n1) {
+                        const int cx = s_col[x];
+                        s_phi[x] = cx < n2 ? cx : -1;
+                    }
+                }
             }
+            for (int t = 0; t < m; ++t) set_free(s_alloc[t], false);
+            __syncthreads();
+
+            // ---------------- its induced edit cost (wave 0)
+            if (wv == 0) {
+                uint32_t vc = 0u, matched = 0u, nsub = 0u;
+#pragma unroll
+                for (int k = 0; k < CPL; ++k) {
+                    const int x = lane + 64 * k;
+                    if (x >= n1) continue;
+                    const int fx = s_phi[x];
+                    if (fx < 0) {
+                        vc += (uint32_t)vdel;
+                    } else {
+                        ++nsub;
+                        vc += a.dst.vlab[g2.vlab + fx] != l1[k] ? (uint32_t)vsub : 0u;
+                    }
+                    // earlier neighbours b < x: kept (both mapped onto a g2
+                    // edge, relabelled when a label plane differs) or deleted
+                    for (int wd = 0; wd <= (x >> 5); ++wd) {
+                        uint32_t row = A1[(size_t)x * w1 + wd];
+                        if (wd == (x >> 5)) row &= (1u << (x & 31)) - 1u;
+                        while (row) {
+                            const int b = 32 * wd + __builtin_ctz(row);
+                            row &= row - 1u;
+                            const int fb = s_phi[b];
+                            if (fx >= 0 && fb >= 0 && adj_bit(A2, w2, fx, fb)) {
+                                ++matched;
+                                if (PL > 0) {
+                                    bool diff = false;
+                                    for (int pl = 0; pl < P; ++pl)
+                                        diff = diff || (adj_bit(A1 + (size_t)(1 + pl) * n1 * w1, w1, x, b) !=
+                                                        adj_bit(A2 + (size_t)(1 + pl) * n2 * w2, w2, fx, fb));
+                                    vc += diff ? (uint32_t)esub : 0u;
+                                }
+                            } else {
+                                vc += (uint32_t)edel;
+                            }
+                        }
+                    }
+                }
+                const uint32_t nsub_all = wave_sum(nsub);
+                const uint32_t d = wave_sum(vc) + (uint32_t)vins * ((uint32_t)n2 - nsub_all) +
+                                   (uint32_t)eins * ((uint32_t)g2.m - wave_sum(matched));
+                if (d < best) {
+                    best = d;
+#pragma unroll
+                    for (int k = 0; k < CPL; ++k) bestphi[k] = lane + 64 * k < n1 ? s_phi[lane + 64 * k] : -1;
+                }
+            }
+            ++popped;
             if (popped == K) break;
 
-            // ---------------- partition: one child per free row, ascending
+            // ---------------- partition: one child per free row, ascending;
+            // child t is solved by wave t mod NWAV
             unsigned long long cfix[CPL];
             bool blocked[CPL];
 #pragma unroll
@@ -477,6 +529,7 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                 const int pk = p_par[k];
                 blocked[k] = pk >= 0 && pk < n1 && ((pick(fixm, pk >> 6) >> (pk & 63)) & 1ull);
             }
+            int t = 0;
             for (int wsl = 0; wsl < CPL; ++wsl) {
                 const int base = 64 * wsl;
                 unsigned long long freem = ~pick(fixm, wsl);
@@ -485,53 +538,21 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                     const int r = base + (int)__builtin_ctzll(freem);
                     freem &= freem - 1ull;
                     const int c = s_col[r];   // uniform
-                    int32_t cu[CPL], cv[CPL];
-                    int cp[CPL];
-                    bool open[CPL];
+                    if (t % NWAV == wv) {
+                        int32_t cu[CPL], cv[CPL];
+                        int cp[CPL];
+                        bool open[CPL];
 #pragma unroll
-                    for (int k = 0; k < CPL; ++k) {
-                        cu[k] = u_par[k];
-                        cv[k] = v_par[k];
-                        cp[k] = lane + 64 * k == c ? -1 : p_par[k];
-                        open[k] = lane + 64 * k < M && !blocked[k];
-                    }
-                    ++solves;
-                    if (augment(r, cu, cv, cp, open, r, c)) {
-                        const uint32_t cost = assignment_cost(cu, cv);
-                        const uint32_t cseq = seq++;
-                        const int cap = K - popped;
-                        int occn = 0;
-#pragma unroll
-                        for (int s = 0; s < QPL; ++s) occn += __popcll(__ballot(qocc[s]));
-                        int slot = -1;
-                        if (occn < cap) {
-#pragma unroll
-                            for (int s = QPL - 1; s >= 0; --s) {
-                                const unsigned long long bl = __ballot(!qocc[s] && lane + 64 * s < K);
-                                slot = bl ? 64 * s + (int)__builtin_ctzll(bl) : slot;
-                            }
-                        } else {
-                            // the child's creation number exceeds every queued
-                            // one, so it displaces the largest key only when
-                            // cheaper
-                            uint32_t xl = 0u;
-#pragma unroll
-                            for (int s = 0; s < QPL; ++s) xl = max(xl, qocc[s] ? qcost[s] : 0u);
-                            const uint32_t xc = wave_umax(xl);
-                            uint32_t sl = 0u;
-#pragma unroll
-                            for (int s = 0; s < QPL; ++s) sl = max(sl, (qocc[s] && qcost[s] == xc) ? qseq[s] : 0u);
-                            const uint32_t xs = wave_umax(sl);
-                            if (cost < xc) {
-#pragma unroll
-                                for (int s = QPL - 1; s >= 0; --s) {
-                                    const unsigned long long bl = __ballot(qocc[s] && qcost[s] == xc && qseq[s] == xs);
-                                    slot = bl ? 64 * s + (int)__builtin_ctzll(bl) : slot;
-                                }
-                            }
+                        for (int k = 0; k < CPL; ++k) {
+                            cu[k] = u_par[k];
+                            cv[k] = v_par[k];
+                            cp[k] = lane + 64 * k == c ? -1 : p_par[k];
+                            open[k] = lane + 64 * k < M && !blocked[k];
                         }
-                        if (slot >= 0) {
-                            unsigned char *nb = ws + (size_t)slot * NB;
+                        uint32_t cost = 0xffffffffu;
+                        if (augment(r, cu, cv, cp, open, r, c)) {
+                            cost = assignment_cost(cu, cv);
+                            unsigned char *nb = ws + (size_t)s_alloc[t] * NB;
 #pragma unroll
                             for (int k = 0; k < CPL; ++k) {
                                 reinterpret_cast<int32_t *>(nb)[lane + 64 * k] = cu[k];
@@ -547,14 +568,8 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                                     reinterpret_cast<uint32_t *>(nb + oForb)[x] =
                                         x < nf ? fent[s] : ((uint32_t)r | ((uint32_t)c << 16));
                             }
-#pragma unroll
-                            for (int s = 0; s < QPL; ++s) {
-                                const bool mine = lane + 64 * s == slot;
-                                qocc[s] = qocc[s] || mine;
-                                qcost[s] = mine ? cost : qcost[s];
-                                qseq[s] = mine ? cseq : qseq[s];
-                            }
                         }
+                        if (lane == 0) s_res[t] = (int)cost;
                     }
                     // r is fixed for the later children
 #pragma unroll
@@ -562,56 +577,124 @@ __global__ __launch_bounds__(64) void kb_bip_kernel(BipArgs a) {
                         cfix[k] |= (r >> 6) == k ? (1ull << (r & 63)) : 0ull;
                         blocked[k] = blocked[k] || lane + 64 * k == c;
                     }
+                    ++t;
                 }
             }
+            solves += m;
+            __syncthreads();
+
+            // ---------------- push the children in order (every wave alike)
+            for (int tt = 0; tt < m; ++tt) {
+                const uint32_t cost = (uint32_t)s_res[tt];
+                const int x = s_alloc[tt];
+                if (cost == 0xffffffffu) {   // no assignment: its slot returns to the pool
+                    set_free(x, true);
+                    continue;
+                }
+                const uint32_t cseq = seq++;
+                const int cap = K - popped;
+                int occn = 0;
+#pragma unroll
+                for (int s = 0; s < QPL; ++s) occn += __popcll(__ballot(qocc[s]));
+                int slot = -1;
+                if (occn < cap) {
+#pragma unroll
+                    for (int s = QPL - 1; s >= 0; --s) {
+                        const unsigned long long bl = __ballot(!qocc[s] && lane + 64 * s < K);
+                        slot = bl ? 64 * s + (int)__builtin_ctzll(bl) : slot;
+                    }
+                } else {
+                    // the child's creation number exceeds every queued one, so
+                    // it displaces the largest key only when cheaper
+                    uint32_t xl = 0u;
+#pragma unroll
+                    for (int s = 0; s < QPL; ++s) xl = max(xl, qocc[s] ? qcost[s] : 0u);
+                    const uint32_t xc = wave_umax(xl);
+                    uint32_t sl = 0u;
+#pragma unroll
+                    for (int s = 0; s < QPL; ++s) sl = max(sl, (qocc[s] && qcost[s] == xc) ? qseq[s] : 0u);
+                    const uint32_t xs = wave_umax(sl);
+                    if (cost < xc) {
+#pragma unroll
+                        for (int s = QPL - 1; s >= 0; --s) {
+                            const unsigned long long bl = __ballot(qocc[s] && qcost[s] == xc && qseq[s] == xs);
+                            slot = bl ? 64 * s + (int)__builtin_ctzll(bl) : slot;
+                        }
+                        // the evicted node's slot returns to the pool
+                        set_free(__builtin_amdgcn_readlane(pick(qidx, slot >> 6), slot & 63), true);
+                    }
+                }
+                if (slot >= 0) {
+#pragma unroll
+                    for (int s = 0; s < QPL; ++s) {
+                        const bool mine = lane + 64 * s == slot;
+                        qocc[s] = qocc[s] || mine;
+                        qcost[s] = mine ? cost : qcost[s];
+                        qseq[s] = mine ? cseq : qseq[s];
+                        qidx[s] = mine ? x : qidx[s];
+                    }
+                } else {
+                    set_free(x, true);
+                }
+            }
+            __syncthreads();
         }
 
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             a.out.dist[wi.out] = (int32_t)best;
             if (a.out.cand) a.out.cand[wi.out] = solves;
         }
+        if (wv == 0) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k)
-            if (lane + 64 * k < n1) a.out.map[wi.map_off + lane + 64 * k] = bestphi[k];
+            for (int k = 0; k < CPL; ++k)
+                if (lane + 64 * k < n1) a.out.map[wi.map_off + lane + 64 * k] = bestphi[k];
+        }
         __syncthreads();
     }
 }
 
+template <int PL, int CPL, int QPL>
+const void *bip_ptr_w(int nwav) {
+    if (nwav == 1) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, QPL, 1>);
+    if (nwav == 4) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, QPL, 4>);
+    return nullptr;
+}
+
 template <int PL, int CPL>
-const void *bip_ptr_q(int qpl) {
-    if (qpl == 1) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, 1>);
-    if (qpl == 2) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, 2>);
-    if (qpl == 4) return reinterpret_cast<const void *>(&kb_bip_kernel<PL, CPL, 4>);
+const void *bip_ptr_q(int qpl, int nwav) {
+    if (qpl == 1) return bip_ptr_w<PL, CPL, 1>(nwav);
+    if (qpl == 2) return bip_ptr_w<PL, CPL, 2>(nwav);
+    if (qpl == 4) return bip_ptr_w<PL, CPL, 4>(nwav);
     return nullptr;
 }
 
 template <int PL>
-const void *bip_ptr_c(int cpl, int qpl) {
-    if (cpl == 1) return bip_ptr_q<PL, 1>(qpl);
-    if (cpl == 2) return bip_ptr_q<PL, 2>(qpl);
-    if (cpl == 3) return bip_ptr_q<PL, 3>(qpl);
-    if (cpl == 4) return bip_ptr_q<PL, 4>(qpl);
+const void *bip_ptr_c(int cpl, int qpl, int nwav) {
+    if (cpl == 1) return bip_ptr_q<PL, 1>(qpl, nwav);
+    if (cpl == 2) return bip_ptr_q<PL, 2>(qpl, nwav);
+    if (cpl == 3) return bip_ptr_q<PL, 3>(qpl, nwav);
+    if (cpl == 4) return bip_ptr_q<PL, 4>(qpl, nwav);
     return nullptr;
 }
 
-const void *select_bip(int PL, int cpl, int qpl) {
-    if (PL == 0) return bip_ptr_c<0>(cpl, qpl);
-    if (PL == 2) return bip_ptr_c<2>(cpl, qpl);
-    if (PL == 4) return bip_ptr_c<4>(cpl, qpl);
+const void *select_bip(int PL, int cpl, int qpl, int nwav) {
+    if (PL == 0) return bip_ptr_c<0>(cpl, qpl, nwav);
+    if (PL == 2) return bip_ptr_c<2>(cpl, qpl, nwav);
+    if (PL == 4) return bip_ptr_c<4>(cpl, qpl, nwav);
     return nullptr;
 }
 
 }  // namespace
 
-hipError_t bip_max_resident(int PL, int cpl, int K, int *blocks_per_cu) {
-    const void *k = select_bip(PL, cpl, bip_queue_words(K));
+hipError_t bip_max_resident(int PL, int cpl, int K, int nwav, int *blocks_per_cu) {
+    const void *k = select_bip(PL, cpl, bip_queue_words(K), nwav);
     if (!k) return hipErrorInvalidValue;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, 64 * nwav, 0);
 }
 
-hipError_t launch_bip(int PL, int cpl, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
-                      int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_bip(PL, cpl, bip_queue_words(K));
+hipError_t launch_bip(int PL, int cpl, int nwav, const DbView &src, const DbView &dst, const WorkItem *work,
+                      int nwork, int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream) {
+    const void *k = select_bip(PL, cpl, bip_queue_words(K), nwav);
     if (!k || grid <= 0 || K < 1 || K > kBipMaxK || !ws) return hipErrorInvalidValue;
     BipArgs a;
     a.src = src;
@@ -626,7 +709,7 @@ hipError_t launch_bip(int PL, int cpl, const DbView &src, const DbView &dst, con
     a.ws = static_cast<unsigned char *>(ws);
     a.out = out;
     void *args[] = {&a};
-    return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, stream);
+    return hipLaunchKernel(k, dim3(grid), dim3(64 * nwav), args, 0, stream);
 }
 
 }  // namespace gedk
