@@ -58,9 +58,9 @@ def ops_per_candidate(w: int, planes: int) -> int:
     return 4 * w + lab + 16
 
 
-KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "wave_common.h", "ged_internal.h"),
-                  "kb_wave2_kernel": ("kb_wave2.hip", "wave_common.h", "ged_internal.h"),
-                  "kb_block_kernel": ("kb_block.hip", "ged_internal.h")}
+KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "wave_common.h", "ged_types.h"),
+                  "kb_wave2_kernel": ("kb_wave2.hip", "wave_common.h", "ged_types.h"),
+                  "kb_block_kernel": ("kb_block.hip", "ged_internal.h", "ged_types.h")}
 
 
 def kernel_source_hash(kernel: str) -> str:

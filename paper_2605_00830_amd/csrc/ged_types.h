@@ -1,0 +1,70 @@
+// Types shared by the host side of the library and its HIP kernels, and the
+// wavefront kernels' entry points: everything kb_wave.hip and kb_wave2.hip
+// compile against (nothing else of the library's internals).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gedk {
+
+// Graph record in the device database.  The adjacency pool holds, from
+// word `adj` on: n rows of w 32-bit words (bit x of row v set iff {v,x} is
+// an edge), then `planes` blocks of the same shape, block b holding bit b
+// of the database-wide edge-label code at each edge position.
+struct GraphRec {
+    int32_t n;
+    int32_t m;
+    int32_t w;       // ceil(n / 32)
+    int32_t pad;
+    int64_t adj;     // word offset into the adjacency pool
+    int64_t vlab;    // offset into the vertex-label pool
+};
+
+// A set of packed graphs: a database, or the staged queries of a serving
+// batch.  Work items index graphs of a source view (g1) and a target view
+// (g2); both use the same edge-label coding.
+struct DbView {
+    const GraphRec *graphs;
+    const uint32_t *adj;
+    const int32_t *vlab;
+    int32_t planes;  // edge-label bit planes in this database (0..4)
+};
+
+// One pair of a batch, in schedule order.
+struct WorkItem {
+    int32_t src;     // g1 id
+    int32_t dst;     // g2 id
+    int32_t out;     // index of the pair in the caller's order
+    int32_t pad;
+    int64_t map_off; // first mapping entry of the pair in d_map
+};
+
+struct Costs {
+    int32_t vsub, vdel, vins, esub, edel, eins;
+};
+
+struct Outputs {
+    int32_t *dist;
+    int32_t *map;
+    int64_t *cand;   // may be null
+};
+
+// Wavefront-per-pair kernel family: n1, n2 <= 32 and K <= 64; the beam lives
+// in registers (one slot per lane) and LDS.
+constexpr int kWaveMaxN = 32;
+constexpr int kWaveMaxK = 64;
+
+hipError_t wave_max_resident(int PL, int last_complete, int *blocks_per_cu);
+hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue, Costs c,
+                       int K, int last_complete, Outputs out, int grid, hipStream_t stream);
+
+// The same scheme for n1, n2 <= 64 (two-word vertex sets, children scored
+// into bytes), K <= 64.
+constexpr int kWave2MaxN = 64;
+
+hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu);
+hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
+                        Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream);
+
+}  // namespace gedk

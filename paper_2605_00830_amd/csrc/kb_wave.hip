@@ -60,7 +60,7 @@
 // (counts are at most 32, and the plan's overflow bound keeps every sum in
 // range); otherwise full 32-bit multiplies.  All sums are taken modulo 2^32;
 // the true values are below 2^31, so they come out exact.
-#include "ged_internal.h"
+#include "ged_types.h"
 #include "wave_common.h"
 
 namespace gedk {

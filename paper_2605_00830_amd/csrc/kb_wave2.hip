@@ -43,7 +43,7 @@
 // (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the first lane of least total
 // is the result.  The COMPLETE instantiation's last level instead completes every
 // child and keeps only the least total (first in generation order).
-#include "ged_internal.h"
+#include "ged_types.h"
 #include "wave_common.h"
 
 namespace gedk {
