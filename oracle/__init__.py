@@ -56,15 +56,15 @@ def _load():
     graph_args = [ctypes.c_int, P, ctypes.c_int, P, P, P]
     lib.oracle_kbest.argtypes = graph_args + graph_args + [P, i64, P, P]
     lib.oracle_kbest.restype = ctypes.c_int
-    lib.oracle_kbest_ex.argtypes = graph_args + graph_args + [P, i64, ctypes.c_int, P, P]
+    lib.oracle_kbest_ex.argtypes = graph_args + graph_args + [P, i64, ctypes.c_int, ctypes.c_int, P, P]
     lib.oracle_kbest_ex.restype = ctypes.c_int
-    lib.oracle_exact.argtypes = graph_args + graph_args + [P, ctypes.c_double, P, P]
+    lib.oracle_exact.argtypes = graph_args + graph_args + [P, ctypes.c_int, ctypes.c_double, P, P]
     lib.oracle_exact.restype = ctypes.c_int
-    lib.oracle_induced_cost.argtypes = graph_args + graph_args + [P, P, P]
+    lib.oracle_induced_cost.argtypes = graph_args + graph_args + [P, ctypes.c_int, P, P]
     lib.oracle_induced_cost.restype = ctypes.c_int
     lib.oracle_count_mappings.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.oracle_count_mappings.restype = ctypes.c_double
-    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, P, P, P, P]
+    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, ctypes.c_int, P, P, P, P]
     lib.oracle_kbest_pairs.restype = ctypes.c_int
     lib.oracle_bipartite.argtypes = graph_args + graph_args + [P, i64, P, P, P, P, P, P, P]
     lib.oracle_bipartite.restype = ctypes.c_int
@@ -96,23 +96,26 @@ def _check(st: int, what: str):
         raise OracleError(f"{what}: oracle status {st}")
 
 
-def kbest(g1, g2, costs: Sequence[int], K: int, last_complete: bool = False) -> Tuple[int, np.ndarray]:
+def kbest(g1, g2, costs: Sequence[int], K: int, last_complete: bool = False,
+          directed: bool = False) -> Tuple[int, np.ndarray]:
     """K-Best search g1 -> g2; returns (distance, mapping) with -1 = deleted.
 
     last_complete: complete every child of the last level and keep the least total
-    (instead of keeping the K of least partial distance, then completing)."""
+    (instead of keeping the K of least partial distance, then completing).
+    directed: edge k is the arc eu[k] -> ev[k]; each arc is one edit operation."""
     lib = _load()
     keep: list = []
     c = _arr(costs)
     dist = ctypes.c_int64(0)
     mp = np.zeros(max(int(g1.n), 1), dtype=np.int32)
     st = lib.oracle_kbest_ex(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
-                             1 if last_complete else 0, ctypes.byref(dist), _ptr(mp))
+                             1 if last_complete else 0, 1 if directed else 0, ctypes.byref(dist), _ptr(mp))
     _check(st, "kbest")
     return int(dist.value), mp[: int(g1.n)].copy()
 
 
-def exact(g1, g2, costs: Sequence[int], max_mappings: float = 1e8) -> Tuple[int, np.ndarray]:
+def exact(g1, g2, costs: Sequence[int], max_mappings: float = 1e8,
+          directed: bool = False) -> Tuple[int, np.ndarray]:
     """Exact GED by enumerating every injective partial mapping."""
     lib = _load()
     keep: list = []
@@ -120,12 +123,12 @@ def exact(g1, g2, costs: Sequence[int], max_mappings: float = 1e8) -> Tuple[int,
     dist = ctypes.c_int64(0)
     mp = np.zeros(max(int(g1.n), 1), dtype=np.int32)
     st = lib.oracle_exact(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c),
-                          float(max_mappings), ctypes.byref(dist), _ptr(mp))
+                          1 if directed else 0, float(max_mappings), ctypes.byref(dist), _ptr(mp))
     _check(st, "exact")
     return int(dist.value), mp[: int(g1.n)].copy()
 
 
-def induced_cost(g1, g2, costs: Sequence[int], mapping) -> int:
+def induced_cost(g1, g2, costs: Sequence[int], mapping, directed: bool = False) -> int:
     """Edit cost of a complete mapping (mapping[v] = -1 deletes v)."""
     lib = _load()
     keep: list = []
@@ -135,7 +138,7 @@ def induced_cost(g1, g2, costs: Sequence[int], mapping) -> int:
         raise OracleError("mapping length must equal g1.n")
     out = ctypes.c_int64(0)
     st = lib.oracle_induced_cost(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c),
-                                 _ptr(mp if mp.size else np.zeros(1, np.int32)), ctypes.byref(out))
+                                 1 if directed else 0, _ptr(mp if mp.size else np.zeros(1, np.int32)), ctypes.byref(out))
     _check(st, "induced_cost")
     return int(out.value)
 
@@ -154,7 +157,8 @@ def map_offsets(graphs, pairs: np.ndarray) -> np.ndarray:
     return off
 
 
-def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_complete: bool = False):
+def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_complete: bool = False,
+                directed: bool = False):
     """Run the oracle over many pairs of a GraphSet.
 
     Returns (dist int64 [P], maps int32 [sum n_src], offsets int64 [P]).
@@ -177,7 +181,7 @@ def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_co
     failed = ctypes.c_int64(-1)
     st = lib.oracle_kbest_pairs(_ptr(n), _ptr(m), _ptr(voff), _ptr(eoff), _ptr(vl), _ptr(eu),
                                 _ptr(ev), _ptr(el), _ptr(pairs), int(len(pairs)), _ptr(c), int(K),
-                                1 if last_complete else 0, _ptr(dist), _ptr(maps), _ptr(off),
+                                1 if last_complete else 0, 1 if directed else 0, _ptr(dist), _ptr(maps), _ptr(off),
                                 ctypes.byref(failed))
     _check(st, f"kbest_pairs (pair {failed.value})")
     return dist, maps[:total], off

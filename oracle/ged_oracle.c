@@ -32,6 +32,15 @@
  *                           (Alg. 1's final minimum taken over all of them
  *                           instead of over the K kept by partial distance).
  *
+ * Directed graphs (each function's `directed` argument): the edges are arcs
+ * (a, b), a != b, at most one per ordered pair, so a and b may be joined by
+ * two arcs.  Every place that looks at the unordered pair {a, b} of an
+ * undirected graph looks at the ordered pairs (a, b) and (b, a) instead: the
+ * implied operations of Sec. 2.3 between the edited vertex and an earlier
+ * one are taken for each direction (the "source or destination" scan of
+ * Sec. 4.4.1, read as both arc directions), and each arc is one edit
+ * operation.
+ *
  * Readings taken where the paper is silent (each is listed in the design
  * notes): g1 vertices are processed in index order; the children of a node
  * are the substitutions by ascending g2 index followed by the deletion;
@@ -56,6 +65,7 @@ typedef struct {
     uint8_t *has;        /* has[a*n+b] = 1 iff {a,b} is an edge */
     int32_t *lab;        /* lab[a*n+b] = label of edge {a,b} (0 when unlabelled) */
     int m;
+    int directed;        /* 1: has[a*n+b] is the arc a -> b only */
 } dgraph;
 
 static void dg_free(dgraph *g) {
@@ -66,12 +76,14 @@ static void dg_free(dgraph *g) {
 }
 
 /* Build the dense form; rejects out-of-range vertices, self-loops and
- * repeated edges (the paper's graphs are simple, Sec. 2.1). */
+ * repeated edges (the paper's graphs are simple, Sec. 2.1).  Directed: edge k
+ * is the arc eu[k] -> ev[k]; the reverse arc is another edge. */
 static int dg_build(dgraph *g, int n, const int32_t *vl, int m, const int32_t *eu,
-                    const int32_t *ev, const int32_t *el) {
+                    const int32_t *ev, const int32_t *el, int directed) {
     g->n = n;
     g->vl = vl;
     g->m = m;
+    g->directed = directed ? 1 : 0;
     g->has = NULL;
     g->lab = NULL;
     if (n < 0 || m < 0) return OR_EINVAL;
@@ -84,8 +96,12 @@ static int dg_build(dgraph *g, int n, const int32_t *vl, int m, const int32_t *e
         if (a < 0 || b < 0 || a >= n || b >= n || a == b) { dg_free(g); return OR_EINVAL; }
         if (g->has[(size_t)a * n + b]) { dg_free(g); return OR_EINVAL; }
         int32_t l = el ? el[k] : 0;
-        g->has[(size_t)a * n + b] = g->has[(size_t)b * n + a] = 1;
-        g->lab[(size_t)a * n + b] = g->lab[(size_t)b * n + a] = l;
+        g->has[(size_t)a * n + b] = 1;
+        g->lab[(size_t)a * n + b] = l;
+        if (!g->directed) {
+            g->has[(size_t)b * n + a] = 1;
+            g->lab[(size_t)b * n + a] = l;
+        }
     }
     return OR_OK;
 }
@@ -118,18 +134,19 @@ static int64_t induced_cost(const dgraph *g1, const dgraph *g2, const int32_t *c
     for (int u = 0; u < g2->n; u++)
         if (pre[u] < 0) cost += c[2];                     /* vertex insertion */
     /* every g1 edge: deleted unless both ends map onto a g2 edge; substituted
-     * when it does and the labels differ */
+     * when it does and the labels differ.  Undirected: each pair a < b once;
+     * directed: every ordered pair (a, b), the arc a -> b onto phi(a) -> phi(b) */
     for (int a = 0; a < g1->n; a++)
-        for (int b = a + 1; b < g1->n; b++) {
-            if (!edge(g1, a, b)) continue;
+        for (int b = g1->directed ? 0 : a + 1; b < g1->n; b++) {
+            if (b == a || !edge(g1, a, b)) continue;
             int x = map[a], y = map[b];
             if (x < 0 || y < 0 || !edge(g2, x, y)) cost += c[4];
             else if (elab(g1, a, b) != elab(g2, x, y)) cost += c[3];
         }
     /* every g2 edge not the image of a g1 edge is inserted */
     for (int x = 0; x < g2->n; x++)
-        for (int y = x + 1; y < g2->n; y++) {
-            if (!edge(g2, x, y)) continue;
+        for (int y = g2->directed ? 0 : x + 1; y < g2->n; y++) {
+            if (y == x || !edge(g2, x, y)) continue;
             int a = pre[x], b = pre[y];
             if (a < 0 || b < 0 || !edge(g1, a, b)) cost += c[5];
         }
@@ -149,12 +166,12 @@ static int check_map(const int32_t *map, int n1, int n2, int *seen) {
 int oracle_induced_cost(int n1, const int32_t *vl1, int m1, const int32_t *eu1,
                         const int32_t *ev1, const int32_t *el1, int n2, const int32_t *vl2,
                         int m2, const int32_t *eu2, const int32_t *ev2, const int32_t *el2,
-                        const int32_t *costs, const int32_t *map, int64_t *cost_out) {
+                        const int32_t *costs, int directed, const int32_t *map, int64_t *cost_out) {
     if (!costs_ok(costs)) return OR_EINVAL;
     dgraph g1, g2;
-    int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1);
+    int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1, directed);
     if (st) return st;
-    st = dg_build(&g2, n2, vl2, m2, eu2, ev2, el2);
+    st = dg_build(&g2, n2, vl2, m2, eu2, ev2, el2, directed);
     if (st) { dg_free(&g1); return st; }
     int *pre = (int *)malloc(sizeof(int) * (size_t)(n2 + 1));
     if (!pre) { dg_free(&g1); dg_free(&g2); return OR_ENOMEM; }
@@ -214,14 +231,14 @@ double oracle_count_mappings(int n1, int n2) {
 
 int oracle_exact(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                  const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
-                 const int32_t *ev2, const int32_t *el2, const int32_t *costs,
+                 const int32_t *ev2, const int32_t *el2, const int32_t *costs, int directed,
                  double max_mappings, int64_t *dist, int32_t *map_out) {
     if (!costs_ok(costs)) return OR_EINVAL;
     if (oracle_count_mappings(n1, n2) > max_mappings) return OR_ETOOBIG;
     dgraph g1, g2;
-    int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1);
+    int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1, directed);
     if (st) return st;
-    st = dg_build(&g2, n2, vl2, m2, eu2, ev2, el2);
+    st = dg_build(&g2, n2, vl2, m2, eu2, ev2, el2, directed);
     if (st) { dg_free(&g1); return st; }
     exact_ctx x;
     x.g1 = &g1;
@@ -273,16 +290,24 @@ static int cmp_order(const void *a, const void *b) {
  * given the parent's mapping of vertices 0..i-1 (Alg. 2 and Sec. 2.3):
  * the vertex substitution cost plus, for every previously edited vertex j,
  * the implied operation on the pair (i, j) versus (u, phi[j]).            */
+static int64_t pair_op(const dgraph *g1, const dgraph *g2, const int32_t *c, int a, int b, int x,
+                       int y) {
+    int e1 = edge(g1, a, b);
+    int e2 = (x != DELETED && y != DELETED) && edge(g2, x, y);
+    if (e1 && !e2) return c[4];                                       /* edge deletion */
+    if (!e1 && e2) return c[5];                                       /* edge insertion */
+    if (e1 && e2 && elab(g1, a, b) != elab(g2, x, y)) return c[3];    /* substitution */
+    return 0;
+}
+
+/* Directed graphs: the pair (i, j) is the arc i -> j and the arc j -> i, each
+ * against its image. */
 static int64_t sub_step(const dgraph *g1, const dgraph *g2, const int32_t *c, int i, int u,
                         const int32_t *phi) {
     int64_t d = (g1->vl[i] != g2->vl[u]) ? c[0] : 0;
     for (int j = 0; j < i; j++) {
-        int e1 = edge(g1, i, j);
-        int x = phi[j];
-        int e2 = (x != DELETED) && edge(g2, u, x);
-        if (e1 && !e2) d += c[4];                                    /* edge deletion */
-        else if (!e1 && e2) d += c[5];                               /* edge insertion */
-        else if (e1 && e2 && elab(g1, i, j) != elab(g2, u, x)) d += c[3]; /* substitution */
+        d += pair_op(g1, g2, c, i, j, u, phi[j]);
+        if (g1->directed) d += pair_op(g1, g2, c, j, i, phi[j], u);
     }
     return d;
 }
@@ -290,8 +315,10 @@ static int64_t sub_step(const dgraph *g1, const dgraph *g2, const int32_t *c, in
 /* Deleting g1 vertex i deletes it and its edges to earlier vertices. */
 static int64_t del_step(const dgraph *g1, const int32_t *c, int i) {
     int64_t d = c[1];
-    for (int j = 0; j < i; j++)
+    for (int j = 0; j < i; j++) {
         if (edge(g1, i, j)) d += c[4];
+        if (g1->directed && edge(g1, j, i)) d += c[4];
+    }
     return d;
 }
 
@@ -303,33 +330,33 @@ static int64_t completion(const dgraph *g2, const int32_t *c, const int *used) {
     for (int u = 0; u < g2->n; u++)
         if (!used[u]) t += c[2];
     for (int x = 0; x < g2->n; x++)
-        for (int y = x + 1; y < g2->n; y++)
-            if (edge(g2, x, y) && (!used[x] || !used[y])) t += c[5];
+        for (int y = g2->directed ? 0 : x + 1; y < g2->n; y++)
+            if (y != x && edge(g2, x, y) && (!used[x] || !used[y])) t += c[5];
     return t;
 }
 
 int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                     const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
                     const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
-                    int last_complete, int64_t *dist, int32_t *map_out);
+                    int last_complete, int directed, int64_t *dist, int32_t *map_out);
 
 int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                  const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
                  const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
                  int64_t *dist, int32_t *map_out) {
-    return oracle_kbest_ex(n1, vl1, m1, eu1, ev1, el1, n2, vl2, m2, eu2, ev2, el2, costs, K, 0, dist,
+    return oracle_kbest_ex(n1, vl1, m1, eu1, ev1, el1, n2, vl2, m2, eu2, ev2, el2, costs, K, 0, 0, dist,
                            map_out);
 }
 
 int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                     const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
                     const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
-                    int last_complete, int64_t *dist, int32_t *map_out) {
+                    int last_complete, int directed, int64_t *dist, int32_t *map_out) {
     if (!costs_ok(costs) || K < 1) return OR_EINVAL;
     dgraph g1, g2;
-    int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1);
+    int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1, directed);
     if (st) return st;
-    st = dg_build(&g2, n2, vl2, m2, eu2, ev2, el2);
+    st = dg_build(&g2, n2, vl2, m2, eu2, ev2, el2, directed);
     if (st) { dg_free(&g1); return st; }
 
     const size_t width = (size_t)(n1 > 0 ? n1 : 1);
@@ -432,12 +459,7 @@ int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, cons
             for (int u = 0; u < n2; u++) used[u] = 0;
             for (int j = 0; j < n1; j++)
                 if (ph[j] != DELETED) used[ph[j]] = 1;
-            int64_t total = ped[p];
-            for (int u = 0; u < n2; u++)
-                if (!used[u]) total += costs[2];
-            for (int x = 0; x < n2; x++)
-                for (int y = x + 1; y < n2; y++)
-                    if (edge(&g2, x, y) && (!used[x] || !used[y])) total += costs[5];
+            int64_t total = ped[p] + completion(&g2, costs, used);
             if (total < best) {
                 best = total;
                 best_p = p;
@@ -461,7 +483,7 @@ done:
 int oracle_kbest_pairs(const int32_t *n, const int32_t *m, const int64_t *voff,
                        const int64_t *eoff, const int32_t *vlabel, const int32_t *eu,
                        const int32_t *ev, const int32_t *elabel, const int64_t *pairs,
-                       int64_t npairs, const int32_t *costs, int64_t K, int last_complete,
+                       int64_t npairs, const int32_t *costs, int64_t K, int last_complete, int directed,
                        int64_t *dist, int32_t *map_out, const int64_t *map_off, int64_t *failed_pair) {
     for (int64_t p = 0; p < npairs; p++) {
         int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
@@ -469,7 +491,7 @@ int oracle_kbest_pairs(const int32_t *n, const int32_t *m, const int64_t *voff,
         const int32_t *el_b = elabel ? elabel + eoff[b] : NULL;
         int st = oracle_kbest_ex(n[a], vlabel + voff[a], m[a], eu + eoff[a], ev + eoff[a], el_a,
                                  n[b], vlabel + voff[b], m[b], eu + eoff[b], ev + eoff[b], el_b,
-                                 costs, K, last_complete, dist + p, map_out + map_off[p]);
+                                 costs, K, last_complete, directed, dist + p, map_out + map_off[p]);
         if (st) {
             *failed_pair = p;
             return st;

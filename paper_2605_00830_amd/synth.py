@@ -69,10 +69,11 @@ def _uint_below(u: np.ndarray, bound: int) -> np.ndarray:
 
 @dataclass
 class Graph:
-    """One undirected simple labelled graph (Sec. 2.1): vertices 0..n-1."""
+    """One undirected simple labelled graph (Sec. 2.1): vertices 0..n-1.
+    A directed graph uses the same fields, edge k being the arc eu[k] -> ev[k]."""
     n: int
     vlabel: np.ndarray                      # int32 [n]
-    eu: np.ndarray                          # int32 [m], eu < ev
+    eu: np.ndarray                          # int32 [m], eu < ev (undirected)
     ev: np.ndarray                          # int32 [m]
     elabel: Optional[np.ndarray] = None     # int32 [m] or None (all edges label 0)
 
@@ -154,6 +155,26 @@ def er_graph(seed: int, index: int, n_lo: int, n_hi: int, p_lo: float, p_hi: flo
     a, b = np.triu_indices(n, 1)
     keep = uniforms(seed, index, 2, a.shape[0]) < p
     return Graph(n, vl, a[keep].astype(np.int32), b[keep].astype(np.int32), None)
+
+
+def directed_graph(seed: int, index: int, n_lo: int, n_hi: int, p_lo: float, p_hi: float,
+                   n_vlabels: int, n_elabels: int = 0) -> Graph:
+    """Directed G(n, p): n ~ U{n_lo..n_hi}, p ~ U[p_lo, p_hi], vertex labels ~ U{0..L-1}.
+
+    Stream tags: 0 = (n, p), 1 = vertex labels, 2 = one draw per ordered pair
+    (a, b), a != b, in row-major order; the arc a -> b exists iff draw < p (so
+    both arcs of a pair can exist); 5 = arc labels ~ U{0..n_elabels-1}.
+    """
+    u = uniforms(seed, index, 0, 2)
+    n = n_lo + int(_uint_below(u[:1], n_hi - n_lo + 1)[0])
+    p = p_lo + float(u[1]) * (p_hi - p_lo)
+    vl = _uint_below(uniforms(seed, index, 1, n), n_vlabels).astype(np.int32)
+    a, b = np.nonzero(~np.eye(n, dtype=bool))
+    keep = uniforms(seed, index, 2, a.shape[0]) < p
+    g = Graph(n, vl, a[keep].astype(np.int32), b[keep].astype(np.int32), None)
+    if n_elabels > 0:
+        g.elabel = _uint_below(uniforms(seed, index, 5, g.m), n_elabels).astype(np.int32)
+    return g
 
 
 def _prufer_tree(seq: np.ndarray, n: int) -> List[Tuple[int, int]]:
@@ -277,6 +298,15 @@ def batch_molecule_k64(npairs: int = 10000) -> Workload:
     gs = GraphSet.from_graphs([molecule_graph(3, i) for i in range(1, 2 * npairs + 1)])
     pairs = np.stack([np.arange(0, 2 * npairs, 2), np.arange(1, 2 * npairs, 2)], 1)
     return Workload(f"batch_molecule_n10-70_{npairs}pairs_k64", gs, pairs.astype(np.int64), UNIT_COSTS, 64)
+
+
+def batch_directed_10_30(npairs: int = 4096) -> Workload:
+    """npairs directed G(n, p) pairs, n ~ U{10..30}, p ~ U[0.05,0.15] per ordered pair (about the
+    arc count of batch_er_10_30's edges), 5 vertex labels, unit costs, K=64 (seed 6)."""
+    gs = GraphSet.from_graphs([directed_graph(6, i, 10, 30, 0.05, 0.15, 5) for i in range(2 * npairs)])
+    pairs = np.stack([np.arange(0, 2 * npairs, 2), np.arange(1, 2 * npairs, 2)], 1)
+    return Workload(f"batch_directed_n10-30_p0.05-0.15_{npairs}pairs_k64", gs,
+                    pairs.astype(np.int64), UNIT_COSTS, 64)
 
 
 def stress_er_100_500(npairs: int = 256) -> Workload:

@@ -13,6 +13,10 @@ same quantity by a different route:
   scan, and ranking uses the child's mapping tuple itself (deleted = n2) for
   the generation-order tie-break; optionally with the complete-then-minimum
   last level, scored by the padded-permutation cost of each complete path.
+
+Each takes `directed`: edge k is then the arc eu[k] -> ev[k], and every loop
+over unordered vertex pairs runs over ordered pairs instead (one edit
+operation per arc).
 """
 from __future__ import annotations
 
@@ -24,17 +28,25 @@ import numpy as np
 VSUB, VDEL, VINS, ESUB, EDEL, EINS = range(6)
 
 
-def edge_dict(g) -> Dict[Tuple[int, int], int]:
+def edge_dict(g, directed: bool = False) -> Dict[Tuple[int, int], int]:
     el = g.elabel if getattr(g, "elabel", None) is not None else [0] * len(g.eu)
     d = {}
     for a, b, l in zip(g.eu, g.ev, el):
         a, b, l = int(a), int(b), int(l)
         d[(a, b)] = l
-        d[(b, a)] = l
+        if not directed:
+            d[(b, a)] = l
     return d
 
 
-def qap_cost(g1, g2, c: Sequence[int], perm: Sequence[int]) -> int:
+def _pairs(idx: Sequence[int], directed: bool):
+    """Unordered pairs (i < j) of idx, or every ordered pair i != j."""
+    if directed:
+        return [(i, j) for i in idx for j in idx if i != j]
+    return [(idx[a], idx[b]) for a in range(len(idx)) for b in range(a + 1, len(idx))]
+
+
+def qap_cost(g1, g2, c: Sequence[int], perm: Sequence[int], directed: bool = False) -> int:
     """Cost of a permutation of the padded vertex set (size n1+n2).
 
     Position i < n1 is g1 vertex i, position i >= n1 an epsilon; target
@@ -42,7 +54,7 @@ def qap_cost(g1, g2, c: Sequence[int], perm: Sequence[int]) -> int:
     """
     n1, n2 = int(g1.n), int(g2.n)
     N = n1 + n2
-    E1, E2 = edge_dict(g1), edge_dict(g2)
+    E1, E2 = edge_dict(g1, directed), edge_dict(g2, directed)
     cost = 0
     for i in range(N):
         t = perm[i]
@@ -52,17 +64,16 @@ def qap_cost(g1, g2, c: Sequence[int], perm: Sequence[int]) -> int:
             cost += c[VDEL]
         elif t < n2:
             cost += c[VINS]
-    for i in range(N):
-        for j in range(i + 1, N):
-            e1 = E1.get((i, j)) if (i < n1 and j < n1) else None
-            a, b = perm[i], perm[j]
-            e2 = E2.get((a, b)) if (a < n2 and b < n2) else None
-            if e1 is not None and e2 is not None:
-                cost += c[ESUB] if e1 != e2 else 0
-            elif e1 is not None:
-                cost += c[EDEL]
-            elif e2 is not None:
-                cost += c[EINS]
+    for i, j in _pairs(list(range(N)), directed):
+        e1 = E1.get((i, j)) if (i < n1 and j < n1) else None
+        a, b = perm[i], perm[j]
+        e2 = E2.get((a, b)) if (a < n2 and b < n2) else None
+        if e1 is not None and e2 is not None:
+            cost += c[ESUB] if e1 != e2 else 0
+        elif e1 is not None:
+            cost += c[EDEL]
+        elif e2 is not None:
+            cost += c[EINS]
     return cost
 
 
@@ -79,14 +90,14 @@ def perm_from_map(mapping: Sequence[int], n1: int, n2: int) -> List[int]:
     return perm
 
 
-def qap_exact(g1, g2, c: Sequence[int]) -> int:
+def qap_exact(g1, g2, c: Sequence[int], directed: bool = False) -> int:
     n1, n2 = int(g1.n), int(g2.n)
-    return min(qap_cost(g1, g2, c, p) for p in itertools.permutations(range(n1 + n2)))
+    return min(qap_cost(g1, g2, c, p, directed) for p in itertools.permutations(range(n1 + n2)))
 
 
-def partial_cost(g1, g2, c, phi: Sequence[int]) -> int:
+def partial_cost(g1, g2, c, phi: Sequence[int], directed: bool = False) -> int:
     """Cost of all edit operations on the path phi (g1 vertices 0..len(phi)-1 edited)."""
-    E1, E2 = edge_dict(g1), edge_dict(g2)
+    E1, E2 = edge_dict(g1, directed), edge_dict(g2, directed)
     k = len(phi)
     cost = 0
     img = {}
@@ -97,32 +108,29 @@ def partial_cost(g1, g2, c, phi: Sequence[int]) -> int:
         else:
             img[t] = v
             cost += c[VSUB] if int(g1.vlabel[v]) != int(g2.vlabel[t]) else 0
-    for a in range(k):
-        for b in range(a + 1, k):
-            e1 = E1.get((a, b))
-            if e1 is None:
-                continue
-            x, y = phi[a], phi[b]
-            e2 = E2.get((x, y)) if (x >= 0 and y >= 0) else None
-            if e2 is None:
-                cost += c[EDEL]
-            elif e2 != e1:
-                cost += c[ESUB]
-    targets = sorted(img)
-    for ia in range(len(targets)):
-        for ib in range(ia + 1, len(targets)):
-            x, y = targets[ia], targets[ib]
-            if (x, y) in E2 and (img[x], img[y]) not in E1:
-                cost += c[EINS]
+    for a, b in _pairs(list(range(k)), directed):
+        e1 = E1.get((a, b))
+        if e1 is None:
+            continue
+        x, y = phi[a], phi[b]
+        e2 = E2.get((x, y)) if (x >= 0 and y >= 0) else None
+        if e2 is None:
+            cost += c[EDEL]
+        elif e2 != e1:
+            cost += c[ESUB]
+    for x, y in _pairs(sorted(img), directed):
+        if (x, y) in E2 and (img[x], img[y]) not in E1:
+            cost += c[EINS]
     return cost
 
 
-def scratch_beam(g1, g2, c, K: int, last_complete: bool = False) -> Tuple[int, List[int]]:
+def scratch_beam(g1, g2, c, K: int, last_complete: bool = False,
+                 directed: bool = False) -> Tuple[int, List[int]]:
     """last_complete: at the last level every child is scored by the cost of its
     complete edit path (the padded-permutation form, qap_cost) and the least
     (cost, mapping tuple) is returned."""
     n1, n2 = int(g1.n), int(g2.n)
-    E2 = edge_dict(g2)
+    E2 = edge_dict(g2, directed)
 
     def key(phi):  # lexicographic key with deletion after every g2 vertex
         return tuple(n2 if t < 0 else t for t in phi)
@@ -136,9 +144,10 @@ def scratch_beam(g1, g2, c, K: int, last_complete: bool = False) -> Tuple[int, L
                 if u >= 0 and u in used:
                     continue
                 ch = phi + (u,)
-                children.append((partial_cost(g1, g2, c, ch), key(ch), ch))
+                children.append((partial_cost(g1, g2, c, ch, directed), key(ch), ch))
         if last_complete and i == n1 - 1:
-            best_c = min((qap_cost(g1, g2, c, perm_from_map(ch, n1, n2)), key(ch), ch) for _, _, ch in children)
+            best_c = min((qap_cost(g1, g2, c, perm_from_map(ch, n1, n2), directed), key(ch), ch)
+                         for _, _, ch in children)
             return best_c[0], list(best_c[2])
         children.sort(key=lambda x: (x[0], x[1]))
         kept = children[:K]
@@ -147,11 +156,10 @@ def scratch_beam(g1, g2, c, K: int, last_complete: bool = False) -> Tuple[int, L
     best: Optional[Tuple[int, Tuple[int, ...], Tuple[int, ...]]] = None
     for phi in beam:
         used = {t for t in phi if t >= 0}
-        total = partial_cost(g1, g2, c, phi) + c[VINS] * (n2 - len(used))
-        for x in range(n2):
-            for y in range(x + 1, n2):
-                if (x, y) in E2 and (x not in used or y not in used):
-                    total += c[EINS]
+        total = partial_cost(g1, g2, c, phi, directed) + c[VINS] * (n2 - len(used))
+        for x, y in _pairs(list(range(n2)), directed):
+            if (x, y) in E2 and (x not in used or y not in used):
+                total += c[EINS]
         cand = (total, key(phi), phi)
         if best is None or cand[:2] < best[:2]:
             best = cand
