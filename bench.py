@@ -108,7 +108,7 @@ def oracle_mod():
     return oracle
 
 
-def cpu_oracle(graphs, pairs, costs, K, threads: int, last_complete: bool = False):
+def cpu_oracle(graphs, pairs, costs, K, threads: int, last_complete: bool = False, directed: bool = False):
     """Run the CPU oracle over `pairs` with `threads` threads (ctypes releases the GIL)."""
     import oracle
     oracle._load()
@@ -116,7 +116,8 @@ def cpu_oracle(graphs, pairs, costs, K, threads: int, last_complete: bool = Fals
     results = [None] * threads
 
     def work(t):
-        results[t] = oracle.kbest_pairs(graphs, pairs[shards[t]], costs, K, last_complete=last_complete)
+        results[t] = oracle.kbest_pairs(graphs, pairs[shards[t]], costs, K, last_complete=last_complete,
+                                        directed=directed)
 
     t0 = time.perf_counter()
     th = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
@@ -140,10 +141,12 @@ def cpu_oracle(graphs, pairs, costs, K, threads: int, last_complete: bool = Fals
 
 
 def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2000, seed: int = 7,
-                  streams: int = 1):
+                  streams: int = 1, method: int = 0):
     """Serving on the mix workload: saturated throughput (closed loop), then
     Poisson arrivals at fractions of it; latency = completion - scheduled
-    arrival.  The same loop with one launch per query is the per-pair path."""
+    arrival.  The same loop with one launch per query is the per-pair path.
+    method 1 serves the bipartite method, on the queries whose pair has
+    n1 + n2 <= 256 (its limit)."""
     ndb = w.meta["ndb"]
     nq = min(n_queries, len(w.pairs))
     db = ged.Database(w.graphs.slice(0, ndb))
@@ -203,12 +206,19 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         return t_sub, t_done
 
     # the server's size classes: small (both orders <= 32) and mid (<= 64) for K <= 64,
-    # medium (<= 128), large
+    # medium (<= 128), large; bipartite: n1 + n2 <= 64, 128, 192, 256
     n_q = np.asarray(qgs.n, np.int64)
     n_t = np.asarray(w.graphs.n, np.int64)[targets]
     n_max = np.maximum(n_q, n_t)
     wave = w.K <= 64
-    cls = np.where(wave & (n_max <= 32), 0, np.where(wave & (n_max <= 64), 1, np.where(n_max <= 128, 2, 3)))
+    if method == 1:
+        cls = (n_q + n_t + 63) // 64 - 1
+        sel = np.nonzero(n_q + n_t <= 256)[0]
+        class_names = ("le64", "le128", "le192", "le256")
+    else:
+        cls = np.where(wave & (n_max <= 32), 0, np.where(wave & (n_max <= 64), 1, np.where(n_max <= 128, 2, 3)))
+        sel = np.arange(nq)
+        class_names = ("small", "mid", "medium", "large")
 
     def latency_stats(t_done, arrivals, idx=None):
         lat = (t_done - arrivals) / 1e6
@@ -218,7 +228,7 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         out = {"p50_ms": round(float(np.percentile(lat, 50)), 4), "p99_ms": round(float(np.percentile(lat, 99)), 4),
                "p999_ms": round(float(np.percentile(lat, 99.9)), 4), "mean_ms": round(float(lat.mean()), 4)}
         per = {}
-        for k, name in enumerate(("small", "mid", "medium", "large")):
+        for k, name in enumerate(class_names):
             x = lat[c == k]
             if len(x):
                 per[name] = {"queries": int(len(x)), "p50_ms": round(float(np.percentile(x, 50)), 4),
@@ -226,13 +236,16 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         out["by_class"] = per
         return out
 
-    out = {"config": {"workload": w.name, "database_graphs": ndb, "queries": nq, "K": w.K,
+    out = {"config": {"workload": w.name, "database_graphs": ndb, "queries": int(len(sel)), "K": w.K,
                       "costs": list(w.costs), "streams_per_class": streams,
+                      "method": "bipartite" if method == 1 else "tree",
                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}}
-    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=streams, max_batch=2048, max_inflight=8192)
-    warm = np.arange(min(2000, nq))
+    srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=streams, max_batch=2048, max_inflight=8192,
+                     method=method)
+    warm = sel[:min(2000, len(sel))]
     run(srv, warm)
-    idx = np.arange(nq)
+    idx = sel
+    nq = len(idx)
     ts, td = run(srv, idx)
     qps_sat = nq / ((td.max() - ts.min()) / 1e9)
     out["saturated_qps"] = round(qps_sat, 1)
@@ -247,14 +260,14 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         ts, td = run(srv, idx, arrivals)
         achieved = nq / ((td.max() - arrivals[0]) / 1e9)
         entry = {"load": f, "offered_qps": round(lam, 1), "achieved_qps": round(achieved, 1)}
-        entry.update(latency_stats(td, arrivals))
+        entry.update(latency_stats(td, arrivals, idx))
         out["open_loop"].append(entry)
         log(f"serving at {f:.2f} x saturated: {entry}")
     out["server_stats"] = srv.stats()
     srv.close()
     # per-pair path: one launch per query, same loop
-    pp = ged.Server(db, w.K, w.costs, hbm_budget=4 << 30, streams=1, max_batch=1, max_inflight=1)
-    pidx = np.arange(min(perpair_queries, nq))
+    pp = ged.Server(db, w.K, w.costs, hbm_budget=4 << 30, streams=1, max_batch=1, max_inflight=1, method=method)
+    pidx = sel[:min(perpair_queries, nq)]
     ts, td = run(pp, pidx)
     qps_pp = len(pidx) / ((td.max() - ts.min()) / 1e9)
     lam = fracs[0] * qps_sat
@@ -266,7 +279,7 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         t0 = time.monotonic_ns() + 20_000_000
         arrivals = t0 + np.cumsum(gaps * 1e9).astype(np.int64)
         ts, td = run(pp, pidx, arrivals)
-        entry.update(latency_stats(td, arrivals))
+        entry.update(latency_stats(td, arrivals, pidx))
     out["perpair"] = entry
     log(f"serving per-pair path: {entry}")
     pp.close()
@@ -426,6 +439,54 @@ def complete_measure(ged, db, w, steps: int, warmup: int, literal_dist, tune: bo
     return out, d, maps_np
 
 
+def directed_measure(ged, steps: int, warmup: int, tune: bool, tune_cache, threads: int, check_every: int = 8):
+    """Directed graphs: the 4096-pair directed batch (n 10..30, arcs with p 0.05..0.15,
+    K = 64, unit costs) through the workgroup kernel; kernel time, throughput, parity
+    on every `check_every`-th pair, and the oracle's rate on that sample."""
+    import torch
+    from paper_2605_00830_amd import synth
+    w = synth.batch_directed_10_30(4096)
+    P = len(w.pairs)
+    db = ged.Database(w.graphs, directed=True)
+    plan = ged.Plan(db, w.pairs, w.K)
+    dist, maps, _ = plan.outputs()
+    s = torch.cuda.current_stream()
+    plan.set_timing(True)
+    if tune:
+        plan.tune(w.costs, dist, maps, stream=s, cache_path=tune_cache)
+        s.synchronize()
+    for _ in range(warmup):
+        plan.run(w.costs, dist, maps, stream=s)
+        s.synchronize()
+    ks = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(w.costs, dist, maps, stream=s)
+        s.synchronize()
+        ks.append(plan.kernel_ms())
+    wall = time.perf_counter() - t0
+    d = dist[:P].cpu().numpy()
+    m = maps[:plan.map_size].cpu().numpy()
+    out = {"config": {"workload": w.name, "pairs": P, "K": w.K, "costs": list(w.costs),
+                      "mean_order": round(float(w.graphs.n.mean()), 2), "mean_arcs": round(float(w.graphs.m.mean()), 2)},
+           "value": round(P * steps / wall, 2), "unit": "pairs/s", "ms_per_step": round(wall * 1e3 / steps, 4),
+           "kernel_ms": round(float(np.mean(ks)), 4), "bins": plan.bins()}
+    plan.close()
+    db.close()
+    idx = np.arange(0, P, check_every)
+    cw, cd, cm = cpu_oracle(w.graphs, w.pairs[idx], w.costs, w.K, threads, directed=True)
+    n_src = np.asarray(w.graphs.n, np.int64)[w.pairs[:, 0]]
+    moff = np.concatenate([[0], np.cumsum(n_src)])
+    coff = np.concatenate([[0], np.cumsum(n_src[idx])])
+    maps_ok = all(np.array_equal(m[moff[q]:moff[q + 1]], cm[coff[k]:coff[k + 1]]) for k, q in enumerate(idx))
+    out["parity"] = {"pairs_checked": int(len(idx)), "dist_equal": bool(np.array_equal(d[idx], cd)),
+                     "maps_equal": bool(maps_ok)}
+    out["cpu_baseline"] = {"value": round(len(idx) / cw, 2), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+                           "sample": f"{len(idx)} of {P} pairs, {threads} threads, {cw:.2f} s wall"}
+    log(f"directed: kernel {out['kernel_ms']} ms, {out['value']:.0f} pairs/s, parity {out['parity']}")
+    return out
+
+
 def workload(name: str):
     from paper_2605_00830_amd import synth
     if name == "batch":
@@ -455,6 +516,8 @@ def main():
     ap.add_argument("--large-k-only", action="store_true",
                     help="run only the single-pair large-K measurement and print its JSON")
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS, help="server streams per size class")
+    ap.add_argument("--serve-method", choices=["tree", "bipartite"], default="tree",
+                    help="method the serving measurement runs (--workload serve)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-perpair", action="store_true")
@@ -462,6 +525,7 @@ def main():
                     help="skip the complete-then-minimum last-level measurement")
     ap.add_argument("--no-bipartite", action="store_true",
                     help="skip the bipartite K-best-assignment measurement")
+    ap.add_argument("--no-directed", action="store_true", help="skip the directed-graph measurement")
     ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: reuse its choices, append new ones (default: tune afresh)")
@@ -488,7 +552,8 @@ def main():
         t0 = time.perf_counter()
         sw = synth.serve_mix(args.serve_db, args.serve_queries)
         log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
-        res = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95), streams=args.serve_streams)
+        res = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95), streams=args.serve_streams,
+                            method=1 if args.serve_method == "bipartite" else 0)
         head = res["open_loop"][1]
         print(json.dumps({
             "metric": METRIC, "value": res["saturated_qps"], "unit": "pairs/s", "n_gpus": 1,
@@ -626,6 +691,11 @@ def main():
         bip, b_dist, b_maps, b_cand = bipartite_measure(ged, db, w, args.steps, args.warmup, not args.no_tune,
                                                         args.tune_cache)
 
+    directed = None
+    if not args.no_directed and args.workload == "batch":
+        directed = directed_measure(ged, args.steps, args.warmup, not args.no_tune, args.tune_cache,
+                                    args.cpu_threads or min(16, os.cpu_count() or 1))
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -718,6 +788,7 @@ def main():
         "edit_path": epath,
         "complete_then_min": complete,
         "bipartite": bip,
+        "directed": directed,
         "large_k": large_k,
         "serving": serving,
     }

@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define GED_ABI_VERSION 4
+#define GED_ABI_VERSION 5
 
 /* Limits of this version. */
 #define GED_MAX_VERTICES 512      /* per graph */
@@ -123,6 +123,26 @@ const char *ged_status_name(int32_t status);
  * On success *out owns device memory until ged_db_destroy.
  * ---------------------------------------------------------------------- */
 ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out);
+
+/* Database flags.
+ * GED_DB_DIRECTED: every graph is directed.  Edge k of a ged_graph is then
+ * the arc eu[k] -> ev[k] (eu != ev, each ordered pair at most once, so a
+ * pair of vertices may carry both arcs, with labels of their own; m <=
+ * n(n-1)), and every arc is one edit operation: the implied operations of
+ * Sec. 2.3 between the edited vertex and each earlier one are taken for
+ * both arc directions.  A directed database serves the tree search
+ * (ged_plan_create, ged_plan_create_ex with GED_METHOD_TREE, ged_kbest,
+ * ged_kbest_perpair) for graphs of at most GED_DIRECTED_MAX_ORDER
+ * vertices, and ged_edit_path; ged_wide_create, ged_server_create and the
+ * bipartite method return GED_EUNSUPPORTED for it. */
+#define GED_DB_DIRECTED 1u
+#define GED_DIRECTED_MAX_ORDER 256
+
+/* ged_db_create with flags (0 or GED_DB_DIRECTED).  Errors as ged_db_create;
+ * GED_EINVAL also for unknown flag bits. */
+ged_status ged_db_create_ex(const ged_graph *graphs, int64_t count, uint32_t flags, ged_db **out);
+/* The flags the database was created with. */
+ged_status ged_db_flags(const ged_db *db, uint32_t *flags);
 ged_status ged_db_destroy(ged_db *db);
 ged_status ged_db_count(const ged_db *db, int64_t *count);
 ged_status ged_db_device_bytes(const ged_db *db, int64_t *bytes);
@@ -282,6 +302,9 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
  *      g2 edge, else GED_OP_EDEL (c = d = -1);
  *   4. per g2 edge {c, d}, c < d, in lexicographic order that is no g1 edge's
  *      image: GED_OP_EINS (a = b = -1).
+ * Directed database: steps 3 and 4 list every arc (a, b) in lexicographic
+ * order of (a, b), and a substituted arc's image is (c, d) = (map(a), map(b))
+ * as it stands.
  * cost is the operation's cost (0 for a substitution that keeps the label);
  * the costs of a pair sum to the edit cost of its mapping, i.e. to the
  * distance the search returned with it.

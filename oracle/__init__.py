@@ -246,21 +246,26 @@ def bipartite_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, wit
     return dist, maps[:total], off, solves
 
 
-def edit_path(g1, g2, costs: Sequence[int], mapping):
+def edit_path(g1, g2, costs: Sequence[int], mapping, directed: bool = False):
     """The explicit edit operations of a complete mapping (Sec. 2.2-2.4), plain
     Python: list of (kind, a, b, c, d, cost) with kind 0..5 = vertex substitution,
     vertex deletion, vertex insertion, edge substitution, edge deletion, edge
     insertion, in the order: g1 vertices ascending (substituted or deleted),
     inserted g2 vertices ascending, g1 edges (a < b) lexicographically
     (substituted onto a g2 edge, or deleted), uncovered g2 edges (c < d)
-    lexicographically (inserted).  The costs sum to the mapping's edit cost."""
+    lexicographically (inserted).  The costs sum to the mapping's edit cost.
+    directed: edges are arcs (a, b), listed in lexicographic order of (a, b); a
+    substituted arc's image is (phi(a), phi(b)) as it stands."""
     vsub, vdel, vins, esub, edel, eins = (int(x) for x in costs)
     n1, n2 = int(g1.n), int(g2.n)
     phi = [int(x) for x in mapping]
 
+    def key(a, b):
+        return (a, b) if directed else (min(a, b), max(a, b))
+
     def edges(g):
         el = g.elabel if getattr(g, "elabel", None) is not None else [0] * len(g.eu)
-        return {(min(int(a), int(b)), max(int(a), int(b))): int(l) for a, b, l in zip(g.eu, g.ev, el)}
+        return {key(int(a), int(b)): int(l) for a, b, l in zip(g.eu, g.ev, el)}
 
     E1, E2 = edges(g1), edges(g2)
     pre = {}
@@ -279,13 +284,13 @@ def edit_path(g1, g2, costs: Sequence[int], mapping):
             ops.append((2, -1, u, -1, -1, vins))
     for (a, b) in sorted(E1):
         x, y = phi[a], phi[b]
-        key = (min(x, y), max(x, y))
-        if x >= 0 and y >= 0 and key in E2:
-            ops.append((3, a, b, key[0], key[1], esub if E1[(a, b)] != E2[key] else 0))
+        img = key(x, y)
+        if x >= 0 and y >= 0 and img in E2:
+            ops.append((3, a, b, img[0], img[1], esub if E1[(a, b)] != E2[img] else 0))
         else:
             ops.append((4, a, b, -1, -1, edel))
     for (c, d) in sorted(E2):
         a, b = pre.get(c, -1), pre.get(d, -1)
-        if not (a >= 0 and b >= 0 and (min(a, b), max(a, b)) in E1):
+        if not (a >= 0 and b >= 0 and key(a, b) in E1):
             ops.append((5, -1, -1, c, d, eins))
     return ops

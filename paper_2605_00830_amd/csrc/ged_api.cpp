@@ -54,25 +54,30 @@ ged_status check_device(const ged_db *db) {
 }
 
 
-ged_status check_graph_shape(const ged_graph &G, int64_t g) {
+ged_status check_graph_shape(const ged_graph &G, int64_t g, bool directed) {
     if (G.n < 0 || G.m < 0) return fail(GED_EINVAL, "graph %lld: negative n or m", (long long)g);
     if (G.n > GED_MAX_VERTICES)
         return fail(GED_EUNSUPPORTED, "graph %lld: n = %d exceeds %d", (long long)g, G.n, GED_MAX_VERTICES);
     if (G.n > 0 && !G.vlabel) return fail(GED_EINVAL, "graph %lld: vlabel is NULL", (long long)g);
     if (G.m > 0 && (!G.eu || !G.ev)) return fail(GED_EINVAL, "graph %lld: edge arrays are NULL", (long long)g);
-    if ((int64_t)G.m > (int64_t)G.n * (G.n - 1) / 2)
+    if ((int64_t)G.m > (int64_t)G.n * (G.n - 1) / (directed ? 1 : 2))
         return fail(GED_EINVAL, "graph %lld: more edges than a simple graph allows", (long long)g);
     return ok();
 }
 
-int64_t packed_words(int n, int planes) { return (int64_t)n * ((n + 31) / 32) * (1 + planes); }
+int64_t packed_words(int n, int planes, bool directed) {
+    return (int64_t)n * ((n + 31) / 32) * (1 + planes) * (directed ? 2 : 1);
+}
 
+// Undirected: row v holds the neighbours of v (both ends of every edge set).
+// Directed: the first block's row v holds the heads of v's out-arcs, a second
+// block of the same shape (rows, then planes) the tails of its in-arcs.
 ged_status pack_graph(const ged_graph &G, int64_t g, const std::vector<int32_t> &labels, int planes,
-                      std::vector<uint32_t> &adj, std::vector<int32_t> &vlab, gedk::GraphRec &R) {
+                      std::vector<uint32_t> &adj, std::vector<int32_t> &vlab, gedk::GraphRec &R, bool directed) {
     const int n = G.n, w = (n + 31) / 32;
     const size_t base = adj.size();
     const size_t plane = (size_t)n * w;
-    adj.resize(base + plane * (1 + planes), 0u);
+    adj.resize(base + plane * (1 + planes) * (directed ? 2 : 1), 0u);
     R.n = n;
     R.m = G.m;
     R.w = w;
@@ -80,15 +85,16 @@ ged_status pack_graph(const ged_graph &G, int64_t g, const std::vector<int32_t> 
     R.adj = (int64_t)base;
     R.vlab = (int64_t)vlab.size();
     uint32_t *rows = adj.data() + base;
+    uint32_t *rev = directed ? rows + plane * (1 + planes) : rows;   // where b's row gets a
     for (int k = 0; k < G.m; ++k) {
         const int a = G.eu[k], b = G.ev[k];
         if (a < 0 || b < 0 || a >= n || b >= n)
             return fail(GED_EINVAL, "graph %lld: edge %d has a vertex out of range", (long long)g, k);
         if (a == b) return fail(GED_EINVAL, "graph %lld: edge %d is a self-loop", (long long)g, k);
         if (rows[(size_t)a * w + (b >> 5)] & (1u << (b & 31)))
-            return fail(GED_EINVAL, "graph %lld: edge %d repeats {%d,%d}", (long long)g, k, a, b);
+            return fail(GED_EINVAL, "graph %lld: edge %d repeats (%d,%d)", (long long)g, k, a, b);
         rows[(size_t)a * w + (b >> 5)] |= 1u << (b & 31);
-        rows[(size_t)b * w + (a >> 5)] |= 1u << (a & 31);
+        rev[(size_t)b * w + (a >> 5)] |= 1u << (a & 31);
         const int32_t lab = G.elabel ? G.elabel[k] : 0;
         const auto it = std::lower_bound(labels.begin(), labels.end(), lab);
         if (it == labels.end() || *it != lab)
@@ -96,9 +102,8 @@ ged_status pack_graph(const ged_graph &G, int64_t g, const std::vector<int32_t> 
         const int code = (int)(it - labels.begin());
         for (int p = 0; p < planes; ++p) {
             if ((code >> p) & 1) {
-                uint32_t *pl = rows + (size_t)(1 + p) * plane;
-                pl[(size_t)a * w + (b >> 5)] |= 1u << (b & 31);
-                pl[(size_t)b * w + (a >> 5)] |= 1u << (a & 31);
+                rows[(size_t)(1 + p) * plane + (size_t)a * w + (b >> 5)] |= 1u << (b & 31);
+                rev[(size_t)(1 + p) * plane + (size_t)b * w + (a >> 5)] |= 1u << (a & 31);
             }
         }
     }
@@ -150,8 +155,14 @@ const char *ged_status_name(int32_t s) {
 }
 
 ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out) {
+    return ged_db_create_ex(graphs, count, 0u, out);
+}
+
+ged_status ged_db_create_ex(const ged_graph *graphs, int64_t count, uint32_t flags, ged_db **out) {
     if (!out) return fail(GED_EINVAL, "out is NULL");
     *out = nullptr;
+    if (flags & ~(uint32_t)GED_DB_DIRECTED) return fail(GED_EINVAL, "unknown database flags 0x%x", flags);
+    const bool directed = (flags & GED_DB_DIRECTED) != 0;
     if (count < 0) return fail(GED_EINVAL, "count < 0");
     if (count > 0 && !graphs) return fail(GED_EINVAL, "graphs is NULL");
     if (count > (int64_t)std::numeric_limits<int32_t>::max())
@@ -161,7 +172,7 @@ ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out) {
     std::vector<int32_t> labels;
     int64_t total_words = 0, total_v = 0;
     for (int64_t g = 0; g < count; ++g) {
-        ged_status st = gedh::check_graph_shape(graphs[g], g);
+        ged_status st = gedh::check_graph_shape(graphs[g], g, directed);
         if (st != GED_OK) return st;
         const ged_graph &G = graphs[g];
         if (G.elabel)
@@ -177,12 +188,13 @@ ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out) {
                     GED_MAX_EDGE_LABELS);
     int planes = 0;
     while ((1 << planes) < (int)labels.size()) ++planes;
-    for (int64_t g = 0; g < count; ++g) total_words += gedh::packed_words(graphs[g].n, planes);
+    for (int64_t g = 0; g < count; ++g) total_words += gedh::packed_words(graphs[g].n, planes, directed);
 
     ged_db *db = new (std::nothrow) ged_db;
     if (!db) return fail(GED_ENOMEM, "host allocation failed");
     db->count = count;
     db->planes = planes;
+    db->directed = directed;
     db->elabels = labels;
     db->h_graphs.resize((size_t)count);
 
@@ -192,7 +204,8 @@ ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out) {
     adj.reserve((size_t)std::max<int64_t>(total_words, 1));
     vlab.reserve((size_t)std::max<int64_t>(total_v, 1));
     for (int64_t g = 0; g < count; ++g) {
-        ged_status st = gedh::pack_graph(graphs[g], g, labels, planes, adj, vlab, db->h_graphs[(size_t)g]);
+        ged_status st =
+            gedh::pack_graph(graphs[g], g, labels, planes, adj, vlab, db->h_graphs[(size_t)g], directed);
         if (st != GED_OK) {
             free_db(db);
             return st;
@@ -246,6 +259,12 @@ ged_status ged_db_count(const ged_db *db, int64_t *count) {
 ged_status ged_db_device_bytes(const ged_db *db, int64_t *bytes) {
     if (!db || !bytes) return fail(GED_EINVAL, "NULL argument");
     *bytes = db->bytes;
+    return ok();
+}
+
+ged_status ged_db_flags(const ged_db *db, uint32_t *flags) {
+    if (!db || !flags) return fail(GED_EINVAL, "NULL argument");
+    *flags = db->directed ? (uint32_t)GED_DB_DIRECTED : 0u;
     return ok();
 }
 

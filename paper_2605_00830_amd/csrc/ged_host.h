@@ -26,15 +26,17 @@ inline ged_status ok() { return GED_OK; }
 ged_status check_costs(const ged_costs &c);
 
 // Shape checks of one host graph (index g for messages), host-only.
-ged_status check_graph_shape(const ged_graph &G, int64_t g);
-// Words of the packed adjacency (rows plus label planes) of an n-vertex graph.
-int64_t packed_words(int n, int planes);
+ged_status check_graph_shape(const ged_graph &G, int64_t g, bool directed = false);
+// Words of the packed adjacency (rows plus label planes; twice that for a
+// directed graph, whose in-arc rows and planes follow) of an n-vertex graph.
+int64_t packed_words(int n, int planes, bool directed = false);
 // Append graph G's packed rows, label planes and vertex labels to adj/vlab
 // and describe them in R (offsets into adj/vlab).  `labels` is the sorted
 // table of edge labels whose index is the label code; a label missing from
 // it, a vertex out of range, a self-loop or a repeated edge is GED_EINVAL.
 ged_status pack_graph(const ged_graph &G, int64_t g, const std::vector<int32_t> &labels, int planes,
-                      std::vector<uint32_t> &adj, std::vector<int32_t> &vlab, gedk::GraphRec &R);
+                      std::vector<uint32_t> &adj, std::vector<int32_t> &vlab, gedk::GraphRec &R,
+                      bool directed = false);
 
 // Order the first `grid` items of a longest-first work list (the pairs the
 // workgroups of a persistent launch take statically, workgroup b taking item
@@ -61,6 +63,7 @@ struct ged_db {
     int device = 0;
     int64_t count = 0;
     int32_t planes = 0;
+    bool directed = false;          // arcs; rows then in-arc rows per graph
     std::vector<int32_t> elabels;   // sorted distinct edge labels; index = label code
     std::vector<gedk::GraphRec> h_graphs;
     gedk::GraphRec *d_graphs = nullptr;

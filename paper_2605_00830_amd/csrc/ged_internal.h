@@ -23,6 +23,7 @@ struct BlockShape {
     int nmax1;   // largest source order in the bin
     int nmax2;   // largest target order in the bin
     int BT;      // threads per workgroup: kBlockThreads or kBlockThreadsWide
+    int directed = 0;   // directed database: W covers an out-row and an in-row
 };
 
 // Slot stride of the workgroup kernel for beam width K and `threads` per
@@ -59,9 +60,10 @@ hipError_t launch_bip(int PL, int cpl, int nwav, const DbView &src, const DbView
                       int nwork, int *queue, Costs c, int K, void *ws, Outputs out, int grid, hipStream_t stream);
 
 // Edit-path output (kb_path.hip): one workgroup per pair; cap_off[out] is
-// the pair's first operation slot.
+// the pair's first operation slot; directed: the view's rows hold out-arcs.
 hipError_t launch_path(const DbView &view, const WorkItem *work, const int64_t *cap_off, int nwork, Costs c,
-                       const int32_t *map, ged_edit_op *ops, int32_t *count, int grid, hipStream_t stream);
+                       const int32_t *map, ged_edit_op *ops, int32_t *count, int directed, int grid,
+                       hipStream_t stream);
 
 // Whole-device search of one pair at large K (kb_wide.hip).
 constexpr int kWideMaxK = GED_MAX_K_WIDE;

@@ -90,7 +90,8 @@ ged_status ged_edit_path(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ge
         const int grid = (int)std::min<int64_t>(npairs, (int64_t)cus * 8);
         const gedk::DbView view{db->d_graphs, db->d_adj, db->d_vlab, db->planes};
         const gedk::Costs c{costs.vsub, costs.vdel, costs.vins, costs.esub, costs.edel, costs.eins};
-        e = gedk::launch_path(view, d_work, d_cap, (int)npairs, c, d_map, d_ops, d_count, grid, s);
+        e = gedk::launch_path(view, d_work, d_cap, (int)npairs, c, d_map, d_ops, d_count, db->directed ? 1 : 0, grid,
+                              s);
     }
     std::vector<int32_t> h_count((size_t)npairs);
     if (e == hipSuccess)

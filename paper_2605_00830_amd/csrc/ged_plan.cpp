@@ -292,8 +292,8 @@ std::string bin_key(const std::string &dev, int K, int last_complete, const Bin 
     int lg = 0;
     while ((1ll << (lg + 1)) <= (long long)b.h_work.size()) ++lg;
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|K%d%s%s|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, last_complete ? "c" : "",
-             b.bip ? "bip" : "", b.bip ? b.bip_cpl : (b.wave_ok ? b.wave_words : 0), b.shape.W, b.shape.PL,
+    snprintf(buf, sizeof buf, "%s|K%d%s%s%s|w%d|W%d|PL%d|n%d|m%d|p2^%d", dev.c_str(), K, last_complete ? "c" : "",
+             b.bip ? "bip" : "", b.shape.directed ? "dir" : "", b.bip ? b.bip_cpl : (b.wave_ok ? b.wave_words : 0), b.shape.W, b.shape.PL,
              b.shape.nmax1, b.shape.nmax2, lg);
     return buf;
 }
@@ -353,6 +353,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     if (K > GED_MAX_K) return fail(GED_EUNSUPPORTED, "K = %d exceeds %d", K, GED_MAX_K);
     if (bip && K > GED_BIP_MAX_K)
         return fail(GED_EUNSUPPORTED, "K = %d exceeds the bipartite method's %d", K, GED_BIP_MAX_K);
+    if (bip && db->directed) return fail(GED_EUNSUPPORTED, "the bipartite method takes undirected graphs only");
     ged_status st = gedh::check_device(db);
     if (st != GED_OK) return st;
 
@@ -369,7 +370,8 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     // bins keyed by kernel: -1 / -2 = wavefront kernel for n <= 32 / 64,
     // -3 .. -6 = bipartite kernel with 1 .. 4 columns per lane, else target
     // row words rounded up to a power of two (the workgroup kernel's
-    // instantiation)
+    // instantiation; twice that for a directed database, whose rows hold the
+    // out-arcs and the in-arcs: only the workgroup kernel takes those)
     const int PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     std::map<int, Bin> bins;
     int64_t off = 0;
@@ -383,14 +385,20 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const GraphRec &g2 = db->h_graphs[(size_t)d];
         p->pair_n[(size_t)i] = (int64_t)g1.n + g2.n;
         p->pair_m[(size_t)i] = (int64_t)g1.m + g2.m;
+        if (db->directed && std::max(g1.n, g2.n) > GED_DIRECTED_MAX_ORDER) {
+            free_plan(p);
+            return fail(GED_EUNSUPPORTED, "pair %lld: directed graphs of more than %d vertices", (long long)i,
+                        GED_DIRECTED_MAX_ORDER);
+        }
         if (bip && g1.n + g2.n > GED_BIP_MAX_ORDER) {
             free_plan(p);
             return fail(GED_EUNSUPPORTED, "pair %lld: n1 + n2 = %d exceeds the bipartite method's %d", (long long)i,
                         g1.n + g2.n, GED_BIP_MAX_ORDER);
         }
-        const int ww = (!bip && opt.schedule == GED_SCHED_AUTO) ? gedk::wave_words_for(g1.n, g2.n, K) : 0;
+        const int ww = (!bip && !db->directed && opt.schedule == GED_SCHED_AUTO) ? gedk::wave_words_for(g1.n, g2.n, K)
+                                                                                    : 0;
         const bool wave = ww > 0;
-        const int W = pow2_at_least(std::max(1, g2.w));
+        const int W = pow2_at_least(std::max(1, g2.w)) * (db->directed ? 2 : 1);
         const int cpl = bip ? gedk::bip_cols_per_lane(g1.n + g2.n) : 0;
         Bin &b = bins[bip ? -2 - cpl : (wave ? -ww : W)];
         b.bip = bip;
@@ -400,6 +408,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         b.wave_words = ww;
         b.shape.W = W;
         b.shape.PL = PL;
+        b.shape.directed = db->directed ? 1 : 0;
         b.shape.nmax1 = std::max(b.shape.nmax1, g1.n);
         b.shape.nmax2 = std::max(b.shape.nmax2, g2.n);
         WorkItem wi;

@@ -449,6 +449,7 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     if (!out) return fail(GED_EINVAL, "out is NULL");
     *out = nullptr;
     if (!db || !config) return fail(GED_EINVAL, "NULL argument");
+    if (db->directed) return fail(GED_EUNSUPPORTED, "the server takes undirected graphs only");
     ged_server_config cfg = *config;
     if (cfg.K < 1) return fail(GED_EINVAL, "K must be >= 1 (got %d)", cfg.K);
     if (cfg.K > GED_MAX_K) return fail(GED_EUNSUPPORTED, "K = %d exceeds %d", cfg.K, GED_MAX_K);

@@ -41,6 +41,7 @@ ged_status ged_wide_create_ex(ged_db *db, int64_t src, int64_t dst, int32_t K, c
     if (!db) return fail(GED_EINVAL, "db is NULL");
     if (src < 0 || src >= db->count || dst < 0 || dst >= db->count)
         return fail(GED_EINVAL, "graph id out of range");
+    if (db->directed) return fail(GED_EUNSUPPORTED, "the single-pair search takes undirected graphs only");
     if (K < 1 || K > GED_MAX_K_WIDE) return fail(GED_EINVAL, "K must be in 1..%d (got %d)", GED_MAX_K_WIDE, K);
     ged_status st = gedh::check_device(db);
     if (st != GED_OK) return st;

@@ -39,6 +39,15 @@
 // the per-block global workspace as cand[c][s] (consecutive slots coalesce).
 // Beam state per slot in the workspace (slot-minor): PED, |Img|, g2 edges
 // inside Img, Img bitset, mapping phi[j] (uint16, 0xffff = deleted).
+//
+// Directed graphs (each edge an arc, one edit operation per arc): the
+// database holds a second block of rows and planes after the first, row v of
+// it the in-arcs of v.  Here a vertex's row is its out-row in words
+// [0, W/2) followed by its in-row in words [W/2, W), the image bitset holds
+// Img in both halves, and an earlier neighbour of v_i reached by an in-arc
+// sets its Phi bit in the upper half.  The same popcounts then count kept,
+// deleted, inserted and relabelled arcs of both directions at once: the
+// implied operations of Sec. 2.3 taken for each arc direction.
 #include "ged_internal.h"
 
 namespace gedk {
@@ -154,7 +163,7 @@ __device__ __forceinline__ uint32_t below_mask(int i, int kw) {
     return rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
 }
 
-template <int W, int PL, bool CL, int BT>
+template <int W, int PL, bool CL, int BT, bool DIR>
 __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     constexpr int NW = BT / 64;
@@ -188,6 +197,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     const int K = a.K;
     const Costs c = a.c;
     const int P = a.dst.planes;
+    constexpr int DH = DIR ? W / 2 : 0;   // first word of the in-half (directed)
+    static_assert(!DIR || W >= 2, "a directed row has two halves");
 
     for (bool first = true;; first = false) {
         // the first pair is the workgroup's own index; later ones come from
@@ -211,6 +222,9 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
         const int *L1 = a.src.vlab + g1.vlab;
         const int *L2 = a.dst.vlab + g2.vlab;
         const size_t pl1 = (size_t)n1 * w1, pl2 = (size_t)n2 * w2;
+        // directed: the in-arc rows and planes follow the out-arc ones
+        const uint32_t *A1in = A1 + (size_t)(1 + a.src.planes) * pl1;
+        const uint32_t *A2in = A2 + (size_t)(1 + P) * pl2;
         const int nc = n2 + 1;                       // children per slot (deletion = n2)
         const int CST = nc | 1;                      // LDS row stride of the candidate matrix
         const int chunk = (nc + TPS - 1) / TPS;      // children per part
@@ -218,13 +232,17 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
 
         for (int x = t; x < n2 * W; x += BT) {
             const int u = x / W, kk = x % W;
-            s_rows[x] = kk < w2 ? A2[(size_t)u * w2 + kk] : 0u;
+            const bool hi = DH > 0 && kk >= DH;
+            const int kr = hi ? kk - DH : kk;
+            s_rows[x] = kr < w2 ? (hi ? A2in : A2)[(size_t)u * w2 + kr] : 0u;
         }
         if (PL > 0 && a.planes_lds) {
             for (int x = t; x < PL * n2 * W; x += BT) {
                 const int b = x / (n2 * W), r = x % (n2 * W), u = r / W, kk = r % W;
+                const bool hi = DH > 0 && kk >= DH;
+                const int kr = hi ? kk - DH : kk;
                 s_planes[(size_t)b * a.rows_words + r] =
-                    (b < P && kk < w2) ? A2[(size_t)(1 + b) * pl2 + (size_t)u * w2 + kk] : 0u;
+                    (b < P && kr < w2) ? (hi ? A2in : A2)[(size_t)(1 + b) * pl2 + (size_t)u * w2 + kr] : 0u;
             }
         }
         if (t == 0) {
@@ -242,27 +260,34 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             const int lab1 = L1[i];
             int degP = 0;
             for (int kw = 0; kw * 32 < i; ++kw) degP += __popc(A1[(size_t)i * w1 + kw] & below_mask(i, kw));
+            if (DH > 0)
+                for (int kw = 0; kw * 32 < i; ++kw) degP += __popc(A1in[(size_t)i * w1 + kw] & below_mask(i, kw));
             const int del_cost = c.vdel + c.edel * degP;
             const bool coop = TPS > 1 && degP >= 2 * TPS;   // split the Phi lookups over a slot's parts
             // the earlier neighbours of v_i (the same for every slot), in index
-            // order, with their edge-label codes: listed once per level by wave 0
+            // order, with their edge-label codes: listed once per level by wave 0.
+            // Directed: the out-arc neighbours, then the in-arc ones with bit 15 set.
             if (t < 64) {
                 int base = 0;
-                for (int kw = 0; kw * 32 < i; ++kw) {
-                    const uint32_t bits = A1[(size_t)i * w1 + kw] & below_mask(i, kw);
-                    const bool mine = t < 32 && ((bits >> t) & 1u);
-                    const unsigned long long m = __ballot(mine);
-                    if (mine) {
-                        const int rank = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                                        __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                        int code = 0;
+                for (int dir = 0; dir < (DH > 0 ? 2 : 1); ++dir) {
+                    const uint32_t *R1 = dir ? A1in : A1;
+                    for (int kw = 0; kw * 32 < i; ++kw) {
+                        const uint32_t bits = R1[(size_t)i * w1 + kw] & below_mask(i, kw);
+                        const bool mine = t < 32 && ((bits >> t) & 1u);
+                        const unsigned long long m = __ballot(mine);
+                        if (mine) {
+                            const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+                                (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                            int code = 0;
 #pragma unroll
-                        for (int b = 0; b < PLA; ++b)
-                            if (PL > 0 && b < P) code |= (int)((A1[(size_t)(1 + b) * pl1 + (size_t)i * w1 + kw] >> t) & 1u) << b;
-                        s_nbr[base + rank] = (uint16_t)(kw * 32 + t);
-                        s_nbl[base + rank] = (uint8_t)code;
+                            for (int b = 0; b < PLA; ++b)
+                                if (PL > 0 && b < P)
+                                    code |= (int)((R1[(size_t)(1 + b) * pl1 + (size_t)i * w1 + kw] >> t) & 1u) << b;
+                            s_nbr[base + rank] = (uint16_t)((kw * 32 + t) | (dir << 15));
+                            s_nbl[base + rank] = (uint8_t)code;
+                        }
+                        base += __popcll(m);
                     }
-                    base += __popcll(m);
                 }
             }
 
@@ -300,10 +325,11 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 // the parts of a slot are adjacent lanes of one wave
 #pragma unroll 8
                 for (int q = coop ? part : 0; q < degP; q += coop ? TPS : 1) {
-                    const int x = phic[(size_t)s_nbr[q] * KS + s];
+                    const int nq = s_nbr[q];
+                    const int x = phic[(size_t)(nq & 0x7fff) * KS + s];
                     if (x != PHI_DEL) {
                         const uint32_t bit = 1u << (x & 31);
-                        const int xw = x >> 5;
+                        const int xw = (x >> 5) + ((nq >> 15) ? DH : 0);
                         const int code = PL > 0 ? s_nbl[q] : 0;
 #pragma unroll
                         for (int k = 0; k < W; ++k) {
@@ -356,10 +382,15 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
 #pragma unroll
                                 for (int bb = 0; bb < PLA; ++bb)
                                     diff |= phib[bb][kk] ^ s_planes[(size_t)bb * a.rows_words + u * W + kk];
-                            } else if (kk < w2) {
+                            } else {
+                                const bool hi = DH > 0 && kk >= DH;
+                                const int kr = hi ? kk - DH : kk;
+                                if (kr < w2) {
+                                    const uint32_t *B = hi ? A2in : A2;
 #pragma unroll
-                                for (int bb = 0; bb < PLA; ++bb)
-                                    if (bb < P) diff |= phib[bb][kk] ^ A2[(size_t)(1 + bb) * pl2 + (size_t)u * w2 + kk];
+                                    for (int bb = 0; bb < PLA; ++bb)
+                                        if (bb < P) diff |= phib[bb][kk] ^ B[(size_t)(1 + bb) * pl2 + (size_t)u * w2 + kr];
+                                }
                             }
                             relab += __popc(both & diff);
                         }
@@ -566,7 +597,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                         const uint32_t ip = imgc[(size_t)k * KS + p];
                         const uint32_t row = sub ? s_rows[u * W + k] : 0u;
                         add_e += __popc(ip & row);
-                        imgn[(size_t)k * KS + s2] = ip | ((sub && (u >> 5) == k) ? (1u << (u & 31)) : 0u);
+                        const bool at = (u >> 5) == k || (DH > 0 && (u >> 5) + DH == k);
+                        imgn[(size_t)k * KS + s2] = ip | ((sub && at) ? (1u << (u & 31)) : 0u);
                     }
                     pedn[s2] = s_selped[s2];
                     einn[s2] = einc[p] + add_e;
@@ -660,19 +692,24 @@ size_t dyn_lds_bytes(const BlockShape &s) {
     return b;
 }
 
-template <int W, int PL, bool CL, int BT>
+template <int W, int PL, bool CL, int BT, bool DIR>
 const void *kernel_ptr() {
-    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL, CL, BT>);
+    return reinterpret_cast<const void *>(&kb_block_kernel<W, PL, CL, BT, DIR>);
 }
 
-const void *select_kernel(int W, int PL, bool CL, int BT) {
-#define GEDK_CASE(w, pl, cl, bt) \
-    if (W == w && PL == pl && CL == cl && BT == bt) return kernel_ptr<w, pl, cl, bt>();
-#define GEDK_ROW(w, cl, bt) GEDK_CASE(w, 0, cl, bt) GEDK_CASE(w, 2, cl, bt) GEDK_CASE(w, 4, cl, bt)
-#define GEDK_ALL(bt)                                                                              \
-    GEDK_ROW(1, true, bt) GEDK_ROW(2, true, bt) GEDK_ROW(4, true, bt) GEDK_ROW(8, true, bt)     \
-    GEDK_ROW(16, true, bt) GEDK_ROW(1, false, bt) GEDK_ROW(2, false, bt) GEDK_ROW(4, false, bt) \
-    GEDK_ROW(8, false, bt) GEDK_ROW(16, false, bt)
+// Directed instantiations exist for W = 2 .. 16 (graphs of up to 256
+// vertices: out-row and in-row of 8 words each).
+const void *select_kernel(int W, int PL, bool CL, int BT, bool DIR) {
+#define GEDK_CASE(w, pl, cl, bt, d) \
+    if (W == w && PL == pl && CL == cl && BT == bt && DIR == d) return kernel_ptr<w, pl, cl, bt, d>();
+#define GEDK_ROW(w, cl, bt, d) GEDK_CASE(w, 0, cl, bt, d) GEDK_CASE(w, 2, cl, bt, d) GEDK_CASE(w, 4, cl, bt, d)
+#define GEDK_ALL(bt)                                                                                        \
+    GEDK_ROW(1, true, bt, false) GEDK_ROW(2, true, bt, false) GEDK_ROW(4, true, bt, false)                  \
+    GEDK_ROW(8, true, bt, false) GEDK_ROW(16, true, bt, false) GEDK_ROW(1, false, bt, false)                \
+    GEDK_ROW(2, false, bt, false) GEDK_ROW(4, false, bt, false) GEDK_ROW(8, false, bt, false)               \
+    GEDK_ROW(16, false, bt, false) GEDK_ROW(2, true, bt, true) GEDK_ROW(4, true, bt, true)                   \
+    GEDK_ROW(8, true, bt, true) GEDK_ROW(16, true, bt, true) GEDK_ROW(2, false, bt, true)                   \
+    GEDK_ROW(4, false, bt, true) GEDK_ROW(8, false, bt, true) GEDK_ROW(16, false, bt, true)
     GEDK_ALL(256)
     GEDK_ALL(512)
 #undef GEDK_ALL
@@ -693,7 +730,7 @@ int block_slot_stride(int K, int threads) {
 size_t block_workspace_bytes(const BlockShape &s) { return layout_for(s).stride; }
 
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
-    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT);
+    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT, s.directed != 0);
     if (!k) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, s.BT, dyn_lds_bytes(s));
 }
@@ -701,7 +738,7 @@ hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
 hipError_t launch_block(const BlockShape &s, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
                         int *queue, Costs c, int K, int last_complete, void *workspace, size_t ws_stride,
                         Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT);
+    const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT, s.directed != 0);
     if (!k || grid <= 0 || s.KS != block_slot_stride(K, s.BT)) return hipErrorInvalidValue;
     BlockArgs a;
     a.src = src;

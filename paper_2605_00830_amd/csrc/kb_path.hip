@@ -13,6 +13,8 @@
 // costs sum to the mapping's edit cost.  Thread t owns vertices 2t and 2t+1
 // of each phase; a block exclusive scan of their operation counts places
 // every operation.
+// Directed graphs: phases 3 and 4 walk every arc (x, y) of the out-rows in
+// lexicographic order, a substituted arc's image being (phi(x), phi(y)).
 #include <hip/hip_runtime.h>
 
 #include "ged.h"
@@ -36,6 +38,7 @@ struct PathArgs {
     const int32_t *map;
     ged_edit_op *ops;
     int32_t *count;         // operations written per pair; -1 for an invalid mapping
+    int directed;           // rows hold out-arcs; every arc is listed
 };
 
 __device__ __forceinline__ uint32_t row_word(const uint32_t *A, int w, int x, int y) {
@@ -48,6 +51,13 @@ __device__ __forceinline__ int edge_code(const uint32_t *A, int n, int w, int P,
     int code = 0;
     for (int pl = 0; pl < P; ++pl) code |= (int)has_edge(A + (size_t)(1 + pl) * n * w, w, x, y) << pl;
     return code;
+}
+
+// the part of row word wd of vertex x the phases list: the bits above x
+// (undirected: each edge once), or all of them (directed: rows hold out-arcs)
+__device__ __forceinline__ uint32_t listed(uint32_t r, int wd, int x, int directed) {
+    if (directed) return r;
+    return r & (wd * 32 + 31 <= x ? 0u : (wd * 32 > x ? ~0u : ~((2u << (x & 31)) - 1u)));
 }
 
 // exclusive prefix of (v0 + v1) over the block's threads; *total = the sum
@@ -149,16 +159,8 @@ __global__ __launch_bounds__(kPathThreads) void kb_path_kernel(PathArgs a) {
         {
             int c0 = 0, c1 = 0;
             for (int wd = 0; wd < w1; ++wd) {
-                if (x0 < n1) {
-                    uint32_t r = A1[(size_t)x0 * w1 + wd];
-                    r &= wd * 32 + 31 <= x0 ? 0u : (wd * 32 > x0 ? ~0u : ~((2u << (x0 & 31)) - 1u));
-                    c0 += __popc(r);
-                }
-                if (x1 < n1) {
-                    uint32_t r = A1[(size_t)x1 * w1 + wd];
-                    r &= wd * 32 + 31 <= x1 ? 0u : (wd * 32 > x1 ? ~0u : ~((2u << (x1 & 31)) - 1u));
-                    c1 += __popc(r);
-                }
+                if (x0 < n1) c0 += __popc(listed(A1[(size_t)x0 * w1 + wd], wd, x0, a.directed));
+                if (x1 < n1) c1 += __popc(listed(A1[(size_t)x1 * w1 + wd], wd, x1, a.directed));
             }
             int m1 = 0;
             int pos = base + block_excl_scan(c0 + c1, s_wave, &m1);
@@ -167,8 +169,7 @@ __global__ __launch_bounds__(kPathThreads) void kb_path_kernel(PathArgs a) {
                 if (x >= n1) continue;
                 const int fx = s_phi[x];
                 for (int wd = 0; wd < w1; ++wd) {
-                    uint32_t r = A1[(size_t)x * w1 + wd];
-                    r &= wd * 32 + 31 <= x ? 0u : (wd * 32 > x ? ~0u : ~((2u << (x & 31)) - 1u));
+                    uint32_t r = listed(A1[(size_t)x * w1 + wd], wd, x, a.directed);
                     while (r) {
                         const int y = 32 * wd + __builtin_ctz(r);
                         r &= r - 1u;
@@ -178,8 +179,8 @@ __global__ __launch_bounds__(kPathThreads) void kb_path_kernel(PathArgs a) {
                         op.b = y;
                         if (fx >= 0 && fy >= 0 && has_edge(A2, w2, fx, fy)) {
                             op.kind = GED_OP_ESUB;
-                            op.c = min(fx, fy);
-                            op.d = max(fx, fy);
+                            op.c = a.directed ? fx : min(fx, fy);
+                            op.d = a.directed ? fy : max(fx, fy);
                             op.cost = edge_code(A1, n1, w1, P, x, y) != edge_code(A2, n2, w2, P, fx, fy) ? a.c.esub : 0;
                         } else {
                             op.kind = GED_OP_EDEL;
@@ -206,8 +207,7 @@ __global__ __launch_bounds__(kPathThreads) void kb_path_kernel(PathArgs a) {
                 if (x >= n2) continue;
                 int cnt = 0;
                 for (int wd = 0; wd < w2; ++wd) {
-                    uint32_t r = A2[(size_t)x * w2 + wd];
-                    r &= wd * 32 + 31 <= x ? 0u : (wd * 32 > x ? ~0u : ~((2u << (x & 31)) - 1u));
+                    uint32_t r = listed(A2[(size_t)x * w2 + wd], wd, x, a.directed);
                     while (r) {
                         const int y = 32 * wd + __builtin_ctz(r);
                         r &= r - 1u;
@@ -223,8 +223,7 @@ __global__ __launch_bounds__(kPathThreads) void kb_path_kernel(PathArgs a) {
                 const int x = h == 0 ? x0 : x1;
                 if (x >= n2) continue;
                 for (int wd = 0; wd < w2; ++wd) {
-                    uint32_t r = A2[(size_t)x * w2 + wd];
-                    r &= wd * 32 + 31 <= x ? 0u : (wd * 32 > x ? ~0u : ~((2u << (x & 31)) - 1u));
+                    uint32_t r = listed(A2[(size_t)x * w2 + wd], wd, x, a.directed);
                     while (r) {
                         const int y = 32 * wd + __builtin_ctz(r);
                         r &= r - 1u;
@@ -250,7 +249,8 @@ __global__ __launch_bounds__(kPathThreads) void kb_path_kernel(PathArgs a) {
 }  // namespace
 
 hipError_t launch_path(const DbView &view, const WorkItem *work, const int64_t *cap_off, int nwork, Costs c,
-                       const int32_t *map, ged_edit_op *ops, int32_t *count, int grid, hipStream_t stream) {
+                       const int32_t *map, ged_edit_op *ops, int32_t *count, int directed, int grid,
+                       hipStream_t stream) {
     if (grid <= 0 || nwork <= 0) return nwork == 0 ? hipSuccess : hipErrorInvalidValue;
     PathArgs a;
     a.view = view;
@@ -261,6 +261,7 @@ hipError_t launch_path(const DbView &view, const WorkItem *work, const int64_t *
     a.map = map;
     a.ops = ops;
     a.count = count;
+    a.directed = directed;
     void *args[] = {&a};
     return hipLaunchKernel(reinterpret_cast<const void *>(&kb_path_kernel), dim3(grid), dim3(kPathThreads), args,
                            0, stream);

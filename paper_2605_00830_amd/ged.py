@@ -35,6 +35,8 @@ SCHED_AUTO, SCHED_BLOCK = 0, 1
 LAST_SELECT, LAST_COMPLETE = 0, 1
 METHOD_TREE, METHOD_BIPARTITE = 0, 1
 BIP_MAX_ORDER, BIP_MAX_K = 256, 256
+DB_DIRECTED = 1                 # ged_db_create_ex flag: edge k is the arc eu[k] -> ev[k]
+DIRECTED_MAX_ORDER = 256
 
 
 class PlanOptions(ctypes.Structure):
@@ -71,6 +73,7 @@ _lib = None
 EXPORTS = (
     "ged_abi_version", "ged_last_error", "ged_status_name",
     "ged_db_create", "ged_db_destroy", "ged_db_count", "ged_db_device_bytes", "ged_db_order",
+    "ged_db_create_ex", "ged_db_flags",
     "ged_plan_create", "ged_plan_map_size", "ged_plan_run", "ged_plan_run_perpair",
     "ged_plan_destroy", "ged_kbest", "ged_kbest_perpair",
     "ged_plan_set_timing", "ged_plan_kernel_ms", "ged_plan_kernel_launches",
@@ -98,6 +101,8 @@ def load(path: str = LIB_PATH):
         "ged_last_error": ([], ctypes.c_char_p),
         "ged_status_name": ([i32], ctypes.c_char_p),
         "ged_db_create": ([P, i64, P], i32),
+        "ged_db_create_ex": ([P, i64, ctypes.c_uint32, P], i32),
+        "ged_db_flags": ([P, P], i32),
         "ged_db_destroy": ([P], i32),
         "ged_db_count": ([P, P], i32),
         "ged_db_device_bytes": ([P, P], i32),
@@ -165,9 +170,10 @@ def _stream_handle(stream) -> int:
 
 
 class Database:
-    """A device-resident graph database (ged_db_create); `graphs` is a synth.GraphSet."""
+    """A device-resident graph database (ged_db_create_ex); `graphs` is a synth.GraphSet.
+    directed: every graph is directed, edge k being the arc eu[k] -> ev[k]."""
 
-    def __init__(self, graphs):
+    def __init__(self, graphs, directed: bool = False):
         lib = load()
         torch.cuda.init()
         count = len(graphs)
@@ -186,8 +192,10 @@ class Database:
         if el is not None:
             recs["elabel"][:count] = np.uint64(el.ctypes.data) + eoff * np.uint64(4)
         handle = ctypes.c_void_p()
-        _check(lib.ged_db_create(recs.ctypes.data, count, ctypes.byref(handle)))
+        _check(lib.ged_db_create_ex(recs.ctypes.data, count, DB_DIRECTED if directed else 0,
+                                    ctypes.byref(handle)))
         self._h = handle
+        self.directed = bool(directed)
         self.count = count
         self.n = np.asarray(graphs.n, dtype=np.int32).copy()
 

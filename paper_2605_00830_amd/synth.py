@@ -302,8 +302,8 @@ def batch_molecule_k64(npairs: int = 10000) -> Workload:
 
 def batch_directed_10_30(npairs: int = 4096) -> Workload:
     """npairs directed G(n, p) pairs, n ~ U{10..30}, p ~ U[0.05,0.15] per ordered pair (about the
-    arc count of batch_er_10_30's edges), 5 vertex labels, unit costs, K=64 (seed 6)."""
-    gs = GraphSet.from_graphs([directed_graph(6, i, 10, 30, 0.05, 0.15, 5) for i in range(2 * npairs)])
+    arc count of batch_er_10_30's edges), 5 vertex labels, unit costs, K=64 (seed 8)."""
+    gs = GraphSet.from_graphs([directed_graph(8, i, 10, 30, 0.05, 0.15, 5) for i in range(2 * npairs)])
     pairs = np.stack([np.arange(0, 2 * npairs, 2), np.arange(1, 2 * npairs, 2)], 1)
     return Workload(f"batch_directed_n10-30_p0.05-0.15_{npairs}pairs_k64", gs,
                     pairs.astype(np.int64), UNIT_COSTS, 64)

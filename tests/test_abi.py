@@ -29,14 +29,14 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_status_names():
     lib = ged.load()
-    assert lib.ged_abi_version() == 4
+    assert lib.ged_abi_version() == 5
     assert ged.status_name(ged.GED_OK) == "GED_OK"
     assert ged.status_name(ged.GED_EUNSUPPORTED) == "GED_EUNSUPPORTED"
     assert ged.status_name(99) == "GED_UNKNOWN"
 
 
-def _db_create(graph_tuples):
-    """Call ged_db_create on host graphs; returns (status, message)."""
+def _db_create(graph_tuples, flags=None):
+    """Call ged_db_create (ged_db_create_ex with flags) on host graphs; returns (status, message)."""
     lib = ged.load()
     keep = []
     recs = np.zeros(max(len(graph_tuples), 1), dtype=ged.GRAPH_DTYPE)
@@ -48,7 +48,10 @@ def _db_create(graph_tuples):
         for name, a in zip(("vlabel", "eu", "ev", "elabel"), arrs):
             recs[k][name] = 0 if a is None else a.ctypes.data
     h = ctypes.c_void_p()
-    st = lib.ged_db_create(recs.ctypes.data, len(graph_tuples), ctypes.byref(h))
+    if flags is None:
+        st = lib.ged_db_create(recs.ctypes.data, len(graph_tuples), ctypes.byref(h))
+    else:
+        st = lib.ged_db_create_ex(recs.ctypes.data, len(graph_tuples), flags, ctypes.byref(h))
     assert h.value is None  # nothing is returned on failure
     return st, lib.ged_last_error().decode()
 
@@ -65,6 +68,23 @@ def _db_create(graph_tuples):
 def test_db_create_rejects_invalid_graphs(case, status, text):
     st, msg = _db_create([case])
     assert st == status and text in msg
+
+
+@pytest.mark.parametrize("case,status,text", [
+    ((2, [0, 0], [0], [0], None), ged.GED_EINVAL, "self-loop"),
+    ((3, [0, 0, 0], [0, 1, 0], [1, 0, 1], None), ged.GED_EINVAL, "repeats"),
+    ((3, [0, 0, 0], [2], [3], None), ged.GED_EINVAL, "out of range"),
+    ((3, [0] * 3, [0, 0, 1, 1, 2, 2, 0], [1, 2, 0, 2, 0, 1, 1], None), ged.GED_EINVAL, "more edges"),
+])
+def test_directed_db_create_rejects_invalid_graphs(case, status, text):
+    """Directed: arcs a -> b and b -> a are distinct, a repeated arc is not."""
+    st, msg = _db_create([case], flags=ged.DB_DIRECTED)
+    assert st == status and text in msg
+
+
+def test_db_create_ex_rejects_unknown_flags():
+    st, msg = _db_create([(2, [0, 0], [0], [1], None)], flags=2)
+    assert st == ged.GED_EINVAL and "flags" in msg
 
 
 def test_db_create_rejects_too_many_edge_labels():

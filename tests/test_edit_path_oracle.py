@@ -2,7 +2,8 @@
 of small pairs the operation costs sum to the mapping's edit cost (the padded
 permutation brute force of tests/_pins.py), every vertex and edge of both graphs
 appears in exactly one operation, and replaying the operations on g1 rebuilds g2
-exactly (vertex and edge labels included)."""
+exactly (vertex and edge labels included).  The same holds for directed graphs,
+with arcs in place of edges."""
 import numpy as np
 import pytest
 
@@ -13,17 +14,19 @@ from tests import _pins
 COSTS = [synth.UNIT_COSTS, synth.PAPER_COSTS, (3, 2, 5, 9, 1, 2), (4, 12, 12, 1, 10, 10)]
 
 
-def labelled_edges(g):
+def labelled_edges(g, directed=False):
     el = g.elabel if getattr(g, "elabel", None) is not None else [0] * len(g.eu)
+    if directed:
+        return {(int(a), int(b)): int(l) for a, b, l in zip(g.eu, g.ev, el)}
     return {(min(int(a), int(b)), max(int(a), int(b))): int(l) for a, b, l in zip(g.eu, g.ev, el)}
 
 
-def replay(g1, g2, ops, costs):
+def replay(g1, g2, ops, costs, directed=False):
     """Apply the operations to g1; return the resulting labelled graph in g2's
     vertex names, and check that each element is touched exactly once and
     that each operation carries its own cost."""
-    E1 = labelled_edges(g1)
-    E2 = labelled_edges(g2)
+    E1 = labelled_edges(g1, directed)
+    E2 = labelled_edges(g2, directed)
     seen_v1, seen_v2, seen_e1, seen_e2 = set(), set(), set(), set()
     names = {}
     vlab = {}
@@ -59,7 +62,7 @@ def replay(g1, g2, ops, costs):
     out = {}
     for (a, b), l in edges.items():
         x, y = names[a], names[b]                # surviving g1 edges have both ends substituted
-        out[(min(x, y), max(x, y))] = l
+        out[(x, y) if directed else (min(x, y), max(x, y))] = l
     for kind, a, b, c, d, cost in ops:
         if kind == 5:
             out[(c, d)] = E2[(c, d)]
@@ -76,6 +79,21 @@ def test_every_mapping_of_small_pairs(costs):
             total = sum(op[5] for op in ops)
             assert total == _pins.qap_cost(g1, g2, costs, _pins.perm_from_map(mp, int(g1.n), int(g2.n)))
             vlab, edges = replay(g1, g2, ops, costs)
+            assert vlab == {u: int(g2.vlabel[u]) for u in range(int(g2.n))}
+            assert edges == E2
+
+
+@pytest.mark.parametrize("costs", COSTS)
+def test_every_mapping_of_small_directed_pairs(costs):
+    gs = [synth.directed_graph(105, k, 0, 4, 0.45, 0.45, 2, 3) for k in range(8)]
+    for g1, g2 in zip(gs[0::2], gs[1::2]):
+        E2 = labelled_edges(g2, True)
+        for mp in _pins.all_mappings(int(g1.n), int(g2.n)):
+            ops = oracle.edit_path(g1, g2, costs, mp, directed=True)
+            total = sum(op[5] for op in ops)
+            assert total == _pins.qap_cost(g1, g2, costs, _pins.perm_from_map(mp, int(g1.n), int(g2.n)),
+                                           directed=True)
+            vlab, edges = replay(g1, g2, ops, costs, directed=True)
             assert vlab == {u: int(g2.vlabel[u]) for u in range(int(g2.n))}
             assert edges == E2
 

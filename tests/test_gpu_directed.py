@@ -1,0 +1,207 @@
+"""Directed graphs (GED_DB_DIRECTED) through the workgroup kernel: distances
+and mappings equal the oracle's directed search bit for bit, for every row
+width (n up to 32, 64, 128, 256), no / two / four label planes (planes staged
+in LDS and read from HBM), the candidate matrix in LDS and in the workspace,
+256- and 512-thread workgroups, the complete-then-minimum last level and the
+one-launch-per-pair path; the calls that take undirected graphs only refuse
+a directed database (GPU)."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_00830_amd import synth
+from paper_2605_00830_amd.synth import Graph, GraphSet
+
+pytestmark = pytest.mark.gpu
+
+UNIT = synth.UNIT_COSTS
+PAPER = synth.PAPER_COSTS
+NONMETRIC = (3, 2, 5, 9, 1, 2)
+ASYM = (1, 1, 1, 7, 5, 3)
+
+
+@pytest.fixture(scope="module")
+def ged():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2605_00830_amd import ged as g
+    g.load()
+    return g
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def directed_set(seed, count, n_lo, n_hi, p_lo, p_hi, nl=4, nel=0):
+    return GraphSet.from_graphs([synth.directed_graph(seed, k, n_lo, n_hi, p_lo, p_hi, nl, nel)
+                                 for k in range(count)])
+
+
+def check(ged, graphs, pairs, costs, K, last_level=0, perpair=False, expect_words=None):
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    say(f"  case: {len(pairs)} pairs, K={K}, costs={costs}, last={last_level}, perpair={perpair}, "
+        f"n<={int(graphs.n.max())}")
+    db = ged.Database(graphs, directed=True)
+    plan = ged.Plan(db, pairs, K, last_level=last_level)
+    bins = plan.bins()
+    assert all(name == "kb_block_kernel" for name, *_ in bins), bins
+    if expect_words is not None:
+        assert {w for *_, w in bins} == expect_words, bins
+    plan.close()
+    res = ged.kbest(db, pairs, costs, K, perpair=perpair, last_level=last_level)
+    db.close()
+    d, m, off = oracle.kbest_pairs(graphs, pairs, costs, K, last_complete=last_level == 1, directed=True)
+    np.testing.assert_array_equal(res.offsets, off)
+    bad = np.nonzero(res.dist != d)[0]
+    assert bad.size == 0, (f"dist differs on pairs {bad[:8].tolist()}: gpu {res.dist[bad[:8]].tolist()} "
+                           f"oracle {d[bad[:8]].tolist()}")
+    np.testing.assert_array_equal(res.maps, m)
+    return res
+
+
+@pytest.mark.parametrize("costs", [UNIT, PAPER, NONMETRIC, ASYM])
+@pytest.mark.parametrize("K", [1, 8, 64])
+def test_small_directed_pairs(ged, costs, K):
+    """n 0..32 (two-word rows: out and in), unlabelled arcs, ragged orders incl. empty graphs."""
+    gs = directed_set(700, 40, 0, 32, 0.05, 0.4)
+    rng = np.random.default_rng(701)
+    pairs = rng.integers(0, 40, size=(150, 2))
+    check(ged, gs, pairs, costs, K, expect_words={2})
+
+
+@pytest.mark.parametrize("last_level", [0, 1])
+def test_labelled_arcs_two_and_four_planes(ged, last_level):
+    for nel, seed in ((3, 710), (12, 711)):
+        gs = directed_set(seed, 30, 5, 30, 0.1, 0.3, nl=3, nel=nel)
+        rng = np.random.default_rng(seed)
+        check(ged, gs, rng.integers(0, 30, size=(120, 2)), NONMETRIC, 16, last_level=last_level)
+
+
+@pytest.mark.parametrize("n_lo,n_hi,words,npairs", [(33, 64, 4, 40), (65, 128, 8, 30), (129, 200, 16, 12)])
+def test_row_widths(ged, n_lo, n_hi, words, npairs):
+    gs = directed_set(720 + words, 12, n_lo, n_hi, 0.02, 0.08, nl=5, nel=3)
+    pairs = [[a, b] for a in range(12) for b in range(12) if a != b][:npairs]
+    check(ged, gs, pairs, PAPER, 8, expect_words={words})
+
+
+def test_planes_from_hbm_and_candidates_in_workspace(ged):
+    """Targets of 230..256 vertices with 4 label planes: (1 + 4) planes of n2 x 16 words
+    exceed the LDS staging budget, so planes are read from HBM; K = 256 from a
+    20-vertex source puts the candidate matrix (256 slots x n2 + 1 children) in the
+    workspace."""
+    big = [synth.directed_graph(730, k, 230, 256, 0.01, 0.03, 4, 12) for k in range(3)]
+    small = [synth.directed_graph(731, 0, 20, 20, 0.1, 0.1, 4, 12)]
+    gs = GraphSet.from_graphs(big + small)
+    check(ged, gs, [[0, 1], [2, 0], [3, 2]], NONMETRIC, 4, expect_words={16})
+    check(ged, gs, [[3, 1], [3, 0]], UNIT, 256, expect_words={16})
+
+
+def test_batch_of_256_thread_workgroups_and_complete(ged):
+    """600 pairs (more than two per CU: 256-thread workgroups), both last levels."""
+    w = synth.batch_directed_10_30(600)
+    check(ged, w.graphs, w.pairs, w.costs, w.K)
+    check(ged, w.graphs, w.pairs[:200], w.costs, w.K, last_level=1)
+
+
+def test_perpair_path(ged):
+    w = synth.batch_directed_10_30(40)
+    check(ged, w.graphs, w.pairs, PAPER, 32, perpair=True)
+
+
+def test_two_cycles_and_reversed_arcs(ged):
+    """Hand cases: an arc against its reverse (distance 0 by swapping), a 2-cycle
+    against one arc, a path against a cycle."""
+    def dg(n, arcs, el=None):
+        return Graph(n, np.zeros(n, np.int32), np.asarray([a for a, _ in arcs], np.int32).reshape(-1),
+                     np.asarray([b for _, b in arcs], np.int32).reshape(-1),
+                     None if el is None else np.asarray(el, np.int32))
+    gs = GraphSet.from_graphs([dg(2, [(0, 1)]), dg(2, [(1, 0)]), dg(2, [(0, 1), (1, 0)]),
+                               dg(3, [(0, 1), (1, 2)]), dg(3, [(0, 1), (1, 2), (2, 0)]), dg(0, [])])
+    pairs = [[0, 1], [1, 0], [2, 0], [0, 2], [3, 4], [4, 3], [5, 2], [2, 5], [5, 5]]
+    res = check(ged, gs, pairs, UNIT, 4)
+    assert res.dist[0] == 0 and res.dist[4] == 1
+
+
+def test_symmetric_closure_matches_undirected_doubled(ged):
+    """Both arcs of every edge of undirected graphs, searched as a directed database, give
+    the undirected search's result with the edge costs doubled (also on the GPU's
+    undirected kernels)."""
+    w = synth.batch_er_10_30(200)
+    g = w.graphs
+    sym = GraphSet(g.n, 2 * g.m, g.voff, 2 * g.eoff, g.vlabel,
+                   np.concatenate([np.concatenate([g.eu[a:b], g.ev[a:b]]) for a, b in zip(g.eoff[:-1], g.eoff[1:])]),
+                   np.concatenate([np.concatenate([g.ev[a:b], g.eu[a:b]]) for a, b in zip(g.eoff[:-1], g.eoff[1:])]),
+                   None)
+    c = w.costs
+    c2 = (c[0], c[1], c[2], 2 * c[3], 2 * c[4], 2 * c[5])
+    dd = ged.Database(sym, directed=True)
+    du = ged.Database(g)
+    a = ged.kbest(dd, w.pairs, c, w.K)
+    b = ged.kbest(du, w.pairs, c2, w.K)
+    dd.close()
+    du.close()
+    np.testing.assert_array_equal(a.dist, b.dist)
+    np.testing.assert_array_equal(a.maps, b.maps)
+
+
+def test_directed_database_refusals(ged):
+    import torch
+    gs = GraphSet.from_graphs([synth.directed_graph(740, k, 5, 10, 0.2, 0.2, 2) for k in range(3)]
+                              + [synth.directed_graph(741, 0, 257, 257, 0.01, 0.01, 2)])
+    db = ged.Database(gs, directed=True)
+    flags = ctypes.c_uint32()
+    assert ged.load().ged_db_flags(db.handle, ctypes.byref(flags)) == ged.GED_OK
+    assert flags.value == ged.DB_DIRECTED
+    for make in (lambda: ged.Plan(db, [[0, 3]], 4),
+                 lambda: ged.Plan(db, [[0, 1]], 4, method=ged.METHOD_BIPARTITE),
+                 lambda: ged.Wide(db, 0, 1, 1024),
+                 lambda: ged.Server(db, 8, UNIT)):
+        with pytest.raises(ged.GedError) as e:
+            make()
+        assert e.value.status == ged.GED_EUNSUPPORTED, e.value
+    db.close()
+
+
+def test_edit_paths_of_directed_mappings(ged):
+    """Edit paths of the directed search's mappings, operation for operation against the
+    oracle's expansion; each pair's costs sum to its distance."""
+    import torch
+    gs = directed_set(750, 24, 0, 40, 0.05, 0.3, nl=3, nel=5)
+    rng = np.random.default_rng(751)
+    pairs = rng.integers(0, 24, size=(80, 2)).astype(np.int64)
+    db = ged.Database(gs, directed=True)
+    plan = ged.Plan(db, pairs, 8)
+    dist, maps, _ = plan.outputs()
+    plan.run(NONMETRIC, dist, maps)
+    torch.cuda.synchronize()
+    ops, off, cnt = ged.edit_path(db, pairs, NONMETRIC, maps)
+    d = dist[:len(pairs)].cpu().numpy()
+    m = maps[:plan.map_size].cpu().numpy()
+    plan.close()
+    db.close()
+    moff = np.concatenate([[0], np.cumsum(gs.n[pairs[:, 0]])])
+    for q, (a, b) in enumerate(pairs):
+        ref = oracle.edit_path(gs.graph(int(a)), gs.graph(int(b)), NONMETRIC, m[moff[q]:moff[q + 1]], directed=True)
+        got = ops[off[q]:off[q] + cnt[q]]
+        np.testing.assert_array_equal(got, np.asarray(ref, dtype=np.int32).reshape(-1, 6))
+        assert int(got[:, 5].sum()) == d[q]
+
+
+def test_full_batch_sampled(ged):
+    """The 4096-pair directed batch (n 10..30, K = 64) in one plan; every 8th pair
+    against the oracle."""
+    w = synth.batch_directed_10_30(4096)
+    db = ged.Database(w.graphs, directed=True)
+    res = ged.kbest(db, w.pairs, w.costs, w.K)
+    db.close()
+    idx = np.arange(0, len(w.pairs), 8)
+    d, m, off = oracle.kbest_pairs(w.graphs, w.pairs[idx], w.costs, w.K, directed=True)
+    np.testing.assert_array_equal(res.dist[idx], d)
+    n1 = w.graphs.n[w.pairs[idx, 0]]
+    for k, q in enumerate(idx):
+        np.testing.assert_array_equal(res.mapping(q, n1[k]), m[off[k]:off[k] + n1[k]])
