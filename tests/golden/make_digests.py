@@ -36,7 +36,7 @@ def digest(dist: np.ndarray, maps: np.ndarray) -> str:
     return h.hexdigest()
 
 
-def run_oracle(w, pairs, threads):
+def run_oracle(w, pairs, threads, directed=False):
     """Oracle over `pairs`, sharded over threads; results in pair order."""
     oracle._load()
     order = np.argsort(-(w.graphs.n[pairs[:, 0]].astype(np.int64) * (w.graphs.n[pairs[:, 1]] + 1)), kind="stable")
@@ -44,7 +44,7 @@ def run_oracle(w, pairs, threads):
     res = [None] * threads
 
     def work(t):
-        res[t] = oracle.kbest_pairs(w.graphs, pairs[shards[t]], w.costs, w.K)
+        res[t] = oracle.kbest_pairs(w.graphs, pairs[shards[t]], w.costs, w.K, directed=directed)
 
     th = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
     for x in th:
@@ -69,7 +69,10 @@ WORKLOADS = {
     "query_molecule_n10-70_1x10000_k128": lambda: (synth.query_molecule_10_70(10000), None),
     "stress_er_n100-500_p0.05-0.5_256pairs_k256": lambda: (synth.stress_er_100_500(256), None),
     "serve_mix_db100000_q100000_k64:first2000": lambda: (synth.serve_mix(), 2000),
+    "batch_directed_n10-30_p0.05-0.15_4096pairs_k64": lambda: (synth.batch_directed_10_30(4096), None),
 }
+# workloads whose graphs are directed (edge k = arc eu[k] -> ev[k])
+DIRECTED = {"batch_directed_n10-30_p0.05-0.15_4096pairs_k64"}
 
 
 def main():
@@ -84,8 +87,8 @@ def main():
         t0 = time.time()
         w, limit = make()
         pairs = w.pairs if limit is None else w.pairs[:limit]
-        dist, maps = run_oracle(w, pairs, args.threads)
-        entry = {"workload": w.name, "pairs": int(len(pairs)), "K": w.K, "costs": list(w.costs),
+        dist, maps = run_oracle(w, pairs, args.threads, directed=name in DIRECTED)
+        entry = {"workload": w.name, "directed": name in DIRECTED, "pairs": int(len(pairs)), "K": w.K, "costs": list(w.costs),
                  "sha256": digest(dist.astype(np.int32), maps),
                  "dist_sum": int(dist.sum()), "dist_head": [int(x) for x in dist[:16]],
                  "oracle_seconds": round(time.time() - t0, 1), "threads": args.threads}

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2605_00830_amd import synth
-from tests.golden.make_digests import digest
+from tests.golden.make_digests import DIRECTED, digest
 
 pytestmark = pytest.mark.gpu
 
@@ -24,6 +24,7 @@ WORKLOADS = {
     "query_molecule_n10-70_1x10000_k128": (lambda: synth.query_molecule_10_70(10000), None),
     "stress_er_n100-500_p0.05-0.5_256pairs_k256": (lambda: synth.stress_er_100_500(256), None),
     "serve_mix_db100000_q100000_k64:first2000": (lambda: synth.serve_mix(100000, 2000), 2000),
+    "batch_directed_n10-30_p0.05-0.15_4096pairs_k64": (lambda: synth.batch_directed_10_30(4096), None),
 }
 
 
@@ -49,7 +50,8 @@ def test_full_workload_digest(ged, name, schedule):
     pairs = w.pairs if limit is None else w.pairs[:limit]
     assert len(pairs) == ref["pairs"] and w.K == ref["K"] and list(w.costs) == ref["costs"]
     print(f"  case: {name}, {len(pairs)} pairs, schedule {schedule}", flush=True)
-    db = ged.Database(w.graphs)
+    directed = name in DIRECTED
+    db = ged.Database(w.graphs, directed=directed)
     res = ged.kbest(db, pairs, w.costs, w.K, schedule=schedule)
     db.close()
     got = digest(res.dist, res.maps)
@@ -59,7 +61,7 @@ def test_full_workload_digest(ged, name, schedule):
             bad = np.nonzero(res.dist != np.asarray(ref["dist"]))[0][:5].tolist()
         detail = []
         for p in bad[:3]:
-            d, m, _ = oracle.kbest_pairs(w.graphs, pairs[p:p + 1], w.costs, w.K)
+            d, m, _ = oracle.kbest_pairs(w.graphs, pairs[p:p + 1], w.costs, w.K, directed=directed)
             detail.append((p, int(res.dist[p]), int(d[0])))
         pytest.fail(f"{name}: digest {got[:16]} != {ref['sha256'][:16]}; differing pairs "
                     f"(pair, gpu, oracle): {detail or bad}")
