@@ -23,8 +23,9 @@
  *     has been synchronized.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *   - Graphs are undirected and simple (Sec. 2.1): no self-loops, no repeated
- *     edge.  Vertex and edge labels are int32 values compared for equality
- *     only (Sec. 2.4).
+ *     edge; a database created with GED_DB_DIRECTED holds directed graphs
+ *     instead (see ged_db_create_ex).  Vertex and edge labels are int32
+ *     values compared for equality only (Sec. 2.4).
  *   - Costs are non-negative int32 (Sec. 2.4; the paper's default setting is
  *     vsub 2, vdel 4, vins 4, esub 1, edel 2, eins 2, Sec. 5).  A substitution
  *     costs 0 when the two labels are equal.  All arithmetic is exact int32.

@@ -83,13 +83,29 @@ inline int wave_words_for(int n1, int n2, int K) {
     const int n = n1 > n2 ? n1 : n2;
     return n <= kWaveMaxN ? 1 : (n <= kWave2MaxN ? 2 : 0);
 }
-inline hipError_t wave_family_max_resident(int words, int PL, int last_complete, int *blocks_per_cu) {
+// Directed pairs of up to 32 vertices on the two-word wavefront kernel
+// (kb_wave2.hip, DIR instantiations): a row word of out-arcs and one of
+// in-arcs per vertex.
+hipError_t wave2_max_resident_dir(int PL, int last_complete, int directed, int *blocks_per_cu);
+hipError_t launch_wave2_dir(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
+                            Costs c, int K, int last_complete, int directed, Outputs out, int grid,
+                            hipStream_t stream);
+// Wavefront family of a directed pair: 2 when both orders are <= 32 and K <= 64.
+inline int wave_words_for_directed(int n1, int n2, int K) {
+    return (K <= kWaveMaxK && n1 <= kWaveMaxN && n2 <= kWaveMaxN) ? 2 : 0;
+}
+
+inline hipError_t wave_family_max_resident(int words, int PL, int last_complete, int *blocks_per_cu,
+                                           int directed = 0) {
+    if (directed) return wave2_max_resident_dir(PL, last_complete, 1, blocks_per_cu);
     return words == 1 ? wave_max_resident(PL, last_complete, blocks_per_cu)
                       : wave2_max_resident(PL, last_complete, blocks_per_cu);
 }
 inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const DbView &dst, const WorkItem *work,
                                      int nwork, int *queue, Costs c, int K, int last_complete, Outputs out, int grid,
-                                     hipStream_t stream) {
+                                     hipStream_t stream, int directed = 0) {
+    if (directed)
+        return launch_wave2_dir(PL, src, dst, work, nwork, queue, c, K, last_complete, 1, out, grid, stream);
     return words == 1 ? launch_wave(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream)
                       : launch_wave2(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream);
 }

@@ -218,11 +218,12 @@ ged_status launch_bin(const ged_plan *p, const Bin &b, const RunCtx &r, bool per
     } else if (b.wave) {
         if (!perpair) {
             GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work, nwork, b.d_queue, r.c,
-                                             p->K, p->last_complete, r.o, b.grid, r.s));
+                                             p->K, p->last_complete, r.o, b.grid, r.s, b.shape.directed));
         } else {
             for (int i = 0; i < nwork; ++i)
                 GED_HIP(gedk::launch_wave_family(b.wave_words, b.shape.PL, r.view, r.view, b.d_work + i, 1,
-                                                 b.d_queue + 1 + i, r.c, p->K, p->last_complete, r.o, 1, r.s));
+                                                 b.d_queue + 1 + i, r.c, p->K, p->last_complete, r.o, 1, r.s,
+                                                 b.shape.directed));
         }
     } else if (!perpair) {
         GED_HIP(gedk::launch_block(b.shape, r.view, r.view, b.d_work, nwork, b.d_queue, r.c, p->K, p->last_complete,
@@ -395,8 +396,9 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             return fail(GED_EUNSUPPORTED, "pair %lld: n1 + n2 = %d exceeds the bipartite method's %d", (long long)i,
                         g1.n + g2.n, GED_BIP_MAX_ORDER);
         }
-        const int ww = (!bip && !db->directed && opt.schedule == GED_SCHED_AUTO) ? gedk::wave_words_for(g1.n, g2.n, K)
-                                                                                    : 0;
+        const int ww = (bip || opt.schedule != GED_SCHED_AUTO) ? 0
+                       : db->directed ? gedk::wave_words_for_directed(g1.n, g2.n, K)
+                                      : gedk::wave_words_for(g1.n, g2.n, K);
         const bool wave = ww > 0;
         const int W = pow2_at_least(std::max(1, g2.w)) * (db->directed ? 2 : 1);
         const int cpl = bip ? gedk::bip_cols_per_lane(g1.n + g2.n) : 0;
@@ -462,7 +464,8 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             e = gedk::block_max_resident(sh, &b.max_block_per_cu[k]);
         }
         if (e == hipSuccess && b.wave_ok)
-            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, p->last_complete, &b.max_wave_per_cu);
+            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, p->last_complete, &b.max_wave_per_cu,
+                                               b.shape.directed);
         if (e != hipSuccess || b.max_block_per_cu[0] <= 0 || b.max_block_per_cu[1] <= 0 ||
             ((b.wave_ok || b.bip) && b.max_wave_per_cu <= 0)) {
             free_plan(p);

@@ -43,7 +43,16 @@
 // (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the first lane of least total
 // is the result.  The COMPLETE instantiation's last level instead completes every
 // child and keeps only the least total (first in generation order).
-#include "ged_types.h"
+//
+// The DIR instantiation takes directed pairs of up to 32 vertices (each edge
+// an arc, one edit operation per arc): a vertex's 64-bit row is its out-arc
+// row in the low word and its in-arc row in the high word, Img holds the
+// image in both words, and an earlier neighbour j + 32 of the g1 row (an
+// in-arc of v_i from j) sets its Phi bit in the high word.  The formulas
+// above then count kept, deleted, inserted and relabelled arcs of both
+// directions at once (the implied operations of Sec. 2.3 per arc direction);
+// only |Img| reads the low word alone.
+#include "ged_internal.h"
 #include "wave_common.h"
 
 namespace gedk {
@@ -84,7 +93,7 @@ __device__ __forceinline__ uint32_t to_byte(uint32_t d, uint32_t b, int sh) {
     return d < b ? 0u : min((d - b) >> sh, 126u) + 1u;
 }
 
-template <int PL, bool SMALL, bool COMPLETE>
+template <int PL, bool SMALL, bool COMPLETE, bool DIR>
 __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
@@ -116,8 +125,15 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
         const int n1 = g1.n, n2 = g2.n, w1 = g1.w, w2 = g2.w;
         const uint32_t *A1 = a.src.adj + g1.adj;
         const uint32_t *A2 = a.dst.adj + g2.adj;
-        const uint64_t r1 = lane < n1 ? u64(A1[(size_t)lane * w1], w1 > 1 ? A1[(size_t)lane * w1 + 1] : 0u) : 0ull;
-        const uint64_t r2 = lane < n2 ? u64(A2[(size_t)lane * w2], w2 > 1 ? A2[(size_t)lane * w2 + 1] : 0u) : 0ull;
+        // directed (n <= 32, one row word): the in-arc rows and planes follow the out-arc ones
+        const uint32_t *A1in = A1 + (size_t)(1 + a.src.planes) * n1 * w1;
+        const uint32_t *A2in = A2 + (size_t)(1 + P) * n2 * w2;
+        const uint64_t r1 = lane < n1 ? u64(A1[(size_t)lane * w1], DIR ? A1in[(size_t)lane * w1]
+                                                                     : (w1 > 1 ? A1[(size_t)lane * w1 + 1] : 0u))
+                                      : 0ull;
+        const uint64_t r2 = lane < n2 ? u64(A2[(size_t)lane * w2], DIR ? A2in[(size_t)lane * w2]
+                                                                     : (w2 > 1 ? A2[(size_t)lane * w2 + 1] : 0u))
+                                      : 0ull;
         const int l1 = lane < n1 ? a.src.vlab[g1.vlab + lane] : 0;
         const int l2 = lane < n2 ? a.dst.vlab[g2.vlab + lane] : 0;
         uint64_t p1[PLA];
@@ -126,13 +142,15 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             p1[b] = 0ull;
             if (PL > 0 && b < P && lane < n1) {
                 const uint32_t *B1 = A1 + (size_t)(1 + b) * n1 * w1 + (size_t)lane * w1;
-                p1[b] = u64(B1[0], w1 > 1 ? B1[1] : 0u);
+                const uint32_t *B1in = A1in + (size_t)(1 + b) * n1 * w1 + (size_t)lane * w1;
+                p1[b] = u64(B1[0], DIR ? B1in[0] : (w1 > 1 ? B1[1] : 0u));
             }
             if (PL > 0 && lane <= 64) {
                 uint2 v = make_uint2(0u, 0u);
                 if (b < P && lane < n2) {
                     const uint32_t *B2 = A2 + (size_t)(1 + b) * n2 * w2 + (size_t)lane * w2;
-                    v = make_uint2(B2[0], w2 > 1 ? B2[1] : 0u);
+                    const uint32_t *B2in = A2in + (size_t)(1 + b) * n2 * w2 + (size_t)lane * w2;
+                    v = make_uint2(B2[0], DIR ? B2in[0] : (w2 > 1 ? B2[1] : 0u));
                 }
                 s_pl[b][lane] = v;
             }
@@ -152,7 +170,8 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
         long long ce = 0;
 
         for (int i = 0; i < n1; ++i) {
-            const uint64_t below = i >= 64 ? ~0ull : ((1ull << i) - 1ull);
+            const uint64_t below = DIR ? (((1ull << i) - 1ull) * 0x100000001ull)   // i < 32: both words
+                                       : (i >= 64 ? ~0ull : ((1ull << i) - 1ull));
             const uint64_t nbm = readlane64(r1, i) & below;
             const int lab1 = __builtin_amdgcn_readlane(l1, i);
             const uint32_t degP = popc64(nbm);
@@ -175,8 +194,10 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 for (int k = 0; k < 4; ++k) {
                     const int j = 4 * w + k;
                     if (!((nbm >> j) & 1ull)) continue;
-                    const uint32_t x = __builtin_amdgcn_ubfe(ph[w], (uint32_t)k * 8u, 8u);
-                    const uint64_t bit = x < 64u ? (1ull << x) : 0ull;
+                    // directed: bit j >= 32 is the in-arc from vertex j - 32
+                    const int wsrc = DIR && w >= 8 ? w - 8 : w;   // a constant once unrolled
+                    const uint32_t x = __builtin_amdgcn_ubfe(ph[wsrc], (uint32_t)k * 8u, 8u);
+                    const uint64_t bit = x < 64u ? (1ull << (x + (DIR && w >= 8 ? 32u : 0u))) : 0ull;
                     phi |= bit;
 #pragma unroll
                     for (int b = 0; b < PLA; ++b)
@@ -288,7 +309,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 // ---------------- complete-then-minimum last level: each
                 // child's total (Sec. 4.4.1); the least, first in generation
                 // order, is the one survivor
-                const uint32_t nu = (uint32_t)n2 - popc64(img);
+                const uint32_t nu = (uint32_t)n2 - (DIR ? (uint32_t)__popc((uint32_t)img) : popc64(img));
                 const uint32_t mo = (uint32_t)g2.m - ein;   // g2 edges not inside Img
                 uint32_t bt = INVALID, bj = DEL8;
                 uint64_t fr = free;
@@ -447,7 +468,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                         d += mul_cost<SMALL>(popc64(phi_p & R & diff), esub);
                     }
                     ped = d;
-                    img = img_p | (1ull << (us & 63u));
+                    img = img_p | (1ull << (us & 63u)) | (DIR ? (1ull << ((us + 32u) & 63u)) : 0ull);
                     ein = ein_p + popc64(img_p & R);
                 } else {
                     ped = basel_p + vdel;
@@ -464,7 +485,8 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
         }
 
         // ---------------- completion and best leaf
-        const uint32_t total = lane < nb ? ped + mul_cost<SMALL>((uint32_t)n2 - popc64(img), vins) +
+        const uint32_t nimg = DIR ? (uint32_t)__popc((uint32_t)img) : popc64(img);
+        const uint32_t total = lane < nb ? ped + mul_cost<SMALL>((uint32_t)n2 - nimg, vins) +
                                                mul_cost<SMALL>((uint32_t)g2.m - ein, eins)
                                          : INVALID;
         const uint32_t best_total = wave_umin(total);
@@ -487,23 +509,24 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
     }
 }
 
-template <int PL, bool SMALL, bool COMPLETE>
+template <int PL, bool SMALL, bool COMPLETE, bool DIR>
 const void *wave2_ptr() {
-    return reinterpret_cast<const void *>(&kb_wave2_kernel<PL, SMALL, COMPLETE>);
+    return reinterpret_cast<const void *>(&kb_wave2_kernel<PL, SMALL, COMPLETE, DIR>);
 }
 
 // the complete-then-minimum last level is a kernel of its own, so that the
-// default search keeps its register budget
-template <bool COMPLETE>
+// default search keeps its register budget; so are directed pairs
+template <bool COMPLETE, bool DIR>
 const void *select_wave2_c(int PL, bool small) {
-    if (PL == 0) return small ? wave2_ptr<0, true, COMPLETE>() : wave2_ptr<0, false, COMPLETE>();
-    if (PL == 2) return small ? wave2_ptr<2, true, COMPLETE>() : wave2_ptr<2, false, COMPLETE>();
-    if (PL == 4) return small ? wave2_ptr<4, true, COMPLETE>() : wave2_ptr<4, false, COMPLETE>();
+    if (PL == 0) return small ? wave2_ptr<0, true, COMPLETE, DIR>() : wave2_ptr<0, false, COMPLETE, DIR>();
+    if (PL == 2) return small ? wave2_ptr<2, true, COMPLETE, DIR>() : wave2_ptr<2, false, COMPLETE, DIR>();
+    if (PL == 4) return small ? wave2_ptr<4, true, COMPLETE, DIR>() : wave2_ptr<4, false, COMPLETE, DIR>();
     return nullptr;
 }
 
-const void *select_wave2(int PL, bool small, bool complete) {
-    return complete ? select_wave2_c<true>(PL, small) : select_wave2_c<false>(PL, small);
+const void *select_wave2(int PL, bool small, bool complete, bool dir = false) {
+    if (dir) return complete ? select_wave2_c<true, true>(PL, small) : select_wave2_c<false, true>(PL, small);
+    return complete ? select_wave2_c<true, false>(PL, small) : select_wave2_c<false, false>(PL, small);
 }
 
 bool small_costs2(const Costs &c) {
@@ -513,9 +536,9 @@ bool small_costs2(const Costs &c) {
 
 }  // namespace
 
-hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu) {
-    const void *k = select_wave2(PL, true, last_complete != 0);
-    const void *k2 = select_wave2(PL, false, last_complete != 0);
+hipError_t wave2_max_resident_dir(int PL, int last_complete, int directed, int *blocks_per_cu) {
+    const void *k = select_wave2(PL, true, last_complete != 0, directed != 0);
+    const void *k2 = select_wave2(PL, false, last_complete != 0, directed != 0);
     if (!k || !k2) return hipErrorInvalidValue;
     int x = 0, y = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&x, k, 64, 0);
@@ -524,9 +547,14 @@ hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu) {
     return e;
 }
 
-hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
-                        Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream) {
-    const void *k = select_wave2(PL, small_costs2(c), last_complete != 0);
+hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu) {
+    return wave2_max_resident_dir(PL, last_complete, 0, blocks_per_cu);
+}
+
+hipError_t launch_wave2_dir(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
+                            Costs c, int K, int last_complete, int directed, Outputs out, int grid,
+                            hipStream_t stream) {
+    const void *k = select_wave2(PL, small_costs2(c), last_complete != 0, directed != 0);
     if (!k || grid <= 0 || K > kWaveMaxK) return hipErrorInvalidValue;
     Wave2Args a;
     a.src = src;
@@ -539,6 +567,11 @@ hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const Work
     a.out = out;
     void *args[] = {&a};
     return hipLaunchKernel(k, dim3(grid), dim3(64), args, 0, stream);
+}
+
+hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
+                        Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream) {
+    return launch_wave2_dir(PL, src, dst, work, nwork, queue, c, K, last_complete, 0, out, grid, stream);
 }
 
 }  // namespace gedk

@@ -1,7 +1,9 @@
-"""Directed graphs (GED_DB_DIRECTED) through the workgroup kernel: distances
-and mappings equal the oracle's directed search bit for bit, for every row
-width (n up to 32, 64, 128, 256), no / two / four label planes (planes staged
-in LDS and read from HBM), the candidate matrix in LDS and in the workspace,
+"""Directed graphs (GED_DB_DIRECTED) through the two-word wavefront kernel
+(pairs of up to 32 vertices, K <= 64) and the workgroup kernel (everything
+else, and every pair under the workgroup-only schedule): distances and
+mappings equal the oracle's directed search bit for bit, for every row width
+(n up to 32, 64, 128, 256), no / two / four label planes (planes staged in
+LDS and read from HBM), the candidate matrix in LDS and in the workspace,
 256- and 512-thread workgroups, the complete-then-minimum last level and the
 one-launch-per-pair path; the calls that take undirected graphs only refuse
 a directed database (GPU)."""
@@ -42,18 +44,24 @@ def directed_set(seed, count, n_lo, n_hi, p_lo, p_hi, nl=4, nel=0):
                                  for k in range(count)])
 
 
-def check(ged, graphs, pairs, costs, K, last_level=0, perpair=False, expect_words=None):
+def check(ged, graphs, pairs, costs, K, last_level=0, perpair=False, expect_words=None, schedule=0,
+          kinds=None):
     pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
     say(f"  case: {len(pairs)} pairs, K={K}, costs={costs}, last={last_level}, perpair={perpair}, "
-        f"n<={int(graphs.n.max())}")
+        f"schedule={schedule}, n<={int(graphs.n.max())}")
     db = ged.Database(graphs, directed=True)
-    plan = ged.Plan(db, pairs, K, last_level=last_level)
+    plan = ged.Plan(db, pairs, K, last_level=last_level, schedule=schedule)
     bins = plan.bins()
-    assert all(name == "kb_block_kernel" for name, *_ in bins), bins
+    names = {name for name, *_ in bins}
+    assert names <= {"kb_block_kernel", "kb_wave2_kernel"}, bins
+    if schedule == 1:
+        assert names == {"kb_block_kernel"}, bins
+    if kinds is not None:
+        assert names == kinds, bins
     if expect_words is not None:
         assert {w for *_, w in bins} == expect_words, bins
     plan.close()
-    res = ged.kbest(db, pairs, costs, K, perpair=perpair, last_level=last_level)
+    res = ged.kbest(db, pairs, costs, K, perpair=perpair, last_level=last_level, schedule=schedule)
     db.close()
     d, m, off = oracle.kbest_pairs(graphs, pairs, costs, K, last_complete=last_level == 1, directed=True)
     np.testing.assert_array_equal(res.offsets, off)
@@ -64,22 +72,37 @@ def check(ged, graphs, pairs, costs, K, last_level=0, perpair=False, expect_word
     return res
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("costs", [UNIT, PAPER, NONMETRIC, ASYM])
 @pytest.mark.parametrize("K", [1, 8, 64])
-def test_small_directed_pairs(ged, costs, K):
-    """n 0..32 (two-word rows: out and in), unlabelled arcs, ragged orders incl. empty graphs."""
+def test_small_directed_pairs(ged, costs, K, schedule):
+    """n 0..32 (two-word rows: out and in), unlabelled arcs, ragged orders incl. empty graphs;
+    the wavefront kernel by default, the workgroup kernel under schedule 1."""
     gs = directed_set(700, 40, 0, 32, 0.05, 0.4)
     rng = np.random.default_rng(701)
     pairs = rng.integers(0, 40, size=(150, 2))
-    check(ged, gs, pairs, costs, K, expect_words={2})
+    check(ged, gs, pairs, costs, K, expect_words={2}, schedule=schedule,
+          kinds={"kb_wave2_kernel"} if schedule == 0 else None)
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("last_level", [0, 1])
-def test_labelled_arcs_two_and_four_planes(ged, last_level):
+def test_labelled_arcs_two_and_four_planes(ged, last_level, schedule):
     for nel, seed in ((3, 710), (12, 711)):
         gs = directed_set(seed, 30, 5, 30, 0.1, 0.3, nl=3, nel=nel)
         rng = np.random.default_rng(seed)
-        check(ged, gs, rng.integers(0, 30, size=(120, 2)), NONMETRIC, 16, last_level=last_level)
+        check(ged, gs, rng.integers(0, 30, size=(120, 2)), NONMETRIC, 16, last_level=last_level,
+              schedule=schedule)
+
+
+def test_wavefront_and_workgroup_bins_together(ged):
+    """One plan over directed pairs of up to 32 vertices (wavefront kernel) and larger
+    ones (workgroup kernel), and K = 65 (past the wavefront kernel's limit)."""
+    gs = GraphSet.from_graphs([synth.directed_graph(715, k, 3, 32, 0.1, 0.3, 3, 3) for k in range(10)]
+                              + [synth.directed_graph(716, k, 33, 60, 0.05, 0.1, 3, 3) for k in range(4)])
+    pairs = [[a, b] for a in range(14) for b in range(14) if a != b][::3]
+    check(ged, gs, pairs, PAPER, 24, kinds={"kb_wave2_kernel", "kb_block_kernel"})
+    check(ged, gs, pairs[:30], PAPER, 65, kinds={"kb_block_kernel"})
 
 
 @pytest.mark.parametrize("n_lo,n_hi,words,npairs", [(33, 64, 4, 40), (65, 128, 8, 30), (129, 200, 16, 12)])
@@ -101,16 +124,19 @@ def test_planes_from_hbm_and_candidates_in_workspace(ged):
     check(ged, gs, [[3, 1], [3, 0]], UNIT, 256, expect_words={16})
 
 
-def test_batch_of_256_thread_workgroups_and_complete(ged):
-    """600 pairs (more than two per CU: 256-thread workgroups), both last levels."""
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batch_of_256_thread_workgroups_and_complete(ged, schedule):
+    """600 pairs (more than two per CU: 256-thread workgroups under schedule 1), both last
+    levels."""
     w = synth.batch_directed_10_30(600)
-    check(ged, w.graphs, w.pairs, w.costs, w.K)
-    check(ged, w.graphs, w.pairs[:200], w.costs, w.K, last_level=1)
+    check(ged, w.graphs, w.pairs, w.costs, w.K, schedule=schedule)
+    check(ged, w.graphs, w.pairs[:200], w.costs, w.K, last_level=1, schedule=schedule)
 
 
-def test_perpair_path(ged):
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_perpair_path(ged, schedule):
     w = synth.batch_directed_10_30(40)
-    check(ged, w.graphs, w.pairs, PAPER, 32, perpair=True)
+    check(ged, w.graphs, w.pairs, PAPER, 32, perpair=True, schedule=schedule)
 
 
 def test_two_cycles_and_reversed_arcs(ged):
