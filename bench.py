@@ -449,28 +449,39 @@ def directed_measure(ged, steps: int, warmup: int, tune: bool, tune_cache, threa
     P = len(w.pairs)
     db = ged.Database(w.graphs, directed=True)
     plan = ged.Plan(db, w.pairs, w.K)
-    dist, maps, _ = plan.outputs()
+    dist, maps, cand = plan.outputs(with_cand=True)
     s = torch.cuda.current_stream()
     plan.set_timing(True)
     if tune:
         plan.tune(w.costs, dist, maps, stream=s, cache_path=tune_cache)
         s.synchronize()
     for _ in range(warmup):
-        plan.run(w.costs, dist, maps, stream=s)
+        plan.run(w.costs, dist, maps, cand, stream=s)
         s.synchronize()
     ks = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        plan.run(w.costs, dist, maps, stream=s)
+        plan.run(w.costs, dist, maps, cand, stream=s)
         s.synchronize()
         ks.append(plan.kernel_ms())
     wall = time.perf_counter() - t0
     d = dist[:P].cpu().numpy()
     m = maps[:plan.map_size].cpu().numpy()
+    # algorithmic work: a directed vertex's row is an out-row and an in-row, so
+    # twice the words of an undirected row of the same order
+    ce = cand[:P].cpu().numpy().astype(np.int64)
+    n2 = np.asarray(w.graphs.n, np.int64)[w.pairs[:, 1]]
+    words = 2 * np.maximum((n2 + 31) // 32, 1)
+    ops = float(sum(ops_per_candidate(int(x), 0) * int(c) for x, c in zip(words, ce)))
+    kms = float(np.mean(ks))
+    achieved = ops / (kms / 1e3) / 1e12
     out = {"config": {"workload": w.name, "pairs": P, "K": w.K, "costs": list(w.costs),
                       "mean_order": round(float(w.graphs.n.mean()), 2), "mean_arcs": round(float(w.graphs.m.mean()), 2)},
            "value": round(P * steps / wall, 2), "unit": "pairs/s", "ms_per_step": round(wall * 1e3 / steps, 4),
-           "kernel_ms": round(float(np.mean(ks)), 4), "bins": plan.bins()}
+           "kernel_ms": round(kms, 4), "bins": plan.bins(),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 2),
+                        "unit": "Tops/s", "frac": round(achieved / PEAK_INT32_TOPS, 5),
+                        "candidates_per_launch": int(ce.sum()), "ops_per_launch": ops}}
     plan.close()
     db.close()
     idx = np.arange(0, P, check_every)

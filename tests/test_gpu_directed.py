@@ -231,3 +231,39 @@ def test_full_batch_sampled(ged):
     n1 = w.graphs.n[w.pairs[idx, 0]]
     for k, q in enumerate(idx):
         np.testing.assert_array_equal(res.mapping(q, n1[k]), m[off[k]:off[k] + n1[k]])
+
+
+def test_graph_replay_and_tune(ged, tmp_path):
+    """A directed plan with a wavefront bin and a workgroup bin, tuned (choices cached), then
+    captured once and replayed four times with another plan's eager run between replays;
+    every replay equals the oracle."""
+    import torch
+    gs = GraphSet.from_graphs([synth.directed_graph(760, k, 5, 32, 0.1, 0.25, 3, 2) for k in range(30)]
+                              + [synth.directed_graph(761, k, 33, 50, 0.05, 0.1, 3, 2) for k in range(6)])
+    rng = np.random.default_rng(762)
+    pairs = rng.integers(0, 36, size=(150, 2)).astype(np.int64)
+    costs, K = PAPER, 20
+    d_ref, m_ref, _ = oracle.kbest_pairs(gs, pairs, costs, K, directed=True)
+    db = ged.Database(gs, directed=True)
+    plan = ged.Plan(db, pairs, K)
+    assert {name for name, *_ in plan.bins()} == {"kb_wave2_kernel", "kb_block_kernel"}
+    dist, maps, _ = plan.outputs()
+    cache = str(tmp_path / "tune.txt")
+    assert plan.tune(costs, dist, maps, cache_path=cache) >= 1
+    other = ged.Plan(db, pairs[::-1].copy(), 7)
+    od, om, _ = other.outputs()
+    s = torch.cuda.Stream()
+    plan.capture(costs, dist, maps, stream=s)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            dist.fill_(-7)
+            maps.fill_(-7)
+        plan.replay(stream=s)
+        s.synchronize()
+        np.testing.assert_array_equal(dist[:len(pairs)].cpu().numpy(), d_ref)
+        np.testing.assert_array_equal(maps[:plan.map_size].cpu().numpy(), m_ref)
+        other.run(costs, od, om)
+        torch.cuda.synchronize()
+    plan.close()
+    other.close()
+    db.close()
