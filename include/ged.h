@@ -133,9 +133,10 @@ ged_status ged_db_create(const ged_graph *graphs, int64_t count, ged_db **out);
  * Sec. 2.3 between the edited vertex and each earlier one are taken for
  * both arc directions.  A directed database serves the tree search
  * (ged_plan_create, ged_plan_create_ex with GED_METHOD_TREE, ged_kbest,
- * ged_kbest_perpair) for graphs of at most GED_DIRECTED_MAX_ORDER
- * vertices, and ged_edit_path; ged_wide_create, ged_server_create and the
- * bipartite method return GED_EUNSUPPORTED for it. */
+ * ged_kbest_perpair) and the server (ged_server_create; its queries are
+ * then directed graphs too) for graphs of at most GED_DIRECTED_MAX_ORDER
+ * vertices, and ged_edit_path; ged_wide_create and the bipartite method
+ * return GED_EUNSUPPORTED for it. */
 #define GED_DB_DIRECTED 1u
 #define GED_DIRECTED_MAX_ORDER 256
 

@@ -122,6 +122,7 @@ struct ged_server {
     int wave_per_cu[kWaveBins] = {0, 0};   // n <= 32, n <= 64 kernels
     int block_per_cu[2][5] = {};   // [256 | 512 threads][W = 1, 2, 4, 8, 16]
     bool bip = false;              // bipartite method
+    bool directed = false;         // directed database: rows [out | in], W doubled
     int bip_per_cu[kClasses] = {0, 0, 0, 0};   // its kernel, 1..4 columns per lane
     int64_t device_bytes = 0;
     std::vector<Slab> slabs;
@@ -155,7 +156,8 @@ constexpr int kMediumMaxN = 128;
 
 int server_class(const ged_server *s, int n1, int n2) {
     if (s->bip) return gedk::bip_cols_per_lane(n1 + n2) - 1;
-    const int ww = gedk::wave_words_for(n1, n2, s->cfg.K);
+    // directed pairs of up to 32 vertices take the two-word kernel (class 1)
+    const int ww = s->directed ? gedk::wave_words_for_directed(n1, n2, s->cfg.K) : gedk::wave_words_for(n1, n2, s->cfg.K);
     if (ww > 0) return ww - 1;
     if (n1 <= kMediumMaxN && n2 <= kMediumMaxN) return 2;
     return 3;
@@ -169,6 +171,7 @@ gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2, int
     sh.KS = gedk::block_slot_stride(s->cfg.K, threads);
     sh.nmax1 = nmax1;
     sh.nmax2 = nmax2;
+    sh.directed = s->directed ? 1 : 0;
     return sh;
 }
 
@@ -258,8 +261,9 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
     for (int k = 0; k < nq; ++k) {
         const Request &r = *b.batch[(size_t)k];
         const GraphRec &g2 = dbg[(size_t)r.target];
-        const int ww = gedk::wave_words_for(r.n1, g2.n, K);
-        const int bin = ww > 0 ? ww - 1 : kWaveBins + w_index(pow2_at_least(std::max(1, g2.w)));
+        const int ww = s->directed ? gedk::wave_words_for_directed(r.n1, g2.n, K) : gedk::wave_words_for(r.n1, g2.n, K);
+        const int bin =
+            ww > 0 ? ww - 1 : kWaveBins + w_index(pow2_at_least(std::max(1, g2.w)) * (s->directed ? 2 : 1));
         WorkItem wi;
         wi.src = k;
         wi.dst = r.target;
@@ -316,7 +320,7 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         if (cnt == 0) continue;
         if (bin < kWaveBins) {
             e = gedk::launch_wave_family(bin + 1, s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K,
-                                         0, out, grid[bin], b.stream);
+                                         0, out, grid[bin], b.stream, s->directed ? 1 : 0);
         } else {
             e = gedk::launch_block(shape[bin], src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, 0,
                                    b.d_ws, stride[bin], out, grid[bin], b.stream);
@@ -449,7 +453,6 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     if (!out) return fail(GED_EINVAL, "out is NULL");
     *out = nullptr;
     if (!db || !config) return fail(GED_EINVAL, "NULL argument");
-    if (db->directed) return fail(GED_EUNSUPPORTED, "the server takes undirected graphs only");
     ged_server_config cfg = *config;
     if (cfg.K < 1) return fail(GED_EINVAL, "K must be >= 1 (got %d)", cfg.K);
     if (cfg.K > GED_MAX_K) return fail(GED_EUNSUPPORTED, "K = %d exceeds %d", cfg.K, GED_MAX_K);
@@ -467,6 +470,8 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
         return fail(GED_EINVAL, "unknown method %d", cfg.method);
     if (cfg.method == GED_METHOD_BIPARTITE && cfg.K > GED_BIP_MAX_K)
         return fail(GED_EUNSUPPORTED, "K = %d exceeds the bipartite method's %d", cfg.K, GED_BIP_MAX_K);
+    if (cfg.method == GED_METHOD_BIPARTITE && db->directed)
+        return fail(GED_EUNSUPPORTED, "the bipartite method takes undirected graphs only");
     st = gedh::check_device(db);
     if (st != GED_OK) return st;
 
@@ -478,10 +483,11 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     s->PL = db->planes == 0 ? 0 : (db->planes <= 2 ? 2 : 4);
     s->device = db->device;
     s->bip = cfg.method == GED_METHOD_BIPARTITE;
+    s->directed = db->directed;
     hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
     const bool wave_classes = !s->bip && cfg.K <= gedk::kWaveMaxK;
     for (int k = 0; k < kWaveBins && e == hipSuccess && wave_classes; ++k)
-        e = gedk::wave_family_max_resident(k + 1, s->PL, 0, &s->wave_per_cu[k]);
+        e = gedk::wave_family_max_resident(k + 1, s->PL, 0, &s->wave_per_cu[k], s->directed ? 1 : 0);
     const int first_class = (wave_classes || s->bip) ? 0 : kFirstBlockClass;
     const int nslabs = (kClasses - first_class) * cfg.streams;
     // every stream gets an equal share of the budget: its class's workspace
@@ -489,8 +495,11 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     // then the arena
     const int64_t per_stream = cfg.hbm_budget / nslabs;
     size_t ws_class[kClasses] = {0, 0, 0, 0};
-    const int max_n[kClasses] = {s->bip ? 64 : gedk::kWaveMaxN, s->bip ? 128 : gedk::kWave2MaxN,
-                                 s->bip ? 192 : kMediumMaxN, s->bip ? 256 : GED_MAX_VERTICES};
+    // directed: class 0 takes no pair, class 1 the pairs of up to 32 vertices, class 3 up to 256
+    const int max_n[kClasses] = {s->bip ? 64 : gedk::kWaveMaxN,
+                                 s->bip ? 128 : (s->directed ? gedk::kWaveMaxN : gedk::kWave2MaxN),
+                                 s->bip ? 192 : kMediumMaxN,
+                                 s->bip ? 256 : (s->directed ? GED_DIRECTED_MAX_ORDER : GED_MAX_VERTICES)};
     // bipartite classes: one queue slice per resident wave, at most half the share
     for (int cls = 0; cls < kClasses && e == hipSuccess && s->bip; ++cls) {
         e = gedk::bip_max_resident(s->PL, cls + 1, cfg.K, 1, &s->bip_per_cu[cls]);
@@ -506,11 +515,13 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     }
     for (int cls = kFirstBlockClass; cls < kClasses && e == hipSuccess && !s->bip; ++cls) {
         size_t ws = 0, one_block = 0;
-        for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        // rows of W words cover 32 W vertices, or 16 W for a directed graph (out and in halves)
+        const int per_word = s->directed ? 16 : 32;
+        for (int k = s->directed ? 1 : 0; k < 5 && e == hipSuccess; ++k) {
             const int W = 1 << k;
-            if (W > 1 && 16 * W >= max_n[cls]) break;   // W / 2 words already cover the class
+            if (W > (s->directed ? 2 : 1) && per_word * W / 2 >= max_n[cls]) break;   // W / 2 words already cover it
             for (int wide = 0; wide < 2 && e == hipSuccess; ++wide) {
-                const gedk::BlockShape sh = shape_for(s, W, max_n[cls], std::min(32 * W, max_n[cls]),
+                const gedk::BlockShape sh = shape_for(s, W, max_n[cls], std::min(per_word * W, max_n[cls]),
                                                       wide ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
                 e = gedk::block_max_resident(sh, &s->block_per_cu[wide][k]);
                 const int64_t grid =
@@ -538,7 +549,7 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
         const int64_t fixed = (int64_t)ws_class[cls] +
                               (int64_t)cfg.max_batch * (int64_t)(sizeof(GraphRec) + sizeof(WorkItem) + 4) + kMaxBins * 4;
         const int64_t rest = per_stream - fixed;
-        const int64_t big = gedh::packed_words(max_n[cls], db->planes);
+        const int64_t big = gedh::packed_words(max_n[cls], db->planes, s->directed);
         cap_words[cls] = std::min({rest / 4 * 8 / 10, (int64_t)cfg.max_batch * big, (int64_t)16 << 20});
         cap_vlab[cls] = std::min(rest / 4 / 20, (int64_t)cfg.max_batch * max_n[cls]);
         if (rest <= 0 || cap_words[cls] < big || cap_vlab[cls] < max_n[cls]) {
@@ -591,14 +602,16 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
 ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t target_id, uint64_t *ticket) {
     if (!srv || !query || !ticket) return fail(GED_EINVAL, "NULL argument");
     if (target_id < 0 || target_id >= srv->db->count) return fail(GED_EINVAL, "target id %lld out of range", (long long)target_id);
-    ged_status st = gedh::check_graph_shape(*query, 0);
+    ged_status st = gedh::check_graph_shape(*query, 0, srv->directed);
     if (st != GED_OK) return st;
     auto r = std::make_shared<Request>();
     r->n1 = query->n;
     r->target = (int32_t)target_id;
-    st = gedh::pack_graph(*query, 0, srv->db->elabels, srv->db->planes, r->adj, r->vlab, r->rec);
+    st = gedh::pack_graph(*query, 0, srv->db->elabels, srv->db->planes, r->adj, r->vlab, r->rec, srv->directed);
     if (st != GED_OK) return st;
     const GraphRec &g2 = srv->db->h_graphs[(size_t)target_id];
+    if (srv->directed && std::max(query->n, g2.n) > GED_DIRECTED_MAX_ORDER)
+        return fail(GED_EUNSUPPORTED, "directed graphs of more than %d vertices", GED_DIRECTED_MAX_ORDER);
     if (srv->bip && query->n + g2.n > GED_BIP_MAX_ORDER)
         return fail(GED_EUNSUPPORTED, "n1 + n2 = %d exceeds the bipartite method's %d", query->n + g2.n,
                     GED_BIP_MAX_ORDER);

@@ -442,7 +442,6 @@ class Server:
         handle = ctypes.c_void_p()
         _check(lib.ged_server_create(db.handle, ctypes.byref(cfg), ctypes.byref(handle)))
         self._h = handle
-        self._map = np.zeros(MAX_VERTICES, dtype=np.int32)
 
     def submit(self, query, target_id: int) -> int:
         """Queue one query; raises GedError (status GED_EBUSY when the queue is full)."""
@@ -453,11 +452,14 @@ class Server:
         return int(t.value)
 
     def _result(self, fn, *args):
+        # the mapping lands in a buffer of this call's own: wait and poll may run
+        # on several client threads at once
         d, n1 = ctypes.c_int32(), ctypes.c_int32()
         times = (ctypes.c_int64 * 2)()
-        st = fn(self._h, *args, ctypes.byref(d), self._map.ctypes.data, MAX_VERTICES, ctypes.byref(n1), times)
+        buf = np.empty(MAX_VERTICES, dtype=np.int32)
+        st = fn(self._h, *args, ctypes.byref(d), buf.ctypes.data, MAX_VERTICES, ctypes.byref(n1), times)
         self.last_times_ns = (int(times[0]), int(times[1]))
-        return st, int(d.value), self._map[: n1.value].copy()
+        return st, int(d.value), buf[: n1.value].copy()
 
     def poll(self, ticket: int):
         """(dist, mapping) when finished, None while it runs; the submission and

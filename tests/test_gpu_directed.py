@@ -176,7 +176,6 @@ def test_symmetric_closure_matches_undirected_doubled(ged):
 
 
 def test_directed_database_refusals(ged):
-    import torch
     gs = GraphSet.from_graphs([synth.directed_graph(740, k, 5, 10, 0.2, 0.2, 2) for k in range(3)]
                               + [synth.directed_graph(741, 0, 257, 257, 0.01, 0.01, 2)])
     db = ged.Database(gs, directed=True)
@@ -186,11 +185,58 @@ def test_directed_database_refusals(ged):
     for make in (lambda: ged.Plan(db, [[0, 3]], 4),
                  lambda: ged.Plan(db, [[0, 1]], 4, method=ged.METHOD_BIPARTITE),
                  lambda: ged.Wide(db, 0, 1, 1024),
-                 lambda: ged.Server(db, 8, UNIT)):
+                 lambda: ged.Server(db, 8, UNIT, method=ged.METHOD_BIPARTITE)):
         with pytest.raises(ged.GedError) as e:
             make()
         assert e.value.status == ged.GED_EUNSUPPORTED, e.value
+    srv = ged.Server(db, 8, UNIT, streams=1)
+    with pytest.raises(ged.GedError) as e:
+        srv.submit(gs.graph(3), 0)          # a 257-vertex directed query
+    assert e.value.status == ged.GED_EUNSUPPORTED
+    srv.close()
     db.close()
+
+
+@pytest.mark.parametrize("K", [16, 80])
+def test_server_serves_directed_queries(ged, K):
+    """The server over a directed database: queries of all sizes up to 256 vertices (the
+    two-word wavefront class at K <= 64, the workgroup classes otherwise), from two
+    concurrent clients, each result equal to the oracle's directed search."""
+    import threading
+    gdb = ([synth.directed_graph(770, k, 3, 32, 0.1, 0.3, 3, 3) for k in range(20)]
+           + [synth.directed_graph(771, k, 33, 120, 0.03, 0.08, 3, 3) for k in range(6)]
+           + [synth.directed_graph(772, k, 129, 200, 0.01, 0.03, 3, 3) for k in range(2)])
+    queries = ([synth.directed_graph(773, k, 3, 32, 0.1, 0.3, 3, 3) for k in range(40)]
+               + [synth.directed_graph(774, k, 33, 100, 0.03, 0.08, 3, 3) for k in range(6)]
+               + [synth.directed_graph(775, 0, 140, 140, 0.01, 0.01, 3, 3)])
+    rng = np.random.default_rng(776)
+    # small queries against small targets (wavefront class), the rest anywhere
+    targets = [int(rng.integers(0, 20)) if q < 40 else int(rng.integers(0, len(gdb))) for q in range(len(queries))]
+    db = ged.Database(GraphSet.from_graphs(gdb), directed=True)
+    srv = ged.Server(db, K, PAPER, max_batch=16, streams=2)
+    results = {}
+    errors = []
+
+    def client(idx):
+        try:
+            tickets = [(q, srv.submit(queries[q], targets[q])) for q in idx]
+            for q, t in tickets:
+                results[q] = srv.wait(t, timeout_us=120_000_000)
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    th = [threading.Thread(target=client, args=(list(range(c, len(queries), 2)),)) for c in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    srv.close()
+    db.close()
+    assert not errors, errors
+    for q in range(len(queries)):
+        d, m = results[q]
+        rd, rm = oracle.kbest(queries[q], gdb[targets[q]], PAPER, K, directed=True)
+        assert d == rd and np.array_equal(m, rm), (q, d, rd)
 
 
 def test_edit_paths_of_directed_mappings(ged):
