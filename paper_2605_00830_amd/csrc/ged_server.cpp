@@ -488,7 +488,9 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     const bool wave_classes = !s->bip && cfg.K <= gedk::kWaveMaxK;
     for (int k = 0; k < kWaveBins && e == hipSuccess && wave_classes; ++k)
         e = gedk::wave_family_max_resident(k + 1, s->PL, 0, &s->wave_per_cu[k], s->directed ? 1 : 0);
-    const int first_class = (wave_classes || s->bip) ? 0 : kFirstBlockClass;
+    // classes that can receive a query get streams: a directed database has no
+    // one-word class (its pairs of up to 32 vertices take the two-word kernel)
+    const int first_class = s->bip ? 0 : (wave_classes ? (s->directed ? 1 : 0) : kFirstBlockClass);
     const int nslabs = (kClasses - first_class) * cfg.streams;
     // every stream gets an equal share of the budget: its class's workspace
     // (at most half of the share; fewer resident workgroups when smaller),
