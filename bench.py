@@ -148,8 +148,9 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
     method 1 serves the bipartite method, on the queries whose pair has
     n1 + n2 <= 256 (its limit)."""
     ndb = w.meta["ndb"]
+    directed = bool(w.meta.get("directed", False))
     nq = min(n_queries, len(w.pairs))
-    db = ged.Database(w.graphs.slice(0, ndb))
+    db = ged.Database(w.graphs.slice(0, ndb), directed=directed)
     qgs = w.graphs.slice(ndb, ndb + nq)
     recs, keep = ged.pack_queries(qgs)
     targets = np.ascontiguousarray(w.pairs[:nq, 1])
@@ -215,6 +216,12 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
         cls = (n_q + n_t + 63) // 64 - 1
         sel = np.nonzero(n_q + n_t <= 256)[0]
         class_names = ("le64", "le128", "le192", "le256")
+    elif directed:
+        # directed: pairs of up to 32 vertices on the two-word kernel (class 1), then
+        # up to 128, then up to 256 (the directed limit)
+        cls = np.where(wave & (n_max <= 32), 1, np.where(n_max <= 128, 2, 3))
+        sel = np.nonzero(n_max <= 256)[0]
+        class_names = ("none", "small", "medium", "large")
     else:
         cls = np.where(wave & (n_max <= 32), 0, np.where(wave & (n_max <= 64), 1, np.where(n_max <= 128, 2, 3)))
         sel = np.arange(nq)
@@ -238,7 +245,7 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
 
     out = {"config": {"workload": w.name, "database_graphs": ndb, "queries": int(len(sel)), "K": w.K,
                       "costs": list(w.costs), "streams_per_class": streams,
-                      "method": "bipartite" if method == 1 else "tree",
+                      "method": "bipartite" if method == 1 else "tree", "directed": directed,
                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}}
     srv = ged.Server(db, w.K, w.costs, hbm_budget=8 << 30, streams=streams, max_batch=2048, max_inflight=8192,
                      method=method)
@@ -529,6 +536,8 @@ def main():
     ap.add_argument("--serve-streams", type=int, default=SERVE_STREAMS, help="server streams per size class")
     ap.add_argument("--serve-method", choices=["tree", "bipartite"], default="tree",
                     help="method the serving measurement runs (--workload serve)")
+    ap.add_argument("--serve-directed", action="store_true",
+                    help="serve the directed mix (--workload serve, tree method)")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0 = min(16, cores))")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-perpair", action="store_true")
@@ -561,7 +570,7 @@ def main():
     if args.workload == "serve":
         from paper_2605_00830_amd import synth
         t0 = time.perf_counter()
-        sw = synth.serve_mix(args.serve_db, args.serve_queries)
+        sw = (synth.serve_mix_directed if args.serve_directed else synth.serve_mix)(args.serve_db, args.serve_queries)
         log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
         res = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95), streams=args.serve_streams,
                             method=1 if args.serve_method == "bipartite" else 0)

@@ -354,6 +354,28 @@ def serve_mix(ndb: int = 100000, nqueries: int = 100000) -> Workload:
                     pairs.astype(np.int64), UNIT_COSTS, 64, {"ndb": ndb})
 
 
+def directed_mix_graph(seed: int, index: int) -> Graph:
+    """Directed serving-mix graph: 49.5% small (n 10..30, arc p 0.05..0.15), 49.5% mid
+    (n 33..70, p 0.02..0.06, 3 arc labels), 1% large (n 100..256, p 0.01..0.05, 3 arc labels)."""
+    u = float(uniforms(seed, index, 9, 1)[0])
+    if u < 0.495:
+        return directed_graph(seed, index, 10, 30, 0.05, 0.15, 5, 3)
+    if u < 0.99:
+        return directed_graph(seed, index, 33, 70, 0.02, 0.06, 5, 3)
+    return directed_graph(seed, index, 100, 256, 0.01, 0.05, 5, 3)
+
+
+def serve_mix_directed(ndb: int = 100000, nqueries: int = 100000) -> Workload:
+    """Directed serving stream, laid out as serve_mix: ndb directed mix graphs, then one
+    query graph per query, targets uniform over the database; K=64, unit costs (seed 9)."""
+    graphs = [directed_mix_graph(9, i) for i in range(ndb)]
+    graphs += [directed_mix_graph(9, 10_000_000 + q) for q in range(nqueries)]
+    tgt = _uint_below(uniforms(9, 0, 10, nqueries), ndb)
+    pairs = np.stack([np.arange(ndb, ndb + nqueries, dtype=np.int64), tgt], 1)
+    return Workload(f"serve_mix_directed_db{ndb}_q{nqueries}_k64", GraphSet.from_graphs(graphs),
+                    pairs.astype(np.int64), UNIT_COSTS, 64, {"ndb": ndb, "directed": True})
+
+
 def random_small_graph(seed: int, index: int, n_max: int, p: float, n_vlabels: int,
                        n_elabels: int = 0, n_min: int = 0) -> Graph:
     """Tiny ER graph for property tests: n ~ U{n_min..n_max}; optional uniform edge labels."""
