@@ -313,3 +313,15 @@ def test_graph_replay_and_tune(ged, tmp_path):
     plan.close()
     other.close()
     db.close()
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+@pytest.mark.parametrize("last_level", [0, 1])
+def test_large_costs(ged, schedule, last_level):
+    """Costs of 2^22 and above (the wavefront kernel's full-width cost products) with
+    labelled arcs, both last levels."""
+    big = (4_194_304, 5_000_011, 4_500_007, 30_011, 20_021, 35_003)
+    gs = directed_set(780, 24, 2, 32, 0.05, 0.3, nl=3, nel=3)
+    rng = np.random.default_rng(781)
+    check(ged, gs, rng.integers(0, 24, size=(80, 2)), big, 12, last_level=last_level, schedule=schedule,
+          kinds={"kb_wave2_kernel"} if schedule == 0 else None)
