@@ -208,10 +208,14 @@ def test_server_serves_directed_queries(ged, K):
            + [synth.directed_graph(772, k, 129, 200, 0.01, 0.03, 3, 3) for k in range(2)])
     queries = ([synth.directed_graph(773, k, 3, 32, 0.1, 0.3, 3, 3) for k in range(40)]
                + [synth.directed_graph(774, k, 33, 100, 0.03, 0.08, 3, 3) for k in range(6)]
-               + [synth.directed_graph(775, 0, 140, 140, 0.01, 0.01, 3, 3)])
+               + [synth.directed_graph(775, 0, 140, 140, 0.01, 0.01, 3, 3)]
+               + [synth.directed_graph(777, 0, 0, 0, 0.0, 0.0, 3, 3),          # empty query
+                  synth.directed_graph(778, 0, 256, 256, 0.005, 0.005, 3, 3)])  # the largest order
     rng = np.random.default_rng(776)
-    # small queries against small targets (wavefront class), the rest anywhere
-    targets = [int(rng.integers(0, 20)) if q < 40 else int(rng.integers(0, len(gdb))) for q in range(len(queries))]
+    # small queries against small targets (wavefront class), the rest anywhere; the
+    # empty query against a small target, the largest against a 129..200-vertex one
+    targets = [int(rng.integers(0, 20)) if q < 40 else int(rng.integers(0, len(gdb))) for q in range(47)]
+    targets += [3, len(gdb) - 1]
     db = ged.Database(GraphSet.from_graphs(gdb), directed=True)
     srv = ged.Server(db, K, PAPER, max_batch=16, streams=2)
     results = {}
