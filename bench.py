@@ -58,9 +58,11 @@ def ops_per_candidate(w: int, planes: int) -> int:
     return 4 * w + lab + 16
 
 
+# the files each kernel is compiled from (names in csrc/, or paths from the repository root)
 KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "wave_common.h", "ged_types.h"),
-                  "kb_wave2_kernel": ("kb_wave2.hip", "wave_common.h", "ged_types.h"),
-                  "kb_block_kernel": ("kb_block.hip", "ged_internal.h", "ged_types.h")}
+                  "kb_wave2_kernel": ("kb_wave2.hip", "wave_common.h", "ged_types.h", "ged_internal.h",
+                                      "include/ged.h"),
+                  "kb_block_kernel": ("kb_block.hip", "ged_internal.h", "ged_types.h", "include/ged.h")}
 
 
 def kernel_source_hash(kernel: str) -> str:
@@ -68,7 +70,8 @@ def kernel_source_hash(kernel: str) -> str:
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(ROOT, "paper_2605_00830_amd", "csrc", f), "rb") as fh:
+        path = os.path.join(ROOT, f) if "/" in f else os.path.join(ROOT, "paper_2605_00830_amd", "csrc", f)
+        with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -482,12 +485,26 @@ def directed_measure(ged, steps: int, warmup: int, tune: bool, tune_cache, threa
     ops = float(sum(ops_per_candidate(int(x), 0) * int(c) for x, c in zip(words, ce)))
     kms = float(np.mean(ks))
     achieved = ops / (kms / 1e3) / 1e12
+    # algorithmic HBM bytes: as for the undirected batch, with each graph's rows
+    # twice (out-arc and in-arc blocks)
+    gn = np.asarray(w.graphs.n, np.int64)
+    gbytes = 2 * gn * np.maximum((gn + 31) // 32, 1) * 4 + gn * 4 + 32
+    n1 = gn[w.pairs[:, 0]]
+    alg_bytes = float(gbytes[w.pairs[:, 0]].sum() + gbytes[w.pairs[:, 1]].sum() + 24 * P + (4 + 4 * n1 + 8).sum())
+    bins = plan.bins()
+    tr = measured_traffic(bins[0][0], w.name) if len(bins) == 1 else None
     out = {"config": {"workload": w.name, "pairs": P, "K": w.K, "costs": list(w.costs),
                       "mean_order": round(float(w.graphs.n.mean()), 2), "mean_arcs": round(float(w.graphs.m.mean()), 2)},
            "value": round(P * steps / wall, 2), "unit": "pairs/s", "ms_per_step": round(wall * 1e3 / steps, 4),
            "kernel_ms": round(kms, 4), "bins": plan.bins(),
            "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 2),
                         "unit": "Tops/s", "frac": round(achieved / PEAK_INT32_TOPS, 5),
+                        "traffic": None if tr is None else tr["bytes_per_launch"],
+                        "kernel": bins[0][0] if len(bins) == 1 else None,
+                        "hbm": {"algorithmic_bytes": alg_bytes,
+                                "algorithmic_gbps": round(alg_bytes / (kms / 1e3) / 1e9, 2),
+                                "measured_gbps": None if tr is None else
+                                round(tr["bytes_per_launch"] / (kms / 1e3) / 1e9, 2)},
                         "candidates_per_launch": int(ce.sum()), "ops_per_launch": ops}}
     plan.close()
     db.close()
