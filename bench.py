@@ -572,7 +572,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); pairs are independent, "
-              "so a multi-GPU run would shard the batch, which this build does not do", file=sys.stderr)
+              "so a multi-GPU run would shard the batch over GPUs; sharding is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
         raise SystemExit("--steps must be >= 1 and --warmup >= 0")
