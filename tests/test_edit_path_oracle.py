@@ -85,7 +85,10 @@ def test_every_mapping_of_small_pairs(costs):
 
 @pytest.mark.parametrize("costs", COSTS)
 def test_every_mapping_of_small_directed_pairs(costs):
-    gs = [synth.directed_graph(105, k, 0, 4, 0.45, 0.45, 2, 3) for k in range(8)]
+    """Both graphs of each pair carry arcs, so substitutions onto arcs whose image runs from
+    a higher to a lower g2 index, and insertions of uncovered arcs, both occur."""
+    gs = [synth.directed_graph(105, k, 2, 4, 0.5, 0.5, 2, 3) for k in range(8)]
+    reversed_images = inserted = 0
     for g1, g2 in zip(gs[0::2], gs[1::2]):
         E2 = labelled_edges(g2, True)
         for mp in _pins.all_mappings(int(g1.n), int(g2.n)):
@@ -96,6 +99,9 @@ def test_every_mapping_of_small_directed_pairs(costs):
             vlab, edges = replay(g1, g2, ops, costs, directed=True)
             assert vlab == {u: int(g2.vlabel[u]) for u in range(int(g2.n))}
             assert edges == E2
+            reversed_images += sum(1 for op in ops if op[0] == 3 and op[3] > op[4])
+            inserted += sum(1 for op in ops if op[0] == 5)
+    assert reversed_images > 0 and inserted > 0
 
 
 def test_order_and_cost_of_each_operation():
