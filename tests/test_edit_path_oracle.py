@@ -71,7 +71,11 @@ def replay(g1, g2, ops, costs, directed=False):
 
 @pytest.mark.parametrize("costs", COSTS)
 def test_every_mapping_of_small_pairs(costs):
+    """Degenerate pairs (an empty or edgeless graph) and pairs with edges on both sides, so
+    that edges substituted under order-reversing mappings and edge insertions occur."""
     gs = [synth.random_small_graph(101, k, 4, 0.6, 2, 3) for k in range(8)]
+    gs += [synth.random_small_graph(102, k, 4, 0.7, 2, 3, n_min=3) for k in range(6)]
+    reversing = inserted = 0
     for g1, g2 in zip(gs[0::2], gs[1::2]):
         E2 = labelled_edges(g2)
         for mp in _pins.all_mappings(int(g1.n), int(g2.n)):
@@ -81,6 +85,9 @@ def test_every_mapping_of_small_pairs(costs):
             vlab, edges = replay(g1, g2, ops, costs)
             assert vlab == {u: int(g2.vlabel[u]) for u in range(int(g2.n))}
             assert edges == E2
+            reversing += sum(1 for op in ops if op[0] == 3 and mp[op[1]] > mp[op[2]])
+            inserted += sum(1 for op in ops if op[0] == 5)
+    assert reversing > 0 and inserted > 0
 
 
 @pytest.mark.parametrize("costs", COSTS)
