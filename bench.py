@@ -449,10 +449,11 @@ def complete_measure(ged, db, w, steps: int, warmup: int, literal_dist, tune: bo
     return out, d, maps_np
 
 
-def directed_measure(ged, steps: int, warmup: int, tune: bool, tune_cache, threads: int, check_every: int = 8):
+def directed_measure(ged, steps: int, warmup: int, tune: bool, tune_cache, threads: int, check_every: int = 1):
     """Directed graphs: the 4096-pair directed batch (n 10..30, arcs with p 0.05..0.15,
-    K = 64, unit costs) through the workgroup kernel; kernel time, throughput, parity
-    on every `check_every`-th pair, and the oracle's rate on that sample."""
+    K = 64, unit costs; pairs of up to 32 vertices take the two-word wavefront kernel's
+    directed instantiation); kernel time, throughput, roofline, parity on every
+    `check_every`-th pair (all of them by default), and the oracle's rate on those pairs."""
     import torch
     from paper_2605_00830_amd import synth
     w = synth.batch_directed_10_30(4096)
