@@ -106,6 +106,10 @@ def test_null_handles_are_rejected():
     lib = ged.load()
     out = ctypes.c_int64()
     assert lib.ged_db_count(None, ctypes.byref(out)) == ged.GED_EINVAL
+    flags = ctypes.c_uint32()
+    assert lib.ged_db_flags(None, ctypes.byref(flags)) == ged.GED_EINVAL
+    assert lib.ged_db_create_ex(None, 1, 0, ctypes.byref(ctypes.c_void_p())) == ged.GED_EINVAL
+    assert lib.ged_db_create_ex(None, 0, 0, None) == ged.GED_EINVAL
     assert lib.ged_plan_map_size(None, ctypes.byref(out)) == ged.GED_EINVAL
     assert lib.ged_plan_create(None, None, 0, 4, ctypes.byref(ctypes.c_void_p())) == ged.GED_EINVAL
     assert lib.ged_plan_run(None, ged.Costs(1, 1, 1, 1, 1, 1), None, None, None, None) == ged.GED_EINVAL
