@@ -64,7 +64,9 @@ def _load():
     lib.oracle_induced_cost.restype = ctypes.c_int
     lib.oracle_count_mappings.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.oracle_count_mappings.restype = ctypes.c_double
-    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, ctypes.c_int, P, P, P, P]
+    lib.oracle_kbest_cand.argtypes = graph_args + graph_args + [P, i64, ctypes.c_int, ctypes.c_int, P, P, P]
+    lib.oracle_kbest_cand.restype = ctypes.c_int
+    lib.oracle_kbest_pairs.argtypes = [P] * 9 + [i64, P, i64, ctypes.c_int, ctypes.c_int, P, P, P, P, P]
     lib.oracle_kbest_pairs.restype = ctypes.c_int
     lib.oracle_bipartite.argtypes = graph_args + graph_args + [P, i64, P, P, P, P, P, P, P]
     lib.oracle_bipartite.restype = ctypes.c_int
@@ -97,8 +99,9 @@ def _check(st: int, what: str):
 
 
 def kbest(g1, g2, costs: Sequence[int], K: int, last_complete: bool = False,
-          directed: bool = False) -> Tuple[int, np.ndarray]:
-    """K-Best search g1 -> g2; returns (distance, mapping) with -1 = deleted.
+          directed: bool = False, with_cand: bool = False):
+    """K-Best search g1 -> g2; returns (distance, mapping) with -1 = deleted,
+    and with with_cand also the number of children generated over all levels.
 
     last_complete: complete every child of the last level and keep the least total
     (instead of keeping the K of least partial distance, then completing).
@@ -107,10 +110,14 @@ def kbest(g1, g2, costs: Sequence[int], K: int, last_complete: bool = False,
     keep: list = []
     c = _arr(costs)
     dist = ctypes.c_int64(0)
+    cand = ctypes.c_int64(0)
     mp = np.zeros(max(int(g1.n), 1), dtype=np.int32)
-    st = lib.oracle_kbest_ex(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
-                             1 if last_complete else 0, 1 if directed else 0, ctypes.byref(dist), _ptr(mp))
+    st = lib.oracle_kbest_cand(*_graph_args(g1, keep), *_graph_args(g2, keep), _ptr(c), int(K),
+                               1 if last_complete else 0, 1 if directed else 0, ctypes.byref(dist), _ptr(mp),
+                               ctypes.byref(cand))
     _check(st, "kbest")
+    if with_cand:
+        return int(dist.value), mp[: int(g1.n)].copy(), int(cand.value)
     return int(dist.value), mp[: int(g1.n)].copy()
 
 
@@ -158,10 +165,11 @@ def map_offsets(graphs, pairs: np.ndarray) -> np.ndarray:
 
 
 def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_complete: bool = False,
-                directed: bool = False):
+                directed: bool = False, with_cand: bool = False):
     """Run the oracle over many pairs of a GraphSet.
 
-    Returns (dist int64 [P], maps int32 [sum n_src], offsets int64 [P]).
+    Returns (dist int64 [P], maps int32 [sum n_src], offsets int64 [P]), and with
+    with_cand also the children generated per pair (int64 [P]).
     """
     lib = _load()
     pairs = _arr(pairs, np.int64).reshape(-1, 2)
@@ -178,12 +186,15 @@ def kbest_pairs(graphs, pairs: np.ndarray, costs: Sequence[int], K: int, last_co
     ev = _arr(graphs.ev) if len(graphs.ev) else np.zeros(1, np.int32)
     el = None if graphs.elabel is None else (_arr(graphs.elabel) if len(graphs.elabel) else np.zeros(1, np.int32))
     c = _arr(costs)
+    cand = np.zeros(max(len(pairs), 1), dtype=np.int64)
     failed = ctypes.c_int64(-1)
     st = lib.oracle_kbest_pairs(_ptr(n), _ptr(m), _ptr(voff), _ptr(eoff), _ptr(vl), _ptr(eu),
                                 _ptr(ev), _ptr(el), _ptr(pairs), int(len(pairs)), _ptr(c), int(K),
                                 1 if last_complete else 0, 1 if directed else 0, _ptr(dist), _ptr(maps), _ptr(off),
-                                ctypes.byref(failed))
+                                _ptr(cand), ctypes.byref(failed))
     _check(st, f"kbest_pairs (pair {failed.value})")
+    if with_cand:
+        return dist, maps[:total], off, cand[:len(pairs)]
     return dist, maps[:total], off
 
 

@@ -335,24 +335,37 @@ static int64_t completion(const dgraph *g2, const int32_t *c, const int *used) {
     return t;
 }
 
-int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
-                    const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
-                    const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
-                    int last_complete, int directed, int64_t *dist, int32_t *map_out);
-
-int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
-                 const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
-                 const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
-                 int64_t *dist, int32_t *map_out) {
-    return oracle_kbest_ex(n1, vl1, m1, eu1, ev1, el1, n2, vl2, m2, eu2, ev2, el2, costs, K, 0, 0, dist,
-                           map_out);
-}
+int oracle_kbest_cand(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
+                      const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
+                      const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
+                      int last_complete, int directed, int64_t *dist, int32_t *map_out, int64_t *cand_out);
 
 int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
                     const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
                     const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
                     int last_complete, int directed, int64_t *dist, int32_t *map_out) {
+    return oracle_kbest_cand(n1, vl1, m1, eu1, ev1, el1, n2, vl2, m2, eu2, ev2, el2, costs, K, last_complete,
+                             directed, dist, map_out, NULL);
+}
+
+int oracle_kbest(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
+                 const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
+                 const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
+                 int64_t *dist, int32_t *map_out) {
+    return oracle_kbest_cand(n1, vl1, m1, eu1, ev1, el1, n2, vl2, m2, eu2, ev2, el2, costs, K, 0, 0, dist,
+                             map_out, NULL);
+}
+
+/* The search; *cand_out (may be NULL) gets the number of children generated
+ * over all levels (Alg. 1's branching, Sec. 4.2.1: per level, one child per
+ * unused g2 vertex of every retained node plus its deletion child), each of
+ * which has its partial edit distance evaluated once. */
+int oracle_kbest_cand(int n1, const int32_t *vl1, int m1, const int32_t *eu1, const int32_t *ev1,
+                      const int32_t *el1, int n2, const int32_t *vl2, int m2, const int32_t *eu2,
+                      const int32_t *ev2, const int32_t *el2, const int32_t *costs, int64_t K,
+                      int last_complete, int directed, int64_t *dist, int32_t *map_out, int64_t *cand_out) {
     if (!costs_ok(costs) || K < 1) return OR_EINVAL;
+    int64_t generated = 0;
     dgraph g1, g2;
     int st = dg_build(&g1, n1, vl1, m1, eu1, ev1, el1, directed);
     if (st) return st;
@@ -399,6 +412,7 @@ int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, cons
             keys[C].order = C;
             C++;
         }
+        generated += C;
         int64_t keep;
         if (last_complete && i == n1 - 1) {
             /* last level, complete-then-minimum: each child's partial edit
@@ -467,6 +481,7 @@ int oracle_kbest_ex(int n1, const int32_t *vl1, int m1, const int32_t *eu1, cons
         }
         *dist = best;
         for (int j = 0; j < n1; j++) map_out[j] = phi[best_p * width + j];
+        if (cand_out) *cand_out = generated;
     }
 done:
     free(phi);
@@ -479,19 +494,22 @@ done:
 
 /* Loop of oracle_kbest over many pairs drawn from concatenated graph arrays
  * (the layout of the workload generator); map_out[map_off[p] ..] gets pair p's
- * mapping.  Returns the first non-zero status, with *failed_pair set. */
+ * mapping, cand_out[p] (cand_out may be NULL) its generated children.
+ * Returns the first non-zero status, with *failed_pair set. */
 int oracle_kbest_pairs(const int32_t *n, const int32_t *m, const int64_t *voff,
                        const int64_t *eoff, const int32_t *vlabel, const int32_t *eu,
                        const int32_t *ev, const int32_t *elabel, const int64_t *pairs,
                        int64_t npairs, const int32_t *costs, int64_t K, int last_complete, int directed,
-                       int64_t *dist, int32_t *map_out, const int64_t *map_off, int64_t *failed_pair) {
+                       int64_t *dist, int32_t *map_out, const int64_t *map_off, int64_t *cand_out,
+                       int64_t *failed_pair) {
     for (int64_t p = 0; p < npairs; p++) {
         int64_t a = pairs[2 * p], b = pairs[2 * p + 1];
         const int32_t *el_a = elabel ? elabel + eoff[a] : NULL;
         const int32_t *el_b = elabel ? elabel + eoff[b] : NULL;
-        int st = oracle_kbest_ex(n[a], vlabel + voff[a], m[a], eu + eoff[a], ev + eoff[a], el_a,
-                                 n[b], vlabel + voff[b], m[b], eu + eoff[b], ev + eoff[b], el_b,
-                                 costs, K, last_complete, directed, dist + p, map_out + map_off[p]);
+        int st = oracle_kbest_cand(n[a], vlabel + voff[a], m[a], eu + eoff[a], ev + eoff[a], el_a,
+                                   n[b], vlabel + voff[b], m[b], eu + eoff[b], ev + eoff[b], el_b,
+                                   costs, K, last_complete, directed, dist + p, map_out + map_off[p],
+                                   cand_out ? cand_out + p : NULL);
         if (st) {
             *failed_pair = p;
             return st;

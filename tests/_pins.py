@@ -125,10 +125,11 @@ def partial_cost(g1, g2, c, phi: Sequence[int], directed: bool = False) -> int:
 
 
 def scratch_beam(g1, g2, c, K: int, last_complete: bool = False,
-                 directed: bool = False) -> Tuple[int, List[int]]:
+                 directed: bool = False, count: Optional[List[int]] = None) -> Tuple[int, List[int]]:
     """last_complete: at the last level every child is scored by the cost of its
     complete edit path (the padded-permutation form, qap_cost) and the least
-    (cost, mapping tuple) is returned."""
+    (cost, mapping tuple) is returned.  count (a list, may be None) gets one
+    entry per level: the number of children generated there."""
     n1, n2 = int(g1.n), int(g2.n)
     E2 = edge_dict(g2, directed)
 
@@ -145,6 +146,8 @@ def scratch_beam(g1, g2, c, K: int, last_complete: bool = False,
                     continue
                 ch = phi + (u,)
                 children.append((partial_cost(g1, g2, c, ch, directed), key(ch), ch))
+        if count is not None:
+            count.append(len(children))
         if last_complete and i == n1 - 1:
             best_c = min((qap_cost(g1, g2, c, perm_from_map(ch, n1, n2), directed), key(ch), ch)
                          for _, _, ch in children)

@@ -196,6 +196,36 @@ def test_kbest_matches_scratch_beam(c, K):
         assert (d, m.tolist()) == (d2, m2)
 
 
+@pytest.mark.parametrize("last_complete", [False, True])
+@pytest.mark.parametrize("K", [1, 2, 5, 1000])
+def test_candidate_count_matches_scratch_beam(K, last_complete):
+    """The children the search generates (one per unused g2 vertex of every kept node,
+    plus its deletion, Sec. 4.2.1), summed over the levels, against the from-scratch
+    beam's own child lists."""
+    for g1, g2 in tiny_pairs(10, 261 + K, 5, 0.5, 3, 2):
+        per_level = []
+        _pins.scratch_beam(g1, g2, PAPER, K, last_complete=last_complete, count=per_level)
+        d, m, cand = oracle.kbest(g1, g2, PAPER, K, last_complete=last_complete, with_cand=True)
+        assert cand == sum(per_level)
+
+
+def test_candidate_count_closed_forms():
+    """K = 1: one node per level, whose children are the g2 vertices its path has not
+    used plus the deletion.  K covering the whole tree: level i generates every partial
+    mapping of vertices 0..i, sum over s of C(i+1, s) n2!/(n2-s)! (counted here with
+    math.comb / math.perm, not by the oracle)."""
+    import math
+    for g1, g2 in tiny_pairs(16, 271, 6, 0.4, 3, 0, n_min=1):
+        n1, n2 = int(g1.n), int(g2.n)
+        d, m, cand = oracle.kbest(g1, g2, UNIT, 1, with_cand=True)
+        used = [0] + list(np.cumsum(np.asarray(m) >= 0))
+        assert cand == sum(n2 - used[i] + 1 for i in range(n1))
+        full = sum(math.comb(i, s) * math.perm(n2, s) for i in range(1, n1 + 1) for s in range(min(i, n2) + 1))
+        K = int(oracle.count_mappings(n1, n2))
+        assert oracle.kbest(g1, g2, UNIT, K, with_cand=True)[2] == full
+        assert oracle.kbest(g1, g2, UNIT, K, last_complete=True, with_cand=True)[2] == full
+
+
 @pytest.mark.parametrize("c", [UNIT, PAPER, ODD, HIGH])
 def test_kbest_properties(c):
     """Upper bound of exact; distance equals the induced cost of the mapping;
@@ -265,8 +295,10 @@ def test_full_k_equals_exact_on_8x9_pair():
     w = pair_er_8x9()
     g1, g2 = w.graphs.graph(0), w.graphs.graph(1)
     ex, exmap = oracle.exact(g1, g2, w.costs)
-    d, m = oracle.kbest(g1, g2, w.costs, int(oracle.count_mappings(8, 9)))
+    d, m, cand = oracle.kbest(g1, g2, w.costs, int(oracle.count_mappings(8, 9)), with_cand=True)
     assert d == ex
+    # every level of the whole tree generated: 10 + 91 + ... + 4,596,553 children
+    assert cand == 10 + 91 + 748 + 5509 + 36046 + 207775 + 1047376 + 4596553
     assert oracle.induced_cost(g1, g2, w.costs, m) == ex
     assert oracle.kbest(g1, g2, w.costs, 16)[0] >= ex
 
