@@ -38,7 +38,9 @@ SERVE_STREAMS = 4
 # four size classes x 4 streams need 16 queues of their own, but the process holds
 # other streams as well (torch's, the runtime's): with exactly 17 queues a mid-size
 # stream still shared a queue with a large-query stream (mid p99 55-58 ms at half
-# load); 24 or 32 queues brought it to 1.3 ms in most runs
+# load); with 32 queues the mid class's p99 at half load was 1.3 ms in the last
+# measured run, but at 0.8 of saturation it reached 137 ms: there the bound is how
+# many launches the server's one worker thread can issue, not the queues
 HW_QUEUES = 32
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < HW_QUEUES:
     os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
@@ -300,14 +302,23 @@ def serve_measure(ged, w, n_queries: int, fracs=(0.8,), perpair_queries: int = 2
 # The paper's single-pair runtimes on an A100 (other hardware: context only):
 # runtime versus K for two 20-vertex graphs, and K = 5000 at 500 vertices.
 LARGE_K_RUNS = [(20, 6, 1000, 35.0), (20, 6, 100_000, 120.0), (20, 6, 700_000, 473.0),
-                (20, 6, 1_200_000, 780.0), (500, 7, 5000, 428.0)]
+                (20, 6, 1_200_000, 780.0), (500, 7, 5000, 428.0), (950, 8, 5000, 1000.0)]
+# the oracle's results on these pairs, written by tests/golden/make_digests.py --large-k
+LARGE_K_ORACLE = os.path.join(ROOT, "tests", "golden", "large_k.json")
+# CPU baseline of the single-pair search: the oracle on one of the shapes above
+LARGE_K_CPU = (20, 6, 100_000)
 
 
-def large_k_measure(ged, reps: int = 5):
+def large_k_measure(ged, reps: int = 5, cpu: bool = True):
     """Single-pair large-K search (ged_wide_*) on the paper's runtime shapes: median of
-    `reps` timed runs (HIP events on the launch stream) after one warm-up run."""
+    `reps` timed runs (HIP events on the launch stream) after one warm-up run; parity
+    with the oracle's stored result where there is one; the roofline of a run: its
+    children at ops_per_candidate(target words, planes) each over its duration against
+    the int32 VALU peak, and its candidate-matrix bytes (each child's PED written once
+    and read back by the count and compaction passes, 12 B) against HBM bandwidth."""
     import torch
     from paper_2605_00830_amd import synth
+    stored = json.load(open(LARGE_K_ORACLE)) if os.path.exists(LARGE_K_ORACLE) else {}
     out = []
     for n, seed, K, paper_ms in LARGE_K_RUNS:
         w = synth.pair_er_large_k(n, seed)
@@ -327,14 +338,45 @@ def large_k_measure(ged, reps: int = 5):
             ts.append(e0.elapsed_time(e1))
         ms = float(np.median(ts))
         ce = int(cand.item())
-        out.append({"workload": w.name, "n": n, "K": K, "costs": list(w.costs), "ms": round(ms, 3),
-                    "dist": int(dist.item()), "children_evaluated": ce, "ce_per_s": round(ce / (ms / 1e3), 1),
-                    "workspace_bytes": wide.bytes, "paper_a100_ms": paper_ms,
-                    "ratio_to_paper_a100": round(paper_ms / ms, 1)})
-        log(f"large K: n={n} K={K}: {ms:.3f} ms, {ce / (ms / 1e3):.3e} children/s")
+        d_gpu = int(dist.item())
+        m_gpu = maps[:n].cpu().numpy()
+        words = (n + 31) // 32
+        ops = float(ce) * ops_per_candidate(words, 0)
+        ach = ops / (ms / 1e3) / 1e12
+        entry = {"workload": w.name, "n": n, "K": K, "costs": list(w.costs), "ms": round(ms, 3),
+                 "dist": d_gpu, "children_evaluated": ce, "ce_per_s": round(ce / (ms / 1e3), 1),
+                 "workspace_bytes": wide.bytes, "paper_a100_ms": paper_ms,
+                 "ratio_to_paper_a100": round(paper_ms / ms, 1),
+                 "roofline": {"bound": "alu", "achieved": round(ach, 4), "peak": round(PEAK_INT32_TOPS, 2),
+                              "unit": "Tops/s", "frac": round(ach / PEAK_INT32_TOPS, 5),
+                              "ops_per_child": ops_per_candidate(words, 0),
+                              "candidate_bytes_gbps": round(12.0 * ce / (ms / 1e3) / 1e9, 1),
+                              "candidate_bytes_frac_of_hbm": round(12.0 * ce / (ms / 1e3) / 8.0e12, 5)}}
+        ref = stored.get(f"{w.name}@K{K}")
+        if ref is not None:
+            entry["parity"] = {"oracle": "tests/golden/large_k.json",
+                               "bit_exact": bool(ref["dist"] == d_gpu and ref["children"] == ce and
+                                                 np.array_equal(np.asarray(ref["map"], np.int32), m_gpu))}
+        else:
+            entry["parity"] = "parity unpinned: no stored oracle result for this shape"
+        out.append(entry)
+        log(f"large K: n={n} K={K}: {ms:.3f} ms, {ce / (ms / 1e3):.3e} children/s, parity {entry['parity']}")
         wide.close()
         db.close()
-    return out
+    if cpu:
+        # the oracle (one thread: it is one pair) on one of the shapes
+        import oracle
+        n, seed, K = LARGE_K_CPU
+        w = synth.pair_er_large_k(n, seed)
+        t0 = time.perf_counter()
+        d, m, _, c = oracle.kbest_pairs(w.graphs, w.pairs, w.costs, K, with_cand=True)
+        sec = time.perf_counter() - t0
+        cb = {"value": round(1.0 / sec, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+              "sample": f"{w.name} at K={K}: {int(c[0])} children in {sec:.2f} s",
+              "children_per_s": round(int(c[0]) / sec, 1)}
+    else:
+        cb = None
+    return {"runs": out, "cpu_baseline": cb}
 
 
 # int32 operations per column relaxation of the bipartite method's solver
@@ -523,6 +565,94 @@ def directed_measure(ged, steps: int, warmup: int, tune: bool, tune_cache, threa
     return out
 
 
+def alu_roofline(w, ce: np.ndarray, kms: float, bins, kernel: str) -> dict:
+    """Roofline of one batched launch: algorithmic int32 operations (ops_per_candidate per
+    evaluated child, from each pair's target words and the database's label planes) over
+    the launch's duration, against the int32 VALU peak; and its algorithmic HBM bytes
+    (both graphs' packed rows and labels, work item in; distance, mapping, count out)."""
+    P = len(w.pairs)
+    n2 = np.asarray(w.graphs.n, np.int64)[w.pairs[:, 1]]
+    words = np.maximum((n2 + 31) // 32, 1)
+    planes = 0
+    if w.graphs.elabel is not None:
+        nl = len(np.unique(w.graphs.elabel))
+        while (1 << planes) < nl:
+            planes += 1
+    ops = float(sum(ops_per_candidate(int(x), planes) * int(c) for x, c in zip(words, ce)))
+    achieved = ops / (kms / 1e3) / 1e12
+    gn = np.asarray(w.graphs.n, np.int64)
+    gw = np.maximum((gn + 31) // 32, 1)
+    gbytes = gn * gw * 4 * (1 + planes) + gn * 4 + 32
+    n1 = gn[w.pairs[:, 0]]
+    alg_bytes = float(gbytes[w.pairs[:, 0]].sum() + gbytes[w.pairs[:, 1]].sum() + 24 * P + (4 + 4 * n1 + 8).sum())
+    hbm_peak = 8.0e12
+    hbm = {"algorithmic_bytes": alg_bytes,
+           "algorithmic_gbps": round(alg_bytes / (kms / 1e3) / 1e9, 2),
+           "algorithmic_frac": round(alg_bytes / (kms / 1e3) / hbm_peak, 6),
+           "peak_gbps": hbm_peak / 1e9}
+    return {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_INT32_TOPS, 2),
+            "unit": "Tops/s", "frac": round(achieved / PEAK_INT32_TOPS, 5), "traffic": None,
+            "ce_per_s": round(float(ce.sum()) / (kms / 1e3), 1), "hbm": hbm,
+            "kernel": kernel, "kernel_ms": round(kms, 4), "bins": bins,
+            "candidates_per_launch": int(ce.sum()), "ops_per_launch": ops}
+
+
+def config_measure(ged, name: str, steps: int, warmup: int, tune: bool, tune_cache, threads: int,
+                   cpu: bool = True) -> dict:
+    """One more of the batched workloads (the molecule query batch, the large-pair
+    stress batch): pairs/s over timed steps, the roofline of its launch (all of its
+    bins), the oracle on the workload's bounded sample with the same threads (its
+    CPU baseline) and a bit-exact comparison of that sample with the GPU results."""
+    import torch
+    w, sample_n = workload(name)
+    P = len(w.pairs)
+    db = ged.Database(w.graphs)
+    plan = ged.Plan(db, w.pairs, w.K)
+    dist, maps, cand = plan.outputs(with_cand=True)
+    s = torch.cuda.current_stream()
+    plan.set_timing(True)
+    if tune:
+        plan.tune(w.costs, dist, maps, stream=s, cache_path=tune_cache)
+        s.synchronize()
+    for _ in range(warmup):
+        plan.run(w.costs, dist, maps, cand, stream=s)
+        s.synchronize()
+    ks = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(w.costs, dist, maps, cand, stream=s)
+        s.synchronize()
+        ks.append(plan.kernel_ms())
+    wall = time.perf_counter() - t0
+    kms = float(np.mean(ks))
+    bins = plan.bins()
+    ce = cand[:P].cpu().numpy().astype(np.int64)
+    gpu_dist = dist[:P].cpu().numpy()
+    gpu_maps = maps[:plan.map_size].cpu().numpy()
+    dominant = max(bins, key=lambda b: b[1])[0] if bins else "none"
+    out = {"config": {"workload": w.name, "pairs": P, "K": w.K, "costs": list(w.costs)},
+           "value": round(P * steps / wall, 2), "unit": "pairs/s", "ms_per_step": round(wall * 1e3 / steps, 4),
+           "roofline": alu_roofline(w, ce, kms, bins, dominant)}
+    log(f"{w.name}: {out['ms_per_step']} ms/step, kernel {kms:.3f} ms, {out['value']:.0f} pairs/s, "
+        f"{out['roofline']['frac']:.4f} of the int32 peak")
+    if cpu:
+        sample = np.arange(min(sample_n, P))
+        cw, cd, cm = cpu_oracle(w.graphs, w.pairs[sample], w.costs, w.K, min(threads, len(sample)))
+        used = min(threads, len(sample))
+        out["cpu_baseline"] = {"value": round(len(sample) / cw, 3), "unit": "pairs/s", "cores": used,
+                               "kind": "oracle",
+                               "sample": f"first {len(sample)} of {P} pairs, {used} threads, {cw:.2f} s wall"}
+        n_src = np.asarray(w.graphs.n, np.int64)[w.pairs[:, 0]]
+        moff = np.concatenate([[0], np.cumsum(n_src)])
+        g_sel = np.concatenate([gpu_maps[moff[p]:moff[p + 1]] for p in sample])
+        out["parity"] = {"pairs_checked": int(len(sample)),
+                         "bit_exact": bool(np.array_equal(gpu_dist[sample], cd) and np.array_equal(g_sel, cm))}
+        log(f"{w.name}: oracle {out['cpu_baseline']['value']} pairs/s, parity {out['parity']}")
+    plan.close()
+    db.close()
+    return out
+
+
 def workload(name: str):
     from paper_2605_00830_amd import synth
     if name == "batch":
@@ -564,6 +694,10 @@ def main():
     ap.add_argument("--no-bipartite", action="store_true",
                     help="skip the bipartite K-best-assignment measurement")
     ap.add_argument("--no-directed", action="store_true", help="skip the directed-graph measurement")
+    ap.add_argument("--eager", action="store_true",
+                    help="time eager plan runs instead of replays of the plan's captured HIP graph")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the molecule query and large-pair stress batches of the default run")
     ap.add_argument("--no-tune", action="store_true", help="keep the plan's default schedule (no autotuning)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file: reuse its choices, append new ones (default: tune afresh)")
@@ -583,7 +717,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.large_k_only:
-        print(json.dumps({"large_k": large_k_measure(ged)}), flush=True)
+        print(json.dumps({"large_k": large_k_measure(ged, cpu=not args.no_cpu_baseline)}), flush=True)
         return
     if args.workload == "serve":
         from paper_2605_00830_amd import synth
@@ -631,6 +765,7 @@ def main():
         plan.run(w.costs, dist, maps, cand, stream=stream)
         stream.synchronize()
     torch.cuda.synchronize()
+    # the search kernels' duration: the plan's HIP events around them, eager runs
     kernel_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -638,11 +773,31 @@ def main():
         stream.synchronize()
         kernel_ms.append(plan.kernel_ms())
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    value = P / (ms_per_step / 1e3)
+    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     kms = float(np.mean(kernel_ms))
-    log(f"batched: {ms_per_step:.3f} ms/step, kernel {kms:.3f} ms, {value:.0f} pairs/s")
+    launch = "eager"
+    if args.eager:
+        ms_per_step = eager_ms
+    else:
+        # the timed steps: the plan's run captured once as a HIP graph (kernel nodes
+        # only) and replayed on a stream of its own, each step followed by a
+        # synchronize of that stream
+        gstream = torch.cuda.Stream()
+        plan.capture(w.costs, dist, maps, cand, stream=gstream)
+        for _ in range(args.warmup):
+            plan.replay(stream=gstream)
+            gstream.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.replay(stream=gstream)
+            gstream.synchronize()
+        torch.cuda.synchronize()
+        ms_per_step = (time.perf_counter() - t0) * 1e3 / args.steps
+        launch = "hip_graph"
+    value = P / (ms_per_step / 1e3)
+    log(f"batched ({launch}): {ms_per_step:.3f} ms/step (eager {eager_ms:.3f}), kernel {kms:.3f} ms, "
+        f"{value:.0f} pairs/s")
 
     gpu_dist = dist[:P].cpu().numpy()
     gpu_maps = maps[:plan.map_size].cpu().numpy()
@@ -792,9 +947,16 @@ def main():
                                    "ops_per_relaxation": BIP_OPS_PER_RELAX, "ops_per_launch": ops}
             log(f"bipartite oracle: {len(sample) / bw:.1f} pairs/s; parity {bip['parity']['bit_exact']}")
 
+    configs = None
+    if not args.no_configs and args.workload == "batch":
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        configs = {nm: config_measure(ged, nm, max(3, args.steps // 4), 1, not args.no_tune, args.tune_cache,
+                                      threads, cpu=not args.no_cpu_baseline)
+                   for nm in ("query", "stress")}
+
     large_k = None
     if not args.no_large_k and args.workload == "batch":
-        large_k = large_k_measure(ged)
+        large_k = large_k_measure(ged, cpu=not args.no_cpu_baseline)
 
     serving = None
     if not args.no_serve and args.workload == "batch":
@@ -802,7 +964,7 @@ def main():
         t0 = time.perf_counter()
         sw = synth.serve_mix(args.serve_db, args.serve_queries)
         log(f"serving workload generated in {time.perf_counter() - t0:.1f} s")
-        serving = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8), streams=args.serve_streams)
+        serving = serve_measure(ged, sw, args.serve_queries, fracs=(0.5, 0.8, 0.95), streams=args.serve_streams)
 
     out = {
         "metric": METRIC,
@@ -817,7 +979,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": w.name, "pairs": P, "K": w.K, "costs": list(w.costs)},
+        "config": {"workload": w.name, "pairs": P, "K": w.K, "costs": list(w.costs), "launch": launch},
+        "eager_ms_per_step": round(eager_ms, 4),
         "perpair": perpair,
         "speedup_vs_perpair": None if perpair is None else round(value / perpair["value"], 2),
         "roofline": roofline,
@@ -827,6 +990,7 @@ def main():
         "complete_then_min": complete,
         "bipartite": bip,
         "directed": directed,
+        "configs": configs,
         "large_k": large_k,
         "serving": serving,
     }

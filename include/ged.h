@@ -52,10 +52,11 @@
 extern "C" {
 #endif
 
-#define GED_ABI_VERSION 5
+#define GED_ABI_VERSION 6
 
 /* Limits of this version. */
-#define GED_MAX_VERTICES 512      /* per graph */
+#define GED_MAX_VERTICES 1024     /* per graph: databases, the single-pair search, edit paths */
+#define GED_MAX_VERTICES_BATCH 512  /* per graph of a pair: batched plans, the per-pair path, serving */
 #define GED_MAX_K 1024            /* beam width (batched plans, serving) */
 #define GED_MAX_K_WIDE (1 << 21)  /* beam width of the single-pair large-K search */
 #define GED_MAX_EDGE_LABELS 16    /* distinct edge labels in one database */
@@ -173,6 +174,11 @@ ged_status ged_db_order(const ged_db *db, int64_t id, int32_t *n);
  * Errors (host-side, nothing enqueued): GED_EINVAL (negative cost, NULL
  * output with npairs > 0, costs that could overflow int32 on some pair of
  * the plan); GED_EDEVICE (launch failure).
+ * ged_plan_create errors: GED_EINVAL (a graph id out of range, K < 1);
+ * GED_EUNSUPPORTED (K > GED_MAX_K, a pair with a graph of more than
+ * GED_MAX_VERTICES_BATCH vertices -- the single-pair search ged_wide_*
+ * takes those); with GED_PLAN_PAIR_STATUS the per-pair ones become
+ * statuses of their pairs instead.
  * ---------------------------------------------------------------------- */
 ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                            ged_plan **out);
@@ -210,21 +216,43 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
 #define GED_METHOD_TREE 0
 #define GED_METHOD_BIPARTITE 1
 
+/* Plan flags.
+ * GED_PLAN_PAIR_STATUS: a pair that cannot be searched does not fail the
+ * plan; it is set aside with a status of its own, which ged_plan_run_ex
+ * reports per pair (the problem statement's result is per pair of graphs,
+ * Alg. 1): GED_EINVAL for a graph id out of range, GED_EUNSUPPORTED for a
+ * pair beyond the method's limits (a graph of more than
+ * GED_MAX_VERTICES_BATCH vertices; directed graphs of more than
+ * GED_DIRECTED_MAX_ORDER; the bipartite method's GED_BIP_MAX_ORDER).  A
+ * set-aside pair's distance is -1, its mapping entries (n of its source
+ * graph; none for a source id out of range) are -1 and its d_cand entry 0.
+ * The other pairs' results are the same as without the flag. */
+#define GED_PLAN_PAIR_STATUS 1u
+
 typedef struct {
     int32_t schedule;        /* GED_SCHED_* */
     int32_t groups_per_cu;   /* resident workgroups per CU of a persistent launch;
                                 0 = the occupancy limit, larger values are clamped to it */
     int32_t last_level;      /* GED_LAST_* */
     int32_t method;          /* GED_METHOD_* */
+    uint32_t flags;          /* GED_PLAN_* bits, 0 = none */
 } ged_plan_options;
 
 /* ged_plan_create with options (NULL = defaults).  GED_EINVAL for an
- * unknown schedule, last level or method, or groups_per_cu < 0. */
+ * unknown schedule, last level, method or flag bit, or groups_per_cu < 0. */
 ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                               const ged_plan_options *options, ged_plan **out);
 ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries);
 ged_status ged_plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
                         int64_t *d_cand, void *stream);
+/* ged_plan_run with per-pair statuses: d_status[p] (int32 [npairs], device,
+ * may be NULL) receives GED_OK for a searched pair and, in a plan created
+ * with GED_PLAN_PAIR_STATUS, the status of each set-aside pair (whose
+ * outputs are written as that flag states).  Enqueues only kernels.  Errors
+ * as ged_plan_run: costs that could overflow int32 on a searched pair fail
+ * the whole call (GED_EINVAL, nothing enqueued). */
+ged_status ged_plan_run_ex(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                           int32_t *d_status, void *stream);
 /* The plan's pairs again, as the per-pair baseline: one kernel launch per
  * pair, back to back on `stream`, same outputs as ged_plan_run. */
 ged_status ged_plan_run_perpair(ged_plan *plan, ged_costs costs, int32_t *d_dist,
@@ -289,6 +317,26 @@ ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_co
 ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs,
                              ged_costs costs, int32_t K, int32_t *d_dist, int32_t *d_map,
                              void *stream);
+/* One-shot form with options (NULL = defaults), the children evaluated
+ * (d_cand, may be NULL) and per-pair statuses (d_status, may be NULL; see
+ * ged_plan_run_ex and GED_PLAN_PAIR_STATUS). */
+ged_status ged_kbest_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs, int32_t K,
+                        const ged_plan_options *options, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                        int32_t *d_status, void *stream);
+
+/* Mapping offsets on the device (the layout of every search's d_map: pair
+ * p's mapping of its source graph g1, n1 entries, one per vertex of g1 as in
+ * Alg. 1's edit path, starts at the sum of n1 over the pairs before it).
+ * d_pairs: npairs pairs in device memory (caller's order); d_off: device,
+ * npairs + 1 int64 entries: d_off[p] for p < npairs as above, d_off[npairs]
+ * the total (the d_map entries the batch needs).  A pair whose source id is
+ * outside the database contributes no entries (a search with
+ * GED_PLAN_PAIR_STATUS reports it GED_EINVAL).  Enqueued on `stream` (one
+ * kernel); allocates nothing.  Errors: GED_EINVAL (NULL db or d_off, NULL
+ * d_pairs with npairs > 0, npairs < 0, a device other than the database's);
+ * GED_EDEVICE. */
+ged_status ged_map_offsets(ged_db *db, const ged_pair *d_pairs, int64_t npairs, int64_t *d_off, void *stream);
+
 
 /* ------------------------------------------------------------------------
  * Edit paths.  A vertex mapping (as the searches return it) induces one edit
@@ -439,9 +487,18 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
 /* Queue one query; *ticket identifies it.  GED_EINVAL for an invalid query
  * graph (as for ged_db_create; also an edge label absent from the database)
  * or target id, or costs that could overflow int32 on this pair;
- * GED_EUNSUPPORTED for n > GED_MAX_VERTICES; GED_EBUSY when the queue is full
+ * GED_EUNSUPPORTED when the query or the target has more than
+ * GED_MAX_VERTICES_BATCH vertices; GED_EBUSY when the queue is full
  * (backpressure: retry later). */
 ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t target_id, uint64_t *ticket);
+
+/* Queue one query whose graph is database graph `query_id` (Sec. 5's
+ * query-versus-database setting: a database graph searched against another):
+ * no host graph is passed, validated or packed; the batch copies the
+ * graph's packed rows from the database on the device.  Same results and
+ * errors as ged_server_submit with that graph (GED_EINVAL also for
+ * query_id out of range). */
+ged_status ged_server_submit_id(ged_server *srv, int64_t query_id, int64_t target_id, uint64_t *ticket);
 
 /* Non-blocking: GED_OK writes the distance and the mapping (n1 entries,
  * -1 = deleted; *n1 gets n1) and releases the ticket; GED_EBUSY if the query

@@ -78,7 +78,7 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
 
 // Wavefront family that fits a pair: 1 (n1, n2 <= 32), 2 (n1, n2 <= 64), 0
 // none (K > 64 or a larger graph).
-inline int wave_words_for(int n1, int n2, int K) {
+__host__ __device__ inline int wave_words_for(int n1, int n2, int K) {
     if (K > kWaveMaxK) return 0;
     const int n = n1 > n2 ? n1 : n2;
     return n <= kWaveMaxN ? 1 : (n <= kWave2MaxN ? 2 : 0);
@@ -91,7 +91,7 @@ hipError_t launch_wave2_dir(int PL, const DbView &src, const DbView &dst, const 
                             Costs c, int K, int last_complete, int directed, Outputs out, int grid,
                             hipStream_t stream);
 // Wavefront family of a directed pair: 2 when both orders are <= 32 and K <= 64.
-inline int wave_words_for_directed(int n1, int n2, int K) {
+__host__ __device__ inline int wave_words_for_directed(int n1, int n2, int K) {
     return (K <= kWaveMaxK && n1 <= kWaveMaxN && n2 <= kWaveMaxN) ? 2 : 0;
 }
 
@@ -110,4 +110,21 @@ inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const
                       : launch_wave2(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream);
 }
 
+// Copy of one database graph into a serving arena (word and label offsets
+// into the two pools).
+struct GatherItem {
+    int64_t src_adj, dst_adj, words;
+    int64_t src_vlab, dst_vlab, nv;
+};
+
+// kb_aux.hip.
+// off[p] (p < np) = sum of n(src) over the pairs before p; off[np] = total.
+hipError_t launch_map_offsets(const GraphRec *graphs, int64_t count, const ged_pair *pairs, int64_t np, int64_t *off,
+                              hipStream_t stream);
+// status_out[p] = status[p] (status_out may be null); set-aside pairs (out,
+// src = mapping entries, map_off) get dist -1, mapping -1, cand 0.
+hipError_t launch_pair_status(const int32_t *status, int64_t np, int32_t *status_out, const WorkItem *aside,
+                              int naside, int32_t *dist, int32_t *map, int64_t *cand, hipStream_t stream);
+hipError_t launch_gather_graphs(const GatherItem *items, int nitems, const uint32_t *src_adj, uint32_t *dst_adj,
+                                const int32_t *src_vlab, int32_t *dst_vlab, hipStream_t stream);
 }  // namespace gedk

@@ -74,6 +74,15 @@ struct ged_plan {
     int64_t launches = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    uint32_t flags = 0;                 // GED_PLAN_* bits
+    int32_t *d_status = nullptr;        // [npairs] GED_OK, or why the pair was set aside
+    WorkItem *d_aside = nullptr;        // set-aside pairs: out, src = mapping entries, map_off
+    int naside = 0;
+    // bins after the first run on streams of their own, forked from and
+    // joined to the caller's stream by events (parallel branches when captured)
+    std::vector<hipStream_t> side;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
 };
 
 namespace {
@@ -95,6 +104,11 @@ void free_plan(ged_plan *p) {
     }
     if (p->ev_start) (void)hipEventDestroy(p->ev_start);
     if (p->ev_stop) (void)hipEventDestroy(p->ev_stop);
+    if (p->d_status) (void)hipFree(p->d_status);
+    if (p->d_aside) (void)hipFree(p->d_aside);
+    for (hipStream_t st : p->side) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : p->ev_join) (void)hipEventDestroy(ev);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     delete p;
 }
 
@@ -255,20 +269,37 @@ ged_status prepare_run(ged_plan *plan, const ged_costs &costs, int32_t *d_dist, 
 }
 
 ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
-                    void *stream, bool perpair, bool allow_timing) {
+                    int32_t *d_status, void *stream, bool perpair, bool allow_timing) {
     RunCtx r;
     ged_status st = prepare_run(plan, costs, d_dist, d_map, d_cand, stream, &r);
     if (st != GED_OK) return st;
     for (Bin &b : plan->bins) GED_HIP(gedk::launch_fill_zero(b.d_queue, (int)b.h_work.size() + 1, r.s));
+    GED_HIP(gedk::launch_pair_status(plan->d_status, plan->npairs, d_status, plan->d_aside, plan->naside, d_dist,
+                                     d_map, d_cand, r.s));
     const bool timing = plan->timing && allow_timing;
     plan->timed_run = false;
     plan->launches = 0;
     if (timing) GED_HIP(hipEventRecord(plan->ev_start, r.s));
-    for (Bin &b : plan->bins) {
+    // the bins are independent: after the first (on the caller's stream)
+    // each runs on a stream of its own, so a bin's last pairs overlap the
+    // others instead of every bin's tail adding up; the per-pair baseline
+    // stays one launch after another
+    const bool fork = !perpair && plan->bins.size() > 1 && !plan->side.empty();
+    if (fork) GED_HIP(hipEventRecord(plan->ev_fork, r.s));
+    for (size_t k = 0; k < plan->bins.size(); ++k) {
+        Bin &b = plan->bins[k];
         plan->launches += perpair ? (int64_t)b.h_work.size() : 1;
-        st = launch_bin(plan, b, r, perpair);
+        RunCtx rb = r;
+        if (fork && k > 0) {
+            rb.s = plan->side[(k - 1) % plan->side.size()];
+            GED_HIP(hipStreamWaitEvent(rb.s, plan->ev_fork, 0));
+        }
+        st = launch_bin(plan, b, rb, perpair);
         if (st != GED_OK) return st;
+        if (fork && k > 0) GED_HIP(hipEventRecord(plan->ev_join[k - 1], rb.s));
     }
+    if (fork)
+        for (size_t k = 1; k < plan->bins.size(); ++k) GED_HIP(hipStreamWaitEvent(r.s, plan->ev_join[k - 1], 0));
     if (timing) {
         GED_HIP(hipEventRecord(plan->ev_stop, r.s));
         plan->timed_run = true;
@@ -332,8 +363,10 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
 
 ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, int32_t K,
                               const ged_plan_options *options, ged_plan **out) {
-    ged_plan_options opt{GED_SCHED_AUTO, 0, GED_LAST_SELECT, GED_METHOD_TREE};
+    ged_plan_options opt{GED_SCHED_AUTO, 0, GED_LAST_SELECT, GED_METHOD_TREE, 0u};
     if (options) opt = *options;
+    if (opt.flags & ~GED_PLAN_PAIR_STATUS) return fail(GED_EINVAL, "unknown plan flags 0x%x", opt.flags);
+    const bool lenient = (opt.flags & GED_PLAN_PAIR_STATUS) != 0;
     if (opt.method != GED_METHOD_TREE && opt.method != GED_METHOD_BIPARTITE)
         return fail(GED_EINVAL, "unknown method %d", opt.method);
     const bool bip = opt.method == GED_METHOD_BIPARTITE;
@@ -365,8 +398,11 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     p->K = K;
     p->last_complete = opt.last_level == GED_LAST_COMPLETE ? 1 : 0;
     p->method = opt.method;
+    p->flags = opt.flags;
     p->pair_n.resize((size_t)npairs);
     p->pair_m.resize((size_t)npairs);
+    std::vector<int32_t> h_status((size_t)npairs, (int32_t)GED_OK);
+    std::vector<WorkItem> h_aside;
 
     // bins keyed by kernel: -1 / -2 = wavefront kernel for n <= 32 / 64,
     // -3 .. -6 = bipartite kernel with 1 .. 4 columns per lane, else target
@@ -378,7 +414,24 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     int64_t off = 0;
     for (int64_t i = 0; i < npairs; ++i) {
         const int64_t s = h_pairs[i].src, d = h_pairs[i].dst;
+        // a pair that cannot be searched: fail the plan, or set it aside
+        // with its status (its mapping entries still take their place)
+        auto refuse = [&](ged_status why, int n1) {
+            WorkItem wi{};
+            wi.src = n1;
+            wi.out = (int32_t)i;
+            wi.map_off = off;
+            h_aside.push_back(wi);
+            h_status[(size_t)i] = (int32_t)why;
+            p->pair_n[(size_t)i] = 0;
+            p->pair_m[(size_t)i] = 0;
+            off += n1;
+        };
         if (s < 0 || s >= db->count || d < 0 || d >= db->count) {
+            if (lenient) {
+                refuse(GED_EINVAL, (s >= 0 && s < db->count) ? db->h_graphs[(size_t)s].n : 0);
+                continue;
+            }
             free_plan(p);
             return fail(GED_EINVAL, "pair %lld: graph id out of range", (long long)i);
         }
@@ -386,15 +439,27 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const GraphRec &g2 = db->h_graphs[(size_t)d];
         p->pair_n[(size_t)i] = (int64_t)g1.n + g2.n;
         p->pair_m[(size_t)i] = (int64_t)g1.m + g2.m;
+        const char *beyond = nullptr;
+        char why[160];
         if (db->directed && std::max(g1.n, g2.n) > GED_DIRECTED_MAX_ORDER) {
-            free_plan(p);
-            return fail(GED_EUNSUPPORTED, "pair %lld: directed graphs of more than %d vertices", (long long)i,
-                        GED_DIRECTED_MAX_ORDER);
+            snprintf(why, sizeof why, "directed graphs of more than %d vertices", GED_DIRECTED_MAX_ORDER);
+            beyond = why;
+        } else if (bip && g1.n + g2.n > GED_BIP_MAX_ORDER) {
+            snprintf(why, sizeof why, "n1 + n2 = %d exceeds the bipartite method's %d", g1.n + g2.n,
+                     GED_BIP_MAX_ORDER);
+            beyond = why;
+        } else if (std::max(g1.n, g2.n) > GED_MAX_VERTICES_BATCH) {
+            snprintf(why, sizeof why, "a graph of %d vertices exceeds the batched search's %d (ged_wide_* takes it)",
+                     std::max(g1.n, g2.n), GED_MAX_VERTICES_BATCH);
+            beyond = why;
         }
-        if (bip && g1.n + g2.n > GED_BIP_MAX_ORDER) {
+        if (beyond) {
+            if (lenient) {
+                refuse(GED_EUNSUPPORTED, g1.n);
+                continue;
+            }
             free_plan(p);
-            return fail(GED_EUNSUPPORTED, "pair %lld: n1 + n2 = %d exceeds the bipartite method's %d", (long long)i,
-                        g1.n + g2.n, GED_BIP_MAX_ORDER);
+            return fail(GED_EUNSUPPORTED, "pair %lld: %s", (long long)i, beyond);
         }
         const int ww = (bip || opt.schedule != GED_SCHED_AUTO) ? 0
                        : db->directed ? gedk::wave_words_for_directed(g1.n, g2.n, K)
@@ -430,6 +495,38 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
     if (e != hipSuccess) {
         free_plan(p);
         return fail(GED_EDEVICE, "device query failed: %s", hipGetErrorString(e));
+    }
+    // per-pair statuses and the set-aside pairs' output records
+    p->naside = (int)h_aside.size();
+    e = hipMalloc((void **)&p->d_status, sizeof(int32_t) * (size_t)std::max<int64_t>(npairs, 1));
+    if (e == hipSuccess && npairs > 0)
+        e = hipMemcpy(p->d_status, h_status.data(), sizeof(int32_t) * (size_t)npairs, hipMemcpyHostToDevice);
+    if (e == hipSuccess && p->naside > 0) {
+        e = hipMalloc((void **)&p->d_aside, sizeof(WorkItem) * h_aside.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_aside, h_aside.data(), sizeof(WorkItem) * h_aside.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(GED_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
+    }
+    // streams and events for running the bins side by side (default
+    // priority; at most three extra streams, bins beyond share them in turn)
+    const size_t nside = std::min<size_t>(bins.size() > 0 ? bins.size() - 1 : 0, 3);
+    for (size_t k = 0; k < nside && e == hipSuccess; ++k) {
+        hipStream_t st = nullptr;
+        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e == hipSuccess) p->side.push_back(st);
+    }
+    if (e == hipSuccess && nside > 0) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    for (size_t k = 0; k + 1 < bins.size() && nside > 0 && e == hipSuccess; ++k) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) p->ev_join.push_back(ev);
+    }
+    if (e != hipSuccess) {
+        free_plan(p);
+        return fail(GED_EDEVICE, "stream or event creation failed: %s", hipGetErrorString(e));
     }
 
     for (auto &kv : bins) {
@@ -496,12 +593,17 @@ ged_status ged_plan_map_size(const ged_plan *plan, int64_t *entries) {
 
 ged_status ged_plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
                         void *stream) {
-    return plan_run(plan, costs, d_dist, d_map, d_cand, stream, false, true);
+    return plan_run(plan, costs, d_dist, d_map, d_cand, nullptr, stream, false, true);
+}
+
+ged_status ged_plan_run_ex(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                           int32_t *d_status, void *stream) {
+    return plan_run(plan, costs, d_dist, d_map, d_cand, d_status, stream, false, true);
 }
 
 ged_status ged_plan_run_perpair(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d_map,
                                 int64_t *d_cand, void *stream) {
-    return plan_run(plan, costs, d_dist, d_map, d_cand, stream, true, true);
+    return plan_run(plan, costs, d_dist, d_map, d_cand, nullptr, stream, true, true);
 }
 
 ged_status ged_plan_destroy(ged_plan *plan) {
@@ -560,7 +662,7 @@ ged_status ged_plan_capture(ged_plan *plan, ged_costs costs, int32_t *d_dist, in
     if (st != GED_OK) return st;
     drop_graph(plan);
     GED_HIP(hipStreamBeginCapture(r.s, hipStreamCaptureModeThreadLocal));
-    st = plan_run(plan, costs, d_dist, d_map, d_cand, stream, false, false);
+    st = plan_run(plan, costs, d_dist, d_map, d_cand, nullptr, stream, false, false);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(r.s, &g);
     if (st != GED_OK) {
@@ -675,7 +777,7 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     (void)hipEventDestroy(e1);
     if (st != GED_OK) return st;
     // leave the outputs holding a full result with the chosen configuration
-    st = plan_run(plan, costs, d_dist, d_map, nullptr, stream, false, false);
+    st = plan_run(plan, costs, d_dist, d_map, nullptr, nullptr, stream, false, false);
     if (st != GED_OK) return st;
     GED_HIP(hipStreamSynchronize(r.s));
     if (timed_bins) *timed_bins = timed;
@@ -689,11 +791,39 @@ ged_status ged_kbest(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_co
     ged_plan *p = nullptr;
     st = ged_plan_create(db, h_pairs, npairs, K, &p);
     if (st != GED_OK) return st;
-    st = plan_run(p, costs, d_dist, d_map, nullptr, stream, false, false);
+    st = plan_run(p, costs, d_dist, d_map, nullptr, nullptr, stream, false, false);
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     free_plan(p);
     if (st != GED_OK) return st;
     if (e != hipSuccess) return fail(GED_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+ged_status ged_kbest_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs, int32_t K,
+                        const ged_plan_options *options, int32_t *d_dist, int32_t *d_map, int64_t *d_cand,
+                        int32_t *d_status, void *stream) {
+    ged_status st = gedh::check_costs(costs);
+    if (st != GED_OK) return st;
+    ged_plan *p = nullptr;
+    st = ged_plan_create_ex(db, h_pairs, npairs, K, options, &p);
+    if (st != GED_OK) return st;
+    st = plan_run(p, costs, d_dist, d_map, d_cand, d_status, stream, false, false);
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    free_plan(p);
+    if (st != GED_OK) return st;
+    if (e != hipSuccess) return fail(GED_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(e));
+    return ok();
+}
+
+ged_status ged_map_offsets(ged_db *db, const ged_pair *d_pairs, int64_t npairs, int64_t *d_off, void *stream) {
+    if (!db) return fail(GED_EINVAL, "db is NULL");
+    if (!d_off) return fail(GED_EINVAL, "d_off is NULL");
+    if (npairs < 0) return fail(GED_EINVAL, "npairs < 0");
+    if (npairs > 0 && !d_pairs) return fail(GED_EINVAL, "d_pairs is NULL");
+    ged_status st = gedh::check_device(db);
+    if (st != GED_OK) return st;
+    GED_HIP(gedk::launch_map_offsets(db->d_graphs, db->count, d_pairs, npairs, d_off,
+                                     static_cast<hipStream_t>(stream)));
     return ok();
 }
 
@@ -704,7 +834,7 @@ ged_status ged_kbest_perpair(ged_db *db, const ged_pair *h_pairs, int64_t npairs
     ged_plan *p = nullptr;
     st = ged_plan_create(db, h_pairs, npairs, K, &p);
     if (st != GED_OK) return st;
-    st = plan_run(p, costs, d_dist, d_map, nullptr, stream, true, false);
+    st = plan_run(p, costs, d_dist, d_map, nullptr, nullptr, stream, true, false);
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     free_plan(p);
     if (st != GED_OK) return st;

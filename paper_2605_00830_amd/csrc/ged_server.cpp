@@ -58,8 +58,10 @@ struct Request {
     int32_t n1 = 0;
     int32_t target = 0;
     GraphRec rec{};                 // adj / vlab offsets relative to this request's vectors
-    std::vector<uint32_t> adj;      // packed rows and label planes
+    std::vector<uint32_t> adj;      // packed rows and label planes (empty for a database query)
     std::vector<int32_t> vlab;
+    int64_t words = 0;              // packed words of the query graph
+    int64_t db_query = -1;          // the query is this database graph (copied on the device)
     int state = QUEUED;
     int32_t dist = -1;
     std::vector<int32_t> map;
@@ -73,32 +75,33 @@ int64_t now_ns() {
 
 using ReqPtr = std::shared_ptr<Request>;
 
+// Batch formation while a class already has a batch on the device: wait for
+// this many queued queries, or until the oldest has waited this long.
+constexpr int64_t kFillQueries = 64;
+constexpr int64_t kHoldNs = 1'000'000;
+
 constexpr int kWaveBins = 2;        // wavefront bins: n <= 32, n <= 64
 constexpr int kMaxBins = 7;         // wavefront bins + workgroup bins W = 1, 2, 4, 8, 16
 
-// Device and pinned-host buffers of one stream.
+// Device and pinned-host buffers of one stream.  A batch's inputs are
+// staged in one pinned buffer and reach the device in one copy: the queue
+// counters (zeros), the work list, the database queries to gather, the query
+// graph records, then the vertex labels and packed rows of the query graphs
+// (the last two packed back to back, so the copy stops where the batch's
+// data ends).  Its outputs come back in one copy as well: the distances, then
+// the mappings.
 struct Slab {
     int cls = 0;                    // size class this stream serves
     size_t ws_bytes = 0;            // its workgroup-kernel workspace
     int64_t cap_words = 0, cap_vlab = 0;   // arena capacity (mappings share cap_vlab)
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    // device
-    GraphRec *d_recs = nullptr;
-    uint32_t *d_adj = nullptr;
-    int32_t *d_vlab = nullptr;
-    WorkItem *d_work = nullptr;
-    int *d_queue = nullptr;
-    int32_t *d_dist = nullptr;
-    int32_t *d_map = nullptr;
+    size_t o_work = 0, o_gather = 0, o_recs = 0, o_var = 0, in_bytes = 0;   // input layout
+    char *d_in = nullptr;           // device inputs
+    char *h_in = nullptr;           // pinned staging of the inputs
+    int32_t *d_out = nullptr;       // device outputs: dist[nq], then the mappings
+    int32_t *h_out = nullptr;       // pinned copy of the outputs
     void *d_ws = nullptr;
-    // pinned host staging
-    GraphRec *h_recs = nullptr;
-    uint32_t *h_adj = nullptr;
-    int32_t *h_vlab = nullptr;
-    WorkItem *h_work = nullptr;
-    int32_t *h_dist = nullptr;
-    int32_t *h_map = nullptr;
     // the batch on the device
     bool busy = false;
     std::vector<ReqPtr> batch;
@@ -176,46 +179,81 @@ gedk::BlockShape shape_for(const ged_server *s, int W, int nmax1, int nmax2, int
 }
 
 void free_slab(Slab &b) {
-    if (b.d_recs) (void)hipFree(b.d_recs);
-    if (b.d_adj) (void)hipFree(b.d_adj);
-    if (b.d_vlab) (void)hipFree(b.d_vlab);
-    if (b.d_work) (void)hipFree(b.d_work);
-    if (b.d_queue) (void)hipFree(b.d_queue);
-    if (b.d_dist) (void)hipFree(b.d_dist);
-    if (b.d_map) (void)hipFree(b.d_map);
+    if (b.d_in) (void)hipFree(b.d_in);
+    if (b.d_out) (void)hipFree(b.d_out);
     if (b.d_ws) (void)hipFree(b.d_ws);
-    if (b.h_recs) (void)hipHostFree(b.h_recs);
-    if (b.h_adj) (void)hipHostFree(b.h_adj);
-    if (b.h_vlab) (void)hipHostFree(b.h_vlab);
-    if (b.h_work) (void)hipHostFree(b.h_work);
-    if (b.h_dist) (void)hipHostFree(b.h_dist);
-    if (b.h_map) (void)hipHostFree(b.h_map);
+    if (b.h_in) (void)hipHostFree(b.h_in);
+    if (b.h_out) (void)hipHostFree(b.h_out);
     if (b.done) (void)hipEventDestroy(b.done);
     if (b.stream) (void)hipStreamDestroy(b.stream);
     b = Slab();
 }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Launch the slab's batch; on error the caller fails the batch.
 hipError_t launch_batch(ged_server *s, Slab &b) {
     const int nq = (int)b.batch.size();
     const int K = s->cfg.K;
     const auto &dbg = s->db->h_graphs;
-    // stage query graphs and map offsets
+    int *h_queue = reinterpret_cast<int *>(b.h_in);
+    WorkItem *h_work = reinterpret_cast<WorkItem *>(b.h_in + b.o_work);
+    gedk::GatherItem *h_gather = reinterpret_cast<gedk::GatherItem *>(b.h_in + b.o_gather);
+    GraphRec *h_recs = reinterpret_cast<GraphRec *>(b.h_in + b.o_recs);
+    int32_t *h_vlab = reinterpret_cast<int32_t *>(b.h_in + b.o_var);
+    // vertex labels first; the rows start at the next 256-byte boundary
+    int64_t nv = 0;
+    for (int k = 0; k < nq; ++k) nv += b.batch[(size_t)k]->n1;
+    const size_t o_adj = align256(b.o_var + sizeof(int32_t) * (size_t)nv);
+    uint32_t *h_adj = reinterpret_cast<uint32_t *>(b.h_in + o_adj);
+    // stage query graphs and map offsets; a database query's words are
+    // copied from the database on the device after the staged ones arrive
     int64_t aw = 0, vo = 0, mo = 0;
+    int ngather = 0;
     b.map_off.resize((size_t)nq);
     for (int k = 0; k < nq; ++k) {
         const Request &r = *b.batch[(size_t)k];
-        std::memcpy(b.h_adj + aw, r.adj.data(), sizeof(uint32_t) * r.adj.size());
-        std::memcpy(b.h_vlab + vo, r.vlab.data(), sizeof(int32_t) * r.vlab.size());
+        if (r.db_query >= 0) {
+            const GraphRec &q = dbg[(size_t)r.db_query];
+            h_gather[ngather++] = gedk::GatherItem{q.adj, aw, r.words, q.vlab, vo, (int64_t)r.n1};
+        } else {
+            std::memcpy(h_adj + aw, r.adj.data(), sizeof(uint32_t) * r.adj.size());
+            std::memcpy(h_vlab + vo, r.vlab.data(), sizeof(int32_t) * r.vlab.size());
+        }
         GraphRec rec = r.rec;
         rec.adj = aw;
         rec.vlab = vo;
-        b.h_recs[k] = rec;
+        h_recs[k] = rec;
         b.map_off[(size_t)k] = mo;
-        aw += (int64_t)r.adj.size();
-        vo += (int64_t)r.vlab.size();
+        aw += r.words;
+        vo += r.n1;
         mo += r.n1;
     }
+    for (int k = 0; k < kMaxBins; ++k) h_queue[k] = 0;
+    const gedk::DbView src{reinterpret_cast<const GraphRec *>(b.d_in + b.o_recs),
+                           reinterpret_cast<const uint32_t *>(b.d_in + o_adj),
+                           reinterpret_cast<const int32_t *>(b.d_in + b.o_var), s->db->planes};
+    const gedk::DbView dst{s->db->d_graphs, s->db->d_adj, s->db->d_vlab, s->db->planes};
+    int *d_queue = reinterpret_cast<int *>(b.d_in);
+    const WorkItem *d_work = reinterpret_cast<const WorkItem *>(b.d_in + b.o_work);
+    const gedk::Outputs out{b.d_out, b.d_out + nq, nullptr};
+    // one copy of everything staged, then the gather of database queries
+    auto stage = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(b.d_in, b.h_in, o_adj + sizeof(uint32_t) * (size_t)aw, hipMemcpyHostToDevice,
+                                      b.stream);
+        if (e == hipSuccess && ngather > 0)
+            e = gedk::launch_gather_graphs(reinterpret_cast<const gedk::GatherItem *>(b.d_in + b.o_gather), ngather,
+                                           s->db->d_adj, reinterpret_cast<uint32_t *>(b.d_in + o_adj), s->db->d_vlab,
+                                           reinterpret_cast<int32_t *>(b.d_in + b.o_var), b.stream);
+        return e;
+    };
+    // one copy of the results, then the batch's event
+    auto finish = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(b.h_out, b.d_out, sizeof(int32_t) * (size_t)(nq + mo), hipMemcpyDeviceToHost,
+                                      b.stream);
+        if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+        return e;
+    };
     // the bipartite method: one launch of the class's instantiation
     if (s->bip) {
         for (int k = 0; k < nq; ++k) {
@@ -225,33 +263,17 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
             wi.out = k;
             wi.pad = 0;
             wi.map_off = b.map_off[(size_t)k];
-            b.h_work[k] = wi;
+            h_work[k] = wi;
         }
         const int cpl = b.cls + 1;
         const size_t per_wave = gedk::bip_workgroup_bytes(cpl, K);
         const int fit = (int)std::min<size_t>(b.ws_bytes / per_wave, (size_t)std::numeric_limits<int>::max());
         const int grid = std::min({nq, s->bip_per_cu[b.cls] * s->cus, fit});
         if (grid <= 0) return hipErrorOutOfMemory;
-        hipError_t e = hipMemcpyAsync(b.d_recs, b.h_recs, sizeof(GraphRec) * (size_t)nq, hipMemcpyHostToDevice,
-                                      b.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(b.d_adj, b.h_adj, sizeof(uint32_t) * (size_t)std::max<int64_t>(aw, 1),
-                                                hipMemcpyHostToDevice, b.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(b.d_vlab, b.h_vlab, sizeof(int32_t) * (size_t)std::max<int64_t>(vo, 1),
-                                                hipMemcpyHostToDevice, b.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(b.d_work, b.h_work, sizeof(WorkItem) * (size_t)nq,
-                                                hipMemcpyHostToDevice, b.stream);
-        if (e == hipSuccess) e = gedk::launch_fill_zero(b.d_queue, kMaxBins, b.stream);
-        const gedk::DbView src{b.d_recs, b.d_adj, b.d_vlab, s->db->planes};
-        const gedk::DbView dst{s->db->d_graphs, s->db->d_adj, s->db->d_vlab, s->db->planes};
-        const gedk::Outputs out{b.d_dist, b.d_map, nullptr};
+        hipError_t e = stage();
         if (e == hipSuccess)
-            e = gedk::launch_bip(s->PL, cpl, 1, src, dst, b.d_work, nq, b.d_queue, s->c, K, b.d_ws, out, grid,
-                                 b.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq,
-                                                hipMemcpyDeviceToHost, b.stream);
-        if (e == hipSuccess && mo > 0)
-            e = hipMemcpyAsync(b.h_map, b.d_map, sizeof(int32_t) * (size_t)mo, hipMemcpyDeviceToHost, b.stream);
-        if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+            e = gedk::launch_bip(s->PL, cpl, 1, src, dst, d_work, nq, d_queue, s->c, K, b.d_ws, out, grid, b.stream);
+        if (e == hipSuccess) e = finish();
         return e;
     }
     // work items by bin: 0, 1 = wavefront kernels (n <= 32, n <= 64),
@@ -284,8 +306,8 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
         grid[bin] = 0;
         if (cnt == 0) continue;
         std::stable_sort(bins[bin].begin(), bins[bin].end(), [&](const WorkItem &x, const WorkItem &y) {
-            return (int64_t)b.h_recs[x.src].n * (dbg[(size_t)x.dst].n + 1) >
-                   (int64_t)b.h_recs[y.src].n * (dbg[(size_t)y.dst].n + 1);
+            return (int64_t)h_recs[x.src].n * (dbg[(size_t)x.dst].n + 1) >
+                   (int64_t)h_recs[y.src].n * (dbg[(size_t)y.dst].n + 1);
         });
         if (bin < kWaveBins) {
             grid[bin] = std::min(cnt, s->wave_per_cu[bin] * s->cus);
@@ -301,36 +323,21 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
             if (grid[bin] <= 0) return hipErrorOutOfMemory;
         }
         gedh::deal_alternating(bins[bin], grid[bin], bin < kWaveBins ? 4 * (int64_t)s->cus : (int64_t)s->cus);
-        for (const WorkItem &wi : bins[bin]) b.h_work[wo++] = wi;
+        for (const WorkItem &wi : bins[bin]) h_work[wo++] = wi;
     }
-    hipError_t e = hipMemcpyAsync(b.d_recs, b.h_recs, sizeof(GraphRec) * (size_t)nq, hipMemcpyHostToDevice, b.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.d_adj, b.h_adj, sizeof(uint32_t) * (size_t)std::max<int64_t>(aw, 1),
-                                            hipMemcpyHostToDevice, b.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.d_vlab, b.h_vlab, sizeof(int32_t) * (size_t)std::max<int64_t>(vo, 1),
-                                            hipMemcpyHostToDevice, b.stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b.d_work, b.h_work, sizeof(WorkItem) * (size_t)nq, hipMemcpyHostToDevice,
-                                            b.stream);
-    if (e == hipSuccess) e = gedk::launch_fill_zero(b.d_queue, kMaxBins, b.stream);
-    if (e != hipSuccess) return e;
-    const gedk::DbView src{b.d_recs, b.d_adj, b.d_vlab, s->db->planes};
-    const gedk::DbView dst{s->db->d_graphs, s->db->d_adj, s->db->d_vlab, s->db->planes};
-    const gedk::Outputs out{b.d_dist, b.d_map, nullptr};
+    hipError_t e = stage();
     for (int bin = 0; bin < kMaxBins && e == hipSuccess; ++bin) {
         const int cnt = (int)bins[bin].size();
         if (cnt == 0) continue;
         if (bin < kWaveBins) {
-            e = gedk::launch_wave_family(bin + 1, s->PL, src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K,
-                                         0, out, grid[bin], b.stream, s->directed ? 1 : 0);
+            e = gedk::launch_wave_family(bin + 1, s->PL, src, dst, d_work + start[bin], cnt, d_queue + bin, s->c, K, 0,
+                                         out, grid[bin], b.stream, s->directed ? 1 : 0);
         } else {
-            e = gedk::launch_block(shape[bin], src, dst, b.d_work + start[bin], cnt, b.d_queue + bin, s->c, K, 0,
-                                   b.d_ws, stride[bin], out, grid[bin], b.stream);
+            e = gedk::launch_block(shape[bin], src, dst, d_work + start[bin], cnt, d_queue + bin, s->c, K, 0, b.d_ws,
+                                   stride[bin], out, grid[bin], b.stream);
         }
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(b.h_dist, b.d_dist, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost,
-                                            b.stream);
-    if (e == hipSuccess && mo > 0)
-        e = hipMemcpyAsync(b.h_map, b.d_map, sizeof(int32_t) * (size_t)mo, hipMemcpyDeviceToHost, b.stream);
-    if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+    if (e == hipSuccess) e = finish();
     return e;
 }
 
@@ -344,8 +351,9 @@ void finish_batch(ged_server *s, Slab &b, bool failed) {
         if (failed) {
             r.state = FAILED;
         } else {
-            r.dist = b.h_dist[k];
-            r.map.assign(b.h_map + b.map_off[k], b.h_map + b.map_off[k] + r.n1);
+            const int32_t *maps = b.h_out + b.batch.size();
+            r.dist = b.h_out[k];
+            r.map.assign(maps + b.map_off[k], maps + b.map_off[k] + r.n1);
             r.state = DONE;
             r.adj.clear();
             r.adj.shrink_to_fit();
@@ -397,19 +405,29 @@ void worker_loop(ged_server *s) {
             s->cv_done.notify_all();
             if (!any_busy) break;
         }
-        // 2. admission and launch: each idle stream takes from its class's queue
+        // 2. admission and launch: each idle stream takes from its class's queue.
+        // A class with a batch on the device launches another only once the
+        // queue holds a batch worth the launch (kFillQueries) or its oldest
+        // query has waited kHoldNs: many tiny launches would cost more host
+        // time per query than the device time they save.
         bool launched = false;
         if (!s->stop && s->queued_total > 0) {
+            int class_busy[kClasses] = {0, 0, 0, 0};
+            for (const Slab &b : s->slabs) class_busy[b.cls] += b.busy ? 1 : 0;
+            const int64_t now = now_ns();
             for (Slab &b : s->slabs) {
                 std::deque<ReqPtr> &queue = s->queue[b.cls];
                 if (b.busy || queue.empty()) continue;
                 if (s->stats.inflight >= s->cfg.max_inflight) break;
+                if (class_busy[b.cls] > 0 && (int64_t)queue.size() < std::min<int64_t>(kFillQueries, s->cfg.max_batch) &&
+                    now - queue.front()->t_submit < kHoldNs)
+                    continue;
                 int64_t aw = 0, vo = 0;
                 while (!queue.empty() && (int)b.batch.size() < s->cfg.max_batch &&
                        s->stats.inflight + (int64_t)b.batch.size() < s->cfg.max_inflight) {
                     const Request &r = *queue.front();
-                    if (aw + (int64_t)r.adj.size() > b.cap_words || vo + r.n1 > b.cap_vlab) break;
-                    aw += (int64_t)r.adj.size();
+                    if (aw + r.words > b.cap_words || vo + r.n1 > b.cap_vlab) break;
+                    aw += r.words;
                     vo += r.n1;
                     queue.front()->state = INFLIGHT;
                     b.batch.push_back(queue.front());
@@ -417,6 +435,7 @@ void worker_loop(ged_server *s) {
                 }
                 if (b.batch.empty()) continue;
                 b.busy = true;
+                class_busy[b.cls] += 1;
                 s->queued_total -= (int64_t)b.batch.size();
                 s->stats.queued = s->queued_total;
                 s->stats.inflight += (int64_t)b.batch.size();
@@ -501,7 +520,7 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     const int max_n[kClasses] = {s->bip ? 64 : gedk::kWaveMaxN,
                                  s->bip ? 128 : (s->directed ? gedk::kWaveMaxN : gedk::kWave2MaxN),
                                  s->bip ? 192 : kMediumMaxN,
-                                 s->bip ? 256 : (s->directed ? GED_DIRECTED_MAX_ORDER : GED_MAX_VERTICES)};
+                                 s->bip ? 256 : (s->directed ? GED_DIRECTED_MAX_ORDER : GED_MAX_VERTICES_BATCH)};
     // bipartite classes: one queue slice per resident wave, at most half the share
     for (int cls = 0; cls < kClasses && e == hipSuccess && s->bip; ++cls) {
         e = gedk::bip_max_resident(s->PL, cls + 1, cfg.K, 1, &s->bip_per_cu[cls]);
@@ -549,7 +568,8 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     int64_t cap_words[kClasses], cap_vlab[kClasses];
     for (int cls = first_class; cls < kClasses; ++cls) {
         const int64_t fixed = (int64_t)ws_class[cls] +
-                              (int64_t)cfg.max_batch * (int64_t)(sizeof(GraphRec) + sizeof(WorkItem) + 4) + kMaxBins * 4;
+                              (int64_t)cfg.max_batch * (int64_t)(sizeof(GraphRec) + sizeof(WorkItem) + 4 +
+                                                                 sizeof(gedk::GatherItem)) + kMaxBins * 4;
         const int64_t rest = per_stream - fixed;
         const int64_t big = gedh::packed_words(max_n[cls], db->planes, s->directed);
         cap_words[cls] = std::min({rest / 4 * 8 / 10, (int64_t)cfg.max_batch * big, (int64_t)16 << 20});
@@ -571,24 +591,19 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
         e = hipStreamCreate(&b.stream);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming);
         const size_t nb = (size_t)cfg.max_batch;
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_recs, sizeof(GraphRec) * nb);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_adj, sizeof(uint32_t) * (size_t)b.cap_words);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_vlab, sizeof(int32_t) * (size_t)b.cap_vlab);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * nb);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * kMaxBins);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_dist, sizeof(int32_t) * nb);
-        if (e == hipSuccess) e = hipMalloc((void **)&b.d_map, sizeof(int32_t) * (size_t)b.cap_vlab);
+        b.o_work = align256(sizeof(int) * kMaxBins);
+        b.o_gather = b.o_work + align256(sizeof(WorkItem) * nb);
+        b.o_recs = b.o_gather + align256(sizeof(gedk::GatherItem) * nb);
+        b.o_var = b.o_recs + align256(sizeof(GraphRec) * nb);
+        b.in_bytes = b.o_var + align256(sizeof(int32_t) * (size_t)b.cap_vlab) + sizeof(uint32_t) * (size_t)b.cap_words;
+        const size_t out_bytes = sizeof(int32_t) * (nb + (size_t)b.cap_vlab);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_in, b.in_bytes);
+        if (e == hipSuccess) e = hipMalloc((void **)&b.d_out, out_bytes);
         if (e == hipSuccess && b.ws_bytes > 0) e = hipMalloc(&b.d_ws, b.ws_bytes);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_recs, sizeof(GraphRec) * nb, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_adj, sizeof(uint32_t) * (size_t)b.cap_words, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_vlab, sizeof(int32_t) * (size_t)b.cap_vlab, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_work, sizeof(WorkItem) * nb, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_dist, sizeof(int32_t) * nb, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_map, sizeof(int32_t) * (size_t)b.cap_vlab, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_in, b.in_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&b.h_out, out_bytes, hipHostMallocDefault);
         if (e != hipSuccess) break;
-        s->device_bytes += (int64_t)(sizeof(GraphRec) * nb + sizeof(uint32_t) * (size_t)b.cap_words +
-                                     sizeof(int32_t) * (size_t)b.cap_vlab + sizeof(WorkItem) * nb + sizeof(int) * kMaxBins +
-                                     sizeof(int32_t) * nb + sizeof(int32_t) * (size_t)b.cap_vlab + b.ws_bytes);
+        s->device_bytes += (int64_t)(b.in_bytes + out_bytes + b.ws_bytes);
     }
     if (e != hipSuccess) {
         for (Slab &b : s->slabs) free_slab(b);
@@ -601,6 +616,34 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     return ok();
 }
 
+// Limits and the overflow bound of query r (n1 = r->n1, m1 edges) against
+// its target; sets its class.
+static ged_status admit_pair(ged_server *srv, Request *r, int32_t m1) {
+    const GraphRec &g2 = srv->db->h_graphs[(size_t)r->target];
+    const int n1 = r->n1;
+    if (srv->directed && std::max(n1, g2.n) > GED_DIRECTED_MAX_ORDER)
+        return fail(GED_EUNSUPPORTED, "directed graphs of more than %d vertices", GED_DIRECTED_MAX_ORDER);
+    if (srv->bip && n1 + g2.n > GED_BIP_MAX_ORDER)
+        return fail(GED_EUNSUPPORTED, "n1 + n2 = %d exceeds the bipartite method's %d", n1 + g2.n,
+                    GED_BIP_MAX_ORDER);
+    if (std::max(n1, g2.n) > GED_MAX_VERTICES_BATCH)
+        return fail(GED_EUNSUPPORTED, "a graph of %d vertices exceeds the server's %d", std::max(n1, g2.n),
+                    GED_MAX_VERTICES_BATCH);
+    r->cls = server_class(srv, n1, g2.n);
+    const ged_costs &c = srv->cfg.costs;
+    const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
+    const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
+    if (vmax * ((int64_t)n1 + g2.n) + emax * ((int64_t)m1 + g2.m) > (int64_t)std::numeric_limits<int32_t>::max() - 1)
+        return fail(GED_EINVAL, "costs may overflow int32 on this pair");
+    // the bipartite solver's bound (as for plans): (n1 + n2 + 1) entries below 2^24
+    const int64_t order = (int64_t)n1 + g2.n;
+    if (srv->bip && (order + 1) * (2 * vmax + 4 * emax * order) >= ((int64_t)1 << 24))
+        return fail(GED_EINVAL, "costs may overflow the bipartite solver on this pair");
+    return ok();
+}
+
+static ged_status enqueue(ged_server *srv, std::shared_ptr<Request> r, uint64_t *ticket);
+
 ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t target_id, uint64_t *ticket) {
     if (!srv || !query || !ticket) return fail(GED_EINVAL, "NULL argument");
     if (target_id < 0 || target_id >= srv->db->count) return fail(GED_EINVAL, "target id %lld out of range", (long long)target_id);
@@ -611,22 +654,29 @@ ged_status ged_server_submit(ged_server *srv, const ged_graph *query, int64_t ta
     r->target = (int32_t)target_id;
     st = gedh::pack_graph(*query, 0, srv->db->elabels, srv->db->planes, r->adj, r->vlab, r->rec, srv->directed);
     if (st != GED_OK) return st;
-    const GraphRec &g2 = srv->db->h_graphs[(size_t)target_id];
-    if (srv->directed && std::max(query->n, g2.n) > GED_DIRECTED_MAX_ORDER)
-        return fail(GED_EUNSUPPORTED, "directed graphs of more than %d vertices", GED_DIRECTED_MAX_ORDER);
-    if (srv->bip && query->n + g2.n > GED_BIP_MAX_ORDER)
-        return fail(GED_EUNSUPPORTED, "n1 + n2 = %d exceeds the bipartite method's %d", query->n + g2.n,
-                    GED_BIP_MAX_ORDER);
-    r->cls = server_class(srv, query->n, g2.n);
-    const ged_costs &c = srv->cfg.costs;
-    const int64_t vmax = std::max({(int64_t)c.vsub, (int64_t)c.vdel, (int64_t)c.vins});
-    const int64_t emax = std::max({(int64_t)c.esub, (int64_t)c.edel, (int64_t)c.eins});
-    if (vmax * ((int64_t)query->n + g2.n) + emax * ((int64_t)query->m + g2.m) > (int64_t)std::numeric_limits<int32_t>::max() - 1)
-        return fail(GED_EINVAL, "costs may overflow int32 on this pair");
-    // the bipartite solver's bound (as for plans): (n1 + n2 + 1) entries below 2^24
-    const int64_t order = (int64_t)query->n + g2.n;
-    if (srv->bip && (order + 1) * (2 * vmax + 4 * emax * order) >= ((int64_t)1 << 24))
-        return fail(GED_EINVAL, "costs may overflow the bipartite solver on this pair");
+    r->words = (int64_t)r->adj.size();
+    st = admit_pair(srv, r.get(), query->m);
+    if (st != GED_OK) return st;
+    return enqueue(srv, std::move(r), ticket);
+}
+
+ged_status ged_server_submit_id(ged_server *srv, int64_t query_id, int64_t target_id, uint64_t *ticket) {
+    if (!srv || !ticket) return fail(GED_EINVAL, "NULL argument");
+    if (query_id < 0 || query_id >= srv->db->count) return fail(GED_EINVAL, "query id %lld out of range", (long long)query_id);
+    if (target_id < 0 || target_id >= srv->db->count) return fail(GED_EINVAL, "target id %lld out of range", (long long)target_id);
+    const GraphRec &q = srv->db->h_graphs[(size_t)query_id];
+    auto r = std::make_shared<Request>();
+    r->n1 = q.n;
+    r->target = (int32_t)target_id;
+    r->db_query = query_id;
+    r->rec = q;
+    r->words = gedh::packed_words(q.n, srv->db->planes, srv->directed);
+    ged_status st = admit_pair(srv, r.get(), q.m);
+    if (st != GED_OK) return st;
+    return enqueue(srv, std::move(r), ticket);
+}
+
+static ged_status enqueue(ged_server *srv, std::shared_ptr<Request> r, uint64_t *ticket) {
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stop) return fail(GED_ECANCELED, "server is shutting down");

@@ -171,8 +171,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     __shared__ int s_sel[GED_MAX_K];      // survivor: parent slot << 10 | child (n2 = deletion)
     __shared__ int s_selped[GED_MAX_K];   // survivor partial edit distance
     __shared__ int s_hist[NBINS];
-    __shared__ uint16_t s_nbr[GED_MAX_VERTICES];   // earlier neighbours of v_i
-    __shared__ uint8_t s_nbl[GED_MAX_VERTICES];    // their edge-label codes
+    __shared__ uint16_t s_nbr[GED_MAX_VERTICES_BATCH];   // earlier neighbours of v_i
+    __shared__ uint8_t s_nbl[GED_MAX_VERTICES_BATCH];    // their edge-label codes
     __shared__ int s_red[NW];
     __shared__ unsigned long long s_red64[NW];
     __shared__ int s_bc[4];

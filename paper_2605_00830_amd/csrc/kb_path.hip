@@ -26,7 +26,7 @@ namespace {
 
 using namespace wv;
 
-constexpr int kPathThreads = 256;
+constexpr int kPathThreads = 512;
 static_assert(2 * kPathThreads >= GED_MAX_VERTICES, "two vertices per thread");
 
 struct PathArgs {

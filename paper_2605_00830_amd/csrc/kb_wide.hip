@@ -60,8 +60,13 @@ constexpr int NWV = WT / 64;
 constexpr int ST = 1024;         // threads of the single-workgroup kernels
 constexpr int HBITS = 12;
 constexpr int HB = 1 << HBITS;   // histogram bins
-constexpr int CBITS = 10;        // survivor record: parent << CBITS | column
+constexpr int CBITS = 11;        // survivor record: parent << CBITS | column (n2 < 2^11, K <= 2^21)
 constexpr int MAXS = 16;         // column chunks (one per target word at most)
+constexpr int MAXCW = 8;         // target words of a chunk when rows have more than 16 words
+
+// Target words a chunk of the W-word instantiation can hold (its LDS rows).
+template <int W>
+constexpr int chunk_words() { return W > 16 ? MAXCW : W; }
 constexpr int JR = 64;           // mapping entries per update workgroup
 
 struct LevelState {
@@ -176,8 +181,9 @@ __global__ __launch_bounds__(WT) void wide_init(WideCtx c) {
 template <int W, int PL, bool SMALL>
 __global__ __launch_bounds__(WT) void wide_expand(WideCtx c, int i, int S, int tiles) {
     constexpr int PLA = PL > 0 ? PL : 1;
-    __shared__ uint32_t s_rows[32 * W * W];   // N2(u) rows of the chunk, W words each
-    __shared__ uint32_t s_lc[32 * W];         // label cost of substituting v_i by u
+    constexpr int CW = chunk_words<W>();
+    __shared__ uint32_t s_rows[32 * CW * W];  // N2(u) rows of the chunk, W words each
+    __shared__ uint32_t s_lc[32 * CW];        // label cost of substituting v_i by u
     __shared__ uint32_t s_hist[HB];
     const int tid = threadIdx.x;
     const uint32_t B = sgpr(c.st[i].B);
@@ -553,12 +559,19 @@ __device__ __forceinline__ void read_record(const WideCtx &c, uint32_t s, uint32
 }
 
 // ------------------------------------------------------------------ update
-// Phi of level v for slot s from the images x(j) of v's earlier neighbours j
-// in [j0, j1): bits OR-ed into this thread's LDS column of s_set.
-template <int W, int PL, class GetX>
+// Sets of the level's Phi handled per pass: all of them (Phi and its label
+// planes) when they fit the update's LDS, else one (rows of more than 16
+// words: 32 words x 256 slots is 32 KB per set).
+template <int W, int PL>
+constexpr int sets_per_pass() { return W > 16 ? 1 : 1 + PL; }
+
+// Sets b0 .. b0 + NG - 1 (0 = Phi, 1 + b = label plane b) of level v for
+// slot s from the images x(j) of v's earlier neighbours j in [j0, j1): bits
+// OR-ed into this thread's LDS column of s_set.
+template <int W, int NG, class GetX>
 __device__ __forceinline__ void collect_phi(const WideCtx &c, int v, int j0, int j1, bool live, uint32_t *s_set,
-                                            GetX getx) {
-    constexpr int NS = (1 + PL) * W;
+                                            int b0, GetX getx) {
+    constexpr int NS = NG * W;
     const int tid = threadIdx.x;
     const uint32_t *planes1 = c.a1 + (size_t)c.n1 * c.w1;
 #pragma unroll
@@ -572,27 +585,41 @@ __device__ __forceinline__ void collect_phi(const WideCtx &c, int v, int j0, int
             if (!live) continue;
             const uint32_t x = getx(j);
             if (x == DEL16) continue;
-            atomicOr(&s_set[(x >> 5) * WT + tid], 1u << (x & 31u));
 #pragma unroll
-            for (int b = 0; b < PL; ++b) {
-                if (b < c.planes && ((planes1[((size_t)b * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u))
-                    atomicOr(&s_set[((1 + b) * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
+            for (int g = 0; g < NG; ++g) {
+                const int b = b0 + g;   // set b: Phi (b = 0) or plane b - 1
+                if (b == 0 || (b - 1 < c.planes &&
+                               ((planes1[((size_t)(b - 1) * c.n1 + v) * c.w1 + (j >> 5)] >> (j & 31)) & 1u)))
+                    atomicOr(&s_set[(g * W + (x >> 5)) * WT + tid], 1u << (x & 31u));
             }
         }
     }
 }
 
-// Store (whole) or OR in (partial) this thread's Phi words for slot s.
-template <int W, int PL>
-__device__ __forceinline__ void store_phi(const WideCtx &c, uint32_t s, const uint32_t *s_set, bool whole) {
+// Store (whole) or OR in (partial) this thread's words of sets b0 ..
+// b0 + NG - 1 for slot s.
+template <int W, int NG>
+__device__ __forceinline__ void store_phi(const WideCtx &c, uint32_t s, const uint32_t *s_set, bool whole, int b0) {
     const int tid = threadIdx.x;
-    for (int b = 0; b < 1 + c.planes && b < 1 + PL; ++b) {
+    for (int g = 0; g < NG && b0 + g < 1 + c.planes; ++g) {
+        const int b = b0 + g;
         for (int k = 0; k < c.w2; ++k) {
-            const uint32_t word = s_set[(b * W + k) * WT + tid];
+            const uint32_t word = s_set[(g * W + k) * WT + tid];
             uint32_t *dstw = &c.sets[(size_t)(b * c.w2 + k) * c.Kp + s];
             if (whole) *dstw = word;
             else if (word) atomicOr(dstw, word);
         }
+    }
+}
+
+// All sets of level v for slot s, pass by pass.
+template <int W, int PL, class GetX>
+__device__ __forceinline__ void build_phi(const WideCtx &c, int v, int j0, int j1, bool live, uint32_t s,
+                                          uint32_t *s_set, bool whole, GetX getx) {
+    constexpr int NG = sets_per_pass<W, PL>();
+    for (int b0 = 0; b0 < 1 + c.planes && b0 < 1 + PL; b0 += NG) {
+        collect_phi<W, NG>(c, v, j0, j1, live, s_set, b0, getx);
+        if (live) store_phi<W, NG>(c, s, s_set, whole, b0);
     }
 }
 
@@ -603,7 +630,7 @@ __device__ __forceinline__ void store_phi(const WideCtx &c, uint32_t s, const ui
 // Phi for the sets kernel.
 template <int W, int PL>
 __global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles, int nranges) {
-    constexpr int NS = (1 + PL) * W;
+    constexpr int NS = sets_per_pass<W, PL>() * W;
     __shared__ uint32_t s_set[NS * WT];
     const int jr = blockIdx.x / utiles, tile = blockIdx.x % utiles;
     const uint32_t Bn = sgpr(c.st[i + 1].B);
@@ -648,10 +675,9 @@ __global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles, 
     const int v = i + 1;
     if (v >= c.n1) return;
     if (nranges == 1) {
-        collect_phi<W, PL>(c, v, 0, v, live, s_set, [&](int j) -> uint32_t {
+        build_phi<W, PL>(c, v, 0, v, live, s, s_set, true, [&](int j) -> uint32_t {
             return j < i ? (uint32_t)src[(size_t)j * Kp + p] : (sub ? u : DEL16);
         });
-        if (live) store_phi<W, PL>(c, s, s_set, true);
     } else if (live) {
         for (int k = 0; k < (1 + c.planes) * w2; ++k) c.sets[(size_t)k * Kp + s] = 0u;
     }
@@ -663,7 +689,7 @@ __global__ __launch_bounds__(WT) void wide_update(WideCtx c, int i, int utiles, 
 // sets the update cleared.
 template <int W, int PL>
 __global__ __launch_bounds__(WT) void wide_sets(WideCtx c, int i, int utiles) {
-    constexpr int NS = (1 + PL) * W;
+    constexpr int NS = sets_per_pass<W, PL>() * W;
     __shared__ uint32_t s_set[NS * WT];
     const int jr = blockIdx.x / utiles, tile = blockIdx.x % utiles;
     const uint32_t Bn = sgpr(c.st[i + 1].B);
@@ -673,9 +699,8 @@ __global__ __launch_bounds__(WT) void wide_sets(WideCtx c, int i, int utiles) {
     const int v = i + 1;
     const uint16_t *phin = c.phi[v & 1];
     const int j0 = jr * JR, j1 = min(j0 + JR, v);
-    collect_phi<W, PL>(c, v, j0, j1, live, s_set,
-                       [&](int j) -> uint32_t { return (uint32_t)phin[(size_t)j * c.Kp + s]; });
-    if (live) store_phi<W, PL>(c, s, s_set, false);
+    build_phi<W, PL>(c, v, j0, j1, live, s, s_set, false,
+                     [&](int j) -> uint32_t { return (uint32_t)phin[(size_t)j * c.Kp + s]; });
 }
 
 // ------------------------------------------------------------------ complete-then-minimum
@@ -832,11 +857,14 @@ Layout layout(int n1, int n2, int w2, int planes, uint32_t Kp) {
 uint32_t slot_stride(int K) { return (uint32_t)((K + WT - 1) / WT) * WT; }
 
 // Column chunks for a level of `tiles` parent tiles: enough workgroups to
-// cover the device twice over, at most one chunk per target word.
+// cover the device twice over, at most one chunk per target word, and
+// chunks of at most MAXCW words when the rows have more than 16 (the
+// expansion's LDS rows of such instantiations hold MAXCW words of vertices).
 int column_chunks(int tiles, int w2, int cus) {
     if (w2 <= 1) return 1;
     const int want = (2 * cus + tiles - 1) / tiles;
-    return std::max(1, std::min({want, w2, MAXS}));
+    const int least = w2 > 16 ? (w2 + MAXCW - 1) / MAXCW : 1;
+    return std::max(least, std::min({want, w2, MAXS}));
 }
 
 template <int W, int PL>
@@ -911,7 +939,7 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
     while (W < g2.w) W <<= 1;
     const uint32_t Kp = slot_stride(K);
     const Layout L = layout(g1.n, g2.n, g2.w, planes, Kp);
-    if (K < 1 || K > kWideMaxK || L.total > ws_bytes || W > 16 || g1.n > GED_MAX_VERTICES ||
+    if (K < 1 || K > kWideMaxK || L.total > ws_bytes || W > 32 || g1.n > GED_MAX_VERTICES ||
         g2.n > GED_MAX_VERTICES || cus < 1)
         return hipErrorInvalidValue;
     char *base = static_cast<char *>(ws);
@@ -961,6 +989,7 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
         case 4: return launch_pl<4>(PL, c, refine_possible, lc, cus, stream);
         case 8: return launch_pl<8>(PL, c, refine_possible, lc, cus, stream);
         case 16: return launch_pl<16>(PL, c, refine_possible, lc, cus, stream);
+        case 32: return launch_pl<32>(PL, c, refine_possible, lc, cus, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -19,7 +19,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libged.so")
 
 GED_OK, GED_EINVAL, GED_ENOMEM, GED_EUNSUPPORTED, GED_EDEVICE, GED_EBUSY, GED_ETIMEOUT, GED_ECANCELED = range(8)
-MAX_VERTICES = 512
+MAX_VERTICES = 1024           # databases, the single-pair search, edit paths
+MAX_VERTICES_BATCH = 512      # batched plans, the per-pair path, serving
 MAX_K = 1024
 MAX_K_WIDE = 1 << 21
 MAX_EDGE_LABELS = 16
@@ -37,11 +38,12 @@ METHOD_TREE, METHOD_BIPARTITE = 0, 1
 BIP_MAX_ORDER, BIP_MAX_K = 256, 256
 DB_DIRECTED = 1                 # ged_db_create_ex flag: edge k is the arc eu[k] -> ev[k]
 DIRECTED_MAX_ORDER = 256
+PLAN_PAIR_STATUS = 1            # ged_plan_options.flags: set unsearchable pairs aside with a status each
 
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32), ("last_level", ctypes.c_int32),
-                ("method", ctypes.c_int32)]
+                ("method", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class Costs(ctypes.Structure):
@@ -83,6 +85,7 @@ EXPORTS = (
     "ged_server_stats_get", "ged_server_destroy", "ged_server_submit_batch", "ged_server_collect",
     "ged_wide_create", "ged_wide_create_ex", "ged_wide_bytes", "ged_wide_run", "ged_wide_destroy",
     "ged_edit_path_capacity", "ged_edit_path",
+    "ged_plan_run_ex", "ged_kbest_ex", "ged_map_offsets", "ged_server_submit_id",
 )
 
 
@@ -138,6 +141,10 @@ def load(path: str = LIB_PATH):
         "ged_wide_destroy": ([P], i32),
         "ged_edit_path_capacity": ([P, P, i64, P], i32),
         "ged_edit_path": ([P, P, i64, Costs, P, P, P, P], i32),
+        "ged_plan_run_ex": ([P, Costs, P, P, P, P, P], i32),
+        "ged_kbest_ex": ([P, P, i64, Costs, i32, P, P, P, P, P, P], i32),
+        "ged_map_offsets": ([P, P, i64, P, P], i32),
+        "ged_server_submit_id": ([P, i64, i64, P], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -230,20 +237,23 @@ class Plan:
     """A reusable batched launch plan (ged_plan_create)."""
 
     def __init__(self, db: Database, pairs, K: int, schedule: int = SCHED_AUTO, groups_per_cu: int = 0,
-                 last_level: int = LAST_SELECT, method: int = METHOD_TREE):
+                 last_level: int = LAST_SELECT, method: int = METHOD_TREE, flags: int = 0):
         lib = load()
         self.db = db
         self.pairs = _pairs_array(pairs)
         self.K = int(K)
         handle = ctypes.c_void_p()
-        opt = PlanOptions(int(schedule), int(groups_per_cu), int(last_level), int(method))
+        opt = PlanOptions(int(schedule), int(groups_per_cu), int(last_level), int(method), int(flags))
         _check(lib.ged_plan_create_ex(db.handle, self.pairs.ctypes.data, len(self.pairs), self.K,
                                       ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
         size = ctypes.c_int64()
         _check(lib.ged_plan_map_size(self._h, ctypes.byref(size)))
         self.map_size = int(size.value)
-        n_src = db.n[self.pairs[:, 0]].astype(np.int64) if len(self.pairs) else np.zeros(0, np.int64)
+        # where each pair's mapping starts (ids out of range take no entries)
+        src = self.pairs[:, 0] if len(self.pairs) else np.zeros(0, np.int64)
+        ok = (src >= 0) & (src < db.count)
+        n_src = np.where(ok, db.n[np.where(ok, src, 0)] if db.count else 0, 0).astype(np.int64)
         self.offsets = np.zeros(len(self.pairs), dtype=np.int64)
         if len(self.pairs) > 1:
             np.cumsum(n_src[:-1], out=self.offsets[1:])
@@ -264,12 +274,22 @@ class Plan:
             raise ValueError("cand must be an int64 CUDA tensor of npairs entries")
 
     def run(self, costs, dist: torch.Tensor, maps: torch.Tensor, cand: Optional[torch.Tensor] = None,
-            stream=None, perpair: bool = False):
+            stream=None, perpair: bool = False, status: Optional[torch.Tensor] = None):
+        """ged_plan_run (ged_plan_run_ex with `status`, an int32 tensor of npairs
+        entries for the per-pair statuses; ged_plan_run_perpair with perpair)."""
         lib = load()
-        fn = lib.ged_plan_run_perpair if perpair else lib.ged_plan_run
         self._check_outputs(dist, maps, cand)
-        _check(fn(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(),
-                  None if cand is None else cand.data_ptr(), _stream_handle(stream)))
+        cp = None if cand is None else cand.data_ptr()
+        if status is not None:
+            if perpair:
+                raise ValueError("the per-pair path reports no statuses")
+            if status.dtype != torch.int32 or not status.is_cuda or status.numel() < len(self.pairs):
+                raise ValueError("status must be an int32 CUDA tensor of npairs entries")
+            _check(lib.ged_plan_run_ex(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(), cp,
+                                       status.data_ptr(), _stream_handle(stream)))
+            return
+        fn = lib.ged_plan_run_perpair if perpair else lib.ged_plan_run
+        _check(fn(self._h, _costs(costs), dist.data_ptr(), maps.data_ptr(), cp, _stream_handle(stream)))
 
     def set_timing(self, enable: bool = True):
         _check(load().ged_plan_set_timing(self._h, 1 if enable else 0))
@@ -366,6 +386,43 @@ def kbest(db: Database, pairs, costs, K: int, perpair: bool = False, with_cand: 
         plan.close()
 
 
+def kbest_ex(db: Database, pairs, costs, K: int, last_level: int = LAST_SELECT, method: int = METHOD_TREE,
+             flags: int = PLAN_PAIR_STATUS, stream=None):
+    """ged_kbest_ex: (Result with cand, status int32 [P]); synchronizes."""
+    lib = load()
+    pairs = _pairs_array(pairs)
+    P = len(pairs)
+    opt = PlanOptions(SCHED_AUTO, 0, int(last_level), int(method), int(flags))
+    # output sizes from the same layout the library uses
+    src = pairs[:, 0] if P else np.zeros(0, np.int64)
+    ok = (src >= 0) & (src < db.count)
+    n_src = np.where(ok, db.n[np.where(ok, src, 0)] if db.count else 0, 0).astype(np.int64)
+    off = np.zeros(P, dtype=np.int64)
+    if P > 1:
+        np.cumsum(n_src[:-1], out=off[1:])
+    total = int(n_src.sum())
+    dist = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
+    maps = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+    cand = torch.empty(max(P, 1), dtype=torch.int64, device="cuda")
+    status = torch.empty(max(P, 1), dtype=torch.int32, device="cuda")
+    _check(lib.ged_kbest_ex(db.handle, pairs.ctypes.data, P, _costs(costs), int(K), ctypes.byref(opt),
+                            dist.data_ptr(), maps.data_ptr(), cand.data_ptr(), status.data_ptr(),
+                            _stream_handle(stream)))
+    return (Result(dist[:P].cpu().numpy(), maps[:total].cpu().numpy(), off, cand[:P].cpu().numpy()),
+            status[:P].cpu().numpy())
+
+
+def map_offsets(db: Database, d_pairs: torch.Tensor, stream=None) -> torch.Tensor:
+    """ged_map_offsets on device pairs (int64 tensor [P, 2]): int64 tensor [P + 1]."""
+    if d_pairs.dtype != torch.int64 or not d_pairs.is_cuda or not d_pairs.is_contiguous():
+        raise ValueError("d_pairs must be a contiguous int64 CUDA tensor of shape [P, 2]")
+    P = d_pairs.numel() // 2
+    off = torch.empty(P + 1, dtype=torch.int64, device=d_pairs.device)
+    _check(load().ged_map_offsets(db.handle, d_pairs.data_ptr() if P else None, P, off.data_ptr(),
+                                  _stream_handle(stream)))
+    return off
+
+
 class Wide:
     """Single-pair search at large K with the whole device (ged_wide_*)."""
 
@@ -374,7 +431,7 @@ class Wide:
         self.db = db
         self.src, self.dst, self.K = int(src), int(dst), int(K)
         handle = ctypes.c_void_p()
-        opt = PlanOptions(SCHED_AUTO, 0, int(last_level), METHOD_TREE)
+        opt = PlanOptions(SCHED_AUTO, 0, int(last_level), METHOD_TREE, 0)
         _check(lib.ged_wide_create_ex(db.handle, self.src, self.dst, self.K, ctypes.byref(opt), ctypes.byref(handle)))
         self._h = handle
         self.n1 = int(db.n[self.src])
@@ -451,29 +508,34 @@ class Server:
         _check(load().ged_server_submit(self._h, ctypes.byref(gs), int(target_id), ctypes.byref(t)))
         return int(t.value)
 
+    def submit_id(self, query_id: int, target_id: int) -> int:
+        """Queue database graph `query_id` against `target_id` (ged_server_submit_id)."""
+        t = ctypes.c_uint64()
+        _check(load().ged_server_submit_id(self._h, int(query_id), int(target_id), ctypes.byref(t)))
+        return int(t.value)
+
     def _result(self, fn, *args):
-        # the mapping lands in a buffer of this call's own: wait and poll may run
-        # on several client threads at once
+        # the mapping and the times land in buffers of this call's own: wait and
+        # poll may run on several client threads at once
         d, n1 = ctypes.c_int32(), ctypes.c_int32()
         times = (ctypes.c_int64 * 2)()
-        buf = np.empty(MAX_VERTICES, dtype=np.int32)
-        st = fn(self._h, *args, ctypes.byref(d), buf.ctypes.data, MAX_VERTICES, ctypes.byref(n1), times)
-        self.last_times_ns = (int(times[0]), int(times[1]))
-        return st, int(d.value), buf[: n1.value].copy()
+        buf = np.empty(MAX_VERTICES_BATCH, dtype=np.int32)
+        st = fn(self._h, *args, ctypes.byref(d), buf.ctypes.data, MAX_VERTICES_BATCH, ctypes.byref(n1), times)
+        return st, int(d.value), buf[: n1.value].copy(), (int(times[0]), int(times[1]))
 
-    def poll(self, ticket: int):
-        """(dist, mapping) when finished, None while it runs; the submission and
-        completion times (monotonic ns) are left in self.last_times_ns."""
-        st, d, m = self._result(load().ged_server_poll, ctypes.c_uint64(ticket))
+    def poll(self, ticket: int, with_times: bool = False):
+        """(dist, mapping) when finished, None while it runs; with_times adds the
+        (submission, completion) times of this query (monotonic clock, ns)."""
+        st, d, m, t = self._result(load().ged_server_poll, ctypes.c_uint64(ticket))
         if st == GED_EBUSY:
             return None
         _check(st)
-        return d, m
+        return (d, m, t) if with_times else (d, m)
 
-    def wait(self, ticket: int, timeout_us: int = -1):
-        st, d, m = self._result(load().ged_server_wait, ctypes.c_uint64(ticket), int(timeout_us))
+    def wait(self, ticket: int, timeout_us: int = -1, with_times: bool = False):
+        st, d, m, t = self._result(load().ged_server_wait, ctypes.c_uint64(ticket), int(timeout_us))
         _check(st)
-        return d, m
+        return (d, m, t) if with_times else (d, m)
 
     def submit_batch(self, recs: np.ndarray, targets: np.ndarray) -> np.ndarray:
         """Submit ged_graph records (GRAPH_DTYPE array, see pack_queries) in order; returns

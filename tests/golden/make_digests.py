@@ -6,10 +6,12 @@ Calls only oracle/ (and the input generators); nothing here comes from the
 GPU library.  Run from the repository root:
 
     python tests/golden/make_digests.py [--threads 8] [--only NAME ...]
+    python tests/golden/make_digests.py --large-k [NAME ...]     (tests/golden/large_k.json)
 """
 from __future__ import annotations
 
 import argparse
+import fcntl
 import hashlib
 import json
 import os
@@ -27,6 +29,21 @@ import oracle  # noqa: E402
 from paper_2605_00830_amd import synth  # noqa: E402
 
 OUT = os.path.join(HERE, "digests.json")
+OUT_LARGE_K = os.path.join(HERE, "large_k.json")
+
+# Single pairs at the paper's large beam widths (Sec. 5: runtime versus K on two
+# 20-vertex graphs, K = 5000 as the graphs grow to 950 vertices), plus pairs above
+# 512 vertices at small K.  Key: "<workload>@K<K>"; value: (n, seed, K).
+LARGE_K = {
+    "pair_er_n20_p0.4@K1000": (20, 6, 1000),
+    "pair_er_n20_p0.4@K100000": (20, 6, 100_000),
+    "pair_er_n20_p0.4@K700000": (20, 6, 700_000),
+    "pair_er_n20_p0.4@K1200000": (20, 6, 1_200_000),
+    "pair_er_n500_p0.4@K5000": (500, 7, 5000),
+    "pair_er_n600_p0.4@K16": (600, 8, 16),
+    "pair_er_n950_p0.4@K64": (950, 8, 64),
+    "pair_er_n950_p0.4@K5000": (950, 8, 5000),
+}
 
 
 def digest(dist: np.ndarray, maps: np.ndarray) -> str:
@@ -75,11 +92,36 @@ WORKLOADS = {
 DIRECTED = {"batch_directed_n10-30_p0.05-0.15_4096pairs_k64"}
 
 
+def large_k(names):
+    """Oracle on the single large-K pairs; one entry per name, written as soon as it is done
+    (the file is re-read first, so runs for different names may go on side by side)."""
+    for name in names:
+        n, seed, K = LARGE_K[name]
+        w = synth.pair_er_large_k(n, seed)
+        t0 = time.time()
+        dist, maps, _, cand = oracle.kbest_pairs(w.graphs, w.pairs, w.costs, K, with_cand=True)
+        entry = {"workload": w.name, "n": n, "seed": seed, "K": K, "costs": list(w.costs),
+                 "dist": int(dist[0]), "map": [int(x) for x in maps], "children": int(cand[0]),
+                 "oracle_seconds": round(time.time() - t0, 1), "threads": 1}
+        with open(OUT_LARGE_K + ".lock", "w") as lk:
+            fcntl.flock(lk, fcntl.LOCK_EX)
+            data = json.load(open(OUT_LARGE_K)) if os.path.exists(OUT_LARGE_K) else {}
+            data[name] = entry
+            tmp = OUT_LARGE_K + ".tmp%d" % os.getpid()
+            json.dump(data, open(tmp, "w"), indent=None, separators=(",", ":"))
+            os.replace(tmp, OUT_LARGE_K)
+        print(name, entry["dist"], entry["children"], f"{entry['oracle_seconds']}s", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=min(8, os.cpu_count() or 1))
     ap.add_argument("--only", nargs="*")
+    ap.add_argument("--large-k", nargs="*", help="single large-K pairs (names of LARGE_K; none given: all)")
     args = ap.parse_args()
+    if args.large_k is not None:
+        large_k(args.large_k or list(LARGE_K))
+        return
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for name, make in WORKLOADS.items():
         if args.only and name not in args.only:

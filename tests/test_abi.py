@@ -29,7 +29,7 @@ def test_library_exports_every_declared_function():
 
 def test_abi_version_and_status_names():
     lib = ged.load()
-    assert lib.ged_abi_version() == 5
+    assert lib.ged_abi_version() == 6
     assert ged.status_name(ged.GED_OK) == "GED_OK"
     assert ged.status_name(ged.GED_EUNSUPPORTED) == "GED_EUNSUPPORTED"
     assert ged.status_name(99) == "GED_UNKNOWN"
@@ -61,7 +61,7 @@ def _db_create(graph_tuples, flags=None):
     ((3, [0, 0, 0], [0, 1], [1, 0], None), ged.GED_EINVAL, "repeats"),
     ((3, [0, 0, 0], [0], [3], None), ged.GED_EINVAL, "out of range"),
     ((-1, [], [], [], None), ged.GED_EINVAL, "negative"),
-    ((513, [0] * 513, [], [], None), ged.GED_EUNSUPPORTED, "exceeds"),
+    ((1025, [0] * 1025, [], [], None), ged.GED_EUNSUPPORTED, "exceeds"),
     ((6, [0] * 6, [0, 0, 0, 0, 0, 1, 1, 1, 1, 2, 2, 2, 3, 3, 4, 1, 2],
       [1, 2, 3, 4, 5, 2, 3, 4, 5, 3, 4, 5, 4, 5, 5, 2, 3], None), ged.GED_EINVAL, "more edges"),
 ])
@@ -115,3 +115,20 @@ def test_null_handles_are_rejected():
     assert lib.ged_plan_run(None, ged.Costs(1, 1, 1, 1, 1, 1), None, None, None, None) == ged.GED_EINVAL
     assert lib.ged_db_destroy(None) == ged.GED_OK
     assert lib.ged_plan_destroy(None) == ged.GED_OK
+
+
+def test_new_boundary_calls_reject_null_arguments():
+    """ged_plan_run_ex, ged_kbest_ex, ged_map_offsets and ged_server_submit_id check
+    their arguments on the host first."""
+    lib = ged.load()
+    c = ged.Costs(1, 1, 1, 1, 1, 1)
+    h = ctypes.c_void_p()
+    t = ctypes.c_uint64()
+    assert lib.ged_plan_run_ex(None, c, None, None, None, None, None) == ged.GED_EINVAL
+    assert lib.ged_kbest_ex(None, None, 0, c, 4, None, None, None, None, None, None) == ged.GED_EINVAL
+    bad = ged.PlanOptions(0, 0, 0, 0, 0x10)
+    assert lib.ged_kbest_ex(None, None, 0, c, 4, ctypes.byref(bad), None, None, None, None, None) == ged.GED_EINVAL
+    assert "flags" in lib.ged_last_error().decode()
+    assert lib.ged_map_offsets(None, None, 0, None, None) == ged.GED_EINVAL
+    assert lib.ged_server_submit_id(None, 0, 0, ctypes.byref(t)) == ged.GED_EINVAL
+    assert h.value is None

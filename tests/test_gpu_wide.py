@@ -2,6 +2,8 @@
 sizes the oracle finishes in seconds, equal to the batched search at K <= 1024 on
 larger pairs, and at K in the hundreds of thousands the returned mapping's
 induced cost is the returned distance (GPU)."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -141,4 +143,57 @@ def test_wide_errors(ged):
         w.run((2**30, 2**30, 2**30, 1, 1, 1), dist, maps, cand)
     assert e.value.status == ged.GED_EINVAL
     w.close()
+    db.close()
+
+
+LARGE_K_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_k.json")
+LARGE_K = json.load(open(LARGE_K_FILE)) if os.path.exists(LARGE_K_FILE) else {}
+
+
+@pytest.mark.parametrize("name", sorted(LARGE_K))
+def test_wide_paper_shapes_match_stored_oracle(ged, name):
+    """The paper's single-pair shapes (two 20-vertex graphs at K up to 1.2 million;
+    500 and 950 vertices at K = 5000; pairs beyond 512 vertices at small K): distance,
+    mapping and children evaluated equal to the oracle's, stored by
+    tests/golden/make_digests.py --large-k."""
+    e = LARGE_K[name]
+    w = synth.pair_er_large_k(e["n"], e["seed"])
+    assert w.name == e["workload"] and list(w.costs) == e["costs"]
+    db = ged.Database(w.graphs)
+    say(f"  {name}: n={e['n']} K={e['K']}")
+    dist, mp, cand = ged.kbest_wide(db, 0, 1, w.costs, e["K"])
+    db.close()
+    assert dist == e["dist"]
+    np.testing.assert_array_equal(mp, np.asarray(e["map"], np.int32))
+    assert cand == e["children"]
+
+
+@pytest.mark.parametrize("nlab", [0, 3, 9])
+def test_wide_above_512_vertices_matches_oracle(ged, nlab):
+    """Rows of 17..32 words (the 32-word instantiation: chunked target rows, one Phi set
+    per pass with label planes) against the oracle, live, on 1024-vertex targets too."""
+    specs = [(40, 0.1), (700, 0.02), (30, 0.2), (1024, 0.01), (520, 0.03)]
+    graphs = labelled_set(163 + nlab, specs, nlab)
+    db = ged.Database(graphs)
+    for costs in (PAPER, WIDE_RANGE):
+        wide_vs_oracle(ged, db, graphs, [(0, 1), (2, 3), (1, 0), (0, 4)], costs, 8)
+    db.close()
+
+
+def test_wide_above_512_complete_mode(ged):
+    graphs = labelled_set(167, [(36, 0.1), (800, 0.02)], 3)
+    db = ged.Database(graphs)
+    d, m = oracle.kbest(graphs.graph(0), graphs.graph(1), PAPER, 16, last_complete=True)
+    dist, mp, _ = ged.kbest_wide(db, 0, 1, PAPER, 16, last_level=ged.LAST_COMPLETE)
+    db.close()
+    assert dist == d
+    np.testing.assert_array_equal(mp, m)
+
+
+def test_batched_search_refuses_pairs_beyond_512(ged):
+    graphs = labelled_set(173, [(20, 0.2), (600, 0.01)], 0)
+    db = ged.Database(graphs)
+    with pytest.raises(ged.GedError) as e:
+        ged.Plan(db, [(0, 1)], 8)
+    assert e.value.status == ged.GED_EUNSUPPORTED
     db.close()
