@@ -337,6 +337,28 @@ ged_status ged_kbest_ex(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged
  * GED_EDEVICE. */
 ged_status ged_map_offsets(ged_db *db, const ged_pair *d_pairs, int64_t npairs, int64_t *d_off, void *stream);
 
+/* ------------------------------------------------------------------------
+ * ged_kbest without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks and results as ged_kbest (K-Best
+ * search of every pair, default schedule and last level), bit for bit.
+ *
+ * Its staging (a device copy of the pairs, the mapping offsets, the work
+ * lists and queue counters, the workgroup kernel's per-workgroup beam
+ * workspace) lives in one device array of GED_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every device it runs on until the process ends, so
+ * the call allocates no device memory.  Every call on a device shares that
+ * device's array: calls that overlap on one device (from several host
+ * threads or on several streams) race and must be serialized by the
+ * caller.  The call enqueues its work on `stream` and synchronizes it.
+ * Errors: as ged_kbest; GED_EUNSUPPORTED when the batch's staging (about
+ * 48 bytes per pair) plus one workgroup's workspace for each of its
+ * workgroup-kernel bins exceeds GED_NOALLOC_SCRATCH_BYTES (workgroup bins
+ * otherwise run as many workgroups as the remaining scratch holds).
+ * ---------------------------------------------------------------------- */
+#define GED_NOALLOC_SCRATCH_BYTES (64ll << 20)
+ged_status ged_kbest_noalloc(ged_db *db, const ged_pair *h_pairs, int64_t npairs, ged_costs costs, int32_t K,
+                             int32_t *d_dist, int32_t *d_map, void *stream);
 
 /* ------------------------------------------------------------------------
  * Edit paths.  A vertex mapping (as the searches return it) induces one edit

@@ -110,6 +110,32 @@ inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const
                       : launch_wave2(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream);
 }
 
+// Size bins of the default schedule of the tree search: 0 / 1 = the
+// wavefront kernels (n <= 32 / n <= 64, K <= 64; a directed pair of up to 32
+// vertices takes 1), 2 + log2(W) = the workgroup kernel whose rows have W
+// words (target words rounded up to a power of two, doubled for a directed
+// database's out and in rows).  The same function classifies pairs on the
+// host and on the device.
+constexpr int kPairBins = 7;
+__host__ __device__ inline int pair_bin(int n1, int n2, int K, int directed) {
+    const int ww = directed ? wave_words_for_directed(n1, n2, K) : wave_words_for(n1, n2, K);
+    if (ww > 0) return ww - 1;
+    const int w2 = n2 > 32 ? (n2 + 31) / 32 : 1;
+    int W = 1;
+    while (W < w2) W <<= 1;
+    if (directed) W <<= 1;
+    int lg = 0;
+    while ((1 << lg) < W) ++lg;
+    return 2 + lg;
+}
+// Row words of workgroup-kernel bin b (2..6).
+__host__ __device__ inline int bin_words(int b) { return 1 << (b - 2); }
+
+// Start of each bin's work list in one array of work items.
+struct BinBases {
+    int64_t at[kPairBins];
+};
+
 // Copy of one database graph into a serving arena (word and label offsets
 // into the two pools).
 struct GatherItem {
@@ -127,4 +153,10 @@ hipError_t launch_pair_status(const int32_t *status, int64_t np, int32_t *status
                               int naside, int32_t *dist, int32_t *map, int64_t *cand, hipStream_t stream);
 hipError_t launch_gather_graphs(const GatherItem *items, int nitems, const uint32_t *src_adj, uint32_t *dst_adj,
                                 const int32_t *src_vlab, int32_t *dst_vlab, hipStream_t stream);
+// Work items of pairs[0..np) into lists[base.at[pair_bin(..)] + k] (counters
+// zeroed beforehand; pair ids already validated).
+hipError_t launch_classify_pairs(const GraphRec *graphs, const ged_pair *pairs, int64_t np, const int64_t *off, int K,
+                                 int directed, WorkItem *lists, const BinBases &base, int *counters,
+                                 hipStream_t stream);
+
 }  // namespace gedk

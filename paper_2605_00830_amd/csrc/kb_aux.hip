@@ -1,8 +1,8 @@
 // kb_aux.hip -- small kernels around the search: where each pair's mapping
 // starts in the output (exclusive prefix sum of the source orders), the
-// per-pair statuses of a plan's set-aside pairs, and the copy of database
-// graphs into a serving arena.  None of them does any step of the search
-// itself.
+// per-pair statuses of a plan's set-aside pairs, the copy of database graphs
+// into a serving arena, and the work lists of the allocation-free batched
+// call.  None of them does any step of the search itself.
 #include <hip/hip_runtime.h>
 
 #include "ged_internal.h"
@@ -95,6 +95,27 @@ __global__ __launch_bounds__(256) void gather_graphs_kernel(const GatherItem *it
     }
 }
 
+// Work lists of the allocation-free call: pair p goes to bin
+// pair_bin(n1, n2, K, directed) at the next free position of that bin's
+// list (lists[base[bin] ..]); counters[bin] starts at 0.  The host counted
+// the same bins with the same function, so every list is filled exactly.
+__global__ void classify_pairs_kernel(const GraphRec *graphs, const ged_pair *pairs, int64_t np, const int64_t *off,
+                                      int K, int directed, WorkItem *lists, BinBases base, int *counters) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += stride) {
+        const int32_t s = (int32_t)pairs[p].src, d = (int32_t)pairs[p].dst;
+        const int b = pair_bin(graphs[s].n, graphs[d].n, K, directed);
+        const int slot = atomicAdd(&counters[b], 1);
+        WorkItem w;
+        w.src = s;
+        w.dst = d;
+        w.out = (int32_t)p;
+        w.pad = 0;
+        w.map_off = off[p];
+        lists[base.at[b] + slot] = w;
+    }
+}
+
 int grid_for(int64_t n, int threads) {
     const int64_t g = (n + threads - 1) / threads;
     return (int)(g < 1 ? 1 : (g > 4096 ? 4096 : g));
@@ -123,6 +144,15 @@ hipError_t launch_gather_graphs(const GatherItem *items, int nitems, const uint3
     const int grid = nitems < 1024 ? nitems : 1024;
     hipLaunchKernelGGL(gather_graphs_kernel, dim3(grid), dim3(256), 0, stream, items, nitems, src_adj, dst_adj,
                        src_vlab, dst_vlab);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify_pairs(const GraphRec *graphs, const ged_pair *pairs, int64_t np, const int64_t *off, int K,
+                                 int directed, WorkItem *lists, const BinBases &base, int *counters,
+                                 hipStream_t stream) {
+    if (np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(classify_pairs_kernel, dim3(grid_for(np, 256)), dim3(256), 0, stream, graphs, pairs, np, off, K,
+                       directed, lists, base, counters);
     return hipGetLastError();
 }
 

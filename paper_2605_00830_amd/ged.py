@@ -39,6 +39,7 @@ BIP_MAX_ORDER, BIP_MAX_K = 256, 256
 DB_DIRECTED = 1                 # ged_db_create_ex flag: edge k is the arc eu[k] -> ev[k]
 DIRECTED_MAX_ORDER = 256
 PLAN_PAIR_STATUS = 1            # ged_plan_options.flags: set unsearchable pairs aside with a status each
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class PlanOptions(ctypes.Structure):
@@ -85,7 +86,7 @@ EXPORTS = (
     "ged_server_stats_get", "ged_server_destroy", "ged_server_submit_batch", "ged_server_collect",
     "ged_wide_create", "ged_wide_create_ex", "ged_wide_bytes", "ged_wide_run", "ged_wide_destroy",
     "ged_edit_path_capacity", "ged_edit_path",
-    "ged_plan_run_ex", "ged_kbest_ex", "ged_map_offsets", "ged_server_submit_id",
+    "ged_plan_run_ex", "ged_kbest_ex", "ged_map_offsets", "ged_kbest_noalloc", "ged_server_submit_id",
 )
 
 
@@ -144,6 +145,7 @@ def load(path: str = LIB_PATH):
         "ged_plan_run_ex": ([P, Costs, P, P, P, P, P], i32),
         "ged_kbest_ex": ([P, P, i64, Costs, i32, P, P, P, P, P, P], i32),
         "ged_map_offsets": ([P, P, i64, P, P], i32),
+        "ged_kbest_noalloc": ([P, P, i64, Costs, i32, P, P, P], i32),
         "ged_server_submit_id": ([P, i64, i64, P], i32),
     }
     for name, (args, res) in sig.items():
@@ -421,6 +423,18 @@ def map_offsets(db: Database, d_pairs: torch.Tensor, stream=None) -> torch.Tenso
     _check(load().ged_map_offsets(db.handle, d_pairs.data_ptr() if P else None, P, off.data_ptr(),
                                   _stream_handle(stream)))
     return off
+
+
+def kbest_noalloc(db: Database, pairs, costs, K: int, dist: torch.Tensor, maps: torch.Tensor, stream=None):
+    """ged_kbest_noalloc into caller-owned outputs (int32 CUDA tensors of P and sum n(src)
+    entries); synchronizes the stream."""
+    pairs = _pairs_array(pairs)
+    for t in (dist, maps):
+        if t.dtype != torch.int32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("outputs must be contiguous int32 CUDA tensors")
+    _check(load().ged_kbest_noalloc(db.handle, pairs.ctypes.data if len(pairs) else None, len(pairs),
+                                    _costs(costs), int(K), dist.data_ptr(), maps.data_ptr(),
+                                    _stream_handle(stream)))
 
 
 class Wide:

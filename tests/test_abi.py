@@ -118,8 +118,8 @@ def test_null_handles_are_rejected():
 
 
 def test_new_boundary_calls_reject_null_arguments():
-    """ged_plan_run_ex, ged_kbest_ex, ged_map_offsets and ged_server_submit_id check
-    their arguments on the host first."""
+    """ged_plan_run_ex, ged_kbest_ex, ged_map_offsets, ged_kbest_noalloc and
+    ged_server_submit_id check their arguments on the host first."""
     lib = ged.load()
     c = ged.Costs(1, 1, 1, 1, 1, 1)
     h = ctypes.c_void_p()
@@ -130,5 +130,7 @@ def test_new_boundary_calls_reject_null_arguments():
     assert lib.ged_kbest_ex(None, None, 0, c, 4, ctypes.byref(bad), None, None, None, None, None) == ged.GED_EINVAL
     assert "flags" in lib.ged_last_error().decode()
     assert lib.ged_map_offsets(None, None, 0, None, None) == ged.GED_EINVAL
+    assert lib.ged_kbest_noalloc(None, None, 0, c, 4, None, None, None) == ged.GED_EINVAL
+    assert lib.ged_kbest_noalloc(None, None, 0, ged.Costs(1, -1, 1, 1, 1, 1), 4, None, None, None) == ged.GED_EINVAL
     assert lib.ged_server_submit_id(None, 0, 0, ctypes.byref(t)) == ged.GED_EINVAL
     assert h.value is None
