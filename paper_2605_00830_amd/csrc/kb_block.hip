@@ -173,6 +173,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     __shared__ int s_hist[NBINS];
     __shared__ uint16_t s_nbr[GED_MAX_VERTICES_BATCH];   // earlier neighbours of v_i
     __shared__ uint8_t s_nbl[GED_MAX_VERTICES_BATCH];    // their edge-label codes
+    __shared__ int s_lc[GED_MAX_VERTICES_BATCH];         // vertex cost of substituting v_i by u
     __shared__ int s_red[NW];
     __shared__ unsigned long long s_red64[NW];
     __shared__ int s_bc[4];
@@ -302,7 +303,9 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 if (s < nb && part == 0) lpmin = min(lpmin, pedc[s]);
             }
             for (int b = t; b < NBINS; b += BT) s_hist[b] = 0;
-            const int m0 = block_min<NW>(lpmin, s_red);   // also orders the histogram reset and the list
+            for (int u = t; u < n2; u += BT) s_lc[u] = lab1 != L2[u] ? c.vsub : 0;
+            // also orders the histogram reset, the neighbour list and the label costs
+            const int m0 = block_min<NW>(lpmin, s_red);
 
             // ---------------- expand, evaluate, histogram
             int lcnt = 0, ovmin = SENT;
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                             relab += __popc(both & diff);
                         }
                     }
-                    const int d = pp + (lab1 != L2[u] ? c.vsub : 0) + c.edel * (degP - kept) +
+                    const int d = pp + s_lc[u] + c.edel * (degP - kept) +
                                   c.eins * (inimg - kept) + c.esub * relab;
                     const bool used = (cur_img >> (u & 31)) & 1u;
                     const int v = used ? SENT : d;

@@ -61,7 +61,7 @@ def run_oracle(w, pairs, threads, directed=False):
     res = [None] * threads
 
     def work(t):
-        res[t] = oracle.kbest_pairs(w.graphs, pairs[shards[t]], w.costs, w.K, directed=directed)
+        res[t] = oracle.kbest_pairs(w.graphs, pairs[shards[t]], w.costs, w.K, directed=directed, with_cand=True)
 
     th = [threading.Thread(target=work, args=(t,)) for t in range(threads)]
     for x in th:
@@ -71,13 +71,15 @@ def run_oracle(w, pairs, threads, directed=False):
     n_src = w.graphs.n[pairs[:, 0]].astype(np.int64)
     off = np.concatenate([[0], np.cumsum(n_src)])
     dist = np.zeros(len(pairs), np.int64)
+    cand = np.zeros(len(pairs), np.int64)
     maps = np.zeros(int(off[-1]), np.int32)
     for t in range(threads):
-        d, m, o = res[t]
+        d, m, o, c = res[t]
         dist[shards[t]] = d
+        cand[shards[t]] = c
         for k, p in enumerate(shards[t]):
             maps[off[p]:off[p + 1]] = m[o[k]:o[k] + n_src[p]]
-    return dist, maps
+    return dist, maps, cand
 
 
 WORKLOADS = {
@@ -129,10 +131,11 @@ def main():
         t0 = time.time()
         w, limit = make()
         pairs = w.pairs if limit is None else w.pairs[:limit]
-        dist, maps = run_oracle(w, pairs, args.threads, directed=name in DIRECTED)
+        dist, maps, cand = run_oracle(w, pairs, args.threads, directed=name in DIRECTED)
         entry = {"workload": w.name, "directed": name in DIRECTED, "pairs": int(len(pairs)), "K": w.K, "costs": list(w.costs),
                  "sha256": digest(dist.astype(np.int32), maps),
                  "dist_sum": int(dist.sum()), "dist_head": [int(x) for x in dist[:16]],
+                 "children_sum": int(cand.sum()),
                  "oracle_seconds": round(time.time() - t0, 1), "threads": args.threads}
         if len(pairs) <= 10000:
             entry["dist"] = [int(x) for x in dist]

@@ -42,8 +42,8 @@ def ged():
 def test_full_workload_digest(ged, name, schedule):
     if name not in DIGESTS:
         pytest.skip(f"no stored digest for {name}")
-    if schedule == 1 and name.startswith(("stress", "serve", "query")):
-        pytest.skip("the workgroup-only schedule is checked on the small-pair workloads")
+    if schedule == 1 and name.startswith("stress"):
+        pytest.skip("every stress pair takes the workgroup kernel under both schedules: one run covers it")
     ref = DIGESTS[name]
     make, limit = WORKLOADS[name]
     w = make()
@@ -52,7 +52,7 @@ def test_full_workload_digest(ged, name, schedule):
     print(f"  case: {name}, {len(pairs)} pairs, schedule {schedule}", flush=True)
     directed = name in DIRECTED
     db = ged.Database(w.graphs, directed=directed)
-    res = ged.kbest(db, pairs, w.costs, w.K, schedule=schedule)
+    res = ged.kbest(db, pairs, w.costs, w.K, schedule=schedule, with_cand=True)
     db.close()
     got = digest(res.dist, res.maps)
     if got != ref["sha256"]:
@@ -66,3 +66,7 @@ def test_full_workload_digest(ged, name, schedule):
         pytest.fail(f"{name}: digest {got[:16]} != {ref['sha256'][:16]}; differing pairs "
                     f"(pair, gpu, oracle): {detail or bad}")
     assert int(res.dist.astype(np.int64).sum()) == ref["dist_sum"]
+    if "children_sum" in ref:
+        # every child the search evaluated, summed over the workload: the
+        # oracle's count of generated children
+        assert int(res.cand.sum()) == ref["children_sum"]
