@@ -477,14 +477,19 @@ typedef struct {
     int32_t max_inflight;     /* queries admitted to the device at once; 0 = 4096 */
     int32_t max_batch;        /* queries per launch; 0 = 1024 */
     int32_t streams;          /* streams per size class (launches of a class that
-                                 may overlap), 1..4; 0 = 1.  With more than one,
-                                 a class's next batch starts while a slow one
-                                 runs.  Streams beyond the process's hardware
+                                 may overlap), 1..4; 0 = 1; the tree search's
+                                 large class gets twice as many.  With more than
+                                 one, a class's next batch starts while a slow
+                                 one runs.  Streams beyond the process's hardware
                                  queues (HIP: GPU_MAX_HW_QUEUES, 4 by default)
                                  share queues, and a long launch then delays the
                                  others on its queue; give the process well
-                                 over 4 * streams queues (other streams of the
-                                 process take queues too). */
+                                 over 5 * streams queues (other streams of the
+                                 process take queues too).  While a class has a
+                                 batch on the device, its next batch waits for
+                                 64 queued queries or 1 ms; a batch of the
+                                 medium / large class holds at most 2 / 1
+                                 workgroups per CU. */
     int32_t queue_capacity;   /* queued (not yet admitted) queries before
                                  ged_server_submit returns GED_EBUSY; 0 = 1<<20 */
     int32_t method;           /* GED_METHOD_TREE (0) or GED_METHOD_BIPARTITE: the

@@ -280,26 +280,29 @@ ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d
     plan->timed_run = false;
     plan->launches = 0;
     if (timing) GED_HIP(hipEventRecord(plan->ev_start, r.s));
-    // the bins are independent: after the first (on the caller's stream)
-    // each runs on a stream of its own, so a bin's last pairs overlap the
-    // others instead of every bin's tail adding up; the per-pair baseline
-    // stays one launch after another
+    // the bins are independent.  A bin whose persistent grid fills the device
+    // (at least as many pairs as resident workgroups) runs on the caller's
+    // stream, one after another; a bin with fewer pairs than the device
+    // holds leaves CUs idle for its whole launch, so it runs on a stream of
+    // its own beside the others, forked from and joined to the caller's
+    // stream by events.  The per-pair baseline stays one launch after another.
     const bool fork = !perpair && plan->bins.size() > 1 && !plan->side.empty();
     if (fork) GED_HIP(hipEventRecord(plan->ev_fork, r.s));
+    size_t nside = 0;
     for (size_t k = 0; k < plan->bins.size(); ++k) {
         Bin &b = plan->bins[k];
         plan->launches += perpair ? (int64_t)b.h_work.size() : 1;
         RunCtx rb = r;
-        if (fork && k > 0) {
-            rb.s = plan->side[(k - 1) % plan->side.size()];
+        const bool beside = fork && (int64_t)b.grid < (int64_t)b.groups_per_cu * plan->cus;
+        if (beside) {
+            rb.s = plan->side[nside % plan->side.size()];
             GED_HIP(hipStreamWaitEvent(rb.s, plan->ev_fork, 0));
         }
         st = launch_bin(plan, b, rb, perpair);
         if (st != GED_OK) return st;
-        if (fork && k > 0) GED_HIP(hipEventRecord(plan->ev_join[k - 1], rb.s));
+        if (beside) GED_HIP(hipEventRecord(plan->ev_join[nside++], rb.s));
     }
-    if (fork)
-        for (size_t k = 1; k < plan->bins.size(); ++k) GED_HIP(hipStreamWaitEvent(r.s, plan->ev_join[k - 1], 0));
+    for (size_t k = 0; k < nside; ++k) GED_HIP(hipStreamWaitEvent(r.s, plan->ev_join[k], 0));
     if (timing) {
         GED_HIP(hipEventRecord(plan->ev_stop, r.s));
         plan->timed_run = true;
@@ -510,16 +513,17 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         free_plan(p);
         return fail(GED_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));
     }
-    // streams and events for running the bins side by side (default
-    // priority; at most three extra streams, bins beyond share them in turn)
-    const size_t nside = std::min<size_t>(bins.size() > 0 ? bins.size() - 1 : 0, 3);
+    // streams and events for running bins side by side (default priority;
+    // at most three extra streams, bins beyond share them in turn; one join
+    // event per bin)
+    const size_t nside = bins.size() > 1 ? std::min<size_t>(bins.size(), 3) : 0;
     for (size_t k = 0; k < nside && e == hipSuccess; ++k) {
         hipStream_t st = nullptr;
         e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
         if (e == hipSuccess) p->side.push_back(st);
     }
     if (e == hipSuccess && nside > 0) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
-    for (size_t k = 0; k + 1 < bins.size() && nside > 0 && e == hipSuccess; ++k) {
+    for (size_t k = 0; k < bins.size() && nside > 0 && e == hipSuccess; ++k) {
         hipEvent_t ev = nullptr;
         e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
         if (e == hipSuccess) p->ev_join.push_back(ev);

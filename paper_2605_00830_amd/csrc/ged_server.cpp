@@ -80,6 +80,13 @@ using ReqPtr = std::shared_ptr<Request>;
 constexpr int64_t kFillQueries = 64;
 constexpr int64_t kHoldNs = 1'000'000;
 
+// Resident workgroups per CU a batch of each class may hold (the wavefront
+// classes are not capped): one 512-thread workgroup of the large class takes
+// at most 288 of a SIMD lane's 512 VGPRs, leaving room for two waves of the
+// wavefront kernels beside it.
+constexpr int kBlockClassPerCu[4] = {1 << 20, 1 << 20, 2, 1};
+constexpr int kLargeStreams = 2;
+
 constexpr int kWaveBins = 2;        // wavefront bins: n <= 32, n <= 64
 constexpr int kMaxBins = 7;         // wavefront bins + workgroup bins W = 1, 2, 4, 8, 16
 
@@ -319,7 +326,12 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
                                    wide ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
             stride[bin] = gedk::block_workspace_bytes(shape[bin]);
             const int fit = (int)std::min<size_t>(b.ws_bytes / stride[bin], (size_t)std::numeric_limits<int>::max());
-            grid[bin] = std::min({cnt, s->block_per_cu[wide][bin - kWaveBins] * s->cus, fit});
+            // the workgroup classes hold at most kBlockClassPerCu[class]
+            // workgroups per CU: a batch of large queries at full occupancy
+            // would fill every SIMD's registers for tens of milliseconds and
+            // keep the small and mid classes' waves off the device
+            const int per_cu = std::min(s->block_per_cu[wide][bin - kWaveBins], kBlockClassPerCu[b.cls]);
+            grid[bin] = std::min({cnt, per_cu * s->cus, fit});
             if (grid[bin] <= 0) return hipErrorOutOfMemory;
         }
         gedh::deal_alternating(bins[bin], grid[bin], bin < kWaveBins ? 4 * (int64_t)s->cus : (int64_t)s->cus);
@@ -510,7 +522,16 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     // classes that can receive a query get streams: a directed database has no
     // one-word class (its pairs of up to 32 vertices take the two-word kernel)
     const int first_class = s->bip ? 0 : (wave_classes ? (s->directed ? 1 : 0) : kFirstBlockClass);
-    const int nslabs = (kClasses - first_class) * cfg.streams;
+    // streams per class: the configured number, and kLargeStreams times it for
+    // the tree search's large class, whose batches last as long as their
+    // slowest pair (tens of milliseconds): more of them in flight keep its
+    // CUs busy while a batch's last pairs finish
+    int nstr[kClasses];
+    int nslabs = 0;
+    for (int cls = 0; cls < kClasses; ++cls) {
+        nstr[cls] = cls < first_class ? 0 : cfg.streams * ((!s->bip && cls == kClasses - 1) ? kLargeStreams : 1);
+        nslabs += nstr[cls];
+    }
     // every stream gets an equal share of the budget: its class's workspace
     // (at most half of the share; fewer resident workgroups when smaller),
     // then the arena
@@ -582,9 +603,10 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
         }
     }
     s->slabs.resize((size_t)nslabs);
-    for (int k = 0; k < nslabs; ++k) {
+    for (int k = 0, cls = first_class, left = nstr[first_class]; k < nslabs; ++k, --left) {
+        while (left == 0) left = nstr[++cls];
         Slab &b = s->slabs[(size_t)k];
-        b.cls = first_class + k / cfg.streams;
+        b.cls = cls;
         b.ws_bytes = ws_class[b.cls];
         b.cap_words = cap_words[b.cls];
         b.cap_vlab = cap_vlab[b.cls];

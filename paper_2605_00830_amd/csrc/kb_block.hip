@@ -6,8 +6,9 @@
 // Beam slots are spread over the threads: G = min(KS, 256) slots per round,
 // TPS = 256 / G threads per slot (thread t = slot-in-round * TPS + part),
 // each part owning a contiguous range of the slot's children (substitutions
-// by ascending g2 vertex, the deletion last), so thread order is generation
-// order.
+// by ascending free g2 vertex -- child j substitutes the slot's j-th unused
+// vertex -- the deletion last), so thread order is generation order and only
+// valid children are ever evaluated.
 // Per level i (the loop of Alg. 1, g1 vertex v_i):
 //   expand    every thread builds its slot's Phi = image of v_i's earlier
 //             neighbours (one bit per g2 vertex, one set per edge-label
@@ -34,9 +35,10 @@
 //
 // LDS holds g2's rows padded to W words (read with vector loads, no bounds
 // tests), its label planes when they fit, and the candidate matrix as
-// cand[s][c] (odd row stride, so the parts of a wave hit different banks)
-// when everything fits 136 KB (CL); otherwise the candidate matrix lives in
-// the per-block global workspace as cand[c][s] (consecutive slots coalesce).
+// cand[s][j] (child j of slot s; odd row stride, so the parts of a wave hit
+// different banks) when everything fits 136 KB (CL); otherwise the candidate
+// matrix lives in the per-block global workspace as cand[j][s] (consecutive
+// slots coalesce).
 // Beam state per slot in the workspace (slot-minor): PED, |Img|, g2 edges
 // inside Img, Img bitset, mapping phi[j] (uint16, 0xffff = deleted).
 //
@@ -54,7 +56,13 @@ namespace gedk {
 namespace {
 
 constexpr int NBINS = 1024;
-constexpr int SENT = 0x7fffffff;        // invalid child (target vertex already used)
+// beam-state loads a thread issues together: many for large graphs, whose
+// beam state lives in HBM and whose levels are long; few for small ones,
+// whose occupancy the extra registers would cut (and fewer again where the
+// sets already take most registers)
+template <int W, int PL>
+constexpr int loads_together() { return W < 8 ? 2 : (W * (1 + PL) >= 64 ? 8 : 16); }
+constexpr int SENT = 0x7fffffff;        // above every partial edit distance (empty minima)
 constexpr uint16_t PHI_DEL = 0xffff;
 constexpr size_t kDynLdsBytes = 136 * 1024;    // rows, staged planes, candidate matrix
 constexpr size_t kPlaneLdsBytes = 48 * 1024;   // rows plus planes staged when they fit this
@@ -75,7 +83,7 @@ struct BlockArgs {
     int last_complete;   // last level: complete every child, keep the least total
     int KS;        // slot stride
     int TPS;       // threads per slot
-    int rows_words;   // LDS words per staged block of g2 rows (nmax2 x W)
+    int rows_words;   // LDS words per staged block of g2 rows (nmax2 x row_stride(W))
     int planes_lds;   // label planes staged in LDS after the rows
     char *ws;
     WsLayout L;
@@ -163,6 +171,55 @@ __device__ __forceinline__ uint32_t below_mask(int i, int kw) {
     return rem >= 32 ? 0xffffffffu : ((1u << rem) - 1u);
 }
 
+// The free g2 vertices of a slot -- vertices below n2 whose bit in the first
+// NWF words of Img is clear -- in ascending order, from a given rank on.  A
+// slot's substitution children are its free vertices in this order (the
+// deletion child comes last), so child j substitutes the j-th free vertex.
+// Word selection is unrolled: no register array is indexed dynamically.
+// LDS stride of a staged row of W words: rows of 8 or more words are padded
+// by four words, so that lanes reading the rows of different vertices (each
+// lane visits its own slot's free vertices) start on different banks; the
+// stride stays a multiple of four words for 16-byte loads.
+__host__ __device__ constexpr int row_stride(int W) { return W >= 8 ? W + 4 : W; }
+
+template <int W, int NWF>
+struct FreeIter {
+    uint32_t fr = 0u;   // free bits of word cw not yet visited
+    int cw = 0;         // current word
+
+    __device__ __forceinline__ static uint32_t free_word(const uint32_t (&img)[W], int k, int n2) {
+        uint32_t w = 0u;
+#pragma unroll
+        for (int q = 0; q < NWF; ++q) w = (q == k) ? img[q] : w;
+        const int rem = n2 - 32 * k;
+        const uint32_t valid = rem >= 32 ? 0xffffffffu : (rem <= 0 ? 0u : ((1u << rem) - 1u));
+        return ~w & valid;
+    }
+    // position before the free vertex of rank j0
+    __device__ __forceinline__ void seek(const uint32_t (&img)[W], int n2, int j0) {
+        cw = 0;
+        fr = free_word(img, 0, n2);
+        for (;;) {
+            const int c = __popc(fr);
+            if (j0 < c || cw >= NWF - 1) break;
+            j0 -= c;
+            ++cw;
+            fr = free_word(img, cw, n2);
+        }
+        for (; j0 > 0 && fr; --j0) fr &= fr - 1u;
+    }
+    // the next free vertex (the caller asks only while one remains)
+    __device__ __forceinline__ int next(const uint32_t (&img)[W], int n2) {
+        while (fr == 0u && cw < NWF - 1) {
+            ++cw;
+            fr = free_word(img, cw, n2);
+        }
+        const int u = 32 * cw + (int)__builtin_ctzg(fr, 31);
+        fr &= fr - 1u;
+        return u;
+    }
+};
+
 template <int W, int PL, bool CL, int BT, bool DIR>
 __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
@@ -186,7 +243,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     uint32_t *img_b = reinterpret_cast<uint32_t *>(wsb + a.L.img);
     uint16_t *phi_b = reinterpret_cast<uint16_t *>(wsb + a.L.phi);
     int *__restrict__ cand_g = reinterpret_cast<int *>(wsb + a.L.cand);
-    uint32_t *s_rows = s_dyn;             // row u at u * W, padded with zero words
+    constexpr int RS = row_stride(W);
+    uint32_t *s_rows = s_dyn;             // row u at u * RS, padded with zero words
     uint32_t *s_planes = s_dyn + a.rows_words;
     int *cand_l = reinterpret_cast<int *>(s_dyn + a.rows_words * (1 + (a.planes_lds ? PL : 0)));
     const int KS = a.KS;
@@ -199,6 +257,8 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     const Costs c = a.c;
     const int P = a.dst.planes;
     constexpr int DH = DIR ? W / 2 : 0;   // first word of the in-half (directed)
+    constexpr int NWF = DIR ? W / 2 : W;  // words of Img that name g2 vertices
+    constexpr int LB = loads_together<W, PL>();
     static_assert(!DIR || W >= 2, "a directed row has two halves");
 
     for (bool first = true;; first = false) {
@@ -226,24 +286,31 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
         // directed: the in-arc rows and planes follow the out-arc ones
         const uint32_t *A1in = A1 + (size_t)(1 + a.src.planes) * pl1;
         const uint32_t *A2in = A2 + (size_t)(1 + P) * pl2;
-        const int nc = n2 + 1;                       // children per slot (deletion = n2)
+        const int nc = n2 + 1;                       // most children of a slot (deletion last)
         const int CST = nc | 1;                      // LDS row stride of the candidate matrix
-        const int chunk = (nc + TPS - 1) / TPS;      // children per part
-        const int c_lo = min(part * chunk, nc), c_hi = min(c_lo + chunk, nc);
+        // a slot with `ns` substitutions so far has n2 - ns + 1 children;
+        // part `part` of its threads owns a contiguous range of them
+        auto part_range = [&](int ns, int *jlo, int *jhi) {
+            const int ncs = n2 - ns + 1;
+            const int ch = (ncs + TPS - 1) / TPS;
+            *jlo = min(part * ch, ncs);
+            *jhi = min(*jlo + ch, ncs);
+            return ncs;
+        };
 
-        for (int x = t; x < n2 * W; x += BT) {
-            const int u = x / W, kk = x % W;
+        for (int x = t; x < n2 * RS; x += BT) {
+            const int u = x / RS, kk = x % RS;
             const bool hi = DH > 0 && kk >= DH;
             const int kr = hi ? kk - DH : kk;
-            s_rows[x] = kr < w2 ? (hi ? A2in : A2)[(size_t)u * w2 + kr] : 0u;
+            s_rows[x] = (kk < W && kr < w2) ? (hi ? A2in : A2)[(size_t)u * w2 + kr] : 0u;
         }
         if (PL > 0 && a.planes_lds) {
-            for (int x = t; x < PL * n2 * W; x += BT) {
-                const int b = x / (n2 * W), r = x % (n2 * W), u = r / W, kk = r % W;
+            for (int x = t; x < PL * n2 * RS; x += BT) {
+                const int b = x / (n2 * RS), r = x % (n2 * RS), u = r / RS, kk = r % RS;
                 const bool hi = DH > 0 && kk >= DH;
                 const int kr = hi ? kk - DH : kk;
                 s_planes[(size_t)b * a.rows_words + r] =
-                    (b < P && kr < w2) ? (hi ? A2in : A2)[(size_t)(1 + b) * pl2 + (size_t)u * w2 + kr] : 0u;
+                    (b < P && kk < W && kr < w2) ? (hi ? A2in : A2)[(size_t)(1 + b) * pl2 + (size_t)u * w2 + kr] : 0u;
             }
         }
         if (t == 0) {
@@ -293,6 +360,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             }
 
             const int *__restrict__ pedc = ped_b + cur * KS;
+            const int *__restrict__ nsubc = nsub_b + cur * KS;
             const uint32_t *__restrict__ imgc = img_b + (size_t)cur * W * KS;
             const uint16_t *__restrict__ phic = phi_b + cur * a.L.phi_half;
 
@@ -326,21 +394,32 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 // with many earlier neighbours the slot's parts split them (each
                 // part looks up every TPS-th one) and OR their sets together:
                 // the parts of a slot are adjacent lanes of one wave
-#pragma unroll 8
-                for (int q = coop ? part : 0; q < degP; q += coop ? TPS : 1) {
-                    const int nq = s_nbr[q];
-                    const int x = phic[(size_t)(nq & 0x7fff) * KS + s];
-                    if (x != PHI_DEL) {
+                // (the images are loaded LB at a time, so that many loads are
+                // in flight before the first is used)
+                const int q0 = coop ? part : 0, qs = coop ? TPS : 1;
+                for (int qb = q0; qb < degP; qb += LB * qs) {
+                    int xs[LB];
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) {
+                        const int q = qb + k * qs;
+                        xs[k] = q < degP ? (int)phic[(size_t)(s_nbr[q] & 0x7fff) * KS + s] : (int)PHI_DEL;
+                    }
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) {
+                        const int x = xs[k];
+                        if (x == PHI_DEL) continue;   // deleted, or past the list
+                        const int q = qb + k * qs;
+                        const int nq = s_nbr[q];
                         const uint32_t bit = 1u << (x & 31);
                         const int xw = (x >> 5) + ((nq >> 15) ? DH : 0);
                         const int code = PL > 0 ? s_nbl[q] : 0;
 #pragma unroll
-                        for (int k = 0; k < W; ++k) {
-                            const uint32_t hit = (k == xw) ? bit : 0u;
-                            phi_r[k] |= hit;
+                        for (int kk = 0; kk < W; ++kk) {
+                            const uint32_t hit = (kk == xw) ? bit : 0u;
+                            phi_r[kk] |= hit;
 #pragma unroll
                             for (int b = 0; b < PLA; ++b)
-                                phib[b][k] |= ((code >> b) & 1) ? hit : 0u;
+                                phib[b][kk] |= ((code >> b) & 1) ? hit : 0u;
                         }
                     }
                 }
@@ -355,21 +434,18 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                         }
                     }
                 }
-                // children u = c_lo .. min(c_hi, n2)-1 in order; the image word of
-                // u is refreshed once per 32 children (no dynamic register index)
-                uint32_t cur_img = 0u;
-                int cur_w = -1;
-                const int u_end = min(c_hi, n2);
+                // this part's children j = jlo .. jhi-1 in generation order: the
+                // j-th free g2 vertex, the deletion last (j = ncs - 1); only free
+                // vertices are evaluated
+                int jlo, jhi;
+                const int ncs = part_range(nsubc[s], &jlo, &jhi);
+                const int jsub = min(jhi, ncs - 1);
+                FreeIter<W, NWF> it;
+                it.seek(img_r, n2, jlo);
 #pragma unroll 2
-                for (int u = c_lo; u < u_end; ++u) {
-                    const int uw = u >> 5;
-                    if (uw != cur_w) {
-                        cur_w = uw;
-                        cur_img = 0u;
-#pragma unroll
-                        for (int k = 0; k < W; ++k) cur_img = (k == uw) ? img_r[k] : cur_img;
-                    }
-                    const uint32_t *R = s_rows + u * W;
+                for (int j = jlo; j < jsub; ++j) {
+                    const int u = it.next(img_r, n2);
+                    const uint32_t *R = s_rows + u * RS;
                     uint32_t row[W];
 #pragma unroll
                     for (int kk = 0; kk < W; ++kk) row[kk] = R[kk];
@@ -384,7 +460,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                             if (a.planes_lds) {
 #pragma unroll
                                 for (int bb = 0; bb < PLA; ++bb)
-                                    diff |= phib[bb][kk] ^ s_planes[(size_t)bb * a.rows_words + u * W + kk];
+                                    diff |= phib[bb][kk] ^ s_planes[(size_t)bb * a.rows_words + u * RS + kk];
                             } else {
                                 const bool hi = DH > 0 && kk >= DH;
                                 const int kr = hi ? kk - DH : kk;
@@ -400,20 +476,16 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     }
                     const int d = pp + s_lc[u] + c.edel * (degP - kept) +
                                   c.eins * (inimg - kept) + c.esub * relab;
-                    const bool used = (cur_img >> (u & 31)) & 1u;
-                    const int v = used ? SENT : d;
-                    if (CL) cand_l[s * CST + u] = v;
-                    else cand_g[(size_t)u * KS + s] = v;
-                    if (!used) {
-                        ++lcnt;
-                        if (d - m0 < NBINS) atomicAdd(&s_hist[d - m0], 1);
-                        else ovmin = min(ovmin, d);
-                    }
+                    if (CL) cand_l[s * CST + j] = d;
+                    else cand_g[(size_t)j * KS + s] = d;
+                    ++lcnt;
+                    if (d - m0 < NBINS) atomicAdd(&s_hist[d - m0], 1);
+                    else ovmin = min(ovmin, d);
                 }
-                if (c_lo <= n2 && c_hi == nc) {   // this part owns the deletion child
+                if (jlo < jhi && jhi == ncs) {   // this part owns the deletion child
                     const int dd = pp + del_cost;
-                    if (CL) cand_l[s * CST + n2] = dd;
-                    else cand_g[(size_t)n2 * KS + s] = dd;
+                    if (CL) cand_l[s * CST + ncs - 1] = dd;
+                    else cand_g[(size_t)(ncs - 1) * KS + s] = dd;
                     ++lcnt;
                     if (dd - m0 < NBINS) atomicAdd(&s_hist[dd - m0], 1);
                     else ovmin = min(ovmin, dd);
@@ -430,8 +502,9 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 // ---------------- complete-then-minimum last level: each
                 // child's total (Sec. 4.4.1); the least, first in generation
                 // order (slot, then column), is the one survivor
+                // (key: total, then slot << 20 | child << 10 | vertex; the child
+                // rank orders a slot's children as the vertex does)
                 const int *einc = ein_b + cur * KS;
-                const int *nsubc = nsub_b + cur * KS;
                 unsigned long long bk = ~0ull;
                 for (int r = 0; r < SPT; ++r) {
                     const int s = r * G + sg;
@@ -440,18 +513,23 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
 #pragma unroll
                     for (int k = 0; k < W; ++k) img_r[k] = imgc[(size_t)k * KS + s];
                     const int e0 = einc[s], used0 = nsubc[s];
-                    for (int u = c_lo; u < c_hi; ++u) {
-                        const int v = cand_at(s, u);
-                        if (v == SENT) continue;
+                    int jlo, jhi;
+                    const int ncs = part_range(used0, &jlo, &jhi);
+                    FreeIter<W, NWF> it;
+                    it.seek(img_r, n2, jlo);
+                    for (int j = jlo; j < jhi; ++j) {
+                        const int v = cand_at(s, j);
+                        const bool sub = j < ncs - 1;
+                        const int u = sub ? it.next(img_r, n2) : n2;
                         int add_e = 0, used = used0;
-                        if (u < n2) {
+                        if (sub) {
 #pragma unroll
-                            for (int k = 0; k < W; ++k) add_e += __popc(img_r[k] & s_rows[u * W + k]);
+                            for (int k = 0; k < W; ++k) add_e += __popc(img_r[k] & s_rows[u * RS + k]);
                             ++used;
                         }
                         const int total = v + c.vins * (n2 - used) + c.eins * (g2.m - e0 - add_e);
-                        const unsigned long long key =
-                            ((unsigned long long)(unsigned)total << 32) | (unsigned)((s << 10) | u);
+                        const unsigned long long key = ((unsigned long long)(unsigned)total << 32) |
+                                                       (unsigned)((s << 20) | (j << 10) | u);
                         bk = key < bk ? key : bk;
                     }
                 }
@@ -462,9 +540,10 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     unsigned long long m = s_red64[0];
 #pragma unroll
                     for (int k = 1; k < NW; ++k) m = s_red64[k] < m ? s_red64[k] : m;
-                    const int sel = (int)(m & 0xffffffffu);
-                    s_sel[0] = sel;
-                    s_selped[0] = cand_at(sel >> 10, sel & 1023);
+                    const int low = (int)(m & 0xffffffffu);
+                    const int bs = low >> 20, bj = (low >> 10) & 1023, bu = low & 1023;
+                    s_sel[0] = (bs << 10) | bu;
+                    s_selped[0] = cand_at(bs, bj);
                 }
                 nb_new = 1;
             } else {
@@ -521,10 +600,12 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     for (int r = 0; r < SPT; ++r) {
                         const int s = r * G + sg;
                         if (s >= nb) break;
-#pragma unroll 8
-                        for (int u = c_lo; u < c_hi; ++u) {
-                            const int v = cand_at(s, u);
-                            if (v == SENT || v < lo) continue;
+                        int jlo, jhi;
+                        (void)part_range(nsubc[s], &jlo, &jhi);
+#pragma unroll 16
+                        for (int j = jlo; j < jhi; ++j) {
+                            const int v = cand_at(s, j);
+                            if (v < lo) continue;
                             if (v - lo < NBINS) atomicAdd(&s_hist[v - lo], 1);
                             else nn = min(nn, v);
                         }
@@ -539,12 +620,19 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 const int s = r * G + sg;
                 const bool live = s < nb;
                 int lt = 0, eq = 0;
+                int jlo = 0, jhi = 0, ncs = 0;
                 if (live) {
-#pragma unroll 8
-                    for (int u = c_lo; u < c_hi; ++u) {
-                        const int v = cand_at(s, u);
-                        lt += v < T;
-                        eq += v == T;
+                    ncs = part_range(nsubc[s], &jlo, &jhi);
+                    for (int jb = jlo; jb < jhi; jb += LB) {
+                        int vv[LB];
+#pragma unroll
+                        for (int k = 0; k < LB; ++k) vv[k] = jb + k < jhi ? cand_at(s, jb + k) : 0;
+#pragma unroll
+                        for (int k = 0; k < LB; ++k) {
+                            const bool in = jb + k < jhi;
+                            lt += (in && vv[k] < T) ? 1 : 0;
+                            eq += (in && vv[k] == T) ? 1 : 0;
+                        }
                     }
                 }
                 int tot;
@@ -555,18 +643,29 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 out_carry += tot;
                 if (live && keep > 0) {
                     int pos = OUT, e = EQ;
-#pragma unroll 8
-                    for (int u = c_lo; u < c_hi; ++u) {
-                        const int v = cand_at(s, u);
-                        bool take = v < T;
-                        if (v == T) {
-                            take = e < quota;
-                            ++e;
-                        }
-                        if (take) {
-                            s_sel[pos] = (s << 10) | u;
-                            s_selped[pos] = v;
-                            ++pos;
+                    uint32_t img_r[W];
+#pragma unroll
+                    for (int k = 0; k < W; ++k) img_r[k] = imgc[(size_t)k * KS + s];
+                    FreeIter<W, NWF> it;
+                    it.seek(img_r, n2, jlo);
+                    for (int jb = jlo; jb < jhi; jb += LB) {
+                        int vv[LB];
+#pragma unroll
+                        for (int k = 0; k < LB; ++k) vv[k] = jb + k < jhi ? cand_at(s, jb + k) : 0;
+                        for (int k = 0; k < LB && jb + k < jhi; ++k) {
+                            const int j = jb + k;
+                            const int v = vv[k];
+                            const int u = j < ncs - 1 ? it.next(img_r, n2) : n2;
+                            bool take = v < T;
+                            if (v == T) {
+                                take = e < quota;
+                                ++e;
+                            }
+                            if (take) {
+                                s_sel[pos] = (s << 10) | u;
+                                s_selped[pos] = v;
+                                ++pos;
+                            }
                         }
                     }
                 }
@@ -581,7 +680,6 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
             int *einn = ein_b + nxt * KS;
             int *nsubn = nsub_b + nxt * KS;
             const int *einc = ein_b + cur * KS;
-            const int *nsubc = nsub_b + cur * KS;
             uint32_t *__restrict__ imgn = img_b + (size_t)nxt * W * KS;
             uint16_t *__restrict__ phin = phi_b + nxt * a.L.phi_half;
             for (int r = 0; r < SPT; ++r) {
@@ -590,15 +688,26 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 const int sel = s_sel[s2];
                 const int p = sel >> 10, u = sel & 1023;
                 const bool sub = u < n2;
-#pragma unroll 8
-                for (int j = part; j < i; j += TPS) phin[(size_t)j * KS + s2] = phic[(size_t)j * KS + p];
+                for (int jb = part; jb < i; jb += LB * TPS) {
+                    uint16_t x[LB];
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) {
+                        const int j = jb + k * TPS;
+                        x[k] = j < i ? phic[(size_t)j * KS + p] : (uint16_t)0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < LB; ++k) {
+                        const int j = jb + k * TPS;
+                        if (j < i) phin[(size_t)j * KS + s2] = x[k];
+                    }
+                }
                 if (part == 0) {
                     phin[(size_t)i * KS + s2] = sub ? (uint16_t)u : PHI_DEL;
                     int add_e = 0;
 #pragma unroll
                     for (int k = 0; k < W; ++k) {
                         const uint32_t ip = imgc[(size_t)k * KS + p];
-                        const uint32_t row = sub ? s_rows[u * W + k] : 0u;
+                        const uint32_t row = sub ? s_rows[u * RS + k] : 0u;
                         add_e += __popc(ip & row);
                         const bool at = (u >> 5) == k || (DH > 0 && (u >> 5) + DH == k);
                         imgn[(size_t)k * KS + s2] = ip | ((sub && at) ? (1u << (u & 31)) : 0u);
@@ -654,7 +763,7 @@ __global__ void fill_zero_kernel(int *p, int count) {
 
 int cand_stride_max(const BlockShape &s) { return (s.nmax2 + 1) | 1; }
 
-int rows_words(const BlockShape &s) { return s.nmax2 * s.W; }
+int rows_words(const BlockShape &s) { return s.nmax2 * row_stride(s.W); }
 
 bool planes_in_lds(const BlockShape &s) {
     return s.PL > 0 && (size_t)(1 + s.PL) * (size_t)rows_words(s) * 4 <= kPlaneLdsBytes;
