@@ -184,9 +184,9 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
                            ged_plan **out);
 
 /* Kernel schedules.  GED_SCHED_AUTO lets the library choose per size bin:
- * a wavefront per pair (beam in registers) where n1, n2 <= 64 and K <= 64
- * (one instantiation for n <= 32, one for n <= 64), else a workgroup per
- * pair.  GED_SCHED_BLOCK forces the
+ * a wavefront per pair (beam in registers) where n1, n2 <= 64 and K <= 128
+ * (one kernel for n <= 32 at K <= 64, one for the rest, with two beam slots
+ * per lane above K = 64), else a workgroup per pair.  GED_SCHED_BLOCK forces the
  * workgroup-per-pair kernel for every pair.  Every schedule computes the
  * same result bit for bit. */
 #define GED_SCHED_AUTO 0
@@ -454,7 +454,7 @@ ged_status ged_wide_destroy(ged_wide *w);
  * with the database's edge-label coding) to be edited into database graph
  * `target_id` -- and poll for results.  Queries are sorted at submission
  * into four size classes with queues and streams of their own: small
- * (n1, n2 <= 32) and mid (n1, n2 <= 64), both for K <= 64 (the wavefront
+ * (n1, n2 <= 32, K <= 64) and mid (n1, n2 <= 64, K <= 128; the wavefront
  * kernels), medium (n1, n2 <= 128) and large, so a small query never waits
  * for a larger one's batch.  A
  * worker thread owned by the server admits queued queries while device

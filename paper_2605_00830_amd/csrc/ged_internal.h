@@ -76,30 +76,31 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
                        int last_complete, void *ws, size_t ws_bytes, int32_t *dist, int32_t *map, int64_t *cand,
                        int cus, hipStream_t stream);
 
-// Wavefront family that fits a pair: 1 (n1, n2 <= 32), 2 (n1, n2 <= 64), 0
-// none (K > 64 or a larger graph).
+// Wavefront family that fits a pair: 1 (n1, n2 <= 32 and K <= 64), 2 (else
+// n1, n2 <= 64 and K <= 128), 0 none (K > 128 or a larger graph).
 __host__ __device__ inline int wave_words_for(int n1, int n2, int K) {
-    if (K > kWaveMaxK) return 0;
+    if (K > kWave2MaxK) return 0;
     const int n = n1 > n2 ? n1 : n2;
-    return n <= kWaveMaxN ? 1 : (n <= kWave2MaxN ? 2 : 0);
+    if (n > kWave2MaxN) return 0;
+    return (n <= kWaveMaxN && K <= kWaveMaxK) ? 1 : 2;
 }
 // Directed pairs of up to 32 vertices on the two-word wavefront kernel
 // (kb_wave2.hip, DIR instantiations): a row word of out-arcs and one of
 // in-arcs per vertex.
-hipError_t wave2_max_resident_dir(int PL, int last_complete, int directed, int *blocks_per_cu);
+hipError_t wave2_max_resident_dir(int PL, int K, int last_complete, int directed, int *blocks_per_cu);
 hipError_t launch_wave2_dir(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                             Costs c, int K, int last_complete, int directed, Outputs out, int grid,
                             hipStream_t stream);
-// Wavefront family of a directed pair: 2 when both orders are <= 32 and K <= 64.
+// Wavefront family of a directed pair: 2 when both orders are <= 32 and K <= 128.
 __host__ __device__ inline int wave_words_for_directed(int n1, int n2, int K) {
-    return (K <= kWaveMaxK && n1 <= kWaveMaxN && n2 <= kWaveMaxN) ? 2 : 0;
+    return (K <= kWave2MaxK && n1 <= kWaveMaxN && n2 <= kWaveMaxN) ? 2 : 0;
 }
 
-inline hipError_t wave_family_max_resident(int words, int PL, int last_complete, int *blocks_per_cu,
+inline hipError_t wave_family_max_resident(int words, int PL, int K, int last_complete, int *blocks_per_cu,
                                            int directed = 0) {
-    if (directed) return wave2_max_resident_dir(PL, last_complete, 1, blocks_per_cu);
+    if (directed) return wave2_max_resident_dir(PL, K, last_complete, 1, blocks_per_cu);
     return words == 1 ? wave_max_resident(PL, last_complete, blocks_per_cu)
-                      : wave2_max_resident(PL, last_complete, blocks_per_cu);
+                      : wave2_max_resident(PL, K, last_complete, blocks_per_cu);
 }
 inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const DbView &dst, const WorkItem *work,
                                      int nwork, int *queue, Costs c, int K, int last_complete, Outputs out, int grid,
@@ -111,8 +112,8 @@ inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const
 }
 
 // Size bins of the default schedule of the tree search: 0 / 1 = the
-// wavefront kernels (n <= 32 / n <= 64, K <= 64; a directed pair of up to 32
-// vertices takes 1), 2 + log2(W) = the workgroup kernel whose rows have W
+// wavefront kernels (n <= 32 and K <= 64 / the rest of n <= 64 and K <= 128;
+// a directed pair of up to 32 vertices takes 1), 2 + log2(W) = the workgroup kernel whose rows have W
 // words (target words rounded up to a power of two, doubled for a directed
 // database's out and in rows).  The same function classifies pairs on the
 // host and on the device.

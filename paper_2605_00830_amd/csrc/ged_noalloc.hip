@@ -142,7 +142,7 @@ extern "C" ged_status ged_kbest_noalloc(ged_db *db, const ged_pair *h_pairs, int
     for (int b = 0; b < gedk::kPairBins; ++b) {
         if (count[b] == 0) continue;
         int per_cu = 0;
-        hipError_t e = b < 2 ? gedk::wave_family_max_resident(b + 1, PL, 0, &per_cu, directed)
+        hipError_t e = b < 2 ? gedk::wave_family_max_resident(b + 1, PL, K, 0, &per_cu, directed)
                              : gedk::block_max_resident(shape[b], &per_cu);
         if (e != hipSuccess || per_cu <= 0)
             return fail(GED_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));

@@ -565,7 +565,7 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             e = gedk::block_max_resident(sh, &b.max_block_per_cu[k]);
         }
         if (e == hipSuccess && b.wave_ok)
-            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, p->last_complete, &b.max_wave_per_cu,
+            e = gedk::wave_family_max_resident(b.wave_words, b.shape.PL, K, p->last_complete, &b.max_wave_per_cu,
                                                b.shape.directed);
         if (e != hipSuccess || b.max_block_per_cu[0] <= 0 || b.max_block_per_cu[1] <= 0 ||
             ((b.wave_ok || b.bip) && b.max_wave_per_cu <= 0)) {

@@ -516,12 +516,14 @@ ged_status ged_server_create(ged_db *db, const ged_server_config *config, ged_se
     s->bip = cfg.method == GED_METHOD_BIPARTITE;
     s->directed = db->directed;
     hipError_t e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device);
-    const bool wave_classes = !s->bip && cfg.K <= gedk::kWaveMaxK;
+    const bool wave_classes = !s->bip && cfg.K <= gedk::kWave2MaxK;
     for (int k = 0; k < kWaveBins && e == hipSuccess && wave_classes; ++k)
-        e = gedk::wave_family_max_resident(k + 1, s->PL, 0, &s->wave_per_cu[k], s->directed ? 1 : 0);
-    // classes that can receive a query get streams: a directed database has no
-    // one-word class (its pairs of up to 32 vertices take the two-word kernel)
-    const int first_class = s->bip ? 0 : (wave_classes ? (s->directed ? 1 : 0) : kFirstBlockClass);
+        e = gedk::wave_family_max_resident(k + 1, s->PL, cfg.K, 0, &s->wave_per_cu[k], s->directed ? 1 : 0);
+    // classes that can receive a query get streams: a directed database and a
+    // beam above 64 slots have no one-word class (their pairs of up to 32
+    // vertices take the two-word kernel)
+    const int first_class =
+        s->bip ? 0 : (wave_classes ? ((s->directed || cfg.K > gedk::kWaveMaxK) ? 1 : 0) : kFirstBlockClass);
     // streams per class: the configured number, and kLargeStreams times it for
     // the tree search's large class, whose batches last as long as their
     // slowest pair (tens of milliseconds): more of them in flight keep its

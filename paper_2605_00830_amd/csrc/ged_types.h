@@ -60,10 +60,11 @@ hipError_t launch_wave(int PL, const DbView &src, const DbView &dst, const WorkI
                        int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 
 // The same scheme for n1, n2 <= 64 (two-word vertex sets, children scored
-// into bytes), K <= 64.
+// into bytes), K <= 128 (two beam slots per lane above 64).
 constexpr int kWave2MaxN = 64;
+constexpr int kWave2MaxK = 128;
 
-hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu);
+hipError_t wave2_max_resident(int PL, int K, int last_complete, int *blocks_per_cu);
 hipError_t launch_wave2(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                         Costs c, int K, int last_complete, Outputs out, int grid, hipStream_t stream);
 

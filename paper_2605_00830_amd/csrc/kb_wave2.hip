@@ -1,544 +1,28 @@
-// kb_wave2.hip -- wavefront-per-pair K-Best search for pairs of up to 64
-// vertices on gfx950.
-//
-// The same scheme as kb_wave.hip (one 64-lane wavefront per pair, lane s =
-// beam slot s, persistent over a work queue whose first pair is the
-// workgroup's index) for n1, n2 <= 64 and K <= 64: vertex sets are 64-bit
-// (two words), the mapping phi is sixteen words of bytes, and a slot has up
-// to 64 substitution children, too many to keep as 32-bit values.  Children
-// are therefore scored straight into bytes relative to a base b:
-//   x = 0 if PED < b, else min((PED - b) >> sh, 126) + 1,
-// four to a register, and the threshold search, the keep masks and the tie
-// quota all work on those bytes:
-//   fast pass   b = the least PED of the beam's slots (every child's PED is at
-//               least its parent's, so nothing lies below b) and sh = 0: the
-//               bytes are exact offsets for PEDs below b + 126.  This holds
-//               whenever the K-th smallest child is within 125 of the least
-//               parent, which is the common case.
-//   otherwise   the children are scored again with b = that least PED + 126
-//               and sh = 24 (buckets of 2^24 cover every valid PED), the
-//               bucket holding the K-th smallest child becomes the new base
-//               and sh drops by 7, until sh = 0 and the threshold is exact
-//               (at most five more passes).
-// count(x <= t) for 1 <= t <= 126 is a popcount of byte-wise compares
-// (((t * 0x01010101) | 0x80808080) - packed) & 0x80808080, summed over the
-// wave; two thresholds per reduction, starting from the previous level's t.
-// With T = b + t* - 1 found in the final pass, a child is below T iff its
-// byte is below t* and equal to T iff its byte is t*; children below b have
-// byte 0 and are below T.
-//
-// Per level i (Alg. 1), with P = earlier neighbours of v_i, Phi = images of
-// P, A = Img \ Phi: the child (v_i -> u) costs
-//   (PED + edel |P|) + vsub [alpha1(v_i) != alpha2(u)] + eins |A & N2(u)|
-//   - edel |Phi & N2(u)| [+ esub |Phi & N2(u) & relabelled|]      (Sec. 2.3)
-// and child j of a slot substitutes its j-th free g2 vertex (ascending, so
-// j order is generation order), with N2(u) and the label cost from a
-// per-level LDS table whose entry 64 is a sentinel for exhausted free sets
-// (empty row, label cost 0xffffffff, saturating add: the invalid value
-// 0xffffffff).  The deletion child costs PED + vdel + edel |P|.  Survivors:
-// every child below T and the first (K - #below) children equal to T in
-// generation order (lane, then j, then the deletion), written to LDS as
-// (parent, j); a new slot reads its vertex from the parent's record and
-// recomputes its PED with the same formula.  Completion adds vins
-// (n2 - |Img|) + eins (m2 - e_in) (Sec. 4.4.1); the first lane of least total
-// is the result.  The COMPLETE instantiation's last level instead completes every
-// child and keeps only the least total (first in generation order).
-//
-// The DIR instantiation takes directed pairs of up to 32 vertices (each edge
-// an arc, one edit operation per arc): a vertex's 64-bit row is its out-arc
-// row in the low word and its in-arc row in the high word, Img holds the
-// image in both words, and an earlier neighbour j + 32 of the g1 row (an
-// in-arc of v_i from j) sets its Phi bit in the high word.  The formulas
-// above then count kept, deleted, inserted and relabelled arcs of both
-// directions at once (the implied operations of Sec. 2.3 per arc direction);
-// only |Img| reads the low word alone.
-#include "ged_internal.h"
-#include "wave_common.h"
+// kb_wave2.hip -- the two-word wavefront kernel (kb_wave2.h) with one beam
+// slot per lane (K <= 64), and the launch and occupancy functions of the
+// family, which take the two-slot instantiations of kb_wave2_k128.hip for
+// 64 < K <= 128.
+#include "kb_wave2.h"
 
 namespace gedk {
 namespace {
-
-using namespace wv;
-
-constexpr uint32_t INVALID = 0xffffffffu;
-constexpr uint32_t DEL8 = 0xffu;
-constexpr int TOP = 127;          // byte above every threshold (126 is the largest)
-
-struct Wave2Args {
-    DbView src;   // graphs edited (g1)
-    DbView dst;   // target graphs (g2); same edge-label coding as src
-    const WorkItem *work;
-    int nwork;
-    int *queue;
-    Costs c;
-    int K;
-    Outputs out;
-};
-
-__device__ __forceinline__ uint64_t u64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
-    return u64((uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l),
-               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l));
-}
-
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int l) {
-    return u64((uint32_t)__shfl((int)(uint32_t)v, l), (uint32_t)__shfl((int)(uint32_t)(v >> 32), l));
-}
-
-__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
-
-// byte of a child's PED against base b and shift sh (see above)
-__device__ __forceinline__ uint32_t to_byte(uint32_t d, uint32_t b, int sh) {
-    return d < b ? 0u : min((d - b) >> sh, 126u) + 1u;
-}
-
-template <int PL, bool SMALL, bool COMPLETE, bool DIR>
-__global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
-    constexpr int PLA = PL > 0 ? PL : 1;
-    __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
-    __shared__ uint4 s_tab[65];             // per level: (N2(u) lo, hi, label cost, 0); [64] = sentinel
-    __shared__ uint32_t s_uv[16][64];       // per level: [j / 4][slot] = g2 vertices of children j, bytes
-    __shared__ uint2 s_pl[PLA][65];         // label-plane rows of g2; [64] = 0
-    __shared__ int s_item;
-
-    const int lane = threadIdx.x;
-    const uint32_t vsub = (uint32_t)a.c.vsub, vdel = (uint32_t)a.c.vdel, vins = (uint32_t)a.c.vins;
-    const uint32_t esub = (uint32_t)a.c.esub, edel = (uint32_t)a.c.edel, eins = (uint32_t)a.c.eins;
-    const uint32_t nedel = 0u - edel;
-    const int K = a.K;
-    const int P = a.dst.planes;
-
-    for (bool first = true;; first = false) {
-        int item = (int)blockIdx.x;
-        if (!first) {
-            if (lane == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
-            __syncthreads();
-            item = __builtin_amdgcn_readfirstlane(s_item);
-            __syncthreads();
-        }
-        if (item >= a.nwork) break;
-
-        const WorkItem wi = a.work[item];
-        const GraphRec g1 = a.src.graphs[wi.src];
-        const GraphRec g2 = a.dst.graphs[wi.dst];
-        const int n1 = g1.n, n2 = g2.n, w1 = g1.w, w2 = g2.w;
-        const uint32_t *A1 = a.src.adj + g1.adj;
-        const uint32_t *A2 = a.dst.adj + g2.adj;
-        // directed (n <= 32, one row word): the in-arc rows and planes follow the out-arc ones
-        const uint32_t *A1in = A1 + (size_t)(1 + a.src.planes) * n1 * w1;
-        const uint32_t *A2in = A2 + (size_t)(1 + P) * n2 * w2;
-        const uint64_t r1 = lane < n1 ? u64(A1[(size_t)lane * w1], DIR ? A1in[(size_t)lane * w1]
-                                                                     : (w1 > 1 ? A1[(size_t)lane * w1 + 1] : 0u))
-                                      : 0ull;
-        const uint64_t r2 = lane < n2 ? u64(A2[(size_t)lane * w2], DIR ? A2in[(size_t)lane * w2]
-                                                                     : (w2 > 1 ? A2[(size_t)lane * w2 + 1] : 0u))
-                                      : 0ull;
-        const int l1 = lane < n1 ? a.src.vlab[g1.vlab + lane] : 0;
-        const int l2 = lane < n2 ? a.dst.vlab[g2.vlab + lane] : 0;
-        uint64_t p1[PLA];
-#pragma unroll
-        for (int b = 0; b < PLA; ++b) {
-            p1[b] = 0ull;
-            if (PL > 0 && b < P && lane < n1) {
-                const uint32_t *B1 = A1 + (size_t)(1 + b) * n1 * w1 + (size_t)lane * w1;
-                const uint32_t *B1in = A1in + (size_t)(1 + b) * n1 * w1 + (size_t)lane * w1;
-                p1[b] = u64(B1[0], DIR ? B1in[0] : (w1 > 1 ? B1[1] : 0u));
-            }
-            if (PL > 0 && lane <= 64) {
-                uint2 v = make_uint2(0u, 0u);
-                if (b < P && lane < n2) {
-                    const uint32_t *B2 = A2 + (size_t)(1 + b) * n2 * w2 + (size_t)lane * w2;
-                    const uint32_t *B2in = A2in + (size_t)(1 + b) * n2 * w2 + (size_t)lane * w2;
-                    v = make_uint2(B2[0], DIR ? B2in[0] : (w2 > 1 ? B2[1] : 0u));
-                }
-                s_pl[b][lane] = v;
-            }
-        }
-        if (PL > 0 && lane == 0) {
-#pragma unroll
-            for (int b = 0; b < PLA; ++b) s_pl[b][64] = make_uint2(0u, 0u);
-        }
-        const uint64_t umask = n2 >= 64 ? ~0ull : ((1ull << n2) - 1ull);
-
-        uint32_t ped = 0u, ein = 0u;
-        uint64_t img = 0ull;
-        uint32_t ph[16];
-#pragma unroll
-        for (int w = 0; w < 16; ++w) ph[w] = 0u;
-        int nb = 1, hint = 1;
-        long long ce = 0;
-
-        for (int i = 0; i < n1; ++i) {
-            const uint64_t below = DIR ? (((1ull << i) - 1ull) * 0x100000001ull)   // i < 32: both words
-                                       : (i >= 64 ? ~0ull : ((1ull << i) - 1ull));
-            const uint64_t nbm = readlane64(r1, i) & below;
-            const int lab1 = __builtin_amdgcn_readlane(l1, i);
-            const uint32_t degP = popc64(nbm);
-            uint64_t q[PLA];
-#pragma unroll
-            for (int b = 0; b < PLA; ++b) q[b] = PL > 0 ? readlane64(p1[b], i) & nbm : 0ull;
-            const bool live = lane < nb;
-            // lane u: (N2(u), label cost); entry 64: the exhausted-set sentinel
-            s_tab[lane] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), l2 != lab1 ? vsub : 0u, 0u);
-            if (lane == 0) s_tab[64] = make_uint4(0u, 0u, INVALID, 0u);
-
-            // ---------------- Phi, word by word of the mapping
-            uint64_t phi = 0ull, phib[PLA];
-#pragma unroll
-            for (int b = 0; b < PLA; ++b) phib[b] = 0ull;
-#pragma unroll
-            for (int w = 0; w < 16; ++w) {
-                if (((nbm >> (4 * w)) & 0xfull) == 0ull) continue;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int j = 4 * w + k;
-                    if (!((nbm >> j) & 1ull)) continue;
-                    // directed: bit j >= 32 is the in-arc from vertex j - 32
-                    const int wsrc = DIR && w >= 8 ? w - 8 : w;   // a constant once unrolled
-                    const uint32_t x = __builtin_amdgcn_ubfe(ph[wsrc], (uint32_t)k * 8u, 8u);
-                    const uint64_t bit = x < 64u ? (1ull << (x + (DIR && w >= 8 ? 32u : 0u))) : 0ull;
-                    phi |= bit;
-#pragma unroll
-                    for (int b = 0; b < PLA; ++b)
-                        if (PL > 0 && ((q[b] >> j) & 1ull)) phib[b] |= bit;
-                }
-            }
-            const uint64_t ai = img & ~phi;
-            const uint32_t basel = live ? ped + mul_cost<SMALL>(degP, edel) : 0u;
-            const uint64_t free = live ? (~img & umask) : 0ull;
-            const uint32_t nfree = popc64(free);
-            const int ngroups = (int)(wave_umax(nfree) + 3u) >> 2;   // children in groups of four
-            const int V = (int)wave_sum(live ? nfree + 1u : 0u);
-            ce += V;
-            const bool trim = V > K;
-            const uint32_t cdel = live ? basel + vdel : INVALID;
-            __syncthreads();
-
-            // PED of the child substituting v_i by u (u = 64: the exhausted-set
-            // sentinel, whose label cost saturates the sum to 0xffffffff)
-            auto score = [&](uint32_t u) -> uint32_t {
-                const uint4 t = s_tab[u];
-                const uint64_t R = u64(t.x, t.y);
-                uint32_t d = msub_cost<SMALL>(popc64(phi & R), nedel,
-                                              mad_cost<SMALL>(popc64(ai & R), eins,
-                                                              __builtin_elementwise_add_sat(basel, t.z)));
-                if (PL > 0) {
-                    uint64_t diff = 0ull;
-#pragma unroll
-                    for (int b = 0; b < PLA; ++b) {
-                        const uint2 pl = s_pl[b][u];
-                        diff |= phib[b] ^ u64(pl.x, pl.y);
-                    }
-                    d += mul_cost<SMALL>(popc64(phi & R & diff), esub);
-                }
-                return d;
-            };
-            // one pass: every child's byte against (base, sh) into pk; the
-            // first pass also records each child's vertex
-            uint32_t pk[16];
-            auto pass = [&](uint32_t base, int sh, bool record) {
-                uint64_t fr = free;
-#pragma unroll
-                for (int g = 0; g < 16; ++g) {
-                    if (g < ngroups) {
-                        uint32_t w = 0u, uw = 0u;
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const uint32_t u = (uint32_t)__builtin_ctzg(fr, 64);   // 64 once exhausted
-                            fr &= fr - 1ull;
-                            uw |= u << (8 * k);
-                            w |= to_byte(score(u), base, sh) << (8 * k);
-                        }
-                        pk[g] = w;
-                        if (record) s_uv[g][lane] = uw;
-                    } else {
-                        pk[g] = 0x7f7f7f7fu;
-                    }
-                }
-            };
-            // count(byte <= ta) and count(byte <= tb), summed over the wave in
-            // the low and high halves of one word
-            auto counts2 = [&](uint32_t pkd, int ta, int tb) {
-                const uint32_t Ca = ((uint32_t)ta * 0x01010101u) | 0x80808080u;
-                const uint32_t Cb = ((uint32_t)tb * 0x01010101u) | 0x80808080u;
-                uint32_t ca = (uint32_t)__popc((Ca - pkd) & 0x80808080u);
-                uint32_t cb = (uint32_t)__popc((Cb - pkd) & 0x80808080u);
-#pragma unroll
-                for (int g = 0; g < 16; ++g) {
-                    if (g < ngroups) {
-                        ca += (uint32_t)__popc((Ca - pk[g]) & 0x80808080u);
-                        cb += (uint32_t)__popc((Cb - pk[g]) & 0x80808080u);
-                    }
-                }
-                return wave_sum(ca | (cb << 16));
-            };
-            // smallest t in [1, 126] with count(byte <= t) >= K (127 = none),
-            // two thresholds per round starting at `start`
-            auto search = [&](uint32_t pkd, int start) {
-                int lo = 1, hi = TOP;
-                int ta = max(min(start, TOP - 1) - 1, 1);
-                int tb = min(ta + 1, TOP - 1);
-                for (int s = 1;; s <<= 1) {
-                    const uint32_t c2 = counts2(pkd, ta, tb);
-                    if ((int)(c2 >> 16) >= K) hi = min(hi, tb);
-                    else lo = max(lo, tb + 1);
-                    if ((int)(c2 & 0xffffu) >= K) hi = min(hi, ta);
-                    else lo = max(lo, ta + 1);
-                    if (lo >= hi) break;
-                    if (hi == TOP) {
-                        ta = min(lo + s - 1, TOP - 1);
-                        tb = min(lo + 2 * s, TOP - 1);
-                    } else if (lo == 1) {
-                        tb = hi - 1;
-                        ta = max(hi - 1 - s, 1);
-                    } else {
-                        const int span = hi - lo;   // probe points lie in [lo, hi - 1]
-                        ta = lo + (span - 1) / 3;
-                        tb = lo + (2 * span - 1) / 3;
-                    }
-                }
-                return lo;
-            };
-
-            // ---------------- threshold T (byte t_T in the final pass)
-            const uint32_t m0 = wave_umin(live ? ped : INVALID);   // no child lies below
-            pass(m0, 0, true);
-            int nb_new;
-            if (COMPLETE && i == n1 - 1) {
-                // ---------------- complete-then-minimum last level: each
-                // child's total (Sec. 4.4.1); the least, first in generation
-                // order, is the one survivor
-                const uint32_t nu = (uint32_t)n2 - (DIR ? (uint32_t)__popc((uint32_t)img) : popc64(img));
-                const uint32_t mo = (uint32_t)g2.m - ein;   // g2 edges not inside Img
-                uint32_t bt = INVALID, bj = DEL8;
-                uint64_t fr = free;
-                for (uint32_t j = 0; fr; ++j, fr &= fr - 1ull) {
-                    const uint32_t u = (uint32_t)__builtin_ctzll(fr);
-                    const uint4 tu = s_tab[u];
-                    const uint32_t t = score(u) + mul_cost<SMALL>(nu - 1u, vins) +
-                                       mul_cost<SMALL>(mo - popc64(img & u64(tu.x, tu.y)), eins);
-                    if (t < bt) {
-                        bt = t;
-                        bj = j;
-                    }
-                }
-                if (live) {
-                    const uint32_t t = cdel + mul_cost<SMALL>(nu, vins) + mul_cost<SMALL>(mo, eins);
-                    if (t < bt) {
-                        bt = t;
-                        bj = DEL8;
-                    }
-                }
-                const uint32_t wmin = wave_umin(bt);
-                const int bl = (int)__builtin_ctzll(__ballot(bt == wmin));
-                if (lane == bl) s_sel[0] = ((uint32_t)lane << 8) | bj;
-                nb_new = 1;
-            } else {
-            uint32_t T = INVALID;
-            int tT = TOP;   // no trimming: every child with a byte below 127 survives
-            if (trim) {
-                uint32_t base = m0;
-                int sh = 0;
-                int t = search(0x7f7f7f00u | to_byte(cdel, base, sh), hint);
-                if (t < TOP) {
-                    hint = t;
-                } else {
-                    // the K-th child lies 126 or more above the least parent:
-                    // bucket passes from 2^24 down to exact offsets
-                    base = m0 + 126u;
-                    sh = 24;
-                    for (;;) {
-                        pass(base, sh, false);
-                        t = search(0x7f7f7f00u | to_byte(cdel, base, sh), 63);
-                        if (sh == 0 && t < TOP) break;
-                        if (t < TOP) {
-                            base += (uint32_t)(t - 1) << sh;
-                            sh = sh > 7 ? sh - 7 : 0;
-                        } else {
-                            base += 126u << sh;   // only while sh = 0: coarse buckets cover every PED
-                        }
-                    }
-                    hint = TOP - 1;
-                }
-                T = base + (uint32_t)t - 1u;
-                tT = t;
-            }
-
-            // ---------------- survivors in generation order
-            // bit j of ltm / lem: child j below / at most T (built high j first)
-            uint32_t ltl = 0u, lel = 0u, lth = 0u, leh = 0u;
-            const uint32_t uT = (uint32_t)tT;
-#pragma unroll
-            for (int g = 15; g >= 8; --g) {
-                if (g < ngroups) {
-#pragma unroll
-                    for (int k = 3; k >= 0; --k) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(pk[g], (uint32_t)k * 8u, 8u);
-                        shift_in2(lth, x < uT, leh, x <= uT);
-                    }
-                }
-            }
-#pragma unroll
-            for (int g = 7; g >= 0; --g) {
-                if (g < ngroups) {
-#pragma unroll
-                    for (int k = 3; k >= 0; --k) {
-                        const uint32_t x = __builtin_amdgcn_ubfe(pk[g], (uint32_t)k * 8u, 8u);
-                        shift_in2(ltl, x < uT, lel, x <= uT);
-                    }
-                }
-            }
-            // the groups above the highest one were never shifted in: align
-            const int gap = 4 * (ngroups > 8 ? 16 - ngroups : 8 - ngroups);
-            uint64_t ltm, lem;
-            if (ngroups > 8) {
-                ltm = u64(ltl, lth);
-                lem = u64(lel, leh);
-            } else {
-                ltm = (uint64_t)ltl;
-                lem = (uint64_t)lel;
-            }
-            (void)gap;
-            if (!trim) {
-                // without trimming T is not set: every valid child survives
-                const uint64_t all = nfree >= 64 ? ~0ull : ((1ull << nfree) - 1ull);
-                ltm = live ? all : 0ull;
-                lem = ltm;
-            }
-            const uint64_t eqm = trim ? (lem & ~ltm) : 0ull;
-            const bool ltd = trim ? cdel < T : live;
-            const bool eqd = trim && cdel == T;
-            const int lt_l = (int)popc64(ltm) + (ltd ? 1 : 0);
-            const int eq_l = (int)popc64(eqm) + (eqd ? 1 : 0);
-            const int quota = trim ? K - (int)wave_sum((uint32_t)lt_l) : 0;
-            int r = min(max(quota - wave_excl_scan(eq_l), 0), eq_l);
-            uint64_t keepm = ltm;
-            bool keepd = ltd;
-            const int ne = (int)popc64(eqm);
-            if (r >= ne) {
-                keepm |= eqm;
-                r -= ne;
-            } else {
-                for (uint64_t e = eqm; r > 0; e &= e - 1ull, --r) keepm |= e & (0ull - e);
-            }
-            if (r > 0 && eqd) keepd = true;
-            int pos = wave_excl_scan((int)popc64(keepm) + (keepd ? 1 : 0));
-            for (uint64_t mk = keepm; mk; mk &= mk - 1ull)
-                s_sel[pos++] = ((uint32_t)lane << 8) | (uint32_t)__builtin_ctzll(mk);
-            if (keepd) s_sel[pos] = ((uint32_t)lane << 8) | DEL8;
-            nb_new = min(V, K);
-            }
-            __syncthreads();
-
-            // ---------------- update: child = parent + (v_i -> u)
-            const bool live2 = lane < nb_new;
-            const uint32_t sel = live2 ? s_sel[lane] : 0u;
-            const int p = (int)(sel >> 8);
-            const uint32_t jc = sel & 0xffu;
-            const bool sub = jc != DEL8;
-            const uint32_t u = sub ? __builtin_amdgcn_ubfe(s_uv[(jc >> 2) & 15u][p], (jc & 3u) * 8u, 8u) : DEL8;
-            const uint32_t us = sub ? min(u, 64u) : 0u;
-            const uint32_t basel_p = (uint32_t)__shfl((int)basel, p);
-            const uint64_t phi_p = shfl64(phi, p);
-            const uint64_t ai_p = shfl64(ai, p);
-            const uint64_t img_p = shfl64(img, p);
-            const uint32_t ein_p = (uint32_t)__shfl((int)ein, p);
-            const uint4 tu = s_tab[us];
-            const uint64_t R = u64(tu.x, tu.y);
-            uint64_t phbp[PLA], rp[PLA];
-#pragma unroll
-            for (int b = 0; b < PLA; ++b) {
-                phbp[b] = PL > 0 ? shfl64(phib[b], p) : 0ull;
-                const uint2 pl = PL > 0 ? s_pl[b][us] : make_uint2(0u, 0u);
-                rp[b] = u64(pl.x, pl.y);
-            }
-            const int wl = i >> 2;
-#pragma unroll
-            for (int w = 0; w < 16; ++w)
-                if (w <= wl) ph[w] = (uint32_t)__shfl((int)ph[w], p);
-            if (live2) {
-                if (sub) {
-                    uint32_t d = msub_cost<SMALL>(popc64(phi_p & R), nedel,
-                                                  mad_cost<SMALL>(popc64(ai_p & R), eins, basel_p + tu.z));
-                    if (PL > 0) {
-                        uint64_t diff = 0ull;
-#pragma unroll
-                        for (int b = 0; b < PLA; ++b) diff |= phbp[b] ^ rp[b];
-                        d += mul_cost<SMALL>(popc64(phi_p & R & diff), esub);
-                    }
-                    ped = d;
-                    img = img_p | (1ull << (us & 63u)) | (DIR ? (1ull << ((us + 32u) & 63u)) : 0ull);
-                    ein = ein_p + popc64(img_p & R);
-                } else {
-                    ped = basel_p + vdel;
-                    img = img_p;
-                    ein = ein_p;
-                }
-            }
-            // byte i of the mapping
-            const uint32_t sh8 = (uint32_t)(i & 3) * 8u;
-#pragma unroll
-            for (int w = 0; w < 16; ++w)
-                if (w == wl) ph[w] = (ph[w] & ~(0xffu << sh8)) | (u << sh8);
-            nb = nb_new;
-        }
-
-        // ---------------- completion and best leaf
-        const uint32_t nimg = DIR ? (uint32_t)__popc((uint32_t)img) : popc64(img);
-        const uint32_t total = lane < nb ? ped + mul_cost<SMALL>((uint32_t)n2 - nimg, vins) +
-                                               mul_cost<SMALL>((uint32_t)g2.m - ein, eins)
-                                         : INVALID;
-        const uint32_t best_total = wave_umin(total);
-        const int best = (int)__builtin_ctzll(__ballot(total == best_total));
-        if (lane == 0) {
-            a.out.dist[wi.out] = (int)best_total;
-            if (a.out.cand) a.out.cand[wi.out] = ce;
-        }
-        uint32_t word = 0u;
-#pragma unroll
-        for (int w = 0; w < 16; ++w) {
-            const uint32_t bw = (uint32_t)__builtin_amdgcn_readlane((int)ph[w], best);
-            word = (lane >> 2) == w ? bw : word;
-        }
-        if (lane < n1) {
-            const uint32_t x = __builtin_amdgcn_ubfe(word, (uint32_t)(lane & 3) * 8u, 8u);
-            a.out.map[wi.map_off + lane] = (x == DEL8) ? -1 : (int)x;
-        }
-        __syncthreads();
-    }
-}
-
-template <int PL, bool SMALL, bool COMPLETE, bool DIR>
-const void *wave2_ptr() {
-    return reinterpret_cast<const void *>(&kb_wave2_kernel<PL, SMALL, COMPLETE, DIR>);
-}
-
-// the complete-then-minimum last level is a kernel of its own, so that the
-// default search keeps its register budget; so are directed pairs
-template <bool COMPLETE, bool DIR>
-const void *select_wave2_c(int PL, bool small) {
-    if (PL == 0) return small ? wave2_ptr<0, true, COMPLETE, DIR>() : wave2_ptr<0, false, COMPLETE, DIR>();
-    if (PL == 2) return small ? wave2_ptr<2, true, COMPLETE, DIR>() : wave2_ptr<2, false, COMPLETE, DIR>();
-    if (PL == 4) return small ? wave2_ptr<4, true, COMPLETE, DIR>() : wave2_ptr<4, false, COMPLETE, DIR>();
-    return nullptr;
-}
-
-const void *select_wave2(int PL, bool small, bool complete, bool dir = false) {
-    if (dir) return complete ? select_wave2_c<true, true>(PL, small) : select_wave2_c<false, true>(PL, small);
-    return complete ? select_wave2_c<true, false>(PL, small) : select_wave2_c<false, false>(PL, small);
-}
 
 bool small_costs2(const Costs &c) {
     const int32_t lim = 1 << 22;
     return c.vsub < lim && c.vdel < lim && c.vins < lim && c.esub < lim && c.edel < lim && c.eins < lim;
 }
 
+const void *select_wave2(int K, int PL, bool small, bool complete, bool dir) {
+    if (K <= kWaveMaxK) return w2::select_wave2_s<1>(PL, small, complete, dir);
+    if (K <= kWave2MaxK) return select_wave2_two_slots(PL, small, complete, dir);
+    return nullptr;
+}
+
 }  // namespace
 
-hipError_t wave2_max_resident_dir(int PL, int last_complete, int directed, int *blocks_per_cu) {
-    const void *k = select_wave2(PL, true, last_complete != 0, directed != 0);
-    const void *k2 = select_wave2(PL, false, last_complete != 0, directed != 0);
+hipError_t wave2_max_resident_dir(int PL, int K, int last_complete, int directed, int *blocks_per_cu) {
+    const void *k = select_wave2(K, PL, true, last_complete != 0, directed != 0);
+    const void *k2 = select_wave2(K, PL, false, last_complete != 0, directed != 0);
     if (!k || !k2) return hipErrorInvalidValue;
     int x = 0, y = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&x, k, 64, 0);
@@ -547,16 +31,16 @@ hipError_t wave2_max_resident_dir(int PL, int last_complete, int directed, int *
     return e;
 }
 
-hipError_t wave2_max_resident(int PL, int last_complete, int *blocks_per_cu) {
-    return wave2_max_resident_dir(PL, last_complete, 0, blocks_per_cu);
+hipError_t wave2_max_resident(int PL, int K, int last_complete, int *blocks_per_cu) {
+    return wave2_max_resident_dir(PL, K, last_complete, 0, blocks_per_cu);
 }
 
 hipError_t launch_wave2_dir(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
                             Costs c, int K, int last_complete, int directed, Outputs out, int grid,
                             hipStream_t stream) {
-    const void *k = select_wave2(PL, small_costs2(c), last_complete != 0, directed != 0);
-    if (!k || grid <= 0 || K > kWaveMaxK) return hipErrorInvalidValue;
-    Wave2Args a;
+    const void *k = select_wave2(K, PL, small_costs2(c), last_complete != 0, directed != 0);
+    if (!k || grid <= 0 || K < 1) return hipErrorInvalidValue;
+    w2::Wave2Args a;
     a.src = src;
     a.dst = dst;
     a.work = work;

@@ -109,10 +109,10 @@ WAVE64_COSTS = [UNIT, (40, 90, 70, 25, 60, 45), WIDE_RANGE, BIG_VERTEX]
 
 
 @pytest.mark.parametrize("costs", WAVE64_COSTS)
-@pytest.mark.parametrize("K", [1, 16, 64])
+@pytest.mark.parametrize("K", [1, 16, 64, 128])
 def test_wave64_range(ged, costs, K):
-    """Pairs of 33..64 vertices: the two-word wavefront kernel alone in the plan, then
-    the workgroup kernel on the same pairs."""
+    """Pairs of 33..64 vertices: the two-word wavefront kernel alone in the plan (two
+    beam slots per lane at K = 128), then the workgroup kernel on the same pairs."""
     gs = []
     for k, (n, p) in enumerate([(64, 0.1), (64, 0.0), (63, 0.3), (33, 0.2), (48, 0.05), (64, 1.0),
                                 (40, 0.15), (57, 0.08), (20, 0.3), (35, 0.5), (1, 0.0)]):

@@ -74,7 +74,7 @@ def check(ged, graphs, pairs, costs, K, last_level=0, perpair=False, expect_word
 
 @pytest.mark.parametrize("schedule", [0, 1])
 @pytest.mark.parametrize("costs", [UNIT, PAPER, NONMETRIC, ASYM])
-@pytest.mark.parametrize("K", [1, 8, 64])
+@pytest.mark.parametrize("K", [1, 8, 64, 100])
 def test_small_directed_pairs(ged, costs, K, schedule):
     """n 0..32 (two-word rows: out and in), unlabelled arcs, ragged orders incl. empty graphs;
     the wavefront kernel by default, the workgroup kernel under schedule 1."""
@@ -97,12 +97,15 @@ def test_labelled_arcs_two_and_four_planes(ged, last_level, schedule):
 
 def test_wavefront_and_workgroup_bins_together(ged):
     """One plan over directed pairs of up to 32 vertices (wavefront kernel) and larger
-    ones (workgroup kernel), and K = 65 (past the wavefront kernel's limit)."""
+    ones (workgroup kernel), at K = 24, at K = 65 and 128 (two beam slots per lane) and
+    at K = 129 (past the wavefront kernel's limit)."""
     gs = GraphSet.from_graphs([synth.directed_graph(715, k, 3, 32, 0.1, 0.3, 3, 3) for k in range(10)]
                               + [synth.directed_graph(716, k, 33, 60, 0.05, 0.1, 3, 3) for k in range(4)])
     pairs = [[a, b] for a in range(14) for b in range(14) if a != b][::3]
     check(ged, gs, pairs, PAPER, 24, kinds={"kb_wave2_kernel", "kb_block_kernel"})
-    check(ged, gs, pairs[:30], PAPER, 65, kinds={"kb_block_kernel"})
+    check(ged, gs, pairs[:30], PAPER, 65, kinds={"kb_wave2_kernel", "kb_block_kernel"})
+    check(ged, gs, pairs[:30], PAPER, 128, kinds={"kb_wave2_kernel", "kb_block_kernel"})
+    check(ged, gs, pairs[:30], PAPER, 129, kinds={"kb_block_kernel"})
 
 
 @pytest.mark.parametrize("n_lo,n_hi,words,npairs", [(33, 64, 4, 40), (65, 128, 8, 30), (129, 200, 16, 12)])

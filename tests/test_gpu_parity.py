@@ -61,7 +61,7 @@ def tiny_set(seed, count, n_max, p, nvl, nel):
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("costs", [UNIT, PAPER, ODD, HIGH])
-@pytest.mark.parametrize("K", [1, 2, 3, 7, 63, 64, 65, 1024])
+@pytest.mark.parametrize("K", [1, 2, 3, 7, 63, 64, 65, 128, 1024])
 def test_tiny_random_pairs(ged, costs, K, schedule):
     graphs = tiny_set(100 + K, 60, 9, 0.45, 3, 3)
     pairs = [[2 * k, 2 * k + 1] for k in range(30)] + [[k, k] for k in range(0, 60, 7)]
@@ -146,13 +146,8 @@ WAVE64_COSTS = [UNIT, ODD, (40, 90, 70, 25, 60, 45), (1000, 3000, 2500, 700, 130
                 (4_194_304, 5_000_011, 4_500_007, 30_011, 20_021, 35_003)]
 
 
-@pytest.mark.parametrize("costs", WAVE64_COSTS)
-@pytest.mark.parametrize("K", [1, 3, 16, 63, 64])
-def test_wave64_range(ged, costs, K):
-    """Pairs of 33..64 vertices (the two-word wavefront kernel): both word boundaries,
-    empty and complete graphs, labelled edges, cost scales that put the K-th smallest
-    child inside the first byte window, past it (bucket passes) and past 24-bit
-    products.  The workgroup kernel must agree on the candidate counts as well."""
+def wave64_set():
+    """1..64 vertices: both word boundaries, empty and complete graphs, labelled edges."""
     gs = []
     for k, (n, p) in enumerate([(64, 0.1), (64, 0.0), (63, 0.3), (33, 0.2), (48, 0.05), (64, 1.0),
                                 (40, 0.15), (57, 0.08), (20, 0.3), (35, 0.5), (1, 0.0)]):
@@ -160,9 +155,19 @@ def test_wave64_range(ged, costs, K):
         if k % 2 == 0:
             g.elabel = (np.arange(g.m) % 5).astype(np.int32)
         gs.append(g)
-    graphs = GraphSet.from_graphs(gs)
+    return GraphSet.from_graphs(gs)
+
+
+@pytest.mark.parametrize("costs", WAVE64_COSTS)
+@pytest.mark.parametrize("K", [1, 3, 16, 63, 64])
+def test_wave64_range(ged, costs, K):
+    """Pairs of 33..64 vertices (the two-word wavefront kernel): both word boundaries,
+    empty and complete graphs, labelled edges, cost scales that put the K-th smallest
+    child inside the first byte window, past it (bucket passes) and past 24-bit
+    products.  The workgroup kernel must agree on the candidate counts as well."""
+    graphs = wave64_set()
     n = graphs.n
-    pairs = [[a, b] for a in range(len(gs)) for b in range(len(gs)) if max(n[a], n[b]) > 32]
+    pairs = [[a, b] for a in range(len(n)) for b in range(len(n)) if max(n[a], n[b]) > 32]
     db = ged.Database(graphs)
     plan = ged.Plan(db, pairs, K)
     kinds = {name for name, *_ in plan.bins()}
@@ -176,10 +181,33 @@ def test_wave64_range(ged, costs, K):
     np.testing.assert_array_equal(res.cand, res2.cand)
 
 
-@pytest.mark.parametrize("K", [8, 64])
+@pytest.mark.parametrize("costs", WAVE64_COSTS)
+@pytest.mark.parametrize("K", [65, 100, 128])
+def test_wave64_two_slots(ged, costs, K):
+    """Beams of 65..128 slots (two slots per lane of the two-word wavefront kernel) on
+    every pair of 1..64 vertices, the ones of up to 32 included: the same cost scales
+    (byte window, bucket passes, 32-bit products); the workgroup kernel agrees on
+    distances, mappings and candidate counts."""
+    graphs = wave64_set()
+    nn = len(graphs.n)
+    pairs = [[a, b] for a in range(nn) for b in range(nn)]
+    db = ged.Database(graphs)
+    plan = ged.Plan(db, pairs, K)
+    kinds = {name for name, *_ in plan.bins()}
+    plan.close()
+    assert kinds == {"kb_wave2_kernel"}, kinds
+    res = gpu_vs_oracle(ged, graphs, pairs, costs, K, db=db, schedule=0)
+    res2 = ged.kbest(db, pairs, costs, K, with_cand=True, schedule=1)
+    db.close()
+    np.testing.assert_array_equal(res.dist, res2.dist)
+    np.testing.assert_array_equal(res.maps, res2.maps)
+    np.testing.assert_array_equal(res.cand, res2.cand)
+
+
+@pytest.mark.parametrize("K", [8, 64, 128])
 def test_query_molecule_wave64(ged, K):
-    """Molecule-like pairs (n 10..70) at K <= 64: the n <= 32, n <= 64 wavefront bins and
-    the workgroup bin for n > 64 in one plan."""
+    """Molecule-like pairs (n 10..70): the wavefront bins (n <= 32 and n <= 64 at K <= 64,
+    the two-slot one for n <= 64 at K = 128) and the workgroup bin for n > 64 in one plan."""
     w = synth.query_molecule_10_70(200)
     gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, K)
 

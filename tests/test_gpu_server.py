@@ -165,3 +165,26 @@ def test_batch_submit_and_collect(ged, setting):
             seen.add(q)
     assert srv.collect(timeout_us=1000) is None
     srv.close()
+
+
+def test_beam_of_128(ged):
+    """K = 128: queries of up to 64 vertices take the two-slot wavefront kernel (the
+    two-word class; there is no one-word class above 64 slots), larger ones the
+    workgroup classes; every result equals the oracle's."""
+    db_graphs = [synth.er_graph(51, i, 5, 90, 0.05, 0.25, 4) for i in range(50)]
+    queries = [synth.er_graph(52, q, 5, 80, 0.05, 0.25, 4) for q in range(70)]
+    targets = np.random.default_rng(53).integers(0, len(db_graphs), len(queries))
+    gs = GraphSet.from_graphs(db_graphs + queries)
+    pairs = np.stack([np.arange(len(db_graphs), len(db_graphs) + len(queries)), targets], 1).astype(np.int64)
+    print(f"  case: server at K=128, {len(queries)} queries of 5..80 vertices", flush=True)
+    d, m, off = oracle.kbest_pairs(gs, pairs, COSTS, 128)
+    db = ged.Database(GraphSet.from_graphs(db_graphs))
+    srv = ged.Server(db, 128, COSTS, max_batch=16, streams=2)
+    tickets = [srv.submit(queries[q], int(targets[q])) for q in range(len(queries))]
+    for q, t in enumerate(tickets):
+        dd, mm = srv.wait(t, timeout_us=120_000_000)
+        assert (dd, mm.tolist()) == (int(d[q]), m[off[q]:off[q] + queries[q].n].tolist()), q
+    st = srv.stats()
+    assert st["completed"] == len(queries)
+    srv.close()
+    db.close()
