@@ -184,9 +184,9 @@ ged_status ged_plan_create(ged_db *db, const ged_pair *h_pairs, int64_t npairs, 
                            ged_plan **out);
 
 /* Kernel schedules.  GED_SCHED_AUTO lets the library choose per size bin:
- * a wavefront per pair (beam in registers) where n1, n2 <= 64 and K <= 128
- * (one kernel for n <= 32 at K <= 64, one for the rest, with two beam slots
- * per lane above K = 64), else a workgroup per pair.  GED_SCHED_BLOCK forces the
+ * a wavefront per pair (beam in registers) where n2 <= 64, n1 <= 128 and
+ * K <= 128 (one kernel for n <= 32 at K <= 64, one for the rest, with two
+ * beam slots per lane above K = 64), else a workgroup per pair.  GED_SCHED_BLOCK forces the
  * workgroup-per-pair kernel for every pair.  Every schedule computes the
  * same result bit for bit. */
 #define GED_SCHED_AUTO 0
@@ -275,7 +275,7 @@ ged_status ged_plan_kernel_launches(const ged_plan *plan, int64_t *launches);
  * per pair) or GED_KERNEL_BIPARTITE (bipartite method; *words is then
  * its columns per lane, ceil((n1 + n2) / 64)), *npairs the pairs in the bin, *grid the persistent launch's
  * workgroups, *words the target-row words the instantiation handles (1
- * or 2 for the wavefront kernels: n <= 32 or n <= 64).
+ * or 2 for the wavefront kernels: targets of up to 32 or 64 vertices).
  * Any output pointer may be NULL. */
 /* HIP graphs.  ged_plan_capture records one ged_plan_run with these costs
  * and outputs into a HIP graph owned by the plan (replacing any previous

@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(PKG, "_build")
 LIB_PATH = os.path.join(PKG, "libged.so")
 
 SOURCES = ["ged_api.cpp", "ged_plan.cpp", "ged_server.cpp", "ged_wide.cpp", "kb_block.hip", "kb_wave.hip",
-           "kb_wave2.hip", "kb_wave2_k128.hip", "kb_wide.hip", "kb_bip.hip", "kb_path.hip", "ged_path.cpp", "kb_aux.hip", "ged_noalloc.hip"]
+           "kb_wave2.hip", "kb_wave2_k128.hip", "kb_wave2_src128.hip", "kb_wide.hip", "kb_bip.hip", "kb_path.hip", "ged_path.cpp", "kb_aux.hip", "ged_noalloc.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -77,47 +77,55 @@ hipError_t launch_wide(const DbView &src, const DbView &dst, const GraphRec &g1,
                        int cus, hipStream_t stream);
 
 // Wavefront family that fits a pair: 1 (n1, n2 <= 32 and K <= 64), 2 (else
-// n1, n2 <= 64 and K <= 128), 0 none (K > 128 or a larger graph).
+// n1, n2 <= 64 and K <= 128), 3 (n2 <= 64, 64 < n1 <= 128 and K <= 128: the
+// two-word kernel with a 128-vertex mapping), 0 none (K > 128 or a larger
+// graph).
+constexpr int kWaveFamilies = 3;
+constexpr int kWave3MaxN1 = 128;
 __host__ __device__ inline int wave_words_for(int n1, int n2, int K) {
-    if (K > kWave2MaxK) return 0;
+    if (K > kWave2MaxK || n2 > kWave2MaxN) return 0;
+    if (n1 > kWave2MaxN) return n1 <= kWave3MaxN1 ? 3 : 0;
     const int n = n1 > n2 ? n1 : n2;
-    if (n > kWave2MaxN) return 0;
     return (n <= kWaveMaxN && K <= kWaveMaxK) ? 1 : 2;
 }
 // Directed pairs of up to 32 vertices on the two-word wavefront kernel
 // (kb_wave2.hip, DIR instantiations): a row word of out-arcs and one of
 // in-arcs per vertex.
-hipError_t wave2_max_resident_dir(int PL, int K, int last_complete, int directed, int *blocks_per_cu);
-hipError_t launch_wave2_dir(int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork, int *queue,
-                            Costs c, int K, int last_complete, int directed, Outputs out, int grid,
+// family: 2 (sources of up to 64 vertices; directed: 32) or 3 (undirected
+// sources of up to 128).
+hipError_t wave2_max_resident_dir(int family, int PL, int K, int last_complete, int directed, int *blocks_per_cu);
+hipError_t launch_wave2_dir(int family, int PL, const DbView &src, const DbView &dst, const WorkItem *work, int nwork,
+                            int *queue, Costs c, int K, int last_complete, int directed, Outputs out, int grid,
                             hipStream_t stream);
 // Wavefront family of a directed pair: 2 when both orders are <= 32 and K <= 128.
 __host__ __device__ inline int wave_words_for_directed(int n1, int n2, int K) {
     return (K <= kWave2MaxK && n1 <= kWaveMaxN && n2 <= kWaveMaxN) ? 2 : 0;
 }
 
-inline hipError_t wave_family_max_resident(int words, int PL, int K, int last_complete, int *blocks_per_cu,
+inline hipError_t wave_family_max_resident(int family, int PL, int K, int last_complete, int *blocks_per_cu,
                                            int directed = 0) {
-    if (directed) return wave2_max_resident_dir(PL, K, last_complete, 1, blocks_per_cu);
-    return words == 1 ? wave_max_resident(PL, last_complete, blocks_per_cu)
-                      : wave2_max_resident(PL, K, last_complete, blocks_per_cu);
+    if (directed) return wave2_max_resident_dir(2, PL, K, last_complete, 1, blocks_per_cu);
+    return family == 1 ? wave_max_resident(PL, last_complete, blocks_per_cu)
+                       : wave2_max_resident_dir(family, PL, K, last_complete, 0, blocks_per_cu);
 }
-inline hipError_t launch_wave_family(int words, int PL, const DbView &src, const DbView &dst, const WorkItem *work,
+inline hipError_t launch_wave_family(int family, int PL, const DbView &src, const DbView &dst, const WorkItem *work,
                                      int nwork, int *queue, Costs c, int K, int last_complete, Outputs out, int grid,
                                      hipStream_t stream, int directed = 0) {
     if (directed)
-        return launch_wave2_dir(PL, src, dst, work, nwork, queue, c, K, last_complete, 1, out, grid, stream);
-    return words == 1 ? launch_wave(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream)
-                      : launch_wave2(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream);
+        return launch_wave2_dir(2, PL, src, dst, work, nwork, queue, c, K, last_complete, 1, out, grid, stream);
+    return family == 1 ? launch_wave(PL, src, dst, work, nwork, queue, c, K, last_complete, out, grid, stream)
+                       : launch_wave2_dir(family, PL, src, dst, work, nwork, queue, c, K, last_complete, 0, out, grid,
+                                          stream);
 }
 
-// Size bins of the default schedule of the tree search: 0 / 1 = the
-// wavefront kernels (n <= 32 and K <= 64 / the rest of n <= 64 and K <= 128;
-// a directed pair of up to 32 vertices takes 1), 2 + log2(W) = the workgroup kernel whose rows have W
-// words (target words rounded up to a power of two, doubled for a directed
-// database's out and in rows).  The same function classifies pairs on the
-// host and on the device.
-constexpr int kPairBins = 7;
+// Size bins of the default schedule of the tree search: 0 / 1 / 2 = the
+// wavefront families 1 / 2 / 3 (n <= 32 and K <= 64 / the rest of n <= 64
+// and K <= 128 / sources of 65..128 vertices against targets of up to 64;
+// a directed pair of up to 32 vertices takes 1), 3 + log2(W) = the workgroup
+// kernel whose rows have W words (target words rounded up to a power of two,
+// doubled for a directed database's out and in rows).  The same function
+// classifies pairs on the host and on the device.
+constexpr int kPairBins = kWaveFamilies + 5;
 __host__ __device__ inline int pair_bin(int n1, int n2, int K, int directed) {
     const int ww = directed ? wave_words_for_directed(n1, n2, K) : wave_words_for(n1, n2, K);
     if (ww > 0) return ww - 1;
@@ -127,10 +135,10 @@ __host__ __device__ inline int pair_bin(int n1, int n2, int K, int directed) {
     if (directed) W <<= 1;
     int lg = 0;
     while ((1 << lg) < W) ++lg;
-    return 2 + lg;
+    return kWaveFamilies + lg;
 }
-// Row words of workgroup-kernel bin b (2..6).
-__host__ __device__ inline int bin_words(int b) { return 1 << (b - 2); }
+// Row words of workgroup-kernel bin b (kWaveFamilies .. kPairBins - 1).
+__host__ __device__ inline int bin_words(int b) { return 1 << (b - kWaveFamilies); }
 
 // Start of each bin's work list in one array of work items.
 struct BinBases {

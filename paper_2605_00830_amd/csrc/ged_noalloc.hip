@@ -128,7 +128,7 @@ extern "C" ged_status ged_kbest_noalloc(ged_db *db, const ged_pair *h_pairs, int
     size_t stride[gedk::kPairBins] = {0}, o_ws[gedk::kPairBins] = {0};
     int grid[gedk::kPairBins] = {0};
     size_t reserve = 0;   // one workgroup's workspace for every workgroup bin
-    for (int b = 2; b < gedk::kPairBins; ++b) {
+    for (int b = gedk::kWaveFamilies; b < gedk::kPairBins; ++b) {
         if (count[b] == 0) continue;
         const int threads = count[b] < 2 * (int64_t)cus ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
         shape[b] = gedk::BlockShape{gedk::bin_words(b), PL, gedk::block_slot_stride(K, threads), nmax1[b], nmax2[b],
@@ -142,12 +142,12 @@ extern "C" ged_status ged_kbest_noalloc(ged_db *db, const ged_pair *h_pairs, int
     for (int b = 0; b < gedk::kPairBins; ++b) {
         if (count[b] == 0) continue;
         int per_cu = 0;
-        hipError_t e = b < 2 ? gedk::wave_family_max_resident(b + 1, PL, K, 0, &per_cu, directed)
+        hipError_t e = b < gedk::kWaveFamilies ? gedk::wave_family_max_resident(b + 1, PL, K, 0, &per_cu, directed)
                              : gedk::block_max_resident(shape[b], &per_cu);
         if (e != hipSuccess || per_cu <= 0)
             return fail(GED_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
         int64_t g = std::min<int64_t>(count[b], (int64_t)per_cu * cus);
-        if (b >= 2) {
+        if (b >= gedk::kWaveFamilies) {
             // as many workgroups as the scratch holds, keeping one for each later bin
             // (the reservation guarantees room for one, rounded up to 256 bytes)
             reserve -= (stride[b] + 255) & ~(size_t)255;
@@ -178,7 +178,7 @@ extern "C" ged_status ged_kbest_noalloc(ged_db *db, const ged_pair *h_pairs, int
     for (int b = 0; b < gedk::kPairBins; ++b) {
         if (count[b] == 0) continue;
         const WorkItem *work = lists + lb.at[b];
-        if (b < 2) {
+        if (b < gedk::kWaveFamilies) {
             GED_HIP(gedk::launch_wave_family(b + 1, PL, view, view, work, (int)count[b], queue + b, c, K, 0, out,
                                              grid[b], s, directed));
         } else {

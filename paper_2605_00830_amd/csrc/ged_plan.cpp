@@ -36,7 +36,7 @@ struct Bin {
     int bip_nwav = 1;            // its waves per pair (1 or 4)
     int bip_max_per_cu[2] = {0, 0};   // occupancy: 1 and 4 waves per workgroup
     bool wave_ok = false;        // every pair fits the wavefront kernel
-    int wave_words = 0;          // its family: 1 (n <= 32), 2 (n <= 64)
+    int wave_words = 0;          // its family: 1 (n <= 32), 2 (n <= 64), 3 (n1 <= 128, n2 <= 64)
     bool wave = false;           // current choice: wavefront kernel, else workgroup kernel
     gedk::BlockShape shape{};    // workgroup-kernel instantiation and workspace shape
     std::vector<WorkItem> h_sorted;   // longest first
@@ -653,7 +653,7 @@ ged_status ged_plan_bin_info(const ged_plan *plan, int32_t index, int32_t *kerne
     if (kernel) *kernel = b.bip ? GED_KERNEL_BIPARTITE : (b.wave ? GED_KERNEL_WAVE : GED_KERNEL_BLOCK);
     if (npairs) *npairs = (int64_t)b.h_work.size();
     if (grid) *grid = b.grid;
-    if (words) *words = b.bip ? b.bip_cpl : (b.wave ? b.wave_words : b.shape.W);
+    if (words) *words = b.bip ? b.bip_cpl : (b.wave ? std::min(b.wave_words, 2) : b.shape.W);
     return ok();
 }
 

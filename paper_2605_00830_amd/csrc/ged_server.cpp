@@ -87,8 +87,8 @@ constexpr int64_t kHoldNs = 1'000'000;
 constexpr int kBlockClassPerCu[4] = {1 << 20, 1 << 20, 2, 1};
 constexpr int kLargeStreams = 2;
 
-constexpr int kWaveBins = 2;        // wavefront bins: n <= 32, n <= 64
-constexpr int kMaxBins = 7;         // wavefront bins + workgroup bins W = 1, 2, 4, 8, 16
+constexpr int kWaveBins = gedk::kWaveFamilies;   // wavefront bins: the three families
+constexpr int kMaxBins = kWaveBins + 5;            // + workgroup bins W = 1, 2, 4, 8, 16
 
 // Device and pinned-host buffers of one stream.  A batch's inputs are
 // staged in one pinned buffer and reach the device in one copy: the queue
@@ -129,7 +129,7 @@ struct ged_server {
     gedk::Costs c{};
     int PL = 0;
     int cus = 0;
-    int wave_per_cu[kWaveBins] = {0, 0};   // n <= 32, n <= 64 kernels
+    int wave_per_cu[kWaveBins] = {0, 0, 0};   // the wavefront families' kernels
     int block_per_cu[2][5] = {};   // [256 | 512 threads][W = 1, 2, 4, 8, 16]
     bool bip = false;              // bipartite method
     bool directed = false;         // directed database: rows [out | in], W doubled
@@ -166,8 +166,11 @@ constexpr int kMediumMaxN = 128;
 
 int server_class(const ged_server *s, int n1, int n2) {
     if (s->bip) return gedk::bip_cols_per_lane(n1 + n2) - 1;
-    // directed pairs of up to 32 vertices take the two-word kernel (class 1)
+    // directed pairs of up to 32 vertices take the two-word kernel (class 1);
+    // sources of 65..128 vertices against targets of up to 64 are medium
+    // queries, searched on the wavefront kernel's third family
     const int ww = s->directed ? gedk::wave_words_for_directed(n1, n2, s->cfg.K) : gedk::wave_words_for(n1, n2, s->cfg.K);
+    if (ww == 3) return 2;
     if (ww > 0) return ww - 1;
     if (n1 <= kMediumMaxN && n2 <= kMediumMaxN) return 2;
     return 3;
@@ -317,7 +320,10 @@ hipError_t launch_batch(ged_server *s, Slab &b) {
                    (int64_t)h_recs[y.src].n * (dbg[(size_t)y.dst].n + 1);
         });
         if (bin < kWaveBins) {
-            grid[bin] = std::min(cnt, s->wave_per_cu[bin] * s->cus);
+            // in a workgroup class, as many waves per CU as its workgroups would hold
+            const int per_cu = b.cls < kFirstBlockClass ? s->wave_per_cu[bin]
+                                                        : std::min(s->wave_per_cu[bin], 4 * kBlockClassPerCu[b.cls]);
+            grid[bin] = std::min(cnt, per_cu * s->cus);
         } else {
             // 512-thread workgroups when the bin cannot put two workgroups on
             // every CU: two waves per SIMD on each pair instead of one

@@ -1,16 +1,19 @@
-// kb_wave2.h -- wavefront-per-pair K-Best search for pairs of up to 64
+// kb_wave2.h -- wavefront-per-pair K-Best search for targets of up to 64
 // vertices on gfx950 (the kernel template; kb_wave2.hip instantiates one
-// beam slot per lane, kb_wave2_k128.hip two).
+// beam slot per lane, kb_wave2_k128.hip two, kb_wave2_src128.hip sources of
+// up to 128 vertices).
 //
 // The same scheme as kb_wave.hip (one 64-lane wavefront per pair, persistent
-// over a work queue whose first pair is the workgroup's index) for n1, n2 <=
-// 64: vertex sets are 64-bit (two words), the mapping phi is sixteen words of
-// bytes, and a slot has up to 64 substitution children, too many to keep as
-// 32-bit values.  A lane holds S beam slots (S = 1: K <= 64; S = 2: K <=
-// 128); slot s lives in lane s / S, register set s % S, so the slots of one
-// lane are neighbours in the beam's order and every scan over lanes gives
-// the slots' order directly.  Children are scored straight into bytes
-// relative to a base b:
+// over a work queue whose first pair is the workgroup's index) for n2 <= 64:
+// target vertex sets are 64-bit (two words), the mapping phi is M words of
+// bytes (M = 16: sources of up to 64 vertices, a lane holding g1's row of
+// its own index; M = 32: up to 128, row v_i read once per level), and a
+// slot has up to 64 substitution children, too many to keep as 32-bit
+// values.  A lane holds S beam slots (S = 1: K <= 64; S = 2: K <= 128);
+// slot s lives in lane s / S, register set s % S, so the slots of one lane
+// are neighbours in the beam's order and every scan over lanes gives the
+// slots' order directly.  Children are scored straight into bytes relative
+// to a base b:
 //   x = 0 if PED < b, else min((PED - b) >> sh, 126) + 1,
 // four to a register, and the threshold search, the keep masks and the tie
 // quota all work on those bytes:
@@ -122,15 +125,16 @@ __device__ __forceinline__ uint32_t nth_bit64(uint64_t m, uint32_t j) {
     return pos;
 }
 
-template <int S, int PL, bool SMALL, bool COMPLETE, bool DIR>
+template <int S, int M, int PL, bool SMALL, bool COMPLETE, bool DIR>
 __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
+    static_assert(M == 16 || (M == 32 && !DIR), "mapping of 64 source vertices, or 128 undirected");
     constexpr int PLA = PL > 0 ? PL : 1;
     constexpr int NS = 64 * S;              // beam slots
-    constexpr int PW = 20;                  // parent words (S = 2): phi 0..15, PED, e_in, Img lo, Img hi
+    constexpr int PW = M + 4;               // parent words (S = 2): phi 0..M-1, PED, e_in, Img lo, Img hi
     __shared__ uint32_t s_sel[NS];          // survivor: parent slot << 8 | j (0xff = deletion)
     __shared__ uint4 s_tab[65];             // per level: (N2(u) lo, hi, label cost, 0); [64] = sentinel
     // S = 1: [j / 4 * 64 + slot] = g2 vertices of children j, bytes;
-    // S = 2: [w * NS + slot] = parent word w
+    // S = 2: [w * NS + slot] = parent word w (mapping words, then PED, e_in, Img)
     __shared__ __align__(16) uint32_t s_aux[S == 1 ? 16 * 64 : PW * NS];
     __shared__ uint2 s_pl[PLA][65];         // label-plane rows of g2; [64] = 0
     __shared__ int s_item;
@@ -161,19 +165,20 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
         // directed (n <= 32, one row word): the in-arc rows and planes follow the out-arc ones
         const uint32_t *A1in = A1 + (size_t)(1 + a.src.planes) * n1 * w1;
         const uint32_t *A2in = A2 + (size_t)(1 + P) * n2 * w2;
-        const uint64_t r1 = lane < n1 ? u64(A1[(size_t)lane * w1], DIR ? A1in[(size_t)lane * w1]
+        // M = 16: lane v holds g1's row v and its label; M = 32 loads row v_i per level
+        const uint64_t r1 = M == 16 && lane < n1 ? u64(A1[(size_t)lane * w1], DIR ? A1in[(size_t)lane * w1]
                                                                      : (w1 > 1 ? A1[(size_t)lane * w1 + 1] : 0u))
                                       : 0ull;
         const uint64_t r2 = lane < n2 ? u64(A2[(size_t)lane * w2], DIR ? A2in[(size_t)lane * w2]
                                                                      : (w2 > 1 ? A2[(size_t)lane * w2 + 1] : 0u))
                                       : 0ull;
-        const int l1 = lane < n1 ? a.src.vlab[g1.vlab + lane] : 0;
+        const int l1 = M == 16 && lane < n1 ? a.src.vlab[g1.vlab + lane] : 0;
         const int l2 = lane < n2 ? a.dst.vlab[g2.vlab + lane] : 0;
         uint64_t p1[PLA];
 #pragma unroll
         for (int b = 0; b < PLA; ++b) {
             p1[b] = 0ull;
-            if (PL > 0 && b < P && lane < n1) {
+            if (PL > 0 && M == 16 && b < P && lane < n1) {
                 const uint32_t *B1 = A1 + (size_t)(1 + b) * n1 * w1 + (size_t)lane * w1;
                 const uint32_t *B1in = A1in + (size_t)(1 + b) * n1 * w1 + (size_t)lane * w1;
                 p1[b] = u64(B1[0], DIR ? B1in[0] : (w1 > 1 ? B1[1] : 0u));
@@ -197,53 +202,90 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
         // the lane's beam slots S * lane + h
         uint32_t ped[S], ein[S];
         uint64_t img[S];
-        uint32_t ph[S][16];
+        uint32_t ph[S][M];
 #pragma unroll
         for (int h = 0; h < S; ++h) {
             ped[h] = 0u;
             ein[h] = 0u;
             img[h] = 0ull;
 #pragma unroll
-            for (int w = 0; w < 16; ++w) ph[h][w] = 0u;
+            for (int w = 0; w < M; ++w) ph[h][w] = 0u;
         }
         int nb = 1, hint = 1;
         long long ce = 0;
 
         for (int i = 0; i < n1; ++i) {
-            const uint64_t below = DIR ? (((1ull << i) - 1ull) * 0x100000001ull)   // i < 32: both words
-                                       : (i >= 64 ? ~0ull : ((1ull << i) - 1ull));
-            const uint64_t nbm = readlane64(r1, i) & below;
-            const int lab1 = __builtin_amdgcn_readlane(l1, i);
-            const uint32_t degP = popc64(nbm);
-            const uint32_t edP = mul_cost<SMALL>(degP, edel);
-            uint64_t q[PLA];
+            // earlier neighbours of v_i (nlo: vertices 0..63, nhi: 64..127) and
+            // their label-plane bits
+            uint64_t nlo, nhi = 0ull, qlo[PLA], qhi[PLA];
+            int lab1;
+            if constexpr (M == 16) {
+                const uint64_t below = DIR ? (((1ull << i) - 1ull) * 0x100000001ull)   // i < 32: both words
+                                           : (i >= 64 ? ~0ull : ((1ull << i) - 1ull));
+                nlo = readlane64(r1, i) & below;
+                lab1 = __builtin_amdgcn_readlane(l1, i);
 #pragma unroll
-            for (int b = 0; b < PLA; ++b) q[b] = PL > 0 ? readlane64(p1[b], i) & nbm : 0ull;
+                for (int b = 0; b < PLA; ++b) {
+                    qlo[b] = PL > 0 ? readlane64(p1[b], i) & nlo : 0ull;
+                    qhi[b] = 0ull;
+                }
+            } else {
+                // row v_i of g1 (w1 <= 4 words) and its planes, the same address in every lane
+                auto word = [&](const uint32_t *r, int k) -> uint32_t {
+                    return k < w1 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)r[k]) : 0u;
+                };
+                const uint32_t *row = A1 + (size_t)i * w1;
+                const uint64_t blo = i >= 64 ? ~0ull : ((1ull << i) - 1ull);
+                const uint64_t bhi = i <= 64 ? 0ull : ((1ull << (i - 64)) - 1ull);
+                nlo = u64(word(row, 0), word(row, 1)) & blo;
+                nhi = u64(word(row, 2), word(row, 3)) & bhi;
+                lab1 = __builtin_amdgcn_readfirstlane(a.src.vlab[g1.vlab + i]);
+#pragma unroll
+                for (int b = 0; b < PLA; ++b) {
+                    qlo[b] = 0ull;
+                    qhi[b] = 0ull;
+                    if (PL > 0 && b < P) {
+                        const uint32_t *pr = A1 + (size_t)(1 + b) * n1 * w1 + (size_t)i * w1;
+                        qlo[b] = u64(word(pr, 0), word(pr, 1)) & nlo;
+                        qhi[b] = u64(word(pr, 2), word(pr, 3)) & nhi;
+                    }
+                }
+            }
+            const uint32_t degP = popc64(nlo) + popc64(nhi);
+            const uint32_t edP = mul_cost<SMALL>(degP, edel);
             // lane u: (N2(u), label cost); entry 64: the exhausted-set sentinel
             s_tab[lane] = make_uint4((uint32_t)r2, (uint32_t)(r2 >> 32), l2 != lab1 ? vsub : 0u, 0u);
             if (lane == 0) s_tab[64] = make_uint4(0u, 0u, INVALID, 0u);
 
-            // Phi (and its label-plane sets) of a slot whose mapping words are m
-            auto build_phi = [&](const uint32_t (&m)[16], uint64_t &phi, uint64_t (&phib)[PLA]) {
+            // Phi (and its label-plane sets) of a slot whose mapping words are m:
+            // word by word, the earlier neighbours in it by a loop over the
+            // word's bits (uniform), so that no per-bit condition outlives it
+            auto build_phi = [&](const uint32_t (&m)[M], uint64_t &phi, uint64_t (&phib)[PLA]) {
                 phi = 0ull;
 #pragma unroll
                 for (int b = 0; b < PLA; ++b) phib[b] = 0ull;
 #pragma unroll
-                for (int w = 0; w < 16; ++w) {
-                    if (((nbm >> (4 * w)) & 0xfull) == 0ull) continue;
+                for (int w = 0; w < M; ++w) {
+                    const uint64_t nw = w < 16 ? nlo : nhi;   // a constant choice once unrolled
+                    uint32_t nib = (uint32_t)(nw >> (4 * (w & 15))) & 0xfu;
+                    if (nib == 0u) continue;
+                    // directed: bits 32..63 (words 8..15) are in-arcs from vertices j - 32
+                    const uint32_t mw = m[DIR && w >= 8 ? w - 8 : w];   // a constant index once unrolled
+                    const uint32_t up = DIR && w >= 8 ? 32u : 0u;
+                    uint32_t qn[PLA];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int j = 4 * w + k;
-                        if (!((nbm >> j) & 1ull)) continue;
-                        // directed: bit j >= 32 is the in-arc from vertex j - 32
-                        const int wsrc = DIR && w >= 8 ? w - 8 : w;   // a constant once unrolled
-                        const uint32_t x = __builtin_amdgcn_ubfe(m[wsrc], (uint32_t)k * 8u, 8u);
-                        const uint64_t bit = x < 64u ? (1ull << (x + (DIR && w >= 8 ? 32u : 0u))) : 0ull;
+                    for (int b = 0; b < PLA; ++b)
+                        qn[b] = PL > 0 ? (uint32_t)((w < 16 ? qlo[b] : qhi[b]) >> (4 * (w & 15))) & 0xfu : 0u;
+                    do {
+                        const uint32_t k = (uint32_t)__builtin_ctz(nib);
+                        const uint32_t x = __builtin_amdgcn_ubfe(mw, k * 8u, 8u);
+                        const uint64_t bit = x < 64u ? (1ull << (x + up)) : 0ull;
                         phi |= bit;
 #pragma unroll
                         for (int b = 0; b < PLA; ++b)
-                            if (PL > 0 && ((q[b] >> j) & 1ull)) phib[b] |= bit;
-                    }
+                            if (PL > 0 && ((qn[b] >> k) & 1u)) phib[b] |= bit;
+                        nib &= nib - 1u;
+                    } while (nib != 0u);
                 }
             };
 
@@ -528,13 +570,13 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             if constexpr (S > 1) {
                 // every slot's mapping words up to word wl, PED, edge count and Img for the update
 #pragma unroll
-                for (int w = 0; w < 16; ++w)
+                for (int w = 0; w < M; ++w)
                     if (w <= wl) *reinterpret_cast<uint2 *>(&s_aux[w * NS + S * lane]) = make_uint2(ph[0][w], ph[S - 1][w]);
-                *reinterpret_cast<uint2 *>(&s_aux[16 * NS + S * lane]) = make_uint2(ped[0], ped[S - 1]);
-                *reinterpret_cast<uint2 *>(&s_aux[17 * NS + S * lane]) = make_uint2(ein[0], ein[S - 1]);
-                *reinterpret_cast<uint2 *>(&s_aux[18 * NS + S * lane]) =
+                *reinterpret_cast<uint2 *>(&s_aux[M * NS + S * lane]) = make_uint2(ped[0], ped[S - 1]);
+                *reinterpret_cast<uint2 *>(&s_aux[(M + 1) * NS + S * lane]) = make_uint2(ein[0], ein[S - 1]);
+                *reinterpret_cast<uint2 *>(&s_aux[(M + 2) * NS + S * lane]) =
                     make_uint2((uint32_t)img[0], (uint32_t)img[S - 1]);
-                *reinterpret_cast<uint2 *>(&s_aux[19 * NS + S * lane]) =
+                *reinterpret_cast<uint2 *>(&s_aux[(M + 3) * NS + S * lane]) =
                     make_uint2((uint32_t)(img[0] >> 32), (uint32_t)(img[S - 1] >> 32));
             }
             __syncthreads();
@@ -565,7 +607,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                     rp[b] = u64(pl.x, pl.y);
                 }
 #pragma unroll
-                for (int w = 0; w < 16; ++w)
+                for (int w = 0; w < M; ++w)
                     if (w <= wl) ph[0][w] = (uint32_t)__shfl((int)ph[0][w], p);
                 if (live2) {
                     if (sub) {
@@ -588,7 +630,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 }
                 // byte i of the mapping
 #pragma unroll
-                for (int w = 0; w < 16; ++w)
+                for (int w = 0; w < M; ++w)
                     if (w == wl) ph[0][w] = (ph[0][w] & ~(0xffu << sh8)) | (u << sh8);
             } else {
 #pragma unroll
@@ -598,12 +640,12 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                     const int p = (int)(sel >> 8);
                     const uint32_t jc = sel & 0xffu;
                     const bool sub = jc != DEL8;
-                    uint32_t m[16];
+                    uint32_t m[M];
 #pragma unroll
-                    for (int w = 0; w < 16; ++w) m[w] = w <= wl ? s_aux[w * NS + p] : 0u;
-                    const uint32_t ped_p = s_aux[16 * NS + p];
-                    const uint32_t ein_p = s_aux[17 * NS + p];
-                    const uint64_t img_p = u64(s_aux[18 * NS + p], s_aux[19 * NS + p]);
+                    for (int w = 0; w < M; ++w) m[w] = w <= wl ? s_aux[w * NS + p] : 0u;
+                    const uint32_t ped_p = s_aux[M * NS + p];
+                    const uint32_t ein_p = s_aux[(M + 1) * NS + p];
+                    const uint64_t img_p = u64(s_aux[(M + 2) * NS + p], s_aux[(M + 3) * NS + p]);
                     // the parent's j-th free vertex (a survivor is never an exhausted child)
                     const uint32_t u = sub ? nth_bit64(~img_p & umask, jc) : DEL8;
                     const uint32_t us = sub ? min(u, 64u) : 0u;
@@ -636,7 +678,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                         }
                     }
 #pragma unroll
-                    for (int w = 0; w < 16; ++w) {
+                    for (int w = 0; w < M; ++w) {
                         if (w < wl) ph[h][w] = m[w];
                         if (w == wl) ph[h][w] = (m[w] & ~(0xffu << sh8)) | (u << sh8);
                     }
@@ -663,45 +705,57 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             a.out.dist[wi.out] = (int)best_total;
             if (a.out.cand) a.out.cand[wi.out] = ce;
         }
-        uint32_t word = 0u;
+        // lane v writes the images of source vertices v and v + 64
 #pragma unroll
-        for (int w = 0; w < 16; ++w) {
-            const uint32_t v = hb == 0 ? ph[0][w] : ph[S - 1][w];
-            const uint32_t bw = (uint32_t)__builtin_amdgcn_readlane((int)v, best);
-            word = (lane >> 2) == w ? bw : word;
-        }
-        if (lane < n1) {
-            const uint32_t x = __builtin_amdgcn_ubfe(word, (uint32_t)(lane & 3) * 8u, 8u);
-            a.out.map[wi.map_off + lane] = (x == DEL8) ? -1 : (int)x;
+        for (int half = 0; half < M / 16; ++half) {
+            uint32_t word = 0u;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) {
+                const uint32_t v = hb == 0 ? ph[0][16 * half + w] : ph[S - 1][16 * half + w];
+                const uint32_t bw = (uint32_t)__builtin_amdgcn_readlane((int)v, best);
+                word = (lane >> 2) == w ? bw : word;
+            }
+            const int v1 = 64 * half + lane;
+            if (v1 < n1) {
+                const uint32_t x = __builtin_amdgcn_ubfe(word, (uint32_t)(lane & 3) * 8u, 8u);
+                a.out.map[wi.map_off + v1] = (x == DEL8) ? -1 : (int)x;
+            }
         }
         __syncthreads();
     }
 }
 
-template <int S, int PL, bool SMALL, bool COMPLETE, bool DIR>
+template <int S, int M, int PL, bool SMALL, bool COMPLETE, bool DIR>
 const void *wave2_ptr() {
-    return reinterpret_cast<const void *>(&kb_wave2_kernel<S, PL, SMALL, COMPLETE, DIR>);
+    return reinterpret_cast<const void *>(&kb_wave2_kernel<S, M, PL, SMALL, COMPLETE, DIR>);
 }
 
 // the complete-then-minimum last level is a kernel of its own, so that the
 // default search keeps its register budget; so are directed pairs
-template <int S, bool COMPLETE, bool DIR>
+template <int S, int M, bool COMPLETE, bool DIR>
 const void *select_wave2_c(int PL, bool small) {
-    if (PL == 0) return small ? wave2_ptr<S, 0, true, COMPLETE, DIR>() : wave2_ptr<S, 0, false, COMPLETE, DIR>();
-    if (PL == 2) return small ? wave2_ptr<S, 2, true, COMPLETE, DIR>() : wave2_ptr<S, 2, false, COMPLETE, DIR>();
-    if (PL == 4) return small ? wave2_ptr<S, 4, true, COMPLETE, DIR>() : wave2_ptr<S, 4, false, COMPLETE, DIR>();
+    if (PL == 0) return small ? wave2_ptr<S, M, 0, true, COMPLETE, DIR>() : wave2_ptr<S, M, 0, false, COMPLETE, DIR>();
+    if (PL == 2) return small ? wave2_ptr<S, M, 2, true, COMPLETE, DIR>() : wave2_ptr<S, M, 2, false, COMPLETE, DIR>();
+    if (PL == 4) return small ? wave2_ptr<S, M, 4, true, COMPLETE, DIR>() : wave2_ptr<S, M, 4, false, COMPLETE, DIR>();
     return nullptr;
 }
 
 template <int S>
 const void *select_wave2_s(int PL, bool small, bool complete, bool dir) {
-    if (dir) return complete ? select_wave2_c<S, true, true>(PL, small) : select_wave2_c<S, false, true>(PL, small);
-    return complete ? select_wave2_c<S, true, false>(PL, small) : select_wave2_c<S, false, false>(PL, small);
+    if (dir) return complete ? select_wave2_c<S, 16, true, true>(PL, small) : select_wave2_c<S, 16, false, true>(PL, small);
+    return complete ? select_wave2_c<S, 16, true, false>(PL, small) : select_wave2_c<S, 16, false, false>(PL, small);
+}
+
+template <int S>
+const void *select_wave2_wide_src(int PL, bool small, bool complete) {
+    return complete ? select_wave2_c<S, 32, true, false>(PL, small) : select_wave2_c<S, 32, false, false>(PL, small);
 }
 
 }  // namespace w2
 
 // kb_wave2_k128.hip: the two-slot instantiations (64 < K <= 128)
 const void *select_wave2_two_slots(int PL, bool small, bool complete, bool dir);
+// kb_wave2_src128.hip: sources of 65..128 vertices (undirected), slots = 1 or 2 per lane
+const void *select_wave2_wide_source(int slots, int PL, bool small, bool complete);
 
 }  // namespace gedk

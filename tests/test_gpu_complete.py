@@ -141,6 +141,20 @@ def test_query_molecule_subset(ged):
     complete_vs_oracle(ged, w.graphs, w.pairs, w.costs, 64)
 
 
+@pytest.mark.parametrize("K", [16, 128])
+def test_wide_source_wave(ged, K):
+    """Sources of 65..128 vertices against targets of up to 64 (the wavefront kernel's
+    third family) with the last level completed, then the workgroup kernel."""
+    from tests.test_gpu_parity import wide_source_set
+    graphs, ns = wide_source_set()
+    pairs = [[a, ns + b] for a in range(ns) for b in range(len(graphs.n) - ns)]
+    db = ged.Database(graphs)
+    for costs in (UNIT, WIDE_RANGE):
+        complete_vs_oracle(ged, graphs, pairs, costs, K, schedule=0, db=db, kinds={"kb_wave2_kernel"})
+        complete_vs_oracle(ged, graphs, pairs, costs, K, schedule=1, db=db)
+    db.close()
+
+
 @pytest.mark.parametrize("n1,n2", [(64, 65), (65, 64), (40, 100), (130, 129)])
 def test_word_boundaries(ged, n1, n2):
     g1 = synth.er_graph(13, n1, n1, n1, 0.2, 0.2, 3)

@@ -204,10 +204,50 @@ def test_wave64_two_slots(ged, costs, K):
     np.testing.assert_array_equal(res.cand, res2.cand)
 
 
+def wide_source_set():
+    """Sources of 65..128 vertices and targets of 0..64 (both ends of each range, empty
+    and edgeless graphs, labelled edges); returns the set and the number of sources."""
+    z = np.zeros(0, np.int32)
+    src = [(128, 0.05), (65, 0.1), (100, 0.03), (128, 0.0), (90, 0.08), (70, 0.2)]
+    dst = [(64, 0.1), (1, 0.0), (33, 0.2), (64, 0.0), (20, 0.3), (0, 0.0), (48, 0.06)]
+    gs = []
+    for k, (n, p) in enumerate(src + dst):
+        if n == 0:
+            gs.append(Graph(0, z, z, z, z))
+            continue
+        g = synth.er_graph(37, k, n, n, p, p, 4)
+        if k % 2 == 1:
+            g.elabel = (np.arange(g.m) % 5).astype(np.int32)
+        gs.append(g)
+    return GraphSet.from_graphs(gs), len(src)
+
+
+@pytest.mark.parametrize("costs", WAVE64_COSTS[:4])
+@pytest.mark.parametrize("K", [1, 16, 64, 128])
+def test_wide_source_wave(ged, costs, K):
+    """Sources of 65..128 vertices against targets of up to 64: the two-word wavefront
+    kernel with a 128-vertex mapping (one beam slot per lane up to K = 64, two above);
+    the workgroup kernel agrees on distances, mappings and candidate counts."""
+    graphs, ns = wide_source_set()
+    pairs = [[a, ns + b] for a in range(ns) for b in range(len(graphs.n) - ns)]
+    db = ged.Database(graphs)
+    plan = ged.Plan(db, pairs, K)
+    kinds = {name for name, *_ in plan.bins()}
+    plan.close()
+    assert kinds == {"kb_wave2_kernel"}, kinds
+    res = gpu_vs_oracle(ged, graphs, pairs, costs, K, db=db, schedule=0)
+    res2 = ged.kbest(db, pairs, costs, K, with_cand=True, schedule=1)
+    db.close()
+    np.testing.assert_array_equal(res.dist, res2.dist)
+    np.testing.assert_array_equal(res.maps, res2.maps)
+    np.testing.assert_array_equal(res.cand, res2.cand)
+
+
 @pytest.mark.parametrize("K", [8, 64, 128])
 def test_query_molecule_wave64(ged, K):
     """Molecule-like pairs (n 10..70): the wavefront bins (n <= 32 and n <= 64 at K <= 64,
-    the two-slot one for n <= 64 at K = 128) and the workgroup bin for n > 64 in one plan."""
+    the two-slot one for n <= 64 at K = 128, sources above 64 against targets of up to
+    64) and the workgroup bin for targets above 64 in one plan."""
     w = synth.query_molecule_10_70(200)
     gpu_vs_oracle(ged, w.graphs, w.pairs, w.costs, K)
 
