@@ -160,22 +160,25 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
 #pragma unroll
             for (int b = 0; b < PLA; ++b) phib[b] = 0u;
             // word w of phi holds the images of g1 vertices 4w .. 4w+3: the
-            // earlier neighbours are visited word by word (uniform branches,
-            // static register indices)
+            // earlier neighbours are visited word by word (static register
+            // indices), inside a word by a uniform loop over its set bits
 #pragma unroll
             for (int w = 0; w < 8; ++w) {
-                if (((nbm >> (4 * w)) & 0xfu) == 0u) continue;
+                uint32_t nib = (nbm >> (4 * w)) & 0xfu;
+                if (nib == 0u) continue;
+                uint32_t qn[PLA];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int j = 4 * w + k;
-                    if (!((nbm >> j) & 1u)) continue;
-                    const uint32_t x = __builtin_amdgcn_ubfe(ph[w], (uint32_t)k * 8u, 8u);
+                for (int b = 0; b < PLA; ++b) qn[b] = PL > 0 ? (q[b] >> (4 * w)) & 0xfu : 0u;
+                do {
+                    const uint32_t k = (uint32_t)__builtin_ctz(nib);
+                    const uint32_t x = __builtin_amdgcn_ubfe(ph[w], k * 8u, 8u);
                     const uint32_t bit = x < 32u ? (1u << x) : 0u;
                     phi |= bit;
 #pragma unroll
                     for (int b = 0; b < PLA; ++b)
-                        if (PL > 0 && ((q[b] >> j) & 1u)) phib[b] |= bit;
-                }
+                        if (PL > 0 && ((qn[b] >> k) & 1u)) phib[b] |= bit;
+                    nib &= nib - 1u;
+                } while (nib != 0u);
             }
             const uint32_t ai = img & ~phi;
             const uint32_t basel = live ? ped + mul_cost<SMALL>(degP, edel) : 0u;
