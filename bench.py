@@ -62,8 +62,8 @@ def ops_per_candidate(w: int, planes: int) -> int:
 
 # the files each kernel is compiled from (names in csrc/, or paths from the repository root)
 KERNEL_SOURCES = {"kb_wave_kernel": ("kb_wave.hip", "wave_common.h", "ged_types.h"),
-                  "kb_wave2_kernel": ("kb_wave2.hip", "wave_common.h", "ged_types.h", "ged_internal.h",
-                                      "include/ged.h"),
+                  "kb_wave2_kernel": ("kb_wave2.h", "kb_wave2.hip", "kb_wave2_k128.hip", "kb_wave2_src128.hip",
+                                      "wave_common.h", "ged_types.h", "ged_internal.h", "include/ged.h"),
                   "kb_block_kernel": ("kb_block.hip", "ged_internal.h", "ged_types.h", "include/ged.h")}
 
 
@@ -873,7 +873,9 @@ def main():
             t1 = time.perf_counter()
             e_ops, e_off, e_cnt = ged.edit_path(db, w.pairs, w.costs, maps)
             eps.append(time.perf_counter() - t1)
-        e_sum = np.add.reduceat(e_ops[:, 5].astype(np.int64), e_off[:-1]) if len(e_ops) else np.zeros(0)
+        # pair p's operations are the first e_cnt[p] of its slots from e_off[p]
+        # (its capacity, n1 + n2 + m1 + m2, may leave unwritten slots after them)
+        e_sum = np.array([int(e_ops[e_off[p]:e_off[p] + e_cnt[p], 5].sum()) for p in range(P)], dtype=np.int64)
         epath = {"ms_per_call": round(float(np.median(eps)) * 1e3, 3), "operations": int(e_cnt.sum()),
                  "costs_sum_to_distance": bool(np.array_equal(e_sum, gpu_dist.astype(np.int64)))}
         log(f"edit paths: {epath}")
