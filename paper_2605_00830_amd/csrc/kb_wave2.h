@@ -130,11 +130,12 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
     static_assert(M == 16 || (M == 32 && !DIR), "mapping of 64 source vertices, or 128 undirected");
     constexpr int PLA = PL > 0 ? PL : 1;
     constexpr int NS = 64 * S;              // beam slots
-    constexpr int PW = M + 4;               // parent words (S = 2): phi 0..M-1, PED, e_in, Img lo, Img hi
+    constexpr int PW = 20;                  // parent words (S = 2): 16 of phi, PED, e_in, Img lo, Img hi
     __shared__ uint32_t s_sel[NS];          // survivor: parent slot << 8 | j (0xff = deletion)
     __shared__ uint4 s_tab[65];             // per level: (N2(u) lo, hi, label cost, 0); [64] = sentinel
     // S = 1: [j / 4 * 64 + slot] = g2 vertices of children j, bytes;
-    // S = 2: [w * NS + slot] = parent word w (mapping words, then PED, e_in, Img)
+    // S = 2: [w * NS + slot] = parent word w (16 mapping words -- a 32-word
+    // mapping goes through in two halves -- then PED, e_in, Img)
     __shared__ __align__(16) uint32_t s_aux[S == 1 ? 16 * 64 : PW * NS];
     __shared__ uint2 s_pl[PLA][65];         // label-plane rows of g2; [64] = 0
     __shared__ int s_item;
@@ -568,15 +569,16 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             }
             const int wl = i >> 2;
             if constexpr (S > 1) {
-                // every slot's mapping words up to word wl, PED, edge count and Img for the update
+                // every slot's mapping words up to word wl (the first 16), PED,
+                // edge count and Img for the update
 #pragma unroll
-                for (int w = 0; w < M; ++w)
+                for (int w = 0; w < 16; ++w)
                     if (w <= wl) *reinterpret_cast<uint2 *>(&s_aux[w * NS + S * lane]) = make_uint2(ph[0][w], ph[S - 1][w]);
-                *reinterpret_cast<uint2 *>(&s_aux[M * NS + S * lane]) = make_uint2(ped[0], ped[S - 1]);
-                *reinterpret_cast<uint2 *>(&s_aux[(M + 1) * NS + S * lane]) = make_uint2(ein[0], ein[S - 1]);
-                *reinterpret_cast<uint2 *>(&s_aux[(M + 2) * NS + S * lane]) =
+                *reinterpret_cast<uint2 *>(&s_aux[16 * NS + S * lane]) = make_uint2(ped[0], ped[S - 1]);
+                *reinterpret_cast<uint2 *>(&s_aux[17 * NS + S * lane]) = make_uint2(ein[0], ein[S - 1]);
+                *reinterpret_cast<uint2 *>(&s_aux[18 * NS + S * lane]) =
                     make_uint2((uint32_t)img[0], (uint32_t)img[S - 1]);
-                *reinterpret_cast<uint2 *>(&s_aux[(M + 3) * NS + S * lane]) =
+                *reinterpret_cast<uint2 *>(&s_aux[19 * NS + S * lane]) =
                     make_uint2((uint32_t)(img[0] >> 32), (uint32_t)(img[S - 1] >> 32));
             }
             __syncthreads();
@@ -633,26 +635,54 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 for (int w = 0; w < M; ++w)
                     if (w == wl) ph[0][w] = (ph[0][w] & ~(0xffu << sh8)) | (u << sh8);
             } else {
+                // the new slots' parents: first their mapping words 0..15 (read
+                // straight into the slot's words, whose old values are in LDS
+                // already), PED, edge count and Img; a 32-word mapping's upper
+                // half then goes through the same LDS rows in a second round
+                int pp[S];
+                uint32_t jcs[S], ped_ps[S], ein_ps[S];
+                uint64_t img_ps[S];
 #pragma unroll
                 for (int h = 0; h < S; ++h) {
                     const bool live2 = S * lane + h < nb_new;
                     const uint32_t sel = live2 ? s_sel[S * lane + h] : 0u;
-                    const int p = (int)(sel >> 8);
-                    const uint32_t jc = sel & 0xffu;
-                    const bool sub = jc != DEL8;
-                    uint32_t m[M];
+                    pp[h] = (int)(sel >> 8);
+                    jcs[h] = sel & 0xffu;
+                    ped_ps[h] = s_aux[16 * NS + pp[h]];
+                    ein_ps[h] = s_aux[17 * NS + pp[h]];
+                    img_ps[h] = u64(s_aux[18 * NS + pp[h]], s_aux[19 * NS + pp[h]]);
 #pragma unroll
-                    for (int w = 0; w < M; ++w) m[w] = w <= wl ? s_aux[w * NS + p] : 0u;
-                    const uint32_t ped_p = s_aux[M * NS + p];
-                    const uint32_t ein_p = s_aux[(M + 1) * NS + p];
-                    const uint64_t img_p = u64(s_aux[(M + 2) * NS + p], s_aux[(M + 3) * NS + p]);
+                    for (int w = 0; w < 16; ++w) ph[h][w] = w <= wl ? s_aux[w * NS + pp[h]] : 0u;
+                }
+                if constexpr (M > 16) {
+                    if (wl >= 16) {
+                        __syncthreads();   // every read of the first half is done
+#pragma unroll
+                        for (int w = 0; w < 16; ++w)
+                            if (16 + w <= wl)
+                                *reinterpret_cast<uint2 *>(&s_aux[w * NS + S * lane]) =
+                                    make_uint2(ph[0][16 + w], ph[S - 1][16 + w]);
+                        __syncthreads();
+#pragma unroll
+                        for (int h = 0; h < S; ++h) {
+#pragma unroll
+                            for (int w = 0; w < 16; ++w) ph[h][16 + w] = 16 + w <= wl ? s_aux[w * NS + pp[h]] : 0u;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < S; ++h) {
+                    const bool live2 = S * lane + h < nb_new;
+                    const bool sub = jcs[h] != DEL8;
+                    const uint64_t img_p = img_ps[h];
                     // the parent's j-th free vertex (a survivor is never an exhausted child)
-                    const uint32_t u = sub ? nth_bit64(~img_p & umask, jc) : DEL8;
+                    const uint32_t u = sub ? nth_bit64(~img_p & umask, jcs[h]) : DEL8;
                     const uint32_t us = sub ? min(u, 64u) : 0u;
+                    // ph[h] holds the parent's mapping (byte i not yet set)
                     uint64_t phi_p, phbp[PLA];
-                    build_phi(m, phi_p, phbp);
+                    build_phi(ph[h], phi_p, phbp);
                     const uint64_t ai_p = img_p & ~phi_p;
-                    const uint32_t basel_p = ped_p + edP;
+                    const uint32_t basel_p = ped_ps[h] + edP;
                     const uint4 tu = s_tab[us];
                     const uint64_t R = u64(tu.x, tu.y);
                     if (live2) {
@@ -670,18 +700,16 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                             }
                             ped[h] = d;
                             img[h] = img_p | (1ull << (us & 63u)) | (DIR ? (1ull << ((us + 32u) & 63u)) : 0ull);
-                            ein[h] = ein_p + popc64(img_p & R);
+                            ein[h] = ein_ps[h] + popc64(img_p & R);
                         } else {
                             ped[h] = basel_p + vdel;
                             img[h] = img_p;
-                            ein[h] = ein_p;
+                            ein[h] = ein_ps[h];
                         }
                     }
 #pragma unroll
-                    for (int w = 0; w < M; ++w) {
-                        if (w < wl) ph[h][w] = m[w];
-                        if (w == wl) ph[h][w] = (m[w] & ~(0xffu << sh8)) | (u << sh8);
-                    }
+                    for (int w = 0; w < M; ++w)
+                        if (w == wl) ph[h][w] = (ph[h][w] & ~(0xffu << sh8)) | (u << sh8);
                 }
             }
             nb = nb_new;

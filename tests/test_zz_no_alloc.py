@@ -54,7 +54,12 @@ def test_noalloc_equals_kbest_twice(ged, K, costs):
     small = rng.integers(0, 40, size=(300, 2))
     mid = rng.integers(40, 60, size=(60, 2))
     big = np.stack([rng.integers(0, 76, 24), rng.integers(60, 76, 24)], 1)
-    first = np.concatenate([small, mid, big]).astype(np.int64)
+    # sources of 65..128 vertices against targets of up to 64 (the third wavefront bin)
+    n = graphs.n
+    wsrc = [a for a in range(60, 76) if n[a] <= 128]
+    assert wsrc, "the set has a source of 65..128 vertices"
+    wide = np.stack([rng.choice(wsrc, 12), rng.integers(40, 60, 12)], 1)
+    first = np.concatenate([small, mid, big, wide]).astype(np.int64)
     rng.shuffle(first)
     second = first[:97].copy()
     for name, pairs in (("first", first), ("second (smaller)", second)):
