@@ -15,6 +15,7 @@ namespace gedk {
 // SIMD on one pair instead of one).
 constexpr int kBlockThreads = 256;
 constexpr int kBlockThreadsWide = 512;
+constexpr int kBlockThreadsXL = 1024;   // unlabelled 8- and 16-word rows, one pair per CU
 
 struct BlockShape {
     int W;       // words per target row the instantiation handles (1,2,4,8,16)
@@ -31,6 +32,8 @@ struct BlockShape {
 // BlockShape::KS must equal it.
 int block_slot_stride(int K, int threads);
 size_t block_workspace_bytes(const BlockShape &s);
+// An instantiation exists for this shape (every shape at 256 and 512 threads).
+bool block_shape_supported(const BlockShape &s);
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu);
 // last_complete: at the last level every child is completed (Sec. 4.4.1) and
 // only the least total is kept, instead of the K of least partial distance

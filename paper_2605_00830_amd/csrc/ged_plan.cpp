@@ -49,11 +49,15 @@ struct Bin {
     int grid = 0;                // current persistent grid
     int groups_per_cu = 0;       // current resident workgroups per CU
     int max_wave_per_cu = 0;     // occupancy limits
-    int max_block_per_cu[2] = {0, 0};   // workgroups of 256, 512 threads
+    int max_block_per_cu[3] = {0, 0, 0};   // workgroups of 256, 512, 1024 threads (0: no such instantiation)
 };
 
-int bt_index(int threads) { return threads == gedk::kBlockThreadsWide ? 1 : 0; }
-int bt_of(int index) { return index == 1 ? gedk::kBlockThreadsWide : gedk::kBlockThreads; }
+int bt_index(int threads) {
+    return threads == gedk::kBlockThreadsXL ? 2 : (threads == gedk::kBlockThreadsWide ? 1 : 0);
+}
+int bt_of(int index) {
+    return index == 2 ? gedk::kBlockThreadsXL : (index == 1 ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
+}
 
 }  // namespace
 
@@ -146,7 +150,12 @@ int default_threads(const ged_plan *p, const Bin &b) {
     // resident at once with one (the launch then lasts as long as its
     // slowest pair, which four waves shorten), else one
     if (b.bip) return (int64_t)b.h_sorted.size() <= (int64_t)b.bip_max_per_cu[0] * p->cus ? 256 : 64;
-    return (int64_t)b.h_sorted.size() < 2 * (int64_t)p->cus ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
+    // the workgroup kernel: four waves per SIMD on one pair when the bin has
+    // at most one pair per CU (and the shape that instantiation), two when it
+    // cannot fill every CU twice, else one
+    const int64_t n = (int64_t)b.h_sorted.size();
+    if (n <= (int64_t)p->cus && b.max_block_per_cu[2] > 0) return gedk::kBlockThreadsXL;
+    return n < 2 * (int64_t)p->cus ? gedk::kBlockThreadsWide : gedk::kBlockThreads;
 }
 
 // Point bin `b` at one kernel family, workgroup size (workgroup kernel) and
@@ -349,7 +358,7 @@ std::map<std::string, Choice> read_cache(const char *path) {
     while (fgets(line, sizeof line, f)) {
         int w = 0, g = 0, t = 0;
         if (sscanf(line, "%511s %d %d %d", key, &w, &g, &t) == 4 &&
-            (t == gedk::kBlockThreads || t == gedk::kBlockThreadsWide || t == 64))
+            (t == gedk::kBlockThreads || t == gedk::kBlockThreadsWide || t == gedk::kBlockThreadsXL || t == 64))
             m[key] = Choice{w != 0, g, t};
     }
     fclose(f);
@@ -558,10 +567,11 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
             b.max_wave_per_cu = std::min(b.bip_max_per_cu[0], b.bip_max_per_cu[1]);
             b.max_block_per_cu[0] = b.max_block_per_cu[1] = 1;   // not used
         }
-        for (int k = 0; k < 2 && e == hipSuccess && !b.bip; ++k) {
+        for (int k = 0; k < 3 && e == hipSuccess && !b.bip; ++k) {
             gedk::BlockShape sh = b.shape;
             sh.BT = bt_of(k);
             sh.KS = gedk::block_slot_stride(K, sh.BT);
+            if (k == 2 && !gedk::block_shape_supported(sh)) continue;   // 1024 threads: some shapes only
             e = gedk::block_max_resident(sh, &b.max_block_per_cu[k]);
         }
         if (e == hipSuccess && b.wave_ok)
@@ -710,7 +720,8 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
     for (Bin &b : plan->bins) {
         const std::string key = bin_key(dev, plan->K, plan->last_complete, b);
         auto hit = cache.find(key);
-        if (hit != cache.end() && (!hit->second.wave || b.wave_ok || b.bip)) {
+        if (hit != cache.end() && (!hit->second.wave || b.wave_ok || b.bip) &&
+            (b.bip || hit->second.wave || b.max_block_per_cu[bt_index(hit->second.threads)] > 0)) {
             st = configure_bin(plan, b, hit->second.wave, hit->second.groups_per_cu, hit->second.threads);
             if (st != GED_OK) break;
             continue;
@@ -720,11 +731,12 @@ ged_status ged_plan_tune(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32
         // candidate per distinct grid
         std::vector<Choice> cands;
         const int64_t nwork = (int64_t)b.h_sorted.size();
-        for (int fam = 0; fam < 3; ++fam) {
+        for (int fam = 0; fam < 4; ++fam) {
             const bool wave = fam == 0;
-            if (b.bip && fam == 2) continue;   // the bipartite kernel: one or four waves per pair
+            if (b.bip && fam >= 2) continue;   // the bipartite kernel: one or four waves per pair
             if (wave && !b.wave_ok && !b.bip) continue;
-            const int threads = b.bip ? (fam == 0 ? 64 : 256) : (fam == 2 ? gedk::kBlockThreadsWide : gedk::kBlockThreads);
+            if (fam == 3 && b.max_block_per_cu[2] <= 0) continue;   // no 1024-thread instantiation
+            const int threads = b.bip ? (fam == 0 ? 64 : 256) : bt_of(fam == 0 ? 0 : fam - 1);
             const int lim = b.bip ? b.bip_max_per_cu[fam] : (wave ? b.max_wave_per_cu : b.max_block_per_cu[bt_index(threads)]);
             int64_t last_grid = -1;
             for (int g = lim; g >= 1; g = g / 2) {

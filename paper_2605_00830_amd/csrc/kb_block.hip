@@ -60,8 +60,8 @@ constexpr int NBINS = 1024;
 // beam state lives in HBM and whose levels are long; few for small ones,
 // whose occupancy the extra registers would cut (and fewer again where the
 // sets already take most registers)
-template <int W, int PL>
-constexpr int loads_together() { return W < 8 ? 2 : (W * (1 + PL) >= 64 ? 8 : 16); }
+template <int W, int PL, int BT>
+constexpr int loads_together() { return W < 8 ? 2 : (BT >= 1024 ? 4 : (W * (1 + PL) >= 64 ? 8 : 16)); }
 constexpr int SENT = 0x7fffffff;        // above every partial edit distance (empty minima)
 constexpr uint16_t PHI_DEL = 0xffff;
 constexpr size_t kDynLdsBytes = 136 * 1024;    // rows, staged planes, candidate matrix
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     const int P = a.dst.planes;
     constexpr int DH = DIR ? W / 2 : 0;   // first word of the in-half (directed)
     constexpr int NWF = DIR ? W / 2 : W;  // words of Img that name g2 vertices
-    constexpr int LB = loads_together<W, PL>();
+    constexpr int LB = loads_together<W, PL, BT>();
     static_assert(!DIR || W >= 2, "a directed row has two halves");
 
     for (bool first = true;; first = false) {
@@ -824,6 +824,8 @@ const void *select_kernel(int W, int PL, bool CL, int BT, bool DIR) {
     GEDK_ROW(4, false, bt, true) GEDK_ROW(8, false, bt, true) GEDK_ROW(16, false, bt, true)
     GEDK_ALL(256)
     GEDK_ALL(512)
+    // four waves per SIMD on one pair: the largest rows without label planes
+    GEDK_CASE(8, 0, false, 1024, false) GEDK_CASE(16, 0, false, 1024, false)
 #undef GEDK_ALL
 #undef GEDK_ROW
 #undef GEDK_CASE
@@ -840,6 +842,10 @@ int block_slot_stride(int K, int threads) {
 }
 
 size_t block_workspace_bytes(const BlockShape &s) { return layout_for(s).stride; }
+
+bool block_shape_supported(const BlockShape &s) {
+    return select_kernel(s.W, s.PL, cand_in_lds(s), s.BT, s.directed != 0) != nullptr;
+}
 
 hipError_t block_max_resident(const BlockShape &s, int *blocks_per_cu) {
     const void *k = select_kernel(s.W, s.PL, cand_in_lds(s), s.BT, s.directed != 0);
