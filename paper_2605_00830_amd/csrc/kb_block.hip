@@ -259,6 +259,9 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
     constexpr int DH = DIR ? W / 2 : 0;   // first word of the in-half (directed)
     constexpr int NWF = DIR ? W / 2 : W;  // words of Img that name g2 vertices
     constexpr int LB = loads_together<W, PL, BT>();
+    // the keep, compaction and mapping-copy passes hold few other values: at
+    // 1024 threads, where the expansion's registers keep LB at 4, they batch 8
+    constexpr int LBK = BT >= 1024 ? 8 : LB;
     static_assert(!DIR || W >= 2, "a directed row has two halves");
 
     for (bool first = true;; first = false) {
@@ -623,12 +626,12 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 int jlo = 0, jhi = 0, ncs = 0;
                 if (live) {
                     ncs = part_range(nsubc[s], &jlo, &jhi);
-                    for (int jb = jlo; jb < jhi; jb += LB) {
-                        int vv[LB];
+                    for (int jb = jlo; jb < jhi; jb += LBK) {
+                        int vv[LBK];
 #pragma unroll
-                        for (int k = 0; k < LB; ++k) vv[k] = jb + k < jhi ? cand_at(s, jb + k) : 0;
+                        for (int k = 0; k < LBK; ++k) vv[k] = jb + k < jhi ? cand_at(s, jb + k) : 0;
 #pragma unroll
-                        for (int k = 0; k < LB; ++k) {
+                        for (int k = 0; k < LBK; ++k) {
                             const bool in = jb + k < jhi;
                             lt += (in && vv[k] < T) ? 1 : 0;
                             eq += (in && vv[k] == T) ? 1 : 0;
@@ -648,11 +651,11 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                     for (int k = 0; k < W; ++k) img_r[k] = imgc[(size_t)k * KS + s];
                     FreeIter<W, NWF> it;
                     it.seek(img_r, n2, jlo);
-                    for (int jb = jlo; jb < jhi; jb += LB) {
-                        int vv[LB];
+                    for (int jb = jlo; jb < jhi; jb += LBK) {
+                        int vv[LBK];
 #pragma unroll
-                        for (int k = 0; k < LB; ++k) vv[k] = jb + k < jhi ? cand_at(s, jb + k) : 0;
-                        for (int k = 0; k < LB && jb + k < jhi; ++k) {
+                        for (int k = 0; k < LBK; ++k) vv[k] = jb + k < jhi ? cand_at(s, jb + k) : 0;
+                        for (int k = 0; k < LBK && jb + k < jhi; ++k) {
                             const int j = jb + k;
                             const int v = vv[k];
                             const int u = j < ncs - 1 ? it.next(img_r, n2) : n2;
@@ -688,15 +691,15 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
                 const int sel = s_sel[s2];
                 const int p = sel >> 10, u = sel & 1023;
                 const bool sub = u < n2;
-                for (int jb = part; jb < i; jb += LB * TPS) {
-                    uint16_t x[LB];
+                for (int jb = part; jb < i; jb += LBK * TPS) {
+                    uint16_t x[LBK];
 #pragma unroll
-                    for (int k = 0; k < LB; ++k) {
+                    for (int k = 0; k < LBK; ++k) {
                         const int j = jb + k * TPS;
                         x[k] = j < i ? phic[(size_t)j * KS + p] : (uint16_t)0;
                     }
 #pragma unroll
-                    for (int k = 0; k < LB; ++k) {
+                    for (int k = 0; k < LBK; ++k) {
                         const int j = jb + k * TPS;
                         if (j < i) phin[(size_t)j * KS + s2] = x[k];
                     }
