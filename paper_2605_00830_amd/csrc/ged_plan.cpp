@@ -282,7 +282,6 @@ ged_status plan_run(ged_plan *plan, ged_costs costs, int32_t *d_dist, int32_t *d
     RunCtx r;
     ged_status st = prepare_run(plan, costs, d_dist, d_map, d_cand, stream, &r);
     if (st != GED_OK) return st;
-    for (Bin &b : plan->bins) GED_HIP(gedk::launch_fill_zero(b.d_queue, (int)b.h_work.size() + 1, r.s));
     GED_HIP(gedk::launch_pair_status(plan->d_status, plan->npairs, d_status, plan->d_aside, plan->naside, d_dist,
                                      d_map, d_cand, r.s));
     const bool timing = plan->timing && allow_timing;
@@ -585,6 +584,8 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         const int64_t nwork = (int64_t)b.h_work.size();
         e = hipMalloc((void **)&b.d_work, sizeof(WorkItem) * (size_t)nwork);
         if (e == hipSuccess) e = hipMalloc((void **)&b.d_queue, sizeof(int) * (size_t)(nwork + 1));
+        // the queue counters start at 0; every run leaves them at 0 again
+        if (e == hipSuccess) e = hipMemset(b.d_queue, 0, sizeof(int) * (size_t)(nwork + 1));
         if (e != hipSuccess) {
             free_plan(p);
             return fail(GED_ENOMEM, "plan allocation failed: %s", hipGetErrorString(e));

@@ -40,6 +40,18 @@ struct WorkItem {
     int64_t map_off; // first mapping entry of the pair in d_map
 };
 
+// Next item of a persistent launch for a workgroup that has finished one:
+// items [0, grid) are the workgroups' own first items, the others come from
+// the launch's queue counter.  Every workgroup pulls until it gets an item
+// >= nwork, so a run takes exactly the values 0 .. nwork - 1 from the counter,
+// and the workgroup that takes the last one puts it back to 0 for the next
+// run (the counter starts at 0 when it is allocated): no reset between runs.
+__device__ __forceinline__ int pull_item(int *queue, int nwork) {
+    const int v = atomicAdd(queue, 1);
+    if (v == nwork - 1) atomicExch(queue, 0);
+    return (int)gridDim.x + v;
+}
+
 struct Costs {
     int32_t vsub, vdel, vins, esub, edel, eins;
 };

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(64 * NWAV) void kb_bip_kernel(BipArgs a) {
     for (bool first = true;; first = false) {
         int item = (int)blockIdx.x;
         if (!first) {
-            if (threadIdx.x == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
+            if (threadIdx.x == 0) s_item = pull_item(a.queue, a.nwork);
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(s_item);
             __syncthreads();

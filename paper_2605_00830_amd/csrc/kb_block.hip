@@ -270,7 +270,7 @@ __global__ __launch_bounds__(BT) void kb_block_kernel(BlockArgs a) {
         // serialise the grid's start on one atomic)
         int item = (int)blockIdx.x;
         if (!first) {
-            if (t == 0) s_bc[0] = (int)gridDim.x + atomicAdd(a.queue, 1);
+            if (t == 0) s_bc[0] = pull_item(a.queue, a.nwork);
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(s_bc[0]);
             __syncthreads();

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
         // serialise the whole grid's start on one atomic)
         int item = (int)blockIdx.x;
         if (!first) {
-            if (lane == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
+            if (lane == 0) s_item = pull_item(a.queue, a.nwork);
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(s_item);
             __syncthreads();

@@ -150,7 +150,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
     for (bool first = true;; first = false) {
         int item = (int)blockIdx.x;
         if (!first) {
-            if (lane == 0) s_item = (int)gridDim.x + atomicAdd(a.queue, 1);
+            if (lane == 0) s_item = pull_item(a.queue, a.nwork);
             __syncthreads();
             item = __builtin_amdgcn_readfirstlane(s_item);
             __syncthreads();
