@@ -35,12 +35,13 @@ METRIC = "GED pairs/sec at K=64 batched vs per-pair on 1 GPU; serving p50/p99 la
 # default is 4 queues per process, so the bench asks for enough queues before
 # the runtime starts.
 SERVE_STREAMS = 4
-# four size classes x 4 streams need 16 queues of their own, but the process holds
-# other streams as well (torch's, the runtime's): with exactly 17 queues a mid-size
-# stream still shared a queue with a large-query stream (mid p99 55-58 ms at half
-# load); with 32 queues the mid class's p99 at half load was 1.3 ms in the last
-# measured run, but at 0.8 of saturation it reached 137 ms: there the bound is how
-# many launches the server's one worker thread can issue, not the queues
+# four size classes x 4 streams (the large class twice that) need queues of their
+# own, and the process holds other streams as well (torch's, the runtime's): with
+# exactly 17 queues a mid-size stream still shared a queue with a large-query
+# stream (mid p99 55-58 ms at half load).  With 32 queues and the server's batch
+# formation and residency caps, the mid class's p99 stays near 1.4 ms at 0.8 of
+# saturation; the large class, whose launches last tens of milliseconds, sets the
+# overall p99 there
 HW_QUEUES = 32
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < HW_QUEUES:
     os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
