@@ -46,7 +46,11 @@ struct WorkItem {
 // >= nwork, so a run takes exactly the values 0 .. nwork - 1 from the counter,
 // and the workgroup that takes the last one puts it back to 0 for the next
 // run (the counter starts at 0 when it is allocated): no reset between runs.
+// A grid of at least nwork workgroups has no item to draw and leaves the
+// counter alone: device-scope atomics on one address are serialised at the
+// memory side, and a grid of thousands of short items would wait on them.
 __device__ __forceinline__ int pull_item(int *queue, int nwork) {
+    if ((int)gridDim.x >= nwork) return nwork;
     const int v = atomicAdd(queue, 1);
     if (v == nwork - 1) atomicExch(queue, 0);
     return (int)gridDim.x + v;

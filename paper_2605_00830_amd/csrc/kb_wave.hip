@@ -43,8 +43,10 @@
 //            compares) takes over.  Every child below T survives and the
 //            first (K - #below) children equal to T in generation order
 //            (lane order, then j, then the deletion), via per-lane bit masks
-//            and ballot/mbcnt exclusive scans; survivor (parent, j) pairs are
-//            written to LDS in generation order.
+//            and one exclusive scan of the per-lane (below, tie) counts in
+//            16-bit halves; survivor (parent, j) pairs are written to LDS in
+//            generation order.  With a full beam only V > K matters, which
+//            one ballot decides.
 //   update   new slot s reads its (parent, j) and the parent's child-j
 //            vertex u (recorded in LDS during the expand), fetches the
 //            parent's registers (PED + edel |P|, Phi, A, Img, e_in, the phi
@@ -87,9 +89,9 @@ template <int PL, bool SMALL, bool COMPLETE>
 __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
     constexpr int PLA = PL > 0 ? PL : 1;
     __shared__ uint32_t s_sel[64];          // survivor: parent slot << 8 | j (0xff = deletion)
-    __shared__ uint2 s_tab[33];             // per level: (N2(u), vsub [labels differ]); [32] = sentinel
+    __shared__ uint2 s_tab[33];             // per level: [1 + u] = (N2(u), vsub [labels differ]); [0] = sentinel
     __shared__ uint32_t s_uv[8][64];        // per level: [j / 4][slot] = g2 vertices of children j, bytes
-    __shared__ uint32_t s_pl[PLA][33];      // label-plane rows of g2; [32] = 0
+    __shared__ uint32_t s_pl[PLA][33];      // label-plane rows of g2 at [1 + u]; [0] = 0
     __shared__ int s_item;
 
     const int lane = threadIdx.x;
@@ -131,7 +133,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
         const uint32_t umask = n2 >= 32 ? 0xffffffffu : ((1u << n2) - 1u);
         if (PL > 0 && lane <= 32) {
 #pragma unroll
-            for (int b = 0; b < PLA; ++b) s_pl[b][lane] = p2[b];
+            for (int b = 0; b < PLA; ++b) s_pl[b][lane < 32 ? lane + 1 : 0] = lane < 32 ? p2[b] : 0u;
         }
 
         uint32_t ped = 0u, img = 0u, ein = 0u;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
 #pragma unroll
         for (int w = 0; w < 8; ++w) ph[w] = 0u;
         int nb = 1, hint = 0;
-        long long ce = 0;
+        uint32_t ce = 0u;   // this lane's evaluated children, summed over the wave at the end
 
         for (int i = 0; i < n1; ++i) {
             const uint32_t nbm = (uint32_t)__builtin_amdgcn_readlane((int)r1, i) & ((1u << i) - 1u);
@@ -149,11 +151,12 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
 #pragma unroll
             for (int b = 0; b < PLA; ++b) q[b] = (uint32_t)__builtin_amdgcn_readlane((int)p1[b], i) & nbm;
             const bool live = lane < nb;
-            // lane u: (N2(u), label cost); entry 32 is the sentinel of an
-            // exhausted free set: an empty row and a label cost of
-            // 0xffffffff, which the saturating add below turns into an
+            // entry 1 + u: (N2(u), label cost); entry 0 is the sentinel of an
+            // exhausted free set (find-lowest-bit of an empty set is
+            // 0xffffffff, one below entry 1): an empty row and a label cost
+            // of 0xffffffff, which the saturating add below turns into an
             // invalid child
-            if (lane <= 32) s_tab[lane] = lane < 32 ? make_uint2(r2, l2 != lab1 ? vsub : 0u) : make_uint2(0u, INVALID);
+            if (lane <= 32) s_tab[lane < 32 ? lane + 1 : 0] = lane < 32 ? make_uint2(r2, l2 != lab1 ? vsub : 0u) : make_uint2(0u, INVALID);
 
             // ---------------- expand and evaluate
             uint32_t phi = 0u, phib[PLA];
@@ -197,10 +200,12 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     uint32_t uw = 0u;
 #pragma unroll
                     for (int j = 4 * g; j < 4 * g + 4; ++j) {
-                        const uint32_t u = (uint32_t)__builtin_ctzg(fr, 32);   // 32 once exhausted
+                        // 0xffffffff once exhausted: its byte and the later
+                        // bytes of the word read 0xff, never selected
+                        const uint32_t u = find_low(fr);
                         fr &= fr - 1u;
                         uw |= u << (8 * (j & 3));
-                        const uint2 t = s_tab[u];
+                        const uint2 t = s_tab[u + 1u];
                         const uint32_t R = t.x;
                         // PED + label cost saturates only for the sentinel; its
                         // empty row keeps the edge terms at zero
@@ -210,7 +215,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         if (PL > 0) {
                             uint32_t diff = 0u;
 #pragma unroll
-                            for (int b = 0; b < PLA; ++b) diff |= phib[b] ^ s_pl[b][u];
+                            for (int b = 0; b < PLA; ++b) diff |= phib[b] ^ s_pl[b][u + 1u];
                             d += mul_cost<SMALL>((uint32_t)__popc(phi & R & diff), esub);
                         }
                         cand[j] = d;
@@ -224,8 +229,12 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             }
             const uint32_t cdel = live ? basel + vdel : INVALID;
             lmin = min(lmin, cdel);
-            const int V = (int)wave_sum(live ? nfree + 1u : 0u);
-            ce += V;
+            // V = number of children; only V > K and min(V, K) are used, so
+            // a full beam (every slot has its deletion child) needs one ballot
+            ce += live ? nfree + 1u : 0u;
+            int V;
+            if (nb < K) V = (int)wave_sum(live ? nfree + 1u : 0u);
+            else V = __ballot(nfree != 0u) != 0ull ? K + 1 : K;
 
             int nb_new;
             if (COMPLETE && i == n1 - 1) {
@@ -244,7 +253,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         for (int k = 0; k < 4; ++k) {
                             const uint32_t d = cand[4 * g + k];
                             if (d == INVALID) continue;
-                            const uint32_t R = s_tab[__builtin_amdgcn_ubfe(uw, (uint32_t)k * 8u, 8u)].x;
+                            const uint32_t R = s_tab[__builtin_amdgcn_ubfe(uw, (uint32_t)k * 8u, 8u) + 1u].x;
                             const uint32_t t = d + mul_cost<SMALL>(nu - 1u, vins) +
                                                mul_cost<SMALL>(mo - (uint32_t)__popc(img & R), eins);
                             if (t < bt) {
@@ -285,28 +294,27 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 }
                 const uint32_t pkd = 0x7f7f7f00u | min(cdel - m0, (uint32_t)TBYTE);
                 // count(PED <= m0 + ta) and count(PED <= m0 + tb), ta, tb in
-                // [0, 126], summed in one reduction (low and high halves)
+                // [0, 126], summed in one reduction (low and high halves).
+                // Words past the last group hold 127s and count nothing, so
+                // the probe takes four or all eight words, straight-line.
+                const bool wide = ngroups > 4;
                 auto counts2 = [&](int ta, int tb) {
                     const uint32_t Ca = ((uint32_t)ta * 0x01010101u) | 0x80808080u;
                     const uint32_t Cb = ((uint32_t)tb * 0x01010101u) | 0x80808080u;
                     uint32_t ca = (uint32_t)__popc((Ca - pkd) & 0x80808080u);
                     uint32_t cb = (uint32_t)__popc((Cb - pkd) & 0x80808080u);
-                    // words past the last group hold 127s and count nothing
-#define GED_PROBE_WORD(g)                                            \
-    ca += (uint32_t)__popc((Ca - pk[g]) & 0x80808080u);              \
-    cb += (uint32_t)__popc((Cb - pk[g]) & 0x80808080u);
-                    switch (ngroups) {
-                    case 8: GED_PROBE_WORD(7) [[fallthrough]];
-                    case 7: GED_PROBE_WORD(6) [[fallthrough]];
-                    case 6: GED_PROBE_WORD(5) [[fallthrough]];
-                    case 5: GED_PROBE_WORD(4) [[fallthrough]];
-                    case 4: GED_PROBE_WORD(3) [[fallthrough]];
-                    case 3: GED_PROBE_WORD(2) [[fallthrough]];
-                    case 2: GED_PROBE_WORD(1) [[fallthrough]];
-                    case 1: GED_PROBE_WORD(0) [[fallthrough]];
-                    default: break;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        ca += (uint32_t)__popc((Ca - pk[g]) & 0x80808080u);
+                        cb += (uint32_t)__popc((Cb - pk[g]) & 0x80808080u);
                     }
-#undef GED_PROBE_WORD
+                    if (wide) {
+#pragma unroll
+                        for (int g = 4; g < 8; ++g) {
+                            ca += (uint32_t)__popc((Ca - pk[g]) & 0x80808080u);
+                            cb += (uint32_t)__popc((Cb - pk[g]) & 0x80808080u);
+                        }
+                    }
                     return wave_sum(ca | (cb << 16));
                 };
                 // smallest t in [lo, hi] with count(t) >= K; hi = 127 stands
@@ -390,8 +398,16 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const bool eqd = trim && cdel == T;
             const int lt_l = __popc(ltm) + (ltd ? 1 : 0);
             const int eq_l = __popc(eqm) + (eqd ? 1 : 0);
-            const int quota = trim ? K - (int)wave_sum((uint32_t)lt_l) : 0;
-            int r = min(max(quota - wave_excl_scan(eq_l), 0), eq_l);
+            // one scan of (lt_l, eq_l) in 16-bit halves (sums <= 64 * 33):
+            // the children below T in earlier lanes, the ties in earlier
+            // lanes, and from the last lane the wave's total below T
+            const int own = lt_l | (eq_l << 16);
+            const int ex = wave_excl_scan(own);
+            const int tot_lt = __builtin_amdgcn_readlane(ex + own, 63) & 0xffff;
+            const int ex_lt = ex & 0xffff, ex_eq = (int)((uint32_t)ex >> 16);
+            // quota > 0 under trim: fewer than K children lie below T
+            const int quota = trim ? K - tot_lt : 0;
+            int r = min(max(quota - ex_eq, 0), eq_l);
             uint32_t keepm = ltm;
             bool keepd = ltd;
             const int ne = __popc(eqm);
@@ -402,7 +418,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 for (uint32_t e = eqm; r > 0; e &= e - 1u, --r) keepm |= e & (0u - e);
             }
             if (r > 0 && eqd) keepd = true;
-            int pos = wave_excl_scan(__popc(keepm) + (keepd ? 1 : 0));
+            // earlier lanes keep all their children below T and the ties up
+            // to the quota, in lane order
+            int pos = ex_lt + min(quota, ex_eq);
             for (uint32_t mk = keepm; mk; mk &= mk - 1u) s_sel[pos++] = ((uint32_t)lane << 8) | (uint32_t)__builtin_ctz(mk);
             if (keepd) s_sel[pos] = ((uint32_t)lane << 8) | DEL8;
             nb_new = min(V, K);
@@ -416,7 +434,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const uint32_t jc = sel & 0xffu;
             const bool sub = jc != DEL8;
             const uint32_t u = sub ? __builtin_amdgcn_ubfe(s_uv[(jc >> 2) & 7u][p], (jc & 3u) * 8u, 8u) : DEL8;
-            const uint32_t us = sub ? u : 0u;
+            const uint32_t us = sub ? u + 1u : 0u;   // table entry (0: the sentinel)
             const uint32_t basel_p = (uint32_t)__shfl((int)basel, p);
             const uint32_t phi_p = (uint32_t)__shfl((int)phi, p);
             const uint32_t ai_p = (uint32_t)__shfl((int)ai, p);
@@ -467,10 +485,11 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                                                mul_cost<SMALL>((uint32_t)g2.m - ein, eins)
                                          : INVALID;
         const uint32_t best_total = wave_umin(total);
+        const uint32_t ce_total = wave_sum(ce);
         const int best = (int)__builtin_ctzll(__ballot(total == best_total));
         if (lane == 0) {
             a.out.dist[wi.out] = (int)best_total;
-            if (a.out.cand) a.out.cand[wi.out] = ce;
+            if (a.out.cand) a.out.cand[wi.out] = (long long)ce_total;
         }
         uint32_t word = 0u;
 #pragma unroll

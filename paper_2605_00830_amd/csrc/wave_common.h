@@ -108,6 +108,14 @@ __device__ __forceinline__ uint32_t msub_cost(uint32_t count, uint32_t neg_cost,
     return count * neg_cost + acc;
 }
 
+// Index of the lowest set bit, 0xffffffff for 0 (the hardware's find-first-
+// bit, whose result for an empty word the compiler does not model).
+__device__ __forceinline__ uint32_t find_low(uint32_t x) {
+    uint32_t r;
+    asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t pack4(uint32_t e0, uint32_t e1, uint32_t e2, uint32_t e3) {
     return e0 | (e1 << 8) | (e2 << 16) | (e3 << 24);
 }
