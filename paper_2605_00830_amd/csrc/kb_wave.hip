@@ -31,19 +31,21 @@
 //            Per child: two AND + popcount and two 24-bit multiply-adds (the
 //            second with -edel).  The deletion child costs PED + vdel +
 //            edel |P|.
-//   select   T = K-th smallest PED.  Children are packed four to a word as
-//            bytes e = min(PED - m0, 127) (m0 = least child), and
-//            count(PED <= m0 + t) for t < 127 is the sum over lanes of
+//   select   T = K-th smallest PED.  As they are scored, children are
+//            packed four to a word as bytes e = min(PED - base, 127), base =
+//            least parent PED (no child costs less than its parent), and
+//            count(PED <= base + t) for t < 127 is the sum over lanes of
 //            popcount(((t * 0x01010101) | 0x80808080) - packed) & 0x80808080
 //            (each byte's top bit is set iff e <= t; no borrow crosses a
 //            byte).  The smallest t with count >= K is searched two
-//            thresholds per reduction, starting at the previous level's t
-//            (galloping, then thirds).  When T lies 127
-//            or more above m0 the exact count (wave ballots of full-width
-//            compares) takes over.  Every child below T survives and the
-//            first (K - #below) children equal to T in generation order
-//            (lane order, then j, then the deletion), via per-lane bit masks
-//            and one exclusive scan of the per-lane (below, tie) counts in
+//            thresholds per reduction, starting from the previous level's
+//            T - m0 (m0 = least child; galloping, then thirds).  When T lies 127 or more above the
+//            base the exact count (wave ballots of full-width compares)
+//            takes over.  Every child below T survives and the first
+//            (K - #below) children equal to T in generation order (lane
+//            order, then j, then the deletion), via per-lane bit masks
+//            (gathered from the same byte flags by byte dot products) and
+//            one exclusive scan of the per-lane (below, tie) counts in
 //            16-bit halves; survivor (parent, j) pairs are written to LDS in
 //            generation order.  With a full beam only V > K matters, which
 //            one ballot decides.
@@ -72,7 +74,7 @@ using namespace wv;
 
 constexpr uint32_t INVALID = 0xffffffffu;
 constexpr uint32_t DEL8 = 0xffu;
-constexpr int TBYTE = 127;        // byte-domain cap: e = min(PED - m0, 127)
+constexpr int TBYTE = 127;        // byte-domain cap: e = min(PED - base, 127)
 
 struct WaveArgs {
     DbView src;   // graphs edited (g1)
@@ -190,14 +192,18 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             const uint32_t free = live ? (~img & umask) : 0u;
             const uint32_t nfree = (uint32_t)__popc(free);
             const int ngroups = (int)(wave_umax(nfree) + 3u) >> 2;   // children in groups of four
+            // every child costs at least its parent (costs are
+            // non-negative and |Phi & N2(u)| <= |P|), so the least parent
+            // PED bounds every child from below: the byte-domain base
+            const uint32_t base = wave_umin(live ? ped : INVALID);
             __syncthreads();
-            uint32_t cand[32];
+            uint32_t cand[32], pk[8];
             uint32_t lmin = INVALID;
             uint32_t fr = free;
 #pragma unroll
             for (int g = 0; g < 8; ++g) {
                 if (g < ngroups) {
-                    uint32_t uw = 0u;
+                    uint32_t uw = 0u, e[4];
 #pragma unroll
                     for (int j = 4 * g; j < 4 * g + 4; ++j) {
                         // 0xffffffff once exhausted: its byte and the later
@@ -220,15 +226,18 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         }
                         cand[j] = d;
                         lmin = min(lmin, d);
+                        // byte of the threshold search: min(PED - base, 127)
+                        e[j & 3] = min(d - base, (uint32_t)TBYTE);
                     }
                     s_uv[g][lane] = uw;
+                    pk[g] = pack4(e[0], e[1], e[2], e[3]);
                 } else {
 #pragma unroll
                     for (int j = 4 * g; j < 4 * g + 4; ++j) cand[j] = INVALID;
+                    pk[g] = 0x7f7f7f7fu;   // 127s count below no threshold
                 }
             }
             const uint32_t cdel = live ? basel + vdel : INVALID;
-            lmin = min(lmin, cdel);
             // V = number of children; only V > K and min(V, K) are used, so
             // a full beam (every slot has its deletion child) needs one ballot
             ce += live ? nfree + 1u : 0u;
@@ -277,27 +286,20 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             } else {
             // ---------------- threshold T: the K-th smallest PED
             uint32_t T = INVALID;
+            int tbyte = -1;   // T - base when below 127
             const bool trim = V > K;
+            const bool wide = ngroups > 4;
             if (trim) {
-                const uint32_t m0 = wave_umin(lmin);
-                uint32_t pk[8];
-#pragma unroll
-                for (int g = 0; g < 8; ++g) {
-                    if (g < ngroups) {
-                        uint32_t e[4];
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) e[b] = min(cand[4 * g + b] - m0, (uint32_t)TBYTE);
-                        pk[g] = pack4(e[0], e[1], e[2], e[3]);
-                    } else {
-                        pk[g] = 0x7f7f7f7fu;
-                    }
-                }
-                const uint32_t pkd = 0x7f7f7f00u | min(cdel - m0, (uint32_t)TBYTE);
-                // count(PED <= m0 + ta) and count(PED <= m0 + tb), ta, tb in
-                // [0, 126], summed in one reduction (low and high halves).
+                // the least child m0 only steers the search: T - m0 (the
+                // width of the kept window) changes little from level to
+                // level, unlike T - base
+                const uint32_t m0 = wave_umin(min(lmin, cdel));
+                const int off = (int)min(m0 - base, (uint32_t)TBYTE);   // count(t) = 0 for t < off
+                const uint32_t pkd = 0x7f7f7f00u | min(cdel - base, (uint32_t)TBYTE);
+                // count(PED <= base + ta) and count(PED <= base + tb), ta, tb
+                // in [0, 126], summed in one reduction (low and high halves).
                 // Words past the last group hold 127s and count nothing, so
                 // the probe takes four or all eight words, straight-line.
-                const bool wide = ngroups > 4;
                 auto counts2 = [&](int ta, int tb) {
                     const uint32_t Ca = ((uint32_t)ta * 0x01010101u) | 0x80808080u;
                     const uint32_t Cb = ((uint32_t)tb * 0x01010101u) | 0x80808080u;
@@ -318,14 +320,14 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     return wave_sum(ca | (cb << 16));
                 };
                 // smallest t in [lo, hi] with count(t) >= K; hi = 127 stands
-                // for "none below 127".  Two thresholds per round: first the
-                // previous level's t and the one below it, then galloping
-                // up (no upper bound yet) or down (no lower bound yet), then
-                // thirds of [lo, hi).
-                int lo = 0, hi = TBYTE;
-                int ta = max(min(hint, TBYTE - 1) - 1, 0);
+                // for "none below 127".  Two thresholds per round: first
+                // m0 - base plus the previous level's T - m0, and the one
+                // below it, then galloping up (no upper bound yet) or down
+                // (no lower bound yet), then thirds of [lo, hi).
+                int lo = off, hi = TBYTE;
+                int ta = max(min(hint + off, TBYTE - 1) - 1, off);
                 int tb = min(ta + 1, TBYTE - 1);
-                for (int s = 1;; s <<= 1) {
+                for (int s = 1; lo < hi; s <<= 1) {
                     const uint32_t c2 = counts2(ta, tb);
                     if ((int)(c2 >> 16) >= K) hi = min(hi, tb);
                     else lo = max(lo, tb + 1);
@@ -335,9 +337,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     if (hi == TBYTE) {
                         ta = min(lo + s - 1, TBYTE - 1);
                         tb = min(lo + 2 * s, TBYTE - 1);
-                    } else if (lo == 0) {
+                    } else if (lo == off) {
                         tb = hi - 1;
-                        ta = max(hi - 1 - s, 0);
+                        ta = max(hi - 1 - s, off);
                     } else {
                         const int span = hi - lo;     // probe points lie in [lo, hi - 1]
                         ta = lo + (span - 1) / 3;
@@ -345,10 +347,11 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     }
                 }
                 if (lo < TBYTE) {
-                    T = m0 + (uint32_t)lo;
-                    hint = lo;
+                    T = base + (uint32_t)lo;
+                    tbyte = lo;
+                    hint = lo - off;
                 } else {
-                    // T >= m0 + 127: exact counts on the full values
+                    // T >= base + 127: exact counts on the full values
                     auto count_le = [&](uint32_t t) {
                         int cnt = __popcll(__ballot(cdel <= t));
 #pragma unroll
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         }
                         return cnt;
                     };
-                    uint32_t l2o = m0 + (uint32_t)TBYTE, tt = l2o, step = 1, h2;
+                    uint32_t l2o = base + (uint32_t)TBYTE, tt = l2o, step = 1, h2;
                     for (;;) {
                         if (count_le(tt) >= K) {
                             h2 = tt;
@@ -382,14 +385,40 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             }
 
             // ---------------- survivors in generation order
-            // bit u of ltm / lem: child u below / at most T (built high u first)
+            // bit j of ltm / lem: child j below / at most T
             uint32_t ltm = 0u, lem = 0u;
+            if (tbyte >= 0) {
+                // from the bytes: the flag bits of byte b of word g (set iff
+                // e <= t, as in the probes) are gathered by byte dot
+                // products with the weights 2^b (even g) and 2^(4+b) (odd g)
+                // into 128 x the mask byte of words g, g + 1
+                const uint32_t Cle = ((uint32_t)tbyte * 0x01010101u) | 0x80808080u;
+                const uint32_t Clt = tbyte > 0 ? (((uint32_t)tbyte - 1u) * 0x01010101u) | 0x80808080u : 0x7f7f7f7fu;
+                auto byte_mask = [&](uint32_t C) {
+                    uint32_t acc[4];
 #pragma unroll
-            for (int g = 7; g >= 0; --g) {
-                if (g < ngroups) {
+                    for (int h = 0; h < 4; ++h) {
+                        if (h < 2 || wide) {
+                            acc[h] = __builtin_amdgcn_udot4((C - pk[2 * h + 1]) & 0x80808080u, 0x80402010u, 0u, false);
+                            acc[h] = __builtin_amdgcn_udot4((C - pk[2 * h]) & 0x80808080u, 0x08040201u, acc[h], false);
+                        }
+                    }
+                    uint32_t m = (acc[0] >> 7) | (acc[1] << 1);
+                    if (wide) m |= (acc[2] << 9) | (acc[3] << 17);
+                    return m;
+                };
+                lem = byte_mask(Cle);
+                ltm = byte_mask(Clt);
+            } else {
+                // full-width compares (every child kept, or T 127 or more
+                // above the base), built high j first
 #pragma unroll
-                    for (int u = 4 * g + 3; u >= 4 * g; --u) {
-                        shift_in2(ltm, cand[u] < T, lem, cand[u] <= T);
+                for (int g = 7; g >= 0; --g) {
+                    if (g < ngroups) {
+#pragma unroll
+                        for (int u = 4 * g + 3; u >= 4 * g; --u) {
+                            shift_in2(ltm, cand[u] < T, lem, cand[u] <= T);
+                        }
                     }
                 }
             }
