@@ -44,9 +44,12 @@
 // (empty row, label cost 0xffffffff, saturating add: the invalid value
 // 0xffffffff).  The deletion child costs PED + vdel + edel |P|.  Survivors:
 // every child below T and the first (K - #below) children equal to T in
-// generation order (slot, then j, then the deletion), written to LDS as
-// (parent slot, j); a new slot finds its vertex and recomputes its PED with
-// the same formula.  With one slot per lane the parent's state comes over
+// generation order (slot, then j, then the deletion) -- bit masks gathered
+// from the bytes' flags by byte dot products, and one exclusive scan of the
+// per-lane (below, tie) counts in 16-bit halves for the quota and the
+// positions -- written to LDS as (parent slot, j); a new slot finds its
+// vertex and recomputes its PED with the same formula.  With a full beam
+// only V > K matters (the number of children), which one ballot decides.  With one slot per lane the parent's state comes over
 // the wave's lane permute and the child's vertex from a per-level LDS table;
 // with two, every parent's mapping words, PED, edge count and Img go through
 // LDS, the new slot rebuilds the parent's Phi from them and finds its vertex
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             for (int w = 0; w < M; ++w) ph[h][w] = 0u;
         }
         int nb = 1, hint = 1;
-        long long ce = 0;
+        uint32_t ce = 0u;   // this lane's evaluated children, summed over the wave at the end
 
         for (int i = 0; i < n1; ++i) {
             // earlier neighbours of v_i (nlo: vertices 0..63, nhi: 64..127) and
@@ -308,8 +311,12 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 cdel[h] = live[h] ? basel[h] + vdel : INVALID;
             }
             const int ngroups = (int)(wave_umax(nfmax) + 3u) >> 2;   // children in groups of four
-            const int V = (int)wave_sum(vl);
-            ce += V;
+            // V = number of children; only V > K and min(V, K) are used, so
+            // a full beam (every slot has its deletion child) needs one ballot
+            ce += vl;
+            int V;
+            if (nb < K) V = (int)wave_sum(vl);
+            else V = __ballot(nfmax != 0u) != 0ull ? K + 1 : K;
             const bool trim = V > K;
             __syncthreads();
 
@@ -374,13 +381,18 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 const uint32_t Cb = ((uint32_t)tb * 0x01010101u) | 0x80808080u;
                 uint32_t ca = (uint32_t)__popc((Ca - pkd) & 0x80808080u);
                 uint32_t cb = (uint32_t)__popc((Cb - pkd) & 0x80808080u);
+                // words past the last group hold 127s and count nothing:
+                // guards per four words
 #pragma unroll
                 for (int h = 0; h < S; ++h) {
 #pragma unroll
-                    for (int g = 0; g < 16; ++g) {
-                        if (g < ngroups) {
-                            ca += (uint32_t)__popc((Ca - pk[h][g]) & 0x80808080u);
-                            cb += (uint32_t)__popc((Cb - pk[h][g]) & 0x80808080u);
+                    for (int q = 0; q < 4; ++q) {
+                        if (4 * q < ngroups) {
+#pragma unroll
+                            for (int g = 4 * q; g < 4 * q + 4; ++g) {
+                                ca += (uint32_t)__popc((Ca - pk[h][g]) & 0x80808080u);
+                                cb += (uint32_t)__popc((Cb - pk[h][g]) & 0x80808080u);
+                            }
                         }
                     }
                 }
@@ -491,39 +503,33 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             int eqc[S];
             uint32_t lt_l = 0u;
             const uint32_t uT = (uint32_t)tT;
+            // bit j set iff byte j <= t, for C = (t * 0x01010101) | 0x80808080
+            // (t <= 126): the flag bits of byte b of word g (as in the
+            // probes) are gathered by byte dot products with the weights 2^b
+            // (even g) and 2^(4+b) (odd g) into 128 x the mask byte of words
+            // g, g + 1; words past the last group hold 127s and give none
+            auto byte_mask = [&](int h, uint32_t C) {
+                uint32_t acc[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    acc[q] = 0u;
+                    if (2 * q < ngroups) {
+                        acc[q] = __builtin_amdgcn_udot4((C - pk[h][2 * q + 1]) & 0x80808080u, 0x80402010u, 0u, false);
+                        acc[q] = __builtin_amdgcn_udot4((C - pk[h][2 * q]) & 0x80808080u, 0x08040201u, acc[q], false);
+                    }
+                }
+                const uint32_t lo = (acc[0] >> 7) | (acc[1] << 1) | (acc[2] << 9) | (acc[3] << 17);
+                const uint32_t hi = (acc[4] >> 7) | (acc[5] << 1) | (acc[6] << 9) | (acc[7] << 17);
+                return u64(lo, hi);
+            };
 #pragma unroll
             for (int h = 0; h < S; ++h) {
-                // bit j of ltm / lem: child j below / at most T (built high j first)
-                uint32_t ltl = 0u, lel = 0u, lth = 0u, leh = 0u;
-#pragma unroll
-                for (int g = 15; g >= 8; --g) {
-                    if (g < ngroups) {
-#pragma unroll
-                        for (int k = 3; k >= 0; --k) {
-                            const uint32_t x = __builtin_amdgcn_ubfe(pk[h][g], (uint32_t)k * 8u, 8u);
-                            shift_in2(lth, x < uT, leh, x <= uT);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int g = 7; g >= 0; --g) {
-                    if (g < ngroups) {
-#pragma unroll
-                        for (int k = 3; k >= 0; --k) {
-                            const uint32_t x = __builtin_amdgcn_ubfe(pk[h][g], (uint32_t)k * 8u, 8u);
-                            shift_in2(ltl, x < uT, lel, x <= uT);
-                        }
-                    }
-                }
-                uint64_t ltm, lem;
-                if (ngroups > 8) {
-                    ltm = u64(ltl, lth);
-                    lem = u64(lel, leh);
+                // bit j of ltm / lem: child j below / at most T
+                uint64_t ltm = 0ull, lem = 0ull;
+                if (trim) {
+                    lem = byte_mask(h, (uT * 0x01010101u) | 0x80808080u);
+                    ltm = byte_mask(h, ((uT - 1u) * 0x01010101u) | 0x80808080u);
                 } else {
-                    ltm = (uint64_t)ltl;
-                    lem = (uint64_t)lel;
-                }
-                if (!trim) {
                     // without trimming T is not set: every valid child survives
                     const uint64_t all = nfree[h] >= 64 ? ~0ull : ((1ull << nfree[h]) - 1ull);
                     ltm = live[h] ? all : 0ull;
@@ -537,12 +543,19 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 lt_l += popc64(ltm) + (ltd ? 1u : 0u);
                 eqc[h] = (int)popc64(eqm[h]) + (eqd[h] ? 1 : 0);
             }
-            const int quota = trim ? K - (int)wave_sum(lt_l) : 0;
             int eq_l = 0;
 #pragma unroll
             for (int h = 0; h < S; ++h) eq_l += eqc[h];
-            int ex = wave_excl_scan(eq_l);
-            int kept = 0;
+            // one scan of (below, ties) per lane in 16-bit halves (sums <=
+            // 64 * 130): the children below T in earlier lanes, the ties in
+            // earlier lanes, and from the last lane the wave's total below T
+            const int own = (int)lt_l | (eq_l << 16);
+            const int exs = wave_excl_scan(own);
+            const int tot_lt = __builtin_amdgcn_readlane(exs + own, 63) & 0xffff;
+            // quota > 0 under trim: fewer than K children lie below T
+            const int quota = trim ? K - tot_lt : 0;
+            const int ex_eq = (int)((uint32_t)exs >> 16);
+            int ex = ex_eq;
 #pragma unroll
             for (int h = 0; h < S; ++h) {
                 int r = min(max(quota - ex, 0), eqc[h]);
@@ -555,9 +568,10 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                     for (uint64_t e = eqm[h]; r > 0; e &= e - 1ull, --r) keepm[h] |= e & (0ull - e);
                 }
                 if (r > 0 && eqd[h]) keepd[h] = true;
-                kept += (int)popc64(keepm[h]) + (keepd[h] ? 1 : 0);
             }
-            int pos = wave_excl_scan(kept);
+            // earlier lanes keep all their children below T and the ties up
+            // to the quota, in lane order
+            int pos = (exs & 0xffff) + min(quota, ex_eq);
 #pragma unroll
             for (int h = 0; h < S; ++h) {
                 const uint32_t slot = (uint32_t)(S * lane + h);
@@ -726,12 +740,13 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             tmin = min(tmin, tot[h]);
         }
         const uint32_t best_total = wave_umin(tmin);
+        const uint32_t ce_total = wave_sum(ce);
         const int best = (int)__builtin_ctzll(__ballot(tmin == best_total));
         // the slot of the best lane that holds it (the first one)
         const int hb = S == 1 ? 0 : __builtin_amdgcn_readlane(tot[0] == best_total ? 0 : 1, best);
         if (lane == 0) {
             a.out.dist[wi.out] = (int)best_total;
-            if (a.out.cand) a.out.cand[wi.out] = ce;
+            if (a.out.cand) a.out.cand[wi.out] = (long long)ce_total;
         }
         // lane v writes the images of source vertices v and v + 64
 #pragma unroll
