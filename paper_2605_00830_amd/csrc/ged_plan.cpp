@@ -552,10 +552,15 @@ ged_status ged_plan_create_ex(ged_db *db, const ged_pair *h_pairs, int64_t npair
         b.h_work.swap(kv.second.h_work);
         // longest first: the tree search's work grows with n1 * (n2 + 1); the
         // bipartite method's with n1^2 (n1 + n2) (children per pop times
-        // solver steps, measured by rank correlation with its step counts)
+        // solver steps, measured by rank correlation with its step counts).
+        // A wavefront pair's duration is n1 levels of a fixed part (reductions,
+        // LDS round trips, the update) plus one that grows with n2, so those
+        // bins go by n1 * (n2 + 24), so the pairs of most levels start first
+        // (measured on the 4096-pair batches: 91.5 us against 99.7 with
+        // n1 * (n2 + 1); constants from 16 to 32 are equally good)
         auto work_of = [&](const WorkItem &x) -> int64_t {
             const int64_t a = db->h_graphs[x.src].n, c = db->h_graphs[x.dst].n;
-            return b.bip ? a * a * (a + c) : a * (c + 1);
+            return b.bip ? a * a * (a + c) : (b.wave_ok ? a * (c + 24) : a * (c + 1));
         };
         std::stable_sort(b.h_work.begin(), b.h_work.end(),
                          [&](const WorkItem &x, const WorkItem &y) { return work_of(x) > work_of(y); });
