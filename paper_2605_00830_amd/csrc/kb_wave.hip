@@ -196,6 +196,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
             // non-negative and |Phi & N2(u)| <= |P|), so the least parent
             // PED bounds every child from below: the byte-domain base
             const uint32_t base = wave_umin(live ? ped : INVALID);
+            // the level's selection works on PEDs minus the base (candidates,
+            // the deletion child, T), so a child's byte is min(value, 127)
+            const uint32_t basel_r = basel - base;
             __syncthreads();
             uint32_t cand[32], pk[8];
             uint32_t lmin = INVALID;
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         // empty row keeps the edge terms at zero
                         uint32_t d = msub_cost<SMALL>((uint32_t)__popc(phi & R), nedel,
                                                       mad_cost<SMALL>((uint32_t)__popc(ai & R), eins,
-                                                                      __builtin_elementwise_add_sat(basel, t.y)));
+                                                                      __builtin_elementwise_add_sat(basel_r, t.y)));
                         if (PL > 0) {
                             uint32_t diff = 0u;
 #pragma unroll
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         cand[j] = d;
                         lmin = min(lmin, d);
                         // byte of the threshold search: min(PED - base, 127)
-                        e[j & 3] = min(d - base, (uint32_t)TBYTE);
+                        e[j & 3] = min(d, (uint32_t)TBYTE);
                     }
                     s_uv[g][lane] = uw;
                     pk[g] = pack4(e[0], e[1], e[2], e[3]);
@@ -237,7 +240,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     pk[g] = 0x7f7f7f7fu;   // 127s count below no threshold
                 }
             }
-            const uint32_t cdel = live ? basel + vdel : INVALID;
+            const uint32_t cdel = live ? basel_r + vdel : INVALID;
             // V = number of children; only V > K and min(V, K) are used, so
             // a full beam (every slot has its deletion child) needs one ballot
             ce += live ? nfree + 1u : 0u;
@@ -293,9 +296,9 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                 // the least child m0 only steers the search: T - m0 (the
                 // width of the kept window) changes little from level to
                 // level, unlike T - base
-                const uint32_t m0 = wave_umin(min(lmin, cdel));
-                const int off = (int)min(m0 - base, (uint32_t)TBYTE);   // count(t) = 0 for t < off
-                const uint32_t pkd = 0x7f7f7f00u | min(cdel - base, (uint32_t)TBYTE);
+                const uint32_t m0 = wave_umin(min(lmin, cdel));   // minus the base
+                const int off = (int)min(m0, (uint32_t)TBYTE);   // count(t) = 0 for t < off
+                const uint32_t pkd = 0x7f7f7f00u | min(cdel, (uint32_t)TBYTE);
                 // count(PED <= base + ta) and count(PED <= base + tb), ta, tb
                 // in [0, 126], summed in one reduction (low and high halves).
                 // Words past the last group hold 127s and count nothing, so
@@ -347,7 +350,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                     }
                 }
                 if (lo < TBYTE) {
-                    T = base + (uint32_t)lo;
+                    T = (uint32_t)lo;
                     tbyte = lo;
                     hint = lo - off;
                 } else {
@@ -363,7 +366,7 @@ __global__ __launch_bounds__(64) void kb_wave_kernel(WaveArgs a) {
                         }
                         return cnt;
                     };
-                    uint32_t l2o = base + (uint32_t)TBYTE, tt = l2o, step = 1, h2;
+                    uint32_t l2o = (uint32_t)TBYTE, tt = l2o, step = 1, h2;
                     for (;;) {
                         if (count_le(tt) >= K) {
                             h2 = tt;
