@@ -296,7 +296,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             // ---------------- Phi and the children of every slot
             bool live[S];
             uint64_t phi[S], phib[S][PLA], ai[S], free[S];
-            uint32_t basel[S], nfree[S], cdel[S];
+            uint32_t basel[S], basel_r[S], nfree[S], cdel[S];
             uint32_t nfmax = 0u, vl = 0u;
 #pragma unroll
             for (int h = 0; h < S; ++h) {
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 const uint64_t R = u64(t.x, t.y);
                 uint32_t d = msub_cost<SMALL>(popc64(phi[h] & R), nedel,
                                               mad_cost<SMALL>(popc64(ai[h] & R), eins,
-                                                              __builtin_elementwise_add_sat(basel[h], t.z)));
+                                                              __builtin_elementwise_add_sat(basel_r[h], t.z)));
                 if (PL > 0) {
                     uint64_t diff = 0ull;
 #pragma unroll
@@ -341,7 +341,9 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 return d;
             };
             // one pass: every child's byte against (base, sh) into pk; the
-            // first pass of a one-slot wave also records each child's vertex
+            // first pass (base 0, sh 0: a child's byte is min(value, 126) + 1,
+            // nothing lies below) of a one-slot wave also records each
+            // child's vertex.  Values are PEDs minus the least parent PED.
             uint32_t pk[S][16];
             auto pass = [&](uint32_t base, int sh, bool record) {
 #pragma unroll
@@ -356,9 +358,10 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                                 const uint32_t u = (uint32_t)__builtin_ctzg(fr, 64);   // 64 once exhausted
                                 fr &= fr - 1ull;
                                 uw |= u << (8 * k);
-                                w |= to_byte(score(h, u), base, sh) << (8 * k);
+                                const uint32_t d = score(h, u);
+                                w |= (record ? min(d, 126u) : to_byte(d, base, sh)) << (8 * k);
                             }
-                            pk[h][g] = w;
+                            pk[h][g] = record ? w + 0x01010101u : w;   // bytes <= 127: no carry
                             if constexpr (S == 1)
                                 if (record) s_aux[g * 64 + lane] = uw;
                         } else {
@@ -431,7 +434,13 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
 #pragma unroll
             for (int h = 0; h < S; ++h) mp = min(mp, live[h] ? ped[h] : INVALID);
             const uint32_t m0 = wave_umin(mp);   // no child lies below
-            pass(m0, 0, true);
+            // the level's selection works on PEDs minus m0
+#pragma unroll
+            for (int h = 0; h < S; ++h) {
+                basel_r[h] = basel[h] - m0;
+                cdel[h] = live[h] ? cdel[h] - m0 : INVALID;
+            }
+            pass(0u, 0, true);
             int nb_new;
             if (COMPLETE && i == n1 - 1) {
                 // ---------------- complete-then-minimum last level: each
@@ -470,7 +479,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
             uint32_t T = INVALID;
             int tT = TOP;   // no trimming: every child with a byte below 127 survives
             if (trim) {
-                uint32_t base = m0;
+                uint32_t base = 0u;
                 int sh = 0;
                 int t = search(del_bytes(base, sh), hint);
                 if (t < TOP) {
@@ -478,7 +487,7 @@ __global__ __launch_bounds__(64) void kb_wave2_kernel(Wave2Args a) {
                 } else {
                     // the K-th child lies 126 or more above the least parent:
                     // bucket passes from 2^24 down to exact offsets
-                    base = m0 + 126u;
+                    base = 126u;
                     sh = 24;
                     for (;;) {
                         pass(base, sh, false);
